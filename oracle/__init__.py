@@ -1,0 +1,127 @@
+"""FP64 CPU oracle for Gaussian beam summation (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline leg may use this package; the library under test never does.  The C
+source (gbs_oracle.c) is the plain definition of the sum (paper Sec. 2,
+Eqs. (1)-(3)); this module only marshals numpy arrays to it and builds it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gbs_oracle.c")
+_LIB = os.path.join(_HERE, "libgbs_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-Wall", "-shared", "-fPIC", "-o", tmp,
+                               _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        common = [i32, i64, P, P, P, i64, P, P, P, P, P, P, P, i32, P, i64, P, i32, P, P, f64, f64]
+        lib.gbso_forward.argtypes = common + [i32, i32, P, P, P]
+        lib.gbso_forward.restype = ctypes.c_int
+        lib.gbso_backward.argtypes = common + [P, i32, P, P, P, P]
+        lib.gbso_backward.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _table_args(table, gamma, rcv, freqs, eps, c, gate):
+    arrs = dict(
+        ray_ptr=np.ascontiguousarray(table.ray_ptr, np.int64),
+        ray_w=np.ascontiguousarray(table.ray_w, np.float64),
+        ray_src=np.ascontiguousarray(table.ray_src, np.int32),
+        a=np.ascontiguousarray(table.seg_a, np.float64),
+        t=np.ascontiguousarray(table.seg_t, np.float64),
+        s0=np.ascontiguousarray(table.seg_s0, np.float64),
+        lo=np.ascontiguousarray(table.seg_lo, np.float64),
+        hi=np.ascontiguousarray(table.seg_hi, np.float64),
+        face_ptr=np.ascontiguousarray(table.face_ptr, np.int64),
+        face_ids=np.ascontiguousarray(table.face_ids, np.int32),
+        gamma=np.ascontiguousarray(np.stack([np.real(gamma), np.imag(gamma)], axis=-1).reshape(-1), np.float64),
+        rcv=np.ascontiguousarray(rcv, np.float64).reshape(-1, 3),
+        freqs=np.ascontiguousarray(freqs, np.float64).reshape(-1),
+        eps=np.ascontiguousarray(eps, np.float64).reshape(-1),
+    )
+    if arrs["eps"].shape[0] != table.n_src * arrs["freqs"].shape[0]:
+        raise ValueError("eps must hold one value per (source, band) job")
+    if len(gamma) != table.n_faces:
+        raise ValueError("gamma must hold one coefficient per face")
+    args = [table.n_src, table.n_rays, _ptr(arrs["ray_ptr"]), _ptr(arrs["ray_w"]), _ptr(arrs["ray_src"]),
+            table.n_segs, _ptr(arrs["a"]), _ptr(arrs["t"]), _ptr(arrs["s0"]), _ptr(arrs["lo"]), _ptr(arrs["hi"]),
+            _ptr(arrs["face_ptr"]), _ptr(arrs["face_ids"]), table.n_faces, _ptr(arrs["gamma"]),
+            arrs["rcv"].shape[0], _ptr(arrs["rcv"]), arrs["freqs"].shape[0], _ptr(arrs["freqs"]),
+            _ptr(arrs["eps"]), float(c), float(gate)]
+    return args, arrs
+
+
+def forward(table, gamma, rcv, freqs, eps, c=343.0, gate=9.21, n_threads=1, mask_mode=0, mask=None):
+    """P [n_jobs, n_rcv] complex128 and TL [n_jobs, n_rcv] float64.
+
+    mask_mode 1 records the active (job, receiver, segment) set into `mask`
+    (uint8, shape [n_jobs, n_rcv, n_segs]); mask_mode 2 evaluates with that set
+    frozen instead of the gate.
+    """
+    args, arrs = _table_args(table, gamma, rcv, freqs, eps, c, gate)
+    n_jobs = table.n_src * arrs["freqs"].shape[0]
+    n_rcv = arrs["rcv"].shape[0]
+    P = np.zeros((n_jobs, n_rcv, 2), np.float64)
+    TL = np.zeros((n_jobs, n_rcv), np.float64)
+    if mask_mode:
+        if mask is None or mask.dtype != np.uint8 or mask.size != n_jobs * n_rcv * table.n_segs:
+            raise ValueError("mask must be uint8 [n_jobs, n_rcv, n_segs]")
+    rc = _load().gbso_forward(*args, int(n_threads), int(mask_mode), _ptr(mask), _ptr(P), _ptr(TL))
+    if rc != 0:
+        raise RuntimeError(f"gbso_forward failed ({rc})")
+    return P[..., 0] + 1j * P[..., 1], TL
+
+
+def backward(table, gamma, rcv, freqs, eps, lam, c=343.0, gate=9.21, mask_mode=0, mask=None):
+    """Hand adjoint for dL = Re sum lam * dP.
+
+    Returns (d_gamma [n_faces, 2] = (dL/dRe, dL/dIm), d_rcv [n_rcv, 3],
+    d_eps [n_jobs])."""
+    args, arrs = _table_args(table, gamma, rcv, freqs, eps, c, gate)
+    n_jobs = table.n_src * arrs["freqs"].shape[0]
+    n_rcv = arrs["rcv"].shape[0]
+    lam = np.asarray(lam, np.complex128).reshape(n_jobs, n_rcv)
+    lam_ri = np.ascontiguousarray(np.stack([lam.real, lam.imag], axis=-1))
+    d_gamma = np.zeros((table.n_faces, 2), np.float64)
+    d_rcv = np.zeros((n_rcv, 3), np.float64)
+    d_eps = np.zeros(n_jobs, np.float64)
+    rc = _load().gbso_backward(*args, _ptr(lam_ri), int(mask_mode), _ptr(mask), _ptr(d_gamma), _ptr(d_rcv),
+                               _ptr(d_eps))
+    if rc != 0:
+        raise RuntimeError(f"gbso_backward failed ({rc})")
+    return d_gamma, d_rcv, d_eps
+
+
+def scene_forward(scene, rcv=None, gamma=None, eps=None, n_threads=1):
+    """Forward on a scenes.Scene (optionally a receiver subset / other gamma)."""
+    return forward(scene.table, scene.gamma if gamma is None else gamma, scene.rcv if rcv is None else rcv,
+                   scene.freqs, scene.eps if eps is None else eps, c=scene.c, gate=scene.gate,
+                   n_threads=n_threads)

@@ -1,0 +1,270 @@
+/*
+ * Plain FP64 reference ("oracle") for Gaussian beam summation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * definition that the HIP library is checked against.  It shares no code,
+ * header, table or constant with the library; only the tests, the smoke
+ * check and the benchmark's CPU-baseline leg may load it.
+ *
+ * What it computes (paper Sec. 2):
+ *
+ *   Eq. (1) gives the field of one Gaussian beam in ray-centred coordinates,
+ *   amplitude sqrt(det Q0 / det Q) and exponent
+ *   i*omega*(tau + 1/2 q^T (P Q^-1) q).  We take the isotropic 3-D beam
+ *   P = p I, Q = q I, so det Q0 / det Q = (q0/q)^2 and the amplitude is q0/q.
+ *
+ *   Eq. (2) (dQ/ds = c P, dP/ds = 0) in a homogeneous medium gives p = 1/c
+ *   constant and q(s) = q0 + s with q0 = -i*eps (eps > 0: the beam decays away
+ *   from its axis under the exp(-i omega t) convention of Eq. (1)).
+ *
+ *   Eq. (3) sums beams over the launch parameters with a weighting function.
+ *   Discretised over rays j with launch solid angle w_j, the weight per ray is
+ *   (i k / 2 pi) w_j / (4 pi): the stationary-phase value of the beam integral
+ *   that reproduces a unit monopole exp(i k r) / (4 pi r) in free field.
+ *   A reflected beam carries the product of the reflection coefficients of
+ *   the faces it has hit (angle independent).
+ *
+ * For receiver R and segment j (start a, unit axis t, arc length s0 at a,
+ * beam interval [lo, hi) in sigma):
+ *
+ *   sigma = (R - a).t        keep iff lo <= sigma < hi
+ *   n^2   = |R - a|^2 - sigma^2            (squared normal distance)
+ *   s     = s0 + sigma,  q = q0 + s,  tau = s / c
+ *   E     = i omega (tau + 1/2 (p/q) n^2)  keep iff Re E >= -G
+ *   u     = (i k w_j / (8 pi^2)) * prod Gamma * (q0 / q) * exp(E)
+ *   P(R)  = sum_j u,   TL = -20 log10 |P|
+ *
+ * Sums are Neumaier-compensated, in table order.  Jobs are (source, band)
+ * pairs, job = src * n_freq + band; eps is given per job.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+#define PI 3.14159265358979323846
+
+/* Neumaier (improved Kahan) running sum of doubles. */
+typedef struct { double sum, comp; } nsum;
+
+static void nsum_add(nsum* a, double x) {
+    double t = a->sum + x;
+    if (fabs(a->sum) >= fabs(x))
+        a->comp += (a->sum - t) + x;
+    else
+        a->comp += (x - t) + a->sum;
+    a->sum = t;
+}
+
+static double nsum_get(const nsum* a) { return a->sum + a->comp; }
+
+/* Product of the reflection coefficients of the faces a segment has hit. */
+static cplx face_product(const int64_t* face_ptr, const int32_t* face_ids, const double* gamma, int64_t j) {
+    cplx g = 1.0;
+    for (int64_t m = face_ptr[j]; m < face_ptr[j + 1]; ++m) {
+        int32_t f = face_ids[m];
+        g *= gamma[2 * f] + I * gamma[2 * f + 1];
+    }
+    return g;
+}
+
+/* Derivative of the face product with respect to Gamma_f (holomorphic):
+ * sum over the occurrences of f of the product of the other factors. */
+static cplx face_product_deriv(const int64_t* face_ptr, const int32_t* face_ids, const double* gamma,
+                               int64_t j, int32_t f) {
+    cplx d = 0.0;
+    for (int64_t l = face_ptr[j]; l < face_ptr[j + 1]; ++l) {
+        if (face_ids[l] != f) continue;
+        cplx others = 1.0;
+        for (int64_t m = face_ptr[j]; m < face_ptr[j + 1]; ++m) {
+            if (m == l) continue;
+            int32_t g = face_ids[m];
+            others *= gamma[2 * g] + I * gamma[2 * g + 1];
+        }
+        d += others;
+    }
+    return d;
+}
+
+/* Geometry of one (receiver, segment) pair; returns whether sigma lies in
+ * the segment's beam interval [lo, hi). */
+typedef struct {
+    double sigma, n2, s;
+    double v[3];      /* R - a */
+} pair_geom;
+
+static int pair_geometry(const double* R, const double* a, const double* t, double s0, double lo, double hi,
+                         pair_geom* g) {
+    g->v[0] = R[0] - a[0];
+    g->v[1] = R[1] - a[1];
+    g->v[2] = R[2] - a[2];
+    g->sigma = g->v[0] * t[0] + g->v[1] * t[1] + g->v[2] * t[2];
+    double vv = g->v[0] * g->v[0] + g->v[1] * g->v[1] + g->v[2] * g->v[2];
+    g->n2 = vv - g->sigma * g->sigma;
+    if (g->n2 < 0.0) g->n2 = 0.0;
+    g->s = s0 + g->sigma;
+    return lo <= g->sigma && g->sigma < hi;
+}
+
+/* Beam exponent E = i omega (tau + 1/2 (p/q) n^2) and q for a pair. */
+static cplx beam_exponent(double omega, double c, double eps, double s, double n2, cplx* q_out) {
+    cplx q0 = -I * eps;
+    cplx q = q0 + s;
+    double p = 1.0 / c;
+    double tau = s / c;
+    *q_out = q;
+    return I * omega * (tau + 0.5 * (p / q) * n2);
+}
+
+/* mask_mode: 0 gate normally; 1 gate normally and record the active set in
+ * mask[job][rcv][seg]; 2 use the recorded active set instead of the gate
+ * (frozen-mask evaluation for finite differences). */
+int gbso_forward(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const double* ray_w,
+                 const int32_t* ray_src, int64_t n_segs, const double* seg_a, const double* seg_t,
+                 const double* seg_s0, const double* seg_lo, const double* seg_hi, const int64_t* face_ptr,
+                 const int32_t* face_ids, int32_t n_faces, const double* gamma, int64_t n_rcv,
+                 const double* rcv, int32_t n_freq, const double* freqs, const double* eps, double c,
+                 double gate_G, int32_t n_threads, int32_t mask_mode, uint8_t* mask, double* P_out,
+                 double* TL_out) {
+    (void)n_faces;
+    if (n_src < 0 || n_rays < 0 || n_segs < 0 || n_rcv < 0 || n_freq < 0 || c <= 0) return -1;
+    if (mask_mode != 0 && mask == NULL) return -1;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    for (int32_t src = 0; src < n_src; ++src) {
+        for (int32_t b = 0; b < n_freq; ++b) {
+            const int64_t job = (int64_t)src * n_freq + b;
+            const double omega = 2.0 * PI * freqs[b];
+            const double k = omega / c;
+            const double e = eps[job];
+#pragma omp parallel for schedule(dynamic, 16) if (n_threads != 1)
+            for (int64_t r = 0; r < n_rcv; ++r) {
+                const double* R = rcv + 3 * r;
+                nsum re = {0, 0}, im = {0, 0};
+                for (int64_t i = 0; i < n_rays; ++i) {
+                    if (ray_src[i] != src) continue;
+                    const cplx weight = I * k * ray_w[i] / (8.0 * PI * PI);
+                    for (int64_t j = ray_ptr[i]; j < ray_ptr[i + 1]; ++j) {
+                        pair_geom g;
+                        int inside = pair_geometry(R, seg_a + 3 * j, seg_t + 3 * j, seg_s0[j], seg_lo[j],
+                                                   seg_hi[j], &g);
+                        cplx q;
+                        cplx E = beam_exponent(omega, c, e, g.s, g.n2, &q);
+                        int active = inside && creal(E) >= -gate_G;
+                        if (mask_mode == 1) mask[(job * n_rcv + r) * n_segs + j] = (uint8_t)active;
+                        if (mask_mode == 2) active = mask[(job * n_rcv + r) * n_segs + j];
+                        if (!active) continue;
+                        cplx q0 = -I * e;
+                        cplx u = weight * face_product(face_ptr, face_ids, gamma, j) * (q0 / q) * cexp(E);
+                        nsum_add(&re, creal(u));
+                        nsum_add(&im, cimag(u));
+                    }
+                }
+                double pr = nsum_get(&re), pi = nsum_get(&im);
+                P_out[2 * (job * n_rcv + r)] = pr;
+                P_out[2 * (job * n_rcv + r) + 1] = pi;
+                double mag = hypot(pr, pi);
+                TL_out[job * n_rcv + r] = mag > 0 ? -20.0 * log10(mag) : INFINITY;
+            }
+        }
+    }
+    return 0;
+}
+
+/*
+ * Hand-derived adjoint.  With dL = Re sum_{job,r} lambda[job,r] dP[job,r]:
+ *
+ *   d ln u / dR   = t (ik - 1/q - (ik/2) n^2 / q^2) + (ik/q) nvec,
+ *                   nvec = (R - a) - sigma t   (dq/dR = t, d(n^2)/dR = 2 nvec)
+ *   d ln u / deps = 1/eps + i/q - (k/2) n^2 / q^2
+ *                   (weight*q0 is proportional to eps; dq/deps = -i)
+ *   dP / dGamma_f = sum_j (d prod Gamma_j / dGamma_f) * u_j / prod Gamma_j
+ *                   computed without dividing: u_j / prod Gamma_j is the
+ *                   beam term with the coefficient product left out.
+ *
+ * Outputs: d_rcv[r][3] = Re(sum_job lambda * sum_j u * dln u/dR);
+ *          d_eps[job]  = Re(sum_r lambda * sum_j u * dln u/deps);
+ *          d_gamma[f]  = (Re Z_f, -Im Z_f) = (dL/dRe Gamma_f, dL/dIm Gamma_f),
+ *          Z_f = sum_{job,r} lambda * dP/dGamma_f.
+ * The gate is taken as fixed (almost-everywhere derivative); mask_mode 2
+ * uses a recorded active set.
+ */
+int gbso_backward(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const double* ray_w,
+                  const int32_t* ray_src, int64_t n_segs, const double* seg_a, const double* seg_t,
+                  const double* seg_s0, const double* seg_lo, const double* seg_hi, const int64_t* face_ptr,
+                  const int32_t* face_ids, int32_t n_faces, const double* gamma, int64_t n_rcv,
+                  const double* rcv, int32_t n_freq, const double* freqs, const double* eps, double c,
+                  double gate_G, const double* lambda, int32_t mask_mode, const uint8_t* mask,
+                  double* d_gamma, double* d_rcv, double* d_eps) {
+    if (n_src < 0 || n_rays < 0 || n_segs < 0 || n_rcv < 0 || n_freq < 0 || c <= 0) return -1;
+    if (mask_mode == 2 && mask == NULL) return -1;
+    cplx* Z = (cplx*)calloc((size_t)(n_faces > 0 ? n_faces : 1), sizeof(cplx));
+    if (!Z) return -2;
+    for (int64_t r = 0; r < n_rcv; ++r) d_rcv[3 * r] = d_rcv[3 * r + 1] = d_rcv[3 * r + 2] = 0.0;
+    for (int32_t src = 0; src < n_src; ++src) {
+        for (int32_t b = 0; b < n_freq; ++b) {
+            const int64_t job = (int64_t)src * n_freq + b;
+            const double omega = 2.0 * PI * freqs[b];
+            const double k = omega / c;
+            const double e = eps[job];
+            double deps_job = 0.0;
+            for (int64_t r = 0; r < n_rcv; ++r) {
+                const double* R = rcv + 3 * r;
+                const cplx lam = lambda[2 * (job * n_rcv + r)] + I * lambda[2 * (job * n_rcv + r) + 1];
+                for (int64_t i = 0; i < n_rays; ++i) {
+                    if (ray_src[i] != src) continue;
+                    const cplx weight = I * k * ray_w[i] / (8.0 * PI * PI);
+                    for (int64_t j = ray_ptr[i]; j < ray_ptr[i + 1]; ++j) {
+                        const double* a = seg_a + 3 * j;
+                        const double* t = seg_t + 3 * j;
+                        pair_geom g;
+                        int inside = pair_geometry(R, a, t, seg_s0[j], seg_lo[j], seg_hi[j], &g);
+                        cplx q;
+                        cplx E = beam_exponent(omega, c, e, g.s, g.n2, &q);
+                        int active = inside && creal(E) >= -gate_G;
+                        if (mask_mode == 2) active = mask[(job * n_rcv + r) * n_segs + j];
+                        if (!active) continue;
+                        cplx q0 = -I * e;
+                        cplx bare = weight * (q0 / q) * cexp(E);      /* beam term without prod Gamma */
+                        cplx gp = face_product(face_ptr, face_ids, gamma, j);
+                        cplx u = gp * bare;
+                        /* receiver gradient */
+                        double nvec[3] = {g.v[0] - g.sigma * t[0], g.v[1] - g.sigma * t[1], g.v[2] - g.sigma * t[2]};
+                        cplx ct = I * k - 1.0 / q - 0.5 * I * k * g.n2 / (q * q);
+                        cplx cn = I * k / q;
+                        for (int d = 0; d < 3; ++d) d_rcv[3 * r + d] += creal(lam * u * (ct * t[d] + cn * nvec[d]));
+                        /* beam-parameter gradient */
+                        deps_job += creal(lam * u * (1.0 / e + I / q - 0.5 * k * g.n2 / (q * q)));
+                        /* reflection-coefficient gradient */
+                        for (int64_t m = face_ptr[j]; m < face_ptr[j + 1]; ++m) {
+                            int32_t f = face_ids[m];
+                            /* count each distinct face once per segment */
+                            int seen = 0;
+                            for (int64_t mm = face_ptr[j]; mm < m; ++mm) seen |= (face_ids[mm] == f);
+                            if (seen) continue;
+                            Z[f] += lam * bare * face_product_deriv(face_ptr, face_ids, gamma, j, f);
+                        }
+                    }
+                }
+            }
+            d_eps[job] = deps_job;
+        }
+    }
+    for (int32_t f = 0; f < n_faces; ++f) {
+        d_gamma[2 * f] = creal(Z[f]);
+        d_gamma[2 * f + 1] = -cimag(Z[f]);
+    }
+    free(Z);
+    return 0;
+}
+
+int gbso_version(void) { return 1; }
