@@ -1,0 +1,202 @@
+/*
+ * libgbs: Gaussian beam summation on AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates the beam-summation stage of Gaussian beam tracing
+ * (paper Sec. 2, Eq. (3)): given a traced ray table and observers, it sums
+ * every nearby Gaussian beam (Eq. (1), with the dynamic-ray solution of
+ * Eq. (2)) into each observer's complex pressure, and reports transmission
+ * loss.  Inputs and outputs follow the paper's problem statement (Sec. 3.1
+ * and Sec. 4.2: source, traced environment and observation points in,
+ * pressure at the observation points out).
+ *
+ * Beam model.  For receiver R and segment j (start a, unit axis t, arc
+ * length s0 at a, beam interval [lo, hi) along sigma = (R - a).t):
+ *   n^2 = |R - a|^2 - sigma^2,  s = s0 + sigma,  q = s - i eps,  k = 2 pi f / c
+ *   u   = (i k w / (8 pi^2)) prod(Gamma) (-i eps / q) exp(i k s + (i k / 2) n^2 / q)
+ * kept iff lo <= sigma < hi and the Gaussian factor exp(-(k eps/2) n^2/|q|^2)
+ * is >= exp(-gate_G).  P(R) = sum over the kept pairs, TL = -20 log10 |P|.
+ * w is the launch solid angle of the segment's ray; prod(Gamma) the product of
+ * the complex reflection coefficients of the faces the ray hit before the
+ * segment.  A dense fan reproduces the unit monopole exp(ikr)/(4 pi r).
+ *
+ * Jobs.  A job is a (source, band) pair, job = src * n_freq + band; every job
+ * has its own beam parameter eps[job].  All jobs run in one persistent launch.
+ *
+ * Memory.  Unless a flag says otherwise every pointer is DEVICE memory on the
+ * context's device.  With GBS_FLAG_TABLE_HOST the ray and segment arrays are
+ * host memory and are streamed to the device in chunks of at most
+ * params.chunk_segs segments.  The caller owns every input and output; inputs
+ * are read-only, outputs are caller-allocated and fully overwritten.  The
+ * library never frees caller memory and keeps no caller pointer after a call
+ * returns, except for graphs (gbs_graph_*), which hold the pointers given at
+ * creation until gbs_graph_destroy.
+ *
+ * Errors.  Every entry point returns GBS_OK (0) or a negative gbs_status;
+ * gbs_last_error() describes the last failure on the context.  Argument
+ * checks run on the host before any device work.  No C++ exception crosses
+ * this interface.  Calls on one context are not thread-safe; use one context
+ * per host thread.  Work is enqueued on the context's stream; outputs are
+ * complete when that stream is synchronised.
+ */
+#ifndef GBS_H
+#define GBS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GBS_VERSION 1
+
+typedef enum gbs_status {
+    GBS_OK = 0,
+    GBS_E_INVALID = -1,      /* bad argument (null, size, non-finite, range)     */
+    GBS_E_OOM = -2,          /* device or host allocation failed                */
+    GBS_E_HIP = -3,          /* a HIP runtime call failed (message has details) */
+    GBS_E_UNSUPPORTED = -4,  /* valid request this build does not support       */
+    GBS_E_STATE = -5         /* context/graph used in the wrong state           */
+} gbs_status;
+
+/* Arithmetic of the pair evaluation.
+ * F64: everything in FP64.
+ * MIX: geometry, arc length, normal distance and the phase in cycles with its
+ *      reduction modulo one in FP64; Gaussian weight, sine/cosine, amplitude
+ *      and complex products in FP32; per-receiver sums in FP64.
+ * F32: everything in FP32 (ablation). */
+typedef enum gbs_mode { GBS_MODE_F64 = 0, GBS_MODE_MIX = 1, GBS_MODE_F32 = 2 } gbs_mode;
+
+/* params.flags */
+#define GBS_FLAG_TABLE_HOST   1   /* ray/segment arrays are host memory: stream them */
+#define GBS_FLAG_VALIDATE     2   /* check table contents on the device first (syncs) */
+#define GBS_FLAG_COUNT_ACTIVE 4   /* count kept pairs into gbs_stats (slower)          */
+#define GBS_FLAG_TIME_KERNELS 8   /* time the pair kernel with HIP events (syncs)      */
+
+typedef struct gbs_ctx gbs_ctx;
+
+/* Rays: CSR over segments; rays sorted by source (ray_src non-decreasing). */
+typedef struct gbs_rays {
+    int32_t n_src;
+    int64_t n_rays;
+    const int64_t* ray_ptr;   /* [n_rays + 1], ray_ptr[0] = 0, last = n_segs   */
+    const double* ray_w;      /* [n_rays] launch solid angle of each ray (sr)  */
+    const int32_t* ray_src;   /* [n_rays] source index in [0, n_src)           */
+} gbs_rays;
+
+/* Segments: straight beam axes in table order (segments of ray i are
+ * ray_ptr[i] .. ray_ptr[i+1]-1). */
+typedef struct gbs_segs {
+    int64_t n_segs;
+    const double* a;          /* [n_segs * 3] start point (m)                  */
+    const double* t;          /* [n_segs * 3] unit axis direction              */
+    const double* s0;         /* [n_segs] arc length from the source at a (m)  */
+    const double* lo;         /* [n_segs] beam interval start in sigma (m)     */
+    const double* hi;         /* [n_segs] beam interval end, exclusive (m)     */
+    const int64_t* face_ptr;  /* [n_segs + 1] CSR into face_ids                */
+    const int32_t* face_ids;  /* faces hit before the segment, in hit order    */
+} gbs_segs;
+
+/* Faces: complex reflection coefficients (always device memory). */
+typedef struct gbs_faces {
+    int32_t n_faces;
+    const double* gamma;      /* [n_faces * 2] (re, im)                         */
+} gbs_faces;
+
+typedef struct gbs_params {
+    double c;                 /* speed of sound (m/s), > 0                       */
+    double gate_G;            /* Gaussian gate exponent, > 0 (9.21 ~ 1e-4)       */
+    int32_t mode;             /* gbs_mode                                        */
+    int32_t flags;            /* GBS_FLAG_*                                      */
+    int64_t chunk_segs;       /* max segments per pass; 0 = whole table          */
+    int32_t rcv_per_lane;     /* pair kernel receivers per lane: 0 auto, 1, 2, 4 */
+    int32_t reserved;         /* must be 0                                       */
+} gbs_params;
+
+/* Plan statistics of the last forward/backward call on a context. */
+typedef struct gbs_stats {
+    int64_t dense_pairs;      /* sum over jobs of segments x receivers           */
+    int64_t listed_pairs;     /* (segment, receiver) pairs left after culling    */
+    int64_t active_pairs;     /* pairs kept by the gate (GBS_FLAG_COUNT_ACTIVE)  */
+    int64_t n_items;          /* work items of the persistent pair kernel        */
+    int32_t n_chunks;         /* passes over the table                           */
+    int32_t patch_rcv;        /* receivers per work item                         */
+    double ms_pairs;          /* pair-kernel time, all passes (GBS_FLAG_TIME_KERNELS) */
+    double ms_cull;           /* culling/list-building time (GBS_FLAG_TIME_KERNELS)   */
+} gbs_stats;
+
+/* Create a context on `device` (HIP ordinal) that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the context. */
+int gbs_create(gbs_ctx** out, int device, void* hip_stream);
+
+/* Release library-owned device scratch.  Safe on NULL. */
+void gbs_destroy(gbs_ctx* ctx);
+
+/* Change the stream later calls enqueue on. */
+int gbs_set_stream(gbs_ctx* ctx, void* hip_stream);
+
+/*
+ * Forward beam summation (Eq. (3) discretised over the rays).
+ *   rcv   [n_rcv * 3]            receiver positions (m)
+ *   freqs [n_freq]               band frequencies (Hz), > 0
+ *   eps   [n_src * n_freq]       beam parameter per job (m), > 0
+ *   P     [n_src*n_freq*n_rcv*2] out: complex pressure (re, im), job-major
+ *   TL    [n_src*n_freq*n_rcv]   out: -20 log10 |P| (+inf where P = 0); may be NULL
+ * Deterministic: repeated calls with equal inputs give bitwise-equal P.
+ */
+int gbs_forward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces,
+                const double* rcv, int64_t n_rcv, const double* freqs, int32_t n_freq, const double* eps,
+                const gbs_params* params, double* P, double* TL);
+
+/*
+ * Adjoint of gbs_forward for dL = Re sum_{job,r} lambda[job,r] * dP[job,r],
+ * with the ray geometry and the gate's active set held fixed.
+ *   lambda  [n_src*n_freq*n_rcv*2]  (re, im)
+ *   d_gamma [n_faces * 2]  out: (dL/dRe Gamma_f, dL/dIm Gamma_f)
+ *   d_rcv   [n_rcv * 3]    out: dL/dR
+ *   d_eps   [n_src*n_freq] out: dL/deps per job
+ * Any output pointer may be NULL to skip it.  Sums of per-segment terms use
+ * FP64 atomics: results agree to rounding but are not bitwise repeatable.
+ */
+int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces,
+                 const double* rcv, int64_t n_rcv, const double* freqs, int32_t n_freq, const double* eps,
+                 const gbs_params* params, const double* lambda, double* d_gamma, double* d_rcv,
+                 double* d_eps);
+
+/* Statistics of the last gbs_forward / gbs_backward on ctx. */
+int gbs_get_stats(const gbs_ctx* ctx, gbs_stats* out);
+
+/*
+ * Graphs: capture one forward call (all jobs, one persistent launch) into a
+ * hipGraph and replay it.  Creation runs the full plan once (receiver
+ * ordering, culling, work lists) and captures the per-call kernels.  Between
+ * replays the caller may change the CONTENTS of faces->gamma, but not the
+ * geometry, receivers, frequencies or eps (the culled work lists are baked in).
+ * The graph holds the pointers given at creation.
+ */
+typedef struct gbs_graph gbs_graph;
+int gbs_graph_create(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces,
+                     const double* rcv, int64_t n_rcv, const double* freqs, int32_t n_freq, const double* eps,
+                     const gbs_params* params, double* P, double* TL, gbs_graph** out);
+int gbs_graph_launch(gbs_graph* g);
+void gbs_graph_destroy(gbs_graph* g);
+
+/*
+ * Autotuner: times candidate pair-kernel shapes (receivers per lane) on the
+ * given problem and stores the fastest in the context (used when
+ * params.rcv_per_lane == 0).  Writes the choice to *rcv_per_lane if non-NULL.
+ */
+int gbs_autotune(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces,
+                 const double* rcv, int64_t n_rcv, const double* freqs, int32_t n_freq, const double* eps,
+                 const gbs_params* params, double* P, int32_t* rcv_per_lane);
+
+/* Message describing the last error on ctx (never NULL). */
+const char* gbs_last_error(const gbs_ctx* ctx);
+
+/* GBS_VERSION of the built library. */
+int gbs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GBS_H */

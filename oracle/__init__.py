@@ -38,7 +38,7 @@ def _load():
         P = ctypes.c_void_p
         i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         common = [i32, i64, P, P, P, i64, P, P, P, P, P, P, P, i32, P, i64, P, i32, P, P, f64, f64]
-        lib.gbso_forward.argtypes = common + [i32, i32, P, P, P]
+        lib.gbso_forward.argtypes = common + [i32, i32, P, P, P, P]
         lib.gbso_forward.restype = ctypes.c_int
         lib.gbso_backward.argtypes = common + [P, i32, P, P, P, P]
         lib.gbso_backward.restype = ctypes.c_int
@@ -79,12 +79,14 @@ def _table_args(table, gamma, rcv, freqs, eps, c, gate):
     return args, arrs
 
 
-def forward(table, gamma, rcv, freqs, eps, c=343.0, gate=9.21, n_threads=1, mask_mode=0, mask=None):
+def forward(table, gamma, rcv, freqs, eps, c=343.0, gate=9.21, n_threads=1, mask_mode=0, mask=None,
+            return_absum=False):
     """P [n_jobs, n_rcv] complex128 and TL [n_jobs, n_rcv] float64.
 
     mask_mode 1 records the active (job, receiver, segment) set into `mask`
     (uint8, shape [n_jobs, n_rcv, n_segs]); mask_mode 2 evaluates with that set
-    frozen instead of the gate.
+    frozen instead of the gate.  return_absum adds sum |u| per output (the
+    scale against which cancellation in P is judged).
     """
     args, arrs = _table_args(table, gamma, rcv, freqs, eps, c, gate)
     n_jobs = table.n_src * arrs["freqs"].shape[0]
@@ -94,9 +96,12 @@ def forward(table, gamma, rcv, freqs, eps, c=343.0, gate=9.21, n_threads=1, mask
     if mask_mode:
         if mask is None or mask.dtype != np.uint8 or mask.size != n_jobs * n_rcv * table.n_segs:
             raise ValueError("mask must be uint8 [n_jobs, n_rcv, n_segs]")
-    rc = _load().gbso_forward(*args, int(n_threads), int(mask_mode), _ptr(mask), _ptr(P), _ptr(TL))
+    absum = np.zeros((n_jobs, n_rcv), np.float64) if return_absum else None
+    rc = _load().gbso_forward(*args, int(n_threads), int(mask_mode), _ptr(mask), _ptr(P), _ptr(TL), _ptr(absum))
     if rc != 0:
         raise RuntimeError(f"gbso_forward failed ({rc})")
+    if return_absum:
+        return P[..., 0] + 1j * P[..., 1], TL, absum
     return P[..., 0] + 1j * P[..., 1], TL
 
 
@@ -120,8 +125,8 @@ def backward(table, gamma, rcv, freqs, eps, lam, c=343.0, gate=9.21, mask_mode=0
     return d_gamma, d_rcv, d_eps
 
 
-def scene_forward(scene, rcv=None, gamma=None, eps=None, n_threads=1):
+def scene_forward(scene, rcv=None, gamma=None, eps=None, n_threads=1, return_absum=False):
     """Forward on a scenes.Scene (optionally a receiver subset / other gamma)."""
     return forward(scene.table, scene.gamma if gamma is None else gamma, scene.rcv if rcv is None else rcv,
                    scene.freqs, scene.eps if eps is None else eps, c=scene.c, gate=scene.gate,
-                   n_threads=n_threads)
+                   n_threads=n_threads, return_absum=return_absum)

@@ -35,7 +35,9 @@
  *   P(R)  = sum_j u,   TL = -20 log10 |P|
  *
  * Sums are Neumaier-compensated, in table order.  Jobs are (source, band)
- * pairs, job = src * n_freq + band; eps is given per job.
+ * pairs, job = src * n_freq + band; eps is given per job.  Optionally the
+ * sum of |u| is returned: |P| / sum |u| measures the cancellation in the sum
+ * (near interference nulls it is small and TL is ill-conditioned).
  */
 #include <complex.h>
 #include <math.h>
@@ -131,7 +133,7 @@ int gbso_forward(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const do
                  const int32_t* face_ids, int32_t n_faces, const double* gamma, int64_t n_rcv,
                  const double* rcv, int32_t n_freq, const double* freqs, const double* eps, double c,
                  double gate_G, int32_t n_threads, int32_t mask_mode, uint8_t* mask, double* P_out,
-                 double* TL_out) {
+                 double* TL_out, double* absum_out) {
     (void)n_faces;
     if (n_src < 0 || n_rays < 0 || n_segs < 0 || n_rcv < 0 || n_freq < 0 || c <= 0) return -1;
     if (mask_mode != 0 && mask == NULL) return -1;
@@ -149,7 +151,7 @@ int gbso_forward(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const do
 #pragma omp parallel for schedule(dynamic, 16) if (n_threads != 1)
             for (int64_t r = 0; r < n_rcv; ++r) {
                 const double* R = rcv + 3 * r;
-                nsum re = {0, 0}, im = {0, 0};
+                nsum re = {0, 0}, im = {0, 0}, ab = {0, 0};
                 for (int64_t i = 0; i < n_rays; ++i) {
                     if (ray_src[i] != src) continue;
                     const cplx weight = I * k * ray_w[i] / (8.0 * PI * PI);
@@ -167,9 +169,11 @@ int gbso_forward(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const do
                         cplx u = weight * face_product(face_ptr, face_ids, gamma, j) * (q0 / q) * cexp(E);
                         nsum_add(&re, creal(u));
                         nsum_add(&im, cimag(u));
+                        nsum_add(&ab, cabs(u));
                     }
                 }
                 double pr = nsum_get(&re), pi = nsum_get(&im);
+                if (absum_out) absum_out[job * n_rcv + r] = nsum_get(&ab);
                 P_out[2 * (job * n_rcv + r)] = pr;
                 P_out[2 * (job * n_rcv + r) + 1] = pi;
                 double mag = hypot(pr, pi);

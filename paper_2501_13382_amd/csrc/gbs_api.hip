@@ -1,0 +1,930 @@
+// Host side of libgbs: C ABI, argument validation, planning (receiver
+// ordering, passes over the table, culled work lists), launches, graphs and
+// the autotuner.  See include/gbs.h for the contract of every entry point.
+#include "gbs.h"
+#include "gbs_internal.h"
+
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+// kernels (gbs_kernels.hip)
+namespace gbs {
+__global__ void k_fill_f64(double*, int64_t, double);
+__global__ void k_reset_counter(unsigned*);
+__global__ void k_bbox_partial(const double*, int64_t, double*);
+__global__ void k_bbox_final(const double*, int, double*);
+__global__ void k_morton(const double*, int64_t, const double*, uint32_t*, int32_t*);
+__global__ void k_gather_rcv(const double*, int64_t, int64_t, const int32_t*, double*, double*, double*, double*,
+                             int32_t*);
+__global__ void k_patches(const double*, const double*, const double*, int64_t, int64_t, int, Patch*);
+__global__ void k_src_ranges(const int64_t*, const int32_t*, int64_t, int32_t, int64_t*);
+__global__ void k_seg2ray(const int64_t*, int64_t, int64_t, int64_t, int32_t*);
+__global__ void k_records(int64_t, const double*, const double*, const double*, const double*, const double*,
+                          const int64_t*, int64_t, const int32_t*, int32_t, const double*, const double*,
+                          const int32_t*, SegRec*);
+template <bool FILL>
+__global__ void k_cull(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int32_t*, const int64_t*,
+                       int32_t*);
+template <int MODE, int NR, bool COUNT>
+__global__ void k_pairs(const JobConst*, const int64_t*, const int32_t*, int32_t, int32_t, unsigned*,
+                        const int32_t*, const SegRec*, const double*, const double*, const double*, const double*,
+                        const int32_t*, int64_t, double*, unsigned long long*);
+__global__ void k_tl(const double*, int64_t, double*);
+template <int MODE>
+__global__ void k_adjoint(const JobConst*, const int64_t*, const int32_t*, int32_t, int32_t, unsigned*,
+                          const int32_t*, const SegRec*, const double*, const double*, const double*,
+                          const double*, const int32_t*, int64_t, const double*, double*, double*, double*);
+__global__ void k_sum_jobs(const double*, int32_t, int64_t, double*);
+__global__ void k_face_scatter(int64_t, const int64_t*, int64_t, const int32_t*, int32_t, const double*,
+                               const double*, const int32_t*, const double*, double*);
+__global__ void k_dgamma(const double*, int32_t, double*);
+__global__ void k_validate(int64_t, const double*, const double*, const double*, const int64_t*, int64_t,
+                           const int32_t*, int32_t, int*);
+}  // namespace gbs
+
+using namespace gbs;
+
+namespace {
+
+struct GbsError : std::runtime_error {
+    int code;
+    GbsError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define GBS_HIP(call)                                                                                     \
+    do {                                                                                                  \
+        hipError_t e_ = (call);                                                                           \
+        if (e_ != hipSuccess)                                                                             \
+            throw GbsError(e_ == hipErrorOutOfMemory ? GBS_E_OOM : GBS_E_HIP,                             \
+                           std::string(#call) + ": " + hipGetErrorString(e_));                            \
+    } while (0)
+
+#define GBS_CHECK(cond, msg)                                   \
+    do {                                                       \
+        if (!(cond)) throw GbsError(GBS_E_INVALID, (msg));     \
+    } while (0)
+
+inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)std::max<int64_t>(1, (n + threads - 1) / threads); }
+
+// Grow-only device buffers, keyed by name.
+struct Workspace {
+    std::map<std::string, std::pair<void*, size_t>> bufs;
+    hipStream_t stream = nullptr;
+    ~Workspace() { release(); }
+    void release() {
+        for (auto& kv : bufs)
+            if (kv.second.first) (void)hipFree(kv.second.first);
+        bufs.clear();
+    }
+    template <typename T>
+    T* get(const std::string& name, size_t count) {
+        size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+        auto& b = bufs[name];
+        if (b.second < bytes) {
+            if (b.first) {
+                GBS_HIP(hipStreamSynchronize(stream));
+                GBS_HIP(hipFree(b.first));
+                b.first = nullptr;
+                b.second = 0;
+            }
+            size_t cap = bytes + bytes / 4;
+            GBS_HIP(hipMalloc(&b.first, cap));
+            b.second = cap;
+        }
+        return static_cast<T*>(b.first);
+    }
+};
+
+struct RcvPlan {
+    int64_t n = 0, n_pad = 0;
+    int per = 0;                 // receivers per patch
+    int n_patch = 0, n_super = 0;
+    double *rx = nullptr, *ry = nullptr, *rz = nullptr, *r2 = nullptr;
+    int32_t* perm = nullptr;
+    Patch* patches = nullptr;
+    Patch* supers = nullptr;
+};
+
+struct PassRange {
+    int64_t ray_begin, ray_end, seg_begin, seg_end, face_begin, face_end;
+};
+
+}  // namespace
+
+struct gbs_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int n_cu = 0;
+    std::string err;
+    gbs_stats stats{};
+    std::unique_ptr<Workspace> ws{new Workspace};
+    int tuned_nr[3] = {0, 0, 0};
+    void* pinned = nullptr;
+    size_t pinned_cap = 0;
+};
+
+struct gbs_graph {
+    gbs_ctx* ctx = nullptr;
+    std::unique_ptr<Workspace> ws{new Workspace};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void set_err(gbs_ctx* ctx, const std::string& m) {
+    if (ctx) ctx->err = m;
+}
+
+template <typename F>
+int guarded(gbs_ctx* ctx, F&& f) {
+    try {
+        int rc = f();
+        if (rc == GBS_OK && ctx) ctx->err.clear();
+        return rc;
+    } catch (const GbsError& e) {
+        set_err(ctx, e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_err(ctx, "host allocation failed");
+        return GBS_E_OOM;
+    } catch (const std::exception& e) {
+        set_err(ctx, e.what());
+        return GBS_E_HIP;
+    } catch (...) {
+        set_err(ctx, "unknown failure");
+        return GBS_E_HIP;
+    }
+}
+
+void* pinned_staging(gbs_ctx* ctx, size_t bytes) {
+    if (ctx->pinned_cap < bytes) {
+        if (ctx->pinned) {
+            GBS_HIP(hipStreamSynchronize(ctx->stream));
+            GBS_HIP(hipHostFree(ctx->pinned));
+            ctx->pinned = nullptr;
+            ctx->pinned_cap = 0;
+        }
+        size_t cap = std::max<size_t>(bytes, 1 << 16);
+        GBS_HIP(hipHostMalloc(&ctx->pinned, cap, hipHostMallocDefault));
+        ctx->pinned_cap = cap;
+    }
+    return ctx->pinned;
+}
+
+// ------------------------------------------------------------- validation
+struct Args {
+    const gbs_rays* rays;
+    const gbs_segs* segs;
+    const gbs_faces* faces;
+    const double* rcv;
+    int64_t n_rcv;
+    const double* freqs;
+    int32_t n_freq;
+    const double* eps;
+    const gbs_params* params;
+};
+
+void validate_host(const Args& a) {
+    GBS_CHECK(a.rays && a.segs && a.faces && a.params, "null struct argument");
+    const gbs_params& p = *a.params;
+    GBS_CHECK(std::isfinite(p.c) && p.c > 0, "params.c must be finite and > 0");
+    GBS_CHECK(std::isfinite(p.gate_G) && p.gate_G > 0, "params.gate_G must be finite and > 0");
+    GBS_CHECK(p.mode == GBS_MODE_F64 || p.mode == GBS_MODE_MIX || p.mode == GBS_MODE_F32, "params.mode invalid");
+    GBS_CHECK((p.flags & ~(GBS_FLAG_TABLE_HOST | GBS_FLAG_VALIDATE | GBS_FLAG_COUNT_ACTIVE |
+                            GBS_FLAG_TIME_KERNELS)) == 0,
+              "params.flags has unknown bits");
+    GBS_CHECK(p.chunk_segs >= 0, "params.chunk_segs must be >= 0");
+    GBS_CHECK(p.rcv_per_lane == 0 || p.rcv_per_lane == 1 || p.rcv_per_lane == 2 || p.rcv_per_lane == 4,
+              "params.rcv_per_lane must be 0, 1, 2 or 4");
+    GBS_CHECK(p.reserved == 0, "params.reserved must be 0");
+    GBS_CHECK(a.rays->n_src >= 0 && a.rays->n_rays >= 0 && a.segs->n_segs >= 0 && a.n_rcv >= 0 && a.n_freq >= 0,
+              "negative size");
+    GBS_CHECK(a.faces->n_faces >= 0, "negative face count");
+    GBS_CHECK(a.n_rcv <= (int64_t)INT32_MAX - 4096, "too many receivers");
+    GBS_CHECK(a.segs->n_segs <= (int64_t)INT32_MAX, "too many segments");
+    GBS_CHECK(a.rays->n_rays == 0 || a.rays->n_src > 0, "rays without sources");
+    if (a.rays->n_rays > 0)
+        GBS_CHECK(a.rays->ray_ptr && a.rays->ray_w && a.rays->ray_src, "null ray array");
+    if (a.rays->n_rays == 0) GBS_CHECK(a.segs->n_segs == 0, "segments without rays");
+    GBS_CHECK(a.rays->ray_ptr || a.rays->n_rays == 0, "null ray_ptr");
+    if (a.segs->n_segs > 0)
+        GBS_CHECK(a.segs->a && a.segs->t && a.segs->s0 && a.segs->lo && a.segs->hi && a.segs->face_ptr,
+                  "null segment array");
+    if (a.faces->n_faces > 0) GBS_CHECK(a.faces->gamma, "null gamma");
+    if (a.n_rcv > 0) GBS_CHECK(a.rcv, "null receivers");
+    if (a.n_freq > 0) GBS_CHECK(a.freqs && a.eps, "null freqs/eps");
+}
+
+// ------------------------------------------------------------- planning
+struct Planner {
+    gbs_ctx* ctx;
+    Workspace& ws;
+    hipStream_t st;
+    const Args& a;
+    int mode, nr;
+    int n_jobs;
+    std::vector<double> h_freqs, h_eps;
+    std::vector<int64_t> src_off;     // [n_src + 1] first segment of each source
+    std::vector<PassRange> passes;
+    std::vector<int64_t> h_ray_ptr, h_face_ptr;  // host copies (only when chunking)
+    RcvPlan R;
+
+    Planner(gbs_ctx* c, Workspace& w, const Args& args, int nr_)
+        : ctx(c), ws(w), st(c->stream), a(args), mode(args.params->mode), nr(nr_) {
+        ws.stream = st;
+        n_jobs = a.rays->n_src * a.n_freq;
+    }
+
+    bool table_host() const { return (a.params->flags & GBS_FLAG_TABLE_HOST) != 0; }
+
+    void read_job_inputs() {
+        h_freqs.resize(a.n_freq);
+        h_eps.resize(n_jobs);
+        if (a.n_freq > 0) {
+            GBS_HIP(hipMemcpyAsync(h_freqs.data(), a.freqs, sizeof(double) * a.n_freq, hipMemcpyDeviceToHost, st));
+            if (n_jobs > 0)
+                GBS_HIP(hipMemcpyAsync(h_eps.data(), a.eps, sizeof(double) * n_jobs, hipMemcpyDeviceToHost, st));
+            GBS_HIP(hipStreamSynchronize(st));
+        }
+        for (double f : h_freqs) GBS_CHECK(std::isfinite(f) && f > 0, "frequencies must be finite and > 0");
+        for (double e : h_eps) GBS_CHECK(std::isfinite(e) && e > 0, "eps must be finite and > 0");
+    }
+
+    void source_offsets() {
+        const int32_t n_src = a.rays->n_src;
+        const int64_t n_rays = a.rays->n_rays;
+        src_off.assign(n_src + 1, 0);
+        if (n_src == 0) return;
+        if (table_host()) {
+            const int64_t* rp = a.rays->ray_ptr;
+            const int32_t* rs = a.rays->ray_src;
+            GBS_CHECK(rp[0] == 0 && rp[n_rays] == a.segs->n_segs, "ray_ptr must span the segments");
+            for (int64_t i = 0; i <= n_rays; ++i) {
+                int32_t prev = i == 0 ? -1 : rs[i - 1];
+                int32_t cur = i == n_rays ? n_src : rs[i];
+                GBS_CHECK(i == n_rays || (cur >= 0 && cur < n_src), "ray_src out of range");
+                GBS_CHECK(cur >= prev, "rays must be sorted by source");
+                if (i < n_rays) GBS_CHECK(rp[i + 1] >= rp[i], "ray_ptr must be non-decreasing");
+                for (int32_t s = prev + 1; s <= cur; ++s) src_off[s] = rp[i];
+            }
+            return;
+        }
+        int64_t* d_off = ws.get<int64_t>("src_off", n_src + 1);
+        if (n_rays > 0) {
+            hipLaunchKernelGGL(k_src_ranges, dim3(blocks_for(n_rays + 1, 256)), dim3(256), 0, st,
+                               a.rays->ray_ptr, a.rays->ray_src, n_rays, n_src, d_off);
+            GBS_HIP(hipGetLastError());
+            GBS_HIP(hipMemcpyAsync(src_off.data(), d_off, sizeof(int64_t) * (n_src + 1), hipMemcpyDeviceToHost, st));
+            GBS_HIP(hipStreamSynchronize(st));
+        }
+    }
+
+    void make_passes() {
+        const int64_t n_rays = a.rays->n_rays, n_segs = a.segs->n_segs;
+        const int64_t cs = a.params->chunk_segs;
+        passes.clear();
+        if (n_rays == 0) return;
+        bool chunk = table_host() || (cs > 0 && cs < n_segs);
+        if (!chunk) {
+            passes.push_back({0, n_rays, 0, n_segs, 0, 0});
+            return;
+        }
+        const int64_t* rp;
+        const int64_t* fp;
+        if (table_host()) {
+            rp = a.rays->ray_ptr;
+            fp = a.segs->face_ptr;
+        } else {
+            h_ray_ptr.resize(n_rays + 1);
+            h_face_ptr.resize(n_segs + 1);
+            GBS_HIP(hipMemcpyAsync(h_ray_ptr.data(), a.rays->ray_ptr, sizeof(int64_t) * (n_rays + 1),
+                                   hipMemcpyDeviceToHost, st));
+            GBS_HIP(hipMemcpyAsync(h_face_ptr.data(), a.segs->face_ptr, sizeof(int64_t) * (n_segs + 1),
+                                   hipMemcpyDeviceToHost, st));
+            GBS_HIP(hipStreamSynchronize(st));
+            rp = h_ray_ptr.data();
+            fp = h_face_ptr.data();
+        }
+        const int64_t limit = cs > 0 ? cs : n_segs;
+        int64_t r0 = 0;
+        while (r0 < n_rays) {
+            int64_t r1 = r0 + 1;
+            while (r1 < n_rays && rp[r1 + 1] - rp[r0] <= limit) ++r1;
+            passes.push_back({r0, r1, rp[r0], rp[r1], fp[rp[r0]], fp[rp[r1]]});
+            r0 = r1;
+        }
+    }
+
+    // Receivers in Morton order, padded to whole patches; patch and
+    // super-patch bounding spheres.
+    void plan_receivers(int per) {
+        R = RcvPlan{};
+        R.n = a.n_rcv;
+        R.per = per;
+        if (R.n == 0) return;
+        R.n_patch = (int)((R.n + per - 1) / per);
+        R.n_pad = (int64_t)R.n_patch * per;
+        R.n_super = (R.n_patch + kSuperPatches - 1) / kSuperPatches;
+        const int nb = (int)std::min<int64_t>(1024, blocks_for(R.n, 256));
+        double* part = ws.get<double>("bbox_part", 6 * nb);
+        double* bbox = ws.get<double>("bbox", 6);
+        hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(256), 0, st, a.rcv, R.n, part);
+        hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, part, nb, bbox);
+        uint32_t* keys = ws.get<uint32_t>("mkeys", R.n);
+        uint32_t* keys2 = ws.get<uint32_t>("mkeys2", R.n);
+        int32_t* vals = ws.get<int32_t>("mvals", R.n);
+        int32_t* vals2 = ws.get<int32_t>("mvals2", R.n);
+        hipLaunchKernelGGL(k_morton, dim3(blocks_for(R.n, 256)), dim3(256), 0, st, a.rcv, R.n, bbox, keys, vals);
+        size_t tmp = 0;
+        GBS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, keys, keys2, vals, vals2, (int)R.n, 0, 30, st));
+        void* t = ws.get<char>("cub_tmp_sort", tmp);
+        GBS_HIP(hipcub::DeviceRadixSort::SortPairs(t, tmp, keys, keys2, vals, vals2, (int)R.n, 0, 30, st));
+        R.rx = ws.get<double>("rx", R.n_pad);
+        R.ry = ws.get<double>("ry", R.n_pad);
+        R.rz = ws.get<double>("rz", R.n_pad);
+        R.r2 = ws.get<double>("r2", R.n_pad);
+        R.perm = ws.get<int32_t>("perm", R.n_pad);
+        hipLaunchKernelGGL(k_gather_rcv, dim3(blocks_for(R.n_pad, 256)), dim3(256), 0, st, a.rcv, R.n, R.n_pad,
+                           vals2, R.rx, R.ry, R.rz, R.r2, R.perm);
+        R.patches = ws.get<Patch>("patches", R.n_patch);
+        R.supers = ws.get<Patch>("supers", R.n_super);
+        hipLaunchKernelGGL(k_patches, dim3(R.n_patch), dim3(64), 0, st, R.rx, R.ry, R.rz, R.n_pad, (int64_t)per,
+                           R.n_patch, R.patches);
+        hipLaunchKernelGGL(k_patches, dim3(R.n_super), dim3(64), 0, st, R.rx, R.ry, R.rz, R.n_pad,
+                           (int64_t)per * kSuperPatches, R.n_super, R.supers);
+        GBS_HIP(hipGetLastError());
+    }
+
+    std::vector<JobConst> job_consts(const PassRange& ps) const {
+        std::vector<JobConst> J(n_jobs);
+        const double G = a.params->gate_G, c = a.params->c;
+        const double pi = 3.14159265358979323846;
+        for (int s = 0; s < a.rays->n_src; ++s)
+            for (int b = 0; b < a.n_freq; ++b) {
+                JobConst& j = J[s * a.n_freq + b];
+                const double f = h_freqs[b], e = h_eps[s * a.n_freq + b];
+                const double k = 2.0 * pi * f / c;
+                const double ke = k * e;
+                j.seg_begin = std::max(src_off[s], ps.seg_begin) - ps.seg_begin;
+                j.seg_end = std::min(src_off[s + 1], ps.seg_end) - ps.seg_begin;
+                if (j.seg_end < j.seg_begin) j.seg_end = j.seg_begin;
+                j.k = k;
+                j.eps = e;
+                j.eps2 = e * e;
+                j.gate_c1 = 1.0 + 2.0 * G / ke;
+                j.gate_c2 = 2.0 * G * e * e / ke;
+                j.kappa = 2.0 * G / ke;
+                j.fk = f / c;
+                j.hfk = 0.5 * f / c;
+                j.gexp2 = -0.5 * ke * 1.4426950408889634;
+                j.gexp = -0.5 * ke;
+                j.scale = ke / (8.0 * pi * pi);
+                j.src = s;
+                j.band = b;
+            }
+        return J;
+    }
+
+    // Device views of one pass of the table (copied in if the table is on the host).
+    struct PassView {
+        int64_t n_rays, n_segs;
+        const int64_t* ray_ptr;   // absolute offsets
+        const double* ray_w;
+        const double *a, *t, *s0, *lo, *hi;
+        const int64_t* face_ptr;  // absolute offsets into the full face_ids
+        int64_t face_base;
+        const int32_t* face_ids;  // starts at face_base
+    };
+
+    template <typename T>
+    const T* stage(const char* name, const T* src, int64_t count) {
+        T* d = ws.get<T>(name, std::max<int64_t>(count, 1));
+        if (count > 0) GBS_HIP(hipMemcpyAsync(d, src, sizeof(T) * count, hipMemcpyHostToDevice, st));
+        return d;
+    }
+
+    PassView view(const PassRange& ps) {
+        PassView v;
+        v.n_rays = ps.ray_end - ps.ray_begin;
+        v.n_segs = ps.seg_end - ps.seg_begin;
+        const gbs_segs& S = *a.segs;
+        if (!table_host()) {
+            v.ray_ptr = a.rays->ray_ptr + ps.ray_begin;
+            v.ray_w = a.rays->ray_w + ps.ray_begin;
+            v.a = S.a + 3 * ps.seg_begin;
+            v.t = S.t + 3 * ps.seg_begin;
+            v.s0 = S.s0 + ps.seg_begin;
+            v.lo = S.lo + ps.seg_begin;
+            v.hi = S.hi + ps.seg_begin;
+            v.face_ptr = S.face_ptr + ps.seg_begin;
+            v.face_base = 0;
+            v.face_ids = S.face_ids;
+            return v;
+        }
+        v.ray_ptr = stage("p_ray_ptr", a.rays->ray_ptr + ps.ray_begin, v.n_rays + 1);
+        v.ray_w = stage("p_ray_w", a.rays->ray_w + ps.ray_begin, v.n_rays);
+        v.a = stage("p_a", S.a + 3 * ps.seg_begin, 3 * v.n_segs);
+        v.t = stage("p_t", S.t + 3 * ps.seg_begin, 3 * v.n_segs);
+        v.s0 = stage("p_s0", S.s0 + ps.seg_begin, v.n_segs);
+        v.lo = stage("p_lo", S.lo + ps.seg_begin, v.n_segs);
+        v.hi = stage("p_hi", S.hi + ps.seg_begin, v.n_segs);
+        v.face_ptr = stage("p_face_ptr", S.face_ptr + ps.seg_begin, v.n_segs + 1);
+        v.face_base = ps.face_begin;
+        v.face_ids = stage("p_face_ids", S.face_ids ? S.face_ids + ps.face_begin : nullptr,
+                           ps.face_end - ps.face_begin);
+        return v;
+    }
+
+    struct Lists {
+        int32_t n_items = 0;
+        int64_t total = 0;
+        const JobConst* jobs = nullptr;
+        const SegRec* rec = nullptr;
+        const int32_t* seg_ray = nullptr;
+        const int64_t* item_off = nullptr;
+        const int32_t* item_order = nullptr;
+        const int32_t* lists = nullptr;
+    };
+
+    // Records, job constants, culled lists and the longest-first item order
+    // for one pass.  Synchronises once to size the lists.
+    Lists build_lists(const PassRange& ps, const PassView& v, int pass_idx) {
+        Lists L;
+        const int64_t nseg = v.n_segs;
+        int32_t* seg_ray = ws.get<int32_t>("seg_ray", nseg);
+        SegRec* rec = ws.get<SegRec>("rec", nseg);
+        if (nseg > 0) {
+            if (a.params->flags & GBS_FLAG_VALIDATE) {
+                int* bad = ws.get<int>("bad", 1);
+                GBS_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+                hipLaunchKernelGGL(k_validate, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, nseg, v.t, v.lo, v.hi,
+                                   v.face_ptr, v.face_base, v.face_ids, a.faces->n_faces, bad);
+                int hb = 0;
+                GBS_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+                GBS_HIP(hipStreamSynchronize(st));
+                GBS_CHECK(hb == 0, "segment table failed validation (non-unit t, lo > hi, or face id out of range)");
+            }
+            hipLaunchKernelGGL(k_seg2ray, dim3(blocks_for(v.n_rays, 256)), dim3(256), 0, st, v.ray_ptr, v.n_rays,
+                               ps.seg_begin, nseg, seg_ray);
+            hipLaunchKernelGGL(k_records, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, nseg, v.a, v.t, v.s0, v.lo,
+                               v.hi, v.face_ptr, v.face_base, v.face_ids, a.faces->n_faces, a.faces->gamma, v.ray_w,
+                               seg_ray, rec);
+            GBS_HIP(hipGetLastError());
+        }
+        L.rec = rec;
+        L.seg_ray = seg_ray;
+        std::vector<JobConst> J = job_consts(ps);
+        JobConst* dJ = ws.get<JobConst>("jobs" + std::to_string(pass_idx % 2), n_jobs);
+        void* h = pinned_staging(ctx, sizeof(JobConst) * n_jobs);
+        GBS_HIP(hipStreamSynchronize(st));  // the staging buffer may still feed an earlier copy
+        std::memcpy(h, J.data(), sizeof(JobConst) * n_jobs);
+        GBS_HIP(hipMemcpyAsync(dJ, h, sizeof(JobConst) * n_jobs, hipMemcpyHostToDevice, st));
+        L.jobs = dJ;
+        const int64_t n_items = (int64_t)n_jobs * R.n_patch;
+        GBS_CHECK(n_items < INT32_MAX, "too many work items");
+        L.n_items = (int32_t)n_items;
+        if (n_items == 0) return L;
+        int32_t* counts = ws.get<int32_t>("counts", n_items + 2);
+        int64_t* off = ws.get<int64_t>("item_off", n_items + 1);
+        hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for((n_items + 2) / 2, 256)), dim3(256), 0, st, (double*)counts,
+                           (int64_t)((n_items + 2) / 2), 0.0);
+        dim3 cg(R.n_super, n_jobs);
+        hipLaunchKernelGGL(k_cull<false>, cg, dim3(kCullThreads), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
+                           counts, nullptr, nullptr);
+        GBS_HIP(hipGetLastError());
+        // counts are int32; accumulate in int64 through a converting iterator
+        auto in64 = hipcub::TransformInputIterator<int64_t, Widen, const int32_t*>(counts, Widen());
+        size_t tmp = 0;
+        GBS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, in64, off, (int)(n_items + 1), st));
+        void* t = ws.get<char>("cub_tmp_scan", tmp);
+        GBS_HIP(hipcub::DeviceScan::ExclusiveSum(t, tmp, in64, off, (int)(n_items + 1), st));
+        GBS_HIP(hipMemcpyAsync(&L.total, off + n_items, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        GBS_HIP(hipStreamSynchronize(st));
+        int32_t* lists = ws.get<int32_t>("lists", std::max<int64_t>(L.total, 1));
+        hipLaunchKernelGGL(k_cull<true>, cg, dim3(kCullThreads), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
+                           nullptr, off, lists);
+        GBS_HIP(hipGetLastError());
+        // longest lists first
+        int32_t* keys2 = ws.get<int32_t>("okeys", n_items);
+        int32_t* ids = ws.get<int32_t>("oids", n_items);
+        int32_t* order = ws.get<int32_t>("order", n_items);
+        std::vector<int32_t> iota(n_items);
+        for (int64_t i = 0; i < n_items; ++i) iota[i] = (int32_t)i;
+        GBS_HIP(hipMemcpyAsync(ids, iota.data(), sizeof(int32_t) * n_items, hipMemcpyHostToDevice, st));
+        size_t tmp2 = 0;
+        GBS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tmp2, counts, keys2, ids, order, (int)n_items,
+                                                             0, 32, st));
+        void* t2 = ws.get<char>("cub_tmp_order", tmp2);
+        GBS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(t2, tmp2, counts, keys2, ids, order, (int)n_items, 0, 32,
+                                                             st));
+        GBS_HIP(hipStreamSynchronize(st));  // iota staging is pageable host memory
+        L.item_off = off;
+        L.item_order = order;
+        L.lists = lists;
+        return L;
+    }
+
+    struct Widen {
+        __host__ __device__ int64_t operator()(const int32_t& x) const { return (int64_t)x; }
+    };
+};
+
+// HIP events around a stretch of work on the context stream (only when
+// timing was requested; end() synchronises on the stop event).
+struct EventPair {
+    bool on;
+    hipEvent_t a = nullptr, b = nullptr;
+    explicit EventPair(bool enabled) : on(enabled) {
+        if (on) {
+            GBS_HIP(hipEventCreate(&a));
+            GBS_HIP(hipEventCreate(&b));
+        }
+    }
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    void begin(hipStream_t st) {
+        if (on) GBS_HIP(hipEventRecord(a, st));
+    }
+    double end(hipStream_t st) {
+        if (!on) return 0.0;
+        GBS_HIP(hipEventRecord(b, st));
+        GBS_HIP(hipEventSynchronize(b));
+        float ms = 0.f;
+        GBS_HIP(hipEventElapsedTime(&ms, a, b));
+        return ms;
+    }
+};
+
+int pick_nr(gbs_ctx* ctx, const gbs_params* p, int64_t n_rcv) {
+    if (p->rcv_per_lane) return p->rcv_per_lane;
+    if (ctx->tuned_nr[p->mode]) return ctx->tuned_nr[p->mode];
+    if (n_rcv < 64 * 256) return 1;
+    return p->mode == GBS_MODE_F64 ? 1 : 2;
+}
+
+template <int MODE, int NR, bool COUNT>
+void launch_pairs(gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const RcvPlan& R, int64_t n_rcv, double* P,
+                  unsigned* ctr, unsigned long long* n_active) {
+    auto kern = k_pairs<MODE, NR, COUNT>;
+    int per_cu = 0;
+    GBS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, 0));
+    int64_t grid = std::max(1, per_cu) * (int64_t)ctx->n_cu;
+    grid = std::min<int64_t>(grid, L.n_items);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, ctr);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), 0, st, L.jobs, L.item_off, L.item_order, L.n_items,
+                       R.n_patch, ctr, L.lists, L.rec, R.rx, R.ry, R.rz, R.r2, R.perm, n_rcv, P, n_active);
+    GBS_HIP(hipGetLastError());
+}
+
+template <int MODE, bool COUNT>
+void dispatch_nr(int nr, gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const RcvPlan& R, int64_t n_rcv,
+                 double* P, unsigned* ctr, unsigned long long* na) {
+    if (nr == 1) launch_pairs<MODE, 1, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na);
+    else if (nr == 2) launch_pairs<MODE, 2, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na);
+    else launch_pairs<MODE, 4, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na);
+}
+
+void dispatch_pairs(int mode, bool count, int nr, gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L,
+                    const RcvPlan& R, int64_t n_rcv, double* P, unsigned* ctr, unsigned long long* na) {
+    if (mode == GBS_MODE_F64) {
+        count ? dispatch_nr<0, true>(nr, ctx, st, L, R, n_rcv, P, ctr, na)
+              : dispatch_nr<0, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na);
+    } else if (mode == GBS_MODE_MIX) {
+        count ? dispatch_nr<1, true>(nr, ctx, st, L, R, n_rcv, P, ctr, na)
+              : dispatch_nr<1, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na);
+    } else {
+        count ? dispatch_nr<2, true>(nr, ctx, st, L, R, n_rcv, P, ctr, na)
+              : dispatch_nr<2, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na);
+    }
+}
+
+void fill(hipStream_t st, double* p, int64_t n, double v) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)std::min<int64_t>(4096, blocks_for(n, 256))), dim3(256), 0, st, p,
+                       n, v);
+}
+
+int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* TL, int nr_override) {
+    validate_host(a);
+    GBS_CHECK(P || (int64_t)a.rays->n_src * a.n_freq * a.n_rcv == 0, "null P");
+    const int nr = nr_override ? nr_override : pick_nr(ctx, a.params, a.n_rcv);
+    Planner pl(ctx, ws, a, nr);
+    hipStream_t st = ctx->stream;
+    const int64_t n_out = (int64_t)pl.n_jobs * a.n_rcv;
+    pl.read_job_inputs();
+    fill(st, P, 2 * n_out, 0.0);
+    gbs_stats stats{};
+    stats.patch_rcv = 64 * nr;
+    if (n_out > 0 && a.segs->n_segs > 0) {
+        pl.source_offsets();
+        for (int s = 0; s < a.rays->n_src; ++s)
+            stats.dense_pairs += (pl.src_off[s + 1] - pl.src_off[s]) * a.n_rcv * a.n_freq;
+        pl.make_passes();
+        pl.plan_receivers(64 * nr);
+        unsigned* ctr = ws.get<unsigned>("ctr", 1);
+        const bool count = (a.params->flags & GBS_FLAG_COUNT_ACTIVE) != 0;
+        unsigned long long* na = ws.get<unsigned long long>("n_active", 1);
+        if (count) GBS_HIP(hipMemsetAsync(na, 0, sizeof(unsigned long long), st));
+        const bool timed = (a.params->flags & GBS_FLAG_TIME_KERNELS) != 0;
+        EventPair ev_pairs(timed), ev_cull(timed);
+        for (size_t pi = 0; pi < pl.passes.size(); ++pi) {
+            const PassRange& ps = pl.passes[pi];
+            Planner::PassView v = pl.view(ps);
+            ev_cull.begin(st);
+            Planner::Lists L = pl.build_lists(ps, v, (int)pi);
+            stats.ms_cull += ev_cull.end(st);
+            stats.listed_pairs += L.total * (int64_t)pl.R.per;
+            stats.n_items += L.n_items;
+            if (L.n_items > 0 && L.total > 0) {
+                ev_pairs.begin(st);
+                dispatch_pairs(a.params->mode, count, nr, ctx, st, L, pl.R, a.n_rcv, P, ctr, na);
+                stats.ms_pairs += ev_pairs.end(st);
+            }
+        }
+        stats.n_chunks = (int32_t)pl.passes.size();
+        if (count) {
+            unsigned long long h = 0;
+            GBS_HIP(hipMemcpyAsync(&h, na, sizeof(h), hipMemcpyDeviceToHost, st));
+            GBS_HIP(hipStreamSynchronize(st));
+            stats.active_pairs = (int64_t)h;
+        }
+    }
+    if (TL && n_out > 0) {
+        hipLaunchKernelGGL(k_tl, dim3(blocks_for(n_out, 256)), dim3(256), 0, st, P, n_out, TL);
+        GBS_HIP(hipGetLastError());
+    }
+    ctx->stats = stats;
+    return GBS_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+int gbs_version(void) { return GBS_VERSION; }
+
+int gbs_create(gbs_ctx** out, int device, void* hip_stream) {
+    if (!out) return GBS_E_INVALID;
+    *out = nullptr;
+    gbs_ctx* ctx = nullptr;
+    try {
+        ctx = new gbs_ctx;
+    } catch (...) {
+        return GBS_E_OOM;
+    }
+    int rc = guarded(ctx, [&]() {
+        int n = 0;
+        GBS_HIP(hipGetDeviceCount(&n));
+        GBS_CHECK(device >= 0 && device < n, "device ordinal out of range");
+        GBS_HIP(hipSetDevice(device));
+        hipDeviceProp_t prop;
+        GBS_HIP(hipGetDeviceProperties(&prop, device));
+        ctx->device = device;
+        ctx->n_cu = prop.multiProcessorCount;
+        ctx->stream = (hipStream_t)hip_stream;
+        ctx->ws->stream = ctx->stream;
+        return GBS_OK;
+    });
+    if (rc != GBS_OK) {
+        delete ctx;
+        return rc;
+    }
+    *out = ctx;
+    return GBS_OK;
+}
+
+void gbs_destroy(gbs_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->ws.reset();
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+}
+
+int gbs_set_stream(gbs_ctx* ctx, void* hip_stream) {
+    if (!ctx) return GBS_E_INVALID;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->ws->stream = ctx->stream;
+    return GBS_OK;
+}
+
+const char* gbs_last_error(const gbs_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int gbs_get_stats(const gbs_ctx* ctx, gbs_stats* out) {
+    if (!ctx || !out) return GBS_E_INVALID;
+    *out = ctx->stats;
+    return GBS_OK;
+}
+
+int gbs_forward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces, const double* rcv,
+                int64_t n_rcv, const double* freqs, int32_t n_freq, const double* eps, const gbs_params* params,
+                double* P, double* TL) {
+    if (!ctx) return GBS_E_INVALID;
+    return guarded(ctx, [&]() {
+        GBS_HIP(hipSetDevice(ctx->device));
+        Args a{rays, segs, faces, rcv, n_rcv, freqs, n_freq, eps, params};
+        return forward_impl(ctx, *ctx->ws, a, P, TL, 0);
+    });
+}
+
+int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces, const double* rcv,
+                 int64_t n_rcv, const double* freqs, int32_t n_freq, const double* eps, const gbs_params* params,
+                 const double* lambda, double* d_gamma, double* d_rcv, double* d_eps) {
+    if (!ctx) return GBS_E_INVALID;
+    return guarded(ctx, [&]() {
+        GBS_HIP(hipSetDevice(ctx->device));
+        Args a{rays, segs, faces, rcv, n_rcv, freqs, n_freq, eps, params};
+        validate_host(a);
+        GBS_CHECK(params->mode != GBS_MODE_F32, "the adjoint supports F64 and MIX");
+        Workspace& ws = *ctx->ws;
+        Planner pl(ctx, ws, a, 1);
+        hipStream_t st = ctx->stream;
+        const int n_jobs = pl.n_jobs;
+        const int64_t n_out = (int64_t)n_jobs * n_rcv;
+        GBS_CHECK(lambda || n_out == 0, "null lambda");
+        pl.read_job_inputs();
+        const int32_t nf = faces->n_faces;
+        double* Zf = ws.get<double>("Zf", 2 * std::max(nf, 1));
+        double* dE = ws.get<double>("dE", std::max(n_jobs, 1));
+        double* dRj = ws.get<double>("dR_job", std::max<int64_t>(3 * n_out, 1));
+        fill(st, Zf, 2 * nf, 0.0);
+        fill(st, dE, n_jobs, 0.0);
+        fill(st, dRj, 3 * n_out, 0.0);
+        gbs_stats stats{};
+        stats.patch_rcv = 64;
+        if (n_out > 0 && segs->n_segs > 0) {
+            pl.source_offsets();
+            pl.make_passes();
+            pl.plan_receivers(64);
+            unsigned* ctr = ws.get<unsigned>("ctr", 1);
+            for (size_t pi = 0; pi < pl.passes.size(); ++pi) {
+                const PassRange& ps = pl.passes[pi];
+                Planner::PassView v = pl.view(ps);
+                Planner::Lists L = pl.build_lists(ps, v, (int)pi);
+                stats.listed_pairs += L.total * 64;
+                stats.n_items += L.n_items;
+                const int64_t nseg = v.n_segs;
+                double* Sseg = ws.get<double>("Sseg", 2 * std::max<int64_t>(nseg, 1));
+                fill(st, Sseg, 2 * nseg, 0.0);
+                if (L.n_items > 0 && L.total > 0) {
+                    auto kern = params->mode == GBS_MODE_F64 ? k_adjoint<0> : k_adjoint<1>;
+                    int per_cu = 0;
+                    GBS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, 0));
+                    int64_t grid = std::min<int64_t>(std::max(1, per_cu) * (int64_t)ctx->n_cu, L.n_items);
+                    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, ctr);
+                    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), 0, st, L.jobs, L.item_off, L.item_order,
+                                       L.n_items, pl.R.n_patch, ctr, L.lists, L.rec, pl.R.rx, pl.R.ry, pl.R.rz,
+                                       pl.R.r2, pl.R.perm, n_rcv, lambda, dRj, Sseg, dE);
+                    GBS_HIP(hipGetLastError());
+                }
+                if (nf > 0 && nseg > 0) {
+                    hipLaunchKernelGGL(k_face_scatter, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, nseg,
+                                       v.face_ptr, v.face_base, v.face_ids, nf, faces->gamma, v.ray_w, L.seg_ray,
+                                       Sseg, Zf);
+                    GBS_HIP(hipGetLastError());
+                }
+            }
+            stats.n_chunks = (int32_t)pl.passes.size();
+        }
+        if (d_gamma && nf > 0)
+            hipLaunchKernelGGL(k_dgamma, dim3(blocks_for(nf, 256)), dim3(256), 0, st, Zf, nf, d_gamma);
+        if (d_rcv && n_rcv > 0)
+            hipLaunchKernelGGL(k_sum_jobs, dim3(blocks_for(3 * n_rcv, 256)), dim3(256), 0, st, dRj, n_jobs, n_rcv,
+                               d_rcv);
+        if (d_eps && n_jobs > 0)
+            GBS_HIP(hipMemcpyAsync(d_eps, dE, sizeof(double) * n_jobs, hipMemcpyDeviceToDevice, st));
+        GBS_HIP(hipGetLastError());
+        GBS_HIP(hipStreamSynchronize(st));  // scratch reused by the next call
+        ctx->stats = stats;
+        return GBS_OK;
+    });
+}
+
+int gbs_graph_create(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces,
+                     const double* rcv, int64_t n_rcv, const double* freqs, int32_t n_freq, const double* eps,
+                     const gbs_params* params, double* P, double* TL, gbs_graph** out) {
+    if (!ctx || !out) return GBS_E_INVALID;
+    *out = nullptr;
+    return guarded(ctx, [&]() {
+        GBS_HIP(hipSetDevice(ctx->device));
+        Args a{rays, segs, faces, rcv, n_rcv, freqs, n_freq, eps, params};
+        validate_host(a);
+        GBS_CHECK(!(params->flags & GBS_FLAG_TABLE_HOST), "graphs need a device-resident table");
+        GBS_CHECK(params->chunk_segs == 0 || params->chunk_segs >= segs->n_segs, "graphs run the table in one pass");
+        GBS_CHECK(!(params->flags & GBS_FLAG_COUNT_ACTIVE), "graphs do not count pairs");
+        GBS_CHECK(ctx->stream != nullptr, "graph capture needs a non-null stream");
+        std::unique_ptr<gbs_graph> g(new gbs_graph);
+        g->ctx = ctx;
+        Workspace& ws = *g->ws;
+        const int nr = pick_nr(ctx, params, n_rcv);
+        Planner pl(ctx, ws, a, nr);
+        hipStream_t st = ctx->stream;
+        const int64_t n_out = (int64_t)pl.n_jobs * n_rcv;
+        pl.read_job_inputs();
+        Planner::Lists L;
+        Planner::PassView v{};
+        bool work = n_out > 0 && segs->n_segs > 0;
+        if (work) {
+            pl.source_offsets();
+            pl.make_passes();
+            pl.plan_receivers(64 * nr);
+            v = pl.view(pl.passes[0]);
+            L = pl.build_lists(pl.passes[0], v, 0);
+        }
+        unsigned* ctr = ws.get<unsigned>("ctr", 1);
+        int32_t* seg_ray = const_cast<int32_t*>(L.seg_ray);
+        SegRec* rec = const_cast<SegRec*>(L.rec);
+        GBS_HIP(hipStreamSynchronize(st));
+        GBS_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        try {
+            fill(st, P, 2 * n_out, 0.0);
+            if (work && L.n_items > 0 && L.total > 0) {
+                // coefficients may change between replays: rebuild the records
+                hipLaunchKernelGGL(k_records, dim3(blocks_for(v.n_segs, 256)), dim3(256), 0, st, v.n_segs, v.a, v.t,
+                                   v.s0, v.lo, v.hi, v.face_ptr, v.face_base, v.face_ids, faces->n_faces,
+                                   faces->gamma, v.ray_w, seg_ray, rec);
+                dispatch_pairs(params->mode, false, nr, ctx, st, L, pl.R, n_rcv, P, ctr, nullptr);
+            }
+            if (TL && n_out > 0)
+                hipLaunchKernelGGL(k_tl, dim3(blocks_for(n_out, 256)), dim3(256), 0, st, P, n_out, TL);
+        } catch (...) {
+            hipGraph_t tmp;
+            (void)hipStreamEndCapture(st, &tmp);
+            if (tmp) (void)hipGraphDestroy(tmp);
+            throw;
+        }
+        GBS_HIP(hipStreamEndCapture(st, &g->graph));
+        GBS_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+        *out = g.release();
+        return GBS_OK;
+    });
+}
+
+int gbs_graph_launch(gbs_graph* g) {
+    if (!g || !g->exec) return GBS_E_INVALID;
+    return guarded(g->ctx, [&]() {
+        GBS_HIP(hipSetDevice(g->ctx->device));
+        GBS_HIP(hipGraphLaunch(g->exec, g->ctx->stream));
+        return GBS_OK;
+    });
+}
+
+void gbs_graph_destroy(gbs_graph* g) {
+    if (!g) return;
+    (void)hipSetDevice(g->ctx->device);
+    (void)hipStreamSynchronize(g->ctx->stream);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+int gbs_autotune(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces,
+                 const double* rcv, int64_t n_rcv, const double* freqs, int32_t n_freq, const double* eps,
+                 const gbs_params* params, double* P, int32_t* rcv_per_lane) {
+    if (!ctx) return GBS_E_INVALID;
+    return guarded(ctx, [&]() {
+        GBS_HIP(hipSetDevice(ctx->device));
+        Args a{rays, segs, faces, rcv, n_rcv, freqs, n_freq, eps, params};
+        validate_host(a);
+        hipEvent_t e0, e1;
+        GBS_HIP(hipEventCreate(&e0));
+        GBS_HIP(hipEventCreate(&e1));
+        float best = 1e30f;
+        int best_nr = 1;
+        for (int nr : {1, 2, 4}) {
+            forward_impl(ctx, *ctx->ws, a, P, nullptr, nr);  // warm-up and plan
+            GBS_HIP(hipEventRecord(e0, ctx->stream));
+            forward_impl(ctx, *ctx->ws, a, P, nullptr, nr);
+            GBS_HIP(hipEventRecord(e1, ctx->stream));
+            GBS_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            GBS_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                best_nr = nr;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        ctx->tuned_nr[params->mode] = best_nr;
+        if (rcv_per_lane) *rcv_per_lane = best_nr;
+        return GBS_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,49 @@
+// Internal layout shared by the host planner and the gfx950 kernels of libgbs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gbs {
+
+constexpr int kWave = 64;             // CDNA wavefront width
+constexpr int kCullThreads = 256;     // cull kernel workgroup (4 waves)
+constexpr int kSuperPatches = 16;     // patches per culling super-patch
+
+// Per-job constants (job = (source, band)), computed on the host.
+struct JobConst {
+    int64_t seg_begin;   // segment range of the job's source inside the current pass
+    int64_t seg_end;
+    double k;            // wavenumber 2 pi f / c
+    double eps;          // beam parameter (Rayleigh range) of this job
+    double eps2;         // eps^2
+    double gate_c1;      // pair kept iff |R-o|^2 <= s^2 * gate_c1 + gate_c2
+    double gate_c2;      //   (c1 = 1 + 2G/(k eps), c2 = 2 G eps^2 / (k eps))
+    double kappa;        // 2G/(k eps): normal-distance gate n^2 <= kappa (s^2 + eps^2)
+    double fk;           // f / c: cycles per metre of travel
+    double hfk;          // f / (2c)
+    double gexp2;        // -(k eps / 2) log2(e): Gaussian exponent in base 2 per n^2/den
+    double gexp;         // -(k eps / 2)
+    double scale;        // k eps / (8 pi^2): weight factored out of the per-job sum
+    int32_t src;
+    int32_t band;
+};
+
+// One beam segment, prepared for the pair kernel (job independent).  The
+// axis is re-anchored at the virtual source o = a - s0 t, so that the arc
+// length of the projection of R is s = R.t - o.t and |R - o|^2 - s^2 = n^2.
+struct SegRec {
+    double m2ox, m2oy, m2oz;  // -2 o
+    double oo;                // |o|^2
+    double tx, ty, tz;        // unit axis
+    double mot;               // -o.t
+    double slo, shi;          // beam interval in arc length [s0 + lo, s0 + hi)
+    double wgr, wgi;          // ray solid angle times the reflection-coefficient product
+};
+static_assert(sizeof(SegRec) == 96, "SegRec layout");
+
+struct Patch {
+    double cx, cy, cz, rad;   // bounding sphere of a receiver patch
+};
+
+}  // namespace gbs

@@ -1,0 +1,724 @@
+// gfx950 kernels of libgbs: receiver ordering, segment preparation, culled
+// work lists and the persistent beam-summation kernels (forward and adjoint).
+//
+// Work decomposition.  The paper balances its ragged per-observer beam loops
+// with device-side kernel launches (Sec. 3.4).  Here the ragged work becomes
+// explicit lists: receivers are ordered along a Morton curve and cut into
+// patches; for every (job, patch) a culling pass lists the segments whose
+// Gaussian beam can reach any receiver of the patch; an exclusive prefix sum
+// over the list lengths lays the lists out back to back; a persistent kernel
+// drains (job, patch) items, longest first, with an atomic counter.
+//
+// Pair kernel layout.  One wavefront per item, one receiver per lane (or
+// several, NR).  The item's segment list is wave-uniform, so segment records
+// stream through scalar loads into SGPRs and every lane reads them without
+// LDS traffic; each lane keeps its receivers and FP64 running sums in VGPRs.
+#include "gbs_internal.h"
+
+#include <math.h>
+
+namespace gbs {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ double wave_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+// An empty volatile asm has side effects, so the compiler cannot hoist the
+// gated block above its wave-uniform branch and execute it for every pair.
+__device__ __forceinline__ void branch_barrier() { asm volatile(""); }
+
+__device__ __forceinline__ int lanes_before(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+__global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_reset_counter(unsigned* ctr) { *ctr = 0u; }
+
+// ---------------------------------------------------------------- receivers
+// Bounding box of the receivers: per-block partial min/max, then one block.
+__global__ void k_bbox_partial(const double* __restrict__ rcv, int64_t n, double* __restrict__ part) {
+    __shared__ double sm[6][256];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        for (int d = 0; d < 3; ++d) {
+            double x = rcv[3 * i + d];
+            lo[d] = fmin(lo[d], x);
+            hi[d] = fmax(hi[d], x);
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        sm[d][threadIdx.x] = lo[d];
+        sm[3 + d][threadIdx.x] = hi[d];
+    }
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            for (int d = 0; d < 3; ++d) {
+                sm[d][threadIdx.x] = fmin(sm[d][threadIdx.x], sm[d][threadIdx.x + s]);
+                sm[3 + d][threadIdx.x] = fmax(sm[3 + d][threadIdx.x], sm[3 + d][threadIdx.x + s]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int d = 0; d < 6; ++d) part[6 * blockIdx.x + d] = sm[d][0];
+}
+
+__global__ void k_bbox_final(const double* __restrict__ part, int nb, double* __restrict__ bbox) {
+    if (threadIdx.x != 0) return;
+    double b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int i = 0; i < nb; ++i)
+        for (int d = 0; d < 3; ++d) {
+            b[d] = fmin(b[d], part[6 * i + d]);
+            b[3 + d] = fmax(b[3 + d], part[6 * i + 3 + d]);
+        }
+    for (int d = 0; d < 6; ++d) bbox[d] = b[d];
+}
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {  // 10 bits -> every third bit
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__global__ void k_morton(const double* __restrict__ rcv, int64_t n, const double* __restrict__ bbox,
+                         uint32_t* __restrict__ keys, int32_t* __restrict__ vals) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t q[3];
+    for (int d = 0; d < 3; ++d) {
+        double ext = bbox[3 + d] - bbox[d];
+        double u = ext > 0 ? (rcv[3 * i + d] - bbox[d]) / ext : 0.0;
+        q[d] = (uint32_t)fmin(fmax(u * 1023.0, 0.0), 1023.0);
+    }
+    keys[i] = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
+    vals[i] = (int32_t)i;
+}
+
+// Sorted receivers in SoA, padded to whole patches with copies of the last
+// receiver (perm = -1 marks padding, whose results are discarded).
+__global__ void k_gather_rcv(const double* __restrict__ rcv, int64_t n, int64_t n_pad,
+                             const int32_t* __restrict__ order, double* __restrict__ rx, double* __restrict__ ry,
+                             double* __restrict__ rz, double* __restrict__ r2, int32_t* __restrict__ perm) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_pad) return;
+    int32_t o = order[i < n ? i : n - 1];
+    double x = rcv[3 * (int64_t)o], y = rcv[3 * (int64_t)o + 1], z = rcv[3 * (int64_t)o + 2];
+    rx[i] = x;
+    ry[i] = y;
+    rz[i] = z;
+    r2[i] = x * x + y * y + z * z;
+    perm[i] = i < n ? o : -1;
+}
+
+// Bounding sphere of each group of `per` consecutive sorted receivers; one
+// wavefront per group.
+__global__ __launch_bounds__(64) void k_patches(const double* __restrict__ rx, const double* __restrict__ ry,
+                                                const double* __restrict__ rz, int64_t n_pad, int64_t per,
+                                                int n_groups, Patch* __restrict__ out) {
+    const int g = blockIdx.x;
+    if (g >= n_groups) return;
+    const int lane = threadIdx.x;
+    const int64_t b = (int64_t)g * per, e = b + per < n_pad ? b + per : n_pad;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = b + lane; i < e; i += 64) {
+        double v[3] = {rx[i], ry[i], rz[i]};
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = fmin(lo[d], v[d]);
+            hi[d] = fmax(hi[d], v[d]);
+        }
+    }
+    double c[3];
+    for (int d = 0; d < 3; ++d) c[d] = 0.5 * (wave_min(lo[d]) + wave_max(hi[d]));
+    double r = 0.0;
+    for (int64_t i = b + lane; i < e; i += 64) {
+        double dx = rx[i] - c[0], dy = ry[i] - c[1], dz = rz[i] - c[2];
+        r = fmax(r, sqrt(dx * dx + dy * dy + dz * dz));
+    }
+    r = wave_max(r);
+    if (lane == 0) out[g] = Patch{c[0], c[1], c[2], r};
+}
+
+// ----------------------------------------------------------------- segments
+// First segment of every source (rays are sorted by source); src_off[n_src]
+// is the end of the table.
+__global__ void k_src_ranges(const int64_t* __restrict__ ray_ptr, const int32_t* __restrict__ ray_src,
+                             int64_t n_rays, int32_t n_src, int64_t* __restrict__ src_off) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i > n_rays) return;
+    // clamped so that an unsorted or out-of-range table cannot write outside src_off
+    int32_t prev = i == 0 ? -1 : min(max(ray_src[i - 1], -1), n_src);
+    int32_t cur = i == n_rays ? n_src : min(max(ray_src[i], -1), n_src);
+    for (int32_t s = prev + 1; s <= cur; ++s) src_off[s] = ray_ptr[i];
+}
+
+// seg_ray[j] = index (within the pass) of the ray that owns segment j.
+__global__ void k_seg2ray(const int64_t* __restrict__ ray_ptr, int64_t n_rays, int64_t seg_base, int64_t n_segs,
+                          int32_t* __restrict__ seg_ray) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_rays) return;
+    const int64_t b = max(ray_ptr[i] - seg_base, (int64_t)0), e = min(ray_ptr[i + 1] - seg_base, n_segs);
+    for (int64_t j = b; j < e; ++j) seg_ray[j] = (int32_t)i;
+}
+
+// Segment records: virtual-source anchoring, arc-length interval and the
+// complex weight w * prod(Gamma) over the faces hit before the segment.
+__global__ void k_records(int64_t n_segs, const double* __restrict__ a, const double* __restrict__ t,
+                          const double* __restrict__ s0, const double* __restrict__ lo,
+                          const double* __restrict__ hi, const int64_t* __restrict__ face_ptr,
+                          int64_t face_base, const int32_t* __restrict__ face_ids, int32_t n_faces,
+                          const double* __restrict__ gamma, const double* __restrict__ ray_w,
+                          const int32_t* __restrict__ seg_ray, SegRec* __restrict__ rec) {
+    int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n_segs) return;
+    double tx = t[3 * j], ty = t[3 * j + 1], tz = t[3 * j + 2];
+    double s = s0[j];
+    double ox = a[3 * j] - s * tx, oy = a[3 * j + 1] - s * ty, oz = a[3 * j + 2] - s * tz;
+    double gr = ray_w[seg_ray[j]], gi = 0.0;
+    for (int64_t m = face_ptr[j] - face_base; m < face_ptr[j + 1] - face_base; ++m) {
+        int32_t f = min(max(face_ids[m], 0), n_faces - 1);   // ids are validated on request only
+        double xr = gamma[2 * f], xi = gamma[2 * f + 1];
+        double nr = gr * xr - gi * xi;
+        gi = gr * xi + gi * xr;
+        gr = nr;
+    }
+    SegRec r;
+    r.m2ox = -2.0 * ox;
+    r.m2oy = -2.0 * oy;
+    r.m2oz = -2.0 * oz;
+    r.oo = ox * ox + oy * oy + oz * oz;
+    r.tx = tx;
+    r.ty = ty;
+    r.tz = tz;
+    r.mot = -(ox * tx + oy * ty + oz * tz);
+    r.slo = s + lo[j];
+    r.shi = s + hi[j];
+    r.wgr = gr;
+    r.wgi = gi;
+    rec[j] = r;
+}
+
+// ------------------------------------------------------------------ culling
+// Conservative test: can the beam of segment S pass the gate for any receiver
+// inside the patch's bounding sphere?  For R in the sphere, the arc length is
+// within rad of the centre's and the normal distance is at least the centre's
+// minus rad (distance to a line is 1-Lipschitz), while the gate needs
+// n^2 <= kappa (s^2 + eps^2).  Margins cover rounding.
+__device__ __forceinline__ bool may_reach(const SegRec& S, const Patch& p, const JobConst& J) {
+    double ox = -0.5 * S.m2ox, oy = -0.5 * S.m2oy, oz = -0.5 * S.m2oz;
+    double vx = p.cx - ox, vy = p.cy - oy, vz = p.cz - oz;
+    double sc = vx * S.tx + vy * S.ty + vz * S.tz;
+    double vv = vx * vx + vy * vy + vz * vz;
+    double nc2 = fmax(vv - sc * sc, 0.0);
+    double rad = p.rad * (1.0 + 1e-9) + 1e-6 * (1.0 + fabs(sc));
+    double sa = fmax(sc - rad, S.slo), sb = fmin(sc + rad, S.shi);
+    if (sa > sb) return false;
+    double sm = fmax(fabs(sa), fabs(sb));
+    double X = sqrt(J.kappa * (sm * sm + J.eps2)) * (1.0 + 1e-9);
+    double lim = rad + X;
+    return nc2 <= lim * lim;
+}
+
+// Two-level cull.  One workgroup per (job, super-patch of kSuperPatches
+// patches): the job's segments are first tested against the super-patch
+// sphere, survivors go to LDS, then each wave tests them against its own
+// patches.  The count pass writes list lengths; the fill pass writes the
+// lists at the offsets given by the exclusive prefix sum of the lengths.
+// Lists come out in segment order (deterministic).
+template <bool FILL>
+__global__ __launch_bounds__(kCullThreads) void k_cull(const JobConst* __restrict__ jobs,
+                                                       const SegRec* __restrict__ rec,
+                                                       const Patch* __restrict__ patches,
+                                                       const Patch* __restrict__ supers, int n_patch,
+                                                       int32_t* __restrict__ counts,
+                                                       const int64_t* __restrict__ item_off,
+                                                       int32_t* __restrict__ lists) {
+    constexpr int kWaves = kCullThreads / kWave;
+    constexpr int kOwn = kSuperPatches / kWaves;
+    __shared__ int32_t q[kCullThreads];
+    __shared__ int wave_cnt[kWaves];
+    const int job = blockIdx.y, sp = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const JobConst J = jobs[job];
+    const Patch SPt = supers[sp];
+    const int p0 = sp * kSuperPatches;
+    Patch mine[kOwn];
+    int64_t run[kOwn], base[kOwn];
+    for (int m = 0; m < kOwn; ++m) {
+        int p = p0 + wv + kWaves * m;
+        mine[m] = p < n_patch ? patches[p] : Patch{0, 0, 0, -1};
+        run[m] = 0;
+        base[m] = (FILL && p < n_patch) ? item_off[(int64_t)job * n_patch + p] : 0;
+    }
+    for (int64_t c = J.seg_begin; c < J.seg_end; c += kCullThreads) {
+        int64_t j = c + tid;
+        bool keep = j < J.seg_end && may_reach(rec[j], SPt, J);
+        unsigned long long bal = __ballot(keep);
+        if (lane == 0) wave_cnt[wv] = __popcll(bal);
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            off += w < wv ? wave_cnt[w] : 0;
+            tot += wave_cnt[w];
+        }
+        if (keep) q[off + lanes_before(bal)] = (int32_t)j;
+        __syncthreads();
+        for (int m = 0; m < kOwn; ++m) {
+            if (mine[m].rad < 0) continue;
+            for (int b = 0; b < tot; b += 64) {
+                int i = b + lane;
+                bool k2 = i < tot && may_reach(rec[q[i]], mine[m], J);
+                unsigned long long bl = __ballot(k2);
+                if (FILL && k2) lists[base[m] + run[m] + lanes_before(bl)] = q[i];
+                run[m] += __popcll(bl);
+            }
+        }
+        __syncthreads();
+    }
+    if (!FILL && lane == 0)
+        for (int m = 0; m < kOwn; ++m) {
+            int p = p0 + wv + kWaves * m;
+            if (p < n_patch) counts[(int64_t)job * n_patch + p] = (int32_t)run[m];
+        }
+}
+
+// ------------------------------------------------------------- pair kernels
+// Forward term of one (segment, receiver) pair, added into (accr, acci)
+// without the job's common weight k eps / (8 pi^2):
+//   B = w Gamma (s + i eps)/(s^2 + eps^2) exp(-(k eps/2) n^2/den) exp(2 pi i cyc),
+//   cyc = (f/c) (s + n^2 s / (2 den)),   den = s^2 + eps^2.
+// The pre-gate (arc length, |R - o|^2, gate, interval) is FP64 in F64 and MIX.
+template <int MODE>
+struct PairEval;
+
+constexpr int kF64 = 0, kMIX = 1, kF32 = 2;
+
+template <>
+struct PairEval<kF64> {
+    __device__ __forceinline__ static bool eval(const SegRec& S, const JobConst& J, double X, double Y, double Z,
+                                                double R2, double& accr, double& acci) {
+        double s = fma(X, S.tx, fma(Y, S.ty, fma(Z, S.tz, S.mot)));
+        double l = fma(X, S.m2ox, fma(Y, S.m2oy, fma(Z, S.m2oz, R2)));        // |R-o|^2 - |o|^2
+        double rhs = fma(s * J.gate_c1, s, J.gate_c2 - S.oo);
+        const bool keep = l <= rhs && s >= S.slo && s < S.shi;
+        if (__ballot(keep) == 0ull) return false;    // wave-uniform skip
+        branch_barrier();
+        if (!keep) return false;
+        double n2 = fma(-s, s, l + S.oo);
+        double den = fma(s, s, J.eps2);
+        double rden = 1.0 / den;
+        double cyc = fma(n2 * s, rden * J.hfk, s * J.fk);
+        double ph = cyc - floor(cyc);
+        double sn, cs;
+        sincospi(2.0 * ph, &sn, &cs);
+        double w = rden * exp(n2 * rden * J.gexp);
+        double cr = fma(s, S.wgr, -J.eps * S.wgi) * w;
+        double ci = fma(s, S.wgi, J.eps * S.wgr) * w;
+        accr += cr * cs - ci * sn;
+        acci += cr * sn + ci * cs;
+        return true;
+    }
+};
+
+template <>
+struct PairEval<kMIX> {
+    __device__ __forceinline__ static bool eval(const SegRec& S, const JobConst& J, double X, double Y, double Z,
+                                                double R2, double& accr, double& acci) {
+        double s = fma(X, S.tx, fma(Y, S.ty, fma(Z, S.tz, S.mot)));
+        double l = fma(X, S.m2ox, fma(Y, S.m2oy, fma(Z, S.m2oz, R2)));
+        double rhs = fma(s * J.gate_c1, s, J.gate_c2 - S.oo);
+        const bool keep = l <= rhs && s >= S.slo && s < S.shi;
+        if (__ballot(keep) == 0ull) return false;    // wave-uniform skip
+        branch_barrier();
+        if (!keep) return false;
+        double n2 = fma(-s, s, l + S.oo);
+        double den = fma(s, s, J.eps2);
+        float r0f = __builtin_amdgcn_rcpf((float)den);
+        double r0 = (double)r0f;
+        double rden = fma(r0, fma(-den, r0, 1.0), r0);                       // one Newton step
+        double cyc = fma(n2 * s, rden * J.hfk, s * J.fk);                    // phase in cycles, FP64
+        float ph = (float)__builtin_amdgcn_fract(cyc);                       // reduced modulo one in FP64
+        float sn = __builtin_amdgcn_sinf(ph);                                // sin(2 pi ph)
+        float cs = __builtin_amdgcn_cosf(ph);
+        float w = r0f * __builtin_amdgcn_exp2f((float)n2 * r0f * (float)J.gexp2);
+        float sf = (float)s;
+        float cr = fmaf(sf, (float)S.wgr, -(float)J.eps * (float)S.wgi) * w;
+        float ci = fmaf(sf, (float)S.wgi, (float)J.eps * (float)S.wgr) * w;
+        accr += (double)(cr * cs - ci * sn);
+        acci += (double)(cr * sn + ci * cs);
+        return true;
+    }
+};
+
+template <>
+struct PairEval<kF32> {
+    __device__ __forceinline__ static bool eval(const SegRec& S, const JobConst& J, double Xd, double Yd, double Zd,
+                                                double, double& accr, double& acci) {
+        float X = (float)Xd, Y = (float)Yd, Z = (float)Zd;
+        float vx = X + 0.5f * (float)S.m2ox, vy = Y + 0.5f * (float)S.m2oy, vz = Z + 0.5f * (float)S.m2oz;
+        float s = vx * (float)S.tx + vy * (float)S.ty + vz * (float)S.tz;
+        float vv = vx * vx + vy * vy + vz * vz;
+        float n2 = fmaxf(vv - s * s, 0.0f);
+        float den = fmaf(s, s, (float)J.eps2);
+        const bool keep = n2 <= (float)J.kappa * den && s >= (float)S.slo && s < (float)S.shi;
+        if (__ballot(keep) == 0ull) return false;    // wave-uniform skip
+        branch_barrier();
+        if (!keep) return false;
+        float rden = __builtin_amdgcn_rcpf(den);
+        float cyc = (float)J.fk * fmaf(0.5f * n2 * s, rden, s);
+        float ph = __builtin_amdgcn_fractf(cyc);
+        float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
+        float w = rden * __builtin_amdgcn_exp2f(n2 * rden * (float)J.gexp2);
+        float cr = fmaf(s, (float)S.wgr, -(float)J.eps * (float)S.wgi) * w;
+        float ci = fmaf(s, (float)S.wgi, (float)J.eps * (float)S.wgr) * w;
+        accr += (double)(cr * cs - ci * sn);
+        acci += (double)(cr * sn + ci * cs);
+        return true;
+    }
+};
+
+// Pops the next work item (wave-uniform) from the global counter.
+__device__ __forceinline__ int pop_item(unsigned* ctr) {
+    int it = 0;
+    if (threadIdx.x == 0) it = (int)atomicAdd(ctr, 1u);
+    it = __shfl(it, 0);
+    return __builtin_amdgcn_readfirstlane(it);
+}
+
+// Persistent forward kernel: one wavefront per (job, patch) item; the patch
+// holds 64 * NR receivers, lane l owns receivers l, l + 64, ...
+// P (job-major, original receiver order) accumulates scale * sum.
+template <int MODE, int NR, bool COUNT>
+__global__ __launch_bounds__(64) void k_pairs(const JobConst* __restrict__ jobs,
+                                              const int64_t* __restrict__ item_off,
+                                              const int32_t* __restrict__ item_order, int32_t n_items,
+                                              int32_t n_patch, unsigned* __restrict__ ctr,
+                                              const int32_t* __restrict__ lists, const SegRec* __restrict__ rec,
+                                              const double* __restrict__ rx, const double* __restrict__ ry,
+                                              const double* __restrict__ rz, const double* __restrict__ r2,
+                                              const int32_t* __restrict__ perm, int64_t n_rcv,
+                                              double* __restrict__ P, unsigned long long* __restrict__ n_active) {
+    const int lane = threadIdx.x;
+    unsigned long long active = 0;
+    for (;;) {
+        const int it = pop_item(ctr);
+        if (it >= n_items) break;
+        const int item = __builtin_amdgcn_readfirstlane(item_order[it]);
+        const int64_t beg = item_off[item], end = item_off[item + 1];
+        if (beg == end) continue;
+        const int job = item / n_patch, patch = item - job * n_patch;
+        const JobConst J = jobs[job];
+        double X[NR], Y[NR], Z[NR], R2[NR], ar[NR], ai[NR];
+#pragma unroll
+        for (int m = 0; m < NR; ++m) {
+            const int64_t i = (int64_t)patch * (64 * NR) + 64 * m + lane;
+            X[m] = rx[i];
+            Y[m] = ry[i];
+            Z[m] = rz[i];
+            R2[m] = r2[i];
+            ar[m] = 0.0;
+            ai[m] = 0.0;
+        }
+        // software pipeline: the record of e + 1 and the index of e + 2 load
+        // while segment e is evaluated
+        int32_t jn = lists[beg + 1 < end ? beg + 1 : beg];
+        SegRec Sn = rec[lists[beg]];
+        for (int64_t e = beg; e < end; ++e) {
+            const SegRec S = Sn;
+            Sn = rec[jn];
+            jn = lists[e + 2 < end ? e + 2 : end - 1];
+#pragma unroll
+            for (int m = 0; m < NR; ++m) {
+                bool hit = PairEval<MODE>::eval(S, J, X[m], Y[m], Z[m], R2[m], ar[m], ai[m]);
+                if (COUNT) active += hit ? 1ull : 0ull;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NR; ++m) {
+            const int64_t i = (int64_t)patch * (64 * NR) + 64 * m + lane;
+            const int32_t o = perm[i];
+            if (o >= 0) {
+                double* p = P + 2 * ((int64_t)job * n_rcv + o);
+                p[0] += J.scale * ar[m];
+                p[1] += J.scale * ai[m];
+            }
+        }
+    }
+    if (COUNT) {
+        double tot = wave_sum((double)active);
+        if (lane == 0) atomicAdd(n_active, (unsigned long long)tot);
+    }
+}
+
+// TL = -20 log10 |P|  (+inf where P = 0).
+__global__ void k_tl(const double* __restrict__ P, int64_t n, double* __restrict__ TL) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double m = hypot(P[2 * i], P[2 * i + 1]);
+    TL[i] = m > 0.0 ? -20.0 * log10(m) : INFINITY;
+}
+
+// ----------------------------------------------------------------- adjoint
+// Adjoint pair terms.  With u = scale * wG * B (forward term) and the
+// convention dL = Re sum lambda dP:
+//   d ln u/dR   = t (ik - 1/q - (ik/2) n^2/q^2) + (ik/q) nvec,  nvec = R - o - s t
+//   d ln u/deps = 1/eps + i/q - (k/2) n^2/q^2
+//   dP/dGamma_f = scale * sum_j d(prod Gamma_j)/dGamma_f * w_j * B_j
+// With 1/q = (s + i eps) rden and 1/q^2 = (s^2 - eps^2 + 2 i eps s) rden^2.
+template <typename T>
+struct AdjTerms {
+    T Br, Bi;        // B / (w prod Gamma): beam term without weight and coefficients
+    T ctr, cti;      // coefficient of t in d ln u/dR
+    T cnr, cni;      // coefficient of nvec
+    T der, dei;      // d ln u/deps
+};
+
+template <typename T>
+__device__ __forceinline__ void adj_factors(T s, T n2, T rden, T eps, T k, AdjTerms<T>& A) {
+    T r2d = rden * rden;
+    T iq_r = s * rden, iq_i = eps * rden;                              // 1/q
+    T iq2_r = (s * s - eps * eps) * r2d, iq2_i = 2 * eps * s * r2d;    // 1/q^2
+    T hk = (T)0.5 * k * n2;
+    // ik - 1/q - (ik/2) n^2/q^2 : (ik/2)n^2/q^2 = hk*(i*iq2_r - iq2_i)
+    A.ctr = -iq_r + hk * iq2_i;
+    A.cti = k - iq_i - hk * iq2_r;
+    // ik/q = i k (iq_r + i iq_i) = -k iq_i + i k iq_r
+    A.cnr = -k * iq_i;
+    A.cni = k * iq_r;
+    // 1/eps + i/q - (k/2) n^2/q^2 ; i/q = -iq_i + i iq_r
+    A.der = (T)1 / eps - iq_i - hk * iq2_r;
+    A.dei = iq_r - hk * iq2_i;
+}
+
+template <int MODE>
+__device__ __forceinline__ bool adj_eval(const SegRec& S, const JobConst& J, double X, double Y, double Z, double R2,
+                                         double lr, double li, double& dRx, double& dRy, double& dRz, double& dE,
+                                         double& Sr, double& Si) {
+    double s = fma(X, S.tx, fma(Y, S.ty, fma(Z, S.tz, S.mot)));
+    double l = fma(X, S.m2ox, fma(Y, S.m2oy, fma(Z, S.m2oz, R2)));
+    double rhs = fma(s * J.gate_c1, s, J.gate_c2 - S.oo);
+    const bool keep = l <= rhs && s >= S.slo && s < S.shi;
+    if (__ballot(keep) == 0ull) return false;    // wave-uniform skip
+    branch_barrier();
+    if (!keep) return false;
+    double n2 = fma(-s, s, l + S.oo);
+    double den = fma(s, s, J.eps2);
+    double rden = 1.0 / den;
+    double cyc = fma(n2 * s, rden * J.hfk, s * J.fk);
+    double ph = cyc - floor(cyc);
+    // normal vector R - o - s t  (o = -m2o / 2)
+    double nx = X + 0.5 * S.m2ox - s * S.tx, ny = Y + 0.5 * S.m2oy - s * S.ty, nz = Z + 0.5 * S.m2oz - s * S.tz;
+    if (MODE == kF64) {
+        double sn, cs;
+        sincospi(2.0 * ph, &sn, &cs);
+        double w = rden * exp(n2 * rden * J.gexp);
+        AdjTerms<double> A;
+        adj_factors<double>(s, n2, rden, J.eps, J.k, A);
+        double br = s * w, bi = J.eps * w;                  // (s + i eps) rden e^g
+        A.Br = br * cs - bi * sn;
+        A.Bi = br * sn + bi * cs;
+        double ur = S.wgr * A.Br - S.wgi * A.Bi, ui = S.wgr * A.Bi + S.wgi * A.Br;
+        double vr = lr * ur - li * ui, vi = lr * ui + li * ur;    // lambda u
+        double gt = vr * A.ctr - vi * A.cti, gn = vr * A.cnr - vi * A.cni;
+        dRx += gt * S.tx + gn * nx;
+        dRy += gt * S.ty + gn * ny;
+        dRz += gt * S.tz + gn * nz;
+        dE += vr * A.der - vi * A.dei;
+        Sr += lr * A.Br - li * A.Bi;
+        Si += lr * A.Bi + li * A.Br;
+    } else {
+        float phf = (float)ph;
+        float sn = __builtin_amdgcn_sinf(phf), cs = __builtin_amdgcn_cosf(phf);
+        float rdf = (float)rden;
+        float w = rdf * __builtin_amdgcn_exp2f((float)n2 * rdf * (float)J.gexp2);
+        AdjTerms<float> A;
+        adj_factors<float>((float)s, (float)n2, rdf, (float)J.eps, (float)J.k, A);
+        float br = (float)s * w, bi = (float)J.eps * w;
+        A.Br = br * cs - bi * sn;
+        A.Bi = br * sn + bi * cs;
+        float gr = (float)S.wgr, gi = (float)S.wgi, lrf = (float)lr, lif = (float)li;
+        float ur = gr * A.Br - gi * A.Bi, ui = gr * A.Bi + gi * A.Br;
+        float vr = lrf * ur - lif * ui, vi = lrf * ui + lif * ur;
+        float gt = vr * A.ctr - vi * A.cti, gn = vr * A.cnr - vi * A.cni;
+        dRx += (double)gt * S.tx + (double)gn * nx;
+        dRy += (double)gt * S.ty + (double)gn * ny;
+        dRz += (double)gt * S.tz + (double)gn * nz;
+        dE += (double)(vr * A.der - vi * A.dei);
+        Sr += (double)(lrf * A.Br - lif * A.Bi);
+        Si += (double)(lrf * A.Bi + lif * A.Br);
+    }
+    return true;
+}
+
+// Persistent adjoint kernel (same items as the forward).  Per receiver:
+// dR accumulates in the lane and is written per (job, receiver);
+// per segment: sum over lanes of lambda * B (wave reduction) -> FP64 atomics
+// into Sseg; per job: d eps via a wave reduction and one atomic per item.
+template <int MODE>
+__global__ __launch_bounds__(64) void k_adjoint(const JobConst* __restrict__ jobs,
+                                                const int64_t* __restrict__ item_off,
+                                                const int32_t* __restrict__ item_order, int32_t n_items,
+                                                int32_t n_patch, unsigned* __restrict__ ctr,
+                                                const int32_t* __restrict__ lists, const SegRec* __restrict__ rec,
+                                                const double* __restrict__ rx, const double* __restrict__ ry,
+                                                const double* __restrict__ rz, const double* __restrict__ r2,
+                                                const int32_t* __restrict__ perm, int64_t n_rcv,
+                                                const double* __restrict__ lambda, double* __restrict__ dR_job,
+                                                double* __restrict__ Sseg, double* __restrict__ d_eps) {
+    const int lane = threadIdx.x;
+    for (;;) {
+        const int it = pop_item(ctr);
+        if (it >= n_items) break;
+        const int item = __builtin_amdgcn_readfirstlane(item_order[it]);
+        const int64_t beg = item_off[item], end = item_off[item + 1];
+        if (beg == end) continue;
+        const int job = item / n_patch, patch = item - job * n_patch;
+        const JobConst J = jobs[job];
+        const int64_t i = (int64_t)patch * 64 + lane;
+        const double X = rx[i], Y = ry[i], Z = rz[i], R2 = r2[i];
+        const int32_t o = perm[i];
+        double lr = 0.0, li = 0.0;
+        if (o >= 0) {
+            lr = lambda[2 * ((int64_t)job * n_rcv + o)];
+            li = lambda[2 * ((int64_t)job * n_rcv + o) + 1];
+        }
+        double dRx = 0, dRy = 0, dRz = 0, dE = 0;
+        for (int64_t e = beg; e < end; ++e) {
+            const int32_t j = lists[e];
+            const SegRec S = rec[j];
+            double Sr = 0.0, Si = 0.0;
+            bool hit = adj_eval<MODE>(S, J, X, Y, Z, R2, lr, li, dRx, dRy, dRz, dE, Sr, Si);
+            if (__ballot(hit) != 0ull) {
+                Sr = wave_sum(Sr);
+                Si = wave_sum(Si);
+                if (lane == 0) {
+                    atomicAdd(&Sseg[2 * (int64_t)j], J.scale * Sr);
+                    atomicAdd(&Sseg[2 * (int64_t)j + 1], J.scale * Si);
+                }
+            }
+        }
+        if (o >= 0) {
+            double* d = dR_job + 3 * ((int64_t)job * n_rcv + o);
+            d[0] += J.scale * dRx;
+            d[1] += J.scale * dRy;
+            d[2] += J.scale * dRz;
+        }
+        dE = wave_sum(dE);
+        if (lane == 0) atomicAdd(&d_eps[job], J.scale * dE);
+    }
+}
+
+// dR[r] = sum over jobs of dR_job[job][r]  (fixed order).
+__global__ void k_sum_jobs(const double* __restrict__ dR_job, int32_t n_jobs, int64_t n_rcv, double* __restrict__ dR) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= 3 * n_rcv) return;
+    double s = 0.0;
+    for (int32_t j = 0; j < n_jobs; ++j) s += dR_job[(int64_t)j * 3 * n_rcv + i];
+    dR[i] = s;
+}
+
+// Z_f += d(prod Gamma_j)/dGamma_f * w_j * S_j for every distinct face f in
+// segment j's history (product of the other factors, summed over the
+// occurrences of f).
+__global__ void k_face_scatter(int64_t n_segs, const int64_t* __restrict__ face_ptr, int64_t face_base,
+                               const int32_t* __restrict__ face_ids, int32_t n_faces, const double* __restrict__ gamma,
+                               const double* __restrict__ ray_w, const int32_t* __restrict__ seg_ray,
+                               const double* __restrict__ Sseg, double* __restrict__ Zf) {
+    int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n_segs) return;
+    const double sr = Sseg[2 * j], si = Sseg[2 * j + 1];
+    if (sr == 0.0 && si == 0.0) return;
+    const int64_t b = face_ptr[j] - face_base, e = face_ptr[j + 1] - face_base;
+    const double w = ray_w[seg_ray[j]];
+    for (int64_t l = b; l < e; ++l) {
+        const int32_t f = face_ids[l];
+        if (f < 0 || f >= n_faces) continue;   // ids are validated on request only
+        bool seen = false;
+        for (int64_t m = b; m < l; ++m) seen |= face_ids[m] == f;
+        if (seen) continue;
+        double dr = 0.0, di = 0.0;
+        for (int64_t l2 = l; l2 < e; ++l2) {
+            if (face_ids[l2] != f) continue;
+            double pr = 1.0, pi = 0.0;
+            for (int64_t m = b; m < e; ++m) {
+                if (m == l2) continue;
+                const int32_t g = min(max(face_ids[m], 0), n_faces - 1);
+                double xr = gamma[2 * g], xi = gamma[2 * g + 1];
+                double nr = pr * xr - pi * xi;
+                pi = pr * xi + pi * xr;
+                pr = nr;
+            }
+            dr += pr;
+            di += pi;
+        }
+        double zr = w * (dr * sr - di * si), zi = w * (dr * si + di * sr);
+        atomicAdd(&Zf[2 * (int64_t)f], zr);
+        atomicAdd(&Zf[2 * (int64_t)f + 1], zi);
+    }
+}
+
+// d_gamma = (Re Z, -Im Z).
+__global__ void k_dgamma(const double* __restrict__ Zf, int32_t n_faces, double* __restrict__ d_gamma) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_faces) return;
+    d_gamma[2 * i] = Zf[2 * i];
+    d_gamma[2 * i + 1] = -Zf[2 * i + 1];
+}
+
+// Device-side table validation: writes 1 into *bad on the first problem.
+__global__ void k_validate(int64_t n_segs, const double* __restrict__ t, const double* __restrict__ lo,
+                           const double* __restrict__ hi, const int64_t* __restrict__ face_ptr,
+                           int64_t face_base, const int32_t* __restrict__ face_ids, int32_t n_faces,
+                           int* __restrict__ bad) {
+    int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n_segs) return;
+    double tn = t[3 * j] * t[3 * j] + t[3 * j + 1] * t[3 * j + 1] + t[3 * j + 2] * t[3 * j + 2];
+    bool ok = fabs(tn - 1.0) <= 2e-9 && lo[j] <= hi[j] && isfinite(lo[j]) && isfinite(hi[j]) &&
+              face_ptr[j + 1] >= face_ptr[j];
+    for (int64_t m = face_ptr[j] - face_base; ok && m < face_ptr[j + 1] - face_base; ++m)
+        ok = face_ids[m] >= 0 && face_ids[m] < n_faces;
+    if (!ok) atomicOr(bad, 1);
+}
+
+// Explicit instantiations used by the host planner.
+template __global__ void k_cull<false>(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int32_t*,
+                                       const int64_t*, int32_t*);
+template __global__ void k_cull<true>(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int32_t*,
+                                      const int64_t*, int32_t*);
+#define GBS_INST_PAIRS(M, N, C)                                                                                  \
+    template __global__ void k_pairs<M, N, C>(const JobConst*, const int64_t*, const int32_t*, int32_t, int32_t,  \
+                                              unsigned*, const int32_t*, const SegRec*, const double*,           \
+                                              const double*, const double*, const double*, const int32_t*,       \
+                                              int64_t, double*, unsigned long long*);
+#define GBS_INST_PAIRS_MODE(M) \
+    GBS_INST_PAIRS(M, 1, false) GBS_INST_PAIRS(M, 2, false) GBS_INST_PAIRS(M, 4, false) \
+    GBS_INST_PAIRS(M, 1, true) GBS_INST_PAIRS(M, 2, true) GBS_INST_PAIRS(M, 4, true)
+GBS_INST_PAIRS_MODE(0)
+GBS_INST_PAIRS_MODE(1)
+GBS_INST_PAIRS_MODE(2)
+template __global__ void k_adjoint<0>(const JobConst*, const int64_t*, const int32_t*, int32_t, int32_t, unsigned*,
+                                      const int32_t*, const SegRec*, const double*, const double*, const double*,
+                                      const double*, const int32_t*, int64_t, const double*, double*, double*,
+                                      double*);
+template __global__ void k_adjoint<1>(const JobConst*, const int64_t*, const int32_t*, int32_t, int32_t, unsigned*,
+                                      const int32_t*, const SegRec*, const double*, const double*, const double*,
+                                      const double*, const int32_t*, int64_t, const double*, double*, double*,
+                                      double*);
+
+}  // namespace gbs

@@ -1,0 +1,299 @@
+"""Python surface of libgbs: argument marshalling onto the C ABI.
+
+Every step of the computation runs in the HIP library; this module only
+moves arrays into torch device memory, passes pointers and the current HIP
+stream, and shapes the outputs.  Torch is used for memory and streams only.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_contexts: dict = {}
+
+
+def _device_index(device) -> int:
+    d = torch.device(device)
+    if d.type != "cuda":
+        raise ValueError("libgbs runs on a HIP device (torch 'cuda' device)")
+    return d.index if d.index is not None else torch.cuda.current_device()
+
+
+class Context:
+    """A libgbs context bound to one device; calls enqueue on torch's current stream."""
+
+    def __init__(self, device="cuda"):
+        self.device = torch.device("cuda", _device_index(device))
+        self.lib = _lib.load()
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.gbs_create(ctypes.byref(h), self.device.index, None), None)
+        self.handle = h
+
+    def bind_stream(self, stream=None):
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _lib.check(self.lib.gbs_set_stream(self.handle, ctypes.c_void_p(s.cuda_stream)), self.handle)
+
+    def stats(self) -> dict:
+        st = _lib.GbsStats()
+        _lib.check(self.lib.gbs_get_stats(self.handle, ctypes.byref(st)), self.handle)
+        return st.as_dict()
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                self.lib.gbs_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+def context(device="cuda") -> Context:
+    idx = _device_index(device)
+    if idx not in _contexts:
+        _contexts[idx] = Context(torch.device("cuda", idx))
+    return _contexts[idx]
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _as_tensor(x, dtype, device, pin=False):
+    if isinstance(x, torch.Tensor):
+        t = x.to(dtype=dtype)
+        t = t.to(device) if device is not None else t
+    else:
+        t = torch.as_tensor(np.ascontiguousarray(x), dtype=dtype)
+        if device is not None:
+            t = t.to(device)
+    t = t.contiguous()
+    if pin and device is None and not t.is_pinned():
+        p = torch.empty(t.shape, dtype=dtype, pin_memory=True)
+        p.copy_(t)
+        t = p
+    return t
+
+
+class Table:
+    """A ray table held as torch tensors, on the device or in pinned host
+    memory (host tables are streamed by the library in chunks).
+
+    `src` is any object with the ray-table fields: src_xyz, ray_ptr, ray_w,
+    ray_src, seg_a, seg_t, seg_s0, seg_lo, seg_hi, face_ptr, face_ids,
+    n_faces (numpy arrays or tensors)."""
+
+    def __init__(self, src, device="cuda", on_host=False):
+        dev = None if on_host else torch.device("cuda", _device_index(device))
+        self.on_host = on_host
+        self.device = torch.device("cuda", _device_index(device))
+        self.n_src = int(len(src.src_xyz))
+        self.n_faces = int(src.n_faces)
+        f64, i64, i32 = torch.float64, torch.int64, torch.int32
+        self.ray_ptr = _as_tensor(src.ray_ptr, i64, dev, on_host)
+        self.ray_w = _as_tensor(src.ray_w, f64, dev, on_host)
+        self.ray_src = _as_tensor(src.ray_src, i32, dev, on_host)
+        self.seg_a = _as_tensor(src.seg_a, f64, dev, on_host).reshape(-1, 3)
+        self.seg_t = _as_tensor(src.seg_t, f64, dev, on_host).reshape(-1, 3)
+        self.seg_s0 = _as_tensor(src.seg_s0, f64, dev, on_host)
+        self.seg_lo = _as_tensor(src.seg_lo, f64, dev, on_host)
+        self.seg_hi = _as_tensor(src.seg_hi, f64, dev, on_host)
+        self.face_ptr = _as_tensor(src.face_ptr, i64, dev, on_host)
+        self.face_ids = _as_tensor(src.face_ids, i32, dev, on_host)
+        self.n_rays = int(self.ray_w.numel())
+        self.n_segs = int(self.seg_s0.numel())
+
+    def structs(self):
+        rays = _lib.GbsRays(self.n_src, self.n_rays, _ptr(self.ray_ptr), _ptr(self.ray_w), _ptr(self.ray_src))
+        segs = _lib.GbsSegs(self.n_segs, _ptr(self.seg_a), _ptr(self.seg_t), _ptr(self.seg_s0), _ptr(self.seg_lo),
+                            _ptr(self.seg_hi), _ptr(self.face_ptr), _ptr(self.face_ids))
+        return rays, segs
+
+
+def _gamma_ri(gamma, device):
+    if isinstance(gamma, torch.Tensor) and gamma.is_complex():
+        g = torch.view_as_real(gamma.detach().to(device=device, dtype=torch.complex128).contiguous())
+    elif isinstance(gamma, torch.Tensor):
+        g = gamma.detach().to(device=device, dtype=torch.float64).reshape(-1, 2)
+    else:
+        a = np.asarray(gamma)
+        if np.iscomplexobj(a) or a.ndim == 1:
+            a = np.stack([np.real(a), np.imag(a)], axis=-1)
+        g = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
+    return g.contiguous()
+
+
+def _params(c, gate, mode, flags, chunk_segs, rcv_per_lane):
+    if mode not in _lib.MODES:
+        raise ValueError(f"mode must be one of {sorted(_lib.MODES)}")
+    return _lib.GbsParams(float(c), float(gate), _lib.MODES[mode], int(flags), int(chunk_segs), int(rcv_per_lane), 0)
+
+
+class _Call:
+    """Marshalled arguments of one forward/backward call."""
+
+    def __init__(self, table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, validate,
+                 count_active, time_kernels=False):
+        if not isinstance(table, Table):
+            raise TypeError("table must be a gbs.Table")
+        dev = table.device
+        self.table = table
+        self.rcv = _as_tensor(rcv, torch.float64, dev).reshape(-1, 3)
+        self.freqs = _as_tensor(freqs, torch.float64, dev).reshape(-1)
+        self.eps = _as_tensor(eps, torch.float64, dev).reshape(-1)
+        if self.eps.numel() != table.n_src * self.freqs.numel():
+            raise ValueError("eps must hold one value per (source, band)")
+        self.gamma = _gamma_ri(gamma, dev)
+        if self.gamma.shape[0] != table.n_faces:
+            raise ValueError("gamma must hold one coefficient per face")
+        flags = (_lib.FLAG_TABLE_HOST if table.on_host else 0) | (_lib.FLAG_VALIDATE if validate else 0) | \
+            (_lib.FLAG_COUNT_ACTIVE if count_active else 0) | (_lib.FLAG_TIME_KERNELS if time_kernels else 0)
+        self.params = _params(c, gate, mode, flags, chunk_segs, rcv_per_lane)
+        self.rays, self.segs = table.structs()
+        self.faces = _lib.GbsFaces(table.n_faces, _ptr(self.gamma))
+        self.n_rcv = int(self.rcv.shape[0])
+        self.n_freq = int(self.freqs.numel())
+        self.shape = (table.n_src, self.n_freq, self.n_rcv)
+
+    def common(self, ctx):
+        return (ctx.handle, ctypes.byref(self.rays), ctypes.byref(self.segs), ctypes.byref(self.faces),
+                _ptr(self.rcv), self.n_rcv, _ptr(self.freqs), self.n_freq, _ptr(self.eps), ctypes.byref(self.params))
+
+
+def forward(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix", chunk_segs=0,
+            rcv_per_lane=0, validate=False, count_active=False, time_kernels=False, want_tl=True):
+    """Beam summation.  Returns (P complex128 [n_src, n_freq, n_rcv],
+    TL float64 of the same shape or None).  count_active / time_kernels fill
+    the statistics returned by stats()."""
+    ctx = context(table.device)
+    ctx.bind_stream()
+    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, validate, count_active,
+                 time_kernels)
+    P = torch.empty(call.shape + (2,), dtype=torch.float64, device=table.device)
+    TL = torch.empty(call.shape, dtype=torch.float64, device=table.device) if want_tl else None
+    rc = ctx.lib.gbs_forward(*call.common(ctx), _ptr(P), _ptr(TL))
+    _lib.check(rc, ctx.handle)
+    return torch.view_as_complex(P), TL
+
+
+def backward(table: Table, rcv, freqs, eps, gamma, lam, *, c=343.0, gate=9.21, mode="mix", chunk_segs=0,
+             validate=False):
+    """Adjoint for dL = Re sum lam * dP.  Returns (d_gamma [n_faces, 2] as
+    (dL/dRe, dL/dIm), d_rcv [n_rcv, 3], d_eps [n_src, n_freq])."""
+    ctx = context(table.device)
+    ctx.bind_stream()
+    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, 0, validate, False)
+    lam_t = lam if isinstance(lam, torch.Tensor) else torch.as_tensor(np.asarray(lam))
+    lam_t = lam_t.to(device=table.device, dtype=torch.complex128).reshape(call.shape).contiguous()
+    lam_ri = torch.view_as_real(lam_t).contiguous()
+    d_gamma = torch.empty((table.n_faces, 2), dtype=torch.float64, device=table.device)
+    d_rcv = torch.empty((call.n_rcv, 3), dtype=torch.float64, device=table.device)
+    d_eps = torch.empty((table.n_src, call.n_freq), dtype=torch.float64, device=table.device)
+    rc = ctx.lib.gbs_backward(*call.common(ctx), _ptr(lam_ri), _ptr(d_gamma), _ptr(d_rcv), _ptr(d_eps))
+    _lib.check(rc, ctx.handle)
+    return d_gamma, d_rcv, d_eps
+
+
+def autotune(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix"):
+    """Times the pair-kernel shapes on this problem; later calls in `mode`
+    with rcv_per_lane=0 use the fastest.  Returns the chosen receivers/lane."""
+    ctx = context(table.device)
+    ctx.bind_stream()
+    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, 0, 0, False, False)
+    P = torch.empty(call.shape + (2,), dtype=torch.float64, device=table.device)
+    out = ctypes.c_int32(0)
+    rc = ctx.lib.gbs_autotune(*call.common(ctx), _ptr(P), ctypes.byref(out))
+    _lib.check(rc, ctx.handle)
+    return int(out.value)
+
+
+def stats(device="cuda") -> dict:
+    return context(device).stats()
+
+
+class Graph:
+    """One captured forward (all jobs, one persistent launch) that can be
+    replayed; the coefficient tensor may be updated in place between replays."""
+
+    def __init__(self, table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix", rcv_per_lane=0):
+        self.ctx = context(table.device)
+        self.stream = torch.cuda.Stream(device=table.device)
+        self.call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, 0, rcv_per_lane, False, False)
+        self.gamma = self.call.gamma          # [n_faces, 2] device buffer read at every replay
+        self.P = torch.empty(self.call.shape + (2,), dtype=torch.float64, device=table.device)
+        self.TL = torch.empty(self.call.shape, dtype=torch.float64, device=table.device)
+        torch.cuda.current_stream(table.device).synchronize()
+        self.ctx.bind_stream(self.stream)
+        h = ctypes.c_void_p()
+        try:
+            rc = self.ctx.lib.gbs_graph_create(*self.call.common(self.ctx), _ptr(self.P), _ptr(self.TL),
+                                               ctypes.byref(h))
+            _lib.check(rc, self.ctx.handle)
+        finally:
+            self.ctx.bind_stream()
+        self.handle = h
+
+    def set_gamma(self, gamma):
+        g = _gamma_ri(gamma, self.P.device)
+        with torch.cuda.stream(self.stream):
+            self.gamma.copy_(g)
+
+    def launch(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.P.device))
+        self.ctx.bind_stream(self.stream)
+        try:
+            _lib.check(self.ctx.lib.gbs_graph_launch(self.handle), self.ctx.handle)
+        finally:
+            self.ctx.bind_stream()
+        torch.cuda.current_stream(self.P.device).wait_stream(self.stream)
+        return torch.view_as_complex(self.P), self.TL
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                self.ctx.lib.gbs_graph_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+LN10 = math.log(10.0)
+
+
+class GBSFunction(torch.autograd.Function):
+    """Differentiable beam summation with the ray geometry held fixed.
+
+    apply(gamma [n_faces] complex128, rcv [n_rcv, 3] float64,
+          eps [n_src, n_freq] float64, table, freqs, opts dict) -> (P, TL)
+
+    Gradients flow to the reflection coefficients (torch's complex
+    convention: dL/dRe + i dL/dIm), the receiver positions and eps.
+    """
+
+    @staticmethod
+    def forward(ctx, gamma, rcv, eps, table, freqs, opts):
+        opts = dict(opts or {})
+        P, TL = forward(table, rcv.detach(), freqs, eps.detach(), gamma.detach(), **opts)
+        ctx.save_for_backward(gamma, rcv, eps, P)
+        ctx.table, ctx.freqs, ctx.opts = table, freqs, opts
+        ctx.mark_non_differentiable()
+        return P, TL
+
+    @staticmethod
+    def backward(ctx, gP, gTL):
+        gamma, rcv, eps, P = ctx.saved_tensors
+        lam = torch.zeros_like(P)
+        if gP is not None:
+            lam = lam + torch.conj(gP)
+        if gTL is not None:
+            lam = lam - (20.0 / LN10) * gTL.to(P.dtype) / P
+        opts = {k: v for k, v in ctx.opts.items() if k in ("c", "gate", "mode", "chunk_segs")}
+        dG, dR, dE = backward(ctx.table, rcv.detach(), ctx.freqs, eps.detach(), gamma.detach(), lam, **opts)
+        g_gamma = torch.complex(dG[:, 0], dG[:, 1]).to(gamma.dtype) if ctx.needs_input_grad[0] else None
+        g_rcv = dR.to(rcv.dtype).reshape(rcv.shape) if ctx.needs_input_grad[1] else None
+        g_eps = dE.to(eps.dtype).reshape(eps.shape) if ctx.needs_input_grad[2] else None
+        return g_gamma, g_rcv, g_eps, None, None, None

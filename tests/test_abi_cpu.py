@@ -1,0 +1,54 @@
+"""Host-only checks of the C ABI: the library loads and exports every
+function include/gbs.h declares; struct layouts match the header."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2501_13382_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gbs.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gbs_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    assert set(declared_functions()) == set(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libgbs.so not built")
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert _lib.load().gbs_version() == 1
+
+
+def test_struct_sizes_match_c_layout():
+    assert ctypes.sizeof(_lib.GbsRays) == 40
+    assert ctypes.sizeof(_lib.GbsSegs) == 64
+    assert ctypes.sizeof(_lib.GbsFaces) == 16
+    assert ctypes.sizeof(_lib.GbsParams) == 40
+    assert ctypes.sizeof(_lib.GbsStats) == 56
+
+
+def test_create_without_gpu_fails_cleanly():
+    """With no visible device the context is refused with an error code, no crash."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libgbs.so not built")
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    rc = lib.gbs_create(ctypes.byref(h), 0, None)
+    assert rc in (_lib.GBS_E_INVALID, _lib.GBS_E_HIP)
+    assert not h.value
+    assert lib.gbs_last_error(None) == b"null context"
