@@ -393,13 +393,18 @@ struct PairEval<kF32> {
     }
 };
 
-// Pops the next work item (wave-uniform) from the global counter.
+// Pops the next work item (wave-uniform) from the global counter.  Lane 0
+// issues the atomic.  Callers put branch_barrier() in front of it and issue
+// their own end-of-item atomics from lane kLastLane: if both ends of the loop
+// body were guarded by the same lane predicate, the compiler could thread the
+// two guards across the back edge and re-run the index shuffle without lane 0.
 __device__ __forceinline__ int pop_item(unsigned* ctr) {
     int it = 0;
     if (threadIdx.x == 0) it = (int)atomicAdd(ctr, 1u);
     it = __shfl(it, 0);
     return __builtin_amdgcn_readfirstlane(it);
 }
+constexpr int kLastLane = kWave - 1;
 
 // Persistent forward kernel: one wavefront per (job, patch) item; the patch
 // holds 64 * NR receivers, lane l owns receivers l, l + 64, ...
@@ -417,6 +422,7 @@ __global__ __launch_bounds__(64) void k_pairs(const JobConst* __restrict__ jobs,
     const int lane = threadIdx.x;
     unsigned long long active = 0;
     for (;;) {
+        branch_barrier();
         const int it = pop_item(ctr);
         if (it >= n_items) break;
         const int item = __builtin_amdgcn_readfirstlane(item_order[it]);
@@ -462,7 +468,7 @@ __global__ __launch_bounds__(64) void k_pairs(const JobConst* __restrict__ jobs,
     }
     if (COUNT) {
         double tot = wave_sum((double)active);
-        if (lane == 0) atomicAdd(n_active, (unsigned long long)tot);
+        if (lane == kLastLane) atomicAdd(n_active, (unsigned long long)tot);
     }
 }
 
@@ -583,6 +589,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const JobConst* __restrict__ job
                                                 double* __restrict__ Sseg, double* __restrict__ d_eps) {
     const int lane = threadIdx.x;
     for (;;) {
+        branch_barrier();
         const int it = pop_item(ctr);
         if (it >= n_items) break;
         const int item = __builtin_amdgcn_readfirstlane(item_order[it]);
@@ -607,7 +614,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const JobConst* __restrict__ job
             if (__ballot(hit) != 0ull) {
                 Sr = wave_sum(Sr);
                 Si = wave_sum(Si);
-                if (lane == 0) {
+                if (lane == kLastLane) {
                     atomicAdd(&Sseg[2 * (int64_t)j], J.scale * Sr);
                     atomicAdd(&Sseg[2 * (int64_t)j + 1], J.scale * Si);
                 }
@@ -620,7 +627,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const JobConst* __restrict__ job
             d[2] += J.scale * dRz;
         }
         dE = wave_sum(dE);
-        if (lane == 0) atomicAdd(&d_eps[job], J.scale * dE);
+        if (lane == kLastLane) atomicAdd(&d_eps[job], J.scale * dE);
     }
 }
 
