@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-f64", action="store_true", help="skip the all-FP64 comparison")
     ap.add_argument("--cpu-receivers", type=int, default=4096)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the steps, run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -78,17 +80,21 @@ def main():
         for _ in range(warmup):
             step(mode)
         torch.cuda.synchronize()
-        ms_pairs = []
+        ms_pairs, ms_cull = [], []
         t = time.perf_counter()
         for _ in range(steps):
             out = step(mode, timed=True)
-            ms_pairs.append(gbs.stats(dev)["ms_pairs"])
+            st = gbs.stats(dev)
+            ms_pairs.append(st["ms_pairs"])
+            ms_cull.append(st["ms_cull"])
         torch.cuda.synchronize()
         el = time.perf_counter() - t
+        run.last = {"ms_cull": float(np.mean(ms_cull)), "grid": st["grid"], "blocks_per_cu": st["blocks_per_cu"]}
         return el / steps, float(np.mean(ms_pairs)), out
 
     mode = "mix"
     sec_step, ms_pairs, (P, TL) = run(mode, args.steps, args.warmup)
+    launch = dict(run.last)
     print(f"# mix: {sec_step * 1e3:.2f} ms/step, pair kernel {ms_pairs:.2f} ms", file=sys.stderr, flush=True)
     step(mode, count=True)
     st = gbs.stats(dev)
@@ -125,8 +131,19 @@ def main():
                      "ms_per_launch": ms_pairs, "listed_pairs": listed, "active_pairs": active,
                      "flop_per_listed_pair": FLOP_PRE, "flop_per_active_pair": FLOP_IN[mode]},
         "pair_kernel_share": ms_pairs / (sec_step * 1e3),
+        "ms_cull": launch["ms_cull"],
+        "launch": {"grid": launch["grid"], "blocks_per_cu": launch["blocks_per_cu"], "threads_per_block": 256},
         "f64": f64,
     }
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        dst = src.clone()
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = int(n * 8)
+        del src, dst
 
     # accuracy on a seeded receiver subsample, and the oracle timed on this host
     idx = receiver_subsample(len(sc.rcv), n=args.cpu_receivers, seed=5)

@@ -122,6 +122,8 @@ typedef struct gbs_stats {
     int32_t patch_rcv;        /* receivers per work item                         */
     double ms_pairs;          /* pair-kernel time, all passes (GBS_FLAG_TIME_KERNELS) */
     double ms_cull;           /* culling/list-building time (GBS_FLAG_TIME_KERNELS)   */
+    int32_t grid;             /* workgroups of the last persistent launch          */
+    int32_t blocks_per_cu;    /* resident workgroups per CU for that kernel        */
 } gbs_stats;
 
 /* Create a context on `device` (HIP ordinal) that enqueues on `hip_stream`

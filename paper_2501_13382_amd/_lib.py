@@ -49,7 +49,7 @@ class GbsParams(ctypes.Structure):
 class GbsStats(ctypes.Structure):
     _fields_ = [("dense_pairs", c_int64), ("listed_pairs", c_int64), ("active_pairs", c_int64),
                 ("n_items", c_int64), ("n_chunks", c_int32), ("patch_rcv", c_int32), ("ms_pairs", c_double),
-                ("ms_cull", c_double)]
+                ("ms_cull", c_double), ("grid", c_int32), ("blocks_per_cu", c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

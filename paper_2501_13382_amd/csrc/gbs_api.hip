@@ -33,15 +33,16 @@ __global__ void k_records(int64_t, const double*, const double*, const double*, 
                           const int64_t*, int64_t, const int32_t*, int32_t, const double*, const double*,
                           const int32_t*, SegRec*);
 template <bool FILL>
-__global__ void k_cull(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int32_t*, const int64_t*,
-                       int32_t*);
+__global__ void k_cull(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int, const CullSplit*,
+                       int32_t*, const int64_t*, int32_t*);
+__global__ void k_item_lengths(const int64_t*, int32_t, int, int32_t*);
 template <int MODE, int NR, bool COUNT>
-__global__ void k_pairs(const JobConst*, const int64_t*, const int32_t*, int32_t, int32_t, unsigned*,
+__global__ void k_pairs(const JobConst*, const int64_t*, int32_t, const int32_t*, int32_t, int32_t, unsigned*,
                         const int32_t*, const SegRec*, const double*, const double*, const double*, const double*,
                         const int32_t*, int64_t, double*, unsigned long long*);
 __global__ void k_tl(const double*, int64_t, double*);
 template <int MODE>
-__global__ void k_adjoint(const JobConst*, const int64_t*, const int32_t*, int32_t, int32_t, unsigned*,
+__global__ void k_adjoint(const JobConst*, const int64_t*, int32_t, const int32_t*, int32_t, int32_t, unsigned*,
                           const int32_t*, const SegRec*, const double*, const double*, const double*,
                           const double*, const int32_t*, int64_t, const double*, double*, double*, double*);
 __global__ void k_sum_jobs(const double*, int32_t, int64_t, double*);
@@ -75,6 +76,13 @@ struct GbsError : std::runtime_error {
     } while (0)
 
 inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)std::max<int64_t>(1, (n + threads - 1) / threads); }
+
+// Device fill with a kernel (no memset nodes, so it is safe in captured graphs).
+void fill(hipStream_t st, double* p, int64_t n, double v) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)std::min<int64_t>(4096, blocks_for(n, 256))), dim3(256), 0, st, p,
+                       n, v);
+}
 
 // Grow-only device buffers, keyed by name.
 struct Workspace {
@@ -211,6 +219,8 @@ void validate_host(const Args& a) {
     GBS_CHECK(a.rays->n_src >= 0 && a.rays->n_rays >= 0 && a.segs->n_segs >= 0 && a.n_rcv >= 0 && a.n_freq >= 0,
               "negative size");
     GBS_CHECK(a.faces->n_faces >= 0, "negative face count");
+    if (a.n_freq > kMaxBands)
+        throw GbsError(GBS_E_UNSUPPORTED, "at most 64 bands per call");
     GBS_CHECK(a.n_rcv <= (int64_t)INT32_MAX - 4096, "too many receivers");
     GBS_CHECK(a.segs->n_segs <= (int64_t)INT32_MAX, "too many segments");
     GBS_CHECK(a.rays->n_rays == 0 || a.rays->n_src > 0, "rays without sources");
@@ -448,6 +458,7 @@ struct Planner {
 
     struct Lists {
         int32_t n_items = 0;
+        int32_t n_split = 1;      // list offsets are strided: item i spans off[i*n_split .. (i+1)*n_split]
         int64_t total = 0;
         const JobConst* jobs = nullptr;
         const SegRec* rec = nullptr;
@@ -495,27 +506,52 @@ struct Planner {
         GBS_CHECK(n_items < INT32_MAX, "too many work items");
         L.n_items = (int32_t)n_items;
         if (n_items == 0) return L;
-        int32_t* counts = ws.get<int32_t>("counts", n_items + 2);
-        int64_t* off = ws.get<int64_t>("item_off", n_items + 1);
-        hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for((n_items + 2) / 2, 256)), dim3(256), 0, st, (double*)counts,
-                           (int64_t)((n_items + 2) / 2), 0.0);
-        dim3 cg(R.n_super, n_jobs);
-        hipLaunchKernelGGL(k_cull<false>, cg, dim3(kCullThreads), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
-                           counts, nullptr, nullptr);
+        // split every source's segment range so that culling runs wide; one
+        // workgroup culls one piece for all bands of its source
+        const int n_src = a.rays->n_src, n_freq = a.n_freq;
+        int64_t max_src = 0;
+        for (int sidx = 0; sidx < n_src; ++sidx)
+            max_src = std::max(max_src, J[sidx * n_freq].seg_end - J[sidx * n_freq].seg_begin);
+        int64_t span = std::max<int64_t>(4096, (max_src + 63) / 64);
+        span = (span + kCullThreads - 1) / kCullThreads * kCullThreads;
+        const int n_split = (int)std::max<int64_t>(1, (max_src + span - 1) / span);
+        std::vector<CullSplit> sv;
+        for (int sidx = 0; sidx < n_src; ++sidx) {
+            const int64_t b = J[sidx * n_freq].seg_begin, e = J[sidx * n_freq].seg_end;
+            int k = 0;
+            for (int64_t x = b; x < e; x += span, ++k) sv.push_back(CullSplit{x, std::min(x + span, e), sidx, k});
+        }
+        L.n_split = n_split;
+        const int64_t n_cnt = n_items * n_split;
+        GBS_CHECK(n_cnt < INT32_MAX, "too many cull partitions");
+        int32_t* counts = ws.get<int32_t>("counts", n_cnt + 2);
+        int64_t* off = ws.get<int64_t>("item_off", n_cnt + 1);
+        fill(st, (double*)counts, (n_cnt + 2) / 2, 0.0);
+        CullSplit* d_split = ws.get<CullSplit>("splits", std::max<size_t>(sv.size(), 1));
+        if (!sv.empty())
+            GBS_HIP(hipMemcpyAsync(d_split, sv.data(), sizeof(CullSplit) * sv.size(), hipMemcpyHostToDevice, st));
+        dim3 cg(R.n_super, (unsigned)std::max<size_t>(sv.size(), 1));
+        if (!sv.empty())
+            hipLaunchKernelGGL(k_cull<false>, cg, dim3(kCullThreads), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
+                               n_freq, n_split, d_split, counts, nullptr, nullptr);
         GBS_HIP(hipGetLastError());
         // counts are int32; accumulate in int64 through a converting iterator
         auto in64 = hipcub::TransformInputIterator<int64_t, Widen, const int32_t*>(counts, Widen());
         size_t tmp = 0;
-        GBS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, in64, off, (int)(n_items + 1), st));
+        GBS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, in64, off, (int)(n_cnt + 1), st));
         void* t = ws.get<char>("cub_tmp_scan", tmp);
-        GBS_HIP(hipcub::DeviceScan::ExclusiveSum(t, tmp, in64, off, (int)(n_items + 1), st));
-        GBS_HIP(hipMemcpyAsync(&L.total, off + n_items, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        GBS_HIP(hipcub::DeviceScan::ExclusiveSum(t, tmp, in64, off, (int)(n_cnt + 1), st));
+        GBS_HIP(hipMemcpyAsync(&L.total, off + n_cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st));
         GBS_HIP(hipStreamSynchronize(st));
         int32_t* lists = ws.get<int32_t>("lists", std::max<int64_t>(L.total, 1));
-        hipLaunchKernelGGL(k_cull<true>, cg, dim3(kCullThreads), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
-                           nullptr, off, lists);
+        if (!sv.empty())
+            hipLaunchKernelGGL(k_cull<true>, cg, dim3(kCullThreads), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
+                               n_freq, n_split, d_split, nullptr, off, lists);
         GBS_HIP(hipGetLastError());
         // longest lists first
+        int32_t* lens = ws.get<int32_t>("lens", n_items);
+        hipLaunchKernelGGL(k_item_lengths, dim3(blocks_for(n_items, 256)), dim3(256), 0, st, off, (int32_t)n_items,
+                           n_split, lens);
         int32_t* keys2 = ws.get<int32_t>("okeys", n_items);
         int32_t* ids = ws.get<int32_t>("oids", n_items);
         int32_t* order = ws.get<int32_t>("order", n_items);
@@ -523,10 +559,10 @@ struct Planner {
         for (int64_t i = 0; i < n_items; ++i) iota[i] = (int32_t)i;
         GBS_HIP(hipMemcpyAsync(ids, iota.data(), sizeof(int32_t) * n_items, hipMemcpyHostToDevice, st));
         size_t tmp2 = 0;
-        GBS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tmp2, counts, keys2, ids, order, (int)n_items,
+        GBS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tmp2, lens, keys2, ids, order, (int)n_items,
                                                              0, 32, st));
         void* t2 = ws.get<char>("cub_tmp_order", tmp2);
-        GBS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(t2, tmp2, counts, keys2, ids, order, (int)n_items, 0, 32,
+        GBS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(t2, tmp2, lens, keys2, ids, order, (int)n_items, 0, 32,
                                                              st));
         GBS_HIP(hipStreamSynchronize(st));  // iota staging is pageable host memory
         L.item_off = off;
@@ -571,21 +607,32 @@ struct EventPair {
 int pick_nr(gbs_ctx* ctx, const gbs_params* p, int64_t n_rcv) {
     if (p->rcv_per_lane) return p->rcv_per_lane;
     if (ctx->tuned_nr[p->mode]) return ctx->tuned_nr[p->mode];
-    if (n_rcv < 64 * 256) return 1;
-    return p->mode == GBS_MODE_F64 ? 1 : 2;
+    (void)n_rcv;
+    return 1;   // measured fastest on MI355X: 64-receiver patches cull tightest
+}
+
+// Workgroups of the persistent kernels: as many as can be resident at once
+// (every wave of a workgroup pops its own items), never more than needed.
+int64_t persistent_grid(gbs_ctx* ctx, const void* kern, int64_t n_items) {
+    int per_cu = 0;
+    GBS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kPairThreads, 0));
+    int64_t grid = std::max(1, per_cu) * (int64_t)ctx->n_cu;
+    const int64_t waves = kPairThreads / kWave;
+    grid = std::min<int64_t>(grid, (n_items + waves - 1) / waves);
+    ctx->stats.grid = (int32_t)grid;
+    ctx->stats.blocks_per_cu = per_cu;
+    return std::max<int64_t>(grid, 1);
 }
 
 template <int MODE, int NR, bool COUNT>
 void launch_pairs(gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const RcvPlan& R, int64_t n_rcv, double* P,
                   unsigned* ctr, unsigned long long* n_active) {
     auto kern = k_pairs<MODE, NR, COUNT>;
-    int per_cu = 0;
-    GBS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, 0));
-    int64_t grid = std::max(1, per_cu) * (int64_t)ctx->n_cu;
-    grid = std::min<int64_t>(grid, L.n_items);
+    const int64_t grid = persistent_grid(ctx, (const void*)kern, L.n_items);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, ctr);
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), 0, st, L.jobs, L.item_off, L.item_order, L.n_items,
-                       R.n_patch, ctr, L.lists, L.rec, R.rx, R.ry, R.rz, R.r2, R.perm, n_rcv, P, n_active);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPairThreads), 0, st, L.jobs, L.item_off, L.n_split,
+                       L.item_order, L.n_items, R.n_patch, ctr, L.lists, L.rec, R.rx, R.ry, R.rz, R.r2, R.perm, n_rcv,
+                       P, n_active);
     GBS_HIP(hipGetLastError());
 }
 
@@ -611,11 +658,6 @@ void dispatch_pairs(int mode, bool count, int nr, gbs_ctx* ctx, hipStream_t st, 
     }
 }
 
-void fill(hipStream_t st, double* p, int64_t n, double v) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)std::min<int64_t>(4096, blocks_for(n, 256))), dim3(256), 0, st, p,
-                       n, v);
-}
 
 int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* TL, int nr_override) {
     validate_host(a);
@@ -666,6 +708,8 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
         hipLaunchKernelGGL(k_tl, dim3(blocks_for(n_out, 256)), dim3(256), 0, st, P, n_out, TL);
         GBS_HIP(hipGetLastError());
     }
+    stats.grid = ctx->stats.grid;
+    stats.blocks_per_cu = ctx->stats.blocks_per_cu;
     ctx->stats = stats;
     return GBS_OK;
 }
@@ -783,13 +827,11 @@ int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
                 fill(st, Sseg, 2 * nseg, 0.0);
                 if (L.n_items > 0 && L.total > 0) {
                     auto kern = params->mode == GBS_MODE_F64 ? k_adjoint<0> : k_adjoint<1>;
-                    int per_cu = 0;
-                    GBS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, 0));
-                    int64_t grid = std::min<int64_t>(std::max(1, per_cu) * (int64_t)ctx->n_cu, L.n_items);
+                    const int64_t grid = persistent_grid(ctx, (const void*)kern, L.n_items);
                     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, ctr);
-                    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), 0, st, L.jobs, L.item_off, L.item_order,
-                                       L.n_items, pl.R.n_patch, ctr, L.lists, L.rec, pl.R.rx, pl.R.ry, pl.R.rz,
-                                       pl.R.r2, pl.R.perm, n_rcv, lambda, dRj, Sseg, dE);
+                    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPairThreads), 0, st, L.jobs, L.item_off,
+                                       L.n_split, L.item_order, L.n_items, pl.R.n_patch, ctr, L.lists, L.rec, pl.R.rx,
+                                       pl.R.ry, pl.R.rz, pl.R.r2, pl.R.perm, n_rcv, lambda, dRj, Sseg, dE);
                     GBS_HIP(hipGetLastError());
                 }
                 if (nf > 0 && nseg > 0) {
@@ -810,6 +852,8 @@ int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
             GBS_HIP(hipMemcpyAsync(d_eps, dE, sizeof(double) * n_jobs, hipMemcpyDeviceToDevice, st));
         GBS_HIP(hipGetLastError());
         GBS_HIP(hipStreamSynchronize(st));  // scratch reused by the next call
+        stats.grid = ctx->stats.grid;
+        stats.blocks_per_cu = ctx->stats.blocks_per_cu;
         ctx->stats = stats;
         return GBS_OK;
     });

@@ -9,6 +9,8 @@ namespace gbs {
 constexpr int kWave = 64;             // CDNA wavefront width
 constexpr int kCullThreads = 256;     // cull kernel workgroup (4 waves)
 constexpr int kSuperPatches = 16;     // patches per culling super-patch
+constexpr int kPairThreads = 256;     // pair/adjoint workgroup: 4 independent persistent waves
+constexpr int kMaxBands = 64;         // bands per call (one bit each in the cull's band masks)
 
 // Per-job constants (job = (source, band)), computed on the host.
 struct JobConst {
@@ -44,6 +46,13 @@ static_assert(sizeof(SegRec) == 96, "SegRec layout");
 
 struct Patch {
     double cx, cy, cz, rad;   // bounding sphere of a receiver patch
+};
+
+// A contiguous piece of one source's segments, culled by one workgroup.
+struct CullSplit {
+    int64_t begin, end;       // segment range (pass-local indices)
+    int32_t src;              // source of every segment in the range
+    int32_t idx;              // index of the piece within its source
 };
 
 }  // namespace gbs

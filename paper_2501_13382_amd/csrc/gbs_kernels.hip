@@ -36,6 +36,14 @@ __device__ __forceinline__ double wave_sum(double v) {
 // gated block above its wave-uniform branch and execute it for every pair.
 __device__ __forceinline__ void branch_barrier() { asm volatile(""); }
 
+// Orders this wave's LDS accesses around a tile hand-over: the tile slice is
+// private to the wave and LDS executes one wave's operations in order, so a
+// compiler-level fence is all that is needed.
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 __device__ __forceinline__ int lanes_before(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
@@ -216,11 +224,19 @@ __global__ void k_records(int64_t n_segs, const double* __restrict__ a, const do
 
 // ------------------------------------------------------------------ culling
 // Conservative test: can the beam of segment S pass the gate for any receiver
-// inside the patch's bounding sphere?  For R in the sphere, the arc length is
-// within rad of the centre's and the normal distance is at least the centre's
-// minus rad (distance to a line is 1-Lipschitz), while the gate needs
-// n^2 <= kappa (s^2 + eps^2).  Margins cover rounding.
-__device__ __forceinline__ bool may_reach(const SegRec& S, const Patch& p, const JobConst& J) {
+// inside a bounding sphere (centre C, radius rad)?  For R in the sphere, the
+// arc length is within rad of the centre's and the normal distance is at
+// least the centre's minus rad (distance to a line is 1-Lipschitz), while
+// the gate needs n^2 <= kappa (s^2 + eps^2).  The geometry does not depend on
+// the band; each band then only compares d^2 <= kappa_b sm^2 + kappa_b eps_b^2
+// with d = max(n_C - rad, 0) and sm the largest |s| the sphere can reach
+// inside the beam interval.  Margins cover rounding (n_C is under-estimated).
+struct Reach {
+    double d2, sm2;
+    bool ok;
+};
+
+__device__ __forceinline__ Reach reach(const SegRec& S, const Patch& p) {
     double ox = -0.5 * S.m2ox, oy = -0.5 * S.m2oy, oz = -0.5 * S.m2oz;
     double vx = p.cx - ox, vy = p.cy - oy, vz = p.cz - oz;
     double sc = vx * S.tx + vy * S.ty + vz * S.tz;
@@ -228,74 +244,120 @@ __device__ __forceinline__ bool may_reach(const SegRec& S, const Patch& p, const
     double nc2 = fmax(vv - sc * sc, 0.0);
     double rad = p.rad * (1.0 + 1e-9) + 1e-6 * (1.0 + fabs(sc));
     double sa = fmax(sc - rad, S.slo), sb = fmin(sc + rad, S.shi);
-    if (sa > sb) return false;
     double sm = fmax(fabs(sa), fabs(sb));
-    double X = sqrt(J.kappa * (sm * sm + J.eps2)) * (1.0 + 1e-9);
-    double lim = rad + X;
-    return nc2 <= lim * lim;
+    double nc = (double)__builtin_amdgcn_sqrtf((float)nc2) * (1.0 - 1e-6);
+    double d = fmax(nc - rad, 0.0);
+    return Reach{d * d, sm * sm, sa <= sb};
 }
 
-// Two-level cull.  One workgroup per (job, super-patch of kSuperPatches
-// patches): the job's segments are first tested against the super-patch
-// sphere, survivors go to LDS, then each wave tests them against its own
-// patches.  The count pass writes list lengths; the fill pass writes the
-// lists at the offsets given by the exclusive prefix sum of the lengths.
-// Lists come out in segment order (deterministic).
+__device__ __forceinline__ bool reach_band(const Reach& r, double kap, double kap_eps2) {
+    return r.ok && r.d2 <= fma(kap, r.sm2, kap_eps2) * (1.0 + 1e-9);
+}
+
+// Two-level cull.  One workgroup per (super-patch of kSuperPatches patches,
+// split of one source's segment range).  Each segment record is loaded once
+// and tested for every band of its source: first against the super-patch
+// sphere (survivors and their band mask go to LDS), then each wave tests the
+// survivors against its own patches.  The count pass writes one length per
+// (job, patch, split); the fill pass writes at the exclusive prefix sum of
+// those lengths, so each job-patch list is the concatenation of its splits
+// in order: segment order, deterministic.
 template <bool FILL>
 __global__ __launch_bounds__(kCullThreads) void k_cull(const JobConst* __restrict__ jobs,
                                                        const SegRec* __restrict__ rec,
                                                        const Patch* __restrict__ patches,
-                                                       const Patch* __restrict__ supers, int n_patch,
+                                                       const Patch* __restrict__ supers, int n_patch, int n_freq,
+                                                       int n_split, const CullSplit* __restrict__ splits,
                                                        int32_t* __restrict__ counts,
-                                                       const int64_t* __restrict__ item_off,
+                                                       const int64_t* __restrict__ off,
                                                        int32_t* __restrict__ lists) {
     constexpr int kWaves = kCullThreads / kWave;
     constexpr int kOwn = kSuperPatches / kWaves;
-    __shared__ int32_t q[kCullThreads];
+    __shared__ int32_t q_seg[kCullThreads];
+    __shared__ unsigned long long q_mask[kCullThreads];
     __shared__ int wave_cnt[kWaves];
-    const int job = blockIdx.y, sp = blockIdx.x;
+    __shared__ double kap[kMaxBands], kape[kMaxBands];
+    __shared__ int32_t run[kSuperPatches][kMaxBands];
+    const int sp = blockIdx.x;
+    const CullSplit sl = splits[blockIdx.y];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const JobConst J = jobs[job];
+    const int64_t job0 = (int64_t)sl.src * n_freq;
+    for (int b = tid; b < n_freq; b += kCullThreads) {
+        const JobConst J = jobs[job0 + b];
+        kap[b] = J.kappa;
+        kape[b] = J.kappa * J.eps2;
+    }
+    for (int i = tid; i < kSuperPatches * kMaxBands; i += kCullThreads) run[i / kMaxBands][i % kMaxBands] = 0;
     const Patch SPt = supers[sp];
     const int p0 = sp * kSuperPatches;
     Patch mine[kOwn];
-    int64_t run[kOwn], base[kOwn];
     for (int m = 0; m < kOwn; ++m) {
         int p = p0 + wv + kWaves * m;
         mine[m] = p < n_patch ? patches[p] : Patch{0, 0, 0, -1};
-        run[m] = 0;
-        base[m] = (FILL && p < n_patch) ? item_off[(int64_t)job * n_patch + p] : 0;
     }
-    for (int64_t c = J.seg_begin; c < J.seg_end; c += kCullThreads) {
-        int64_t j = c + tid;
-        bool keep = j < J.seg_end && may_reach(rec[j], SPt, J);
+    __syncthreads();
+    for (int64_t c = sl.begin; c < sl.end; c += kCullThreads) {
+        const int64_t j = c + tid;
+        unsigned long long mask = 0ull;
+        if (j < sl.end) {
+            const Reach r = reach(rec[j], SPt);
+            for (int b = 0; b < n_freq; ++b) mask |= (unsigned long long)reach_band(r, kap[b], kape[b]) << b;
+        }
+        const bool keep = mask != 0ull;
         unsigned long long bal = __ballot(keep);
         if (lane == 0) wave_cnt[wv] = __popcll(bal);
         __syncthreads();
-        int off = 0, tot = 0;
+        int pre = 0, tot = 0;
         for (int w = 0; w < kWaves; ++w) {
-            off += w < wv ? wave_cnt[w] : 0;
+            pre += w < wv ? wave_cnt[w] : 0;
             tot += wave_cnt[w];
         }
-        if (keep) q[off + lanes_before(bal)] = (int32_t)j;
+        if (keep) {
+            q_seg[pre + lanes_before(bal)] = (int32_t)j;
+            q_mask[pre + lanes_before(bal)] = mask;
+        }
         __syncthreads();
         for (int m = 0; m < kOwn; ++m) {
             if (mine[m].rad < 0) continue;
-            for (int b = 0; b < tot; b += 64) {
-                int i = b + lane;
-                bool k2 = i < tot && may_reach(rec[q[i]], mine[m], J);
-                unsigned long long bl = __ballot(k2);
-                if (FILL && k2) lists[base[m] + run[m] + lanes_before(bl)] = q[i];
-                run[m] += __popcll(bl);
+            const int p = p0 + wv + kWaves * m;
+            const int pm = wv + kWaves * m;
+            for (int b0 = 0; b0 < tot; b0 += 64) {
+                const int i = b0 + lane;
+                const int32_t seg = i < tot ? q_seg[i] : 0;
+                const unsigned long long qm = i < tot ? q_mask[i] : 0ull;
+                const Reach r = reach(rec[seg], mine[m]);
+                for (int b = 0; b < n_freq; ++b) {
+                    const bool k2 = ((qm >> b) & 1ull) && reach_band(r, kap[b], kape[b]);
+                    const unsigned long long bl = __ballot(k2);
+                    if (bl == 0ull) continue;
+                    const int32_t done = run[pm][b];
+                    if (FILL && k2) {
+                        const int64_t base = off[((job0 + b) * n_patch + p) * n_split + sl.idx];
+                        lists[base + done + lanes_before(bl)] = seg;
+                    }
+                    run[pm][b] = done + __popcll(bl);   // this wave owns (pm, b): every lane stores the same value
+                }
             }
         }
         __syncthreads();
     }
-    if (!FILL && lane == 0)
+    if (!FILL) {
         for (int m = 0; m < kOwn; ++m) {
-            int p = p0 + wv + kWaves * m;
-            if (p < n_patch) counts[(int64_t)job * n_patch + p] = (int32_t)run[m];
+            const int p = p0 + wv + kWaves * m;
+            if (p >= n_patch) continue;
+            const int pm = wv + kWaves * m;
+            for (int b = lane; b < n_freq; b += 64)
+                counts[((job0 + b) * n_patch + p) * n_split + sl.idx] = run[pm][b];
         }
+    }
+}
+
+// Length of every item's list: the span of its splits in the prefix sum.
+__global__ void k_item_lengths(const int64_t* __restrict__ off, int32_t n_items, int n_split,
+                               int32_t* __restrict__ len) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_items) return;
+    len[i] = (int32_t)(off[(int64_t)(i + 1) * n_split] - off[(int64_t)i * n_split]);
 }
 
 // ------------------------------------------------------------- pair kernels
@@ -393,6 +455,22 @@ struct PairEval<kF32> {
     }
 };
 
+// A segment record in registers, as six named 16-byte vectors (kept out of
+// arrays so the compiler keeps them in VGPRs): vector loads, 128-bit LDS stores.
+#define GBS_REC_REGS(n) double2 n##0, n##1, n##2, n##3, n##4, n##5
+#define GBS_REC_LOAD(n, recp, j)                                                  \
+    do {                                                                          \
+        const double2* p_ = reinterpret_cast<const double2*>((recp) + (j));       \
+        n##0 = p_[0]; n##1 = p_[1]; n##2 = p_[2];                                 \
+        n##3 = p_[3]; n##4 = p_[4]; n##5 = p_[5];                                 \
+    } while (0)
+#define GBS_REC_STORE(dst, n)                                                     \
+    do {                                                                          \
+        double2* q_ = reinterpret_cast<double2*>(dst);                            \
+        q_[0] = n##0; q_[1] = n##1; q_[2] = n##2;                                 \
+        q_[3] = n##3; q_[4] = n##4; q_[5] = n##5;                                 \
+    } while (0)
+
 // Pops the next work item (wave-uniform) from the global counter.  Lane 0
 // issues the atomic.  Callers put branch_barrier() in front of it and issue
 // their own end-of-item atomics from lane kLastLane: if both ends of the loop
@@ -400,7 +478,7 @@ struct PairEval<kF32> {
 // two guards across the back edge and re-run the index shuffle without lane 0.
 __device__ __forceinline__ int pop_item(unsigned* ctr) {
     int it = 0;
-    if (threadIdx.x == 0) it = (int)atomicAdd(ctr, 1u);
+    if ((threadIdx.x & (kWave - 1)) == 0) it = (int)atomicAdd(ctr, 1u);
     it = __shfl(it, 0);
     return __builtin_amdgcn_readfirstlane(it);
 }
@@ -408,10 +486,14 @@ constexpr int kLastLane = kWave - 1;
 
 // Persistent forward kernel: one wavefront per (job, patch) item; the patch
 // holds 64 * NR receivers, lane l owns receivers l, l + 64, ...
+// The item's segment list is walked in tiles of 64: lane l gathers record l
+// of the next tile with vector loads (one memory round trip per tile, issued
+// a whole tile ahead), the tile goes to the wave's LDS slice, and every
+// segment is then read back as a wave-uniform LDS broadcast.
 // P (job-major, original receiver order) accumulates scale * sum.
 template <int MODE, int NR, bool COUNT>
-__global__ __launch_bounds__(64) void k_pairs(const JobConst* __restrict__ jobs,
-                                              const int64_t* __restrict__ item_off,
+__global__ __launch_bounds__(kPairThreads) void k_pairs(const JobConst* __restrict__ jobs,
+                                              const int64_t* __restrict__ item_off, int32_t off_stride,
                                               const int32_t* __restrict__ item_order, int32_t n_items,
                                               int32_t n_patch, unsigned* __restrict__ ctr,
                                               const int32_t* __restrict__ lists, const SegRec* __restrict__ rec,
@@ -419,14 +501,16 @@ __global__ __launch_bounds__(64) void k_pairs(const JobConst* __restrict__ jobs,
                                               const double* __restrict__ rz, const double* __restrict__ r2,
                                               const int32_t* __restrict__ perm, int64_t n_rcv,
                                               double* __restrict__ P, unsigned long long* __restrict__ n_active) {
-    const int lane = threadIdx.x;
+    __shared__ __align__(16) SegRec tile[kPairThreads / kWave][kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    SegRec* const my = tile[threadIdx.x / kWave];
     unsigned long long active = 0;
     for (;;) {
         branch_barrier();
         const int it = pop_item(ctr);
         if (it >= n_items) break;
         const int item = __builtin_amdgcn_readfirstlane(item_order[it]);
-        const int64_t beg = item_off[item], end = item_off[item + 1];
+        const int64_t beg = item_off[(int64_t)item * off_stride], end = item_off[(int64_t)(item + 1) * off_stride];
         if (beg == end) continue;
         const int job = item / n_patch, patch = item - job * n_patch;
         const JobConst J = jobs[job];
@@ -441,18 +525,22 @@ __global__ __launch_bounds__(64) void k_pairs(const JobConst* __restrict__ jobs,
             ar[m] = 0.0;
             ai[m] = 0.0;
         }
-        // software pipeline: the record of e + 1 and the index of e + 2 load
-        // while segment e is evaluated
-        int32_t jn = lists[beg + 1 < end ? beg + 1 : beg];
-        SegRec Sn = rec[lists[beg]];
-        for (int64_t e = beg; e < end; ++e) {
-            const SegRec S = Sn;
-            Sn = rec[jn];
-            jn = lists[e + 2 < end ? e + 2 : end - 1];
+        GBS_REC_REGS(nx);
+        GBS_REC_LOAD(nx, rec, lists[min(beg + lane, end - 1)]);
+        for (int64_t e0 = beg; e0 < end; e0 += kWave) {
+            const int cnt = (int)min<int64_t>(kWave, end - e0);
+            wave_lds_fence();
+            GBS_REC_STORE(my + lane, nx);
+            wave_lds_fence();
+            // next tile (the last one re-reads a valid record: clamped, never out of range)
+            GBS_REC_LOAD(nx, rec, lists[min(e0 + kWave + lane, end - 1)]);
+            for (int k = 0; k < cnt; ++k) {
+                const SegRec S = my[k];
 #pragma unroll
-            for (int m = 0; m < NR; ++m) {
-                bool hit = PairEval<MODE>::eval(S, J, X[m], Y[m], Z[m], R2[m], ar[m], ai[m]);
-                if (COUNT) active += hit ? 1ull : 0ull;
+                for (int m = 0; m < NR; ++m) {
+                    bool hit = PairEval<MODE>::eval(S, J, X[m], Y[m], Z[m], R2[m], ar[m], ai[m]);
+                    if (COUNT) active += hit ? 1ull : 0ull;
+                }
             }
         }
 #pragma unroll
@@ -577,8 +665,8 @@ __device__ __forceinline__ bool adj_eval(const SegRec& S, const JobConst& J, dou
 // per segment: sum over lanes of lambda * B (wave reduction) -> FP64 atomics
 // into Sseg; per job: d eps via a wave reduction and one atomic per item.
 template <int MODE>
-__global__ __launch_bounds__(64) void k_adjoint(const JobConst* __restrict__ jobs,
-                                                const int64_t* __restrict__ item_off,
+__global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __restrict__ jobs,
+                                                const int64_t* __restrict__ item_off, int32_t off_stride,
                                                 const int32_t* __restrict__ item_order, int32_t n_items,
                                                 int32_t n_patch, unsigned* __restrict__ ctr,
                                                 const int32_t* __restrict__ lists, const SegRec* __restrict__ rec,
@@ -587,13 +675,13 @@ __global__ __launch_bounds__(64) void k_adjoint(const JobConst* __restrict__ job
                                                 const int32_t* __restrict__ perm, int64_t n_rcv,
                                                 const double* __restrict__ lambda, double* __restrict__ dR_job,
                                                 double* __restrict__ Sseg, double* __restrict__ d_eps) {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
     for (;;) {
         branch_barrier();
         const int it = pop_item(ctr);
         if (it >= n_items) break;
         const int item = __builtin_amdgcn_readfirstlane(item_order[it]);
-        const int64_t beg = item_off[item], end = item_off[item + 1];
+        const int64_t beg = item_off[(int64_t)item * off_stride], end = item_off[(int64_t)(item + 1) * off_stride];
         if (beg == end) continue;
         const int job = item / n_patch, patch = item - job * n_patch;
         const JobConst J = jobs[job];
@@ -704,13 +792,13 @@ __global__ void k_validate(int64_t n_segs, const double* __restrict__ t, const d
 }
 
 // Explicit instantiations used by the host planner.
-template __global__ void k_cull<false>(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int32_t*,
-                                       const int64_t*, int32_t*);
-template __global__ void k_cull<true>(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int32_t*,
-                                      const int64_t*, int32_t*);
+template __global__ void k_cull<false>(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int,
+                                       const CullSplit*, int32_t*, const int64_t*, int32_t*);
+template __global__ void k_cull<true>(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int,
+                                      const CullSplit*, int32_t*, const int64_t*, int32_t*);
 #define GBS_INST_PAIRS(M, N, C)                                                                                  \
-    template __global__ void k_pairs<M, N, C>(const JobConst*, const int64_t*, const int32_t*, int32_t, int32_t,  \
-                                              unsigned*, const int32_t*, const SegRec*, const double*,           \
+    template __global__ void k_pairs<M, N, C>(const JobConst*, const int64_t*, int32_t, const int32_t*, int32_t,   \
+                                              int32_t, unsigned*, const int32_t*, const SegRec*, const double*,  \
                                               const double*, const double*, const double*, const int32_t*,       \
                                               int64_t, double*, unsigned long long*);
 #define GBS_INST_PAIRS_MODE(M) \
@@ -719,11 +807,11 @@ template __global__ void k_cull<true>(const JobConst*, const SegRec*, const Patc
 GBS_INST_PAIRS_MODE(0)
 GBS_INST_PAIRS_MODE(1)
 GBS_INST_PAIRS_MODE(2)
-template __global__ void k_adjoint<0>(const JobConst*, const int64_t*, const int32_t*, int32_t, int32_t, unsigned*,
+template __global__ void k_adjoint<0>(const JobConst*, const int64_t*, int32_t, const int32_t*, int32_t, int32_t, unsigned*,
                                       const int32_t*, const SegRec*, const double*, const double*, const double*,
                                       const double*, const int32_t*, int64_t, const double*, double*, double*,
                                       double*);
-template __global__ void k_adjoint<1>(const JobConst*, const int64_t*, const int32_t*, int32_t, int32_t, unsigned*,
+template __global__ void k_adjoint<1>(const JobConst*, const int64_t*, int32_t, const int32_t*, int32_t, int32_t, unsigned*,
                                       const int32_t*, const SegRec*, const double*, const double*, const double*,
                                       const double*, const int32_t*, int64_t, const double*, double*, double*,
                                       double*);

@@ -36,7 +36,7 @@ def test_struct_sizes_match_c_layout():
     assert ctypes.sizeof(_lib.GbsSegs) == 64
     assert ctypes.sizeof(_lib.GbsFaces) == 16
     assert ctypes.sizeof(_lib.GbsParams) == 40
-    assert ctypes.sizeof(_lib.GbsStats) == 56
+    assert ctypes.sizeof(_lib.GbsStats) == 64
 
 
 def test_create_without_gpu_fails_cleanly():

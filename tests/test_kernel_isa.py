@@ -7,8 +7,8 @@ item-index shuffle with lanes 1..63 only, so those lanes re-processed a stale
 item forever.  The kernels must keep exactly one loop around the item pop:
 its header issues the counter atomic and no inner loop contains the shuffle
 that broadcasts the popped index.  Also checks that the pair kernels use
-scalar loads for segment records, have a real branch around the gated beam
-term and never spill to scratch.
+tiled segment records (vector gathers into LDS, LDS broadcast reads), have a
+real branch around the gated beam term and never spill to scratch.
 """
 import os
 import re
@@ -74,9 +74,9 @@ def test_single_item_loop_around_pop(asm, prefix):
     assert found > 0
 
 
-def test_pair_kernels_scalar_records_real_branch_no_spill(asm):
+def test_pair_kernels_tiled_records_real_branch_no_spill(asm):
     for name, body, meta in kernels(asm, r"_ZN3gbs7k_pairs"):
-        assert "s_load_dwordx8" in body or "s_load_dwordx16" in body, name   # records via scalar loads
+        assert "ds_read_b128" in body and "global_load_dwordx4" in body, name   # tiles: gathered, then LDS
         assert "s_cbranch_vccz" in body or "s_cbranch_execz" in body, name
         m = re.search(r"\.amdhsa_private_segment_fixed_size\s+(\d+)", meta)
         assert m and int(m.group(1)) == 0, name
