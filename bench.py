@@ -26,15 +26,19 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per pair of the pair kernel (counted from the evaluated
-# formulas; an FMA counts 2, a transcendental 1): the gate on every listed
-# pair, the beam term on every pair the gate keeps.
-FLOP_PRE = 15
-FLOP_IN = {"mix": 35, "f64": 35, "f32": 35}
-# Vector peak with packed FP32 disabled: 256 CUs x 64 lanes x 2 (FMA) x 2.4 GHz,
-# identical for FP32 and FP64 on gfx950.
-PEAK_VALU_FLOPS = 256 * 64 * 2 * 2.4e9
-PEAK_PACKED_FP32 = 157.3e12
+# Algorithmic work per pair of the pair kernel, counted from the evaluated
+# formulas (an FMA counts 2; a transcendental, a reciprocal or a fract 1):
+#   gate, every listed pair:  s (3 FMA), |R-o|^2 (3 FMA), rhs (mul, FMA, add)   -> 16 FP64
+#   beam term, every kept pair: n^2, den, Newton reciprocal, phase in cycles,
+#       fract, FP64 accumulation                                            -> 17 FP64
+#     rcp, sin, cos, exp2, Gaussian, amplitude and complex products         -> 21 FP32
+FLOP_LISTED_F64 = 16
+FLOP_KEPT_F64 = 17
+FLOP_KEPT_F32 = 21
+# Vector peaks from unit counts and clock: 256 CUs x 2.4 GHz x 64 FMA lanes x 2
+# = 78.6 TFLOP/s FP64; FP32 157.3 TFLOP/s (vendor figure).
+PEAK_F64 = 256 * 2.4e9 * 64 * 2
+PEAK_F32 = 157.3e12
 
 
 def parse():
@@ -99,14 +103,18 @@ def main():
     step(mode, count=True)
     st = gbs.stats(dev)
     listed, active = st["listed_pairs"], st["active_pairs"]
-    flops = FLOP_PRE * listed + FLOP_IN[mode] * active
+    f64 = FLOP_LISTED_F64 * listed + FLOP_KEPT_F64 * active
+    f32 = FLOP_KEPT_F32 * active
+    flops = f64 + f32
     achieved = flops / (ms_pairs * 1e-3)
+    # peak for this kernel's FP64/FP32 mix: time at peak = f64/PEAK_F64 + f32/PEAK_F32
+    peak = flops / (f64 / PEAK_F64 + f32 / PEAK_F32)
 
-    f64 = None
+    f64_leg = None
     if not args.no_f64:
         s64, ms64, _ = run("f64", max(2, args.steps // 2), 1)
-        f64 = {"value": dense / s64, "ms_per_step": s64 * 1e3, "ms_pair_kernel": ms64,
-               "mix_speedup": s64 / sec_step}
+        f64_leg = {"value": dense / s64, "ms_per_step": s64 * 1e3, "ms_pair_kernel": ms64,
+                   "mix_speedup": s64 / sec_step}
         print(f"# f64: {s64 * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
 
     result = {
@@ -126,14 +134,15 @@ def main():
                    "receivers": int(len(sc.rcv)), "bands": int(len(sc.freqs)), "mode": mode,
                    "dense_pairs": dense, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": "k_pairs<MIX>", "achieved": achieved / 1e12,
-                     "peak": PEAK_VALU_FLOPS / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_FLOPS,
-                     "frac_of_packed_fp32_peak": achieved / PEAK_PACKED_FP32, "traffic": None,
-                     "ms_per_launch": ms_pairs, "listed_pairs": listed, "active_pairs": active,
-                     "flop_per_listed_pair": FLOP_PRE, "flop_per_active_pair": FLOP_IN[mode]},
+                     "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "frac_of_fp32_peak": achieved / PEAK_F32, "frac_of_fp64_peak": achieved / PEAK_F64,
+                     "traffic": None, "ms_per_launch": ms_pairs, "listed_pairs": listed, "kept_pairs": active,
+                     "flop_per_listed_pair": {"f64": FLOP_LISTED_F64},
+                     "flop_per_kept_pair": {"f64": FLOP_KEPT_F64, "f32": FLOP_KEPT_F32}},
         "pair_kernel_share": ms_pairs / (sec_step * 1e3),
         "ms_cull": launch["ms_cull"],
         "launch": {"grid": launch["grid"], "blocks_per_cu": launch["blocks_per_cu"], "threads_per_block": 256},
-        "f64": f64,
+        "f64": f64_leg,
     }
 
     if args.copy_calibration > 0:

@@ -37,9 +37,14 @@ __global__ void k_cull(const JobConst*, const SegRec*, const Patch*, const Patch
                        int32_t*, const int64_t*, int32_t*);
 __global__ void k_item_lengths(const int64_t*, int32_t, int, int32_t*);
 template <int MODE, int NR, bool COUNT>
-__global__ void k_pairs(const JobConst*, const int64_t*, int32_t, const int32_t*, int32_t, int32_t, unsigned*,
-                        const int32_t*, const SegRec*, const double*, const double*, const double*, const double*,
-                        const int32_t*, int64_t, double*, unsigned long long*);
+__global__ void k_pairs(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*, const int32_t*,
+                        const SegRec*, const double*, const double*, const double*, const double*, double*,
+                        unsigned long long*);
+__global__ void k_work_counts(const int32_t*, const int32_t*, int32_t, int32_t, int32_t*);
+__global__ void k_make_work(const int32_t*, const int64_t*, int32_t, const int32_t*, int32_t, int32_t, Work*, int32_t*,
+                            int32_t*, int32_t*);
+__global__ void k_reduce_partials(const JobConst*, const int32_t*, const int32_t*, int32_t, int32_t, int,
+                                  const int32_t*, int64_t, const double*, double*);
 __global__ void k_tl(const double*, int64_t, double*);
 template <int MODE>
 __global__ void k_adjoint(const JobConst*, const int64_t*, int32_t, const int32_t*, int32_t, int32_t, unsigned*,
@@ -466,6 +471,13 @@ struct Planner {
         const int64_t* item_off = nullptr;
         const int32_t* item_order = nullptr;
         const int32_t* lists = nullptr;
+        // pair-kernel work units (chunks of the item lists) and their partials
+        const Work* work = nullptr;
+        const int32_t* n_work = nullptr;     // device: number of work units
+        const int32_t* item_wbase = nullptr;
+        const int32_t* item_wcount = nullptr;
+        double* partial = nullptr;
+        int64_t work_cap = 0;
     };
 
     // Records, job constants, culled lists and the longest-first item order
@@ -565,6 +577,29 @@ struct Planner {
         GBS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(t2, tmp2, lens, keys2, ids, order, (int)n_items, 0, 32,
                                                              st));
         GBS_HIP(hipStreamSynchronize(st));  // iota staging is pageable host memory
+        // work units: every list cut into chunks of at most kWorkChunk segments
+        const int64_t cap = n_items + L.total / kWorkChunk + 1;
+        GBS_CHECK(cap < INT32_MAX, "too many work units");
+        int32_t* nw = ws.get<int32_t>("nwork", n_items + 1);
+        int32_t* wb = ws.get<int32_t>("wbase", n_items + 1);
+        hipLaunchKernelGGL(k_work_counts, dim3(blocks_for(n_items + 1, 256)), dim3(256), 0, st, order, lens,
+                           (int32_t)n_items, kWorkChunk, nw);
+        size_t tmp3 = 0;
+        GBS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp3, nw, wb, (int)(n_items + 1), st));
+        void* t3 = ws.get<char>("cub_tmp_work", tmp3);
+        GBS_HIP(hipcub::DeviceScan::ExclusiveSum(t3, tmp3, nw, wb, (int)(n_items + 1), st));
+        Work* work = ws.get<Work>("work", cap);
+        int32_t* iwb = ws.get<int32_t>("item_wbase", n_items);
+        int32_t* iwc = ws.get<int32_t>("item_wcount", n_items);
+        int32_t* n_work = ws.get<int32_t>("n_work", 1);
+        hipLaunchKernelGGL(k_make_work, dim3(blocks_for(n_items, 256)), dim3(256), 0, st, order, off, n_split, wb,
+                           (int32_t)n_items, kWorkChunk, work, iwb, iwc, n_work);
+        GBS_HIP(hipGetLastError());
+        L.work = work;
+        L.n_work = n_work;
+        L.item_wbase = iwb;
+        L.item_wcount = iwc;
+        L.work_cap = cap;
         L.item_off = off;
         L.item_order = order;
         L.lists = lists;
@@ -628,11 +663,14 @@ template <int MODE, int NR, bool COUNT>
 void launch_pairs(gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const RcvPlan& R, int64_t n_rcv, double* P,
                   unsigned* ctr, unsigned long long* n_active) {
     auto kern = k_pairs<MODE, NR, COUNT>;
-    const int64_t grid = persistent_grid(ctx, (const void*)kern, L.n_items);
+    const int64_t grid = persistent_grid(ctx, (const void*)kern, L.work_cap);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, ctr);
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPairThreads), 0, st, L.jobs, L.item_off, L.n_split,
-                       L.item_order, L.n_items, R.n_patch, ctr, L.lists, L.rec, R.rx, R.ry, R.rz, R.r2, R.perm, n_rcv,
-                       P, n_active);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPairThreads), 0, st, L.jobs, L.work, L.n_work, R.n_patch, ctr,
+                       L.lists, L.rec, R.rx, R.ry, R.rz, R.r2, L.partial, n_active);
+    GBS_HIP(hipGetLastError());
+    const int64_t threads = (int64_t)L.n_items * 64 * NR;
+    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(threads, 256)), dim3(256), 0, st, L.jobs, L.item_wbase,
+                       L.item_wcount, L.n_items, R.n_patch, NR, R.perm, n_rcv, L.partial, P);
     GBS_HIP(hipGetLastError());
 }
 
@@ -646,6 +684,7 @@ void dispatch_nr(int nr, gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, 
 
 void dispatch_pairs(int mode, bool count, int nr, gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L,
                     const RcvPlan& R, int64_t n_rcv, double* P, unsigned* ctr, unsigned long long* na) {
+    GBS_CHECK(L.partial != nullptr, "work-unit partials not allocated");
     if (mode == GBS_MODE_F64) {
         count ? dispatch_nr<0, true>(nr, ctx, st, L, R, n_rcv, P, ctr, na)
               : dispatch_nr<0, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na);
@@ -691,6 +730,7 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
             stats.listed_pairs += L.total * (int64_t)pl.R.per;
             stats.n_items += L.n_items;
             if (L.n_items > 0 && L.total > 0) {
+                L.partial = ws.get<double>("partial", L.work_cap * nr * 64 * 2);
                 ev_pairs.begin(st);
                 dispatch_pairs(a.params->mode, count, nr, ctx, st, L, pl.R, a.n_rcv, P, ctr, na);
                 stats.ms_pairs += ev_pairs.end(st);
@@ -889,6 +929,7 @@ int gbs_graph_create(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, c
             pl.plan_receivers(64 * nr);
             v = pl.view(pl.passes[0]);
             L = pl.build_lists(pl.passes[0], v, 0);
+            if (L.n_items > 0 && L.total > 0) L.partial = ws.get<double>("partial", L.work_cap * nr * 64 * 2);
         }
         unsigned* ctr = ws.get<unsigned>("ctr", 1);
         int32_t* seg_ray = const_cast<int32_t*>(L.seg_ray);

@@ -48,6 +48,14 @@ struct Patch {
     double cx, cy, cz, rad;   // bounding sphere of a receiver patch
 };
 
+// One unit of pair-kernel work: a chunk [beg, end) of one item's list.
+struct Work {
+    int64_t beg, end;         // range in the concatenated lists
+    int32_t item;             // job * n_patch + patch
+    int32_t pad;
+};
+constexpr int kWorkChunk = 2048;      // segments per work unit (bounds the longest unit)
+
 // A contiguous piece of one source's segments, culled by one workgroup.
 struct CullSplit {
     int64_t begin, end;       // segment range (pass-local indices)

@@ -361,99 +361,142 @@ __global__ void k_item_lengths(const int64_t* __restrict__ off, int32_t n_items,
 }
 
 // ------------------------------------------------------------- pair kernels
-// Forward term of one (segment, receiver) pair, added into (accr, acci)
-// without the job's common weight k eps / (8 pi^2):
+// Beam term of one (segment, receiver) pair without the job's common weight
+// k eps / (8 pi^2):
 //   B = w Gamma (s + i eps)/(s^2 + eps^2) exp(-(k eps/2) n^2/den) exp(2 pi i cyc),
 //   cyc = (f/c) (s + n^2 s / (2 den)),   den = s^2 + eps^2.
-// The pre-gate (arc length, |R - o|^2, gate, interval) is FP64 in F64 and MIX.
+// gate() evaluates the arc length, the gate and the beam interval (FP64 in
+// F64 and MIX); term() the beam term for a pair that passed the gate.  term()
+// has no memory access and stays finite for any gate-rejected input, so the
+// kernel may run it on all lanes and discard the rejected results.
 template <int MODE>
-struct PairEval;
+struct Beam;
 
 constexpr int kF64 = 0, kMIX = 1, kF32 = 2;
 
 template <>
-struct PairEval<kF64> {
-    __device__ __forceinline__ static bool eval(const SegRec& S, const JobConst& J, double X, double Y, double Z,
-                                                double R2, double& accr, double& acci) {
-        double s = fma(X, S.tx, fma(Y, S.ty, fma(Z, S.tz, S.mot)));
-        double l = fma(X, S.m2ox, fma(Y, S.m2oy, fma(Z, S.m2oz, R2)));        // |R-o|^2 - |o|^2
-        double rhs = fma(s * J.gate_c1, s, J.gate_c2 - S.oo);
-        const bool keep = l <= rhs && s >= S.slo && s < S.shi;
-        if (__ballot(keep) == 0ull) return false;    // wave-uniform skip
-        branch_barrier();
-        if (!keep) return false;
-        double n2 = fma(-s, s, l + S.oo);
-        double den = fma(s, s, J.eps2);
-        double rden = 1.0 / den;
-        double cyc = fma(n2 * s, rden * J.hfk, s * J.fk);
-        double ph = cyc - floor(cyc);
+struct Beam<kF64> {
+    using T = double;
+    struct Geo { double s, l; };   // arc length, |R - o|^2 - |o|^2
+    __device__ __forceinline__ static bool gate(const SegRec& S, const JobConst& J, double X, double Y, double Z,
+                                                double R2, Geo& g) {
+        g.s = fma(X, S.tx, fma(Y, S.ty, fma(Z, S.tz, S.mot)));
+        g.l = fma(X, S.m2ox, fma(Y, S.m2oy, fma(Z, S.m2oz, R2)));
+        const double rhs = fma(g.s * J.gate_c1, g.s, J.gate_c2 - S.oo);
+        return g.l <= rhs && g.s >= S.slo && g.s < S.shi;
+    }
+    __device__ __forceinline__ static void term(const SegRec& S, const JobConst& J, const Geo& g, double& ur,
+                                                double& ui) {
+        const double s = g.s;
+        const double n2 = fma(-s, s, g.l + S.oo);
+        const double den = fma(s, s, J.eps2);
+        const double rden = 1.0 / den;
+        const double cyc = fma(n2 * s, rden * J.hfk, s * J.fk);
+        const double ph = cyc - floor(cyc);
         double sn, cs;
         sincospi(2.0 * ph, &sn, &cs);
-        double w = rden * exp(n2 * rden * J.gexp);
-        double cr = fma(s, S.wgr, -J.eps * S.wgi) * w;
-        double ci = fma(s, S.wgi, J.eps * S.wgr) * w;
-        accr += cr * cs - ci * sn;
-        acci += cr * sn + ci * cs;
-        return true;
+        const double w = rden * exp(n2 * rden * J.gexp);
+        const double cr = fma(s, S.wgr, -J.eps * S.wgi) * w;
+        const double ci = fma(s, S.wgi, J.eps * S.wgr) * w;
+        ur = cr * cs - ci * sn;
+        ui = cr * sn + ci * cs;
     }
 };
 
 template <>
-struct PairEval<kMIX> {
-    __device__ __forceinline__ static bool eval(const SegRec& S, const JobConst& J, double X, double Y, double Z,
-                                                double R2, double& accr, double& acci) {
-        double s = fma(X, S.tx, fma(Y, S.ty, fma(Z, S.tz, S.mot)));
-        double l = fma(X, S.m2ox, fma(Y, S.m2oy, fma(Z, S.m2oz, R2)));
-        double rhs = fma(s * J.gate_c1, s, J.gate_c2 - S.oo);
-        const bool keep = l <= rhs && s >= S.slo && s < S.shi;
-        if (__ballot(keep) == 0ull) return false;    // wave-uniform skip
-        branch_barrier();
-        if (!keep) return false;
-        double n2 = fma(-s, s, l + S.oo);
-        double den = fma(s, s, J.eps2);
-        float r0f = __builtin_amdgcn_rcpf((float)den);
-        double r0 = (double)r0f;
-        double rden = fma(r0, fma(-den, r0, 1.0), r0);                       // one Newton step
-        double cyc = fma(n2 * s, rden * J.hfk, s * J.fk);                    // phase in cycles, FP64
-        float ph = (float)__builtin_amdgcn_fract(cyc);                       // reduced modulo one in FP64
-        float sn = __builtin_amdgcn_sinf(ph);                                // sin(2 pi ph)
-        float cs = __builtin_amdgcn_cosf(ph);
-        float w = r0f * __builtin_amdgcn_exp2f((float)n2 * r0f * (float)J.gexp2);
-        float sf = (float)s;
-        float cr = fmaf(sf, (float)S.wgr, -(float)J.eps * (float)S.wgi) * w;
-        float ci = fmaf(sf, (float)S.wgi, (float)J.eps * (float)S.wgr) * w;
-        accr += (double)(cr * cs - ci * sn);
-        acci += (double)(cr * sn + ci * cs);
-        return true;
+struct Beam<kMIX> {
+    using T = float;
+    using Geo = Beam<kF64>::Geo;
+    __device__ __forceinline__ static bool gate(const SegRec& S, const JobConst& J, double X, double Y, double Z,
+                                                double R2, Geo& g) {
+        return Beam<kF64>::gate(S, J, X, Y, Z, R2, g);
+    }
+    __device__ __forceinline__ static void term(const SegRec& S, const JobConst& J, const Geo& g, float& ur,
+                                                float& ui) {
+        const double s = g.s;
+        const double n2 = fma(-s, s, g.l + S.oo);
+        const double den = fma(s, s, J.eps2);
+        const float r0f = __builtin_amdgcn_rcpf((float)den);
+        const double r0 = (double)r0f;
+        const double rden = fma(r0, fma(-den, r0, 1.0), r0);                 // one Newton step
+        const double cyc = fma(n2 * s, rden * J.hfk, s * J.fk);              // phase in cycles, FP64
+        const float ph = (float)__builtin_amdgcn_fract(cyc);                 // reduced modulo one in FP64
+        const float sn = __builtin_amdgcn_sinf(ph);                          // sin(2 pi ph)
+        const float cs = __builtin_amdgcn_cosf(ph);
+        const float w = r0f * __builtin_amdgcn_exp2f((float)n2 * r0f * (float)J.gexp2);
+        const float sf = (float)s;
+        const float cr = fmaf(sf, (float)S.wgr, -(float)J.eps * (float)S.wgi) * w;
+        const float ci = fmaf(sf, (float)S.wgi, (float)J.eps * (float)S.wgr) * w;
+        ur = cr * cs - ci * sn;
+        ui = cr * sn + ci * cs;
     }
 };
 
 template <>
-struct PairEval<kF32> {
-    __device__ __forceinline__ static bool eval(const SegRec& S, const JobConst& J, double Xd, double Yd, double Zd,
-                                                double, double& accr, double& acci) {
-        float X = (float)Xd, Y = (float)Yd, Z = (float)Zd;
-        float vx = X + 0.5f * (float)S.m2ox, vy = Y + 0.5f * (float)S.m2oy, vz = Z + 0.5f * (float)S.m2oz;
-        float s = vx * (float)S.tx + vy * (float)S.ty + vz * (float)S.tz;
-        float vv = vx * vx + vy * vy + vz * vz;
-        float n2 = fmaxf(vv - s * s, 0.0f);
-        float den = fmaf(s, s, (float)J.eps2);
-        const bool keep = n2 <= (float)J.kappa * den && s >= (float)S.slo && s < (float)S.shi;
-        if (__ballot(keep) == 0ull) return false;    // wave-uniform skip
-        branch_barrier();
-        if (!keep) return false;
-        float rden = __builtin_amdgcn_rcpf(den);
-        float cyc = (float)J.fk * fmaf(0.5f * n2 * s, rden, s);
-        float ph = __builtin_amdgcn_fractf(cyc);
-        float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
-        float w = rden * __builtin_amdgcn_exp2f(n2 * rden * (float)J.gexp2);
-        float cr = fmaf(s, (float)S.wgr, -(float)J.eps * (float)S.wgi) * w;
-        float ci = fmaf(s, (float)S.wgi, (float)J.eps * (float)S.wgr) * w;
-        accr += (double)(cr * cs - ci * sn);
-        acci += (double)(cr * sn + ci * cs);
-        return true;
+struct Beam<kF32> {
+    using T = float;
+    struct Geo { float s, n2, den; };
+    __device__ __forceinline__ static bool gate(const SegRec& S, const JobConst& J, double Xd, double Yd, double Zd,
+                                                double, Geo& g) {
+        const float X = (float)Xd, Y = (float)Yd, Z = (float)Zd;
+        const float vx = X + 0.5f * (float)S.m2ox, vy = Y + 0.5f * (float)S.m2oy, vz = Z + 0.5f * (float)S.m2oz;
+        g.s = vx * (float)S.tx + vy * (float)S.ty + vz * (float)S.tz;
+        g.n2 = fmaxf(vx * vx + vy * vy + vz * vz - g.s * g.s, 0.0f);
+        g.den = fmaf(g.s, g.s, (float)J.eps2);
+        return g.n2 <= (float)J.kappa * g.den && g.s >= (float)S.slo && g.s < (float)S.shi;
+    }
+    __device__ __forceinline__ static void term(const SegRec& S, const JobConst& J, const Geo& g, float& ur,
+                                                float& ui) {
+        const float rden = __builtin_amdgcn_rcpf(g.den);
+        const float cyc = (float)J.fk * fmaf(0.5f * g.n2 * g.s, rden, g.s);
+        const float ph = __builtin_amdgcn_fractf(cyc);
+        const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
+        const float w = rden * __builtin_amdgcn_exp2f(g.n2 * rden * (float)J.gexp2);
+        const float cr = fmaf(g.s, (float)S.wgr, -(float)J.eps * (float)S.wgi) * w;
+        const float ci = fmaf(g.s, (float)S.wgi, (float)J.eps * (float)S.wgr) * w;
+        ur = cr * cs - ci * sn;
+        ui = cr * sn + ci * cs;
     }
 };
+
+// One segment for one receiver: wave-uniform skip when no lane passes.
+template <int MODE>
+__device__ __forceinline__ int pair_one(const SegRec& S, const JobConst& J, double X, double Y, double Z, double R2,
+                                        double& ar, double& ai) {
+    using B = Beam<MODE>;
+    typename B::Geo g;
+    const bool k0 = B::gate(S, J, X, Y, Z, R2, g);
+    if (__ballot(k0) == 0ull) return 0;
+    branch_barrier();
+    typename B::T ur, ui;
+    B::term(S, J, g, ur, ui);
+    ar += k0 ? (double)ur : 0.0;
+    ai += k0 ? (double)ui : 0.0;
+    return k0;
+}
+
+// Two consecutive segments for one receiver: their beam terms are independent
+// dependency chains that the compiler interleaves; one wave-uniform branch
+// skips both when no lane passes either gate.
+template <int MODE>
+__device__ __forceinline__ int pair_two(const SegRec& S0, const SegRec& S1, const JobConst& J, double X, double Y,
+                                        double Z, double R2, double& ar, double& ai) {
+    using B = Beam<MODE>;
+    using T = typename B::T;
+    typename B::Geo g0, g1;
+    const bool k0 = B::gate(S0, J, X, Y, Z, R2, g0);
+    const bool k1 = B::gate(S1, J, X, Y, Z, R2, g1);
+    if (__ballot(k0 || k1) == 0ull) return 0;
+    branch_barrier();
+    T u0r, u0i, u1r, u1i;
+    B::term(S0, J, g0, u0r, u0i);
+    B::term(S1, J, g1, u1r, u1i);
+    const T zr = (k0 ? u0r : (T)0) + (k1 ? u1r : (T)0);
+    const T zi = (k0 ? u0i : (T)0) + (k1 ? u1i : (T)0);
+    ar += (double)zr;
+    ai += (double)zi;
+    return (int)k0 + (int)k1;
+}
 
 // A segment record in registers, as six named 16-byte vectors (kept out of
 // arrays so the compiler keeps them in VGPRs): vector loads, 128-bit LDS stores.
@@ -484,34 +527,37 @@ __device__ __forceinline__ int pop_item(unsigned* ctr) {
 }
 constexpr int kLastLane = kWave - 1;
 
-// Persistent forward kernel: one wavefront per (job, patch) item; the patch
-// holds 64 * NR receivers, lane l owns receivers l, l + 64, ...
+// Persistent forward kernel: one wavefront per work unit, a chunk of at most
+// a fixed number of segments of one (job, patch) list (long lists - patches
+// next to a source see nearly every beam - are spread over many waves); the
+// patch holds 64 * NR receivers, lane l owns receivers l, l + 64, ...
 // The item's segment list is walked in tiles of 64: lane l gathers record l
 // of the next tile with vector loads (one memory round trip per tile, issued
 // a whole tile ahead), the tile goes to the wave's LDS slice, and every
 // segment is then read back as a wave-uniform LDS broadcast.
 // P (job-major, original receiver order) accumulates scale * sum.
+#ifndef GBS_PAIR_MIN_WAVES
+#define GBS_PAIR_MIN_WAVES 1
+#endif
 template <int MODE, int NR, bool COUNT>
-__global__ __launch_bounds__(kPairThreads) void k_pairs(const JobConst* __restrict__ jobs,
-                                              const int64_t* __restrict__ item_off, int32_t off_stride,
-                                              const int32_t* __restrict__ item_order, int32_t n_items,
+__global__ __launch_bounds__(kPairThreads, GBS_PAIR_MIN_WAVES) void k_pairs(const JobConst* __restrict__ jobs,
+                                              const Work* __restrict__ work, const int32_t* __restrict__ n_work_p,
                                               int32_t n_patch, unsigned* __restrict__ ctr,
                                               const int32_t* __restrict__ lists, const SegRec* __restrict__ rec,
                                               const double* __restrict__ rx, const double* __restrict__ ry,
                                               const double* __restrict__ rz, const double* __restrict__ r2,
-                                              const int32_t* __restrict__ perm, int64_t n_rcv,
-                                              double* __restrict__ P, unsigned long long* __restrict__ n_active) {
+                                              double* __restrict__ partial, unsigned long long* __restrict__ n_active) {
     __shared__ __align__(16) SegRec tile[kPairThreads / kWave][kWave];
     const int lane = threadIdx.x & (kWave - 1);
     SegRec* const my = tile[threadIdx.x / kWave];
+    const int n_work = __builtin_amdgcn_readfirstlane(*n_work_p);
     unsigned long long active = 0;
     for (;;) {
         branch_barrier();
-        const int it = pop_item(ctr);
-        if (it >= n_items) break;
-        const int item = __builtin_amdgcn_readfirstlane(item_order[it]);
-        const int64_t beg = item_off[(int64_t)item * off_stride], end = item_off[(int64_t)(item + 1) * off_stride];
-        if (beg == end) continue;
+        const int w = pop_item(ctr);
+        if (w >= n_work) break;
+        const int item = __builtin_amdgcn_readfirstlane(work[w].item);
+        const int64_t beg = work[w].beg, end = work[w].end;
         const int job = item / n_patch, patch = item - job * n_patch;
         const JobConst J = jobs[job];
         double X[NR], Y[NR], Z[NR], R2[NR], ar[NR], ai[NR];
@@ -525,39 +571,110 @@ __global__ __launch_bounds__(kPairThreads) void k_pairs(const JobConst* __restri
             ar[m] = 0.0;
             ai[m] = 0.0;
         }
+        // indices run two tiles ahead of the records they address, records one
+        // tile ahead of the tile being evaluated (clamped: the tail re-reads a
+        // valid entry, never out of range)
         GBS_REC_REGS(nx);
         GBS_REC_LOAD(nx, rec, lists[min(beg + lane, end - 1)]);
+        int32_t idx_ahead = lists[min(beg + kWave + lane, end - 1)];
         for (int64_t e0 = beg; e0 < end; e0 += kWave) {
             const int cnt = (int)min<int64_t>(kWave, end - e0);
             wave_lds_fence();
             GBS_REC_STORE(my + lane, nx);
             wave_lds_fence();
-            // next tile (the last one re-reads a valid record: clamped, never out of range)
-            GBS_REC_LOAD(nx, rec, lists[min(e0 + kWave + lane, end - 1)]);
-            for (int k = 0; k < cnt; ++k) {
+            GBS_REC_LOAD(nx, rec, idx_ahead);
+            idx_ahead = lists[min(e0 + 2 * kWave + lane, end - 1)];
+            int k = 0;
+#ifndef GBS_PAIR_SINGLE
+            for (; k + 2 <= cnt; k += 2) {
+                const SegRec S0 = my[k], S1 = my[k + 1];
+#pragma unroll
+                for (int m = 0; m < NR; ++m) {
+                    const int hit = pair_two<MODE>(S0, S1, J, X[m], Y[m], Z[m], R2[m], ar[m], ai[m]);
+                    if (COUNT) active += (unsigned long long)hit;
+                }
+            }
+#endif
+            for (; k < cnt; ++k) {
                 const SegRec S = my[k];
 #pragma unroll
                 for (int m = 0; m < NR; ++m) {
-                    bool hit = PairEval<MODE>::eval(S, J, X[m], Y[m], Z[m], R2[m], ar[m], ai[m]);
-                    if (COUNT) active += hit ? 1ull : 0ull;
+                    const int hit = pair_one<MODE>(S, J, X[m], Y[m], Z[m], R2[m], ar[m], ai[m]);
+                    if (COUNT) active += (unsigned long long)hit;
                 }
             }
         }
 #pragma unroll
         for (int m = 0; m < NR; ++m) {
-            const int64_t i = (int64_t)patch * (64 * NR) + 64 * m + lane;
-            const int32_t o = perm[i];
-            if (o >= 0) {
-                double* p = P + 2 * ((int64_t)job * n_rcv + o);
-                p[0] += J.scale * ar[m];
-                p[1] += J.scale * ai[m];
-            }
+            double* p = partial + 2 * (((int64_t)w * NR + m) * kWave + lane);
+            p[0] = ar[m];
+            p[1] = ai[m];
         }
     }
     if (COUNT) {
         double tot = wave_sum((double)active);
         if (lane == kLastLane) atomicAdd(n_active, (unsigned long long)tot);
     }
+}
+
+// Work units per item, in the longest-first item order: ceil(len / chunk).
+__global__ void k_work_counts(const int32_t* __restrict__ order, const int32_t* __restrict__ len, int32_t n_items,
+                              int32_t chunk, int32_t* __restrict__ nwork) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > n_items) return;
+    nwork[k] = k < n_items ? (len[order[k]] + chunk - 1) / chunk : 0;
+}
+
+// Lays out the work units of every item from the exclusive scan of the counts.
+__global__ void k_make_work(const int32_t* __restrict__ order, const int64_t* __restrict__ off, int32_t off_stride,
+                            const int32_t* __restrict__ wbase, int32_t n_items, int32_t chunk,
+                            Work* __restrict__ work, int32_t* __restrict__ item_wbase,
+                            int32_t* __restrict__ item_wcount, int32_t* __restrict__ n_work) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_items) return;
+    const int item = order[k];
+    const int64_t beg = off[(int64_t)item * off_stride], end = off[(int64_t)(item + 1) * off_stride];
+    const int32_t b = wbase[k], cnt = wbase[k + 1] - b;
+    for (int c = 0; c < cnt; ++c) {
+        Work u;
+        u.beg = beg + (int64_t)c * chunk;
+        u.end = min(u.beg + chunk, end);
+        u.item = item;
+        u.pad = 0;
+        work[b + c] = u;
+    }
+    item_wbase[item] = b;
+    item_wcount[item] = cnt;
+    if (k == n_items - 1) *n_work = b + cnt;
+}
+
+// P[job][receiver] += scale * (sum of the item's work-unit partials, in
+// unit order).  One thread per (item, receiver slot).
+__global__ void k_reduce_partials(const JobConst* __restrict__ jobs, const int32_t* __restrict__ item_wbase,
+                                  const int32_t* __restrict__ item_wcount, int32_t n_items, int32_t n_patch, int nr,
+                                  const int32_t* __restrict__ perm, int64_t n_rcv, const double* __restrict__ partial,
+                                  double* __restrict__ P) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int per = kWave * nr;
+    if (t >= (int64_t)n_items * per) return;
+    const int item = (int)(t / per), slot = (int)(t - (int64_t)item * per);
+    const int cnt = item_wcount[item];
+    if (cnt == 0) return;
+    const int job = item / n_patch, patch = item - job * n_patch;
+    const int m = slot / kWave, lane = slot - m * kWave;
+    const int32_t o = perm[(int64_t)patch * per + slot];
+    if (o < 0) return;
+    const int64_t base = item_wbase[item];
+    double sr = 0.0, si = 0.0;
+    for (int c = 0; c < cnt; ++c) {
+        const double* p = partial + 2 * (((base + c) * nr + m) * kWave + lane);
+        sr += p[0];
+        si += p[1];
+    }
+    double* q = P + 2 * ((int64_t)job * n_rcv + o);
+    const double sc = jobs[job].scale;
+    q[0] += sc * sr;
+    q[1] += sc * si;
 }
 
 // TL = -20 log10 |P|  (+inf where P = 0).
@@ -797,10 +914,9 @@ template __global__ void k_cull<false>(const JobConst*, const SegRec*, const Pat
 template __global__ void k_cull<true>(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int,
                                       const CullSplit*, int32_t*, const int64_t*, int32_t*);
 #define GBS_INST_PAIRS(M, N, C)                                                                                  \
-    template __global__ void k_pairs<M, N, C>(const JobConst*, const int64_t*, int32_t, const int32_t*, int32_t,   \
-                                              int32_t, unsigned*, const int32_t*, const SegRec*, const double*,  \
-                                              const double*, const double*, const double*, const int32_t*,       \
-                                              int64_t, double*, unsigned long long*);
+    template __global__ void k_pairs<M, N, C>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,    \
+                                              const int32_t*, const SegRec*, const double*, const double*,       \
+                                              const double*, const double*, double*, unsigned long long*);
 #define GBS_INST_PAIRS_MODE(M) \
     GBS_INST_PAIRS(M, 1, false) GBS_INST_PAIRS(M, 2, false) GBS_INST_PAIRS(M, 4, false) \
     GBS_INST_PAIRS(M, 1, true) GBS_INST_PAIRS(M, 2, true) GBS_INST_PAIRS(M, 4, true)
