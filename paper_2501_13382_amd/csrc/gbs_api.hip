@@ -47,9 +47,11 @@ __global__ void k_reduce_partials(const JobConst*, const int32_t*, const int32_t
                                   const int32_t*, int64_t, const double*, double*);
 __global__ void k_tl(const double*, int64_t, double*);
 template <int MODE>
-__global__ void k_adjoint(const JobConst*, const int64_t*, int32_t, const int32_t*, int32_t, int32_t, unsigned*,
-                          const int32_t*, const SegRec*, const double*, const double*, const double*,
-                          const double*, const int32_t*, int64_t, const double*, double*, double*, double*);
+__global__ void k_adjoint(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*, const int32_t*,
+                          const SegRec*, const double*, const double*, const double*, const double*, const int32_t*,
+                          int64_t, const double*, double*, double*, double*);
+__global__ void k_reduce_adjoint(const JobConst*, const int32_t*, const int32_t*, int32_t, int32_t, const int32_t*,
+                                 int64_t, const double*, double*);
 __global__ void k_sum_jobs(const double*, int32_t, int64_t, double*);
 __global__ void k_face_scatter(int64_t, const int64_t*, int64_t, const int32_t*, int32_t, const double*,
                                const double*, const int32_t*, const double*, double*);
@@ -355,7 +357,7 @@ struct Planner {
         double* part = ws.get<double>("bbox_part", 6 * nb);
         double* bbox = ws.get<double>("bbox", 6);
         hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(256), 0, st, a.rcv, R.n, part);
-        hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, part, nb, bbox);
+        hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, st, part, nb, bbox);
         uint32_t* keys = ws.get<uint32_t>("mkeys", R.n);
         uint32_t* keys2 = ws.get<uint32_t>("mkeys2", R.n);
         int32_t* vals = ws.get<int32_t>("mvals", R.n);
@@ -867,11 +869,16 @@ int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
                 fill(st, Sseg, 2 * nseg, 0.0);
                 if (L.n_items > 0 && L.total > 0) {
                     auto kern = params->mode == GBS_MODE_F64 ? k_adjoint<0> : k_adjoint<1>;
-                    const int64_t grid = persistent_grid(ctx, (const void*)kern, L.n_items);
+                    double* part = ws.get<double>("adj_partial", L.work_cap * 64 * 3);
+                    const int64_t grid = persistent_grid(ctx, (const void*)kern, L.work_cap);
                     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, ctr);
-                    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPairThreads), 0, st, L.jobs, L.item_off,
-                                       L.n_split, L.item_order, L.n_items, pl.R.n_patch, ctr, L.lists, L.rec, pl.R.rx,
-                                       pl.R.ry, pl.R.rz, pl.R.r2, pl.R.perm, n_rcv, lambda, dRj, Sseg, dE);
+                    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPairThreads), 0, st, L.jobs, L.work,
+                                       L.n_work, pl.R.n_patch, ctr, L.lists, L.rec, pl.R.rx, pl.R.ry, pl.R.rz,
+                                       pl.R.r2, pl.R.perm, n_rcv, lambda, part, Sseg, dE);
+                    GBS_HIP(hipGetLastError());
+                    hipLaunchKernelGGL(k_reduce_adjoint, dim3(blocks_for((int64_t)L.n_items * 64, 256)), dim3(256), 0,
+                                       st, L.jobs, L.item_wbase, L.item_wcount, L.n_items, pl.R.n_patch, pl.R.perm,
+                                       n_rcv, part, dRj);
                     GBS_HIP(hipGetLastError());
                 }
                 if (nf > 0 && nseg > 0) {

@@ -85,15 +85,27 @@ __global__ void k_bbox_partial(const double* __restrict__ rcv, int64_t n, double
         for (int d = 0; d < 6; ++d) part[6 * blockIdx.x + d] = sm[d][0];
 }
 
-__global__ void k_bbox_final(const double* __restrict__ part, int nb, double* __restrict__ bbox) {
-    if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(256) void k_bbox_final(const double* __restrict__ part, int nb,
+                                                    double* __restrict__ bbox) {
+    __shared__ double sm[6][256];
     double b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-    for (int i = 0; i < nb; ++i)
+    for (int i = threadIdx.x; i < nb; i += blockDim.x)
         for (int d = 0; d < 3; ++d) {
             b[d] = fmin(b[d], part[6 * i + d]);
             b[3 + d] = fmax(b[3 + d], part[6 * i + 3 + d]);
         }
-    for (int d = 0; d < 6; ++d) bbox[d] = b[d];
+    for (int d = 0; d < 6; ++d) sm[d][threadIdx.x] = b[d];
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int d = 0; d < 3; ++d) {
+                sm[d][threadIdx.x] = fmin(sm[d][threadIdx.x], sm[d][threadIdx.x + s]);
+                sm[3 + d][threadIdx.x] = fmax(sm[3 + d][threadIdx.x], sm[3 + d][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int d = 0; d < 6; ++d) bbox[d] = sm[d][0];
 }
 
 __device__ __forceinline__ uint32_t spread3(uint32_t v) {  // 10 bits -> every third bit
@@ -777,29 +789,34 @@ __device__ __forceinline__ bool adj_eval(const SegRec& S, const JobConst& J, dou
     return true;
 }
 
-// Persistent adjoint kernel (same items as the forward).  Per receiver:
-// dR accumulates in the lane and is written per (job, receiver);
-// per segment: sum over lanes of lambda * B (wave reduction) -> FP64 atomics
-// into Sseg; per job: d eps via a wave reduction and one atomic per item.
+// Persistent adjoint kernel over the same work units as the forward, with
+// the same LDS-staged segment tiles.  Per receiver (lane): dL/dR accumulates
+// in FP64 and is written as the unit's partial (k_reduce_adjoint adds a
+// patch's units in order); per segment: the sum over lanes of lambda * B
+// (wave reduction) goes to Sseg with FP64 atomics; per job: dL/deps from a
+// wave reduction and one atomic per unit.
 template <int MODE>
 __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __restrict__ jobs,
-                                                const int64_t* __restrict__ item_off, int32_t off_stride,
-                                                const int32_t* __restrict__ item_order, int32_t n_items,
+                                                const Work* __restrict__ work, const int32_t* __restrict__ n_work_p,
                                                 int32_t n_patch, unsigned* __restrict__ ctr,
                                                 const int32_t* __restrict__ lists, const SegRec* __restrict__ rec,
                                                 const double* __restrict__ rx, const double* __restrict__ ry,
                                                 const double* __restrict__ rz, const double* __restrict__ r2,
                                                 const int32_t* __restrict__ perm, int64_t n_rcv,
-                                                const double* __restrict__ lambda, double* __restrict__ dR_job,
+                                                const double* __restrict__ lambda, double* __restrict__ partial,
                                                 double* __restrict__ Sseg, double* __restrict__ d_eps) {
+    __shared__ __align__(16) SegRec tile[kPairThreads / kWave][kWave];
+    __shared__ int32_t tile_idx[kPairThreads / kWave][kWave];
     const int lane = threadIdx.x & (kWave - 1);
+    SegRec* const my = tile[threadIdx.x / kWave];
+    int32_t* const my_idx = tile_idx[threadIdx.x / kWave];
+    const int n_work = __builtin_amdgcn_readfirstlane(*n_work_p);
     for (;;) {
         branch_barrier();
-        const int it = pop_item(ctr);
-        if (it >= n_items) break;
-        const int item = __builtin_amdgcn_readfirstlane(item_order[it]);
-        const int64_t beg = item_off[(int64_t)item * off_stride], end = item_off[(int64_t)(item + 1) * off_stride];
-        if (beg == end) continue;
+        const int w = pop_item(ctr);
+        if (w >= n_work) break;
+        const int item = __builtin_amdgcn_readfirstlane(work[w].item);
+        const int64_t beg = work[w].beg, end = work[w].end;
         const int job = item / n_patch, patch = item - job * n_patch;
         const JobConst J = jobs[job];
         const int64_t i = (int64_t)patch * 64 + lane;
@@ -811,29 +828,68 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
             li = lambda[2 * ((int64_t)job * n_rcv + o) + 1];
         }
         double dRx = 0, dRy = 0, dRz = 0, dE = 0;
-        for (int64_t e = beg; e < end; ++e) {
-            const int32_t j = lists[e];
-            const SegRec S = rec[j];
-            double Sr = 0.0, Si = 0.0;
-            bool hit = adj_eval<MODE>(S, J, X, Y, Z, R2, lr, li, dRx, dRy, dRz, dE, Sr, Si);
-            if (__ballot(hit) != 0ull) {
-                Sr = wave_sum(Sr);
-                Si = wave_sum(Si);
-                if (lane == kLastLane) {
-                    atomicAdd(&Sseg[2 * (int64_t)j], J.scale * Sr);
-                    atomicAdd(&Sseg[2 * (int64_t)j + 1], J.scale * Si);
+        GBS_REC_REGS(nx);
+        int32_t idx_cur = lists[min(beg + lane, end - 1)];
+        GBS_REC_LOAD(nx, rec, idx_cur);
+        for (int64_t e0 = beg; e0 < end; e0 += kWave) {
+            const int cnt = (int)min<int64_t>(kWave, end - e0);
+            wave_lds_fence();
+            GBS_REC_STORE(my + lane, nx);
+            my_idx[lane] = idx_cur;
+            wave_lds_fence();
+            idx_cur = lists[min(e0 + kWave + lane, end - 1)];
+            GBS_REC_LOAD(nx, rec, idx_cur);
+            for (int k = 0; k < cnt; ++k) {
+                const SegRec S = my[k];
+                double Sr = 0.0, Si = 0.0;
+                const bool hit = adj_eval<MODE>(S, J, X, Y, Z, R2, lr, li, dRx, dRy, dRz, dE, Sr, Si);
+                if (__ballot(hit) != 0ull) {
+                    Sr = wave_sum(Sr);
+                    Si = wave_sum(Si);
+                    if (lane == kLastLane) {
+                        const int64_t j = my_idx[k];
+                        atomicAdd(&Sseg[2 * j], J.scale * Sr);
+                        atomicAdd(&Sseg[2 * j + 1], J.scale * Si);
+                    }
                 }
             }
         }
-        if (o >= 0) {
-            double* d = dR_job + 3 * ((int64_t)job * n_rcv + o);
-            d[0] += J.scale * dRx;
-            d[1] += J.scale * dRy;
-            d[2] += J.scale * dRz;
-        }
+        double* p = partial + 3 * ((int64_t)w * kWave + lane);
+        p[0] = dRx;
+        p[1] = dRy;
+        p[2] = dRz;
         dE = wave_sum(dE);
         if (lane == kLastLane) atomicAdd(&d_eps[job], J.scale * dE);
     }
+}
+
+// dR_job[job][receiver] += scale * (sum of the item's unit partials, in unit
+// order).  One thread per (item, lane) of 64-receiver patches.
+__global__ void k_reduce_adjoint(const JobConst* __restrict__ jobs, const int32_t* __restrict__ item_wbase,
+                                 const int32_t* __restrict__ item_wcount, int32_t n_items, int32_t n_patch,
+                                 const int32_t* __restrict__ perm, int64_t n_rcv, const double* __restrict__ partial,
+                                 double* __restrict__ dR_job) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n_items * kWave) return;
+    const int item = (int)(t / kWave), lane = (int)(t - (int64_t)item * kWave);
+    const int cnt = item_wcount[item];
+    if (cnt == 0) return;
+    const int job = item / n_patch, patch = item - job * n_patch;
+    const int32_t o = perm[(int64_t)patch * kWave + lane];
+    if (o < 0) return;
+    const int64_t base = item_wbase[item];
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int c = 0; c < cnt; ++c) {
+        const double* p = partial + 3 * ((base + c) * kWave + lane);
+        sx += p[0];
+        sy += p[1];
+        sz += p[2];
+    }
+    double* d = dR_job + 3 * ((int64_t)job * n_rcv + o);
+    const double sc = jobs[job].scale;
+    d[0] += sc * sx;
+    d[1] += sc * sy;
+    d[2] += sc * sz;
 }
 
 // dR[r] = sum over jobs of dR_job[job][r]  (fixed order).
@@ -923,11 +979,11 @@ template __global__ void k_cull<true>(const JobConst*, const SegRec*, const Patc
 GBS_INST_PAIRS_MODE(0)
 GBS_INST_PAIRS_MODE(1)
 GBS_INST_PAIRS_MODE(2)
-template __global__ void k_adjoint<0>(const JobConst*, const int64_t*, int32_t, const int32_t*, int32_t, int32_t, unsigned*,
+template __global__ void k_adjoint<0>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,
                                       const int32_t*, const SegRec*, const double*, const double*, const double*,
                                       const double*, const int32_t*, int64_t, const double*, double*, double*,
                                       double*);
-template __global__ void k_adjoint<1>(const JobConst*, const int64_t*, int32_t, const int32_t*, int32_t, int32_t, unsigned*,
+template __global__ void k_adjoint<1>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,
                                       const int32_t*, const SegRec*, const double*, const double*, const double*,
                                       const double*, const int32_t*, int64_t, const double*, double*, double*,
                                       double*);

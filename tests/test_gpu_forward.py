@@ -216,3 +216,24 @@ def test_full_size_open_plane_sampled(plane100k, mode):
     st = compare(P[:, :, idx], TL[:, :, idx], P_ref, TL_ref, ab)
     print(st, gbs.stats())
     assert_within(st, mode)
+
+
+def test_autotune_picks_a_valid_shape_and_results_agree(city_small):
+    """The autotuner times the receivers-per-lane shapes and keeps one; later
+    calls with the automatic shape give the same field."""
+    sc, (P_ref, TL_ref, ab) = city_small
+    t = gbs.Table(sc.table, device="cuda")
+    nr = gbs.autotune(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, c=sc.c, gate=sc.gate, mode="f64")
+    assert nr in (1, 2, 4)
+    P, TL = gbs.forward(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, c=sc.c, gate=sc.gate, mode="f64")
+    assert gbs.stats()["patch_rcv"] == 64 * nr
+    assert_within(compare(P.cpu().numpy(), TL.cpu().numpy(), P_ref, TL_ref, ab), "f64")
+
+
+def test_stats_are_consistent(city_small):
+    sc, _ = city_small
+    gpu_forward(sc, mode="mix", count_active=True, time_kernels=True)
+    st = gbs.stats()
+    assert st["dense_pairs"] == sc.dense_pairs
+    assert 0 < st["active_pairs"] <= st["listed_pairs"]
+    assert st["ms_pairs"] > 0 and st["ms_cull"] > 0 and st["grid"] > 0
