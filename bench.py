@@ -10,7 +10,7 @@ evaluations per second (the dense sum the culled kernel reproduces).
 
 Also reported: the pair kernel's roofline (algorithmic FLOPs per launch over
 its HIP-event-timed duration), the all-FP64 mode on the same GPU, the error
-against the FP64 oracle on 4,096 seeded receivers, and the oracle timed on
+against the FP64 oracle on 16,384 seeded receivers, and the oracle timed on
 this host's cores on that sample.
 """
 from __future__ import annotations
@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-f64", action="store_true", help="skip the all-FP64 comparison")
-    ap.add_argument("--cpu-receivers", type=int, default=4096)
+    ap.add_argument("--cpu-receivers", type=int, default=16384)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the steps, run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()

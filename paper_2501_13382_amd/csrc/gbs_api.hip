@@ -32,10 +32,11 @@ __global__ void k_seg2ray(const int64_t*, int64_t, int64_t, int64_t, int32_t*);
 __global__ void k_records(int64_t, const double*, const double*, const double*, const double*, const double*,
                           const int64_t*, int64_t, const int32_t*, int32_t, const double*, const double*,
                           const int32_t*, SegRec*);
-template <bool FILL>
+template <bool FILL, int NB>
 __global__ void k_cull(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int, const CullSplit*,
                        int32_t*, const int64_t*, int32_t*);
 __global__ void k_item_lengths(const int64_t*, int32_t, int, int32_t*);
+__global__ void k_iota(int32_t*, int32_t);
 template <int MODE, int NR, bool COUNT>
 __global__ void k_pairs(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*, const int32_t*,
                         const SegRec*, const double*, const double*, const double*, const double*, double*,
@@ -545,8 +546,11 @@ struct Planner {
         if (!sv.empty())
             GBS_HIP(hipMemcpyAsync(d_split, sv.data(), sizeof(CullSplit) * sv.size(), hipMemcpyHostToDevice, st));
         dim3 cg(R.n_super, (unsigned)std::max<size_t>(sv.size(), 1));
+        // up to 8 bands: band constants in wave-uniform registers
+        auto cull_count = n_freq <= 8 ? k_cull<false, 8> : k_cull<false, 0>;
+        auto cull_fill = n_freq <= 8 ? k_cull<true, 8> : k_cull<true, 0>;
         if (!sv.empty())
-            hipLaunchKernelGGL(k_cull<false>, cg, dim3(kCullThreads), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
+            hipLaunchKernelGGL(cull_count, cg, dim3(kCullThreads), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
                                n_freq, n_split, d_split, counts, nullptr, nullptr);
         GBS_HIP(hipGetLastError());
         // counts are int32; accumulate in int64 through a converting iterator
@@ -559,7 +563,7 @@ struct Planner {
         GBS_HIP(hipStreamSynchronize(st));
         int32_t* lists = ws.get<int32_t>("lists", std::max<int64_t>(L.total, 1));
         if (!sv.empty())
-            hipLaunchKernelGGL(k_cull<true>, cg, dim3(kCullThreads), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
+            hipLaunchKernelGGL(cull_fill, cg, dim3(kCullThreads), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
                                n_freq, n_split, d_split, nullptr, off, lists);
         GBS_HIP(hipGetLastError());
         // longest lists first
@@ -569,16 +573,13 @@ struct Planner {
         int32_t* keys2 = ws.get<int32_t>("okeys", n_items);
         int32_t* ids = ws.get<int32_t>("oids", n_items);
         int32_t* order = ws.get<int32_t>("order", n_items);
-        std::vector<int32_t> iota(n_items);
-        for (int64_t i = 0; i < n_items; ++i) iota[i] = (int32_t)i;
-        GBS_HIP(hipMemcpyAsync(ids, iota.data(), sizeof(int32_t) * n_items, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_iota, dim3(blocks_for(n_items, 256)), dim3(256), 0, st, ids, (int32_t)n_items);
         size_t tmp2 = 0;
         GBS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tmp2, lens, keys2, ids, order, (int)n_items,
                                                              0, 32, st));
         void* t2 = ws.get<char>("cub_tmp_order", tmp2);
         GBS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(t2, tmp2, lens, keys2, ids, order, (int)n_items, 0, 32,
                                                              st));
-        GBS_HIP(hipStreamSynchronize(st));  // iota staging is pageable host memory
         // work units: every list cut into chunks of at most kWorkChunk segments
         const int64_t cap = n_items + L.total / kWorkChunk + 1;
         GBS_CHECK(cap < INT32_MAX, "too many work units");

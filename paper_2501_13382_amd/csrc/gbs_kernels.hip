@@ -243,14 +243,19 @@ __global__ void k_records(int64_t n_segs, const double* __restrict__ a, const do
 // the band; each band then only compares d^2 <= kappa_b sm^2 + kappa_b eps_b^2
 // with d = max(n_C - rad, 0) and sm the largest |s| the sphere can reach
 // inside the beam interval.  Margins cover rounding (n_C is under-estimated).
+struct CullRec {
+    double ox, oy, oz;   // virtual source
+    double tx, ty, tz;   // unit axis
+    double slo, shi;     // beam interval in arc length
+};
+
 struct Reach {
     double d2, sm2;
     bool ok;
 };
 
-__device__ __forceinline__ Reach reach(const SegRec& S, const Patch& p) {
-    double ox = -0.5 * S.m2ox, oy = -0.5 * S.m2oy, oz = -0.5 * S.m2oz;
-    double vx = p.cx - ox, vy = p.cy - oy, vz = p.cz - oz;
+__device__ __forceinline__ Reach reach(const CullRec& S, const Patch& p) {
+    double vx = p.cx - S.ox, vy = p.cy - S.oy, vz = p.cz - S.oz;
     double sc = vx * S.tx + vy * S.ty + vz * S.tz;
     double vv = vx * vx + vy * vy + vz * vz;
     double nc2 = fmax(vv - sc * sc, 0.0);
@@ -263,18 +268,78 @@ __device__ __forceinline__ Reach reach(const SegRec& S, const Patch& p) {
 }
 
 __device__ __forceinline__ bool reach_band(const Reach& r, double kap, double kap_eps2) {
-    return r.ok && r.d2 <= fma(kap, r.sm2, kap_eps2) * (1.0 + 1e-9);
+    return r.ok & (r.d2 <= fma(kap, r.sm2, kap_eps2) * (1.0 + 1e-9));
 }
 
+// A wave-uniform value of lane b of a per-lane double / int64.
+__device__ __forceinline__ double lane_f64(double v, int b) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), b);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), b);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ int64_t lane_i64(int64_t v, int b) {
+    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), b);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), b);
+    return ((int64_t)hi << 32) | (unsigned)lo;
+}
+
+// Band constants of one source for the cull: kappa_b and kappa_b eps_b^2.
+// Bands<8> keeps up to 8 bands in wave-uniform registers (absent bands get
+// constants that never pass); Bands<0> takes any count up to kMaxBands with
+// band b's constants in lane b of a vector register.
+template <int NB>
+struct Bands {
+    double kap[NB], kape[NB];
+    __device__ __forceinline__ void load(const JobConst* __restrict__ jobs, int64_t job0, int n_freq, int) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            kap[b] = -1.0;
+            kape[b] = -1.0;
+            if (b < n_freq) {
+                kap[b] = jobs[job0 + b].kappa;
+                kape[b] = kap[b] * jobs[job0 + b].eps2;
+            }
+        }
+    }
+    __device__ __forceinline__ constexpr int count() const { return NB; }
+    __device__ __forceinline__ bool pass(const Reach& r, int b) const { return reach_band(r, kap[b], kape[b]); }
+};
+
+template <>
+struct Bands<0> {
+    double kapv, kapev;
+    int n;
+    __device__ __forceinline__ void load(const JobConst* __restrict__ jobs, int64_t job0, int n_freq, int lane) {
+        n = n_freq;
+        kapv = kapev = 0.0;
+        if (lane < n_freq) {
+            kapv = jobs[job0 + lane].kappa;
+            kapev = kapv * jobs[job0 + lane].eps2;
+        }
+    }
+    __device__ __forceinline__ int count() const { return n; }
+    __device__ __forceinline__ bool pass(const Reach& r, int b) const {
+        return reach_band(r, lane_f64(kapv, b), lane_f64(kapev, b));
+    }
+};
+
 // Two-level cull.  One workgroup per (super-patch of kSuperPatches patches,
-// split of one source's segment range).  Each segment record is loaded once
-// and tested for every band of its source: first against the super-patch
-// sphere (survivors and their band mask go to LDS), then each wave tests the
-// survivors against its own patches.  The count pass writes one length per
-// (job, patch, split); the fill pass writes at the exclusive prefix sum of
+// split of one source's segment range).  The split is walked in chunks of
+// kCullThreads segments, each record loaded once (the next chunk's load is
+// issued before the current chunk is tested):
+//   level 1: thread t tests segment t against the super-patch sphere for
+//            every band of its source; survivors, with their records and
+//            band masks, are appended to an LDS queue in segment order;
+//   level 2: whenever the queue holds full batches of 64, wave w tests them
+//            against its patches w, w + 4, ..., band by band; the remainder
+//            waits for the next chunk (the last partial batch runs at the end).
+// List cursors stay in registers: lane b of cur[m] holds band b's cursor of
+// the wave's patch m.  The count pass leaves one length per (job, patch,
+// split); the fill pass starts every cursor at the exclusive prefix sum of
 // those lengths, so each job-patch list is the concatenation of its splits
-// in order: segment order, deterministic.
-template <bool FILL>
+// in segment order: deterministic, and identical between the two passes.
+template <bool FILL, int NB>
 __global__ __launch_bounds__(kCullThreads) void k_cull(const JobConst* __restrict__ jobs,
                                                        const SegRec* __restrict__ rec,
                                                        const Patch* __restrict__ patches,
@@ -285,38 +350,70 @@ __global__ __launch_bounds__(kCullThreads) void k_cull(const JobConst* __restric
                                                        int32_t* __restrict__ lists) {
     constexpr int kWaves = kCullThreads / kWave;
     constexpr int kOwn = kSuperPatches / kWaves;
-    __shared__ int32_t q_seg[kCullThreads];
-    __shared__ unsigned long long q_mask[kCullThreads];
+    constexpr int kQ = kWave + kCullThreads;             // a partial batch plus one chunk
+    __shared__ __align__(16) CullRec q_rec[kQ];
+    __shared__ int32_t q_seg[kQ];
+    __shared__ unsigned long long q_mask[kQ];
     __shared__ int wave_cnt[kWaves];
-    __shared__ double kap[kMaxBands], kape[kMaxBands];
-    __shared__ int32_t run[kSuperPatches][kMaxBands];
     const int sp = blockIdx.x;
     const CullSplit sl = splits[blockIdx.y];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t job0 = (int64_t)sl.src * n_freq;
-    for (int b = tid; b < n_freq; b += kCullThreads) {
-        const JobConst J = jobs[job0 + b];
-        kap[b] = J.kappa;
-        kape[b] = J.kappa * J.eps2;
-    }
-    for (int i = tid; i < kSuperPatches * kMaxBands; i += kCullThreads) run[i / kMaxBands][i % kMaxBands] = 0;
+    Bands<NB> B;
+    B.load(jobs, job0, n_freq, lane);
     const Patch SPt = supers[sp];
     const int p0 = sp * kSuperPatches;
     Patch mine[kOwn];
+    int64_t cur[kOwn];
+#pragma unroll
     for (int m = 0; m < kOwn; ++m) {
-        int p = p0 + wv + kWaves * m;
+        const int p = p0 + wv + kWaves * m;
         mine[m] = p < n_patch ? patches[p] : Patch{0, 0, 0, -1};
+        cur[m] = (FILL && p < n_patch && lane < n_freq) ? off[((job0 + lane) * n_patch + p) * n_split + sl.idx] : 0;
     }
-    __syncthreads();
+    // level 2 over queue entries [base, base + n), n <= 64
+    auto level2 = [&](int base, int n) {
+        const bool valid = lane < n;
+        const int i = base + (valid ? lane : 0);
+        const CullRec S = q_rec[i];
+        const int32_t seg = q_seg[i];
+        const unsigned long long bm = valid ? q_mask[i] : 0ull;
+#pragma unroll
+        for (int m = 0; m < kOwn; ++m) {
+            if (__builtin_amdgcn_readfirstlane(mine[m].rad < 0.0 ? 1 : 0)) continue;
+            const Reach r = reach(S, mine[m]);
+#pragma unroll
+            for (int b = 0; b < B.count(); ++b) {
+                const bool k2 = ((bm >> b) & 1ull) & B.pass(r, b);
+                const unsigned long long bl = __ballot(k2);
+                if (bl == 0ull) continue;
+                if (FILL && k2) lists[lane_i64(cur[m], b) + lanes_before(bl)] = seg;
+                cur[m] += lane == b ? (int64_t)__popcll(bl) : 0;
+            }
+        }
+    };
+    auto load = [&](int64_t j, CullRec& r) {
+        if (j < sl.end) {
+            const double2* q = reinterpret_cast<const double2*>(rec + j);
+            const double2 a0 = q[0], a1 = q[1], a2 = q[2], a3 = q[3], a4 = q[4];
+            r = CullRec{-0.5 * a0.x, -0.5 * a0.y, -0.5 * a1.x, a2.x, a2.y, a3.x, a4.x, a4.y};
+        }
+    };
+    CullRec nxt{0, 0, 0, 0, 0, 1, 1, 0};
+    load(sl.begin + tid, nxt);
+    int qn = 0;                                           // queued survivors (workgroup-uniform)
     for (int64_t c = sl.begin; c < sl.end; c += kCullThreads) {
         const int64_t j = c + tid;
+        const CullRec me = nxt;
+        load(j + kCullThreads, nxt);
         unsigned long long mask = 0ull;
         if (j < sl.end) {
-            const Reach r = reach(rec[j], SPt);
-            for (int b = 0; b < n_freq; ++b) mask |= (unsigned long long)reach_band(r, kap[b], kape[b]) << b;
+            const Reach r = reach(me, SPt);
+#pragma unroll
+            for (int b = 0; b < B.count(); ++b) mask |= (unsigned long long)B.pass(r, b) << b;
         }
         const bool keep = mask != 0ull;
-        unsigned long long bal = __ballot(keep);
+        const unsigned long long bal = __ballot(keep);
         if (lane == 0) wave_cnt[wv] = __popcll(bal);
         __syncthreads();
         int pre = 0, tot = 0;
@@ -325,41 +422,48 @@ __global__ __launch_bounds__(kCullThreads) void k_cull(const JobConst* __restric
             tot += wave_cnt[w];
         }
         if (keep) {
-            q_seg[pre + lanes_before(bal)] = (int32_t)j;
-            q_mask[pre + lanes_before(bal)] = mask;
+            const int pos = qn + pre + lanes_before(bal);
+            q_rec[pos] = me;
+            q_seg[pos] = (int32_t)j;
+            q_mask[pos] = mask;
         }
+        qn += tot;
         __syncthreads();
-        for (int m = 0; m < kOwn; ++m) {
-            if (mine[m].rad < 0) continue;
-            const int p = p0 + wv + kWaves * m;
-            const int pm = wv + kWaves * m;
-            for (int b0 = 0; b0 < tot; b0 += 64) {
-                const int i = b0 + lane;
-                const int32_t seg = i < tot ? q_seg[i] : 0;
-                const unsigned long long qm = i < tot ? q_mask[i] : 0ull;
-                const Reach r = reach(rec[seg], mine[m]);
-                for (int b = 0; b < n_freq; ++b) {
-                    const bool k2 = ((qm >> b) & 1ull) && reach_band(r, kap[b], kape[b]);
-                    const unsigned long long bl = __ballot(k2);
-                    if (bl == 0ull) continue;
-                    const int32_t done = run[pm][b];
-                    if (FILL && k2) {
-                        const int64_t base = off[((job0 + b) * n_patch + p) * n_split + sl.idx];
-                        lists[base + done + lanes_before(bl)] = seg;
-                    }
-                    run[pm][b] = done + __popcll(bl);   // this wave owns (pm, b): every lane stores the same value
-                }
+        if (qn >= kWave) {
+            const int nb = qn / kWave, rest = qn - nb * kWave;
+            for (int k = 0; k < nb; ++k) level2(k * kWave, kWave);
+            double2 t0 = make_double2(0, 0), t1 = t0, t2 = t0, t3 = t0;
+            int32_t ts = 0;
+            unsigned long long tm = 0ull;
+            if (tid < rest) {                             // source [nb*64, qn) and target [0, rest) are disjoint
+                const double2* q = reinterpret_cast<const double2*>(q_rec + nb * kWave + tid);
+                t0 = q[0];
+                t1 = q[1];
+                t2 = q[2];
+                t3 = q[3];
+                ts = q_seg[nb * kWave + tid];
+                tm = q_mask[nb * kWave + tid];
             }
+            __syncthreads();
+            if (tid < rest) {
+                double2* q = reinterpret_cast<double2*>(q_rec + tid);
+                q[0] = t0;
+                q[1] = t1;
+                q[2] = t2;
+                q[3] = t3;
+                q_seg[tid] = ts;
+                q_mask[tid] = tm;
+            }
+            __syncthreads();
+            qn = rest;
         }
-        __syncthreads();
     }
+    if (qn > 0) level2(0, qn);
     if (!FILL) {
+#pragma unroll
         for (int m = 0; m < kOwn; ++m) {
             const int p = p0 + wv + kWaves * m;
-            if (p >= n_patch) continue;
-            const int pm = wv + kWaves * m;
-            for (int b = lane; b < n_freq; b += 64)
-                counts[((job0 + b) * n_patch + p) * n_split + sl.idx] = run[pm][b];
+            if (p < n_patch && lane < n_freq) counts[((job0 + lane) * n_patch + p) * n_split + sl.idx] = (int32_t)cur[m];
         }
     }
 }
@@ -372,42 +476,67 @@ __global__ void k_item_lengths(const int64_t* __restrict__ off, int32_t n_items,
     len[i] = (int32_t)(off[(int64_t)(i + 1) * n_split] - off[(int64_t)i * n_split]);
 }
 
+// ids[i] = i: the payload of the longest-first item sort.
+__global__ void k_iota(int32_t* __restrict__ ids, int32_t n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) ids[i] = i;
+}
+
 // ------------------------------------------------------------- pair kernels
 // Beam term of one (segment, receiver) pair without the job's common weight
 // k eps / (8 pi^2):
-//   B = w Gamma (s + i eps)/(s^2 + eps^2) exp(-(k eps/2) n^2/den) exp(2 pi i cyc),
-//   cyc = (f/c) (s + n^2 s / (2 den)),   den = s^2 + eps^2.
-// gate() evaluates the arc length, the gate and the beam interval (FP64 in
-// F64 and MIX); term() the beam term for a pair that passed the gate.  term()
-// has no memory access and stays finite for any gate-rejected input, so the
-// kernel may run it on all lanes and discard the rejected results.
+//   B = w Gamma (s + i eps)/(s^2 + eps^2) exp(-(k eps/2) a) exp(2 pi i cyc),
+//   a = n^2/den,  den = s^2 + eps^2,  cyc = (f/c) s (1 + a/2).
+// The pair kernels read segments from an LDS tile that is staged per work
+// unit, so job-dependent per-segment constants are folded in once per tile:
+// the gate's c2 - |o|^2 and, in MIX and F32, the complex weight and eps times
+// it as FP32.  gate() evaluates the arc length, the gate and the beam
+// interval (FP64 in F64 and MIX); term() the beam term, which is exactly zero
+// when `live` is false (the Gaussian factor is forced to zero) and finite for
+// any input, so the kernel runs it on all lanes of a wave with a passing lane.
+struct TileRec {
+    double m2ox, m2oy;   // -2 o
+    double m2oz, c2oo;   // gate constant of the job minus |o|^2
+    double tx, ty;       // unit axis
+    double tz, mot;      //   and -o.t
+    double slo, shi;     // beam interval in arc length
+    double oo, pad;      // |o|^2
+    double wgr, wgi;     // F64: w Gamma.  MIX/F32: float4 (w Gamma, eps w Gamma) as (Re, Im, Re, Im)
+};
+static_assert(sizeof(TileRec) == 112, "TileRec layout");
+
 template <int MODE>
 struct Beam;
 
 constexpr int kF64 = 0, kMIX = 1, kF32 = 2;
 
+__device__ __forceinline__ float4 tile_weights(const TileRec& S) {
+    return *reinterpret_cast<const float4*>(&S.wgr);
+}
+
 template <>
 struct Beam<kF64> {
     using T = double;
     struct Geo { double s, l; };   // arc length, |R - o|^2 - |o|^2
-    __device__ __forceinline__ static bool gate(const SegRec& S, const JobConst& J, double X, double Y, double Z,
+    __device__ __forceinline__ static bool gate(const TileRec& S, const JobConst& J, double X, double Y, double Z,
                                                 double R2, Geo& g) {
         g.s = fma(X, S.tx, fma(Y, S.ty, fma(Z, S.tz, S.mot)));
         g.l = fma(X, S.m2ox, fma(Y, S.m2oy, fma(Z, S.m2oz, R2)));
-        const double rhs = fma(g.s * J.gate_c1, g.s, J.gate_c2 - S.oo);
+        const double rhs = fma(g.s * J.gate_c1, g.s, S.c2oo);
         return g.l <= rhs && g.s >= S.slo && g.s < S.shi;
     }
-    __device__ __forceinline__ static void term(const SegRec& S, const JobConst& J, const Geo& g, double& ur,
-                                                double& ui) {
+    __device__ __forceinline__ static void term(const TileRec& S, const JobConst& J, const Geo& g, bool live,
+                                                double& ur, double& ui) {
         const double s = g.s;
         const double n2 = fma(-s, s, g.l + S.oo);
         const double den = fma(s, s, J.eps2);
         const double rden = 1.0 / den;
-        const double cyc = fma(n2 * s, rden * J.hfk, s * J.fk);
+        const double a = n2 * rden;
+        const double cyc = s * fma(J.hfk, a, J.fk);
         const double ph = cyc - floor(cyc);
         double sn, cs;
         sincospi(2.0 * ph, &sn, &cs);
-        const double w = rden * exp(n2 * rden * J.gexp);
+        const double w = live ? rden * exp(a * J.gexp) : 0.0;
         const double cr = fma(s, S.wgr, -J.eps * S.wgi) * w;
         const double ci = fma(s, S.wgi, J.eps * S.wgr) * w;
         ur = cr * cs - ci * sn;
@@ -419,26 +548,29 @@ template <>
 struct Beam<kMIX> {
     using T = float;
     using Geo = Beam<kF64>::Geo;
-    __device__ __forceinline__ static bool gate(const SegRec& S, const JobConst& J, double X, double Y, double Z,
+    __device__ __forceinline__ static bool gate(const TileRec& S, const JobConst& J, double X, double Y, double Z,
                                                 double R2, Geo& g) {
         return Beam<kF64>::gate(S, J, X, Y, Z, R2, g);
     }
-    __device__ __forceinline__ static void term(const SegRec& S, const JobConst& J, const Geo& g, float& ur,
-                                                float& ui) {
+    __device__ __forceinline__ static void term(const TileRec& S, const JobConst& J, const Geo& g, bool live,
+                                                float& ur, float& ui) {
         const double s = g.s;
         const double n2 = fma(-s, s, g.l + S.oo);
         const double den = fma(s, s, J.eps2);
         const float r0f = __builtin_amdgcn_rcpf((float)den);
         const double r0 = (double)r0f;
         const double rden = fma(r0, fma(-den, r0, 1.0), r0);                 // one Newton step
-        const double cyc = fma(n2 * s, rden * J.hfk, s * J.fk);              // phase in cycles, FP64
+        const double a = n2 * rden;
+        const double cyc = s * fma(J.hfk, a, J.fk);                          // phase in cycles, FP64
         const float ph = (float)__builtin_amdgcn_fract(cyc);                 // reduced modulo one in FP64
         const float sn = __builtin_amdgcn_sinf(ph);                          // sin(2 pi ph)
         const float cs = __builtin_amdgcn_cosf(ph);
-        const float w = r0f * __builtin_amdgcn_exp2f((float)n2 * r0f * (float)J.gexp2);
+        const float g2 = live ? (float)(a * J.gexp2) : -INFINITY;           // Gaussian exponent, base 2
+        const float w = r0f * __builtin_amdgcn_exp2f(g2);
+        const float4 W = tile_weights(S);
         const float sf = (float)s;
-        const float cr = fmaf(sf, (float)S.wgr, -(float)J.eps * (float)S.wgi) * w;
-        const float ci = fmaf(sf, (float)S.wgi, (float)J.eps * (float)S.wgr) * w;
+        const float cr = fmaf(sf, W.x, -W.w) * w;
+        const float ci = fmaf(sf, W.y, W.z) * w;
         ur = cr * cs - ci * sn;
         ui = cr * sn + ci * cs;
     }
@@ -448,7 +580,7 @@ template <>
 struct Beam<kF32> {
     using T = float;
     struct Geo { float s, n2, den; };
-    __device__ __forceinline__ static bool gate(const SegRec& S, const JobConst& J, double Xd, double Yd, double Zd,
+    __device__ __forceinline__ static bool gate(const TileRec& S, const JobConst& J, double Xd, double Yd, double Zd,
                                                 double, Geo& g) {
         const float X = (float)Xd, Y = (float)Yd, Z = (float)Zd;
         const float vx = X + 0.5f * (float)S.m2ox, vy = Y + 0.5f * (float)S.m2oy, vz = Z + 0.5f * (float)S.m2oz;
@@ -457,15 +589,16 @@ struct Beam<kF32> {
         g.den = fmaf(g.s, g.s, (float)J.eps2);
         return g.n2 <= (float)J.kappa * g.den && g.s >= (float)S.slo && g.s < (float)S.shi;
     }
-    __device__ __forceinline__ static void term(const SegRec& S, const JobConst& J, const Geo& g, float& ur,
-                                                float& ui) {
+    __device__ __forceinline__ static void term(const TileRec& S, const JobConst& J, const Geo& g, bool live,
+                                                float& ur, float& ui) {
         const float rden = __builtin_amdgcn_rcpf(g.den);
         const float cyc = (float)J.fk * fmaf(0.5f * g.n2 * g.s, rden, g.s);
         const float ph = __builtin_amdgcn_fractf(cyc);
         const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
-        const float w = rden * __builtin_amdgcn_exp2f(g.n2 * rden * (float)J.gexp2);
-        const float cr = fmaf(g.s, (float)S.wgr, -(float)J.eps * (float)S.wgi) * w;
-        const float ci = fmaf(g.s, (float)S.wgi, (float)J.eps * (float)S.wgr) * w;
+        const float w = rden * __builtin_amdgcn_exp2f(live ? g.n2 * rden * (float)J.gexp2 : -INFINITY);
+        const float4 W = tile_weights(S);
+        const float cr = fmaf(g.s, W.x, -W.w) * w;
+        const float ci = fmaf(g.s, W.y, W.z) * w;
         ur = cr * cs - ci * sn;
         ui = cr * sn + ci * cs;
     }
@@ -473,7 +606,7 @@ struct Beam<kF32> {
 
 // One segment for one receiver: wave-uniform skip when no lane passes.
 template <int MODE>
-__device__ __forceinline__ int pair_one(const SegRec& S, const JobConst& J, double X, double Y, double Z, double R2,
+__device__ __forceinline__ int pair_one(const TileRec& S, const JobConst& J, double X, double Y, double Z, double R2,
                                         double& ar, double& ai) {
     using B = Beam<MODE>;
     typename B::Geo g;
@@ -481,9 +614,9 @@ __device__ __forceinline__ int pair_one(const SegRec& S, const JobConst& J, doub
     if (__ballot(k0) == 0ull) return 0;
     branch_barrier();
     typename B::T ur, ui;
-    B::term(S, J, g, ur, ui);
-    ar += k0 ? (double)ur : 0.0;
-    ai += k0 ? (double)ui : 0.0;
+    B::term(S, J, g, k0, ur, ui);
+    ar += (double)ur;
+    ai += (double)ui;
     return k0;
 }
 
@@ -491,7 +624,7 @@ __device__ __forceinline__ int pair_one(const SegRec& S, const JobConst& J, doub
 // dependency chains that the compiler interleaves; one wave-uniform branch
 // skips both when no lane passes either gate.
 template <int MODE>
-__device__ __forceinline__ int pair_two(const SegRec& S0, const SegRec& S1, const JobConst& J, double X, double Y,
+__device__ __forceinline__ int pair_two(const TileRec& S0, const TileRec& S1, const JobConst& J, double X, double Y,
                                         double Z, double R2, double& ar, double& ai) {
     using B = Beam<MODE>;
     using T = typename B::T;
@@ -501,12 +634,10 @@ __device__ __forceinline__ int pair_two(const SegRec& S0, const SegRec& S1, cons
     if (__ballot(k0 || k1) == 0ull) return 0;
     branch_barrier();
     T u0r, u0i, u1r, u1i;
-    B::term(S0, J, g0, u0r, u0i);
-    B::term(S1, J, g1, u1r, u1i);
-    const T zr = (k0 ? u0r : (T)0) + (k1 ? u1r : (T)0);
-    const T zi = (k0 ? u0i : (T)0) + (k1 ? u1i : (T)0);
-    ar += (double)zr;
-    ai += (double)zi;
+    B::term(S0, J, g0, k0, u0r, u0i);
+    B::term(S1, J, g1, k1, u1r, u1i);
+    ar += (double)(u0r + u1r);
+    ai += (double)(u0i + u1i);
     return (int)k0 + (int)k1;
 }
 
@@ -525,6 +656,27 @@ __device__ __forceinline__ int pair_two(const SegRec& S0, const SegRec& S1, cons
         q_[0] = n##0; q_[1] = n##1; q_[2] = n##2;                                 \
         q_[3] = n##3; q_[4] = n##4; q_[5] = n##5;                                 \
     } while (0)
+
+// Builds a lane's tile record from its segment record (six 16-byte vectors in
+// SegRec field order) for job J and stores it to the wave's LDS tile.
+template <int MODE>
+__device__ __forceinline__ void stage_rec(TileRec* dst, double2 r0, double2 r1, double2 r2, double2 r3, double2 r4,
+                                          double2 r5, const JobConst& J) {
+    double2* q = reinterpret_cast<double2*>(dst);
+    q[0] = r0;
+    q[1] = make_double2(r1.x, J.gate_c2 - r1.y);
+    q[2] = r2;
+    q[3] = r3;
+    q[4] = r4;
+    q[5] = make_double2(r1.y, 0.0);
+    if (MODE == kF64) {
+        q[6] = r5;
+    } else {
+        *reinterpret_cast<float4*>(q + 6) =
+            make_float4((float)r5.x, (float)r5.y, (float)(J.eps * r5.x), (float)(J.eps * r5.y));
+    }
+}
+#define GBS_STAGE(MODE, dst, n, J) stage_rec<MODE>((dst), n##0, n##1, n##2, n##3, n##4, n##5, (J))
 
 // Pops the next work item (wave-uniform) from the global counter.  Lane 0
 // issues the atomic.  Callers put branch_barrier() in front of it and issue
@@ -559,9 +711,9 @@ __global__ __launch_bounds__(kPairThreads, GBS_PAIR_MIN_WAVES) void k_pairs(cons
                                               const double* __restrict__ rx, const double* __restrict__ ry,
                                               const double* __restrict__ rz, const double* __restrict__ r2,
                                               double* __restrict__ partial, unsigned long long* __restrict__ n_active) {
-    __shared__ __align__(16) SegRec tile[kPairThreads / kWave][kWave];
+    __shared__ __align__(16) TileRec tile[kPairThreads / kWave][kWave];
     const int lane = threadIdx.x & (kWave - 1);
-    SegRec* const my = tile[threadIdx.x / kWave];
+    TileRec* const my = tile[threadIdx.x / kWave];
     const int n_work = __builtin_amdgcn_readfirstlane(*n_work_p);
     unsigned long long active = 0;
     for (;;) {
@@ -592,14 +744,14 @@ __global__ __launch_bounds__(kPairThreads, GBS_PAIR_MIN_WAVES) void k_pairs(cons
         for (int64_t e0 = beg; e0 < end; e0 += kWave) {
             const int cnt = (int)min<int64_t>(kWave, end - e0);
             wave_lds_fence();
-            GBS_REC_STORE(my + lane, nx);
+            GBS_STAGE(MODE, my + lane, nx, J);
             wave_lds_fence();
             GBS_REC_LOAD(nx, rec, idx_ahead);
             idx_ahead = lists[min(e0 + 2 * kWave + lane, end - 1)];
             int k = 0;
 #ifndef GBS_PAIR_SINGLE
             for (; k + 2 <= cnt; k += 2) {
-                const SegRec S0 = my[k], S1 = my[k + 1];
+                const TileRec S0 = my[k], S1 = my[k + 1];
 #pragma unroll
                 for (int m = 0; m < NR; ++m) {
                     const int hit = pair_two<MODE>(S0, S1, J, X[m], Y[m], Z[m], R2[m], ar[m], ai[m]);
@@ -608,7 +760,7 @@ __global__ __launch_bounds__(kPairThreads, GBS_PAIR_MIN_WAVES) void k_pairs(cons
             }
 #endif
             for (; k < cnt; ++k) {
-                const SegRec S = my[k];
+                const TileRec S = my[k];
 #pragma unroll
                 for (int m = 0; m < NR; ++m) {
                     const int hit = pair_one<MODE>(S, J, X[m], Y[m], Z[m], R2[m], ar[m], ai[m]);
@@ -965,10 +1117,13 @@ __global__ void k_validate(int64_t n_segs, const double* __restrict__ t, const d
 }
 
 // Explicit instantiations used by the host planner.
-template __global__ void k_cull<false>(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int,
-                                       const CullSplit*, int32_t*, const int64_t*, int32_t*);
-template __global__ void k_cull<true>(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int,
-                                      const CullSplit*, int32_t*, const int64_t*, int32_t*);
+#define GBS_INST_CULL(F, NB)                                                                                   \
+    template __global__ void k_cull<F, NB>(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int, \
+                                           const CullSplit*, int32_t*, const int64_t*, int32_t*);
+GBS_INST_CULL(false, 8)
+GBS_INST_CULL(true, 8)
+GBS_INST_CULL(false, 0)
+GBS_INST_CULL(true, 0)
 #define GBS_INST_PAIRS(M, N, C)                                                                                  \
     template __global__ void k_pairs<M, N, C>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,    \
                                               const int32_t*, const SegRec*, const double*, const double*,       \
