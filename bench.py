@@ -9,9 +9,11 @@ the table resident in HBM.  `value` = dense segment x receiver x band
 evaluations per second (the dense sum the culled kernel reproduces).
 
 Also reported: the pair kernel's roofline (algorithmic FLOPs per launch over
-its HIP-event-timed duration), the all-FP64 mode on the same GPU, the error
-against the FP64 oracle on 16,384 seeded receivers, and the oracle timed on
-this host's cores on that sample.
+its HIP-event-timed duration), the all-FP64 mode on the same GPU, the table
+streamed from pinned host memory in four overlapped passes (PCIe-inclusive,
+never `value`), the adjoint call on the same workload, the error against the
+FP64 oracle on 16,384 seeded receivers, and the oracle timed on this host's
+cores on that sample (and single-threaded on a smaller one).
 """
 from __future__ import annotations
 
@@ -27,14 +29,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic work per pair of the pair kernel, counted from the evaluated
-# formulas (an FMA counts 2; a transcendental, a reciprocal or a fract 1):
-#   gate, every listed pair:  s (3 FMA), |R-o|^2 (3 FMA), rhs (mul, FMA, add)   -> 16 FP64
-#   beam term, every kept pair: n^2, den, Newton reciprocal, phase in cycles,
-#       fract, FP64 accumulation                                            -> 17 FP64
-#     rcp, sin, cos, exp2, Gaussian, amplitude and complex products         -> 21 FP32
-FLOP_LISTED_F64 = 16
+# formulas (an FMA counts 2; a transcendental, a reciprocal or a fract 1;
+# compares count 0):
+#   every listed pair: arc length s (3 FMA) and |R-o|^2 - |o|^2 (3 FMA)        -> 12 FP64
+#     (the gate's right-hand side, skipped where the cull proved that every
+#     receiver of the patch passes, is not counted)
+#   every kept pair: n^2 (add, FMA), den (FMA), Newton reciprocal (2 FMA),
+#     a = n^2/den, cycles (FMA, mul), fract, Gaussian exponent, accumulation
+#     (2 adds)                                                             -> 17 FP64
+#     rcp, sin, cos, exp2, weight, amplitude (2 x (FMA, mul)), rotation
+#     (2 x (mul, FMA)), pair sum                                           -> 18 FP32
+FLOP_LISTED_F64 = 12
 FLOP_KEPT_F64 = 17
-FLOP_KEPT_F32 = 21
+FLOP_KEPT_F32 = 18
 # Vector peaks from unit counts and clock: 256 CUs x 2.4 GHz x 64 FMA lanes x 2
 # = 78.6 TFLOP/s FP64; FP32 157.3 TFLOP/s (vendor figure).
 PEAK_F64 = 256 * 2.4e9 * 64 * 2
@@ -49,6 +56,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-f64", action="store_true", help="skip the all-FP64 comparison")
     ap.add_argument("--cpu-receivers", type=int, default=16384)
+    ap.add_argument("--cpu1-receivers", type=int, default=512, help="receivers of the single-thread oracle sample")
+    ap.add_argument("--no-stream", action="store_true", help="skip the host-streamed table leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the steps, run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -84,16 +94,23 @@ def main():
         for _ in range(warmup):
             step(mode)
         torch.cuda.synchronize()
-        ms_pairs, ms_cull = [], []
+        ms_pairs, ms_cull, ms_step = [], [], []
+        stream = torch.cuda.current_stream(dev)
         t = time.perf_counter()
         for _ in range(steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
             out = step(mode, timed=True)
+            e1.record(stream)
             st = gbs.stats(dev)
             ms_pairs.append(st["ms_pairs"])
             ms_cull.append(st["ms_cull"])
+            e1.synchronize()
+            ms_step.append(e0.elapsed_time(e1))
         torch.cuda.synchronize()
         el = time.perf_counter() - t
-        run.last = {"ms_cull": float(np.mean(ms_cull)), "grid": st["grid"], "blocks_per_cu": st["blocks_per_cu"]}
+        run.last = {"ms_cull": float(np.mean(ms_cull)), "grid": st["grid"], "blocks_per_cu": st["blocks_per_cu"],
+                    "ms_step_median": float(np.median(ms_step)), "ms_step_min": float(np.min(ms_step))}
         return el / steps, float(np.mean(ms_pairs)), out
 
     mode = "mix"
@@ -109,6 +126,45 @@ def main():
     achieved = flops / (ms_pairs * 1e-3)
     # peak for this kernel's FP64/FP32 mix: time at peak = f64/PEAK_F64 + f32/PEAK_F32
     peak = flops / (f64 / PEAK_F64 + f32 / PEAK_F32)
+
+    stream_leg = None
+    if not args.no_stream:
+        # the table in pinned host memory, copied in 4 passes that overlap compute (PCIe-inclusive)
+        host_table = gbs.Table(sc.table, device=dev, on_host=True)
+        chunk = -(-table.n_segs // 4)
+        call = lambda: gbs.forward(host_table, rcv, freqs, eps, gamma, c=sc.c, gate=sc.gate, mode=mode,
+                                   chunk_segs=chunk)
+        call()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        n_st = max(2, args.steps // 2)
+        for _ in range(n_st):
+            call()
+        torch.cuda.synchronize()
+        s_st = (time.perf_counter() - t) / n_st
+        stream_leg = {"value": dense / s_st, "ms_per_step": s_st * 1e3, "passes": gbs.stats(dev)["n_chunks"],
+                      "table_bytes": int(sum(np.asarray(v).nbytes for v in (sc.table.seg_a, sc.table.seg_t,
+                                             sc.table.seg_s0, sc.table.seg_lo, sc.table.seg_hi)))}
+        del host_table
+        print(f"# streamed: {s_st * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+
+    adj_leg = None
+    if not args.no_adjoint:
+        g = torch.Generator().manual_seed(11)
+        lam = torch.complex(torch.randn(P.shape, generator=g, dtype=torch.float64),
+                            torch.randn(P.shape, generator=g, dtype=torch.float64)).to(dev)
+        bwd = lambda: gbs.backward(table, rcv, freqs, eps, gamma, lam, c=sc.c, gate=sc.gate, mode=mode)
+        bwd()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        n_adj = max(2, args.steps // 4)
+        for _ in range(n_adj):
+            bwd()
+        torch.cuda.synchronize()
+        s_adj = (time.perf_counter() - t) / n_adj
+        adj_leg = {"value": dense / s_adj, "ms_per_call": s_adj * 1e3, "mode": mode,
+                   "forward_plus_adjoint_ms": sec_step * 1e3 + s_adj * 1e3}
+        print(f"# adjoint: {s_adj * 1e3:.2f} ms/call", file=sys.stderr, flush=True)
 
     f64_leg = None
     if not args.no_f64:
@@ -140,9 +196,15 @@ def main():
                      "flop_per_listed_pair": {"f64": FLOP_LISTED_F64},
                      "flop_per_kept_pair": {"f64": FLOP_KEPT_F64, "f32": FLOP_KEPT_F32}},
         "pair_kernel_share": ms_pairs / (sec_step * 1e3),
+        "ms_step_median": launch["ms_step_median"],
+        "ms_step_min": launch["ms_step_min"],
         "ms_cull": launch["ms_cull"],
+        "pairs": {"listed_per_s": listed / sec_step, "kept_per_s": active / sec_step,
+                  "culled_fraction": 1.0 - listed / dense, "kept_fraction_of_listed": active / max(listed, 1)},
         "launch": {"grid": launch["grid"], "blocks_per_cu": launch["blocks_per_cu"], "threads_per_block": 256},
         "f64": f64_leg,
+        "streamed": stream_leg,
+        "adjoint": adj_leg,
     }
 
     if args.copy_calibration > 0:
@@ -166,7 +228,16 @@ def main():
         pairs = table.n_segs * len(idx) * len(sc.freqs)
         result["cpu_baseline"] = {"value": pairs / el, "unit": "evals/s", "cores": threads, "kind": "oracle",
                                   "sample": f"{len(idx)} of {len(sc.rcv)} receivers (seed 5), all "
-                                            f"{table.n_segs} segments, {len(sc.freqs)} bands; {el:.1f}s"}
+                                            f"{table.n_segs} segments, {len(sc.freqs)} bands; {el:.1f}s",
+                                  "extrapolated_full_config_s": dense / (pairs / el)}
+        if args.cpu1_receivers > 0:
+            idx1 = receiver_subsample(len(sc.rcv), n=args.cpu1_receivers, seed=6)
+            t = time.perf_counter()
+            oracle.scene_forward(sc, rcv=sc.rcv[idx1], n_threads=1)
+            el1 = time.perf_counter() - t
+            result["cpu_baseline"]["single_thread"] = {
+                "value": table.n_segs * len(idx1) * len(sc.freqs) / el1, "cores": 1,
+                "sample": f"{len(idx1)} receivers (seed 6); {el1:.1f}s"}
         Pg = P.cpu().numpy().reshape(len(sc.freqs), -1)[:, idx]
         TLg = TL.cpu().numpy().reshape(len(sc.freqs), -1)[:, idx]
         mag = np.abs(P_ref)
@@ -174,7 +245,9 @@ def main():
         dtl = np.abs(TLg - TL_ref)[ok]
         rel = (np.abs(Pg - P_ref) / np.maximum(mag, 1e-300))[ok]
         result["accuracy_vs_oracle"] = {"tl_err_db_max": float(dtl.max()), "tl_err_db_p99": float(
-            np.percentile(dtl, 99)), "rel_err_max": float(rel.max()), "receivers": int(len(idx))}
+            np.percentile(dtl, 99)), "tl_err_db_median": float(np.median(dtl)), "rel_err_max": float(rel.max()),
+            "rel_err_p99": float(np.percentile(rel, 99)), "rel_err_median": float(np.median(rel)),
+            "receivers": int(len(idx)), "masked_fraction": float(1.0 - ok.mean())}
     print(json.dumps(result), flush=True)
 
 

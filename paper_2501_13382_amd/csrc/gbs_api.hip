@@ -96,6 +96,7 @@ void fill(hipStream_t st, double* p, int64_t n, double v) {
 struct Workspace {
     std::map<std::string, std::pair<void*, size_t>> bufs;
     hipStream_t stream = nullptr;
+    hipStream_t copy_stream = nullptr;    // also drained before a buffer is freed
     ~Workspace() { release(); }
     void release() {
         for (auto& kv : bufs)
@@ -109,6 +110,7 @@ struct Workspace {
         if (b.second < bytes) {
             if (b.first) {
                 GBS_HIP(hipStreamSynchronize(stream));
+                if (copy_stream) GBS_HIP(hipStreamSynchronize(copy_stream));
                 GBS_HIP(hipFree(b.first));
                 b.first = nullptr;
                 b.second = 0;
@@ -147,6 +149,11 @@ struct gbs_ctx {
     int tuned_nr[3] = {0, 0, 0};
     void* pinned = nullptr;
     size_t pinned_cap = 0;
+    // streaming of host-resident tables: pass i+1 is copied on copy_stream
+    // while pass i computes; two staging slots, ordered by these events
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t copied[2] = {nullptr, nullptr};
+    hipEvent_t released[2] = {nullptr, nullptr};
 };
 
 struct gbs_graph {
@@ -426,13 +433,17 @@ struct Planner {
     };
 
     template <typename T>
-    const T* stage(const char* name, const T* src, int64_t count) {
+    const T* stage(const std::string& name, const T* src, int64_t count, hipStream_t cs) {
         T* d = ws.get<T>(name, std::max<int64_t>(count, 1));
-        if (count > 0) GBS_HIP(hipMemcpyAsync(d, src, sizeof(T) * count, hipMemcpyHostToDevice, st));
+        if (count > 0) GBS_HIP(hipMemcpyAsync(d, src, sizeof(T) * count, hipMemcpyHostToDevice, cs));
         return d;
     }
 
-    PassView view(const PassRange& ps) {
+    // Device view of one pass.  Host tables are copied into staging slot
+    // `slot` on stream cs (the compute stream unless passes are overlapped).
+    PassView view(const PassRange& ps, int slot = 0, hipStream_t cs = nullptr) {
+        if (!cs) cs = st;
+        const std::string sfx = std::to_string(slot);
         PassView v;
         v.n_rays = ps.ray_end - ps.ray_begin;
         v.n_segs = ps.seg_end - ps.seg_begin;
@@ -450,17 +461,17 @@ struct Planner {
             v.face_ids = S.face_ids;
             return v;
         }
-        v.ray_ptr = stage("p_ray_ptr", a.rays->ray_ptr + ps.ray_begin, v.n_rays + 1);
-        v.ray_w = stage("p_ray_w", a.rays->ray_w + ps.ray_begin, v.n_rays);
-        v.a = stage("p_a", S.a + 3 * ps.seg_begin, 3 * v.n_segs);
-        v.t = stage("p_t", S.t + 3 * ps.seg_begin, 3 * v.n_segs);
-        v.s0 = stage("p_s0", S.s0 + ps.seg_begin, v.n_segs);
-        v.lo = stage("p_lo", S.lo + ps.seg_begin, v.n_segs);
-        v.hi = stage("p_hi", S.hi + ps.seg_begin, v.n_segs);
-        v.face_ptr = stage("p_face_ptr", S.face_ptr + ps.seg_begin, v.n_segs + 1);
+        v.ray_ptr = stage("p_ray_ptr" + sfx, a.rays->ray_ptr + ps.ray_begin, v.n_rays + 1, cs);
+        v.ray_w = stage("p_ray_w" + sfx, a.rays->ray_w + ps.ray_begin, v.n_rays, cs);
+        v.a = stage("p_a" + sfx, S.a + 3 * ps.seg_begin, 3 * v.n_segs, cs);
+        v.t = stage("p_t" + sfx, S.t + 3 * ps.seg_begin, 3 * v.n_segs, cs);
+        v.s0 = stage("p_s0" + sfx, S.s0 + ps.seg_begin, v.n_segs, cs);
+        v.lo = stage("p_lo" + sfx, S.lo + ps.seg_begin, v.n_segs, cs);
+        v.hi = stage("p_hi" + sfx, S.hi + ps.seg_begin, v.n_segs, cs);
+        v.face_ptr = stage("p_face_ptr" + sfx, S.face_ptr + ps.seg_begin, v.n_segs + 1, cs);
         v.face_base = ps.face_begin;
-        v.face_ids = stage("p_face_ids", S.face_ids ? S.face_ids + ps.face_begin : nullptr,
-                           ps.face_end - ps.face_begin);
+        v.face_ids = stage("p_face_ids" + sfx, S.face_ids ? S.face_ids + ps.face_begin : nullptr,
+                           ps.face_end - ps.face_begin, cs);
         return v;
     }
 
@@ -701,6 +712,17 @@ void dispatch_pairs(int mode, bool count, int nr, gbs_ctx* ctx, hipStream_t st, 
 }
 
 
+// The copy stream and its events, created on first use (default priority).
+void ensure_copy_stream(gbs_ctx* ctx) {
+    if (ctx->copy_stream) return;
+    GBS_HIP(hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking));
+    for (int i = 0; i < 2; ++i) {
+        GBS_HIP(hipEventCreateWithFlags(&ctx->copied[i], hipEventDisableTiming));
+        GBS_HIP(hipEventCreateWithFlags(&ctx->released[i], hipEventDisableTiming));
+    }
+    ctx->ws->copy_stream = ctx->copy_stream;
+}
+
 int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* TL, int nr_override) {
     validate_host(a);
     GBS_CHECK(P || (int64_t)a.rays->n_src * a.n_freq * a.n_rcv == 0, "null P");
@@ -724,9 +746,31 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
         if (count) GBS_HIP(hipMemsetAsync(na, 0, sizeof(unsigned long long), st));
         const bool timed = (a.params->flags & GBS_FLAG_TIME_KERNELS) != 0;
         EventPair ev_pairs(timed), ev_cull(timed);
-        for (size_t pi = 0; pi < pl.passes.size(); ++pi) {
+        // host tables over several passes: copy pass i+1 on the copy stream
+        // while pass i computes (two staging slots)
+        const size_t n_pass = pl.passes.size();
+        const bool overlap = pl.table_host() && n_pass > 1;
+        Planner::PassView views[2];
+        auto issue = [&](size_t pi) {
+            const int slot = (int)(pi % 2);
+            if (pi >= 2) GBS_HIP(hipStreamWaitEvent(ctx->copy_stream, ctx->released[slot], 0));
+            views[slot] = pl.view(pl.passes[pi], slot, ctx->copy_stream);
+            GBS_HIP(hipEventRecord(ctx->copied[slot], ctx->copy_stream));
+        };
+        if (overlap) {
+            ensure_copy_stream(ctx);
+            issue(0);
+        }
+        for (size_t pi = 0; pi < n_pass; ++pi) {
             const PassRange& ps = pl.passes[pi];
-            Planner::PassView v = pl.view(ps);
+            Planner::PassView v;
+            if (overlap) {
+                if (pi + 1 < n_pass) issue(pi + 1);
+                GBS_HIP(hipStreamWaitEvent(st, ctx->copied[pi % 2], 0));
+                v = views[pi % 2];
+            } else {
+                v = pl.view(ps);
+            }
             ev_cull.begin(st);
             Planner::Lists L = pl.build_lists(ps, v, (int)pi);
             stats.ms_cull += ev_cull.end(st);
@@ -738,6 +782,7 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
                 dispatch_pairs(a.params->mode, count, nr, ctx, st, L, pl.R, a.n_rcv, P, ctr, na);
                 stats.ms_pairs += ev_pairs.end(st);
             }
+            if (overlap) GBS_HIP(hipEventRecord(ctx->released[pi % 2], st));
         }
         stats.n_chunks = (int32_t)pl.passes.size();
         if (count) {
@@ -798,8 +843,14 @@ void gbs_destroy(gbs_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->copy_stream) (void)hipStreamSynchronize(ctx->copy_stream);
     ctx->ws.reset();
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    for (int i = 0; i < 2; ++i) {
+        if (ctx->copied[i]) (void)hipEventDestroy(ctx->copied[i]);
+        if (ctx->released[i]) (void)hipEventDestroy(ctx->released[i]);
+    }
+    if (ctx->copy_stream) (void)hipStreamDestroy(ctx->copy_stream);
     delete ctx;
 }
 

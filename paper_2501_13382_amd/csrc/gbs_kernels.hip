@@ -28,10 +28,45 @@ __device__ __forceinline__ double wave_max(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     return v;
 }
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+// Wave sums with data-parallel-primitive lane moves (no LDS traffic): an
+// inclusive scan inside each row of 16 lanes (row_shr 1, 2, 4, 8), then the
+// row totals carried by row_bcast 15 and 31.  The full sum ends up in the
+// last lane only; other lanes hold partial sums.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, true);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(dpp_i32<CTRL, ROWS>(__float_as_int(v)));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = dpp_i32<CTRL, ROWS>((int)(u & 0xffffffffll)), hi = dpp_i32<CTRL, ROWS>((int)(u >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <typename T>
+__device__ __forceinline__ T wave_sum_last(T v) {
+    constexpr bool kD = sizeof(T) == 8;
+    if constexpr (kD) {
+        v += dpp_f64<0x111, 0xf>(v);
+        v += dpp_f64<0x112, 0xf>(v);
+        v += dpp_f64<0x114, 0xf>(v);
+        v += dpp_f64<0x118, 0xf>(v);
+        v += dpp_f64<0x142, 0xa>(v);
+        v += dpp_f64<0x143, 0xc>(v);
+    } else {
+        v += dpp_f32<0x111, 0xf>(v);
+        v += dpp_f32<0x112, 0xf>(v);
+        v += dpp_f32<0x114, 0xf>(v);
+        v += dpp_f32<0x118, 0xf>(v);
+        v += dpp_f32<0x142, 0xa>(v);
+        v += dpp_f32<0x143, 0xc>(v);
+    }
     return v;
 }
+
 // An empty volatile asm has side effects, so the compiler cannot hoist the
 // gated block above its wave-uniform branch and execute it for every pair.
 __device__ __forceinline__ void branch_barrier() { asm volatile(""); }
@@ -776,7 +811,7 @@ __global__ __launch_bounds__(kPairThreads, GBS_PAIR_MIN_WAVES) void k_pairs(cons
         }
     }
     if (COUNT) {
-        double tot = wave_sum((double)active);
+        double tot = wave_sum_last((double)active);
         if (lane == kLastLane) atomicAdd(n_active, (unsigned long long)tot);
     }
 }
@@ -881,10 +916,10 @@ __device__ __forceinline__ void adj_factors(T s, T n2, T rden, T eps, T k, AdjTe
     A.dei = iq_r - hk * iq2_i;
 }
 
-template <int MODE>
+template <int MODE, typename ST>
 __device__ __forceinline__ bool adj_eval(const SegRec& S, const JobConst& J, double X, double Y, double Z, double R2,
                                          double lr, double li, double& dRx, double& dRy, double& dRz, double& dE,
-                                         double& Sr, double& Si) {
+                                         ST& Sr, ST& Si) {
     double s = fma(X, S.tx, fma(Y, S.ty, fma(Z, S.tz, S.mot)));
     double l = fma(X, S.m2ox, fma(Y, S.m2oy, fma(Z, S.m2oz, R2)));
     double rhs = fma(s * J.gate_c1, s, J.gate_c2 - S.oo);
@@ -894,7 +929,13 @@ __device__ __forceinline__ bool adj_eval(const SegRec& S, const JobConst& J, dou
     if (!keep) return false;
     double n2 = fma(-s, s, l + S.oo);
     double den = fma(s, s, J.eps2);
-    double rden = 1.0 / den;
+    double rden;
+    if (MODE == kF64) {
+        rden = 1.0 / den;
+    } else {
+        const double r0 = (double)__builtin_amdgcn_rcpf((float)den);
+        rden = fma(r0, fma(-den, r0, 1.0), r0);                      // one Newton step
+    }
     double cyc = fma(n2 * s, rden * J.hfk, s * J.fk);
     double ph = cyc - floor(cyc);
     // normal vector R - o - s t  (o = -m2o / 2)
@@ -935,8 +976,8 @@ __device__ __forceinline__ bool adj_eval(const SegRec& S, const JobConst& J, dou
         dRy += (double)gt * S.ty + (double)gn * ny;
         dRz += (double)gt * S.tz + (double)gn * nz;
         dE += (double)(vr * A.der - vi * A.dei);
-        Sr += (double)(lrf * A.Br - lif * A.Bi);
-        Si += (double)(lrf * A.Bi + lif * A.Br);
+        Sr += lrf * A.Br - lif * A.Bi;
+        Si += lrf * A.Bi + lif * A.Br;
     }
     return true;
 }
@@ -993,15 +1034,16 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
             GBS_REC_LOAD(nx, rec, idx_cur);
             for (int k = 0; k < cnt; ++k) {
                 const SegRec S = my[k];
-                double Sr = 0.0, Si = 0.0;
+                using ST = typename Beam<MODE>::T;        // per-segment sums in the beam-term precision
+                ST Sr = 0, Si = 0;
                 const bool hit = adj_eval<MODE>(S, J, X, Y, Z, R2, lr, li, dRx, dRy, dRz, dE, Sr, Si);
                 if (__ballot(hit) != 0ull) {
-                    Sr = wave_sum(Sr);
-                    Si = wave_sum(Si);
+                    Sr = wave_sum_last(Sr);
+                    Si = wave_sum_last(Si);
                     if (lane == kLastLane) {
                         const int64_t j = my_idx[k];
-                        atomicAdd(&Sseg[2 * j], J.scale * Sr);
-                        atomicAdd(&Sseg[2 * j + 1], J.scale * Si);
+                        atomicAdd(&Sseg[2 * j], J.scale * (double)Sr);
+                        atomicAdd(&Sseg[2 * j + 1], J.scale * (double)Si);
                     }
                 }
             }
@@ -1010,7 +1052,7 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
         p[0] = dRx;
         p[1] = dRy;
         p[2] = dRz;
-        dE = wave_sum(dE);
+        dE = wave_sum_last(dE);
         if (lane == kLastLane) atomicAdd(&d_eps[job], J.scale * dE);
     }
 }
@@ -1055,41 +1097,71 @@ __global__ void k_sum_jobs(const double* __restrict__ dR_job, int32_t n_jobs, in
 
 // Z_f += d(prod Gamma_j)/dGamma_f * w_j * S_j for every distinct face f in
 // segment j's history (product of the other factors, summed over the
-// occurrences of f).
+// occurrences of f).  One thread per segment; the wave walks history
+// positions in step and adds the contributions of lanes that hit the same
+// face with one wave reduction and one atomic per distinct face (most
+// segments of a scene share a few faces, the ground above all).
 __global__ void k_face_scatter(int64_t n_segs, const int64_t* __restrict__ face_ptr, int64_t face_base,
                                const int32_t* __restrict__ face_ids, int32_t n_faces, const double* __restrict__ gamma,
                                const double* __restrict__ ray_w, const int32_t* __restrict__ seg_ray,
                                const double* __restrict__ Sseg, double* __restrict__ Zf) {
-    int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (j >= n_segs) return;
-    const double sr = Sseg[2 * j], si = Sseg[2 * j + 1];
-    if (sr == 0.0 && si == 0.0) return;
-    const int64_t b = face_ptr[j] - face_base, e = face_ptr[j + 1] - face_base;
-    const double w = ray_w[seg_ray[j]];
-    for (int64_t l = b; l < e; ++l) {
-        const int32_t f = face_ids[l];
-        if (f < 0 || f >= n_faces) continue;   // ids are validated on request only
-        bool seen = false;
-        for (int64_t m = b; m < l; ++m) seen |= face_ids[m] == f;
-        if (seen) continue;
-        double dr = 0.0, di = 0.0;
-        for (int64_t l2 = l; l2 < e; ++l2) {
-            if (face_ids[l2] != f) continue;
-            double pr = 1.0, pi = 0.0;
-            for (int64_t m = b; m < e; ++m) {
-                if (m == l2) continue;
-                const int32_t g = min(max(face_ids[m], 0), n_faces - 1);
-                double xr = gamma[2 * g], xi = gamma[2 * g + 1];
-                double nr = pr * xr - pi * xi;
-                pi = pr * xi + pi * xr;
-                pr = nr;
-            }
-            dr += pr;
-            di += pi;
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    double sr = 0.0, si = 0.0, w = 0.0;
+    int64_t b = 0, e = 0;
+    if (j < n_segs) {
+        sr = Sseg[2 * j];
+        si = Sseg[2 * j + 1];
+        if (sr != 0.0 || si != 0.0) {
+            b = face_ptr[j] - face_base;
+            e = face_ptr[j + 1] - face_base;
+            w = ray_w[seg_ray[j]];
         }
-        double zr = w * (dr * sr - di * si), zi = w * (dr * si + di * sr);
-        atomicAdd(&Zf[2 * (int64_t)f], zr);
-        atomicAdd(&Zf[2 * (int64_t)f + 1], zi);
+    }
+    const int len = (int)(e - b);
+    int max_len = len;
+    for (int o = 32; o > 0; o >>= 1) max_len = max(max_len, __shfl_xor(max_len, o));
+    for (int l = 0; l < max_len; ++l) {
+        int32_t f = -1;
+        double zr = 0.0, zi = 0.0;
+        if (l < len) {
+            f = face_ids[b + l];
+            bool skip = f < 0 || f >= n_faces;   // ids are validated on request only
+            for (int64_t m = b; m < b + l; ++m) skip |= face_ids[m] == f;   // counted at its first occurrence
+            if (skip) {
+                f = -1;
+            } else {
+                double dr = 0.0, di = 0.0;
+                for (int64_t l2 = b + l; l2 < e; ++l2) {
+                    if (face_ids[l2] != f) continue;
+                    double pr = 1.0, pi = 0.0;
+                    for (int64_t m = b; m < e; ++m) {
+                        if (m == l2) continue;
+                        const int32_t g = min(max(face_ids[m], 0), n_faces - 1);
+                        const double xr = gamma[2 * g], xi = gamma[2 * g + 1];
+                        const double nr = pr * xr - pi * xi;
+                        pi = pr * xi + pi * xr;
+                        pr = nr;
+                    }
+                    dr += pr;
+                    di += pi;
+                }
+                zr = w * (dr * sr - di * si);
+                zi = w * (dr * si + di * sr);
+            }
+        }
+        unsigned long long pending = __ballot(f >= 0);
+        while (pending) {
+            const int leader = __builtin_ctzll(pending);
+            const int32_t f0 = __builtin_amdgcn_readlane(f, leader);
+            const bool mine = f == f0;
+            const double tr = wave_sum_last(mine ? zr : 0.0), ti = wave_sum_last(mine ? zi : 0.0);
+            if (lane == kLastLane) {
+                atomicAdd(&Zf[2 * (int64_t)f0], tr);
+                atomicAdd(&Zf[2 * (int64_t)f0 + 1], ti);
+            }
+            pending &= ~__ballot(mine);
+        }
     }
 }
 

@@ -146,6 +146,13 @@ def test_host_table_streamed(city_small):
     torch.cuda.synchronize()
     assert gbs.stats()["n_chunks"] >= 3
     assert_within(compare(P.cpu().numpy(), TL.cpu().numpy(), P_ref, TL_ref, ab), "f64")
+    # copies of pass i+1 overlap pass i: the result is the device table's, bit for bit, on repeated calls
+    d = gbs.Table(sc.table, device="cuda")
+    Pd, _ = gbs.forward(d, sc.rcv, sc.freqs, sc.eps, sc.gamma, c=sc.c, gate=sc.gate, mode="mix", chunk_segs=20000)
+    for _ in range(2):
+        Ph, _ = gbs.forward(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, c=sc.c, gate=sc.gate, mode="mix",
+                            chunk_segs=20000)
+        assert torch.equal(Ph, Pd)
 
 
 def test_single_receiver_and_empty():
