@@ -47,6 +47,24 @@ FLOP_KEPT_F32 = 18
 PEAK_F64 = 256 * 2.4e9 * 64 * 2
 PEAK_F32 = 157.3e12
 
+# HBM bytes per launch of the pair kernel on this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy and fill (the summary in
+# profiles/k_pairs_mix_open_plane_100k.md).  Valid only for the kernel source
+# it was measured on; reported as null once that source changes.
+PAIR_TRAFFIC_BYTES = 2.984e9
+PAIR_TRAFFIC_SOURCE_MD5 = {"gbs_kernels.hip": "dfa66259d101dfca87aa9cab36e0e76c",
+                           "gbs_internal.h": "f48053ca35e02096dc67e1bfbdf18b4c"}
+
+
+def pair_traffic():
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2501_13382_amd", "csrc")
+    for name, md5 in PAIR_TRAFFIC_SOURCE_MD5.items():
+        with open(os.path.join(csrc, name), "rb") as f:
+            if hashlib.md5(f.read()).hexdigest() != md5:
+                return None
+    return PAIR_TRAFFIC_BYTES
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -192,7 +210,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_pairs<MIX>", "achieved": achieved / 1e12,
                      "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
                      "frac_of_fp32_peak": achieved / PEAK_F32, "frac_of_fp64_peak": achieved / PEAK_F64,
-                     "traffic": None, "ms_per_launch": ms_pairs, "listed_pairs": listed, "kept_pairs": active,
+                     "traffic": pair_traffic(), "ms_per_launch": ms_pairs, "listed_pairs": listed, "kept_pairs": active,
                      "flop_per_listed_pair": {"f64": FLOP_LISTED_F64},
                      "flop_per_kept_pair": {"f64": FLOP_KEPT_F64, "f32": FLOP_KEPT_F32}},
         "pair_kernel_share": ms_pairs / (sec_step * 1e3),
