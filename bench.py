@@ -9,7 +9,8 @@ the table resident in HBM.  `value` = dense segment x receiver x band
 evaluations per second (the dense sum the culled kernel reproduces).
 
 Also reported: the pair kernel's roofline (algorithmic FLOPs per launch over
-its HIP-event-timed duration), the all-FP64 mode on the same GPU, the table
+its HIP-event-timed duration), the all-FP64 mode on the same GPU, the forward
+captured as a hipGraph and replayed, the table
 streamed from pinned host memory in four overlapped passes (PCIe-inclusive,
 never `value`), the adjoint call on the same workload, the error against the
 FP64 oracle on 16,384 seeded receivers, and the oracle timed on this host's
@@ -66,6 +67,26 @@ def pair_traffic():
     return PAIR_TRAFFIC_BYTES
 
 
+def _open_plane_100k():
+    from scenes import open_plane_100k
+    return open_plane_100k()
+
+
+def _city_1m():
+    from scenes import city_10x10
+    return city_10x10(n_rays=1_000_000, grid=1024)
+
+
+def _city_batched():
+    from scenes import city_batched
+    return city_batched(grid=1024)
+
+
+WORKLOADS = {"open_plane_100k": ("open_plane_100k_8band", _open_plane_100k),
+             "city_1m": ("city_10x10_1m_rays_1024sq", _city_1m),
+             "city_batched": ("city_batched_16src_4band_1024sq", _city_batched)}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +98,10 @@ def parse():
     ap.add_argument("--cpu1-receivers", type=int, default=512, help="receivers of the single-thread oracle sample")
     ap.add_argument("--no-stream", action="store_true", help="skip the host-streamed table leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--workload", default="open_plane_100k", choices=sorted(WORKLOADS),
+                    help="open_plane_100k (default, the headline); city_1m: 10 x 10 city, 1,000,000 rays, "
+                         "1024 x 1024 receivers, 1 kHz; city_batched: 16 sources x 4 bands, ragged ray counts, "
+                         "replayed as a captured graph")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the steps, run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -90,11 +115,13 @@ def main():
     import torch
 
     import paper_2501_13382_amd as gbs
-    from scenes import open_plane_100k, receiver_subsample
+    from scenes import receiver_subsample
 
     dev = torch.device("cuda", 0)
     t0 = time.time()
-    sc = open_plane_100k()
+    workload_name, build = WORKLOADS[args.workload]
+    headline = args.workload == "open_plane_100k"
+    sc = build()
     table = gbs.Table(sc.table, device=dev)
     rcv = torch.as_tensor(sc.rcv, device=dev)
     freqs = torch.as_tensor(sc.freqs, device=dev)
@@ -184,6 +211,22 @@ def main():
                    "forward_plus_adjoint_ms": sec_step * 1e3 + s_adj * 1e3}
         print(f"# adjoint: {s_adj * 1e3:.2f} ms/call", file=sys.stderr, flush=True)
 
+    # the same forward captured once as a hipGraph and replayed (the lists are
+    # planned at capture: a replay re-runs records, pair kernel, reduction, TL)
+    graph = gbs.Graph(table, rcv, freqs, eps, gamma, c=sc.c, gate=sc.gate, mode=mode)
+    graph.launch()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    n_gr = max(2, args.steps // 2)
+    for _ in range(n_gr):
+        graph.launch()
+    torch.cuda.synchronize()
+    s_gr = (time.perf_counter() - t) / n_gr
+    graph_leg = {"value": dense / s_gr, "ms_per_step": s_gr * 1e3, "replays": n_gr,
+                 "note": "culled lists built at capture (fixed geometry); replays re-run records, pairs, reduce, TL"}
+    del graph
+    print(f"# graph replay: {s_gr * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+
     f64_leg = None
     if not args.no_f64:
         s64, ms64, _ = run("f64", max(2, args.steps // 2), 1)
@@ -204,13 +247,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f64 geometry+phase / f32 beam terms",
         "data": "synthetic (seeded tracer)",
-        "config": {"workload": "open_plane_100k_8band", "rays": table.n_rays, "segments": table.n_segs,
+        "config": {"workload": workload_name, "rays": table.n_rays, "segments": table.n_segs,
                    "receivers": int(len(sc.rcv)), "bands": int(len(sc.freqs)), "mode": mode,
                    "dense_pairs": dense, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": "k_pairs<MIX>", "achieved": achieved / 1e12,
                      "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
                      "frac_of_fp32_peak": achieved / PEAK_F32, "frac_of_fp64_peak": achieved / PEAK_F64,
-                     "traffic": pair_traffic(), "ms_per_launch": ms_pairs, "listed_pairs": listed, "kept_pairs": active,
+                     "traffic": pair_traffic() if headline else None, "ms_per_launch": ms_pairs, "listed_pairs": listed, "kept_pairs": active,
                      "flop_per_listed_pair": {"f64": FLOP_LISTED_F64},
                      "flop_per_kept_pair": {"f64": FLOP_KEPT_F64, "f32": FLOP_KEPT_F32}},
         "pair_kernel_share": ms_pairs / (sec_step * 1e3),
@@ -221,6 +264,7 @@ def main():
                   "culled_fraction": 1.0 - listed / dense, "kept_fraction_of_listed": active / max(listed, 1)},
         "launch": {"grid": launch["grid"], "blocks_per_cu": launch["blocks_per_cu"], "threads_per_block": 256},
         "f64": f64_leg,
+        "graph": graph_leg,
         "streamed": stream_leg,
         "adjoint": adj_leg,
     }
@@ -235,7 +279,9 @@ def main():
         del src, dst
 
     # accuracy on a seeded receiver subsample, and the oracle timed on this host
-    idx = receiver_subsample(len(sc.rcv), n=args.cpu_receivers, seed=5)
+    # about 2.5e10 oracle pairs (10-30 s on the host) at most
+    n_cpu = int(min(args.cpu_receivers, max(64, 2.5e10 / (table.n_segs * len(sc.freqs)))))
+    idx = receiver_subsample(len(sc.rcv), n=n_cpu, seed=5)
     if not args.no_cpu:
         import oracle
         oracle.build(force=False)

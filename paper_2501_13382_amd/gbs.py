@@ -290,7 +290,11 @@ class GBSFunction(torch.autograd.Function):
         if gP is not None:
             lam = lam + torch.conj(gP)
         if gTL is not None:
-            lam = lam - (20.0 / LN10) * gTL.to(P.dtype) / P
+            # TL = -20 log10|P|: dTL = -(20/ln10) Re(dP/P); receivers with P = 0
+            # (TL = inf) take no gradient
+            g = gTL.to(P.dtype)
+            lam = lam - (20.0 / LN10) * torch.where(g != 0, g / torch.where(P != 0, P, torch.ones_like(P)),
+                                                     torch.zeros_like(P))
         opts = {k: v for k, v in ctx.opts.items() if k in ("c", "gate", "mode", "chunk_segs")}
         dG, dR, dE = backward(ctx.table, rcv.detach(), ctx.freqs, eps.detach(), gamma.detach(), lam, **opts)
         g_gamma = torch.complex(dG[:, 0], dG[:, 1]).to(gamma.dtype) if ctx.needs_input_grad[0] else None

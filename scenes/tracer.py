@@ -292,6 +292,49 @@ def _box_face_id(city: City, b, axis, side, hit):
     return 1 + b * city.faces_per_box + wall * P * P + cell
 
 
+_TRACE_CHUNK = 16384
+
+
+def _nearest_box(B, p, dd, eps, best, best_box, best_axis, best_side):
+    """Slab test of rays (p, dd) against every box; updates, in place, the
+    nearest hit closer than `best` (distance, box, axis and side of entry).
+    Works on one coordinate at a time (1-D arrays are much faster to reduce)."""
+    P = [np.ascontiguousarray(p[:, j]) for j in range(3)]
+    D = [np.ascontiguousarray(dd[:, j]) for j in range(3)]
+    with np.errstate(divide="ignore"):
+        inv = [np.where(D[j] != 0, 1.0 / np.where(D[j] != 0, D[j], 1.0), np.inf) for j in range(3)]
+    par = [D[j] == 0 for j in range(3)]
+    up = D[2] > 0
+    for b in range(B.shape[0]):
+        x0, x1, y0, y1, hb = B[b]
+        lo_b = (x0, y0, 0.0)
+        hi_b = (x1, y1, hb)
+        tmin, tmax = [], []
+        with np.errstate(invalid="ignore", over="ignore"):
+            for j in range(3):
+                t1 = (lo_b[j] - P[j]) * inv[j]
+                t2 = (hi_b[j] - P[j]) * inv[j]
+                # rays parallel to a slab: inside -> (-inf, inf), outside -> empty
+                inside = (P[j] >= lo_b[j]) & (P[j] <= hi_b[j])
+                tmin.append(np.where(par[j], np.where(inside, -np.inf, np.inf), np.minimum(t1, t2)))
+                tmax.append(np.where(par[j], np.where(inside, np.inf, -np.inf), np.maximum(t1, t2)))
+        tnear = np.maximum(np.maximum(tmin[0], tmin[1]), tmin[2])
+        tfar = np.minimum(np.minimum(tmax[0], tmax[1]), tmax[2])
+        hit = (tnear <= tfar) & (tnear > eps) & (tnear < best)
+        if not np.any(hit):
+            continue
+        # entry axis: the first coordinate attaining tnear
+        axis = np.where((tmin[0] >= tmin[1]) & (tmin[0] >= tmin[2]), 0, np.where(tmin[1] >= tmin[2], 1, 2))
+        # a box is never entered from below: z = 0 is the ground
+        hit &= ~((axis == 2) & up)
+        if np.any(hit):
+            best[hit] = tnear[hit]
+            best_box[hit] = b
+            best_axis[hit] = axis[hit]
+            d_ax = np.where(axis == 0, D[0], np.where(axis == 1, D[1], D[2]))
+            best_side[hit] = np.where(d_ax > 0, 0, 1)[hit]
+
+
 def trace_city(src, dirs, weights, city: City, s_max: float, max_refl: int) -> RayTable:
     """Specular tracing among boxes and the ground plane, up to max_refl
     reflections; the path ends at arc length s_max.  Walls and roofs truncate
@@ -322,31 +365,11 @@ def trace_city(src, dirs, weights, city: City, s_max: float, max_refl: int) -> R
         tg = np.where(tg > eps, tg, np.inf)
         best = tg.copy()
         if k < max_refl:
-            inv = np.where(dd != 0, 1.0 / np.where(dd != 0, dd, 1.0), np.inf)
-            for b in range(B.shape[0]):
-                x0, x1, y0, y1, hb = B[b]
-                lo_b = np.array([x0, y0, 0.0])
-                hi_b = np.array([x1, y1, hb])
-                with np.errstate(invalid="ignore", over="ignore"):
-                    t1 = (lo_b - p) * inv
-                    t2 = (hi_b - p) * inv
-                    # rays parallel to a slab: inside -> (-inf, inf), outside -> empty
-                    par = dd == 0
-                    inside = (p >= lo_b) & (p <= hi_b)
-                    tmin = np.where(par, np.where(inside, -np.inf, np.inf), np.minimum(t1, t2))
-                    tmax = np.where(par, np.where(inside, np.inf, -np.inf), np.maximum(t1, t2))
-                tnear = tmin.max(axis=1)
-                tfar = tmax.min(axis=1)
-                axis = tmin.argmax(axis=1)
-                hit = (tnear <= tfar) & (tnear > eps) & (tnear < best)
-                # a box is never entered from below: z = 0 is the ground
-                hit &= ~((axis == 2) & (dd[:, 2] > 0))
-                if np.any(hit):
-                    best[hit] = tnear[hit]
-                    best_box[hit] = b
-                    best_axis[hit] = axis[hit]
-                    side = np.where(dd[np.arange(len(ids)), axis] > 0, 0, 1)
-                    best_side[hit] = side[hit]
+            # in chunks of rays so that the per-box temporaries stay in cache
+            for c0 in range(0, len(ids), _TRACE_CHUNK):
+                c1 = min(c0 + _TRACE_CHUNK, len(ids))
+                _nearest_box(B, p[c0:c1], dd[c0:c1], eps, best[c0:c1], best_box[c0:c1], best_axis[c0:c1],
+                             best_side[c0:c1])
         remaining = s_max - s[ids]
         ends = (best >= remaining) | (k == max_refl)
         L = np.where(ends, remaining, best)

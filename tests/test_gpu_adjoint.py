@@ -7,7 +7,7 @@ import torch
 
 import oracle
 import paper_2501_13382_amd as gbs
-from scenes import city_5x5_panels, city_scene, open_plane
+from scenes import city_5x5_panels, city_scene, open_plane, perturbed_gamma
 
 pytestmark = pytest.mark.gpu
 
@@ -100,3 +100,68 @@ def test_autograd_matches_oracle_adjoint():
     assert rel_err(gamma.grad.cpu().numpy(), rG[:, 0] + 1j * rG[:, 1]) <= 1e-9
     assert rel_err(rcv.grad.cpu().numpy(), rR) <= 1e-9
     assert rel_err(eps.grad.cpu().numpy().reshape(-1), rE) <= 1e-9
+
+
+@pytest.fixture(scope="module")
+def inversion_case():
+    """Differentiable 5 x 5 paneled city: 501 faces with their own complex
+    coefficients; the target field comes from perturbed coefficients and the
+    loss is sum over receivers outside the buildings of (TL - TL_target)^2."""
+    sc = city_5x5_panels(n_rays=20000, grid=32)
+    target_gamma = perturbed_gamma(sc.gamma, seed=4)
+    t = gbs.Table(sc.table, device="cuda")
+    freqs = torch.tensor(sc.freqs, dtype=torch.float64, device="cuda")
+    _, TLt = gbs.forward(t, sc.rcv, sc.freqs, sc.eps, target_gamma, c=sc.c, gate=sc.gate, mode="f64")
+    keep = torch.tensor(~sc.meta["inside"], device="cuda").reshape(1, 1, -1)
+    return sc, t, freqs, TLt, keep
+
+
+def _loss(sc, t, freqs, TLt, keep, gamma, mode):
+    rcv = torch.tensor(sc.rcv, dtype=torch.float64, device="cuda")
+    eps = torch.tensor(sc.eps, dtype=torch.float64, device="cuda")
+    P, TL = gbs.GBSFunction.apply(gamma, rcv, eps, t, freqs, {"mode": mode, "c": sc.c, "gate": sc.gate})
+    ok = keep & torch.isfinite(TL) & torch.isfinite(TLt)
+    return torch.where(ok, TL - TLt, torch.zeros_like(TL)).pow(2).sum(), P, TL, ok
+
+
+@pytest.mark.parametrize("mode", ["f64", "mix"])
+def test_inversion_gradient_matches_oracle(inversion_case, mode):
+    sc, t, freqs, TLt, keep = inversion_case
+    print(f"case inversion gradient {mode}", flush=True)
+    gamma = torch.tensor(sc.gamma, dtype=torch.complex128, device="cuda", requires_grad=True)
+    loss, P, TL, ok = _loss(sc, t, freqs, TLt, keep, gamma, mode)
+    loss.backward()
+    gTL = torch.where(ok, 2 * (TL - TLt), torch.zeros_like(TL)).detach().cpu().numpy().reshape(1, -1)
+    Pn = P.detach().cpu().numpy().reshape(1, -1)
+    lam = -(20 / np.log(10)) * gTL / np.where(gTL != 0, Pn, 1.0)
+    rG, _, _ = oracle.backward(sc.table, sc.gamma, sc.rcv, sc.freqs, sc.eps, lam, c=sc.c, gate=sc.gate)
+    used = np.unique(sc.table.face_ids)
+    assert len(used) > 250
+    tol = 1e-9 if mode == "f64" else 1e-3
+    assert rel_err(gamma.grad.cpu().numpy(), rG[:, 0] + 1j * rG[:, 1]) <= tol
+
+
+def test_inversion_descends(inversion_case):
+    """The negative gradient is a descent direction: a backtracking step along
+    it lowers the loss at every iteration of a short inversion."""
+    sc, t, freqs, TLt, keep = inversion_case
+    gamma = torch.tensor(sc.gamma, dtype=torch.complex128, device="cuda", requires_grad=True)
+    losses = []
+    for it in range(4):
+        gamma.grad = None
+        loss, _, _, _ = _loss(sc, t, freqs, TLt, keep, gamma, "mix")
+        loss.backward()
+        losses.append(float(loss))
+        g = gamma.grad.detach()
+        step = 0.05 / float(g.abs().max())
+        for _ in range(8):                              # backtracking
+            trial = (gamma.detach() - step * g).requires_grad_(True)
+            with torch.no_grad():
+                lt, _, _, _ = _loss(sc, t, freqs, TLt, keep, trial, "mix")
+            if float(lt) < losses[-1]:
+                break
+            step *= 0.5
+        assert float(lt) < losses[-1], (it, losses)
+        gamma = trial
+    print("case inversion losses", losses, flush=True)
+    assert losses[-1] < losses[0]
