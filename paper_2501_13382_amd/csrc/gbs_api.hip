@@ -34,9 +34,15 @@ __global__ void k_records(int64_t, const double*, const double*, const double*, 
                           const int32_t*, SegRec*);
 template <bool FILL, int NB>
 __global__ void k_cull(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int, const CullSplit*,
-                       int32_t*, const int64_t*, int32_t*);
+                       const unsigned long long*, int, int, int32_t*, const int64_t*, int32_t*);
+template <int NB>
+__global__ void k_cull_hyper(const JobConst*, const SegRec*, const Patch*, int, int, int, const CullSplit*,
+                             unsigned long long*);
 __global__ void k_item_lengths(const int64_t*, int32_t, int, int32_t*);
 __global__ void k_iota(int32_t*, int32_t);
+__global__ void k_seg_keys(int64_t, const SegRec*, const JobConst*, int32_t, int32_t, const double*,
+                           unsigned long long*, int32_t*);
+__global__ void k_permute_rec(int64_t, const SegRec*, const int32_t*, SegRec*);
 template <int MODE, int NR, bool COUNT>
 __global__ void k_pairs(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*, const int32_t*,
                         const SegRec*, const double*, const double*, const double*, const double*, double*,
@@ -50,7 +56,7 @@ __global__ void k_tl(const double*, int64_t, double*);
 template <int MODE>
 __global__ void k_adjoint(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*, const int32_t*,
                           const SegRec*, const double*, const double*, const double*, const double*, const int32_t*,
-                          int64_t, const double*, double*, double*, double*);
+                          int64_t, const double*, double*, const int32_t*, double*, double*);
 __global__ void k_reduce_adjoint(const JobConst*, const int32_t*, const int32_t*, int32_t, int32_t, const int32_t*,
                                  int64_t, const double*, double*);
 __global__ void k_sum_jobs(const double*, int32_t, int64_t, double*);
@@ -126,11 +132,13 @@ struct Workspace {
 struct RcvPlan {
     int64_t n = 0, n_pad = 0;
     int per = 0;                 // receivers per patch
-    int n_patch = 0, n_super = 0;
+    int n_patch = 0, n_super = 0, n_hyper = 0;
     double *rx = nullptr, *ry = nullptr, *rz = nullptr, *r2 = nullptr;
     int32_t* perm = nullptr;
     Patch* patches = nullptr;
     Patch* supers = nullptr;
+    Patch* hypers = nullptr;      // groups of kHyperSupers super-patches
+    const double* bbox = nullptr; // receivers' bounding box (min xyz, max xyz)
 };
 
 struct PassRange {
@@ -361,11 +369,13 @@ struct Planner {
         R.n_patch = (int)((R.n + per - 1) / per);
         R.n_pad = (int64_t)R.n_patch * per;
         R.n_super = (R.n_patch + kSuperPatches - 1) / kSuperPatches;
+        R.n_hyper = (R.n_super + kHyperSupers - 1) / kHyperSupers;
         const int nb = (int)std::min<int64_t>(1024, blocks_for(R.n, 256));
         double* part = ws.get<double>("bbox_part", 6 * nb);
         double* bbox = ws.get<double>("bbox", 6);
         hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(256), 0, st, a.rcv, R.n, part);
         hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, st, part, nb, bbox);
+        R.bbox = bbox;
         uint32_t* keys = ws.get<uint32_t>("mkeys", R.n);
         uint32_t* keys2 = ws.get<uint32_t>("mkeys2", R.n);
         int32_t* vals = ws.get<int32_t>("mvals", R.n);
@@ -388,6 +398,9 @@ struct Planner {
                            R.n_patch, R.patches);
         hipLaunchKernelGGL(k_patches, dim3(R.n_super), dim3(64), 0, st, R.rx, R.ry, R.rz, R.n_pad,
                            (int64_t)per * kSuperPatches, R.n_super, R.supers);
+        R.hypers = ws.get<Patch>("hypers", R.n_hyper);
+        hipLaunchKernelGGL(k_patches, dim3(R.n_hyper), dim3(64), 0, st, R.rx, R.ry, R.rz, R.n_pad,
+                           (int64_t)per * kSuperPatches * kHyperSupers, R.n_hyper, R.hypers);
         GBS_HIP(hipGetLastError());
     }
 
@@ -480,7 +493,9 @@ struct Planner {
         int32_t n_split = 1;      // list offsets are strided: item i spans off[i*n_split .. (i+1)*n_split]
         int64_t total = 0;
         const JobConst* jobs = nullptr;
-        const SegRec* rec = nullptr;
+        const SegRec* rec = nullptr;       // records in spatial order (what the kernels read)
+        SegRec* rec_raw = nullptr;         // records in table order (k_records writes them)
+        const int32_t* seg_perm = nullptr; // spatial position -> table position
         const int32_t* seg_ray = nullptr;
         const int64_t* item_off = nullptr;
         const int32_t* item_order = nullptr;
@@ -520,6 +535,7 @@ struct Planner {
             GBS_HIP(hipGetLastError());
         }
         L.rec = rec;
+        L.rec_raw = rec;
         L.seg_ray = seg_ray;
         std::vector<JobConst> J = job_consts(ps);
         JobConst* dJ = ws.get<JobConst>("jobs" + std::to_string(pass_idx % 2), n_jobs);
@@ -528,6 +544,27 @@ struct Planner {
         std::memcpy(h, J.data(), sizeof(JobConst) * n_jobs);
         GBS_HIP(hipMemcpyAsync(dJ, h, sizeof(JobConst) * n_jobs, hipMemcpyHostToDevice, st));
         L.jobs = dJ;
+        if (nseg > 0 && R.bbox) {
+            // spatial order of the segments (each source's range stays in place)
+            unsigned long long* k1 = ws.get<unsigned long long>("skeys", nseg);
+            unsigned long long* k2 = ws.get<unsigned long long>("skeys2", nseg);
+            int32_t* ids = ws.get<int32_t>("sids", nseg);
+            int32_t* perm = ws.get<int32_t>("seg_perm", nseg);
+            hipLaunchKernelGGL(k_seg_keys, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, nseg, rec, dJ,
+                               a.rays->n_src, a.n_freq, R.bbox, k1, ids);
+            int end_bit = 32;
+            while (end_bit < 64 && (1ll << (end_bit - 32)) < a.rays->n_src) ++end_bit;
+            size_t tmp = 0;
+            GBS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, k1, k2, ids, perm, (int)nseg, 0, end_bit, st));
+            void* t = ws.get<char>("cub_tmp_segsort", tmp);
+            GBS_HIP(hipcub::DeviceRadixSort::SortPairs(t, tmp, k1, k2, ids, perm, (int)nseg, 0, end_bit, st));
+            SegRec* rs = ws.get<SegRec>("rec_sorted", nseg);
+            hipLaunchKernelGGL(k_permute_rec, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, nseg, rec, perm, rs);
+            GBS_HIP(hipGetLastError());
+            L.rec = rs;
+            L.seg_perm = perm;
+            rec = rs;
+        }
         const int64_t n_items = (int64_t)n_jobs * R.n_patch;
         GBS_CHECK(n_items < INT32_MAX, "too many work items");
         L.n_items = (int32_t)n_items;
@@ -538,7 +575,10 @@ struct Planner {
         int64_t max_src = 0;
         for (int sidx = 0; sidx < n_src; ++sidx)
             max_src = std::max(max_src, J[sidx * n_freq].seg_end - J[sidx * n_freq].seg_begin);
-        int64_t span = std::max<int64_t>(4096, (max_src + 63) / 64);
+        // one cull wave per (super-patch, split): up to 256 splits per source,
+        // fewer when the per-split lengths would outgrow 64M counters
+        const int64_t max_split = std::max<int64_t>(1, std::min<int64_t>(256, (int64_t(1) << 26) / n_items));
+        int64_t span = std::max<int64_t>(1024, (max_src + max_split - 1) / max_split);
         span = (span + kCullThreads - 1) / kCullThreads * kCullThreads;
         const int n_split = (int)std::max<int64_t>(1, (max_src + span - 1) / span);
         std::vector<CullSplit> sv;
@@ -560,9 +600,17 @@ struct Planner {
         // up to 8 bands: band constants in wave-uniform registers
         auto cull_count = n_freq <= 8 ? k_cull<false, 8> : k_cull<false, 0>;
         auto cull_fill = n_freq <= 8 ? k_cull<true, 8> : k_cull<true, 0>;
+        auto cull_hyper = n_freq <= 8 ? k_cull_hyper<8> : k_cull_hyper<0>;
+        // level 0: which segments of each chunk may reach each hyper-patch
+        const int cps = (int)(span / kCullThreads);
+        unsigned long long* hmask =
+            ws.get<unsigned long long>("hmask", std::max<size_t>(sv.size(), 1) * cps * R.n_hyper * (kCullThreads / kWave));
         if (!sv.empty())
-            hipLaunchKernelGGL(cull_count, cg, dim3(kCullThreads), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
-                               n_freq, n_split, d_split, counts, nullptr, nullptr);
+            hipLaunchKernelGGL(cull_hyper, dim3(cps, (unsigned)sv.size()), dim3(kCullThreads), 0, st, dJ, rec,
+                               R.hypers, R.n_hyper, n_freq, cps, d_split, hmask);
+        if (!sv.empty())
+            hipLaunchKernelGGL(cull_count, cg, dim3(kWave), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
+                               n_freq, n_split, d_split, hmask, R.n_hyper, cps, counts, nullptr, nullptr);
         GBS_HIP(hipGetLastError());
         // counts are int32; accumulate in int64 through a converting iterator
         auto in64 = hipcub::TransformInputIterator<int64_t, Widen, const int32_t*>(counts, Widen());
@@ -574,8 +622,8 @@ struct Planner {
         GBS_HIP(hipStreamSynchronize(st));
         int32_t* lists = ws.get<int32_t>("lists", std::max<int64_t>(L.total, 1));
         if (!sv.empty())
-            hipLaunchKernelGGL(cull_fill, cg, dim3(kCullThreads), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
-                               n_freq, n_split, d_split, nullptr, off, lists);
+            hipLaunchKernelGGL(cull_fill, cg, dim3(kWave), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
+                               n_freq, n_split, d_split, hmask, R.n_hyper, cps, nullptr, off, lists);
         GBS_HIP(hipGetLastError());
         // longest lists first
         int32_t* lens = ws.get<int32_t>("lens", n_items);
@@ -926,7 +974,7 @@ int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
                     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, ctr);
                     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPairThreads), 0, st, L.jobs, L.work,
                                        L.n_work, pl.R.n_patch, ctr, L.lists, L.rec, pl.R.rx, pl.R.ry, pl.R.rz,
-                                       pl.R.r2, pl.R.perm, n_rcv, lambda, part, Sseg, dE);
+                                       pl.R.r2, pl.R.perm, n_rcv, lambda, part, L.seg_perm, Sseg, dE);
                     GBS_HIP(hipGetLastError());
                     hipLaunchKernelGGL(k_reduce_adjoint, dim3(blocks_for((int64_t)L.n_items * 64, 256)), dim3(256), 0,
                                        st, L.jobs, L.item_wbase, L.item_wcount, L.n_items, pl.R.n_patch, pl.R.perm,
@@ -992,7 +1040,7 @@ int gbs_graph_create(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, c
         }
         unsigned* ctr = ws.get<unsigned>("ctr", 1);
         int32_t* seg_ray = const_cast<int32_t*>(L.seg_ray);
-        SegRec* rec = const_cast<SegRec*>(L.rec);
+        SegRec* rec = L.rec_raw;
         GBS_HIP(hipStreamSynchronize(st));
         GBS_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         try {
@@ -1002,6 +1050,9 @@ int gbs_graph_create(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, c
                 hipLaunchKernelGGL(k_records, dim3(blocks_for(v.n_segs, 256)), dim3(256), 0, st, v.n_segs, v.a, v.t,
                                    v.s0, v.lo, v.hi, v.face_ptr, v.face_base, v.face_ids, faces->n_faces,
                                    faces->gamma, v.ray_w, seg_ray, rec);
+                if (L.seg_perm)   // into the spatial order planned at capture
+                    hipLaunchKernelGGL(k_permute_rec, dim3(blocks_for(v.n_segs, 256)), dim3(256), 0, st, v.n_segs,
+                                       rec, L.seg_perm, const_cast<SegRec*>(L.rec));
                 dispatch_pairs(params->mode, false, nr, ctx, st, L, pl.R, n_rcv, P, ctr, nullptr);
             }
             if (TL && n_out > 0)

@@ -9,6 +9,7 @@ namespace gbs {
 constexpr int kWave = 64;             // CDNA wavefront width
 constexpr int kCullThreads = 256;     // cull kernel workgroup (4 waves)
 constexpr int kSuperPatches = 16;     // patches per culling super-patch
+constexpr int kHyperSupers = 16;      // super-patches per culling hyper-patch (level 0)
 constexpr int kPairThreads = 256;     // pair/adjoint workgroup: 4 independent persistent waves
 constexpr int kMaxBands = 64;         // bands per call (one bit each in the cull's band masks)
 

@@ -269,6 +269,40 @@ __global__ void k_records(int64_t n_segs, const double* __restrict__ a, const do
     rec[j] = r;
 }
 
+// Spatial order of the segments of a pass: key = (source << 32) | 30-bit
+// Morton code of the beam interval's midpoint, clamped to the receivers'
+// bounding box.  Chunks of consecutive segments then reach few hyper-patches
+// together, which lets the cull skip them.  The source of segment j is found
+// from the per-job segment ranges (jobs[s * n_freq] for source s).
+__global__ void k_seg_keys(int64_t n_segs, const SegRec* __restrict__ rec, const JobConst* __restrict__ jobs,
+                           int32_t n_src, int32_t n_freq, const double* __restrict__ bbox,
+                           unsigned long long* __restrict__ keys, int32_t* __restrict__ ids) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n_segs) return;
+    const SegRec S = rec[j];
+    const double h = 0.5 * (S.slo + S.shi);
+    const double m[3] = {-0.5 * S.m2ox + h * S.tx, -0.5 * S.m2oy + h * S.ty, -0.5 * S.m2oz + h * S.tz};
+    uint32_t q[3];
+    for (int d = 0; d < 3; ++d) {
+        const double ext = bbox[3 + d] - bbox[d];
+        const double u = ext > 0 ? (m[d] - bbox[d]) / ext : 0.0;
+        q[d] = (uint32_t)fmin(fmax(u * 1023.0, 0.0), 1023.0);
+    }
+    int32_t src = 0;
+    for (int s = 0; s < n_src; ++s)
+        if (j >= jobs[(int64_t)s * n_freq].seg_begin) src = s;
+    keys[j] = ((unsigned long long)src << 32) | (spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2));
+    ids[j] = (int32_t)j;
+}
+
+// out[i] = in[perm[i]] for 96-byte segment records.
+__global__ void k_permute_rec(int64_t n, const SegRec* __restrict__ in, const int32_t* __restrict__ perm,
+                              SegRec* __restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = in[perm[i]];
+}
+
 // ------------------------------------------------------------------ culling
 // Conservative test: can the beam of segment S pass the gate for any receiver
 // inside a bounding sphere (centre C, radius rad)?  For R in the sphere, the
@@ -359,146 +393,195 @@ struct Bands<0> {
     }
 };
 
-// Two-level cull.  One workgroup per (super-patch of kSuperPatches patches,
-// split of one source's segment range).  The split is walked in chunks of
-// kCullThreads segments, each record loaded once (the next chunk's load is
-// issued before the current chunk is tested):
-//   level 1: thread t tests segment t against the super-patch sphere for
-//            every band of its source; survivors, with their records and
-//            band masks, are appended to an LDS queue in segment order;
-//   level 2: whenever the queue holds full batches of 64, wave w tests them
-//            against its patches w, w + 4, ..., band by band; the remainder
-//            waits for the next chunk (the last partial batch runs at the end).
-// List cursors stay in registers: lane b of cur[m] holds band b's cursor of
-// the wave's patch m.  The count pass leaves one length per (job, patch,
-// split); the fill pass starts every cursor at the exclusive prefix sum of
-// those lengths, so each job-patch list is the concatenation of its splits
-// in segment order: deterministic, and identical between the two passes.
-template <bool FILL, int NB>
-__global__ __launch_bounds__(kCullThreads) void k_cull(const JobConst* __restrict__ jobs,
-                                                       const SegRec* __restrict__ rec,
-                                                       const Patch* __restrict__ patches,
-                                                       const Patch* __restrict__ supers, int n_patch, int n_freq,
-                                                       int n_split, const CullSplit* __restrict__ splits,
-                                                       int32_t* __restrict__ counts,
-                                                       const int64_t* __restrict__ off,
-                                                       int32_t* __restrict__ lists) {
+// Level 0 of the cull: for every chunk of kCullThreads segments of a split
+// and every hyper-patch (kHyperSupers consecutive super-patches), a bit per
+// segment that may pass for some band.  One workgroup per chunk; mask words
+// at ((split * chunks_per_split + chunk) * n_hyper + h) * kWaves + wave.
+template <int NB>
+__global__ __launch_bounds__(kCullThreads) void k_cull_hyper(const JobConst* __restrict__ jobs,
+                                                             const SegRec* __restrict__ rec,
+                                                             const Patch* __restrict__ hypers, int n_hyper,
+                                                             int n_freq, int chunks_per_split,
+                                                             const CullSplit* __restrict__ splits,
+                                                             unsigned long long* __restrict__ hmask) {
     constexpr int kWaves = kCullThreads / kWave;
-    constexpr int kOwn = kSuperPatches / kWaves;
-    constexpr int kQ = kWave + kCullThreads;             // a partial batch plus one chunk
-    __shared__ __align__(16) CullRec q_rec[kQ];
+    const CullSplit sl = splits[blockIdx.y];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t j = sl.begin + (int64_t)blockIdx.x * kCullThreads + tid;
+    Bands<NB> B;
+    B.load(jobs, (int64_t)sl.src * n_freq, n_freq, lane);
+    CullRec me{0, 0, 0, 0, 0, 1, 1, 0};
+    const bool valid = j < sl.end;
+    if (valid) {
+        const double2* q = reinterpret_cast<const double2*>(rec + j);
+        const double2 a0 = q[0], a1 = q[1], a2 = q[2], a3 = q[3], a4 = q[4];
+        me = CullRec{-0.5 * a0.x, -0.5 * a0.y, -0.5 * a1.x, a2.x, a2.y, a3.x, a4.x, a4.y};
+    }
+    unsigned long long* out = hmask + ((int64_t)blockIdx.y * chunks_per_split + blockIdx.x) * n_hyper * kWaves;
+    for (int h = 0; h < n_hyper; ++h) {
+        const Reach r = reach(me, hypers[h]);
+        bool any = false;
+#pragma unroll
+        for (int b = 0; b < B.count(); ++b) any |= B.pass(r, b);
+        const unsigned long long bal = __ballot(valid && any);
+        if (lane == 0) out[h * kWaves + wv] = bal;
+    }
+}
+
+// Cull, levels 1 and 2.  One wave per (super-patch of kSuperPatches
+// patches, split of one source's segment range): no workgroup barriers.
+// Three queues in LDS, each in segment order, each drained in full batches
+// of 64 (a partial batch waits for the next chunk):
+//   the split is walked in chunks of 64 segments; the segments that level 0
+//   keeps for the super-patch's hyper-patch are queued by index;
+//   level 1: a batch of queued segments is loaded (one record per lane) and
+//            tested against the super-patch sphere for every band of its
+//            source; survivors, with their records and band masks, are queued;
+//   level 2: a batch of survivors is tested against the 16 patches, band by
+//            band, and appended to the (job, patch) lists.
+// The list cursors of the wave's 16 patches live in LDS between batches and
+// in lane b of one register (band b) during a patch's band loop.  The count
+// pass leaves one length per (job, patch, split); the fill pass starts every
+// cursor at the exclusive prefix sum of those lengths, so each job-patch list
+// is the concatenation of its splits in segment order: deterministic, and
+// identical between the two passes.
+template <bool FILL, int NB>
+__global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ jobs, const SegRec* __restrict__ rec,
+                                                const Patch* __restrict__ patches, const Patch* __restrict__ supers,
+                                                int n_patch, int n_freq, int n_split,
+                                                const CullSplit* __restrict__ splits,
+                                                const unsigned long long* __restrict__ hmask, int n_hyper,
+                                                int chunks_per_split, int32_t* __restrict__ counts,
+                                                const int64_t* __restrict__ off, int32_t* __restrict__ lists) {
+    constexpr int kQ = 2 * kWave;                         // a partial batch plus one more
+    constexpr int kNB = NB > 0 ? NB : kMaxBands;
+    __shared__ int32_t q1[kQ];                            // level-1 queue: segment indices
+    __shared__ __align__(16) CullRec q_rec[kQ];           // level-2 queue: records, indices, band masks
     __shared__ int32_t q_seg[kQ];
     __shared__ unsigned long long q_mask[kQ];
-    __shared__ int wave_cnt[kWaves];
+    __shared__ int64_t cur_s[kSuperPatches * kNB];        // cursor of (patch pm, band b) at pm * kNB + b
     const int sp = blockIdx.x;
     const CullSplit sl = splits[blockIdx.y];
-    const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = threadIdx.x;
     const int64_t job0 = (int64_t)sl.src * n_freq;
     Bands<NB> B;
     B.load(jobs, job0, n_freq, lane);
     const Patch SPt = supers[sp];
     const int p0 = sp * kSuperPatches;
-    Patch mine[kOwn];
-    int64_t cur[kOwn];
-#pragma unroll
-    for (int m = 0; m < kOwn; ++m) {
-        const int p = p0 + wv + kWaves * m;
-        mine[m] = p < n_patch ? patches[p] : Patch{0, 0, 0, -1};
-        cur[m] = (FILL && p < n_patch && lane < n_freq) ? off[((job0 + lane) * n_patch + p) * n_split + sl.idx] : 0;
+    for (int pm = 0; pm < kSuperPatches; ++pm) {
+        const int p = p0 + pm;
+        if (lane < n_freq)
+            cur_s[pm * kNB + lane] = (FILL && p < n_patch) ? off[((job0 + lane) * n_patch + p) * n_split + sl.idx] : 0;
     }
-    // level 2 over queue entries [base, base + n), n <= 64
-    auto level2 = [&](int base, int n) {
+    wave_lds_fence();
+    // level 2 over queue entries [0, n), n <= 64
+    auto level2 = [&](int n) {
         const bool valid = lane < n;
-        const int i = base + (valid ? lane : 0);
+        const int i = valid ? lane : 0;
         const CullRec S = q_rec[i];
         const int32_t seg = q_seg[i];
         const unsigned long long bm = valid ? q_mask[i] : 0ull;
-#pragma unroll
-        for (int m = 0; m < kOwn; ++m) {
-            if (__builtin_amdgcn_readfirstlane(mine[m].rad < 0.0 ? 1 : 0)) continue;
-            const Reach r = reach(S, mine[m]);
+        for (int pm = 0; pm < kSuperPatches; ++pm) {
+            const int p = p0 + pm;
+            if (p >= n_patch) break;
+            const Reach r = reach(S, patches[p]);
+            int64_t cur = lane < n_freq ? cur_s[pm * kNB + lane] : 0;
 #pragma unroll
             for (int b = 0; b < B.count(); ++b) {
                 const bool k2 = ((bm >> b) & 1ull) & B.pass(r, b);
                 const unsigned long long bl = __ballot(k2);
                 if (bl == 0ull) continue;
-                if (FILL && k2) lists[lane_i64(cur[m], b) + lanes_before(bl)] = seg;
-                cur[m] += lane == b ? (int64_t)__popcll(bl) : 0;
+                if (FILL && k2) lists[lane_i64(cur, b) + lanes_before(bl)] = seg;
+                cur += lane == b ? (int64_t)__popcll(bl) : 0;
             }
+            if (lane < n_freq) cur_s[pm * kNB + lane] = cur;
         }
     };
-    auto load = [&](int64_t j, CullRec& r) {
-        if (j < sl.end) {
+    int qn = 0;                                           // level-2 queue length
+    // level 1 over level-1 queue entries [0, n), n <= 64
+    auto level1 = [&](int n) {
+        const bool valid = lane < n;
+        const int32_t j = q1[valid ? lane : 0];
+        unsigned long long mask = 0ull;
+        CullRec me{0, 0, 0, 0, 0, 1, 1, 0};
+        if (valid) {
             const double2* q = reinterpret_cast<const double2*>(rec + j);
             const double2 a0 = q[0], a1 = q[1], a2 = q[2], a3 = q[3], a4 = q[4];
-            r = CullRec{-0.5 * a0.x, -0.5 * a0.y, -0.5 * a1.x, a2.x, a2.y, a3.x, a4.x, a4.y};
-        }
-    };
-    CullRec nxt{0, 0, 0, 0, 0, 1, 1, 0};
-    load(sl.begin + tid, nxt);
-    int qn = 0;                                           // queued survivors (workgroup-uniform)
-    for (int64_t c = sl.begin; c < sl.end; c += kCullThreads) {
-        const int64_t j = c + tid;
-        const CullRec me = nxt;
-        load(j + kCullThreads, nxt);
-        unsigned long long mask = 0ull;
-        if (j < sl.end) {
+            me = CullRec{-0.5 * a0.x, -0.5 * a0.y, -0.5 * a1.x, a2.x, a2.y, a3.x, a4.x, a4.y};
             const Reach r = reach(me, SPt);
 #pragma unroll
             for (int b = 0; b < B.count(); ++b) mask |= (unsigned long long)B.pass(r, b) << b;
         }
-        const bool keep = mask != 0ull;
-        const unsigned long long bal = __ballot(keep);
-        if (lane == 0) wave_cnt[wv] = __popcll(bal);
-        __syncthreads();
-        int pre = 0, tot = 0;
-        for (int w = 0; w < kWaves; ++w) {
-            pre += w < wv ? wave_cnt[w] : 0;
-            tot += wave_cnt[w];
-        }
-        if (keep) {
-            const int pos = qn + pre + lanes_before(bal);
+        const unsigned long long bal = __ballot(mask != 0ull);
+        if (bal == 0ull) return;
+        if (mask != 0ull) {
+            const int pos = qn + lanes_before(bal);
             q_rec[pos] = me;
-            q_seg[pos] = (int32_t)j;
+            q_seg[pos] = j;
             q_mask[pos] = mask;
         }
-        qn += tot;
-        __syncthreads();
+        qn += __popcll(bal);
+        wave_lds_fence();
         if (qn >= kWave) {
-            const int nb = qn / kWave, rest = qn - nb * kWave;
-            for (int k = 0; k < nb; ++k) level2(k * kWave, kWave);
+            level2(kWave);
+            const int rest = qn - kWave;                  // move the tail [64, qn) to the front
             double2 t0 = make_double2(0, 0), t1 = t0, t2 = t0, t3 = t0;
             int32_t ts = 0;
             unsigned long long tm = 0ull;
-            if (tid < rest) {                             // source [nb*64, qn) and target [0, rest) are disjoint
-                const double2* q = reinterpret_cast<const double2*>(q_rec + nb * kWave + tid);
+            if (lane < rest) {
+                const double2* q = reinterpret_cast<const double2*>(q_rec + kWave + lane);
                 t0 = q[0];
                 t1 = q[1];
                 t2 = q[2];
                 t3 = q[3];
-                ts = q_seg[nb * kWave + tid];
-                tm = q_mask[nb * kWave + tid];
+                ts = q_seg[kWave + lane];
+                tm = q_mask[kWave + lane];
             }
-            __syncthreads();
-            if (tid < rest) {
-                double2* q = reinterpret_cast<double2*>(q_rec + tid);
+            wave_lds_fence();
+            if (lane < rest) {
+                double2* q = reinterpret_cast<double2*>(q_rec + lane);
                 q[0] = t0;
                 q[1] = t1;
                 q[2] = t2;
                 q[3] = t3;
-                q_seg[tid] = ts;
-                q_mask[tid] = tm;
+                q_seg[lane] = ts;
+                q_mask[lane] = tm;
             }
-            __syncthreads();
+            wave_lds_fence();
             qn = rest;
         }
+    };
+    // level-0 bits of 64-segment chunk ci for the super-patch's hyper-patch
+    const unsigned long long* hm = hmask + (int64_t)blockIdx.y * chunks_per_split * n_hyper * 4 +
+                                   (int64_t)(sp / kHyperSupers) * 4;
+    const int n_chunks = (int)((sl.end - sl.begin + kWave - 1) / kWave);
+    int q1n = 0;                                          // level-1 queue length
+    unsigned long long bits_nxt = n_chunks > 0 ? hm[0] : 0ull;
+    for (int ci = 0; ci < n_chunks; ++ci) {
+        const unsigned long long bits = bits_nxt;
+        if (ci + 1 < n_chunks) bits_nxt = hm[(int64_t)((ci + 1) >> 2) * n_hyper * 4 + ((ci + 1) & 3)];
+        if (bits == 0ull) continue;                       // level 0 rules the whole chunk out
+        if ((bits >> lane) & 1ull) q1[q1n + lanes_before(bits)] = (int32_t)(sl.begin + (int64_t)ci * kWave + lane);
+        q1n += __popcll(bits);
+        wave_lds_fence();
+        if (q1n >= kWave) {
+            level1(kWave);
+            const int rest = q1n - kWave;
+            const int32_t t = lane < rest ? q1[kWave + lane] : 0;
+            wave_lds_fence();
+            if (lane < rest) q1[lane] = t;
+            wave_lds_fence();
+            q1n = rest;
+        }
     }
-    if (qn > 0) level2(0, qn);
+    if (q1n > 0) level1(q1n);
+    if (qn > 0) level2(qn);
     if (!FILL) {
-#pragma unroll
-        for (int m = 0; m < kOwn; ++m) {
-            const int p = p0 + wv + kWaves * m;
-            if (p < n_patch && lane < n_freq) counts[((job0 + lane) * n_patch + p) * n_split + sl.idx] = (int32_t)cur[m];
+        wave_lds_fence();
+        for (int pm = 0; pm < kSuperPatches; ++pm) {
+            const int p = p0 + pm;
+            if (p < n_patch && lane < n_freq)
+                counts[((job0 + lane) * n_patch + p) * n_split + sl.idx] = (int32_t)cur_s[pm * kNB + lane];
         }
     }
 }
@@ -997,6 +1080,7 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
                                                 const double* __restrict__ rz, const double* __restrict__ r2,
                                                 const int32_t* __restrict__ perm, int64_t n_rcv,
                                                 const double* __restrict__ lambda, double* __restrict__ partial,
+                                                const int32_t* __restrict__ seg_perm,
                                                 double* __restrict__ Sseg, double* __restrict__ d_eps) {
     __shared__ __align__(16) SegRec tile[kPairThreads / kWave][kWave];
     __shared__ int32_t tile_idx[kPairThreads / kWave][kWave];
@@ -1028,7 +1112,7 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
             const int cnt = (int)min<int64_t>(kWave, end - e0);
             wave_lds_fence();
             GBS_REC_STORE(my + lane, nx);
-            my_idx[lane] = idx_cur;
+            my_idx[lane] = seg_perm ? seg_perm[idx_cur] : idx_cur;   // table order for the segment sums
             wave_lds_fence();
             idx_cur = lists[min(e0 + kWave + lane, end - 1)];
             GBS_REC_LOAD(nx, rec, idx_cur);
@@ -1191,11 +1275,16 @@ __global__ void k_validate(int64_t n_segs, const double* __restrict__ t, const d
 // Explicit instantiations used by the host planner.
 #define GBS_INST_CULL(F, NB)                                                                                   \
     template __global__ void k_cull<F, NB>(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int, \
-                                           const CullSplit*, int32_t*, const int64_t*, int32_t*);
+                                           const CullSplit*, const unsigned long long*, int, int, int32_t*,          \
+                                           const int64_t*, int32_t*);
 GBS_INST_CULL(false, 8)
 GBS_INST_CULL(true, 8)
 GBS_INST_CULL(false, 0)
 GBS_INST_CULL(true, 0)
+template __global__ void k_cull_hyper<8>(const JobConst*, const SegRec*, const Patch*, int, int, int, const CullSplit*,
+                                         unsigned long long*);
+template __global__ void k_cull_hyper<0>(const JobConst*, const SegRec*, const Patch*, int, int, int, const CullSplit*,
+                                         unsigned long long*);
 #define GBS_INST_PAIRS(M, N, C)                                                                                  \
     template __global__ void k_pairs<M, N, C>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,    \
                                               const int32_t*, const SegRec*, const double*, const double*,       \
@@ -1208,11 +1297,11 @@ GBS_INST_PAIRS_MODE(1)
 GBS_INST_PAIRS_MODE(2)
 template __global__ void k_adjoint<0>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,
                                       const int32_t*, const SegRec*, const double*, const double*, const double*,
-                                      const double*, const int32_t*, int64_t, const double*, double*, double*,
-                                      double*);
+                                      const double*, const int32_t*, int64_t, const double*, double*,
+                                      const int32_t*, double*, double*);
 template __global__ void k_adjoint<1>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,
                                       const int32_t*, const SegRec*, const double*, const double*, const double*,
-                                      const double*, const int32_t*, int64_t, const double*, double*, double*,
-                                      double*);
+                                      const double*, const int32_t*, int64_t, const double*, double*,
+                                      const int32_t*, double*, double*);
 
 }  // namespace gbs
