@@ -597,10 +597,13 @@ struct Planner {
         if (!sv.empty())
             GBS_HIP(hipMemcpyAsync(d_split, sv.data(), sizeof(CullSplit) * sv.size(), hipMemcpyHostToDevice, st));
         dim3 cg(R.n_super, (unsigned)std::max<size_t>(sv.size(), 1));
-        // up to 8 bands: band constants in wave-uniform registers
-        auto cull_count = n_freq <= 8 ? k_cull<false, 8> : k_cull<false, 0>;
-        auto cull_fill = n_freq <= 8 ? k_cull<true, 8> : k_cull<true, 0>;
-        auto cull_hyper = n_freq <= 8 ? k_cull_hyper<8> : k_cull_hyper<0>;
+        // up to 8 bands: band constants in wave-uniform registers, as many as needed
+        auto cull_count = n_freq == 1 ? k_cull<false, 1> : n_freq <= 4 ? k_cull<false, 4>
+                        : n_freq <= 8 ? k_cull<false, 8> : k_cull<false, 0>;
+        auto cull_fill = n_freq == 1 ? k_cull<true, 1> : n_freq <= 4 ? k_cull<true, 4>
+                       : n_freq <= 8 ? k_cull<true, 8> : k_cull<true, 0>;
+        auto cull_hyper = n_freq == 1 ? k_cull_hyper<1> : n_freq <= 4 ? k_cull_hyper<4>
+                        : n_freq <= 8 ? k_cull_hyper<8> : k_cull_hyper<0>;
         // level 0: which segments of each chunk may reach each hyper-patch
         const int cps = (int)(span / kCullThreads);
         unsigned long long* hmask =

@@ -354,9 +354,9 @@ __device__ __forceinline__ int64_t lane_i64(int64_t v, int b) {
 }
 
 // Band constants of one source for the cull: kappa_b and kappa_b eps_b^2.
-// Bands<8> keeps up to 8 bands in wave-uniform registers (absent bands get
-// constants that never pass); Bands<0> takes any count up to kMaxBands with
-// band b's constants in lane b of a vector register.
+// Bands<NB> (NB = 1, 4, 8) keeps up to NB bands in wave-uniform registers
+// (absent bands get constants that never pass); Bands<0> takes any count up
+// to kMaxBands with band b's constants in lane b of a vector register.
 template <int NB>
 struct Bands {
     double kap[NB], kape[NB];
@@ -556,22 +556,30 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
                                    (int64_t)(sp / kHyperSupers) * 4;
     const int n_chunks = (int)((sl.end - sl.begin + kWave - 1) / kWave);
     int q1n = 0;                                          // level-1 queue length
-    unsigned long long bits_nxt = n_chunks > 0 ? hm[0] : 0ull;
-    for (int ci = 0; ci < n_chunks; ++ci) {
-        const unsigned long long bits = bits_nxt;
-        if (ci + 1 < n_chunks) bits_nxt = hm[(int64_t)((ci + 1) >> 2) * n_hyper * 4 + ((ci + 1) & 3)];
-        if (bits == 0ull) continue;                       // level 0 rules the whole chunk out
-        if ((bits >> lane) & 1ull) q1[q1n + lanes_before(bits)] = (int32_t)(sl.begin + (int64_t)ci * kWave + lane);
-        q1n += __popcll(bits);
-        wave_lds_fence();
-        if (q1n >= kWave) {
-            level1(kWave);
-            const int rest = q1n - kWave;
-            const int32_t t = lane < rest ? q1[kWave + lane] : 0;
+    // 64 chunks' level-0 words at a time, one per lane; only chunks with a
+    // surviving segment are visited
+    for (int cb = 0; cb < n_chunks; cb += kWave) {
+        const int cl = cb + lane;
+        const unsigned long long word = cl < n_chunks ? hm[(int64_t)(cl >> 2) * n_hyper * 4 + (cl & 3)] : 0ull;
+        unsigned long long live = __ballot(word != 0ull);
+        while (live) {
+            const int k = __builtin_ctzll(live);
+            live &= live - 1ull;
+            const unsigned long long bits = (unsigned long long)lane_i64((int64_t)word, k);
+            const int ci = cb + k;
+            if ((bits >> lane) & 1ull)
+                q1[q1n + lanes_before(bits)] = (int32_t)(sl.begin + (int64_t)ci * kWave + lane);
+            q1n += __popcll(bits);
             wave_lds_fence();
-            if (lane < rest) q1[lane] = t;
-            wave_lds_fence();
-            q1n = rest;
+            if (q1n >= kWave) {
+                level1(kWave);
+                const int rest = q1n - kWave;
+                const int32_t t = lane < rest ? q1[kWave + lane] : 0;
+                wave_lds_fence();
+                if (lane < rest) q1[lane] = t;
+                wave_lds_fence();
+                q1n = rest;
+            }
         }
     }
     if (q1n > 0) level1(q1n);
@@ -1277,14 +1285,15 @@ __global__ void k_validate(int64_t n_segs, const double* __restrict__ t, const d
     template __global__ void k_cull<F, NB>(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int, \
                                            const CullSplit*, const unsigned long long*, int, int, int32_t*,          \
                                            const int64_t*, int32_t*);
-GBS_INST_CULL(false, 8)
-GBS_INST_CULL(true, 8)
-GBS_INST_CULL(false, 0)
-GBS_INST_CULL(true, 0)
-template __global__ void k_cull_hyper<8>(const JobConst*, const SegRec*, const Patch*, int, int, int, const CullSplit*,
-                                         unsigned long long*);
-template __global__ void k_cull_hyper<0>(const JobConst*, const SegRec*, const Patch*, int, int, int, const CullSplit*,
-                                         unsigned long long*);
+#define GBS_INST_CULL_NB(NB)                                                                                   \
+    GBS_INST_CULL(false, NB)                                                                                   \
+    GBS_INST_CULL(true, NB)                                                                                    \
+    template __global__ void k_cull_hyper<NB>(const JobConst*, const SegRec*, const Patch*, int, int, int,       \
+                                              const CullSplit*, unsigned long long*);
+GBS_INST_CULL_NB(1)
+GBS_INST_CULL_NB(4)
+GBS_INST_CULL_NB(8)
+GBS_INST_CULL_NB(0)
 #define GBS_INST_PAIRS(M, N, C)                                                                                  \
     template __global__ void k_pairs<M, N, C>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,    \
                                               const int32_t*, const SegRec*, const double*, const double*,       \
