@@ -109,7 +109,8 @@ typedef struct gbs_params {
     int32_t flags;            /* GBS_FLAG_*                                      */
     int64_t chunk_segs;       /* max segments per pass; 0 = whole table          */
     int32_t rcv_per_lane;     /* pair kernel receivers per lane: 0 auto, 1, 2, 4 */
-    int32_t reserved;         /* must be 0                                       */
+    int32_t work_chunk;       /* segments per pair-kernel work unit: 0 auto, else
+                                 a power of two in [256, 65536]                 */
 } gbs_params;
 
 /* Plan statistics of the last forward/backward call on a context. */
@@ -183,13 +184,16 @@ int gbs_graph_launch(gbs_graph* g);
 void gbs_graph_destroy(gbs_graph* g);
 
 /*
- * Autotuner: times candidate pair-kernel shapes (receivers per lane) on the
- * given problem and stores the fastest in the context (used when
- * params.rcv_per_lane == 0).  Writes the choice to *rcv_per_lane if non-NULL.
+ * Autotuner (spec extension; the paper has none): times the forward on
+ * the given problem for every candidate pair-kernel shape (receivers per
+ * lane 1, 2, 4) and work-unit size (1024, 2048, 4096 segments) and stores the
+ * fastest in the context for `params.mode`; later calls with rcv_per_lane or
+ * work_chunk 0 use it.  Writes the choice to *rcv_per_lane and *work_chunk
+ * when non-NULL.  P [n_src*n_freq*n_rcv*2] is scratch output.
  */
 int gbs_autotune(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces,
                  const double* rcv, int64_t n_rcv, const double* freqs, int32_t n_freq, const double* eps,
-                 const gbs_params* params, double* P, int32_t* rcv_per_lane);
+                 const gbs_params* params, double* P, int32_t* rcv_per_lane, int32_t* work_chunk);
 
 /* Message describing the last error on ctx (never NULL). */
 const char* gbs_last_error(const gbs_ctx* ctx);

@@ -43,7 +43,7 @@ class GbsFaces(ctypes.Structure):
 
 class GbsParams(ctypes.Structure):
     _fields_ = [("c", c_double), ("gate_G", c_double), ("mode", c_int32), ("flags", c_int32),
-                ("chunk_segs", c_int64), ("rcv_per_lane", c_int32), ("reserved", c_int32)]
+                ("chunk_segs", c_int64), ("rcv_per_lane", c_int32), ("work_chunk", c_int32)]
 
 
 class GbsStats(ctypes.Structure):
@@ -96,7 +96,7 @@ def load() -> ctypes.CDLL:
     lib.gbs_graph_launch.restype = ctypes.c_int
     lib.gbs_graph_destroy.argtypes = [c_void_p]
     lib.gbs_graph_destroy.restype = None
-    lib.gbs_autotune.argtypes = common + [c_void_p, P(c_int32)]
+    lib.gbs_autotune.argtypes = common + [c_void_p, P(c_int32), P(c_int32)]
     lib.gbs_autotune.restype = ctypes.c_int
     lib.gbs_last_error.argtypes = [c_void_p]
     lib.gbs_last_error.restype = ctypes.c_char_p

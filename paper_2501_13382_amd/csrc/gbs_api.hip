@@ -154,7 +154,8 @@ struct gbs_ctx {
     std::string err;
     gbs_stats stats{};
     std::unique_ptr<Workspace> ws{new Workspace};
-    int tuned_nr[3] = {0, 0, 0};
+    int tuned_nr[3] = {0, 0, 0};      // per mode, 0 = not tuned
+    int tuned_chunk[3] = {0, 0, 0};
     void* pinned = nullptr;
     size_t pinned_cap = 0;
     // streaming of host-resident tables: pass i+1 is copied on copy_stream
@@ -238,7 +239,9 @@ void validate_host(const Args& a) {
     GBS_CHECK(p.chunk_segs >= 0, "params.chunk_segs must be >= 0");
     GBS_CHECK(p.rcv_per_lane == 0 || p.rcv_per_lane == 1 || p.rcv_per_lane == 2 || p.rcv_per_lane == 4,
               "params.rcv_per_lane must be 0, 1, 2 or 4");
-    GBS_CHECK(p.reserved == 0, "params.reserved must be 0");
+    GBS_CHECK(p.work_chunk == 0 || (p.work_chunk >= 256 && p.work_chunk <= 65536 &&
+                                    (p.work_chunk & (p.work_chunk - 1)) == 0),
+              "params.work_chunk must be 0 or a power of two in [256, 65536]");
     GBS_CHECK(a.rays->n_src >= 0 && a.rays->n_rays >= 0 && a.segs->n_segs >= 0 && a.n_rcv >= 0 && a.n_freq >= 0,
               "negative size");
     GBS_CHECK(a.faces->n_faces >= 0, "negative face count");
@@ -280,6 +283,13 @@ struct Planner {
     }
 
     bool table_host() const { return (a.params->flags & GBS_FLAG_TABLE_HOST) != 0; }
+    int chunk_override = 0;   // autotuner candidate
+    int work_chunk() const {
+        if (chunk_override) return chunk_override;
+        if (a.params->work_chunk) return a.params->work_chunk;
+        if (ctx->tuned_chunk[a.params->mode]) return ctx->tuned_chunk[a.params->mode];
+        return kWorkChunk;
+    }
 
     void read_job_inputs() {
         h_freqs.resize(a.n_freq);
@@ -642,13 +652,14 @@ struct Planner {
         void* t2 = ws.get<char>("cub_tmp_order", tmp2);
         GBS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(t2, tmp2, lens, keys2, ids, order, (int)n_items, 0, 32,
                                                              st));
-        // work units: every list cut into chunks of at most kWorkChunk segments
-        const int64_t cap = n_items + L.total / kWorkChunk + 1;
+        // work units: every list cut into chunks of at most `chunk` segments
+        const int chunk = work_chunk();
+        const int64_t cap = n_items + L.total / chunk + 1;
         GBS_CHECK(cap < INT32_MAX, "too many work units");
         int32_t* nw = ws.get<int32_t>("nwork", n_items + 1);
         int32_t* wb = ws.get<int32_t>("wbase", n_items + 1);
         hipLaunchKernelGGL(k_work_counts, dim3(blocks_for(n_items + 1, 256)), dim3(256), 0, st, order, lens,
-                           (int32_t)n_items, kWorkChunk, nw);
+                           (int32_t)n_items, chunk, nw);
         size_t tmp3 = 0;
         GBS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp3, nw, wb, (int)(n_items + 1), st));
         void* t3 = ws.get<char>("cub_tmp_work", tmp3);
@@ -658,7 +669,7 @@ struct Planner {
         int32_t* iwc = ws.get<int32_t>("item_wcount", n_items);
         int32_t* n_work = ws.get<int32_t>("n_work", 1);
         hipLaunchKernelGGL(k_make_work, dim3(blocks_for(n_items, 256)), dim3(256), 0, st, order, off, n_split, wb,
-                           (int32_t)n_items, kWorkChunk, work, iwb, iwc, n_work);
+                           (int32_t)n_items, chunk, work, iwb, iwc, n_work);
         GBS_HIP(hipGetLastError());
         L.work = work;
         L.n_work = n_work;
@@ -774,11 +785,13 @@ void ensure_copy_stream(gbs_ctx* ctx) {
     ctx->ws->copy_stream = ctx->copy_stream;
 }
 
-int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* TL, int nr_override) {
+int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* TL, int nr_override,
+                 int chunk_override = 0) {
     validate_host(a);
     GBS_CHECK(P || (int64_t)a.rays->n_src * a.n_freq * a.n_rcv == 0, "null P");
     const int nr = nr_override ? nr_override : pick_nr(ctx, a.params, a.n_rcv);
     Planner pl(ctx, ws, a, nr);
+    pl.chunk_override = chunk_override;
     hipStream_t st = ctx->stream;
     const int64_t n_out = (int64_t)pl.n_jobs * a.n_rcv;
     pl.read_job_inputs();
@@ -1093,34 +1106,34 @@ void gbs_graph_destroy(gbs_graph* g) {
 
 int gbs_autotune(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces,
                  const double* rcv, int64_t n_rcv, const double* freqs, int32_t n_freq, const double* eps,
-                 const gbs_params* params, double* P, int32_t* rcv_per_lane) {
+                 const gbs_params* params, double* P, int32_t* rcv_per_lane, int32_t* work_chunk) {
     if (!ctx) return GBS_E_INVALID;
     return guarded(ctx, [&]() {
         GBS_HIP(hipSetDevice(ctx->device));
         Args a{rays, segs, faces, rcv, n_rcv, freqs, n_freq, eps, params};
         validate_host(a);
-        hipEvent_t e0, e1;
-        GBS_HIP(hipEventCreate(&e0));
-        GBS_HIP(hipEventCreate(&e1));
+        EventPair ev(true);
         float best = 1e30f;
-        int best_nr = 1;
-        for (int nr : {1, 2, 4}) {
-            forward_impl(ctx, *ctx->ws, a, P, nullptr, nr);  // warm-up and plan
-            GBS_HIP(hipEventRecord(e0, ctx->stream));
-            forward_impl(ctx, *ctx->ws, a, P, nullptr, nr);
-            GBS_HIP(hipEventRecord(e1, ctx->stream));
-            GBS_HIP(hipEventSynchronize(e1));
-            float ms = 0;
-            GBS_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
-                best = ms;
-                best_nr = nr;
+        int best_nr = 1, best_chunk = kWorkChunk;
+        for (int nr : {1, 2, 4})
+            for (int chunk : {1024, 2048, 4096}) {
+                forward_impl(ctx, *ctx->ws, a, P, nullptr, nr, chunk);  // warm-up and plan
+                float ms = 1e30f;
+                for (int rep = 0; rep < 2; ++rep) {                       // best of two
+                    ev.begin(ctx->stream);
+                    forward_impl(ctx, *ctx->ws, a, P, nullptr, nr, chunk);
+                    ms = std::min(ms, (float)ev.end(ctx->stream));
+                }
+                if (ms < best) {
+                    best = ms;
+                    best_nr = nr;
+                    best_chunk = chunk;
+                }
             }
-        }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
         ctx->tuned_nr[params->mode] = best_nr;
+        ctx->tuned_chunk[params->mode] = best_chunk;
         if (rcv_per_lane) *rcv_per_lane = best_nr;
+        if (work_chunk) *work_chunk = best_chunk;
         return GBS_OK;
     });
 }

@@ -7,6 +7,8 @@ stream, and shapes the outputs.  Torch is used for memory and streams only.
 from __future__ import annotations
 
 import ctypes
+import json
+import os
 import math
 
 import numpy as np
@@ -127,17 +129,25 @@ def _gamma_ri(gamma, device):
     return g.contiguous()
 
 
-def _params(c, gate, mode, flags, chunk_segs, rcv_per_lane):
+# Shapes chosen by autotune() (or read from its JSON cache), per (device, mode);
+# used where a call leaves rcv_per_lane / work_chunk at 0.
+_TUNED = {}
+
+
+def _params(c, gate, mode, flags, chunk_segs, rcv_per_lane, work_chunk, device):
     if mode not in _lib.MODES:
         raise ValueError(f"mode must be one of {sorted(_lib.MODES)}")
-    return _lib.GbsParams(float(c), float(gate), _lib.MODES[mode], int(flags), int(chunk_segs), int(rcv_per_lane), 0)
+    tuned = _TUNED.get((_device_index(device), mode), {})
+    nr = int(rcv_per_lane) or int(tuned.get("rcv_per_lane", 0))
+    wc = int(work_chunk) or int(tuned.get("work_chunk", 0))
+    return _lib.GbsParams(float(c), float(gate), _lib.MODES[mode], int(flags), int(chunk_segs), nr, wc)
 
 
 class _Call:
     """Marshalled arguments of one forward/backward call."""
 
     def __init__(self, table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, validate,
-                 count_active, time_kernels=False):
+                 count_active, time_kernels=False, work_chunk=0):
         if not isinstance(table, Table):
             raise TypeError("table must be a gbs.Table")
         dev = table.device
@@ -152,7 +162,7 @@ class _Call:
             raise ValueError("gamma must hold one coefficient per face")
         flags = (_lib.FLAG_TABLE_HOST if table.on_host else 0) | (_lib.FLAG_VALIDATE if validate else 0) | \
             (_lib.FLAG_COUNT_ACTIVE if count_active else 0) | (_lib.FLAG_TIME_KERNELS if time_kernels else 0)
-        self.params = _params(c, gate, mode, flags, chunk_segs, rcv_per_lane)
+        self.params = _params(c, gate, mode, flags, chunk_segs, rcv_per_lane, work_chunk, dev)
         self.rays, self.segs = table.structs()
         self.faces = _lib.GbsFaces(table.n_faces, _ptr(self.gamma))
         self.n_rcv = int(self.rcv.shape[0])
@@ -165,14 +175,14 @@ class _Call:
 
 
 def forward(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix", chunk_segs=0,
-            rcv_per_lane=0, validate=False, count_active=False, time_kernels=False, want_tl=True):
+            rcv_per_lane=0, work_chunk=0, validate=False, count_active=False, time_kernels=False, want_tl=True):
     """Beam summation.  Returns (P complex128 [n_src, n_freq, n_rcv],
     TL float64 of the same shape or None).  count_active / time_kernels fill
     the statistics returned by stats()."""
     ctx = context(table.device)
     ctx.bind_stream()
     call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, validate, count_active,
-                 time_kernels)
+                 time_kernels, work_chunk)
     P = torch.empty(call.shape + (2,), dtype=torch.float64, device=table.device)
     TL = torch.empty(call.shape, dtype=torch.float64, device=table.device) if want_tl else None
     rc = ctx.lib.gbs_forward(*call.common(ctx), _ptr(P), _ptr(TL))
@@ -198,17 +208,44 @@ def backward(table: Table, rcv, freqs, eps, gamma, lam, *, c=343.0, gate=9.21, m
     return d_gamma, d_rcv, d_eps
 
 
-def autotune(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix"):
-    """Times the pair-kernel shapes on this problem; later calls in `mode`
-    with rcv_per_lane=0 use the fastest.  Returns the chosen receivers/lane."""
+def _tune_key(table: Table, call, mode: str) -> str:
+    """Cache key: GPU architecture, mode and a size bucket of the problem
+    (log2 of the dense pair count, bands, sources)."""
+    arch = torch.cuda.get_device_properties(table.device).gcnArchName.split(":")[0]
+    dense = max(1, table.n_segs * call.n_rcv * call.n_freq)
+    return f"{arch}|{mode}|2^{int(math.log2(dense))}|bands{call.n_freq}|src{table.n_src}"
+
+
+def autotune(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix", cache=None):
+    """Times the pair-kernel shapes (receivers per lane x work-unit size) on
+    this problem; later calls in `mode` that leave rcv_per_lane / work_chunk
+    at 0 use the fastest.  With `cache` (a JSON file path) a stored choice for
+    the same architecture, mode and size bucket is reused without timing, and
+    a new one is stored.  Returns {"rcv_per_lane": .., "work_chunk": ..}."""
     ctx = context(table.device)
     ctx.bind_stream()
     call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, 0, 0, False, False)
+    key = _tune_key(table, call, mode)
+    store = {}
+    if cache is not None and os.path.exists(cache):
+        with open(cache) as f:
+            store = json.load(f)
+        if key in store:
+            _TUNED[(_device_index(table.device), mode)] = dict(store[key])
+            return dict(store[key])
     P = torch.empty(call.shape + (2,), dtype=torch.float64, device=table.device)
-    out = ctypes.c_int32(0)
-    rc = ctx.lib.gbs_autotune(*call.common(ctx), _ptr(P), ctypes.byref(out))
+    nr, wc = ctypes.c_int32(0), ctypes.c_int32(0)
+    rc = ctx.lib.gbs_autotune(*call.common(ctx), _ptr(P), ctypes.byref(nr), ctypes.byref(wc))
     _lib.check(rc, ctx.handle)
-    return int(out.value)
+    choice = {"rcv_per_lane": int(nr.value), "work_chunk": int(wc.value)}
+    _TUNED[(_device_index(table.device), mode)] = choice
+    if cache is not None:
+        store[key] = choice
+        tmp = f"{cache}.tmp{os.getpid()}"
+        with open(tmp, "w") as f:
+            json.dump(store, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return dict(choice)
 
 
 def stats(device="cuda") -> dict:

@@ -7,6 +7,10 @@ configuration.  Tolerances (relative complex error, |dTL|) per mode are in
 gpu_util.TOL: F64 1e-9 / 1e-6 dB, MIX 1e-4 / 0.05 dB, F32 - / 0.2 dB; TL is
 compared where the sum is not cancelled beyond sum|u| / |P| <= 1e4.
 """
+import json
+import os
+import tempfile
+
 import numpy as np
 import pytest
 import torch
@@ -230,11 +234,21 @@ def test_autotune_picks_a_valid_shape_and_results_agree(city_small):
     calls with the automatic shape give the same field."""
     sc, (P_ref, TL_ref, ab) = city_small
     t = gbs.Table(sc.table, device="cuda")
-    nr = gbs.autotune(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, c=sc.c, gate=sc.gate, mode="f64")
-    assert nr in (1, 2, 4)
+    cache = os.path.join(tempfile.mkdtemp(), "tune.json")
+    choice = gbs.autotune(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, c=sc.c, gate=sc.gate, mode="f64", cache=cache)
+    assert choice["rcv_per_lane"] in (1, 2, 4) and choice["work_chunk"] in (1024, 2048, 4096)
     P, TL = gbs.forward(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, c=sc.c, gate=sc.gate, mode="f64")
-    assert gbs.stats()["patch_rcv"] == 64 * nr
+    assert gbs.stats()["patch_rcv"] == 64 * choice["rcv_per_lane"]
     assert_within(compare(P.cpu().numpy(), TL.cpu().numpy(), P_ref, TL_ref, ab), "f64")
+    # the JSON cache answers the same question without timing again
+    with open(cache) as f:
+        assert list(json.load(f).values()) == [choice]
+    assert gbs.autotune(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, c=sc.c, gate=sc.gate, mode="f64",
+                        cache=cache) == choice
+    # every work-unit size gives the same field to rounding
+    for wc in (256, 1024, 65536):
+        P2, _ = gbs.forward(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, c=sc.c, gate=sc.gate, mode="f64", work_chunk=wc)
+        assert np.max(np.abs(P2.cpu().numpy() - P.cpu().numpy()) / np.maximum(np.abs(P.cpu().numpy()), 1e-300)) <= 1e-11
 
 
 def test_stats_are_consistent(city_small):
