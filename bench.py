@@ -286,6 +286,7 @@ def main():
         import oracle
         oracle.build(force=False)
         threads = int(os.environ.get("OMP_NUM_THREADS", str(min(16, os.cpu_count() or 1))))
+        print(f"# oracle, {threads} threads, {len(idx)} receivers", file=sys.stderr, flush=True)
         t = time.perf_counter()
         P_ref, TL_ref, ab = oracle.scene_forward(sc, rcv=sc.rcv[idx], n_threads=threads, return_absum=True)
         el = time.perf_counter() - t
@@ -295,15 +296,18 @@ def main():
                                             f"{table.n_segs} segments, {len(sc.freqs)} bands; {el:.1f}s",
                                   "extrapolated_full_config_s": dense / (pairs / el)}
         if args.cpu1_receivers > 0:
-            idx1 = receiver_subsample(len(sc.rcv), n=args.cpu1_receivers, seed=6)
+            # about 8e8 oracle pairs (a few seconds on one core) at most
+            n1 = int(min(args.cpu1_receivers, max(8, 8e8 / (table.n_segs * len(sc.freqs)))))
+            print(f"# oracle, 1 thread, {n1} receivers", file=sys.stderr, flush=True)
+            idx1 = receiver_subsample(len(sc.rcv), n=n1, seed=6)
             t = time.perf_counter()
             oracle.scene_forward(sc, rcv=sc.rcv[idx1], n_threads=1)
             el1 = time.perf_counter() - t
             result["cpu_baseline"]["single_thread"] = {
                 "value": table.n_segs * len(idx1) * len(sc.freqs) / el1, "cores": 1,
                 "sample": f"{len(idx1)} receivers (seed 6); {el1:.1f}s"}
-        Pg = P.cpu().numpy().reshape(len(sc.freqs), -1)[:, idx]
-        TLg = TL.cpu().numpy().reshape(len(sc.freqs), -1)[:, idx]
+        Pg = P.cpu().numpy().reshape(-1, len(sc.rcv))[:, idx]
+        TLg = TL.cpu().numpy().reshape(-1, len(sc.rcv))[:, idx]
         mag = np.abs(P_ref)
         ok = ab / np.maximum(mag, 1e-300) <= 1e4
         dtl = np.abs(TLg - TL_ref)[ok]

@@ -151,7 +151,7 @@ def test_inversion_descends(inversion_case):
         gamma.grad = None
         loss, _, _, _ = _loss(sc, t, freqs, TLt, keep, gamma, "mix")
         loss.backward()
-        losses.append(float(loss))
+        losses.append(float(loss.detach()))
         g = gamma.grad.detach()
         step = 0.05 / float(g.abs().max())
         for _ in range(8):                              # backtracking
