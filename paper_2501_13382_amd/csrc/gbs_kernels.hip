@@ -1007,69 +1007,91 @@ __device__ __forceinline__ void adj_factors(T s, T n2, T rden, T eps, T k, AdjTe
     A.dei = iq_r - hk * iq2_i;
 }
 
+// Receiver gradient of one pair: gt t + gn nvec with nvec = R - o - s t
+// = (gt - gn s) t + gn R + gn (-2 o) / 2.  Per receiver the kernel sums
+// V = sum (gt - gn s) t, W = sum gn (-2 o) and G = sum gn, and writes
+// dL/dR = V + W / 2 + G R once per work unit: 7 FMAs per pair instead of
+// forming nvec (the cancellation costs about two of FP64's 16 digits).
+struct AdjAcc {
+    double vx, vy, vz, wx, wy, wz, g, e;   // V, W, G and dL/deps
+};
+
 template <int MODE, typename ST>
-__device__ __forceinline__ bool adj_eval(const SegRec& S, const JobConst& J, double X, double Y, double Z, double R2,
-                                         double lr, double li, double& dRx, double& dRy, double& dRz, double& dE,
-                                         ST& Sr, ST& Si) {
-    double s = fma(X, S.tx, fma(Y, S.ty, fma(Z, S.tz, S.mot)));
-    double l = fma(X, S.m2ox, fma(Y, S.m2oy, fma(Z, S.m2oz, R2)));
-    double rhs = fma(s * J.gate_c1, s, J.gate_c2 - S.oo);
-    const bool keep = l <= rhs && s >= S.slo && s < S.shi;
+__device__ __forceinline__ bool adj_eval(const TileRec& S, const JobConst& J, double X, double Y, double Z, double R2,
+                                         ST lr, ST li, AdjAcc& acc, ST& Sr, ST& Si) {
+    Beam<kF64>::Geo g;
+    const bool keep = Beam<kF64>::gate(S, J, X, Y, Z, R2, g);
     if (__ballot(keep) == 0ull) return false;    // wave-uniform skip
     branch_barrier();
     if (!keep) return false;
-    double n2 = fma(-s, s, l + S.oo);
-    double den = fma(s, s, J.eps2);
+    const double s = g.s;
+    const double n2 = fma(-s, s, g.l + S.oo);
+    const double den = fma(s, s, J.eps2);
     double rden;
+    float r0f = 0.f;
     if (MODE == kF64) {
         rden = 1.0 / den;
     } else {
-        const double r0 = (double)__builtin_amdgcn_rcpf((float)den);
-        rden = fma(r0, fma(-den, r0, 1.0), r0);                      // one Newton step
+        r0f = __builtin_amdgcn_rcpf((float)den);
+        const double r0 = (double)r0f;
+        rden = fma(r0, fma(-den, r0, 1.0), r0);                    // one Newton step
     }
-    double cyc = fma(n2 * s, rden * J.hfk, s * J.fk);
-    double ph = cyc - floor(cyc);
-    // normal vector R - o - s t  (o = -m2o / 2)
-    double nx = X + 0.5 * S.m2ox - s * S.tx, ny = Y + 0.5 * S.m2oy - s * S.ty, nz = Z + 0.5 * S.m2oz - s * S.tz;
+    const double a = n2 * rden;
+    const double cyc = s * fma(J.hfk, a, J.fk);
+    double gt, gn;
     if (MODE == kF64) {
+        const double ph = cyc - floor(cyc);
         double sn, cs;
         sincospi(2.0 * ph, &sn, &cs);
-        double w = rden * exp(n2 * rden * J.gexp);
+        const double w = rden * exp(a * J.gexp);
         AdjTerms<double> A;
         adj_factors<double>(s, n2, rden, J.eps, J.k, A);
-        double br = s * w, bi = J.eps * w;                  // (s + i eps) rden e^g
+        const double br = s * w, bi = J.eps * w;                  // (s + i eps) rden e^g
         A.Br = br * cs - bi * sn;
         A.Bi = br * sn + bi * cs;
-        double ur = S.wgr * A.Br - S.wgi * A.Bi, ui = S.wgr * A.Bi + S.wgi * A.Br;
-        double vr = lr * ur - li * ui, vi = lr * ui + li * ur;    // lambda u
-        double gt = vr * A.ctr - vi * A.cti, gn = vr * A.cnr - vi * A.cni;
-        dRx += gt * S.tx + gn * nx;
-        dRy += gt * S.ty + gn * ny;
-        dRz += gt * S.tz + gn * nz;
-        dE += vr * A.der - vi * A.dei;
+        const double ur = S.wgr * A.Br - S.wgi * A.Bi, ui = S.wgr * A.Bi + S.wgi * A.Br;
+        const double vr = lr * ur - li * ui, vi = lr * ui + li * ur;    // lambda u
+        gt = vr * A.ctr - vi * A.cti;
+        gn = vr * A.cnr - vi * A.cni;
+        acc.e += vr * A.der - vi * A.dei;
         Sr += lr * A.Br - li * A.Bi;
         Si += lr * A.Bi + li * A.Br;
     } else {
-        float phf = (float)ph;
-        float sn = __builtin_amdgcn_sinf(phf), cs = __builtin_amdgcn_cosf(phf);
-        float rdf = (float)rden;
-        float w = rdf * __builtin_amdgcn_exp2f((float)n2 * rdf * (float)J.gexp2);
+        const float ph = (float)__builtin_amdgcn_fract(cyc);
+        const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
+        const float w = r0f * __builtin_amdgcn_exp2f((float)(a * J.gexp2));
+        const float sf = (float)s, epsf = (float)J.eps;
         AdjTerms<float> A;
-        adj_factors<float>((float)s, (float)n2, rdf, (float)J.eps, (float)J.k, A);
-        float br = (float)s * w, bi = (float)J.eps * w;
+        adj_factors<float>(sf, (float)n2, r0f, epsf, (float)J.k, A);
+        const float br = sf * w, bi = epsf * w;
         A.Br = br * cs - bi * sn;
         A.Bi = br * sn + bi * cs;
-        float gr = (float)S.wgr, gi = (float)S.wgi, lrf = (float)lr, lif = (float)li;
-        float ur = gr * A.Br - gi * A.Bi, ui = gr * A.Bi + gi * A.Br;
-        float vr = lrf * ur - lif * ui, vi = lrf * ui + lif * ur;
-        float gt = vr * A.ctr - vi * A.cti, gn = vr * A.cnr - vi * A.cni;
-        dRx += (double)gt * S.tx + (double)gn * nx;
-        dRy += (double)gt * S.ty + (double)gn * ny;
-        dRz += (double)gt * S.tz + (double)gn * nz;
-        dE += (double)(vr * A.der - vi * A.dei);
-        Sr += lrf * A.Br - lif * A.Bi;
-        Si += lrf * A.Bi + lif * A.Br;
+        const float4 Wg = tile_weights(S);                       // (w Gamma, eps w Gamma) as FP32
+        const float ur = Wg.x * A.Br - Wg.y * A.Bi, ui = Wg.x * A.Bi + Wg.y * A.Br;
+        const float vr = lr * ur - li * ui, vi = lr * ui + li * ur;
+        const float gtf = vr * A.ctr - vi * A.cti, gnf = vr * A.cnr - vi * A.cni;
+        const double c = (double)fmaf(-gnf, sf, gtf);            // gt - gn s
+        gn = (double)gnf;
+        acc.e += (double)(vr * A.der - vi * A.dei);
+        Sr += lr * A.Br - li * A.Bi;
+        Si += lr * A.Bi + li * A.Br;
+        acc.vx = fma(c, S.tx, acc.vx);
+        acc.vy = fma(c, S.ty, acc.vy);
+        acc.vz = fma(c, S.tz, acc.vz);
+        acc.wx = fma(gn, S.m2ox, acc.wx);
+        acc.wy = fma(gn, S.m2oy, acc.wy);
+        acc.wz = fma(gn, S.m2oz, acc.wz);
+        acc.g += gn;
+        return true;
     }
+    const double c = fma(-gn, s, gt);
+    acc.vx = fma(c, S.tx, acc.vx);
+    acc.vy = fma(c, S.ty, acc.vy);
+    acc.vz = fma(c, S.tz, acc.vz);
+    acc.wx = fma(gn, S.m2ox, acc.wx);
+    acc.wy = fma(gn, S.m2oy, acc.wy);
+    acc.wz = fma(gn, S.m2oz, acc.wz);
+    acc.g += gn;
     return true;
 }
 
@@ -1090,11 +1112,12 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
                                                 const double* __restrict__ lambda, double* __restrict__ partial,
                                                 const int32_t* __restrict__ seg_perm,
                                                 double* __restrict__ Sseg, double* __restrict__ d_eps) {
-    __shared__ __align__(16) SegRec tile[kPairThreads / kWave][kWave];
+    __shared__ __align__(16) TileRec tile[kPairThreads / kWave][kWave];
     __shared__ int32_t tile_idx[kPairThreads / kWave][kWave];
     const int lane = threadIdx.x & (kWave - 1);
-    SegRec* const my = tile[threadIdx.x / kWave];
+    TileRec* const my = tile[threadIdx.x / kWave];
     int32_t* const my_idx = tile_idx[threadIdx.x / kWave];
+    using ST = typename Beam<MODE>::T;                    // beam-term precision
     const int n_work = __builtin_amdgcn_readfirstlane(*n_work_p);
     for (;;) {
         branch_barrier();
@@ -1107,28 +1130,27 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
         const int64_t i = (int64_t)patch * 64 + lane;
         const double X = rx[i], Y = ry[i], Z = rz[i], R2 = r2[i];
         const int32_t o = perm[i];
-        double lr = 0.0, li = 0.0;
+        ST lr = 0, li = 0;
         if (o >= 0) {
-            lr = lambda[2 * ((int64_t)job * n_rcv + o)];
-            li = lambda[2 * ((int64_t)job * n_rcv + o) + 1];
+            lr = (ST)lambda[2 * ((int64_t)job * n_rcv + o)];
+            li = (ST)lambda[2 * ((int64_t)job * n_rcv + o) + 1];
         }
-        double dRx = 0, dRy = 0, dRz = 0, dE = 0;
+        AdjAcc acc{0, 0, 0, 0, 0, 0, 0, 0};
         GBS_REC_REGS(nx);
         int32_t idx_cur = lists[min(beg + lane, end - 1)];
         GBS_REC_LOAD(nx, rec, idx_cur);
         for (int64_t e0 = beg; e0 < end; e0 += kWave) {
             const int cnt = (int)min<int64_t>(kWave, end - e0);
             wave_lds_fence();
-            GBS_REC_STORE(my + lane, nx);
+            GBS_STAGE(MODE, my + lane, nx, J);
             my_idx[lane] = seg_perm ? seg_perm[idx_cur] : idx_cur;   // table order for the segment sums
             wave_lds_fence();
             idx_cur = lists[min(e0 + kWave + lane, end - 1)];
             GBS_REC_LOAD(nx, rec, idx_cur);
             for (int k = 0; k < cnt; ++k) {
-                const SegRec S = my[k];
-                using ST = typename Beam<MODE>::T;        // per-segment sums in the beam-term precision
+                const TileRec S = my[k];
                 ST Sr = 0, Si = 0;
-                const bool hit = adj_eval<MODE>(S, J, X, Y, Z, R2, lr, li, dRx, dRy, dRz, dE, Sr, Si);
+                const bool hit = adj_eval<MODE>(S, J, X, Y, Z, R2, lr, li, acc, Sr, Si);
                 if (__ballot(hit) != 0ull) {
                     Sr = wave_sum_last(Sr);
                     Si = wave_sum_last(Si);
@@ -1141,10 +1163,10 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
             }
         }
         double* p = partial + 3 * ((int64_t)w * kWave + lane);
-        p[0] = dRx;
-        p[1] = dRy;
-        p[2] = dRz;
-        dE = wave_sum_last(dE);
+        p[0] = fma(acc.g, X, fma(0.5, acc.wx, acc.vx));
+        p[1] = fma(acc.g, Y, fma(0.5, acc.wy, acc.vy));
+        p[2] = fma(acc.g, Z, fma(0.5, acc.wz, acc.vz));
+        const double dE = wave_sum_last(acc.e);
         if (lane == kLastLane) atomicAdd(&d_eps[job], J.scale * dE);
     }
 }
