@@ -52,9 +52,9 @@ PEAK_F32 = 157.3e12
 # FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy and fill (the summary in
 # profiles/k_pairs_mix_open_plane_100k.md).  Valid only for the kernel source
 # it was measured on; reported as null once that source changes.
-PAIR_TRAFFIC_BYTES = 2.984e9
-PAIR_TRAFFIC_SOURCE_MD5 = {"gbs_kernels.hip": "dfa66259d101dfca87aa9cab36e0e76c",
-                           "gbs_internal.h": "f48053ca35e02096dc67e1bfbdf18b4c"}
+PAIR_TRAFFIC_BYTES = 3.268e9
+PAIR_TRAFFIC_SOURCE_MD5 = {"gbs_kernels.hip": "81f7c41176b7e674f63d0a2d83a64156",
+                           "gbs_internal.h": "9400136ba77f2a392b463cb42f84b648"}
 
 
 def pair_traffic():
