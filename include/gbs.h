@@ -169,12 +169,16 @@ int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
 int gbs_get_stats(const gbs_ctx* ctx, gbs_stats* out);
 
 /*
- * Graphs: capture one forward call (all jobs, one persistent launch) into a
- * hipGraph and replay it.  Creation runs the full plan once (receiver
- * ordering, culling, work lists) and captures the per-call kernels.  Between
- * replays the caller may change the CONTENTS of faces->gamma, but not the
- * geometry, receivers, frequencies or eps (the culled work lists are baked in).
- * The graph holds the pointers given at creation.
+ * Graphs (spec batching extension): capture one forward call (all
+ * jobs, one persistent launch per pass over the table) into a hipGraph and
+ * replay it.  Creation runs the full plan once (receiver ordering, culling,
+ * work lists for every pass) and captures the per-call work: for each pass
+ * the table slice (copied from host memory with GBS_FLAG_TABLE_HOST, which
+ * then must be page-locked), the segment records and the pair kernel.
+ * Between replays the caller may change the CONTENTS of faces->gamma and of a
+ * host table's arrays, but not the geometry, receivers, frequencies or eps
+ * (the culled work lists are baked in).  The graph holds the pointers given
+ * at creation.
  */
 typedef struct gbs_graph gbs_graph;
 int gbs_graph_create(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces,

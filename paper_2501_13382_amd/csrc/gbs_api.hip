@@ -103,6 +103,7 @@ struct Workspace {
     std::map<std::string, std::pair<void*, size_t>> bufs;
     hipStream_t stream = nullptr;
     hipStream_t copy_stream = nullptr;    // also drained before a buffer is freed
+    bool frozen = false;                  // set during graph capture: no allocation allowed
     ~Workspace() { release(); }
     void release() {
         for (auto& kv : bufs)
@@ -114,6 +115,7 @@ struct Workspace {
         size_t bytes = std::max<size_t>(count * sizeof(T), 256);
         auto& b = bufs[name];
         if (b.second < bytes) {
+            GBS_CHECK(!frozen, "internal: workspace growth during graph capture");
             if (b.first) {
                 GBS_HIP(hipStreamSynchronize(stream));
                 if (copy_stream) GBS_HIP(hipStreamSynchronize(copy_stream));
@@ -284,6 +286,7 @@ struct Planner {
 
     bool table_host() const { return (a.params->flags & GBS_FLAG_TABLE_HOST) != 0; }
     int chunk_override = 0;   // autotuner candidate
+    std::string tag;          // graph creation: per-pass names for the buffers the replays read
     int work_chunk() const {
         if (chunk_override) return chunk_override;
         if (a.params->work_chunk) return a.params->work_chunk;
@@ -548,7 +551,7 @@ struct Planner {
         L.rec_raw = rec;
         L.seg_ray = seg_ray;
         std::vector<JobConst> J = job_consts(ps);
-        JobConst* dJ = ws.get<JobConst>("jobs" + std::to_string(pass_idx % 2), n_jobs);
+        JobConst* dJ = ws.get<JobConst>(tag.empty() ? "jobs" + std::to_string(pass_idx % 2) : "jobs" + tag, n_jobs);
         void* h = pinned_staging(ctx, sizeof(JobConst) * n_jobs);
         GBS_HIP(hipStreamSynchronize(st));  // the staging buffer may still feed an earlier copy
         std::memcpy(h, J.data(), sizeof(JobConst) * n_jobs);
@@ -559,7 +562,7 @@ struct Planner {
             unsigned long long* k1 = ws.get<unsigned long long>("skeys", nseg);
             unsigned long long* k2 = ws.get<unsigned long long>("skeys2", nseg);
             int32_t* ids = ws.get<int32_t>("sids", nseg);
-            int32_t* perm = ws.get<int32_t>("seg_perm", nseg);
+            int32_t* perm = ws.get<int32_t>("seg_perm" + tag, nseg);
             hipLaunchKernelGGL(k_seg_keys, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, nseg, rec, dJ,
                                a.rays->n_src, a.n_freq, R.bbox, k1, ids);
             int end_bit = 32;
@@ -633,7 +636,7 @@ struct Planner {
         GBS_HIP(hipcub::DeviceScan::ExclusiveSum(t, tmp, in64, off, (int)(n_cnt + 1), st));
         GBS_HIP(hipMemcpyAsync(&L.total, off + n_cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st));
         GBS_HIP(hipStreamSynchronize(st));
-        int32_t* lists = ws.get<int32_t>("lists", std::max<int64_t>(L.total, 1));
+        int32_t* lists = ws.get<int32_t>("lists" + tag, std::max<int64_t>(L.total, 1));
         if (!sv.empty())
             hipLaunchKernelGGL(cull_fill, cg, dim3(kWave), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
                                n_freq, n_split, d_split, hmask, R.n_hyper, cps, nullptr, off, lists);
@@ -664,10 +667,10 @@ struct Planner {
         GBS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp3, nw, wb, (int)(n_items + 1), st));
         void* t3 = ws.get<char>("cub_tmp_work", tmp3);
         GBS_HIP(hipcub::DeviceScan::ExclusiveSum(t3, tmp3, nw, wb, (int)(n_items + 1), st));
-        Work* work = ws.get<Work>("work", cap);
-        int32_t* iwb = ws.get<int32_t>("item_wbase", n_items);
-        int32_t* iwc = ws.get<int32_t>("item_wcount", n_items);
-        int32_t* n_work = ws.get<int32_t>("n_work", 1);
+        Work* work = ws.get<Work>("work" + tag, cap);
+        int32_t* iwb = ws.get<int32_t>("item_wbase" + tag, n_items);
+        int32_t* iwc = ws.get<int32_t>("item_wcount" + tag, n_items);
+        int32_t* n_work = ws.get<int32_t>("n_work" + tag, 1);
         hipLaunchKernelGGL(k_make_work, dim3(blocks_for(n_items, 256)), dim3(256), 0, st, order, off, n_split, wb,
                            (int32_t)n_items, chunk, work, iwb, iwc, n_work);
         GBS_HIP(hipGetLastError());
@@ -1031,55 +1034,75 @@ int gbs_graph_create(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, c
         GBS_HIP(hipSetDevice(ctx->device));
         Args a{rays, segs, faces, rcv, n_rcv, freqs, n_freq, eps, params};
         validate_host(a);
-        GBS_CHECK(!(params->flags & GBS_FLAG_TABLE_HOST), "graphs need a device-resident table");
-        GBS_CHECK(params->chunk_segs == 0 || params->chunk_segs >= segs->n_segs, "graphs run the table in one pass");
         GBS_CHECK(!(params->flags & GBS_FLAG_COUNT_ACTIVE), "graphs do not count pairs");
         GBS_CHECK(ctx->stream != nullptr, "graph capture needs a non-null stream");
         std::unique_ptr<gbs_graph> g(new gbs_graph);
         g->ctx = ctx;
         Workspace& ws = *g->ws;
+        ws.stream = ctx->stream;
         const int nr = pick_nr(ctx, params, n_rcv);
         Planner pl(ctx, ws, a, nr);
         hipStream_t st = ctx->stream;
         const int64_t n_out = (int64_t)pl.n_jobs * n_rcv;
         pl.read_job_inputs();
-        Planner::Lists L;
-        Planner::PassView v{};
-        bool work = n_out > 0 && segs->n_segs > 0;
+        // plan every pass once (each pass keeps its own lists and work units);
+        // a replay re-stages each pass's table (host tables: copies captured
+        // from pinned memory), rebuilds its records and runs its pair kernel
+        std::vector<Planner::Lists> Ls;
+        const bool work = n_out > 0 && segs->n_segs > 0;
+        int64_t cap = 0;
         if (work) {
             pl.source_offsets();
             pl.make_passes();
             pl.plan_receivers(64 * nr);
-            v = pl.view(pl.passes[0]);
-            L = pl.build_lists(pl.passes[0], v, 0);
-            if (L.n_items > 0 && L.total > 0) L.partial = ws.get<double>("partial", L.work_cap * nr * 64 * 2);
+            for (size_t pi = 0; pi < pl.passes.size(); ++pi) {
+                pl.tag = "#" + std::to_string(pi);
+                Planner::PassView v = pl.view(pl.passes[pi]);
+                Ls.push_back(pl.build_lists(pl.passes[pi], v, (int)pi));
+                cap = std::max(cap, Ls.back().work_cap);
+            }
         }
+        double* partial = ws.get<double>("partial", std::max<int64_t>(cap, 1) * nr * 64 * 2);
         unsigned* ctr = ws.get<unsigned>("ctr", 1);
-        int32_t* seg_ray = const_cast<int32_t*>(L.seg_ray);
-        SegRec* rec = L.rec_raw;
         GBS_HIP(hipStreamSynchronize(st));
+        ws.frozen = true;
         GBS_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         try {
             fill(st, P, 2 * n_out, 0.0);
-            if (work && L.n_items > 0 && L.total > 0) {
+            for (size_t pi = 0; pi < Ls.size(); ++pi) {
+                Planner::Lists L = Ls[pi];
+                if (L.n_items == 0 || L.total == 0) continue;
+                const Planner::PassView v = pl.view(pl.passes[pi]);
+                // shared buffers: fetched again, they may have grown after this pass was planned
+                int32_t* seg_ray = ws.get<int32_t>("seg_ray", v.n_segs);
+                SegRec* rec = ws.get<SegRec>("rec", v.n_segs);
+                hipLaunchKernelGGL(k_seg2ray, dim3(blocks_for(v.n_rays, 256)), dim3(256), 0, st, v.ray_ptr, v.n_rays,
+                                   pl.passes[pi].seg_begin, v.n_segs, seg_ray);
                 // coefficients may change between replays: rebuild the records
                 hipLaunchKernelGGL(k_records, dim3(blocks_for(v.n_segs, 256)), dim3(256), 0, st, v.n_segs, v.a, v.t,
                                    v.s0, v.lo, v.hi, v.face_ptr, v.face_base, v.face_ids, faces->n_faces,
                                    faces->gamma, v.ray_w, seg_ray, rec);
-                if (L.seg_perm)   // into the spatial order planned at capture
+                L.rec = rec;
+                if (L.seg_perm) {   // into the spatial order planned at creation
+                    SegRec* rs = ws.get<SegRec>("rec_sorted", v.n_segs);
                     hipLaunchKernelGGL(k_permute_rec, dim3(blocks_for(v.n_segs, 256)), dim3(256), 0, st, v.n_segs,
-                                       rec, L.seg_perm, const_cast<SegRec*>(L.rec));
+                                       rec, L.seg_perm, rs);
+                    L.rec = rs;
+                }
+                L.partial = partial;
                 dispatch_pairs(params->mode, false, nr, ctx, st, L, pl.R, n_rcv, P, ctr, nullptr);
             }
             if (TL && n_out > 0)
                 hipLaunchKernelGGL(k_tl, dim3(blocks_for(n_out, 256)), dim3(256), 0, st, P, n_out, TL);
         } catch (...) {
-            hipGraph_t tmp;
+            hipGraph_t tmp = nullptr;
             (void)hipStreamEndCapture(st, &tmp);
             if (tmp) (void)hipGraphDestroy(tmp);
+            ws.frozen = false;
             throw;
         }
         GBS_HIP(hipStreamEndCapture(st, &g->graph));
+        ws.frozen = false;
         GBS_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
         *out = g.release();
         return GBS_OK;

@@ -253,13 +253,15 @@ def stats(device="cuda") -> dict:
 
 
 class Graph:
-    """One captured forward (all jobs, one persistent launch) that can be
-    replayed; the coefficient tensor may be updated in place between replays."""
+    """One captured forward (all jobs, one persistent launch per pass over the
+    table; a host table is streamed by the replay) that can be replayed; the
+    coefficient tensor may be updated in place between replays."""
 
-    def __init__(self, table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix", rcv_per_lane=0):
+    def __init__(self, table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix", rcv_per_lane=0,
+                 chunk_segs=0):
         self.ctx = context(table.device)
         self.stream = torch.cuda.Stream(device=table.device)
-        self.call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, 0, rcv_per_lane, False, False)
+        self.call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, False, False)
         self.gamma = self.call.gamma          # [n_faces, 2] device buffer read at every replay
         self.P = torch.empty(self.call.shape + (2,), dtype=torch.float64, device=table.device)
         self.TL = torch.empty(self.call.shape, dtype=torch.float64, device=table.device)

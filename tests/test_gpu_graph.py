@@ -33,3 +33,24 @@ def test_graph_replays_match_eager():
         torch.cuda.synchronize()
         P2_eager, _ = gbs.forward(t, sc.rcv, sc.freqs, sc.eps, g2, **kw)
         assert np.array_equal(P.cpu().numpy(), P2_eager.cpu().numpy())
+
+
+@pytest.mark.parametrize("on_host", [False, True])
+def test_graph_over_several_passes(on_host):
+    """A table split into passes (device-resident, or streamed from pinned host
+    memory by the replay itself): replays equal the eager call bit for bit."""
+    sc = city_batched(n_src=3, ray_lo=1500, ray_hi=5000, grid=24)
+    t = gbs.Table(sc.table, device="cuda", on_host=on_host)
+    chunk = sc.table.seg_s0.shape[0] // 4 + 1
+    kw = dict(c=sc.c, gate=sc.gate, mode="mix", chunk_segs=chunk)
+    P_eager, _ = gbs.forward(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, **kw)
+    assert gbs.stats()["n_chunks"] >= 4
+    P_eager = P_eager.cpu().numpy()
+    g = gbs.Graph(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, **kw)
+    for rep in range(3):
+        print(f"case graph passes on_host={on_host} replay {rep}", flush=True)
+        P, _ = g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(P.cpu().numpy(), P_eager)
+        x = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
