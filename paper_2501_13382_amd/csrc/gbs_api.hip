@@ -27,6 +27,7 @@ __global__ void k_morton(const double*, int64_t, const double*, uint32_t*, int32
 __global__ void k_gather_rcv(const double*, int64_t, int64_t, const int32_t*, double*, double*, double*, double*,
                              int32_t*);
 __global__ void k_patches(const double*, const double*, const double*, int64_t, int64_t, int, Patch*);
+__global__ void k_sphere_of_spheres(const Patch*, int, int, int, Patch*);
 __global__ void k_src_ranges(const int64_t*, const int32_t*, int64_t, int32_t, int64_t*);
 __global__ void k_seg2ray(const int64_t*, int64_t, int64_t, int64_t, int32_t*);
 __global__ void k_records(int64_t, const double*, const double*, const double*, const double*, const double*,
@@ -409,11 +410,11 @@ struct Planner {
         R.supers = ws.get<Patch>("supers", R.n_super);
         hipLaunchKernelGGL(k_patches, dim3(R.n_patch), dim3(64), 0, st, R.rx, R.ry, R.rz, R.n_pad, (int64_t)per,
                            R.n_patch, R.patches);
-        hipLaunchKernelGGL(k_patches, dim3(R.n_super), dim3(64), 0, st, R.rx, R.ry, R.rz, R.n_pad,
-                           (int64_t)per * kSuperPatches, R.n_super, R.supers);
+        hipLaunchKernelGGL(k_sphere_of_spheres, dim3(R.n_super), dim3(64), 0, st, R.patches, R.n_patch, kSuperPatches,
+                           R.n_super, R.supers);
         R.hypers = ws.get<Patch>("hypers", R.n_hyper);
-        hipLaunchKernelGGL(k_patches, dim3(R.n_hyper), dim3(64), 0, st, R.rx, R.ry, R.rz, R.n_pad,
-                           (int64_t)per * kSuperPatches * kHyperSupers, R.n_hyper, R.hypers);
+        hipLaunchKernelGGL(k_sphere_of_spheres, dim3(R.n_hyper), dim3(64), 0, st, R.supers, R.n_super, kHyperSupers,
+                           R.n_hyper, R.hypers);
         GBS_HIP(hipGetLastError());
     }
 

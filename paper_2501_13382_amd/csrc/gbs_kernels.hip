@@ -210,6 +210,36 @@ __global__ __launch_bounds__(64) void k_patches(const double* __restrict__ rx, c
     if (lane == 0) out[g] = Patch{c[0], c[1], c[2], r};
 }
 
+// Bounding sphere of each group of `per` consecutive child spheres (one
+// wavefront per group): centre at the middle of the children's box, radius
+// the farthest child surface point, so it holds every child's receivers.
+__global__ __launch_bounds__(64) void k_sphere_of_spheres(const Patch* __restrict__ child, int n_child, int per,
+                                                          int n_groups, Patch* __restrict__ out) {
+    const int g = blockIdx.x;
+    if (g >= n_groups) return;
+    const int lane = threadIdx.x;
+    const int b = g * per, e = min(b + per, n_child);
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = b + lane; i < e; i += 64) {
+        const Patch c = child[i];
+        const double v[3] = {c.cx, c.cy, c.cz};
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = fmin(lo[d], v[d] - c.rad);
+            hi[d] = fmax(hi[d], v[d] + c.rad);
+        }
+    }
+    double C[3];
+    for (int d = 0; d < 3; ++d) C[d] = 0.5 * (wave_min(lo[d]) + wave_max(hi[d]));
+    double r = 0.0;
+    for (int i = b + lane; i < e; i += 64) {
+        const Patch c = child[i];
+        const double dx = c.cx - C[0], dy = c.cy - C[1], dz = c.cz - C[2];
+        r = fmax(r, sqrt(dx * dx + dy * dy + dz * dz) + c.rad);
+    }
+    r = wave_max(r);
+    if (lane == 0) out[g] = Patch{C[0], C[1], C[2], r * (1.0 + 1e-12)};
+}
+
 // ----------------------------------------------------------------- segments
 // First segment of every source (rays are sorted by source); src_off[n_src]
 // is the end of the table.
