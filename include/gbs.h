@@ -199,6 +199,75 @@ int gbs_autotune(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
                  const double* rcv, int64_t n_rcv, const double* freqs, int32_t n_freq, const double* eps,
                  const gbs_params* params, double* P, int32_t* rcv_per_lane, int32_t* work_chunk);
 
+/*
+ * Ray tracing: the stage before beam summation (Sec. 3.1; one thread per ray
+ * as in Sec. 3.3).  Traces a fan of rays through a scene of the ground plane
+ * z = 0 (face 0) and axis-aligned boxes standing on it, with specular
+ * reflection (image-source geometry, Sec. 1), at most max_refl reflections
+ * per ray (R_max of Tables 2 and 3), until each ray's arc length reaches
+ * s_max, and writes the ray table that gbs_forward reads.
+ *
+ * Scene.  Box b occupies [x0, x1] x [y0, y1] x [0, h] and owns the faces
+ * 1 + b*5*panels^2 ... : walls -x, +x, -y, +y, then the roof, each split into
+ * panels x panels cells (cell = iu * panels + iv, u along the face's first
+ * in-plane axis (y for x-walls, x otherwise), v along the second (z for
+ * walls, y for the roof)).  n_faces of the table = 1 + n_boxes*5*panels^2.
+ *
+ * Rules.  Hits need a distance > 1e-7 m; a box's entry face is on the first
+ * axis whose slab entry equals the entry distance; a box is never entered
+ * through its floor; the ground wins a tie with a box, the lower box index
+ * a tie between boxes.  Beam extents: walls and roofs truncate (lo = 0,
+ * hi = L); the ground is transparent (a segment ending on it has
+ * hi = L + L_next, the next segment lo = -L).  image_complete (no boxes):
+ * a ray that never reflects from the ground gets a second segment from the
+ * source mirrored in z = 0 along the mirrored direction, lo = 0, hi = s_max,
+ * face history [0].  Segment j of a ray has the end faces of segments
+ * 0..j-1 as its history.  All arithmetic is IEEE double without fused
+ * multiply-adds: the table is deterministic and identical for any launch.
+ */
+typedef struct gbs_scene {
+    int32_t n_boxes;          /* >= 0                                            */
+    int32_t panels;           /* 1..8                                            */
+    const double* boxes;      /* [n_boxes * 5] x0, x1, y0, y1, h (device);
+                                 x0 < x1, y0 < y1, h > 0, finite                 */
+    double s_max;             /* arc length at which every ray ends (m), > 0     */
+    int32_t max_refl;         /* R_max, 0..32                                    */
+    int32_t image_complete;   /* 0/1; 1 needs n_boxes == 0                       */
+} gbs_scene;
+
+/* Launch fan: rays from their sources (device memory). */
+typedef struct gbs_fan {
+    int32_t n_src;
+    const double* src_xyz;    /* [n_src * 3], z > 0                              */
+    int64_t n_rays;           /* >= 0                                            */
+    const double* dirs;       /* [n_rays * 3] unit directions (|d|^2 = 1 +- 1e-9) */
+    const int32_t* ray_src;   /* [n_rays] source of each ray in [0, n_src),
+                                 non-decreasing, or NULL for source 0            */
+} gbs_fan;
+
+/*
+ * Sizes of the table gbs_trace will write: *n_segs segments and *n_face_ids
+ * face-history entries.  Synchronises the context's stream.
+ */
+int gbs_trace_count(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, int64_t* n_segs,
+                    int64_t* n_face_ids);
+
+/*
+ * Trace the fan and write the table (device memory, caller-allocated):
+ *   ray_ptr  [n_rays + 1]    CSR of each ray's segments
+ *   seg_a, seg_t [cap_segs * 3], seg_s0, seg_lo, seg_hi [cap_segs]
+ *   face_ptr [cap_segs + 1]  CSR into face_ids
+ *   face_ids [cap_face_ids]
+ * The ray weights and sources of the table are the caller's (unchanged).
+ * *n_segs and *n_face_ids receive the sizes; a capacity below them is
+ * GBS_E_INVALID (nothing written past the capacities).  A direction that is
+ * not a unit vector is GBS_E_INVALID.  Synchronises the context's stream
+ * once (to read the sizes) before the table is written.
+ */
+int gbs_trace(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, int64_t cap_segs, int64_t cap_face_ids,
+              int64_t* ray_ptr, double* seg_a, double* seg_t, double* seg_s0, double* seg_lo, double* seg_hi,
+              int64_t* face_ptr, int32_t* face_ids, int64_t* n_segs, int64_t* n_face_ids);
+
 /* Message describing the last error on ctx (never NULL). */
 const char* gbs_last_error(const gbs_ctx* ctx);
 

@@ -46,6 +46,16 @@ class GbsParams(ctypes.Structure):
                 ("chunk_segs", c_int64), ("rcv_per_lane", c_int32), ("work_chunk", c_int32)]
 
 
+class GbsScene(ctypes.Structure):
+    _fields_ = [("n_boxes", c_int32), ("panels", c_int32), ("boxes", c_void_p), ("s_max", c_double),
+                ("max_refl", c_int32), ("image_complete", c_int32)]
+
+
+class GbsFan(ctypes.Structure):
+    _fields_ = [("n_src", c_int32), ("src_xyz", c_void_p), ("n_rays", c_int64), ("dirs", c_void_p),
+                ("ray_src", c_void_p)]
+
+
 class GbsStats(ctypes.Structure):
     _fields_ = [("dense_pairs", c_int64), ("listed_pairs", c_int64), ("active_pairs", c_int64),
                 ("n_items", c_int64), ("n_chunks", c_int32), ("patch_rcv", c_int32), ("ms_pairs", c_double),
@@ -56,8 +66,8 @@ class GbsStats(ctypes.Structure):
 
 
 EXPORTS = ("gbs_create", "gbs_destroy", "gbs_set_stream", "gbs_forward", "gbs_backward", "gbs_get_stats",
-           "gbs_graph_create", "gbs_graph_launch", "gbs_graph_destroy", "gbs_autotune", "gbs_last_error",
-           "gbs_version")
+           "gbs_graph_create", "gbs_graph_launch", "gbs_graph_destroy", "gbs_autotune", "gbs_trace_count",
+           "gbs_trace", "gbs_last_error", "gbs_version")
 
 _lib = None
 
@@ -98,6 +108,11 @@ def load() -> ctypes.CDLL:
     lib.gbs_graph_destroy.restype = None
     lib.gbs_autotune.argtypes = common + [c_void_p, P(c_int32), P(c_int32)]
     lib.gbs_autotune.restype = ctypes.c_int
+    lib.gbs_trace_count.argtypes = [c_void_p, P(GbsScene), P(GbsFan), P(c_int64), P(c_int64)]
+    lib.gbs_trace_count.restype = ctypes.c_int
+    lib.gbs_trace.argtypes = [c_void_p, P(GbsScene), P(GbsFan), c_int64, c_int64] + [c_void_p] * 8 + \
+        [P(c_int64), P(c_int64)]
+    lib.gbs_trace.restype = ctypes.c_int
     lib.gbs_last_error.argtypes = [c_void_p]
     lib.gbs_last_error.restype = ctypes.c_char_p
     lib.gbs_version.argtypes = []

@@ -66,6 +66,13 @@ __global__ void k_face_scatter(int64_t, const int64_t*, int64_t, const int32_t*,
 __global__ void k_dgamma(const double*, int32_t, double*);
 __global__ void k_validate(int64_t, const double*, const double*, const double*, const int64_t*, int64_t,
                            const int32_t*, int32_t, int*);
+// ray tracing (gbs_trace.hip)
+template <bool COUNT>
+__global__ void k_trace(int64_t, const double*, const int32_t*, const double*, const double*, const double*,
+                        const int32_t*, int, int, int, double, int, int64_t*, int*, const int64_t*, const int64_t*,
+                        double*, double*, double*, double*, double*, int64_t*, int32_t*);
+__global__ void k_trace_face_counts(int64_t, const int64_t*, int64_t*);
+__global__ void k_trace_close(const int64_t*, int64_t, int64_t, int64_t*);
 }  // namespace gbs
 
 using namespace gbs;
@@ -870,6 +877,172 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
     return GBS_OK;
 }
 
+// ------------------------------------------------------------ ray tracing
+// Groups of kTraceGroup boxes in Morton order of their centres, each with the
+// union of its members' bounds.
+struct TraceScene {
+    std::vector<double> gbox;         // [n_groups * 6]
+    std::vector<int32_t> members;     // [n_groups * kTraceGroup], -1 = empty
+    int n_groups = 0;
+};
+
+TraceScene group_boxes(const std::vector<double>& bx, int n_boxes) {
+    TraceScene S;
+    if (n_boxes == 0) return S;
+    double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
+    for (int b = 0; b < n_boxes; ++b)
+        for (int j = 0; j < 2; ++j) {
+            lo[j] = std::min(lo[j], bx[5 * b + 2 * j]);
+            hi[j] = std::max(hi[j], bx[5 * b + 2 * j + 1]);
+        }
+    auto spread = [](uint32_t v) {                 // 16 bits -> every other bit
+        v &= 0xffffu;
+        v = (v | (v << 8)) & 0x00ff00ffu;
+        v = (v | (v << 4)) & 0x0f0f0f0fu;
+        v = (v | (v << 2)) & 0x33333333u;
+        v = (v | (v << 1)) & 0x55555555u;
+        return v;
+    };
+    std::vector<std::pair<uint32_t, int32_t>> key(n_boxes);
+    for (int b = 0; b < n_boxes; ++b) {
+        uint32_t q[2];
+        for (int j = 0; j < 2; ++j) {
+            const double c = 0.5 * (bx[5 * b + 2 * j] + bx[5 * b + 2 * j + 1]);
+            const double w = hi[j] > lo[j] ? (c - lo[j]) / (hi[j] - lo[j]) : 0.0;
+            q[j] = (uint32_t)std::min(65535.0, std::max(0.0, w * 65535.0));
+        }
+        key[b] = {spread(q[0]) | (spread(q[1]) << 1), b};
+    }
+    std::sort(key.begin(), key.end());
+    S.n_groups = (n_boxes + kTraceGroup - 1) / kTraceGroup;
+    S.gbox.assign((size_t)S.n_groups * 6, 0.0);
+    S.members.assign((size_t)S.n_groups * kTraceGroup, -1);
+    for (int g = 0; g < S.n_groups; ++g) {
+        double glo[3] = {INFINITY, INFINITY, 0.0}, ghi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int m = 0; m < kTraceGroup && g * kTraceGroup + m < n_boxes; ++m) {
+            const int b = key[g * kTraceGroup + m].second;
+            S.members[g * kTraceGroup + m] = b;
+            glo[0] = std::min(glo[0], bx[5 * b]);
+            ghi[0] = std::max(ghi[0], bx[5 * b + 1]);
+            glo[1] = std::min(glo[1], bx[5 * b + 2]);
+            ghi[1] = std::max(ghi[1], bx[5 * b + 3]);
+            ghi[2] = std::max(ghi[2], bx[5 * b + 4]);
+        }
+        for (int j = 0; j < 3; ++j) {
+            S.gbox[6 * g + j] = glo[j];
+            S.gbox[6 * g + 3 + j] = ghi[j];
+        }
+    }
+    return S;
+}
+
+struct TraceOut {
+    int64_t* ray_ptr;
+    double *a, *t, *s0, *lo, *hi;
+    int64_t* face_ptr;
+    int32_t* face_ids;
+};
+
+// Count pass and prefix sums; with `out` also the write pass (after the
+// capacity check).  Returns the sizes.
+std::pair<int64_t, int64_t> trace_impl(gbs_ctx* ctx, const gbs_scene* sc, const gbs_fan* fan, int64_t cap_segs,
+                                       int64_t cap_faces, const TraceOut* out) {
+    GBS_CHECK(sc && fan, "scene and fan must be non-null");
+    GBS_CHECK(sc->n_boxes >= 0 && (sc->n_boxes == 0 || sc->boxes), "scene.boxes");
+    GBS_CHECK(sc->panels >= 1 && sc->panels <= 8, "scene.panels must be in 1..8");
+    GBS_CHECK(sc->max_refl >= 0 && sc->max_refl <= kTraceMaxRefl, "scene.max_refl must be in 0..32");
+    GBS_CHECK(std::isfinite(sc->s_max) && sc->s_max > 0, "scene.s_max must be finite and > 0");
+    GBS_CHECK(sc->image_complete == 0 || sc->image_complete == 1, "scene.image_complete must be 0 or 1");
+    GBS_CHECK(!sc->image_complete || sc->n_boxes == 0, "image completion is defined for the open plane only");
+    GBS_CHECK(fan->n_src >= 1 && fan->src_xyz, "fan.src_xyz");
+    GBS_CHECK(fan->n_rays >= 0 && (fan->n_rays == 0 || fan->dirs), "fan.dirs");
+    GBS_CHECK(fan->n_rays < INT32_MAX - 1, "fan.n_rays too large");
+    const double faces_total = 1.0 + (double)sc->n_boxes * 5.0 * sc->panels * sc->panels;
+    GBS_CHECK(faces_total < (double)INT32_MAX, "too many faces");
+    hipStream_t st = ctx->stream;
+    Workspace& ws = *ctx->ws;
+    // small tables to the host: validation and box groups
+    std::vector<double> bx((size_t)sc->n_boxes * 5), src((size_t)fan->n_src * 3);
+    if (sc->n_boxes)
+        GBS_HIP(hipMemcpyAsync(bx.data(), sc->boxes, bx.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    GBS_HIP(hipMemcpyAsync(src.data(), fan->src_xyz, src.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    GBS_HIP(hipStreamSynchronize(st));
+    for (int b = 0; b < sc->n_boxes; ++b) {
+        const double* q = &bx[5 * b];
+        GBS_CHECK(std::isfinite(q[0]) && std::isfinite(q[1]) && std::isfinite(q[2]) && std::isfinite(q[3]) &&
+                      std::isfinite(q[4]) && q[0] < q[1] && q[2] < q[3] && q[4] > 0,
+                  "box " + std::to_string(b) + " must be finite with x0 < x1, y0 < y1, h > 0");
+    }
+    for (int k = 0; k < fan->n_src; ++k)
+        GBS_CHECK(std::isfinite(src[3 * k]) && std::isfinite(src[3 * k + 1]) && std::isfinite(src[3 * k + 2]) &&
+                      src[3 * k + 2] > 0,
+                  "sources must be finite and above the ground");
+    const int64_t n = fan->n_rays;
+    if (fan->ray_src && n > 0) {
+        // ray sources in range: checked on the host from a copy (small next to the trace)
+        std::vector<int32_t> rs(n);
+        GBS_HIP(hipMemcpyAsync(rs.data(), fan->ray_src, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        GBS_HIP(hipStreamSynchronize(st));
+        for (int64_t i = 0; i < n; ++i) {
+            GBS_CHECK(rs[i] >= 0 && rs[i] < fan->n_src, "fan.ray_src out of range");
+            GBS_CHECK(i == 0 || rs[i] >= rs[i - 1], "fan.ray_src must be non-decreasing");
+        }
+    }
+    const TraceScene S = group_boxes(bx, sc->n_boxes);
+    const size_t ng = std::max<size_t>(S.n_groups, 1);
+    double* d_box = ws.get<double>("tr_box", std::max<size_t>(bx.size(), 1));
+    double* d_gbox = ws.get<double>("tr_gbox", ng * 6);
+    int32_t* d_mem = ws.get<int32_t>("tr_members", ng * kTraceGroup);
+    if (!bx.empty()) GBS_HIP(hipMemcpyAsync(d_box, bx.data(), bx.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    if (S.n_groups) {
+        GBS_HIP(hipMemcpyAsync(d_gbox, S.gbox.data(), S.gbox.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        GBS_HIP(hipMemcpyAsync(d_mem, S.members.data(), S.members.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                               st));
+    }
+    int64_t* nseg = ws.get<int64_t>("tr_nseg", n + 1);
+    int64_t* nface = ws.get<int64_t>("tr_nface", n + 1);
+    int64_t* rp = out ? out->ray_ptr : ws.get<int64_t>("tr_rayptr", n + 1);
+    int64_t* fbase = ws.get<int64_t>("tr_fbase", n + 1);
+    int* bad = ws.get<int>("tr_bad", 1);
+    GBS_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+    GBS_HIP(hipMemsetAsync(nseg + n, 0, sizeof(int64_t), st));
+    const dim3 grid(blocks_for(n, kTraceThreads)), block(kTraceThreads);
+    if (n > 0)
+        hipLaunchKernelGGL(k_trace<true>, grid, block, 0, st, n, fan->src_xyz, fan->ray_src, fan->dirs, d_box, d_gbox,
+                           d_mem, S.n_groups, sc->panels, sc->max_refl, sc->s_max, sc->image_complete, nseg, bad,
+                           nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    GBS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_trace_face_counts, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st, n, nseg, nface);
+    size_t tmp = 0;
+    GBS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, nseg, rp, (int)(n + 1), st));
+    void* tb = ws.get<char>("tr_scan", tmp);
+    GBS_HIP(hipcub::DeviceScan::ExclusiveSum(tb, tmp, nseg, rp, (int)(n + 1), st));
+    GBS_HIP(hipcub::DeviceScan::ExclusiveSum(tb, tmp, nface, fbase, (int)(n + 1), st));
+    int64_t tot[2] = {0, 0};
+    int h_bad = 0;
+    GBS_HIP(hipMemcpyAsync(&tot[0], rp + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    GBS_HIP(hipMemcpyAsync(&tot[1], fbase + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    GBS_HIP(hipMemcpyAsync(&h_bad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    GBS_HIP(hipStreamSynchronize(st));
+    GBS_CHECK(!h_bad, "fan.dirs must be unit vectors");
+    if (!out) return {tot[0], tot[1]};
+    GBS_CHECK(tot[0] <= cap_segs && tot[1] <= cap_faces,
+              "table capacity too small: needs " + std::to_string(tot[0]) + " segments and " +
+                  std::to_string(tot[1]) + " face ids");
+    GBS_CHECK(tot[0] == 0 || (out->a && out->t && out->s0 && out->lo && out->hi && out->face_ptr),
+              "table outputs must be non-null");
+    GBS_CHECK(tot[1] == 0 || out->face_ids, "face_ids must be non-null");
+    GBS_CHECK(out->face_ptr, "face_ptr must be non-null");
+    if (n > 0)
+        hipLaunchKernelGGL(k_trace<false>, grid, block, 0, st, n, fan->src_xyz, fan->ray_src, fan->dirs, d_box,
+                           d_gbox, d_mem, S.n_groups, sc->panels, sc->max_refl, sc->s_max, sc->image_complete,
+                           nullptr, nullptr, rp, fbase, out->a, out->t, out->s0, out->lo, out->hi, out->face_ptr,
+                           out->face_ids);
+    hipLaunchKernelGGL(k_trace_close, dim3(1), dim3(64), 0, st, fbase, n, tot[0], out->face_ptr);
+    GBS_HIP(hipGetLastError());
+    return {tot[0], tot[1]};
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -1126,6 +1299,34 @@ void gbs_graph_destroy(gbs_graph* g) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     delete g;
+}
+
+int gbs_trace_count(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, int64_t* n_segs,
+                    int64_t* n_face_ids) {
+    if (!ctx) return GBS_E_INVALID;
+    return guarded(ctx, [&]() {
+        GBS_CHECK(n_segs && n_face_ids, "n_segs and n_face_ids must be non-null");
+        GBS_HIP(hipSetDevice(ctx->device));
+        const auto r = trace_impl(ctx, scene, fan, 0, 0, nullptr);
+        *n_segs = r.first;
+        *n_face_ids = r.second;
+        return GBS_OK;
+    });
+}
+
+int gbs_trace(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, int64_t cap_segs, int64_t cap_face_ids,
+              int64_t* ray_ptr, double* seg_a, double* seg_t, double* seg_s0, double* seg_lo, double* seg_hi,
+              int64_t* face_ptr, int32_t* face_ids, int64_t* n_segs, int64_t* n_face_ids) {
+    if (!ctx) return GBS_E_INVALID;
+    return guarded(ctx, [&]() {
+        GBS_CHECK(ray_ptr, "ray_ptr must be non-null");
+        GBS_HIP(hipSetDevice(ctx->device));
+        const TraceOut o{ray_ptr, seg_a, seg_t, seg_s0, seg_lo, seg_hi, face_ptr, face_ids};
+        const auto r = trace_impl(ctx, scene, fan, cap_segs, cap_face_ids, &o);
+        if (n_segs) *n_segs = r.first;
+        if (n_face_ids) *n_face_ids = r.second;
+        return GBS_OK;
+    });
 }
 
 int gbs_autotune(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces,

@@ -64,4 +64,10 @@ struct CullSplit {
     int32_t idx;              // index of the piece within its source
 };
 
+// Ray tracing: threads per workgroup (one ray each), the largest R_max (the
+// face history of a ray is staged in LDS) and boxes per bounding group.
+constexpr int kTraceThreads = 128;
+constexpr int kTraceMaxRefl = 32;
+constexpr int kTraceGroup = 8;
+
 }  // namespace gbs

@@ -208,6 +208,55 @@ def backward(table: Table, rcv, freqs, eps, gamma, lam, *, c=343.0, gate=9.21, m
     return d_gamma, d_rcv, d_eps
 
 
+class _Traced:
+    """Fields of a traced table (device tensors) in the layout Table reads."""
+
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+
+def trace(src_xyz, dirs, weights, *, ray_src=None, boxes=None, panels=1, s_max, max_refl=10,
+          image_complete=False, device="cuda") -> Table:
+    """Ray tracing on the device (gbs_trace): the fan `dirs` [n, 3] (unit) from
+    the sources `src_xyz` [n_src, 3] (ray i from source ray_src[i], default 0)
+    through the ground plane and `boxes` [n_boxes, 5] (x0, x1, y0, y1, h);
+    returns the ray table as a device Table with the given ray weights."""
+    ctx = context(device)
+    ctx.bind_stream()
+    dev = ctx.device
+    f64 = torch.float64
+    src = _as_tensor(src_xyz, f64, dev).reshape(-1, 3)
+    d = _as_tensor(dirs, f64, dev).reshape(-1, 3)
+    w = _as_tensor(weights, f64, dev).reshape(-1)
+    n = int(d.shape[0])
+    if w.numel() != n:
+        raise ValueError("one weight per ray")
+    rs = _as_tensor(ray_src, torch.int32, dev).reshape(-1) if ray_src is not None else \
+        torch.zeros(n, dtype=torch.int32, device=dev)
+    if rs.numel() != n:
+        raise ValueError("one source index per ray")
+    bx = _as_tensor(np.zeros((0, 5)) if boxes is None else boxes, f64, dev).reshape(-1, 5)
+    scene = _lib.GbsScene(int(bx.shape[0]), int(panels), _ptr(bx), float(s_max), int(max_refl),
+                          1 if image_complete else 0)
+    fan = _lib.GbsFan(int(src.shape[0]), _ptr(src), n, _ptr(d), _ptr(rs))
+    ns, nf = ctypes.c_int64(0), ctypes.c_int64(0)
+    _lib.check(ctx.lib.gbs_trace_count(ctx.handle, ctypes.byref(scene), ctypes.byref(fan), ctypes.byref(ns),
+                                       ctypes.byref(nf)), ctx.handle)
+    S, F = int(ns.value), int(nf.value)
+    out = _Traced(src_xyz=src, ray_w=w, ray_src=rs, n_faces=1 + int(bx.shape[0]) * 5 * int(panels) ** 2,
+                  ray_ptr=torch.empty(n + 1, dtype=torch.int64, device=dev),
+                  seg_a=torch.empty((S, 3), dtype=f64, device=dev), seg_t=torch.empty((S, 3), dtype=f64, device=dev),
+                  seg_s0=torch.empty(S, dtype=f64, device=dev), seg_lo=torch.empty(S, dtype=f64, device=dev),
+                  seg_hi=torch.empty(S, dtype=f64, device=dev),
+                  face_ptr=torch.empty(S + 1, dtype=torch.int64, device=dev),
+                  face_ids=torch.empty(F, dtype=torch.int32, device=dev))
+    rc = ctx.lib.gbs_trace(ctx.handle, ctypes.byref(scene), ctypes.byref(fan), S, F, _ptr(out.ray_ptr),
+                           _ptr(out.seg_a), _ptr(out.seg_t), _ptr(out.seg_s0), _ptr(out.seg_lo), _ptr(out.seg_hi),
+                           _ptr(out.face_ptr), _ptr(out.face_ids), ctypes.byref(ns), ctypes.byref(nf))
+    _lib.check(rc, ctx.handle)
+    return Table(out, device=dev)
+
+
 def _tune_key(table: Table, call, mode: str) -> str:
     """Cache key: GPU architecture, mode and a size bucket of the problem
     (log2 of the dense pair count, bands, sources)."""

@@ -37,6 +37,8 @@ def test_struct_sizes_match_c_layout():
     assert ctypes.sizeof(_lib.GbsFaces) == 16
     assert ctypes.sizeof(_lib.GbsParams) == 40
     assert ctypes.sizeof(_lib.GbsStats) == 64
+    assert ctypes.sizeof(_lib.GbsScene) == 32
+    assert ctypes.sizeof(_lib.GbsFan) == 40
 
 
 def test_create_without_gpu_fails_cleanly():
