@@ -13,8 +13,10 @@ its HIP-event-timed duration), the all-FP64 mode on the same GPU, the forward
 captured as a hipGraph and replayed, the table
 streamed from pinned host memory in four overlapped passes (PCIe-inclusive,
 never `value`), the adjoint call on the same workload, the error against the
-FP64 oracle on 16,384 seeded receivers, and the oracle timed on this host's
-cores on that sample (and single-threaded on a smaller one).
+FP64 oracle on 16,384 seeded receivers, the oracle timed on this host's
+cores on that sample (and single-threaded on a smaller one), and the device
+ray tracer re-tracing the workload's fan (with the per-ray oracle tracer
+timed on a sample of rays).
 """
 from __future__ import annotations
 
@@ -87,6 +89,73 @@ WORKLOADS = {"open_plane_100k": ("open_plane_100k_8band", _open_plane_100k),
              "city_batched": ("city_batched_16src_4band_1024sq", _city_batched)}
 
 
+def trace_bench(sc, dev, args):
+    """The ray-tracing stage on the device for the workload's own fan (the
+    launch directions are the first segment's axis of every ray): wall time
+    of gbs.trace (count pass, prefix sums, write pass, host reads of the
+    sizes), the table compared with the workload's input table, and the
+    per-ray oracle tracer on a seeded sample of rays on the host."""
+    import torch
+
+    import paper_2501_13382_amd as gbs
+    tab = sc.table
+    kind = tab.meta.get("kind")
+    if kind == "open_plane":
+        kw = dict(boxes=None, panels=1, s_max=tab.meta["s_max"], max_refl=1, image_complete=True)
+    elif kind == "city":
+        city = sc.meta["city"]
+        kw = dict(boxes=city.boxes, panels=city.panels, s_max=tab.meta["s_max"], max_refl=tab.meta["max_refl"])
+    else:
+        return None                       # several sources with their own s_max
+    first = tab.ray_ptr[:-1]
+    dirs = torch.as_tensor(tab.seg_t[first], device=dev)
+    w = torch.as_tensor(tab.ray_w, device=dev)
+    src = tab.src_xyz
+    t = gbs.trace(src, dirs, w, **kw)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        t = gbs.trace(src, dirs, w, **kw)
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1e3)
+    same = {}
+    for k in ("ray_ptr", "seg_a", "seg_t", "seg_s0", "seg_lo", "face_ptr", "face_ids"):
+        same[k] = bool(np.array_equal(getattr(t, k).cpu().numpy().reshape(np.shape(getattr(tab, k))),
+                                      np.asarray(getattr(tab, k))))
+    hi = t.seg_hi.cpu().numpy()
+    # the open-plane generator writes s_max for the direct beam's end; the
+    # general tracer adds the two lengths: equal to rounding
+    same["seg_hi_max_rel"] = float(np.max(np.abs(hi - tab.seg_hi) / np.maximum(np.abs(tab.seg_hi), 1e-300)))
+    med = float(np.median(ms))
+    leg = {"ms_median": med, "ms_min": float(np.min(ms)), "rays": t.n_rays, "segments": t.n_segs,
+           "rays_per_s": t.n_rays / (med * 1e-3), "segments_per_s": t.n_segs / (med * 1e-3),
+           "matches_input_table": same,
+           "note": "wall time of gbs.trace: count pass (twice: sizes, then in the call), prefix sums, write pass"}
+    print(f"# trace: {med:.2f} ms for {t.n_rays} rays, {t.n_segs} segments", file=sys.stderr, flush=True)
+    del t
+    if not args.no_cpu:
+        from oracle import tracer as ot
+        d_host = tab.seg_t[first]
+        rng = np.random.default_rng(7)
+
+        def timed(n_s):
+            rays = np.sort(rng.choice(tab.n_rays, size=n_s, replace=False))
+            t0 = time.perf_counter()
+            ot.trace(src, d_host, tab.ray_w, boxes=kw["boxes"], panels=kw["panels"], s_max=kw["s_max"],
+                     max_refl=kw["max_refl"], image_complete=kw.get("image_complete", False), rays=rays)
+            return time.perf_counter() - t0
+
+        # a probe of 200 rays sizes a sample of about 3 s
+        n_s = min(200, tab.n_rays)
+        el = timed(n_s)
+        n_s = int(min(tab.n_rays, max(n_s, 3.0 * n_s / max(el, 1e-6))))
+        el = timed(n_s)
+        leg["cpu_baseline"] = {"value": n_s / el, "unit": "rays/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{n_s} of {tab.n_rays} rays (seed 7), one by one; {el:.1f}s"}
+    return leg
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +167,7 @@ def parse():
     ap.add_argument("--cpu1-receivers", type=int, default=512, help="receivers of the single-thread oracle sample")
     ap.add_argument("--no-stream", action="store_true", help="skip the host-streamed table leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--no-trace", action="store_true", help="skip the device ray-tracing leg")
     ap.add_argument("--workload", default="open_plane_100k", choices=sorted(WORKLOADS),
                     help="open_plane_100k (default, the headline); city_1m: 10 x 10 city, 1,000,000 rays, "
                          "1024 x 1024 receivers, 1 kHz; city_batched: 16 sources x 4 bands, ragged ray counts, "
@@ -227,6 +297,10 @@ def main():
     del graph
     print(f"# graph replay: {s_gr * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
 
+    trace_leg = None
+    if not args.no_trace:
+        trace_leg = trace_bench(sc, dev, args)
+
     f64_leg = None
     if not args.no_f64:
         s64, ms64, _ = run("f64", max(2, args.steps // 2), 1)
@@ -267,6 +341,7 @@ def main():
         "graph": graph_leg,
         "streamed": stream_leg,
         "adjoint": adj_leg,
+        "trace": trace_leg,
     }
 
     if args.copy_calibration > 0:

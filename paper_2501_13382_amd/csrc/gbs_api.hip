@@ -68,7 +68,7 @@ __global__ void k_validate(int64_t, const double*, const double*, const double*,
                            const int32_t*, int32_t, int*);
 // ray tracing (gbs_trace.hip)
 template <bool COUNT>
-__global__ void k_trace(int64_t, const double*, const int32_t*, const double*, const double*, const double*,
+__global__ void k_trace(int64_t, int, const double*, const int32_t*, const double*, const double*, const double*,
                         const int32_t*, int, int, int, double, int, int64_t*, int*, const int64_t*, const int64_t*,
                         double*, double*, double*, double*, double*, int64_t*, int32_t*);
 __global__ void k_trace_face_counts(int64_t, const int64_t*, int64_t*);
@@ -978,16 +978,6 @@ std::pair<int64_t, int64_t> trace_impl(gbs_ctx* ctx, const gbs_scene* sc, const 
                       src[3 * k + 2] > 0,
                   "sources must be finite and above the ground");
     const int64_t n = fan->n_rays;
-    if (fan->ray_src && n > 0) {
-        // ray sources in range: checked on the host from a copy (small next to the trace)
-        std::vector<int32_t> rs(n);
-        GBS_HIP(hipMemcpyAsync(rs.data(), fan->ray_src, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        GBS_HIP(hipStreamSynchronize(st));
-        for (int64_t i = 0; i < n; ++i) {
-            GBS_CHECK(rs[i] >= 0 && rs[i] < fan->n_src, "fan.ray_src out of range");
-            GBS_CHECK(i == 0 || rs[i] >= rs[i - 1], "fan.ray_src must be non-decreasing");
-        }
-    }
     const TraceScene S = group_boxes(bx, sc->n_boxes);
     const size_t ng = std::max<size_t>(S.n_groups, 1);
     double* d_box = ws.get<double>("tr_box", std::max<size_t>(bx.size(), 1));
@@ -1008,8 +998,8 @@ std::pair<int64_t, int64_t> trace_impl(gbs_ctx* ctx, const gbs_scene* sc, const 
     GBS_HIP(hipMemsetAsync(nseg + n, 0, sizeof(int64_t), st));
     const dim3 grid(blocks_for(n, kTraceThreads)), block(kTraceThreads);
     if (n > 0)
-        hipLaunchKernelGGL(k_trace<true>, grid, block, 0, st, n, fan->src_xyz, fan->ray_src, fan->dirs, d_box, d_gbox,
-                           d_mem, S.n_groups, sc->panels, sc->max_refl, sc->s_max, sc->image_complete, nseg, bad,
+        hipLaunchKernelGGL(k_trace<true>, grid, block, 0, st, n, fan->n_src, fan->src_xyz, fan->ray_src, fan->dirs,
+                           d_box, d_gbox, d_mem, S.n_groups, sc->panels, sc->max_refl, sc->s_max, sc->image_complete, nseg, bad,
                            nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     GBS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_trace_face_counts, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st, n, nseg, nface);
@@ -1024,7 +1014,8 @@ std::pair<int64_t, int64_t> trace_impl(gbs_ctx* ctx, const gbs_scene* sc, const 
     GBS_HIP(hipMemcpyAsync(&tot[1], fbase + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     GBS_HIP(hipMemcpyAsync(&h_bad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
     GBS_HIP(hipStreamSynchronize(st));
-    GBS_CHECK(!h_bad, "fan.dirs must be unit vectors");
+    GBS_CHECK(!(h_bad & 1), "fan.dirs must be unit vectors");
+    GBS_CHECK(!(h_bad & 2), "fan.ray_src must be non-decreasing and in [0, n_src)");
     if (!out) return {tot[0], tot[1]};
     GBS_CHECK(tot[0] <= cap_segs && tot[1] <= cap_faces,
               "table capacity too small: needs " + std::to_string(tot[0]) + " segments and " +
@@ -1034,8 +1025,8 @@ std::pair<int64_t, int64_t> trace_impl(gbs_ctx* ctx, const gbs_scene* sc, const 
     GBS_CHECK(tot[1] == 0 || out->face_ids, "face_ids must be non-null");
     GBS_CHECK(out->face_ptr, "face_ptr must be non-null");
     if (n > 0)
-        hipLaunchKernelGGL(k_trace<false>, grid, block, 0, st, n, fan->src_xyz, fan->ray_src, fan->dirs, d_box,
-                           d_gbox, d_mem, S.n_groups, sc->panels, sc->max_refl, sc->s_max, sc->image_complete,
+        hipLaunchKernelGGL(k_trace<false>, grid, block, 0, st, n, fan->n_src, fan->src_xyz, fan->ray_src,
+                           fan->dirs, d_box, d_gbox, d_mem, S.n_groups, sc->panels, sc->max_refl, sc->s_max, sc->image_complete,
                            nullptr, nullptr, rp, fbase, out->a, out->t, out->s0, out->lo, out->hi, out->face_ptr,
                            out->face_ids);
     hipLaunchKernelGGL(k_trace_close, dim3(1), dim3(64), 0, st, fbase, n, tot[0], out->face_ptr);

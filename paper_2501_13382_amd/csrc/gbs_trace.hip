@@ -84,8 +84,9 @@ __device__ __forceinline__ int32_t face_of(int32_t box, const double* bx, int ax
 
 }  // namespace
 
-// One thread per ray.  COUNT: nseg[i] = segments of ray i (and bad[0] is set
-// for a direction that is not a unit vector).  Otherwise the segments are
+// One thread per ray.  COUNT: nseg[i] = segments of ray i; bad[0] gets bit 0
+// for a direction that is not a unit vector, bit 1 for a source index out of
+// range or out of order (the index is clamped for the reads meanwhile).  Otherwise the segments are
 // written from ray_ptr[i]; their face histories from face_base[i] (segment j
 // of a ray holds j faces, at face_base + j (j - 1) / 2).
 //   boxes   [n_boxes * 5] x0, x1, y0, y1, h in the caller's order
@@ -93,7 +94,7 @@ __device__ __forceinline__ int32_t face_of(int32_t box, const double* bx, int ax
 //   members [n_groups * kTraceGroup] box index per group slot (-1 = empty)
 template <bool COUNT>
 __global__ __launch_bounds__(kTraceThreads) void k_trace(
-    int64_t n_rays, const double* __restrict__ src_xyz, const int32_t* __restrict__ ray_src,
+    int64_t n_rays, int n_src, const double* __restrict__ src_xyz, const int32_t* __restrict__ ray_src,
     const double* __restrict__ dirs, const double* __restrict__ boxes, const double* __restrict__ gbox,
     const int32_t* __restrict__ members, int n_groups, int panels, int max_refl, double s_max, int image_complete,
     int64_t* __restrict__ nseg, int* __restrict__ bad, const int64_t* __restrict__ ray_ptr,
@@ -104,12 +105,15 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace(
     const int64_t i = (int64_t)blockIdx.x * kTraceThreads + threadIdx.x;
     const bool live = i < n_rays;
     const int64_t ii = live ? i : 0;
-    const int sidx = ray_src ? ray_src[ii] : 0;
+    const int sraw = ray_src ? ray_src[ii] : 0;
+    const int sidx = sraw < 0 ? 0 : (sraw >= n_src ? n_src - 1 : sraw);
     const double src[3] = {src_xyz[3 * sidx], src_xyz[3 * sidx + 1], src_xyz[3 * sidx + 2]};
     const double d0[3] = {dirs[3 * ii], dirs[3 * ii + 1], dirs[3 * ii + 2]};
     if (COUNT && live) {
         const double n2 = d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2];
-        if (!(fabs(n2 - 1.0) <= 1e-9)) bad[0] = 1;
+        int flag = fabs(n2 - 1.0) <= 1e-9 ? 0 : 1;
+        if (sraw != sidx || (ray_src && ii > 0 && ray_src[ii - 1] > sraw)) flag |= 2;
+        if (flag) atomicOr(bad, flag);
     }
     double p[3] = {src[0], src[1], src[2]};
     double d[3] = {d0[0], d0[1], d0[2]};
@@ -245,11 +249,11 @@ __global__ void k_trace_close(const int64_t* __restrict__ face_base, int64_t n_r
     if (blockIdx.x == 0 && threadIdx.x == 0) face_ptr[n_segs] = face_base[n_rays];
 }
 
-template __global__ void k_trace<true>(int64_t, const double*, const int32_t*, const double*, const double*,
+template __global__ void k_trace<true>(int64_t, int, const double*, const int32_t*, const double*, const double*,
                                        const double*, const int32_t*, int, int, int, double, int, int64_t*, int*,
                                        const int64_t*, const int64_t*, double*, double*, double*, double*, double*,
                                        int64_t*, int32_t*);
-template __global__ void k_trace<false>(int64_t, const double*, const int32_t*, const double*, const double*,
+template __global__ void k_trace<false>(int64_t, int, const double*, const int32_t*, const double*, const double*,
                                         const double*, const int32_t*, int, int, int, double, int, int64_t*, int*,
                                         const int64_t*, const int64_t*, double*, double*, double*, double*, double*,
                                         int64_t*, int32_t*);

@@ -119,6 +119,8 @@ def test_invalid_requests_rejected():
         gbs.trace(np.array([[40.0, 40.0, -1.0]]), d, w, s_max=100.0)
     with pytest.raises(_lib.GbsError):
         gbs.trace(np.concatenate([src, src]), d, w, ray_src=np.array([1] * 5 + [0] * 5), s_max=100.0)
+    with pytest.raises(_lib.GbsError):
+        gbs.trace(src, d, w, ray_src=np.array([0] * 5 + [1] * 5), s_max=100.0)     # one source only
     bad = city.boxes.copy()
     bad[0, 1] = bad[0, 0]
     with pytest.raises(_lib.GbsError):
