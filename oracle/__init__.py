@@ -3,7 +3,10 @@
 TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
 baseline leg may use this package; the library under test never does.  The C
 source (gbs_oracle.c) is the plain definition of the sum (paper Sec. 2,
-Eqs. (1)-(3)); this module only marshals numpy arrays to it and builds it.
+Eqs. (1)-(3)), with an optional per-job atmospheric absorption exp(-alpha s)
+(the atmosphere of Tables 2 and 3 through ISO 9613-1); this module only
+marshals numpy arrays to it and builds it.  oracle/tracer.py is the oracle
+of the ray-tracing stage.
 """
 from __future__ import annotations
 
@@ -37,11 +40,13 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
-        common = [i32, i64, P, P, P, i64, P, P, P, P, P, P, P, i32, P, i64, P, i32, P, P, f64, f64]
+        common = [i32, i64, P, P, P, i64, P, P, P, P, P, P, P, i32, P, i64, P, i32, P, P, P, f64, f64]
         lib.gbso_forward.argtypes = common + [i32, i32, P, P, P, P]
         lib.gbso_forward.restype = ctypes.c_int
         lib.gbso_backward.argtypes = common + [P, i32, P, P, P, P]
         lib.gbso_backward.restype = ctypes.c_int
+        lib.gbso_air_absorption_db.argtypes = [f64, f64, f64, f64]
+        lib.gbso_air_absorption_db.restype = f64
         _lib = lib
     return _lib
 
@@ -50,7 +55,7 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
 
 
-def _table_args(table, gamma, rcv, freqs, eps, c, gate):
+def _table_args(table, gamma, rcv, freqs, eps, c, gate, alpha=None):
     arrs = dict(
         ray_ptr=np.ascontiguousarray(table.ray_ptr, np.int64),
         ray_w=np.ascontiguousarray(table.ray_w, np.float64),
@@ -66,29 +71,33 @@ def _table_args(table, gamma, rcv, freqs, eps, c, gate):
         rcv=np.ascontiguousarray(rcv, np.float64).reshape(-1, 3),
         freqs=np.ascontiguousarray(freqs, np.float64).reshape(-1),
         eps=np.ascontiguousarray(eps, np.float64).reshape(-1),
+        alpha=None if alpha is None else np.ascontiguousarray(alpha, np.float64).reshape(-1),
     )
     if arrs["eps"].shape[0] != table.n_src * arrs["freqs"].shape[0]:
         raise ValueError("eps must hold one value per (source, band) job")
+    if arrs["alpha"] is not None and arrs["alpha"].shape[0] != arrs["eps"].shape[0]:
+        raise ValueError("alpha must hold one value per (source, band) job")
     if len(gamma) != table.n_faces:
         raise ValueError("gamma must hold one coefficient per face")
     args = [table.n_src, table.n_rays, _ptr(arrs["ray_ptr"]), _ptr(arrs["ray_w"]), _ptr(arrs["ray_src"]),
             table.n_segs, _ptr(arrs["a"]), _ptr(arrs["t"]), _ptr(arrs["s0"]), _ptr(arrs["lo"]), _ptr(arrs["hi"]),
             _ptr(arrs["face_ptr"]), _ptr(arrs["face_ids"]), table.n_faces, _ptr(arrs["gamma"]),
             arrs["rcv"].shape[0], _ptr(arrs["rcv"]), arrs["freqs"].shape[0], _ptr(arrs["freqs"]),
-            _ptr(arrs["eps"]), float(c), float(gate)]
+            _ptr(arrs["eps"]), _ptr(arrs["alpha"]), float(c), float(gate)]
     return args, arrs
 
 
 def forward(table, gamma, rcv, freqs, eps, c=343.0, gate=9.21, n_threads=1, mask_mode=0, mask=None,
-            return_absum=False):
+            return_absum=False, alpha=None):
     """P [n_jobs, n_rcv] complex128 and TL [n_jobs, n_rcv] float64.
 
     mask_mode 1 records the active (job, receiver, segment) set into `mask`
     (uint8, shape [n_jobs, n_rcv, n_segs]); mask_mode 2 evaluates with that set
     frozen instead of the gate.  return_absum adds sum |u| per output (the
-    scale against which cancellation in P is judged).
+    scale against which cancellation in P is judged).  alpha: atmospheric
+    absorption per job in Np/m (amplitude factor exp(-alpha s)), or None.
     """
-    args, arrs = _table_args(table, gamma, rcv, freqs, eps, c, gate)
+    args, arrs = _table_args(table, gamma, rcv, freqs, eps, c, gate, alpha)
     n_jobs = table.n_src * arrs["freqs"].shape[0]
     n_rcv = arrs["rcv"].shape[0]
     P = np.zeros((n_jobs, n_rcv, 2), np.float64)
@@ -105,12 +114,12 @@ def forward(table, gamma, rcv, freqs, eps, c=343.0, gate=9.21, n_threads=1, mask
     return P[..., 0] + 1j * P[..., 1], TL
 
 
-def backward(table, gamma, rcv, freqs, eps, lam, c=343.0, gate=9.21, mask_mode=0, mask=None):
+def backward(table, gamma, rcv, freqs, eps, lam, c=343.0, gate=9.21, mask_mode=0, mask=None, alpha=None):
     """Hand adjoint for dL = Re sum lam * dP.
 
     Returns (d_gamma [n_faces, 2] = (dL/dRe, dL/dIm), d_rcv [n_rcv, 3],
     d_eps [n_jobs])."""
-    args, arrs = _table_args(table, gamma, rcv, freqs, eps, c, gate)
+    args, arrs = _table_args(table, gamma, rcv, freqs, eps, c, gate, alpha)
     n_jobs = table.n_src * arrs["freqs"].shape[0]
     n_rcv = arrs["rcv"].shape[0]
     lam = np.asarray(lam, np.complex128).reshape(n_jobs, n_rcv)
@@ -125,8 +134,20 @@ def backward(table, gamma, rcv, freqs, eps, lam, c=343.0, gate=9.21, mask_mode=0
     return d_gamma, d_rcv, d_eps
 
 
-def scene_forward(scene, rcv=None, gamma=None, eps=None, n_threads=1, return_absum=False):
+def scene_forward(scene, rcv=None, gamma=None, eps=None, n_threads=1, return_absum=False, alpha=None):
     """Forward on a scenes.Scene (optionally a receiver subset / other gamma)."""
     return forward(scene.table, scene.gamma if gamma is None else gamma, scene.rcv if rcv is None else rcv,
                    scene.freqs, scene.eps if eps is None else eps, c=scene.c, gate=scene.gate,
-                   n_threads=n_threads, return_absum=return_absum)
+                   n_threads=n_threads, return_absum=return_absum, alpha=alpha)
+
+
+def air_absorption_db(freqs, temp_c=20.0, rh=70.0, p_atm=1.0):
+    """Pure-tone atmospheric attenuation (ISO 9613-1) in dB/m per frequency."""
+    lib = _load()
+    return np.array([lib.gbso_air_absorption_db(float(f), float(temp_c), float(rh), float(p_atm))
+                     for f in np.atleast_1d(np.asarray(freqs, np.float64))])
+
+
+def air_absorption(freqs, temp_c=20.0, rh=70.0, p_atm=1.0):
+    """The same as an amplitude decay rate alpha in Np/m: |p| ~ exp(-alpha s)."""
+    return air_absorption_db(freqs, temp_c, rh, p_atm) * np.log(10.0) / 20.0

@@ -34,6 +34,11 @@
  *   u     = (i k w_j / (8 pi^2)) * prod Gamma * (q0 / q) * exp(E)
  *   P(R)  = sum_j u,   TL = -20 log10 |P|
  *
+ * Atmospheric absorption (optional, per job): the pressure amplitude of a
+ * beam decays as exp(-alpha s) along its arc length, alpha in Np/m (the
+ * paper's atmosphere of Tables 2 and 3: temperature, humidity, pressure;
+ * alpha from the pure-tone attenuation of ISO 9613-1, gbso_air_absorption_db).
+ *
  * Sums are Neumaier-compensated, in table order.  Jobs are (source, band)
  * pairs, job = src * n_freq + band; eps is given per job.  Optionally the
  * sum of |u| is returned: |P| / sum |u| measures the cancellation in the sum
@@ -131,8 +136,9 @@ int gbso_forward(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const do
                  const int32_t* ray_src, int64_t n_segs, const double* seg_a, const double* seg_t,
                  const double* seg_s0, const double* seg_lo, const double* seg_hi, const int64_t* face_ptr,
                  const int32_t* face_ids, int32_t n_faces, const double* gamma, int64_t n_rcv,
-                 const double* rcv, int32_t n_freq, const double* freqs, const double* eps, double c,
-                 double gate_G, int32_t n_threads, int32_t mask_mode, uint8_t* mask, double* P_out,
+                 const double* rcv, int32_t n_freq, const double* freqs, const double* eps,
+                 const double* alpha, double c, double gate_G, int32_t n_threads, int32_t mask_mode,
+                 uint8_t* mask, double* P_out,
                  double* TL_out, double* absum_out) {
     (void)n_faces;
     if (n_src < 0 || n_rays < 0 || n_segs < 0 || n_rcv < 0 || n_freq < 0 || c <= 0) return -1;
@@ -148,6 +154,7 @@ int gbso_forward(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const do
             const double omega = 2.0 * PI * freqs[b];
             const double k = omega / c;
             const double e = eps[job];
+            const double al = alpha ? alpha[job] : 0.0;
 #pragma omp parallel for schedule(dynamic, 16) if (n_threads != 1)
             for (int64_t r = 0; r < n_rcv; ++r) {
                 const double* R = rcv + 3 * r;
@@ -166,7 +173,8 @@ int gbso_forward(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const do
                         if (mask_mode == 2) active = mask[(job * n_rcv + r) * n_segs + j];
                         if (!active) continue;
                         cplx q0 = -I * e;
-                        cplx u = weight * face_product(face_ptr, face_ids, gamma, j) * (q0 / q) * cexp(E);
+                        cplx u = weight * face_product(face_ptr, face_ids, gamma, j) * (q0 / q) * cexp(E) *
+                                 exp(-al * g.s);
                         nsum_add(&re, creal(u));
                         nsum_add(&im, cimag(u));
                         nsum_add(&ab, cabs(u));
@@ -187,7 +195,7 @@ int gbso_forward(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const do
 /*
  * Hand-derived adjoint.  With dL = Re sum_{job,r} lambda[job,r] dP[job,r]:
  *
- *   d ln u / dR   = t (ik - 1/q - (ik/2) n^2 / q^2) + (ik/q) nvec,
+ *   d ln u / dR   = t (ik - 1/q - (ik/2) n^2 / q^2 - alpha) + (ik/q) nvec,
  *                   nvec = (R - a) - sigma t   (dq/dR = t, d(n^2)/dR = 2 nvec)
  *   d ln u / deps = 1/eps + i/q - (k/2) n^2 / q^2
  *                   (weight*q0 is proportional to eps; dq/deps = -i)
@@ -206,8 +214,9 @@ int gbso_backward(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const d
                   const int32_t* ray_src, int64_t n_segs, const double* seg_a, const double* seg_t,
                   const double* seg_s0, const double* seg_lo, const double* seg_hi, const int64_t* face_ptr,
                   const int32_t* face_ids, int32_t n_faces, const double* gamma, int64_t n_rcv,
-                  const double* rcv, int32_t n_freq, const double* freqs, const double* eps, double c,
-                  double gate_G, const double* lambda, int32_t mask_mode, const uint8_t* mask,
+                  const double* rcv, int32_t n_freq, const double* freqs, const double* eps,
+                  const double* alpha, double c, double gate_G, const double* lambda, int32_t mask_mode,
+                  const uint8_t* mask,
                   double* d_gamma, double* d_rcv, double* d_eps) {
     if (n_src < 0 || n_rays < 0 || n_segs < 0 || n_rcv < 0 || n_freq < 0 || c <= 0) return -1;
     if (mask_mode == 2 && mask == NULL) return -1;
@@ -220,6 +229,7 @@ int gbso_backward(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const d
             const double omega = 2.0 * PI * freqs[b];
             const double k = omega / c;
             const double e = eps[job];
+            const double al = alpha ? alpha[job] : 0.0;
             double deps_job = 0.0;
             for (int64_t r = 0; r < n_rcv; ++r) {
                 const double* R = rcv + 3 * r;
@@ -238,12 +248,12 @@ int gbso_backward(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const d
                         if (mask_mode == 2) active = mask[(job * n_rcv + r) * n_segs + j];
                         if (!active) continue;
                         cplx q0 = -I * e;
-                        cplx bare = weight * (q0 / q) * cexp(E);      /* beam term without prod Gamma */
+                        cplx bare = weight * (q0 / q) * cexp(E) * exp(-al * g.s);   /* without prod Gamma */
                         cplx gp = face_product(face_ptr, face_ids, gamma, j);
                         cplx u = gp * bare;
                         /* receiver gradient */
                         double nvec[3] = {g.v[0] - g.sigma * t[0], g.v[1] - g.sigma * t[1], g.v[2] - g.sigma * t[2]};
-                        cplx ct = I * k - 1.0 / q - 0.5 * I * k * g.n2 / (q * q);
+                        cplx ct = I * k - 1.0 / q - 0.5 * I * k * g.n2 / (q * q) - al;
                         cplx cn = I * k / q;
                         for (int d = 0; d < 3; ++d) d_rcv[3 * r + d] += creal(lam * u * (ct * t[d] + cn * nvec[d]));
                         /* beam-parameter gradient */
@@ -271,4 +281,28 @@ int gbso_backward(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const d
     return 0;
 }
 
-int gbso_version(void) { return 1; }
+/*
+ * Pure-tone atmospheric attenuation coefficient in dB per metre (ISO 9613-1,
+ * its Eqs. for the molar concentration of water vapour, the oxygen and
+ * nitrogen relaxation frequencies and the attenuation), for frequency f (Hz),
+ * air temperature temp_c (deg C), relative humidity rh (%) and pressure
+ * p_atm (atmospheres).  The paper's runs use 20 deg C, 70 % and 1 atm.
+ */
+double gbso_air_absorption_db(double f, double temp_c, double rh, double p_atm) {
+    const double T = temp_c + 273.15;       /* K */
+    const double T0 = 293.15;               /* reference air temperature */
+    const double T01 = 273.16;              /* triple-point isotherm */
+    const double pa = p_atm;                /* pressure relative to 101.325 kPa */
+    const double C = -6.8346 * pow(T01 / T, 1.261) + 4.6151;
+    const double psat = pow(10.0, C);       /* saturation vapour pressure / reference */
+    const double h = rh * psat / pa;        /* molar concentration of water vapour (%) */
+    const double frO = pa * (24.0 + 4.04e4 * h * (0.02 + h) / (0.391 + h));
+    const double frN = pa * pow(T / T0, -0.5) * (9.0 + 280.0 * h * exp(-4.170 * (pow(T / T0, -1.0 / 3.0) - 1.0)));
+    const double f2 = f * f;
+    return 8.686 * f2 *
+           (1.84e-11 / pa * sqrt(T / T0) +
+            pow(T / T0, -2.5) * (0.01275 * exp(-2239.1 / T) / (frO + f2 / frO) +
+                                 0.1068 * exp(-3352.0 / T) / (frN + f2 / frN)));
+}
+
+int gbso_version(void) { return 2; }
