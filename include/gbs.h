@@ -15,6 +15,7 @@
  *   u   = (i k w / (8 pi^2)) prod(Gamma) (-i eps / q) exp(i k s + (i k / 2) n^2 / q)
  * kept iff lo <= sigma < hi and the Gaussian factor exp(-(k eps/2) n^2/|q|^2)
  * is >= exp(-gate_G).  P(R) = sum over the kept pairs, TL = -20 log10 |P|.
+ * With atmospheric absorption (params.alpha) u also carries exp(-alpha s).
  * w is the launch solid angle of the segment's ray; prod(Gamma) the product of
  * the complex reflection coefficients of the faces the ray hit before the
  * segment.  A dense fan reproduces the unit monopole exp(ikr)/(4 pi r).
@@ -47,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GBS_VERSION 1
+#define GBS_VERSION 2
 
 typedef enum gbs_status {
     GBS_OK = 0,
@@ -111,6 +112,11 @@ typedef struct gbs_params {
     int32_t rcv_per_lane;     /* pair kernel receivers per lane: 0 auto, 1, 2, 4 */
     int32_t work_chunk;       /* segments per pair-kernel work unit: 0 auto, else
                                  a power of two in [256, 65536]                 */
+    const double* alpha;      /* [n_src * n_freq] atmospheric absorption per job
+                                 (Np/m, finite, >= 0; device memory), or NULL
+                                 for none: each beam's amplitude carries
+                                 exp(-alpha s) along its arc length s.  The gate
+                                 stays on the Gaussian factor alone.           */
 } gbs_params;
 
 /* Plan statistics of the last forward/backward call on a context. */
@@ -267,6 +273,18 @@ int gbs_trace_count(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, in
 int gbs_trace(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, int64_t cap_segs, int64_t cap_face_ids,
               int64_t* ray_ptr, double* seg_a, double* seg_t, double* seg_s0, double* seg_lo, double* seg_hi,
               int64_t* face_ptr, int32_t* face_ids, int64_t* n_segs, int64_t* n_face_ids);
+
+/*
+ * Atmospheric attenuation of a pure tone in dB per metre: the model of
+ * ISO 9613-1 (water-vapour concentration from the relative humidity, oxygen
+ * and nitrogen relaxation frequencies, classical and rotational absorption)
+ * for the atmosphere the paper's runs specify (Tables 2 and 3: temperature,
+ * relative humidity, pressure; 20 deg C, 70 %, 1 atm there).  As an
+ * amplitude decay rate for gbs_params.alpha: alpha = dB/m * ln(10) / 20.
+ * Host function; needs no context or device.  NaN for arguments outside
+ * f > 0, -100 < temp_c < 100, 0 <= rh_pct <= 100, pressure_atm > 0.
+ */
+double gbs_air_absorption_db(double f_hz, double temp_c, double rh_pct, double pressure_atm);
 
 /* Message describing the last error on ctx (never NULL). */
 const char* gbs_last_error(const gbs_ctx* ctx);

@@ -43,7 +43,7 @@ class GbsFaces(ctypes.Structure):
 
 class GbsParams(ctypes.Structure):
     _fields_ = [("c", c_double), ("gate_G", c_double), ("mode", c_int32), ("flags", c_int32),
-                ("chunk_segs", c_int64), ("rcv_per_lane", c_int32), ("work_chunk", c_int32)]
+                ("chunk_segs", c_int64), ("rcv_per_lane", c_int32), ("work_chunk", c_int32), ("alpha", c_void_p)]
 
 
 class GbsScene(ctypes.Structure):
@@ -67,7 +67,7 @@ class GbsStats(ctypes.Structure):
 
 EXPORTS = ("gbs_create", "gbs_destroy", "gbs_set_stream", "gbs_forward", "gbs_backward", "gbs_get_stats",
            "gbs_graph_create", "gbs_graph_launch", "gbs_graph_destroy", "gbs_autotune", "gbs_trace_count",
-           "gbs_trace", "gbs_last_error", "gbs_version")
+           "gbs_trace", "gbs_air_absorption_db", "gbs_last_error", "gbs_version")
 
 _lib = None
 
@@ -113,6 +113,8 @@ def load() -> ctypes.CDLL:
     lib.gbs_trace.argtypes = [c_void_p, P(GbsScene), P(GbsFan), c_int64, c_int64] + [c_void_p] * 8 + \
         [P(c_int64), P(c_int64)]
     lib.gbs_trace.restype = ctypes.c_int
+    lib.gbs_air_absorption_db.argtypes = [c_double, c_double, c_double, c_double]
+    lib.gbs_air_absorption_db.restype = c_double
     lib.gbs_last_error.argtypes = [c_void_p]
     lib.gbs_last_error.restype = ctypes.c_char_p
     lib.gbs_version.argtypes = []

@@ -280,7 +280,7 @@ struct Planner {
     const Args& a;
     int mode, nr;
     int n_jobs;
-    std::vector<double> h_freqs, h_eps;
+    std::vector<double> h_freqs, h_eps, h_alpha;
     std::vector<int64_t> src_off;     // [n_src + 1] first segment of each source
     std::vector<PassRange> passes;
     std::vector<int64_t> h_ray_ptr, h_face_ptr;  // host copies (only when chunking)
@@ -305,14 +305,20 @@ struct Planner {
     void read_job_inputs() {
         h_freqs.resize(a.n_freq);
         h_eps.resize(n_jobs);
+        h_alpha.assign(n_jobs, 0.0);
         if (a.n_freq > 0) {
             GBS_HIP(hipMemcpyAsync(h_freqs.data(), a.freqs, sizeof(double) * a.n_freq, hipMemcpyDeviceToHost, st));
-            if (n_jobs > 0)
+            if (n_jobs > 0) {
                 GBS_HIP(hipMemcpyAsync(h_eps.data(), a.eps, sizeof(double) * n_jobs, hipMemcpyDeviceToHost, st));
+                if (a.params->alpha)
+                    GBS_HIP(hipMemcpyAsync(h_alpha.data(), a.params->alpha, sizeof(double) * n_jobs,
+                                           hipMemcpyDeviceToHost, st));
+            }
             GBS_HIP(hipStreamSynchronize(st));
         }
         for (double f : h_freqs) GBS_CHECK(std::isfinite(f) && f > 0, "frequencies must be finite and > 0");
         for (double e : h_eps) GBS_CHECK(std::isfinite(e) && e > 0, "eps must be finite and > 0");
+        for (double al : h_alpha) GBS_CHECK(std::isfinite(al) && al >= 0, "alpha must be finite and >= 0");
     }
 
     void source_offsets() {
@@ -449,6 +455,8 @@ struct Planner {
                 j.gexp2 = -0.5 * ke * 1.4426950408889634;
                 j.gexp = -0.5 * ke;
                 j.scale = ke / (8.0 * pi * pi);
+                j.aexp = -h_alpha[s * a.n_freq + b];
+                j.aexp2 = j.aexp * 1.4426950408889634;
                 j.src = s;
                 j.band = b;
             }
@@ -1040,6 +1048,25 @@ std::pair<int64_t, int64_t> trace_impl(gbs_ctx* ctx, const gbs_scene* sc, const 
 extern "C" {
 
 int gbs_version(void) { return GBS_VERSION; }
+
+// ISO 9613-1 pure-tone attenuation: molar concentration of water vapour h
+// from the saturation pressure over the triple-point isotherm, relaxation
+// frequencies of oxygen (frO) and nitrogen (frN), then the classical plus
+// rotational term and the two vibrational relaxation terms, in dB/m.
+double gbs_air_absorption_db(double f_hz, double temp_c, double rh_pct, double pressure_atm) {
+    if (!(f_hz > 0) || !(temp_c > -100 && temp_c < 100) || !(rh_pct >= 0 && rh_pct <= 100) || !(pressure_atm > 0))
+        return NAN;
+    const double T = temp_c + 273.15, tr = T / 293.15, pr = pressure_atm;
+    const double psat_rel = std::pow(10.0, 4.6151 - 6.8346 * std::pow(273.16 / T, 1.261));
+    const double h = rh_pct * psat_rel / pr;
+    const double fro = pr * (24.0 + 4.04e4 * h * (0.02 + h) / (0.391 + h));
+    const double frn = pr / std::sqrt(tr) * (9.0 + 280.0 * h * std::exp(-4.170 * (std::cbrt(1.0 / tr) - 1.0)));
+    const double ff = f_hz * f_hz;
+    const double classical = 1.84e-11 * std::sqrt(tr) / pr;
+    const double vib = std::pow(tr, -2.5) * (0.01275 * std::exp(-2239.1 / T) * fro / (fro * fro + ff) +
+                                             0.1068 * std::exp(-3352.0 / T) * frn / (frn * frn + ff));
+    return 8.686 * ff * (classical + vib);
+}
 
 int gbs_create(gbs_ctx** out, int device, void* hip_stream) {
     if (!out) return GBS_E_INVALID;

@@ -28,6 +28,8 @@ struct JobConst {
     double gexp2;        // -(k eps / 2) log2(e): Gaussian exponent in base 2 per n^2/den
     double gexp;         // -(k eps / 2)
     double scale;        // k eps / (8 pi^2): weight factored out of the per-job sum
+    double aexp;         // -alpha: atmospheric absorption exponent per metre of arc length
+    double aexp2;        // -alpha log2(e)
     int32_t src;
     int32_t band;
 };

@@ -692,7 +692,7 @@ struct Beam<kF64> {
         const double ph = cyc - floor(cyc);
         double sn, cs;
         sincospi(2.0 * ph, &sn, &cs);
-        const double w = live ? rden * exp(a * J.gexp) : 0.0;
+        const double w = live ? rden * exp(fma(s, J.aexp, a * J.gexp)) : 0.0;   // Gaussian and absorption
         const double cr = fma(s, S.wgr, -J.eps * S.wgi) * w;
         const double ci = fma(s, S.wgi, J.eps * S.wgr) * w;
         ur = cr * cs - ci * sn;
@@ -721,10 +721,11 @@ struct Beam<kMIX> {
         const float ph = (float)__builtin_amdgcn_fract(cyc);                 // reduced modulo one in FP64
         const float sn = __builtin_amdgcn_sinf(ph);                          // sin(2 pi ph)
         const float cs = __builtin_amdgcn_cosf(ph);
-        const float g2 = live ? (float)(a * J.gexp2) : -INFINITY;           // Gaussian exponent, base 2
+        const float sf = (float)s;
+        // Gaussian and absorption exponents, base 2
+        const float g2 = live ? fmaf(sf, (float)J.aexp2, (float)(a * J.gexp2)) : -INFINITY;
         const float w = r0f * __builtin_amdgcn_exp2f(g2);
         const float4 W = tile_weights(S);
-        const float sf = (float)s;
         const float cr = fmaf(sf, W.x, -W.w) * w;
         const float ci = fmaf(sf, W.y, W.z) * w;
         ur = cr * cs - ci * sn;
@@ -751,7 +752,8 @@ struct Beam<kF32> {
         const float cyc = (float)J.fk * fmaf(0.5f * g.n2 * g.s, rden, g.s);
         const float ph = __builtin_amdgcn_fractf(cyc);
         const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
-        const float w = rden * __builtin_amdgcn_exp2f(live ? g.n2 * rden * (float)J.gexp2 : -INFINITY);
+        const float w =
+            rden * __builtin_amdgcn_exp2f(live ? fmaf(g.s, (float)J.aexp2, g.n2 * rden * (float)J.gexp2) : -INFINITY);
         const float4 W = tile_weights(S);
         const float cr = fmaf(g.s, W.x, -W.w) * w;
         const float ci = fmaf(g.s, W.y, W.z) * w;
@@ -1008,7 +1010,8 @@ __global__ void k_tl(const double* __restrict__ P, int64_t n, double* __restrict
 // ----------------------------------------------------------------- adjoint
 // Adjoint pair terms.  With u = scale * wG * B (forward term) and the
 // convention dL = Re sum lambda dP:
-//   d ln u/dR   = t (ik - 1/q - (ik/2) n^2/q^2) + (ik/q) nvec,  nvec = R - o - s t
+//   d ln u/dR   = t (ik - 1/q - (ik/2) n^2/q^2 - alpha) + (ik/q) nvec,  nvec = R - o - s t
+//   (alpha: the atmospheric absorption of the job, exp(-alpha s) in u)
 //   d ln u/deps = 1/eps + i/q - (k/2) n^2/q^2
 //   dP/dGamma_f = scale * sum_j d(prod Gamma_j)/dGamma_f * w_j * B_j
 // With 1/q = (s + i eps) rden and 1/q^2 = (s^2 - eps^2 + 2 i eps s) rden^2.
@@ -1021,13 +1024,13 @@ struct AdjTerms {
 };
 
 template <typename T>
-__device__ __forceinline__ void adj_factors(T s, T n2, T rden, T eps, T k, AdjTerms<T>& A) {
+__device__ __forceinline__ void adj_factors(T s, T n2, T rden, T eps, T k, T aexp, AdjTerms<T>& A) {
     T r2d = rden * rden;
     T iq_r = s * rden, iq_i = eps * rden;                              // 1/q
     T iq2_r = (s * s - eps * eps) * r2d, iq2_i = 2 * eps * s * r2d;    // 1/q^2
     T hk = (T)0.5 * k * n2;
-    // ik - 1/q - (ik/2) n^2/q^2 : (ik/2)n^2/q^2 = hk*(i*iq2_r - iq2_i)
-    A.ctr = -iq_r + hk * iq2_i;
+    // ik - 1/q - (ik/2) n^2/q^2 - alpha : (ik/2)n^2/q^2 = hk*(i*iq2_r - iq2_i)
+    A.ctr = -iq_r + hk * iq2_i + aexp;
     A.cti = k - iq_i - hk * iq2_r;
     // ik/q = i k (iq_r + i iq_i) = -k iq_i + i k iq_r
     A.cnr = -k * iq_i;
@@ -1073,9 +1076,9 @@ __device__ __forceinline__ bool adj_eval(const TileRec& S, const JobConst& J, do
         const double ph = cyc - floor(cyc);
         double sn, cs;
         sincospi(2.0 * ph, &sn, &cs);
-        const double w = rden * exp(a * J.gexp);
+        const double w = rden * exp(fma(s, J.aexp, a * J.gexp));
         AdjTerms<double> A;
-        adj_factors<double>(s, n2, rden, J.eps, J.k, A);
+        adj_factors<double>(s, n2, rden, J.eps, J.k, J.aexp, A);
         const double br = s * w, bi = J.eps * w;                  // (s + i eps) rden e^g
         A.Br = br * cs - bi * sn;
         A.Bi = br * sn + bi * cs;
@@ -1089,10 +1092,10 @@ __device__ __forceinline__ bool adj_eval(const TileRec& S, const JobConst& J, do
     } else {
         const float ph = (float)__builtin_amdgcn_fract(cyc);
         const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
-        const float w = r0f * __builtin_amdgcn_exp2f((float)(a * J.gexp2));
         const float sf = (float)s, epsf = (float)J.eps;
+        const float w = r0f * __builtin_amdgcn_exp2f(fmaf(sf, (float)J.aexp2, (float)(a * J.gexp2)));
         AdjTerms<float> A;
-        adj_factors<float>(sf, (float)n2, r0f, epsf, (float)J.k, A);
+        adj_factors<float>(sf, (float)n2, r0f, epsf, (float)J.k, (float)J.aexp, A);
         const float br = sf * w, bi = epsf * w;
         A.Br = br * cs - bi * sn;
         A.Bi = br * sn + bi * cs;

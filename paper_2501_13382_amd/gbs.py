@@ -134,20 +134,21 @@ def _gamma_ri(gamma, device):
 _TUNED = {}
 
 
-def _params(c, gate, mode, flags, chunk_segs, rcv_per_lane, work_chunk, device):
+def _params(c, gate, mode, flags, chunk_segs, rcv_per_lane, work_chunk, device, alpha=None):
     if mode not in _lib.MODES:
         raise ValueError(f"mode must be one of {sorted(_lib.MODES)}")
     tuned = _TUNED.get((_device_index(device), mode), {})
     nr = int(rcv_per_lane) or int(tuned.get("rcv_per_lane", 0))
     wc = int(work_chunk) or int(tuned.get("work_chunk", 0))
-    return _lib.GbsParams(float(c), float(gate), _lib.MODES[mode], int(flags), int(chunk_segs), nr, wc)
+    return _lib.GbsParams(float(c), float(gate), _lib.MODES[mode], int(flags), int(chunk_segs), nr, wc,
+                          _ptr(alpha) if alpha is not None else None)
 
 
 class _Call:
     """Marshalled arguments of one forward/backward call."""
 
     def __init__(self, table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, validate,
-                 count_active, time_kernels=False, work_chunk=0):
+                 count_active, time_kernels=False, work_chunk=0, alpha=None):
         if not isinstance(table, Table):
             raise TypeError("table must be a gbs.Table")
         dev = table.device
@@ -162,7 +163,12 @@ class _Call:
             raise ValueError("gamma must hold one coefficient per face")
         flags = (_lib.FLAG_TABLE_HOST if table.on_host else 0) | (_lib.FLAG_VALIDATE if validate else 0) | \
             (_lib.FLAG_COUNT_ACTIVE if count_active else 0) | (_lib.FLAG_TIME_KERNELS if time_kernels else 0)
-        self.params = _params(c, gate, mode, flags, chunk_segs, rcv_per_lane, work_chunk, dev)
+        self.alpha = None
+        if alpha is not None:
+            self.alpha = _as_tensor(alpha, torch.float64, dev).reshape(-1)
+            if self.alpha.numel() != self.eps.numel():
+                raise ValueError("alpha must hold one value per (source, band)")
+        self.params = _params(c, gate, mode, flags, chunk_segs, rcv_per_lane, work_chunk, dev, self.alpha)
         self.rays, self.segs = table.structs()
         self.faces = _lib.GbsFaces(table.n_faces, _ptr(self.gamma))
         self.n_rcv = int(self.rcv.shape[0])
@@ -175,14 +181,16 @@ class _Call:
 
 
 def forward(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix", chunk_segs=0,
-            rcv_per_lane=0, work_chunk=0, validate=False, count_active=False, time_kernels=False, want_tl=True):
+            rcv_per_lane=0, work_chunk=0, validate=False, count_active=False, time_kernels=False, want_tl=True,
+            alpha=None):
     """Beam summation.  Returns (P complex128 [n_src, n_freq, n_rcv],
     TL float64 of the same shape or None).  count_active / time_kernels fill
-    the statistics returned by stats()."""
+    the statistics returned by stats().  alpha: atmospheric absorption per
+    (source, band) in Np/m (see air_absorption), or None."""
     ctx = context(table.device)
     ctx.bind_stream()
     call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, validate, count_active,
-                 time_kernels, work_chunk)
+                 time_kernels, work_chunk, alpha)
     P = torch.empty(call.shape + (2,), dtype=torch.float64, device=table.device)
     TL = torch.empty(call.shape, dtype=torch.float64, device=table.device) if want_tl else None
     rc = ctx.lib.gbs_forward(*call.common(ctx), _ptr(P), _ptr(TL))
@@ -191,12 +199,12 @@ def forward(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="m
 
 
 def backward(table: Table, rcv, freqs, eps, gamma, lam, *, c=343.0, gate=9.21, mode="mix", chunk_segs=0,
-             validate=False):
+             validate=False, alpha=None):
     """Adjoint for dL = Re sum lam * dP.  Returns (d_gamma [n_faces, 2] as
     (dL/dRe, dL/dIm), d_rcv [n_rcv, 3], d_eps [n_src, n_freq])."""
     ctx = context(table.device)
     ctx.bind_stream()
-    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, 0, validate, False)
+    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, 0, validate, False, alpha=alpha)
     lam_t = lam if isinstance(lam, torch.Tensor) else torch.as_tensor(np.asarray(lam))
     lam_t = lam_t.to(device=table.device, dtype=torch.complex128).reshape(call.shape).contiguous()
     lam_ri = torch.view_as_real(lam_t).contiguous()
@@ -265,7 +273,7 @@ def _tune_key(table: Table, call, mode: str) -> str:
     return f"{arch}|{mode}|2^{int(math.log2(dense))}|bands{call.n_freq}|src{table.n_src}"
 
 
-def autotune(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix", cache=None):
+def autotune(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix", cache=None, alpha=None):
     """Times the pair-kernel shapes (receivers per lane x work-unit size) on
     this problem; later calls in `mode` that leave rcv_per_lane / work_chunk
     at 0 use the fastest.  With `cache` (a JSON file path) a stored choice for
@@ -273,7 +281,7 @@ def autotune(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="
     a new one is stored.  Returns {"rcv_per_lane": .., "work_chunk": ..}."""
     ctx = context(table.device)
     ctx.bind_stream()
-    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, 0, 0, False, False)
+    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, 0, 0, False, False, alpha=alpha)
     key = _tune_key(table, call, mode)
     store = {}
     if cache is not None and os.path.exists(cache):
@@ -297,6 +305,19 @@ def autotune(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="
     return dict(choice)
 
 
+def air_absorption(freqs, temp_c=20.0, rh_pct=70.0, pressure_atm=1.0) -> np.ndarray:
+    """Atmospheric absorption (ISO 9613-1, gbs_air_absorption_db) as the
+    amplitude decay rate alpha in Np/m for each frequency; the defaults are
+    the paper's atmosphere (Tables 2 and 3)."""
+    lib = _lib.load()
+    f = np.atleast_1d(np.asarray(freqs, np.float64))
+    db = np.array([lib.gbs_air_absorption_db(float(x), float(temp_c), float(rh_pct), float(pressure_atm))
+                   for x in f])
+    if not np.all(np.isfinite(db)):
+        raise ValueError("atmosphere or frequency out of range")
+    return db * (math.log(10.0) / 20.0)
+
+
 def stats(device="cuda") -> dict:
     return context(device).stats()
 
@@ -307,10 +328,11 @@ class Graph:
     coefficient tensor may be updated in place between replays."""
 
     def __init__(self, table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix", rcv_per_lane=0,
-                 chunk_segs=0):
+                 chunk_segs=0, alpha=None):
         self.ctx = context(table.device)
         self.stream = torch.cuda.Stream(device=table.device)
-        self.call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, False, False)
+        self.call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, False, False,
+                          alpha=alpha)
         self.gamma = self.call.gamma          # [n_faces, 2] device buffer read at every replay
         self.P = torch.empty(self.call.shape + (2,), dtype=torch.float64, device=table.device)
         self.TL = torch.empty(self.call.shape, dtype=torch.float64, device=table.device)
@@ -383,7 +405,7 @@ class GBSFunction(torch.autograd.Function):
             g = gTL.to(P.dtype)
             lam = lam - (20.0 / LN10) * torch.where(g != 0, g / torch.where(P != 0, P, torch.ones_like(P)),
                                                      torch.zeros_like(P))
-        opts = {k: v for k, v in ctx.opts.items() if k in ("c", "gate", "mode", "chunk_segs")}
+        opts = {k: v for k, v in ctx.opts.items() if k in ("c", "gate", "mode", "chunk_segs", "alpha")}
         dG, dR, dE = backward(ctx.table, rcv.detach(), ctx.freqs, eps.detach(), gamma.detach(), lam, **opts)
         g_gamma = torch.complex(dG[:, 0], dG[:, 1]).to(gamma.dtype) if ctx.needs_input_grad[0] else None
         g_rcv = dR.to(rcv.dtype).reshape(rcv.shape) if ctx.needs_input_grad[1] else None

@@ -28,14 +28,14 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(_lib.LIB_PATH)
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert _lib.load().gbs_version() == 1
+    assert _lib.load().gbs_version() == 2
 
 
 def test_struct_sizes_match_c_layout():
     assert ctypes.sizeof(_lib.GbsRays) == 40
     assert ctypes.sizeof(_lib.GbsSegs) == 64
     assert ctypes.sizeof(_lib.GbsFaces) == 16
-    assert ctypes.sizeof(_lib.GbsParams) == 40
+    assert ctypes.sizeof(_lib.GbsParams) == 48
     assert ctypes.sizeof(_lib.GbsStats) == 64
     assert ctypes.sizeof(_lib.GbsScene) == 32
     assert ctypes.sizeof(_lib.GbsFan) == 40
@@ -54,3 +54,23 @@ def test_create_without_gpu_fails_cleanly():
     assert rc in (_lib.GBS_E_INVALID, _lib.GBS_E_HIP)
     assert not h.value
     assert lib.gbs_last_error(None) == b"null context"
+
+
+def test_air_absorption_helper_matches_the_oracle():
+    """gbs_air_absorption_db is host code: callable without a device; it
+    agrees with the oracle's ISO 9613-1 coefficient and rejects bad input."""
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libgbs.so not built")
+    import math
+
+    import numpy as np
+
+    import oracle
+    lib = _lib.load()
+    f = np.geomspace(20.0, 20000.0, 25)
+    for T, rh, p in ((20.0, 70.0, 1.0), (-10.0, 30.0, 0.9), (35.0, 95.0, 1.05), (15.0, 0.0, 1.0)):
+        got = np.array([lib.gbs_air_absorption_db(x, T, rh, p) for x in f])
+        np.testing.assert_allclose(got, oracle.air_absorption_db(f, T, rh, p), rtol=1e-12)
+    for bad in ((0.0, 20.0, 70.0, 1.0), (1e3, 20.0, 120.0, 1.0), (1e3, 20.0, 70.0, 0.0)):
+        assert math.isnan(lib.gbs_air_absorption_db(*bad))
+
