@@ -16,7 +16,8 @@ never `value`), the adjoint call on the same workload, the error against the
 FP64 oracle on 16,384 seeded receivers, the oracle timed on this host's
 cores on that sample (and single-threaded on a smaller one), and the device
 ray tracer re-tracing the workload's fan (with the per-ray oracle tracer
-timed on a sample of rays).
+timed on a sample of rays), and the forward with atmospheric absorption in
+the paper's atmosphere.
 """
 from __future__ import annotations
 
@@ -54,9 +55,9 @@ PEAK_F32 = 157.3e12
 # FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy and fill (the summary in
 # profiles/k_pairs_mix_open_plane_100k.md).  Valid only for the kernel source
 # it was measured on; reported as null once that source changes.
-PAIR_TRAFFIC_BYTES = 3.270e9
-PAIR_TRAFFIC_SOURCE_MD5 = {"gbs_kernels.hip": "f15e00415105befacb42389e5f33eb95",
-                           "gbs_internal.h": "9400136ba77f2a392b463cb42f84b648"}
+PAIR_TRAFFIC_BYTES = 3.264e9
+PAIR_TRAFFIC_SOURCE_MD5 = {"gbs_kernels.hip": "ef22558239091d865b4432717cd3842b",
+                           "gbs_internal.h": "3552cb7fe25c1481260a0da36eb03e8b"}
 
 
 def pair_traffic():
@@ -87,6 +88,48 @@ def _city_batched():
 WORKLOADS = {"open_plane_100k": ("open_plane_100k_8band", _open_plane_100k),
              "city_1m": ("city_10x10_1m_rays_1024sq", _city_1m),
              "city_batched": ("city_batched_16src_4band_1024sq", _city_batched)}
+
+
+def absorption_bench(sc, dev, table, rcv, freqs, eps, gamma, args, sec_step):
+    """The same forward with atmospheric absorption in the paper's atmosphere
+    (Tables 2 and 3: 20 deg C, 70 % relative humidity, 1 atm; ISO 9613-1 per
+    band): time per step, and the error against the oracle with the same
+    absorption on a small seeded receiver sample."""
+    import torch
+
+    import paper_2501_13382_amd as gbs
+    from scenes import receiver_subsample
+    alpha_band = gbs.air_absorption(sc.freqs, 20.0, 70.0, 1.0)
+    alpha = np.tile(alpha_band, (sc.table.n_src, 1))
+    a_dev = torch.as_tensor(alpha, device=dev)
+    call = lambda: gbs.forward(table, rcv, freqs, eps, gamma, c=sc.c, gate=sc.gate, mode="mix", alpha=a_dev)
+    call()
+    torch.cuda.synchronize()
+    n = max(2, args.steps // 2)
+    t = time.perf_counter()
+    for _ in range(n):
+        P, TL = call()
+    torch.cuda.synchronize()
+    s_ab = (time.perf_counter() - t) / n
+    leg = {"value": sc.dense_pairs / s_ab, "ms_per_step": s_ab * 1e3, "overhead_vs_value": s_ab / sec_step - 1.0,
+           "atmosphere": {"temperature_c": 20.0, "humidity_pct": 70.0, "pressure_atm": 1.0},
+           "alpha_db_per_km": [float(a) * 20.0 / np.log(10.0) * 1e3 for a in alpha_band]}
+    print(f"# absorption: {s_ab * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+    if not args.no_cpu:
+        import oracle
+        n_cpu = int(min(1024, max(16, 4e9 / (sc.table.n_segs * len(sc.freqs)))))
+        idx = receiver_subsample(len(sc.rcv), n=n_cpu, seed=8)
+        threads = int(os.environ.get("OMP_NUM_THREADS", str(min(16, os.cpu_count() or 1))))
+        P_ref, TL_ref, ab = oracle.scene_forward(sc, rcv=sc.rcv[idx], n_threads=threads, return_absum=True,
+                                                 alpha=alpha)
+        Pg = P.cpu().numpy().reshape(-1, len(sc.rcv))[:, idx]
+        TLg = TL.cpu().numpy().reshape(-1, len(sc.rcv))[:, idx]
+        ok = ab / np.maximum(np.abs(P_ref), 1e-300) <= 1e4
+        leg["accuracy_vs_oracle"] = {
+            "tl_err_db_max": float(np.abs(TLg - TL_ref)[ok].max()),
+            "rel_err_max": float((np.abs(Pg - P_ref) / np.maximum(np.abs(P_ref), 1e-300))[ok].max()),
+            "receivers": int(len(idx))}
+    return leg
 
 
 def trace_bench(sc, dev, args):
@@ -168,6 +211,7 @@ def parse():
     ap.add_argument("--no-stream", action="store_true", help="skip the host-streamed table leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--no-trace", action="store_true", help="skip the device ray-tracing leg")
+    ap.add_argument("--no-absorption", action="store_true", help="skip the atmospheric-absorption leg")
     ap.add_argument("--workload", default="open_plane_100k", choices=sorted(WORKLOADS),
                     help="open_plane_100k (default, the headline); city_1m: 10 x 10 city, 1,000,000 rays, "
                          "1024 x 1024 receivers, 1 kHz; city_batched: 16 sources x 4 bands, ragged ray counts, "
@@ -297,6 +341,10 @@ def main():
     del graph
     print(f"# graph replay: {s_gr * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
 
+    absorption_leg = None
+    if not args.no_absorption:
+        absorption_leg = absorption_bench(sc, dev, table, rcv, freqs, eps, gamma, args, sec_step)
+
     trace_leg = None
     if not args.no_trace:
         trace_leg = trace_bench(sc, dev, args)
@@ -342,6 +390,7 @@ def main():
         "streamed": stream_leg,
         "adjoint": adj_leg,
         "trace": trace_leg,
+        "absorption": absorption_leg,
     }
 
     if args.copy_calibration > 0:

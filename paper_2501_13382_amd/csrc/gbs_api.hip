@@ -321,6 +321,12 @@ struct Planner {
         for (double al : h_alpha) GBS_CHECK(std::isfinite(al) && al >= 0, "alpha must be finite and >= 0");
     }
 
+    bool absorb() const {
+        for (double al : h_alpha)
+            if (al != 0.0) return true;
+        return false;
+    }
+
     void source_offsets() {
         const int32_t n_src = a.rays->n_src;
         const int64_t n_rays = a.rays->n_rays;
@@ -777,18 +783,27 @@ void dispatch_nr(int nr, gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, 
     else launch_pairs<MODE, 4, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na);
 }
 
-void dispatch_pairs(int mode, bool count, int nr, gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L,
-                    const RcvPlan& R, int64_t n_rcv, double* P, unsigned* ctr, unsigned long long* na) {
+template <int MODE>
+void dispatch_count(bool count, int nr, gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const RcvPlan& R,
+                    int64_t n_rcv, double* P, unsigned* ctr, unsigned long long* na) {
+    count ? dispatch_nr<MODE, true>(nr, ctx, st, L, R, n_rcv, P, ctr, na)
+          : dispatch_nr<MODE, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na);
+}
+
+// mode: GBS_MODE_*; absorb: some job has atmospheric absorption (the kernel
+// variant with the absorption exponent; the others skip it).
+void dispatch_pairs(int mode, bool absorb, bool count, int nr, gbs_ctx* ctx, hipStream_t st,
+                    const Planner::Lists& L, const RcvPlan& R, int64_t n_rcv, double* P, unsigned* ctr,
+                    unsigned long long* na) {
     GBS_CHECK(L.partial != nullptr, "work-unit partials not allocated");
-    if (mode == GBS_MODE_F64) {
-        count ? dispatch_nr<0, true>(nr, ctx, st, L, R, n_rcv, P, ctr, na)
-              : dispatch_nr<0, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na);
-    } else if (mode == GBS_MODE_MIX) {
-        count ? dispatch_nr<1, true>(nr, ctx, st, L, R, n_rcv, P, ctr, na)
-              : dispatch_nr<1, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na);
-    } else {
-        count ? dispatch_nr<2, true>(nr, ctx, st, L, R, n_rcv, P, ctr, na)
-              : dispatch_nr<2, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na);
+    const int m = (mode == GBS_MODE_F64 ? 0 : mode == GBS_MODE_MIX ? 1 : 2) | (absorb ? 4 : 0);
+    switch (m) {
+        case 0: dispatch_count<0>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
+        case 1: dispatch_count<1>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
+        case 2: dispatch_count<2>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
+        case 4: dispatch_count<4>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
+        case 5: dispatch_count<5>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
+        default: dispatch_count<6>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
     }
 }
 
@@ -862,7 +877,7 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
             if (L.n_items > 0 && L.total > 0) {
                 L.partial = ws.get<double>("partial", L.work_cap * nr * 64 * 2);
                 ev_pairs.begin(st);
-                dispatch_pairs(a.params->mode, count, nr, ctx, st, L, pl.R, a.n_rcv, P, ctr, na);
+                dispatch_pairs(a.params->mode, pl.absorb(), count, nr, ctx, st, L, pl.R, a.n_rcv, P, ctr, na);
                 stats.ms_pairs += ev_pairs.end(st);
             }
             if (overlap) GBS_HIP(hipEventRecord(ctx->released[pi % 2], st));
@@ -1179,7 +1194,8 @@ int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
                 double* Sseg = ws.get<double>("Sseg", 2 * std::max<int64_t>(nseg, 1));
                 fill(st, Sseg, 2 * nseg, 0.0);
                 if (L.n_items > 0 && L.total > 0) {
-                    auto kern = params->mode == GBS_MODE_F64 ? k_adjoint<0> : k_adjoint<1>;
+                    const bool f64 = params->mode == GBS_MODE_F64, ab = pl.absorb();
+                    auto kern = f64 ? (ab ? k_adjoint<4> : k_adjoint<0>) : (ab ? k_adjoint<5> : k_adjoint<1>);
                     double* part = ws.get<double>("adj_partial", L.work_cap * 64 * 3);
                     const int64_t grid = persistent_grid(ctx, (const void*)kern, L.work_cap);
                     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, ctr);
@@ -1282,7 +1298,7 @@ int gbs_graph_create(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, c
                     L.rec = rs;
                 }
                 L.partial = partial;
-                dispatch_pairs(params->mode, false, nr, ctx, st, L, pl.R, n_rcv, P, ctr, nullptr);
+                dispatch_pairs(params->mode, pl.absorb(), false, nr, ctx, st, L, pl.R, n_rcv, P, ctr, nullptr);
             }
             if (TL && n_out > 0)
                 hipLaunchKernelGGL(k_tl, dim3(blocks_for(n_out, 256)), dim3(256), 0, st, P, n_out, TL);

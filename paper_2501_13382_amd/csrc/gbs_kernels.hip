@@ -665,6 +665,9 @@ template <int MODE>
 struct Beam;
 
 constexpr int kF64 = 0, kMIX = 1, kF32 = 2;
+// Pair-kernel variants: the precision mode, plus kAbsorb when any job has
+// atmospheric absorption (without it the term skips the absorption exponent).
+constexpr int kAbsorb = 4;
 
 __device__ __forceinline__ float4 tile_weights(const TileRec& S) {
     return *reinterpret_cast<const float4*>(&S.wgr);
@@ -681,6 +684,7 @@ struct Beam<kF64> {
         const double rhs = fma(g.s * J.gate_c1, g.s, S.c2oo);
         return g.l <= rhs && g.s >= S.slo && g.s < S.shi;
     }
+    template <bool ABS>
     __device__ __forceinline__ static void term(const TileRec& S, const JobConst& J, const Geo& g, bool live,
                                                 double& ur, double& ui) {
         const double s = g.s;
@@ -692,7 +696,8 @@ struct Beam<kF64> {
         const double ph = cyc - floor(cyc);
         double sn, cs;
         sincospi(2.0 * ph, &sn, &cs);
-        const double w = live ? rden * exp(fma(s, J.aexp, a * J.gexp)) : 0.0;   // Gaussian and absorption
+        const double ge = ABS ? fma(s, J.aexp, a * J.gexp) : a * J.gexp;       // Gaussian (and absorption)
+        const double w = live ? rden * exp(ge) : 0.0;
         const double cr = fma(s, S.wgr, -J.eps * S.wgi) * w;
         const double ci = fma(s, S.wgi, J.eps * S.wgr) * w;
         ur = cr * cs - ci * sn;
@@ -708,6 +713,7 @@ struct Beam<kMIX> {
                                                 double R2, Geo& g) {
         return Beam<kF64>::gate(S, J, X, Y, Z, R2, g);
     }
+    template <bool ABS>
     __device__ __forceinline__ static void term(const TileRec& S, const JobConst& J, const Geo& g, bool live,
                                                 float& ur, float& ui) {
         const double s = g.s;
@@ -722,8 +728,9 @@ struct Beam<kMIX> {
         const float sn = __builtin_amdgcn_sinf(ph);                          // sin(2 pi ph)
         const float cs = __builtin_amdgcn_cosf(ph);
         const float sf = (float)s;
-        // Gaussian and absorption exponents, base 2
-        const float g2 = live ? fmaf(sf, (float)J.aexp2, (float)(a * J.gexp2)) : -INFINITY;
+        // Gaussian (and absorption) exponent, base 2
+        const float gg = (float)(a * J.gexp2);
+        const float g2 = live ? (ABS ? fmaf(sf, (float)J.aexp2, gg) : gg) : -INFINITY;
         const float w = r0f * __builtin_amdgcn_exp2f(g2);
         const float4 W = tile_weights(S);
         const float cr = fmaf(sf, W.x, -W.w) * w;
@@ -746,14 +753,15 @@ struct Beam<kF32> {
         g.den = fmaf(g.s, g.s, (float)J.eps2);
         return g.n2 <= (float)J.kappa * g.den && g.s >= (float)S.slo && g.s < (float)S.shi;
     }
+    template <bool ABS>
     __device__ __forceinline__ static void term(const TileRec& S, const JobConst& J, const Geo& g, bool live,
                                                 float& ur, float& ui) {
         const float rden = __builtin_amdgcn_rcpf(g.den);
         const float cyc = (float)J.fk * fmaf(0.5f * g.n2 * g.s, rden, g.s);
         const float ph = __builtin_amdgcn_fractf(cyc);
         const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
-        const float w =
-            rden * __builtin_amdgcn_exp2f(live ? fmaf(g.s, (float)J.aexp2, g.n2 * rden * (float)J.gexp2) : -INFINITY);
+        const float gg = g.n2 * rden * (float)J.gexp2;
+        const float w = rden * __builtin_amdgcn_exp2f(live ? (ABS ? fmaf(g.s, (float)J.aexp2, gg) : gg) : -INFINITY);
         const float4 W = tile_weights(S);
         const float cr = fmaf(g.s, W.x, -W.w) * w;
         const float ci = fmaf(g.s, W.y, W.z) * w;
@@ -766,13 +774,14 @@ struct Beam<kF32> {
 template <int MODE>
 __device__ __forceinline__ int pair_one(const TileRec& S, const JobConst& J, double X, double Y, double Z, double R2,
                                         double& ar, double& ai) {
-    using B = Beam<MODE>;
+    using B = Beam<MODE & 3>;
+    constexpr bool ABS = (MODE & kAbsorb) != 0;
     typename B::Geo g;
     const bool k0 = B::gate(S, J, X, Y, Z, R2, g);
     if (__ballot(k0) == 0ull) return 0;
     branch_barrier();
     typename B::T ur, ui;
-    B::term(S, J, g, k0, ur, ui);
+    B::template term<ABS>(S, J, g, k0, ur, ui);
     ar += (double)ur;
     ai += (double)ui;
     return k0;
@@ -784,7 +793,8 @@ __device__ __forceinline__ int pair_one(const TileRec& S, const JobConst& J, dou
 template <int MODE>
 __device__ __forceinline__ int pair_two(const TileRec& S0, const TileRec& S1, const JobConst& J, double X, double Y,
                                         double Z, double R2, double& ar, double& ai) {
-    using B = Beam<MODE>;
+    using B = Beam<MODE & 3>;
+    constexpr bool ABS = (MODE & kAbsorb) != 0;
     using T = typename B::T;
     typename B::Geo g0, g1;
     const bool k0 = B::gate(S0, J, X, Y, Z, R2, g0);
@@ -792,8 +802,8 @@ __device__ __forceinline__ int pair_two(const TileRec& S0, const TileRec& S1, co
     if (__ballot(k0 || k1) == 0ull) return 0;
     branch_barrier();
     T u0r, u0i, u1r, u1i;
-    B::term(S0, J, g0, k0, u0r, u0i);
-    B::term(S1, J, g1, k1, u1r, u1i);
+    B::template term<ABS>(S0, J, g0, k0, u0r, u0i);
+    B::template term<ABS>(S1, J, g1, k1, u1r, u1i);
     ar += (double)(u0r + u1r);
     ai += (double)(u0i + u1i);
     return (int)k0 + (int)k1;
@@ -902,7 +912,7 @@ __global__ __launch_bounds__(kPairThreads, GBS_PAIR_MIN_WAVES) void k_pairs(cons
         for (int64_t e0 = beg; e0 < end; e0 += kWave) {
             const int cnt = (int)min<int64_t>(kWave, end - e0);
             wave_lds_fence();
-            GBS_STAGE(MODE, my + lane, nx, J);
+            GBS_STAGE((MODE & 3), my + lane, nx, J);
             wave_lds_fence();
             GBS_REC_LOAD(nx, rec, idx_ahead);
             idx_ahead = lists[min(e0 + 2 * kWave + lane, end - 1)];
@@ -1023,14 +1033,15 @@ struct AdjTerms {
     T der, dei;      // d ln u/deps
 };
 
-template <typename T>
+template <typename T, bool ABS>
 __device__ __forceinline__ void adj_factors(T s, T n2, T rden, T eps, T k, T aexp, AdjTerms<T>& A) {
     T r2d = rden * rden;
     T iq_r = s * rden, iq_i = eps * rden;                              // 1/q
     T iq2_r = (s * s - eps * eps) * r2d, iq2_i = 2 * eps * s * r2d;    // 1/q^2
     T hk = (T)0.5 * k * n2;
     // ik - 1/q - (ik/2) n^2/q^2 - alpha : (ik/2)n^2/q^2 = hk*(i*iq2_r - iq2_i)
-    A.ctr = -iq_r + hk * iq2_i + aexp;
+    A.ctr = -iq_r + hk * iq2_i;
+    if (ABS) A.ctr += aexp;
     A.cti = k - iq_i - hk * iq2_r;
     // ik/q = i k (iq_r + i iq_i) = -k iq_i + i k iq_r
     A.cnr = -k * iq_i;
@@ -1052,6 +1063,7 @@ struct AdjAcc {
 template <int MODE, typename ST>
 __device__ __forceinline__ bool adj_eval(const TileRec& S, const JobConst& J, double X, double Y, double Z, double R2,
                                          ST lr, ST li, AdjAcc& acc, ST& Sr, ST& Si) {
+    constexpr bool ABS = (MODE & kAbsorb) != 0;
     Beam<kF64>::Geo g;
     const bool keep = Beam<kF64>::gate(S, J, X, Y, Z, R2, g);
     if (__ballot(keep) == 0ull) return false;    // wave-uniform skip
@@ -1062,7 +1074,7 @@ __device__ __forceinline__ bool adj_eval(const TileRec& S, const JobConst& J, do
     const double den = fma(s, s, J.eps2);
     double rden;
     float r0f = 0.f;
-    if (MODE == kF64) {
+    if ((MODE & 3) == kF64) {
         rden = 1.0 / den;
     } else {
         r0f = __builtin_amdgcn_rcpf((float)den);
@@ -1072,13 +1084,13 @@ __device__ __forceinline__ bool adj_eval(const TileRec& S, const JobConst& J, do
     const double a = n2 * rden;
     const double cyc = s * fma(J.hfk, a, J.fk);
     double gt, gn;
-    if (MODE == kF64) {
+    if ((MODE & 3) == kF64) {
         const double ph = cyc - floor(cyc);
         double sn, cs;
         sincospi(2.0 * ph, &sn, &cs);
-        const double w = rden * exp(fma(s, J.aexp, a * J.gexp));
+        const double w = rden * exp(ABS ? fma(s, J.aexp, a * J.gexp) : a * J.gexp);
         AdjTerms<double> A;
-        adj_factors<double>(s, n2, rden, J.eps, J.k, J.aexp, A);
+        adj_factors<double, ABS>(s, n2, rden, J.eps, J.k, J.aexp, A);
         const double br = s * w, bi = J.eps * w;                  // (s + i eps) rden e^g
         A.Br = br * cs - bi * sn;
         A.Bi = br * sn + bi * cs;
@@ -1093,9 +1105,10 @@ __device__ __forceinline__ bool adj_eval(const TileRec& S, const JobConst& J, do
         const float ph = (float)__builtin_amdgcn_fract(cyc);
         const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
         const float sf = (float)s, epsf = (float)J.eps;
-        const float w = r0f * __builtin_amdgcn_exp2f(fmaf(sf, (float)J.aexp2, (float)(a * J.gexp2)));
+        const float gg = (float)(a * J.gexp2);
+        const float w = r0f * __builtin_amdgcn_exp2f(ABS ? fmaf(sf, (float)J.aexp2, gg) : gg);
         AdjTerms<float> A;
-        adj_factors<float>(sf, (float)n2, r0f, epsf, (float)J.k, (float)J.aexp, A);
+        adj_factors<float, ABS>(sf, (float)n2, r0f, epsf, (float)J.k, (float)J.aexp, A);
         const float br = sf * w, bi = epsf * w;
         A.Br = br * cs - bi * sn;
         A.Bi = br * sn + bi * cs;
@@ -1150,7 +1163,7 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
     const int lane = threadIdx.x & (kWave - 1);
     TileRec* const my = tile[threadIdx.x / kWave];
     int32_t* const my_idx = tile_idx[threadIdx.x / kWave];
-    using ST = typename Beam<MODE>::T;                    // beam-term precision
+    using ST = typename Beam<MODE & 3>::T;                // beam-term precision
     const int n_work = __builtin_amdgcn_readfirstlane(*n_work_p);
     for (;;) {
         branch_barrier();
@@ -1175,7 +1188,7 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
         for (int64_t e0 = beg; e0 < end; e0 += kWave) {
             const int cnt = (int)min<int64_t>(kWave, end - e0);
             wave_lds_fence();
-            GBS_STAGE(MODE, my + lane, nx, J);
+            GBS_STAGE((MODE & 3), my + lane, nx, J);
             my_idx[lane] = seg_perm ? seg_perm[idx_cur] : idx_cur;   // table order for the segment sums
             wave_lds_fence();
             idx_cur = lists[min(e0 + kWave + lane, end - 1)];
@@ -1359,13 +1372,17 @@ GBS_INST_CULL_NB(0)
 GBS_INST_PAIRS_MODE(0)
 GBS_INST_PAIRS_MODE(1)
 GBS_INST_PAIRS_MODE(2)
-template __global__ void k_adjoint<0>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,
-                                      const int32_t*, const SegRec*, const double*, const double*, const double*,
-                                      const double*, const int32_t*, int64_t, const double*, double*,
-                                      const int32_t*, double*, double*);
-template __global__ void k_adjoint<1>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,
-                                      const int32_t*, const SegRec*, const double*, const double*, const double*,
-                                      const double*, const int32_t*, int64_t, const double*, double*,
-                                      const int32_t*, double*, double*);
+GBS_INST_PAIRS_MODE(4)
+GBS_INST_PAIRS_MODE(5)
+GBS_INST_PAIRS_MODE(6)
+#define GBS_INST_ADJ(M)                                                                                          \
+    template __global__ void k_adjoint<M>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,       \
+                                          const int32_t*, const SegRec*, const double*, const double*,            \
+                                          const double*, const double*, const int32_t*, int64_t, const double*,   \
+                                          double*, const int32_t*, double*, double*);
+GBS_INST_ADJ(0)
+GBS_INST_ADJ(1)
+GBS_INST_ADJ(4)
+GBS_INST_ADJ(5)
 
 }  // namespace gbs
