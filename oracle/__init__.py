@@ -151,3 +151,23 @@ def air_absorption_db(freqs, temp_c=20.0, rh=70.0, p_atm=1.0):
 def air_absorption(freqs, temp_c=20.0, rh=70.0, p_atm=1.0):
     """The same as an amplitude decay rate alpha in Np/m: |p| ~ exp(-alpha s)."""
     return air_absorption_db(freqs, temp_c, rh, p_atm) * np.log(10.0) / 20.0
+
+
+def impulse_response(table, gamma, rcv, df, bin0, n_bins, eps, n_fft, n_t, window=None, c=343.0, gate=9.21,
+                     alpha=None, n_threads=1):
+    """Broadband synthesis: the time-domain form of the beam sum.  The
+    spectrum is the forward sum at f_n = (bin0 + n) df, n < n_bins (eps and
+    alpha per (source, bin)); with the exp(-i omega t) convention of Eq. (1)
+    the real pressure at time t is (1/pi) Re of the integral of
+    P(omega) exp(-i omega t) over omega > 0, discretised as
+        h[m] = 2 df Re sum_n w_n P_n exp(-2 pi i f_n m dt),  dt = 1 / (n_fft df),
+    for m < n_t.  Evaluated with numpy's FFT of the zero-padded spectrum.
+    Returns h [n_src, n_rcv, n_t]."""
+    freqs = (bin0 + np.arange(n_bins)) * float(df)
+    P, _ = forward(table, gamma, rcv, freqs, eps, c=c, gate=gate, n_threads=n_threads, alpha=alpha)
+    n_rcv = np.asarray(rcv).reshape(-1, 3).shape[0]
+    P = P.reshape(table.n_src, n_bins, n_rcv)
+    w = np.ones(n_bins) if window is None else np.asarray(window, np.float64)
+    X = np.zeros((table.n_src, n_rcv, n_fft), np.complex128)
+    X[:, :, bin0:bin0 + n_bins] = np.transpose(P, (0, 2, 1)) * w[None, None, :]
+    return 2.0 * float(df) * np.real(np.fft.fft(X, axis=-1))[:, :, :n_t]
