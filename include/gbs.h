@@ -206,6 +206,30 @@ int gbs_autotune(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
                  const gbs_params* params, double* P, int32_t* rcv_per_lane, int32_t* work_chunk);
 
 /*
+ * Broadband synthesis (the time-domain form of Eq. (1); the paper steps its
+ * field in time, Table 2): the forward sum at the n_bins frequencies
+ * f_n = (bin0 + n) df, windowed and transformed to a real time signal per
+ * (source, receiver).  With the exp(-i omega t) convention,
+ *   h[src][r][m] = 2 df Re sum_n w_n P_n(src, r) exp(-2 pi i f_n m dt),
+ *   dt = 1 / (n_fft df),  m < n_t,
+ * a length-n_fft transform of the zero-padded spectrum (period 1/df: choose
+ * df below c / (longest path) to avoid wrap-around).
+ *   eps    [n_src * n_bins]  beam parameter per (source, bin), > 0 (device)
+ *   window [n_bins]          real taper w_n (device), or NULL for 1
+ *   params                   as for gbs_forward; params.alpha, if set, is
+ *                            [n_src * n_bins]
+ *   h      [n_src * n_rcv * n_t] out (device)
+ * n_fft a power of two in [64, 4096]; 1 <= bin0; bin0 + n_bins <= n_fft / 2;
+ * 1 <= n_t <= n_fft.  Runs gbs_forward over chunks of at most 64 bins
+ * (synchronising the stream between chunks), then one transform per row.
+ * Scratch: n_src * n_rcv * n_fft complex doubles.
+ */
+int gbs_impulse_response(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces,
+                         const double* rcv, int64_t n_rcv, double df, int32_t bin0, int32_t n_bins,
+                         const double* eps, const double* window, const gbs_params* params, int32_t n_fft,
+                         int32_t n_t, double* h);
+
+/*
  * Ray tracing: the stage before beam summation (Sec. 3.1; one thread per ray
  * as in Sec. 3.3).  Traces a fan of rays through a scene of the ground plane
  * z = 0 (face 0) and axis-aligned boxes standing on it, with specular

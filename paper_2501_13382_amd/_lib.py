@@ -67,7 +67,7 @@ class GbsStats(ctypes.Structure):
 
 EXPORTS = ("gbs_create", "gbs_destroy", "gbs_set_stream", "gbs_forward", "gbs_backward", "gbs_get_stats",
            "gbs_graph_create", "gbs_graph_launch", "gbs_graph_destroy", "gbs_autotune", "gbs_trace_count",
-           "gbs_trace", "gbs_air_absorption_db", "gbs_last_error", "gbs_version")
+           "gbs_trace", "gbs_air_absorption_db", "gbs_impulse_response", "gbs_last_error", "gbs_version")
 
 _lib = None
 
@@ -113,6 +113,10 @@ def load() -> ctypes.CDLL:
     lib.gbs_trace.argtypes = [c_void_p, P(GbsScene), P(GbsFan), c_int64, c_int64] + [c_void_p] * 8 + \
         [P(c_int64), P(c_int64)]
     lib.gbs_trace.restype = ctypes.c_int
+    lib.gbs_impulse_response.argtypes = [c_void_p, P(GbsRays), P(GbsSegs), P(GbsFaces), c_void_p, c_int64, c_double,
+                                         c_int32, c_int32, c_void_p, c_void_p, P(GbsParams), c_int32, c_int32,
+                                         c_void_p]
+    lib.gbs_impulse_response.restype = ctypes.c_int
     lib.gbs_air_absorption_db.argtypes = [c_double, c_double, c_double, c_double]
     lib.gbs_air_absorption_db.restype = c_double
     lib.gbs_last_error.argtypes = [c_void_p]

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgbs.so")
-SOURCES = ["gbs_api.hip", "gbs_kernels.hip", "gbs_trace.hip"]
+SOURCES = ["gbs_api.hip", "gbs_kernels.hip", "gbs_trace.hip", "gbs_ir.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -72,6 +72,10 @@ __global__ void k_trace(int64_t, int, const double*, const int32_t*, const doubl
                         const int32_t*, int, int, int, double, int, int64_t*, int*, const int64_t*, const int64_t*,
                         double*, double*, double*, double*, double*, int64_t*, int32_t*);
 __global__ void k_trace_face_counts(int64_t, const int64_t*, int64_t*);
+// broadband synthesis (gbs_ir.hip)
+__global__ void k_ir_twiddles(int, double2*);
+__global__ void k_ir_scatter(const double*, int, int, int64_t, int, const double*, int, int, double2*);
+__global__ void k_ir_fft(const double2*, int, int, const double2*, double, int, double*);
 __global__ void k_trace_close(const int64_t*, int64_t, int64_t, int64_t*);
 }  // namespace gbs
 
@@ -1333,6 +1337,84 @@ void gbs_graph_destroy(gbs_graph* g) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     delete g;
+}
+
+int gbs_impulse_response(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces,
+                         const double* rcv, int64_t n_rcv, double df, int32_t bin0, int32_t n_bins, const double* eps,
+                         const double* window, const gbs_params* params, int32_t n_fft, int32_t n_t, double* h) {
+    if (!ctx) return GBS_E_INVALID;
+    return guarded(ctx, [&]() {
+        GBS_HIP(hipSetDevice(ctx->device));
+        GBS_CHECK(rays && segs && faces && params, "null struct argument");
+        GBS_CHECK(std::isfinite(df) && df > 0, "df must be finite and > 0");
+        GBS_CHECK(n_fft >= 64 && n_fft <= kIrMaxFft && (n_fft & (n_fft - 1)) == 0,
+                  "n_fft must be a power of two in [64, 4096]");
+        GBS_CHECK(bin0 >= 1 && n_bins >= 1 && (int64_t)bin0 + n_bins <= n_fft / 2,
+                  "bins must satisfy 1 <= bin0 and bin0 + n_bins <= n_fft / 2");
+        GBS_CHECK(n_t >= 1 && n_t <= n_fft, "n_t must be in [1, n_fft]");
+        GBS_CHECK(n_rcv >= 0 && rays->n_src >= 0, "negative size");
+        const int n_src = rays->n_src;
+        const int64_t rows = (int64_t)n_src * n_rcv;
+        GBS_CHECK(rows == 0 || (eps && h), "null eps or h");
+        GBS_CHECK(rows <= INT32_MAX, "too many (source, receiver) rows");
+        hipStream_t st = ctx->stream;
+        Workspace& ws = *ctx->ws;
+        const int64_t nj = (int64_t)n_src * n_bins;
+        std::vector<double> h_eps(nj), h_alpha(params->alpha ? nj : 0), h_win(window ? n_bins : 0);
+        if (nj > 0) {
+            GBS_HIP(hipMemcpyAsync(h_eps.data(), eps, sizeof(double) * nj, hipMemcpyDeviceToHost, st));
+            if (params->alpha)
+                GBS_HIP(hipMemcpyAsync(h_alpha.data(), params->alpha, sizeof(double) * nj, hipMemcpyDeviceToHost,
+                                       st));
+            if (window)
+                GBS_HIP(hipMemcpyAsync(h_win.data(), window, sizeof(double) * n_bins, hipMemcpyDeviceToHost, st));
+            GBS_HIP(hipStreamSynchronize(st));
+        }
+        for (double w : h_win) GBS_CHECK(std::isfinite(w), "window must be finite");
+        if (rows == 0) return GBS_OK;
+        int log2n = 0;
+        while ((1 << log2n) < n_fft) ++log2n;
+        double2* spec = ws.get<double2>("ir_spec", (size_t)rows * n_fft);
+        fill(st, reinterpret_cast<double*>(spec), 2 * rows * n_fft, 0.0);
+        double2* tw = ws.get<double2>("ir_tw", n_fft / 2);
+        hipLaunchKernelGGL(k_ir_twiddles, dim3(blocks_for(n_fft / 2, 256)), dim3(256), 0, st, n_fft, tw);
+        GBS_HIP(hipGetLastError());
+        // the spectrum, up to kMaxBands bins per forward call
+        std::vector<double> fc, ec, ac;
+        for (int b0 = 0; b0 < n_bins; b0 += kMaxBands) {
+            const int nb = std::min(kMaxBands, n_bins - b0);
+            fc.resize(nb);
+            ec.resize((size_t)n_src * nb);
+            ac.resize(params->alpha ? (size_t)n_src * nb : 0);
+            for (int b = 0; b < nb; ++b) fc[b] = (double)(bin0 + b0 + b) * df;
+            for (int s = 0; s < n_src; ++s)
+                for (int b = 0; b < nb; ++b) {
+                    ec[(size_t)s * nb + b] = h_eps[(size_t)s * n_bins + b0 + b];
+                    if (params->alpha) ac[(size_t)s * nb + b] = h_alpha[(size_t)s * n_bins + b0 + b];
+                }
+            double* d_f = ws.get<double>("ir_freqs", kMaxBands);
+            double* d_e = ws.get<double>("ir_eps", (size_t)n_src * kMaxBands);
+            double* d_a = ws.get<double>("ir_alpha", (size_t)n_src * kMaxBands);
+            GBS_HIP(hipMemcpyAsync(d_f, fc.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st));
+            GBS_HIP(hipMemcpyAsync(d_e, ec.data(), sizeof(double) * ec.size(), hipMemcpyHostToDevice, st));
+            if (params->alpha)
+                GBS_HIP(hipMemcpyAsync(d_a, ac.data(), sizeof(double) * ac.size(), hipMemcpyHostToDevice, st));
+            gbs_params pc = *params;
+            pc.alpha = params->alpha ? d_a : nullptr;
+            double* Pc = ws.get<double>("ir_P", (size_t)2 * n_src * nb * n_rcv);
+            Args a{rays, segs, faces, rcv, n_rcv, d_f, nb, d_e, &pc};
+            forward_impl(ctx, ws, a, Pc, nullptr, 0);
+            const int64_t n_sc = (int64_t)n_src * nb * n_rcv;
+            hipLaunchKernelGGL(k_ir_scatter, dim3(blocks_for(n_sc, 256)), dim3(256), 0, st, Pc, n_src, nb, n_rcv,
+                               bin0 + b0, window, b0, n_fft, spec);
+            GBS_HIP(hipGetLastError());
+            GBS_HIP(hipStreamSynchronize(st));      // the host chunk arrays are rewritten next
+        }
+        hipLaunchKernelGGL(k_ir_fft, dim3((unsigned)rows), dim3(256), sizeof(double2) * n_fft, st, spec, n_fft,
+                           log2n, tw, 2.0 * df, n_t, h);
+        GBS_HIP(hipGetLastError());
+        return GBS_OK;
+    });
 }
 
 int gbs_trace_count(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, int64_t* n_segs,

@@ -72,4 +72,7 @@ constexpr int kTraceThreads = 128;
 constexpr int kTraceMaxRefl = 32;
 constexpr int kTraceGroup = 8;
 
+// Broadband synthesis: the largest transform (one row of double2 in LDS).
+constexpr int kIrMaxFft = 4096;
+
 }  // namespace gbs

@@ -305,6 +305,29 @@ def autotune(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="
     return dict(choice)
 
 
+def impulse_response(table: Table, rcv, df, bin0, n_bins, eps, gamma, *, n_fft, n_t=None, window=None, c=343.0,
+                     gate=9.21, mode="mix", alpha=None, chunk_segs=0):
+    """Broadband synthesis (gbs_impulse_response): the time signal
+    h [n_src, n_rcv, n_t] at dt = 1 / (n_fft df) from the forward sum at
+    f_n = (bin0 + n) df, n < n_bins, with the real taper `window` [n_bins].
+    eps (and alpha) per (source, bin)."""
+    ctx = context(table.device)
+    ctx.bind_stream()
+    n_t = n_fft if n_t is None else int(n_t)
+    freqs = (int(bin0) + np.arange(int(n_bins))) * float(df)
+    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, 0, False, False, alpha=alpha)
+    win = None if window is None else _as_tensor(window, torch.float64, table.device).reshape(-1)
+    if win is not None and win.numel() != int(n_bins):
+        raise ValueError("one window value per bin")
+    h = torch.empty((table.n_src, call.n_rcv, n_t), dtype=torch.float64, device=table.device)
+    rays, segs = call.rays, call.segs
+    rc = ctx.lib.gbs_impulse_response(ctx.handle, ctypes.byref(rays), ctypes.byref(segs), ctypes.byref(call.faces),
+                                      _ptr(call.rcv), call.n_rcv, float(df), int(bin0), int(n_bins), _ptr(call.eps),
+                                      _ptr(win), ctypes.byref(call.params), int(n_fft), n_t, _ptr(h))
+    _lib.check(rc, ctx.handle)
+    return h
+
+
 def air_absorption(freqs, temp_c=20.0, rh_pct=70.0, pressure_atm=1.0) -> np.ndarray:
     """Atmospheric absorption (ISO 9613-1, gbs_air_absorption_db) as the
     amplitude decay rate alpha in Np/m for each frequency; the defaults are

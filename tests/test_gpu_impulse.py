@@ -1,0 +1,91 @@
+"""GPU broadband synthesis (gbs_impulse_response through the C ABI) against
+the oracle's impulse response: the forward sum over a frequency grid (several
+64-bin chunks), windowed, zero-padded and transformed per row in LDS.
+Compared over every sample against each row's error scale
+2 df sum_n w_n sum_j |u_nj| (the sum of the magnitudes that enter the row:
+the analogue of the forward's cancellation measure, since a time signal can
+cancel too, e.g. the direct and ground arrivals at grazing receivers):
+F64 1e-10, MIX 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2501_13382_amd as gbs
+from paper_2501_13382_amd import _lib
+from scenes import city_batched, open_plane_2k
+from tests.gpu_util import oracle_threads
+
+pytestmark = pytest.mark.gpu
+
+C = 343.0
+
+
+def eps_bins(freqs, r_ref):
+    return 6.0 * np.sqrt(r_ref / (2 * np.pi * freqs / C))
+
+
+def row_scale(table, gamma, rcv, freqs, eps, w, df, alpha=None):
+    """2 df sum_n w_n sum_j |u_nj| per (source, receiver)."""
+    _, _, ab = oracle.forward(table, gamma, rcv, freqs, eps, n_threads=oracle_threads(), return_absum=True,
+                              alpha=alpha)
+    ab = ab.reshape(table.n_src, len(freqs), len(rcv))
+    w = np.ones(len(freqs)) if w is None else np.abs(w)
+    return 2 * df * np.einsum("n,snr->sr", w, ab)
+
+
+def check_rows(h, ref, scale, tol):
+    assert np.all(scale > 0)
+    err = np.abs(h - ref) / scale[..., None]
+    assert err.max() <= tol, err.max()
+    assert np.abs(ref).max() > 0.01 * scale.max()           # the signal is not all cancelled
+
+
+@pytest.mark.parametrize("mode,tol", [("f64", 1e-10), ("mix", 1e-5)])
+def test_open_plane_impulse_response(mode, tol):
+    sc = open_plane_2k(eps="rule")
+    sc.gamma = np.array([0.8 * np.exp(1j * np.pi / 8)])
+    rcv = sc.rcv[::61]
+    df, bin0, n_bins, n_fft, n_t = 4.0, 60, 150, 1024, 700        # 240 - 836 Hz in 3 chunks
+    freqs = (bin0 + np.arange(n_bins)) * df
+    eps = eps_bins(freqs, sc.meta["r_ref"])[None, :]
+    w = np.hanning(n_bins + 2)[1:-1]
+    print(f"case impulse response open plane mode={mode}", flush=True)
+    ref = oracle.impulse_response(sc.table, sc.gamma, rcv, df, bin0, n_bins, eps, n_fft, n_t, window=w,
+                                  n_threads=oracle_threads())
+    t = gbs.Table(sc.table, device="cuda")
+    h = gbs.impulse_response(t, rcv, df, bin0, n_bins, eps, sc.gamma, n_fft=n_fft, n_t=n_t, window=w, mode=mode)
+    torch.cuda.synchronize()
+    assert h.shape == (1, len(rcv), n_t)
+    check_rows(h.cpu().numpy(), ref, row_scale(sc.table, sc.gamma, rcv, freqs, eps, w, df), tol)
+
+
+def test_batched_sources_with_absorption_and_no_window():
+    sc = city_batched(n_src=3, ray_lo=1500, ray_hi=3000, grid=12)
+    rcv = sc.rcv[::7]
+    df, bin0, n_bins, n_fft = 2.0, 40, 70, 512                     # 80 - 218 Hz, 2 chunks
+    freqs = (bin0 + np.arange(n_bins)) * df
+    eps = np.stack([eps_bins(freqs, 1200.0)] * 3)
+    alpha = np.tile(gbs.air_absorption(freqs), (3, 1)) * 50.0      # strong, to be visible
+    print("case impulse response batched", flush=True)
+    ref = oracle.impulse_response(sc.table, sc.gamma, rcv, df, bin0, n_bins, eps, n_fft, n_fft, alpha=alpha,
+                                  n_threads=oracle_threads())
+    t = gbs.Table(sc.table, device="cuda")
+    h = gbs.impulse_response(t, rcv, df, bin0, n_bins, eps, sc.gamma, n_fft=n_fft, mode="f64", alpha=alpha)
+    torch.cuda.synchronize()
+    check_rows(h.cpu().numpy(), ref, row_scale(sc.table, sc.gamma, rcv, freqs, eps, None, df, alpha), 1e-10)
+
+
+def test_invalid_requests_rejected():
+    sc = open_plane_2k(eps="rule")
+    t = gbs.Table(sc.table, device="cuda")
+    rcv = sc.rcv[:4]
+    eps = np.full((1, 10), 20.0)
+    for kw in (dict(n_fft=1000), dict(n_fft=64, bin0=30), dict(n_fft=8192), dict(n_fft=256, n_t=300),
+               dict(n_fft=256, bin0=0)):
+        args = dict(bin0=5, n_fft=256)
+        args.update(kw)
+        with pytest.raises(_lib.GbsError):
+            gbs.impulse_response(t, rcv, 4.0, args["bin0"], 10, eps, sc.gamma, n_fft=args["n_fft"],
+                                 n_t=args.get("n_t"))
