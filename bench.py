@@ -16,8 +16,9 @@ never `value`), the adjoint call on the same workload, the error against the
 FP64 oracle on 16,384 seeded receivers, the oracle timed on this host's
 cores on that sample (and single-threaded on a smaller one), and the device
 ray tracer re-tracing the workload's fan (with the per-ray oracle tracer
-timed on a sample of rays), and the forward with atmospheric absorption in
-the paper's atmosphere.
+timed on a sample of rays), the forward with atmospheric absorption in
+the paper's atmosphere, and broadband synthesis (an impulse response per
+receiver from 1,751 frequency bins) on a receiver subsample.
 """
 from __future__ import annotations
 
@@ -132,6 +133,48 @@ def absorption_bench(sc, dev, table, rcv, freqs, eps, gamma, args, sec_step):
     return leg
 
 
+def impulse_bench(sc, dev, table, gamma, args):
+    """Broadband synthesis on the open plane: the time signal at 4,096 seeded
+    receivers from 1,751 frequency bins (50-400 Hz every 0.2 Hz: a 5 s period
+    that holds the longest path), Hann taper, 4,096-point transforms (1.22 ms
+    samples); eps by the workload's rule per bin.  Timed once after a warm-up
+    call; a few receivers against the oracle's impulse response."""
+    import torch
+
+    import paper_2501_13382_amd as gbs
+    from scenes import receiver_subsample
+    df, bin0, n_bins, n_fft = 0.2, 250, 1751, 4096
+    freqs = (bin0 + np.arange(n_bins)) * df
+    eps = (6.0 * np.sqrt(sc.meta["r_ref"] / (2 * np.pi * freqs / sc.c)))[None, :]
+    win = np.hanning(n_bins + 2)[1:-1]
+    idx = receiver_subsample(len(sc.rcv), n=4096, seed=9)
+    rcv = torch.as_tensor(sc.rcv[idx], device=dev)
+    call = lambda: gbs.impulse_response(table, rcv, df, bin0, n_bins, eps, gamma, n_fft=n_fft, window=win,
+                                        c=sc.c, gate=sc.gate, mode="mix")
+    call()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    h = call()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    dense = table.n_segs * len(idx) * n_bins
+    leg = {"ms": el * 1e3, "receivers": int(len(idx)), "bins": n_bins, "df_hz": df, "band_hz": [freqs[0], freqs[-1]],
+           "n_fft": n_fft, "dt_ms": 1e3 / (n_fft * df), "dense_evals_per_s": dense / el}
+    print(f"# impulse response: {el * 1e3:.1f} ms for {len(idx)} receivers x {n_bins} bins", file=sys.stderr,
+          flush=True)
+    if not args.no_cpu:
+        import oracle
+        k = np.array([0, 1000, 2000, 3000])
+        threads = int(os.environ.get("OMP_NUM_THREADS", str(min(16, os.cpu_count() or 1))))
+        ref = oracle.impulse_response(sc.table, sc.gamma, sc.rcv[idx[k]], df, bin0, n_bins, eps, n_fft, n_fft,
+                                      window=win, c=sc.c, gate=sc.gate, n_threads=threads)
+        got = h.cpu().numpy()[:, k, :]
+        peak = np.abs(ref).max(axis=-1)
+        leg["max_err_rel_to_peak"] = float((np.abs(got - ref).max(axis=-1) / peak).max())
+        leg["receivers_checked"] = int(len(k))
+    return leg
+
+
 def trace_bench(sc, dev, args):
     """The ray-tracing stage on the device for the workload's own fan (the
     launch directions are the first segment's axis of every ray): wall time
@@ -212,6 +255,7 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--no-trace", action="store_true", help="skip the device ray-tracing leg")
     ap.add_argument("--no-absorption", action="store_true", help="skip the atmospheric-absorption leg")
+    ap.add_argument("--no-impulse", action="store_true", help="skip the broadband (impulse response) leg")
     ap.add_argument("--workload", default="open_plane_100k", choices=sorted(WORKLOADS),
                     help="open_plane_100k (default, the headline); city_1m: 10 x 10 city, 1,000,000 rays, "
                          "1024 x 1024 receivers, 1 kHz; city_batched: 16 sources x 4 bands, ragged ray counts, "
@@ -345,6 +389,10 @@ def main():
     if not args.no_absorption:
         absorption_leg = absorption_bench(sc, dev, table, rcv, freqs, eps, gamma, args, sec_step)
 
+    impulse_leg = None
+    if not args.no_impulse and sc.table.meta.get("kind") == "open_plane":
+        impulse_leg = impulse_bench(sc, dev, table, gamma, args)
+
     trace_leg = None
     if not args.no_trace:
         trace_leg = trace_bench(sc, dev, args)
@@ -391,6 +439,7 @@ def main():
         "adjoint": adj_leg,
         "trace": trace_leg,
         "absorption": absorption_leg,
+        "impulse_response": impulse_leg,
     }
 
     if args.copy_calibration > 0:
