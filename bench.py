@@ -47,6 +47,8 @@ sys.path.insert(0, ROOT)
 FLOP_LISTED_F64 = 12
 FLOP_KEPT_F64 = 17
 FLOP_KEPT_F32 = 18
+ADJ_FLOP_KEPT_F64 = 29
+ADJ_FLOP_KEPT_F32 = 69
 # Vector peaks from unit counts and clock: 256 CUs x 2.4 GHz x 64 FMA lanes x 2
 # = 78.6 TFLOP/s FP64; FP32 157.3 TFLOP/s (vendor figure).
 PEAK_F64 = 256 * 2.4e9 * 64 * 2
@@ -365,8 +367,24 @@ def main():
             bwd()
         torch.cuda.synchronize()
         s_adj = (time.perf_counter() - t) / n_adj
+        gbs.backward(table, rcv, freqs, eps, gamma, lam, c=sc.c, gate=sc.gate, mode=mode, time_kernels=True)
+        ms_adj_kernel = gbs.stats(dev)["ms_pairs"]
+        # algorithmic work of the adjoint kernel: the forward gate per listed
+        # pair; per kept pair 29 FP64 flops (n^2, den, Newton reciprocal, a,
+        # phase, fract, Gaussian exponent: 15; the receiver-gradient sums
+        # V, W, G and the eps sum: 14) and 69 FP32 (rcp, sin, cos, exp2 and the
+        # weight; d ln u/dR and d ln u/deps: 25; the beam term, lambda u, the
+        # gradient coefficients and the segment and eps sums)
+        a64 = FLOP_LISTED_F64 * listed + ADJ_FLOP_KEPT_F64 * active
+        a32 = ADJ_FLOP_KEPT_F32 * active
+        a_ach = (a64 + a32) / (ms_adj_kernel * 1e-3)
+        a_peak = (a64 + a32) / (a64 / PEAK_F64 + a32 / PEAK_F32)
         adj_leg = {"value": dense / s_adj, "ms_per_call": s_adj * 1e3, "mode": mode,
-                   "forward_plus_adjoint_ms": sec_step * 1e3 + s_adj * 1e3}
+                   "forward_plus_adjoint_ms": sec_step * 1e3 + s_adj * 1e3,
+                   "roofline": {"bound": "alu", "kernel": "k_adjoint<MIX>", "achieved": a_ach / 1e12,
+                                "peak": a_peak / 1e12, "unit": "TFLOP/s", "frac": a_ach / a_peak,
+                                "ms_per_launch": ms_adj_kernel,
+                                "flop_per_kept_pair": {"f64": ADJ_FLOP_KEPT_F64, "f32": ADJ_FLOP_KEPT_F32}}}
         print(f"# adjoint: {s_adj * 1e3:.2f} ms/call", file=sys.stderr, flush=True)
 
     # the same forward captured once as a hipGraph and replayed (the lists are

@@ -127,7 +127,8 @@ typedef struct gbs_stats {
     int64_t n_items;          /* work items of the persistent pair kernel        */
     int32_t n_chunks;         /* passes over the table                           */
     int32_t patch_rcv;        /* receivers per work item                         */
-    double ms_pairs;          /* pair-kernel time, all passes (GBS_FLAG_TIME_KERNELS) */
+    double ms_pairs;          /* pair-kernel time (the adjoint kernel's in gbs_backward),
+                                 all passes (GBS_FLAG_TIME_KERNELS)                    */
     double ms_cull;           /* culling/list-building time (GBS_FLAG_TIME_KERNELS)   */
     int32_t grid;             /* workgroups of the last persistent launch          */
     int32_t blocks_per_cu;    /* resident workgroups per CU for that kernel        */

@@ -1183,6 +1183,7 @@ int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
         fill(st, dRj, 3 * n_out, 0.0);
         gbs_stats stats{};
         stats.patch_rcv = 64;
+        const bool timed = (params->flags & GBS_FLAG_TIME_KERNELS) != 0;
         if (n_out > 0 && segs->n_segs > 0) {
             pl.source_offsets();
             pl.make_passes();
@@ -1203,10 +1204,13 @@ int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
                     double* part = ws.get<double>("adj_partial", L.work_cap * 64 * 3);
                     const int64_t grid = persistent_grid(ctx, (const void*)kern, L.work_cap);
                     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, ctr);
+                    EventPair ev(timed);
+                    ev.begin(st);
                     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPairThreads), 0, st, L.jobs, L.work,
                                        L.n_work, pl.R.n_patch, ctr, L.lists, L.rec, pl.R.rx, pl.R.ry, pl.R.rz,
                                        pl.R.r2, pl.R.perm, n_rcv, lambda, part, L.seg_perm, Sseg, dE);
                     GBS_HIP(hipGetLastError());
+                    stats.ms_pairs += ev.end(st);
                     hipLaunchKernelGGL(k_reduce_adjoint, dim3(blocks_for((int64_t)L.n_items * 64, 256)), dim3(256), 0,
                                        st, L.jobs, L.item_wbase, L.item_wcount, L.n_items, pl.R.n_patch, pl.R.perm,
                                        n_rcv, part, dRj);

@@ -199,12 +199,13 @@ def forward(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="m
 
 
 def backward(table: Table, rcv, freqs, eps, gamma, lam, *, c=343.0, gate=9.21, mode="mix", chunk_segs=0,
-             validate=False, alpha=None):
+             validate=False, alpha=None, time_kernels=False):
     """Adjoint for dL = Re sum lam * dP.  Returns (d_gamma [n_faces, 2] as
     (dL/dRe, dL/dIm), d_rcv [n_rcv, 3], d_eps [n_src, n_freq])."""
     ctx = context(table.device)
     ctx.bind_stream()
-    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, 0, validate, False, alpha=alpha)
+    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, 0, validate, False, time_kernels,
+                 alpha=alpha)
     lam_t = lam if isinstance(lam, torch.Tensor) else torch.as_tensor(np.asarray(lam))
     lam_t = lam_t.to(device=table.device, dtype=torch.complex128).reshape(call.shape).contiguous()
     lam_ri = torch.view_as_real(lam_t).contiguous()
