@@ -270,7 +270,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; use --gpus 1", file=sys.stderr)
+        print("bench.py: runs on one GPU only (no multi-GPU sharding is implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -55,7 +55,7 @@ typedef enum gbs_status {
     GBS_E_INVALID = -1,      /* bad argument (null, size, non-finite, range)     */
     GBS_E_OOM = -2,          /* device or host allocation failed                */
     GBS_E_HIP = -3,          /* a HIP runtime call failed (message has details) */
-    GBS_E_UNSUPPORTED = -4,  /* valid request this build does not support       */
+    GBS_E_UNSUPPORTED = -4,  /* valid request the library does not support      */
     GBS_E_STATE = -5         /* context/graph used in the wrong state           */
 } gbs_status;
 
@@ -176,7 +176,7 @@ int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
 int gbs_get_stats(const gbs_ctx* ctx, gbs_stats* out);
 
 /*
- * Graphs (spec batching extension): capture one forward call (all
+ * Graphs (batched replay; an extension, not in the paper): capture one forward call (all
  * jobs, one persistent launch per pass over the table) into a hipGraph and
  * replay it.  Creation runs the full plan once (receiver ordering, culling,
  * work lists for every pass) and captures the per-call work: for each pass
@@ -195,7 +195,7 @@ int gbs_graph_launch(gbs_graph* g);
 void gbs_graph_destroy(gbs_graph* g);
 
 /*
- * Autotuner (spec extension; the paper has none): times the forward on
+ * Autotuner (an extension; the paper has none): times the forward on
  * the given problem for every candidate pair-kernel shape (receivers per
  * lane 1, 2, 4) and work-unit size (1024, 2048, 4096 segments) and stores the
  * fastest in the context for `params.mode`; later calls with rcv_per_lane or
