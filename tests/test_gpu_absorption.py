@@ -113,3 +113,22 @@ def test_adjoint_with_absorption(panel_case, mode, tol):
     for got, ref in ((dG, rG), (dR, rR), (dE, rE.reshape(-1))):
         got = got.cpu().numpy().reshape(np.shape(ref))
         assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref)), mode
+
+
+def test_full_size_open_plane_with_paper_atmosphere():
+    """The benchmark workload at full size (100,000 rays, 8 bands, 512 x 512
+    receivers) with the ISO 9613-1 absorption of the paper's atmosphere;
+    256 seeded receivers against the oracle with the same alpha."""
+    from scenes import open_plane_100k, receiver_subsample
+    sc = open_plane_100k()
+    alpha = gbs.air_absorption(sc.freqs)[None, :]
+    idx = receiver_subsample(len(sc.rcv), n=256, seed=5)
+    P_ref, TL_ref, ab = oracle.forward(sc.table, sc.gamma, sc.rcv[idx], sc.freqs, sc.eps, c=sc.c, gate=sc.gate,
+                                       n_threads=oracle_threads(), return_absum=True, alpha=alpha)
+    print("case absorption full-size open plane", flush=True)
+    t = gbs.Table(sc.table, device="cuda")
+    P, TL = gbs.forward(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, c=sc.c, gate=sc.gate, mode="mix", alpha=alpha)
+    torch.cuda.synchronize()
+    P = P.cpu().numpy().reshape(8, -1)[:, idx]
+    TL = TL.cpu().numpy().reshape(8, -1)[:, idx]
+    assert_within(compare(P, TL, P_ref, TL_ref, ab), "mix")

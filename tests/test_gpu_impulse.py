@@ -129,3 +129,25 @@ def test_traced_and_streamed_tables():
     torch.cuda.synchronize()
     assert torch.equal(h2, h3)                 # same passes: same bits, host or device table
     check_rows(h2.cpu().numpy(), ref, row_scale(tab, gamma, rcv, freqs, eps, win, df), 1e-10)
+
+
+def test_full_size_impulse_response_sampled():
+    """The benchmark's broadband leg at full size: 1,751 bins (50-400 Hz,
+    df 0.2 Hz), Hann taper, 4,096-point transforms, 4,096 receivers of the
+    100,000-ray open plane in one call; 4 of them against the oracle."""
+    from scenes import open_plane_100k, receiver_subsample
+    sc = open_plane_100k()
+    df, bin0, n_bins, n_fft = 0.2, 250, 1751, 4096
+    freqs = (bin0 + np.arange(n_bins)) * df
+    eps = eps_bins(freqs, sc.meta["r_ref"])[None, :]
+    win = np.hanning(n_bins + 2)[1:-1]
+    idx = receiver_subsample(len(sc.rcv), n=4096, seed=9)
+    print("case impulse response full size", flush=True)
+    t = gbs.Table(sc.table, device="cuda")
+    h = gbs.impulse_response(t, sc.rcv[idx], df, bin0, n_bins, eps, sc.gamma, n_fft=n_fft, window=win, mode="mix")
+    torch.cuda.synchronize()
+    k = np.array([0, 1365, 2730, 4095])
+    ref = oracle.impulse_response(sc.table, sc.gamma, sc.rcv[idx[k]], df, bin0, n_bins, eps, n_fft, n_fft,
+                                  window=win, n_threads=oracle_threads())
+    check_rows(h.cpu().numpy()[:, k, :], ref, row_scale(sc.table, sc.gamma, sc.rcv[idx[k]], freqs, eps, win, df),
+               1e-5)
