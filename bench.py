@@ -193,18 +193,24 @@ def trace_bench(sc, dev, args):
     elif kind == "city":
         city = sc.meta["city"]
         kw = dict(boxes=city.boxes, panels=city.panels, s_max=tab.meta["s_max"], max_refl=tab.meta["max_refl"])
+    elif "parts" in tab.meta:             # several sources, each with its own arc-length budget
+        city = sc.meta["city"]
+        parts = tab.meta["parts"]
+        kw = dict(boxes=city.boxes, panels=city.panels, s_max=np.array([p["s_max"] for p in parts]),
+                  max_refl=parts[0]["max_refl"])
     else:
-        return None                       # several sources with their own s_max
+        return None
     first = tab.ray_ptr[:-1]
     dirs = torch.as_tensor(tab.seg_t[first], device=dev)
     w = torch.as_tensor(tab.ray_w, device=dev)
     src = tab.src_xyz
-    t = gbs.trace(src, dirs, w, **kw)
+    rs = torch.as_tensor(tab.ray_src, device=dev)
+    t = gbs.trace(src, dirs, w, ray_src=rs, **kw)
     torch.cuda.synchronize()
     ms = []
     for _ in range(5):
         t0 = time.perf_counter()
-        t = gbs.trace(src, dirs, w, **kw)
+        t = gbs.trace(src, dirs, w, ray_src=rs, **kw)
         torch.cuda.synchronize()
         ms.append((time.perf_counter() - t0) * 1e3)
     same = {}
@@ -230,8 +236,9 @@ def trace_bench(sc, dev, args):
         def timed(n_s):
             rays = np.sort(rng.choice(tab.n_rays, size=n_s, replace=False))
             t0 = time.perf_counter()
-            ot.trace(src, d_host, tab.ray_w, boxes=kw["boxes"], panels=kw["panels"], s_max=kw["s_max"],
-                     max_refl=kw["max_refl"], image_complete=kw.get("image_complete", False), rays=rays)
+            ot.trace(src, d_host, tab.ray_w, ray_src=tab.ray_src, boxes=kw["boxes"], panels=kw["panels"],
+                     s_max=kw["s_max"], max_refl=kw["max_refl"], image_complete=kw.get("image_complete", False),
+                     rays=rays)
             return time.perf_counter() - t0
 
         # a probe of 200 rays sizes a sample of about 3 s

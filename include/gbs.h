@@ -274,6 +274,8 @@ typedef struct gbs_fan {
     const double* dirs;       /* [n_rays * 3] unit directions (|d|^2 = 1 +- 1e-9) */
     const int32_t* ray_src;   /* [n_rays] source of each ray in [0, n_src),
                                  non-decreasing, or NULL for source 0            */
+    const double* s_max_src;  /* [n_src] arc-length budget per source (m, > 0;
+                                 device), or NULL for scene.s_max everywhere     */
 } gbs_fan;
 
 /*

@@ -166,7 +166,8 @@ def ray_segments(src, d0, boxes, panels, s_max, max_refl, image_complete):
 def trace(src_xyz, dirs, weights, ray_src=None, boxes=None, panels=1, s_max=1.0, max_refl=10,
           image_complete=False, rays=None):
     """Ray table (dict of numpy arrays in the beam-summation table layout)
-    of the given rays, or of the subset `rays` (indices, kept in order)."""
+    of the given rays, or of the subset `rays` (indices, kept in order).
+    s_max: one arc-length budget, or one per source."""
     src_xyz = np.asarray(src_xyz, np.float64).reshape(-1, 3)
     dirs = np.asarray(dirs, np.float64).reshape(-1, 3)
     weights = np.asarray(weights, np.float64).reshape(-1)
@@ -175,11 +176,12 @@ def trace(src_xyz, dirs, weights, ray_src=None, boxes=None, panels=1, s_max=1.0,
     if image_complete and len(boxes):
         raise ValueError("image completion is defined for the open plane only")
     idx = np.arange(len(dirs)) if rays is None else np.asarray(rays, np.int64)
+    s_max_src = np.broadcast_to(np.asarray(s_max, np.float64), (len(src_xyz),))
     ray_ptr, face_ptr = [0], [0]
     A, T, S0, LO, HI, F = [], [], [], [], [], []
     for i in idx:
-        for a, t, s0, lo, hi, hist in ray_segments(src_xyz[ray_src[i]], dirs[i], boxes, panels, s_max, max_refl,
-                                                   image_complete):
+        for a, t, s0, lo, hi, hist in ray_segments(src_xyz[ray_src[i]], dirs[i], boxes, panels,
+                                                   float(s_max_src[ray_src[i]]), max_refl, image_complete):
             A.append(a)
             T.append(t)
             S0.append(s0)

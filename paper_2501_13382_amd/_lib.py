@@ -53,7 +53,7 @@ class GbsScene(ctypes.Structure):
 
 class GbsFan(ctypes.Structure):
     _fields_ = [("n_src", c_int32), ("src_xyz", c_void_p), ("n_rays", c_int64), ("dirs", c_void_p),
-                ("ray_src", c_void_p)]
+                ("ray_src", c_void_p), ("s_max_src", c_void_p)]
 
 
 class GbsStats(ctypes.Structure):

@@ -69,6 +69,7 @@ __global__ void k_validate(int64_t, const double*, const double*, const double*,
 // ray tracing (gbs_trace.hip)
 template <bool COUNT>
 __global__ void k_trace(int64_t, int, const double*, const int32_t*, const double*, const double*, const double*,
+                        const double*,
                         const int32_t*, int, int, int, double, int, int64_t*, int*, const int64_t*, const int64_t*,
                         double*, double*, double*, double*, double*, int64_t*, int32_t*);
 __global__ void k_trace_face_counts(int64_t, const int64_t*, int64_t*);
@@ -990,10 +991,15 @@ std::pair<int64_t, int64_t> trace_impl(gbs_ctx* ctx, const gbs_scene* sc, const 
     Workspace& ws = *ctx->ws;
     // small tables to the host: validation and box groups
     std::vector<double> bx((size_t)sc->n_boxes * 5), src((size_t)fan->n_src * 3);
+    std::vector<double> smax(fan->s_max_src ? fan->n_src : 0);
     if (sc->n_boxes)
         GBS_HIP(hipMemcpyAsync(bx.data(), sc->boxes, bx.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     GBS_HIP(hipMemcpyAsync(src.data(), fan->src_xyz, src.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (fan->s_max_src)
+        GBS_HIP(hipMemcpyAsync(smax.data(), fan->s_max_src, smax.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               st));
     GBS_HIP(hipStreamSynchronize(st));
+    for (double v : smax) GBS_CHECK(std::isfinite(v) && v > 0, "fan.s_max_src must be finite and > 0");
     for (int b = 0; b < sc->n_boxes; ++b) {
         const double* q = &bx[5 * b];
         GBS_CHECK(std::isfinite(q[0]) && std::isfinite(q[1]) && std::isfinite(q[2]) && std::isfinite(q[3]) &&
@@ -1026,7 +1032,8 @@ std::pair<int64_t, int64_t> trace_impl(gbs_ctx* ctx, const gbs_scene* sc, const 
     const dim3 grid(blocks_for(n, kTraceThreads)), block(kTraceThreads);
     if (n > 0)
         hipLaunchKernelGGL(k_trace<true>, grid, block, 0, st, n, fan->n_src, fan->src_xyz, fan->ray_src, fan->dirs,
-                           d_box, d_gbox, d_mem, S.n_groups, sc->panels, sc->max_refl, sc->s_max, sc->image_complete, nseg, bad,
+                           fan->s_max_src, d_box, d_gbox, d_mem, S.n_groups, sc->panels, sc->max_refl, sc->s_max,
+                           sc->image_complete, nseg, bad,
                            nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     GBS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_trace_face_counts, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st, n, nseg, nface);
@@ -1053,7 +1060,8 @@ std::pair<int64_t, int64_t> trace_impl(gbs_ctx* ctx, const gbs_scene* sc, const 
     GBS_CHECK(out->face_ptr, "face_ptr must be non-null");
     if (n > 0)
         hipLaunchKernelGGL(k_trace<false>, grid, block, 0, st, n, fan->n_src, fan->src_xyz, fan->ray_src,
-                           fan->dirs, d_box, d_gbox, d_mem, S.n_groups, sc->panels, sc->max_refl, sc->s_max, sc->image_complete,
+                           fan->dirs, fan->s_max_src, d_box, d_gbox, d_mem, S.n_groups, sc->panels, sc->max_refl,
+                           sc->s_max, sc->image_complete,
                            nullptr, nullptr, rp, fbase, out->a, out->t, out->s0, out->lo, out->hi, out->face_ptr,
                            out->face_ids);
     hipLaunchKernelGGL(k_trace_close, dim3(1), dim3(64), 0, st, fbase, n, tot[0], out->face_ptr);

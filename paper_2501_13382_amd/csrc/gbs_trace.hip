@@ -95,8 +95,9 @@ __device__ __forceinline__ int32_t face_of(int32_t box, const double* bx, int ax
 template <bool COUNT>
 __global__ __launch_bounds__(kTraceThreads) void k_trace(
     int64_t n_rays, int n_src, const double* __restrict__ src_xyz, const int32_t* __restrict__ ray_src,
-    const double* __restrict__ dirs, const double* __restrict__ boxes, const double* __restrict__ gbox,
-    const int32_t* __restrict__ members, int n_groups, int panels, int max_refl, double s_max, int image_complete,
+    const double* __restrict__ dirs, const double* __restrict__ s_max_src, const double* __restrict__ boxes,
+    const double* __restrict__ gbox, const int32_t* __restrict__ members, int n_groups, int panels, int max_refl,
+    double s_max_all, int image_complete,
     int64_t* __restrict__ nseg, int* __restrict__ bad, const int64_t* __restrict__ ray_ptr,
     const int64_t* __restrict__ face_base, double* __restrict__ seg_a, double* __restrict__ seg_t,
     double* __restrict__ seg_s0, double* __restrict__ seg_lo, double* __restrict__ seg_hi,
@@ -109,6 +110,7 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace(
     const int sidx = sraw < 0 ? 0 : (sraw >= n_src ? n_src - 1 : sraw);
     const double src[3] = {src_xyz[3 * sidx], src_xyz[3 * sidx + 1], src_xyz[3 * sidx + 2]};
     const double d0[3] = {dirs[3 * ii], dirs[3 * ii + 1], dirs[3 * ii + 2]};
+    const double s_max = s_max_src ? s_max_src[sidx] : s_max_all;    // the ray's arc-length budget
     if (COUNT && live) {
         const double n2 = d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2];
         int flag = fabs(n2 - 1.0) <= 1e-9 ? 0 : 1;
@@ -250,10 +252,12 @@ __global__ void k_trace_close(const int64_t* __restrict__ face_base, int64_t n_r
 }
 
 template __global__ void k_trace<true>(int64_t, int, const double*, const int32_t*, const double*, const double*,
+                                       const double*,
                                        const double*, const int32_t*, int, int, int, double, int, int64_t*, int*,
                                        const int64_t*, const int64_t*, double*, double*, double*, double*, double*,
                                        int64_t*, int32_t*);
 template __global__ void k_trace<false>(int64_t, int, const double*, const int32_t*, const double*, const double*,
+                                        const double*,
                                         const double*, const int32_t*, int, int, int, double, int, int64_t*, int*,
                                         const int64_t*, const int64_t*, double*, double*, double*, double*, double*,
                                         int64_t*, int32_t*);

@@ -228,7 +228,8 @@ def trace(src_xyz, dirs, weights, *, ray_src=None, boxes=None, panels=1, s_max, 
           image_complete=False, device="cuda") -> Table:
     """Ray tracing on the device (gbs_trace): the fan `dirs` [n, 3] (unit) from
     the sources `src_xyz` [n_src, 3] (ray i from source ray_src[i], default 0)
-    through the ground plane and `boxes` [n_boxes, 5] (x0, x1, y0, y1, h);
+    through the ground plane and `boxes` [n_boxes, 5] (x0, x1, y0, y1, h),
+    each ray until its arc length reaches s_max (a number, or one per source);
     returns the ray table as a device Table with the given ray weights."""
     ctx = context(device)
     ctx.bind_stream()
@@ -245,9 +246,15 @@ def trace(src_xyz, dirs, weights, *, ray_src=None, boxes=None, panels=1, s_max, 
     if rs.numel() != n:
         raise ValueError("one source index per ray")
     bx = _as_tensor(np.zeros((0, 5)) if boxes is None else boxes, f64, dev).reshape(-1, 5)
-    scene = _lib.GbsScene(int(bx.shape[0]), int(panels), _ptr(bx), float(s_max), int(max_refl),
-                          1 if image_complete else 0)
-    fan = _lib.GbsFan(int(src.shape[0]), _ptr(src), n, _ptr(d), _ptr(rs))
+    sm = np.asarray(s_max, np.float64)
+    sm_src = None
+    if sm.ndim > 0:
+        sm_src = _as_tensor(sm, f64, dev).reshape(-1)
+        if sm_src.numel() != src.shape[0]:
+            raise ValueError("s_max: one value, or one per source")
+    scene = _lib.GbsScene(int(bx.shape[0]), int(panels), _ptr(bx), float(sm.max()) if sm.size else 0.0,
+                          int(max_refl), 1 if image_complete else 0)
+    fan = _lib.GbsFan(int(src.shape[0]), _ptr(src), n, _ptr(d), _ptr(rs), _ptr(sm_src) if sm_src is not None else None)
     ns, nf = ctypes.c_int64(0), ctypes.c_int64(0)
     _lib.check(ctx.lib.gbs_trace_count(ctx.handle, ctypes.byref(scene), ctypes.byref(fan), ctypes.byref(ns),
                                        ctypes.byref(nf)), ctx.handle)

@@ -38,7 +38,7 @@ def test_struct_sizes_match_c_layout():
     assert ctypes.sizeof(_lib.GbsParams) == 48
     assert ctypes.sizeof(_lib.GbsStats) == 64
     assert ctypes.sizeof(_lib.GbsScene) == 32
-    assert ctypes.sizeof(_lib.GbsFan) == 40
+    assert ctypes.sizeof(_lib.GbsFan) == 48
 
 
 def test_create_without_gpu_fails_cleanly():

@@ -87,6 +87,27 @@ def test_several_sources_ragged_bit_exact():
     assert t.n_src == 3 and torch.equal(t.ray_src.cpu(), torch.as_tensor(rs))
 
 
+def test_sources_with_their_own_budget_bit_exact():
+    """Per-source arc-length budgets (the batched city gives every source its own s_max)."""
+    city = grid_city(4, 40.0, 20.0, 10.0, 60.0, seed=5)
+    src = np.array([[30.0, 30.0, 3.0], [150.0, 90.0, 12.0], [200.0, 230.0, 25.0]])
+    s_max = np.array([250.0, 600.0, 410.0])
+    fans = [fibonacci_fan(n) for n in (700, 1200, 900)]
+    d = np.concatenate([f[0] for f in fans])
+    w = np.concatenate([f[1] for f in fans])
+    rs = np.repeat(np.arange(3, dtype=np.int32), [700, 1200, 900])
+    print("case trace per-source budgets", flush=True)
+    ref = ot.trace(src, d, w, ray_src=rs, boxes=city.boxes, s_max=s_max, max_refl=8)
+    got, _ = gpu_trace(src, d, w, ray_src=rs, boxes=city.boxes, s_max=s_max, max_refl=8)
+    assert_same(ref, got)
+    last = got["ray_ptr"][1:] - 1                       # every path ends at its source's budget
+    np.testing.assert_allclose(got["seg_s0"][last] + got["seg_hi"][last], s_max[rs], rtol=1e-12)
+    with pytest.raises(_lib.GbsError):
+        gbs.trace(src, d, w, ray_src=rs, boxes=city.boxes, s_max=np.array([250.0, -1.0, 400.0]))
+    with pytest.raises(ValueError):
+        gbs.trace(src, d, w, ray_src=rs, boxes=city.boxes, s_max=np.array([250.0, 300.0]))
+
+
 def test_degenerate_fans():
     city = grid_city(2, 40.0, 20.0, 10.0, 30.0, seed=7)
     src = np.array([[40.0, 40.0, 5.0]])

@@ -211,3 +211,21 @@ def test_input_generator_agrees_with_the_oracle():
     assert np.allclose(ref["seg_hi"], tab.seg_hi, rtol=1e-15, atol=0)
     ref["seg_hi"] = tab.seg_hi
     _same_table(ref, tab)
+
+
+def test_per_source_budgets():
+    """A budget per source: each ray's path ends at its own source's s_max,
+    and a single source's rays match a one-source trace exactly."""
+    city = grid_city(2, 40.0, 20.0, 10.0, 40.0, seed=4)
+    src = np.array([[30.0, 30.0, 5.0], [90.0, 40.0, 8.0]])
+    d, w = fibonacci_fan(120)
+    rs = np.repeat(np.arange(2, dtype=np.int32), 60)
+    tab = ot.trace(src, np.concatenate([d[:60], d[60:]]), w, ray_src=rs, boxes=city.boxes, s_max=[200.0, 333.0],
+                   max_refl=4)
+    last = tab["ray_ptr"][1:] - 1
+    np.testing.assert_allclose(tab["seg_s0"][last] + tab["seg_hi"][last], np.array([200.0, 333.0])[rs],
+                               rtol=1e-12)
+    one = ot.trace(src[1:], d[60:], w[60:], boxes=city.boxes, s_max=333.0, max_refl=4)
+    k0 = tab["ray_ptr"][60]
+    for key in ("seg_a", "seg_t", "seg_s0", "seg_lo", "seg_hi"):
+        assert np.array_equal(tab[key][k0:], one[key]), key
