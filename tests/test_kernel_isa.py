@@ -82,3 +82,45 @@ def test_pair_kernels_tiled_records_real_branch_no_spill(asm):
         assert m and int(m.group(1)) == 0, name
         for op in ("v_pk_fma_f32", "v_pk_mul_f32", "v_pk_add_f32"):
             assert op not in body, (name, op)
+
+
+def _asm_of(source):
+    d = tempfile.mkdtemp()
+    try:
+        out = os.path.join(d, "k.s")
+        subprocess.run([HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-munsafe-fp-atomics", "-Xclang",
+                        "-target-feature", "-Xclang", "-packed-fp32-ops", "--offload-device-only", "-S",
+                        "-I", os.path.join(ROOT, "include"), "-I", os.path.dirname(SRC),
+                        os.path.join(os.path.dirname(SRC), source), "-o", out], check=True, capture_output=True)
+        return open(out).read()
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+
+
+@pytest.mark.parametrize("source", ["gbs_kernels.hip", "gbs_trace.hip", "gbs_ir.hip"])
+def test_every_kernel_no_scratch_no_packed_fp32(source):
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    text = _asm_of(source)
+    names = re.findall(r"\.amdhsa_kernel (\S+)", text)
+    assert names
+    for name in names:
+        meta = text[text.find(".amdhsa_kernel " + name):][:4000]
+        m = re.search(r"\.amdhsa_private_segment_fixed_size\s+(\d+)", meta)
+        assert m and int(m.group(1)) == 0, name
+    for op in ("v_pk_fma_f32", "v_pk_mul_f32", "v_pk_add_f32"):
+        assert op not in text, (source, op)
+
+
+def test_tracer_arithmetic_is_not_contracted():
+    """The tracer's table must equal, bit for bit, a reference doing one IEEE
+    operation at a time: its only FP64 fused multiply-adds are the ones inside
+    correctly rounded divisions (next to v_div_scale / v_div_fmas / v_div_fixup)."""
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    lines = _asm_of("gbs_trace.hip").split("\n")
+    div = [i for i, x in enumerate(lines) if "v_div_scale_f64" in x or "v_div_fmas_f64" in x or "v_div_fixup_f64" in x]
+    fmas = [i for i, x in enumerate(lines) if re.search(r"\bv_fmac?_f64", x)]
+    assert div and fmas
+    for i in fmas:
+        assert any(abs(i - j) <= 14 for j in div), lines[i]
