@@ -225,7 +225,7 @@ def trace_bench(sc, dev, args):
     leg = {"ms_median": med, "ms_min": float(np.min(ms)), "rays": t.n_rays, "segments": t.n_segs,
            "rays_per_s": t.n_rays / (med * 1e-3), "segments_per_s": t.n_segs / (med * 1e-3),
            "matches_input_table": same,
-           "note": "wall time of gbs.trace: count pass (twice: sizes, then in the call), prefix sums, write pass"}
+           "note": "wall time of gbs.trace: count pass, prefix sums, host read of the sizes, write pass"}
     print(f"# trace: {med:.2f} ms for {t.n_rays} rays, {t.n_segs} segments", file=sys.stderr, flush=True)
     del t
     if not args.no_cpu:

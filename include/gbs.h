@@ -280,13 +280,19 @@ typedef struct gbs_fan {
 
 /*
  * Sizes of the table gbs_trace will write: *n_segs segments and *n_face_ids
- * face-history entries.  Synchronises the context's stream.
+ * face-history entries.  Synchronises the context's stream.  *token (if
+ * non-NULL) receives a nonzero token: passed to the next gbs_trace on this
+ * context with the same arguments and unchanged input contents, it lets
+ * gbs_trace reuse this count instead of tracing twice.
  */
 int gbs_trace_count(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, int64_t* n_segs,
-                    int64_t* n_face_ids);
+                    int64_t* n_face_ids, int64_t* token);
 
 /*
- * Trace the fan and write the table (device memory, caller-allocated):
+ * Trace the fan and write the table (device memory, caller-allocated).
+ * token: 0, or the token of the last gbs_trace_count on this context for the
+ * same scene and fan (GBS_E_INVALID if it is not; any trace call in between
+ * invalidates it); the caller guarantees the inputs did not change.
  *   ray_ptr  [n_rays + 1]    CSR of each ray's segments
  *   seg_a, seg_t [cap_segs * 3], seg_s0, seg_lo, seg_hi [cap_segs]
  *   face_ptr [cap_segs + 1]  CSR into face_ids
@@ -297,9 +303,10 @@ int gbs_trace_count(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, in
  * not a unit vector is GBS_E_INVALID.  Synchronises the context's stream
  * once (to read the sizes) before the table is written.
  */
-int gbs_trace(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, int64_t cap_segs, int64_t cap_face_ids,
-              int64_t* ray_ptr, double* seg_a, double* seg_t, double* seg_s0, double* seg_lo, double* seg_hi,
-              int64_t* face_ptr, int32_t* face_ids, int64_t* n_segs, int64_t* n_face_ids);
+int gbs_trace(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, int64_t token, int64_t cap_segs,
+              int64_t cap_face_ids, int64_t* ray_ptr, double* seg_a, double* seg_t, double* seg_s0,
+              double* seg_lo, double* seg_hi, int64_t* face_ptr, int32_t* face_ids, int64_t* n_segs,
+              int64_t* n_face_ids);
 
 /*
  * Atmospheric attenuation of a pure tone in dB per metre: the model of

@@ -108,9 +108,9 @@ def load() -> ctypes.CDLL:
     lib.gbs_graph_destroy.restype = None
     lib.gbs_autotune.argtypes = common + [c_void_p, P(c_int32), P(c_int32)]
     lib.gbs_autotune.restype = ctypes.c_int
-    lib.gbs_trace_count.argtypes = [c_void_p, P(GbsScene), P(GbsFan), P(c_int64), P(c_int64)]
+    lib.gbs_trace_count.argtypes = [c_void_p, P(GbsScene), P(GbsFan), P(c_int64), P(c_int64), P(c_int64)]
     lib.gbs_trace_count.restype = ctypes.c_int
-    lib.gbs_trace.argtypes = [c_void_p, P(GbsScene), P(GbsFan), c_int64, c_int64] + [c_void_p] * 8 + \
+    lib.gbs_trace.argtypes = [c_void_p, P(GbsScene), P(GbsFan), c_int64, c_int64, c_int64] + [c_void_p] * 8 + \
         [P(c_int64), P(c_int64)]
     lib.gbs_trace.restype = ctypes.c_int
     lib.gbs_impulse_response.argtypes = [c_void_p, P(GbsRays), P(GbsSegs), P(GbsFaces), c_void_p, c_int64, c_double,

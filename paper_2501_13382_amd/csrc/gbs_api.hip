@@ -178,6 +178,12 @@ struct gbs_ctx {
     hipStream_t copy_stream = nullptr;
     hipEvent_t copied[2] = {nullptr, nullptr};
     hipEvent_t released[2] = {nullptr, nullptr};
+    // the last gbs_trace_count: its token, what it counted, and its sizes
+    // (the per-ray offsets stay in the workspace for gbs_trace to reuse)
+    int64_t trace_token = 0, trace_token_next = 0;
+    std::vector<uint64_t> trace_sig;
+    int64_t trace_tot[2] = {0, 0};
+    int trace_groups = 0;
 };
 
 struct gbs_graph {
@@ -971,11 +977,28 @@ struct TraceOut {
     int32_t* face_ids;
 };
 
+// What a count token stands for: the arguments of the counted call.
+std::vector<uint64_t> trace_signature(const gbs_scene* sc, const gbs_fan* fan) {
+    auto ptr = [](const void* p) { return (uint64_t)(uintptr_t)p; };
+    uint64_t smax_bits = 0;
+    std::memcpy(&smax_bits, &sc->s_max, sizeof smax_bits);
+    return {(uint64_t)sc->n_boxes, (uint64_t)sc->panels, ptr(sc->boxes), smax_bits, (uint64_t)sc->max_refl,
+            (uint64_t)sc->image_complete, (uint64_t)fan->n_src, ptr(fan->src_xyz), (uint64_t)fan->n_rays,
+            ptr(fan->dirs), ptr(fan->ray_src), ptr(fan->s_max_src)};
+}
+
 // Count pass and prefix sums; with `out` also the write pass (after the
-// capacity check).  Returns the sizes.
+// capacity check).  With a token from the last count of the same arguments,
+// the count is reused.  Returns the sizes.
 std::pair<int64_t, int64_t> trace_impl(gbs_ctx* ctx, const gbs_scene* sc, const gbs_fan* fan, int64_t cap_segs,
-                                       int64_t cap_faces, const TraceOut* out) {
+                                       int64_t cap_faces, const TraceOut* out, int64_t token = 0) {
     GBS_CHECK(sc && fan, "scene and fan must be non-null");
+    const bool reuse = out && token != 0;
+    if (reuse) {
+        GBS_CHECK(token == ctx->trace_token, "count token is not the last gbs_trace_count on this context");
+        GBS_CHECK(trace_signature(sc, fan) == ctx->trace_sig, "count token was issued for other arguments");
+    }
+    ctx->trace_token = 0;                 // the workspace is about to change
     GBS_CHECK(sc->n_boxes >= 0 && (sc->n_boxes == 0 || sc->boxes), "scene.boxes");
     GBS_CHECK(sc->panels >= 1 && sc->panels <= 8, "scene.panels must be in 1..8");
     GBS_CHECK(sc->max_refl >= 0 && sc->max_refl <= kTraceMaxRefl, "scene.max_refl must be in 0..32");
@@ -1011,13 +1034,15 @@ std::pair<int64_t, int64_t> trace_impl(gbs_ctx* ctx, const gbs_scene* sc, const 
                       src[3 * k + 2] > 0,
                   "sources must be finite and above the ground");
     const int64_t n = fan->n_rays;
-    const TraceScene S = group_boxes(bx, sc->n_boxes);
-    const size_t ng = std::max<size_t>(S.n_groups, 1);
+    const TraceScene S = reuse ? TraceScene{} : group_boxes(bx, sc->n_boxes);
+    const int n_groups = reuse ? ctx->trace_groups : S.n_groups;
+    const size_t ng = std::max<size_t>(n_groups, 1);
     double* d_box = ws.get<double>("tr_box", std::max<size_t>(bx.size(), 1));
     double* d_gbox = ws.get<double>("tr_gbox", ng * 6);
     int32_t* d_mem = ws.get<int32_t>("tr_members", ng * kTraceGroup);
-    if (!bx.empty()) GBS_HIP(hipMemcpyAsync(d_box, bx.data(), bx.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    if (S.n_groups) {
+    if (!reuse && !bx.empty())
+        GBS_HIP(hipMemcpyAsync(d_box, bx.data(), bx.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    if (!reuse && S.n_groups) {
         GBS_HIP(hipMemcpyAsync(d_gbox, S.gbox.data(), S.gbox.size() * sizeof(double), hipMemcpyHostToDevice, st));
         GBS_HIP(hipMemcpyAsync(d_mem, S.members.data(), S.members.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                                st));
@@ -1026,31 +1051,46 @@ std::pair<int64_t, int64_t> trace_impl(gbs_ctx* ctx, const gbs_scene* sc, const 
     int64_t* nface = ws.get<int64_t>("tr_nface", n + 1);
     int64_t* rp = out ? out->ray_ptr : ws.get<int64_t>("tr_rayptr", n + 1);
     int64_t* fbase = ws.get<int64_t>("tr_fbase", n + 1);
-    int* bad = ws.get<int>("tr_bad", 1);
-    GBS_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
-    GBS_HIP(hipMemsetAsync(nseg + n, 0, sizeof(int64_t), st));
     const dim3 grid(blocks_for(n, kTraceThreads)), block(kTraceThreads);
-    if (n > 0)
-        hipLaunchKernelGGL(k_trace<true>, grid, block, 0, st, n, fan->n_src, fan->src_xyz, fan->ray_src, fan->dirs,
-                           fan->s_max_src, d_box, d_gbox, d_mem, S.n_groups, sc->panels, sc->max_refl, sc->s_max,
-                           sc->image_complete, nseg, bad,
-                           nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
-    GBS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_trace_face_counts, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st, n, nseg, nface);
-    size_t tmp = 0;
-    GBS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, nseg, rp, (int)(n + 1), st));
-    void* tb = ws.get<char>("tr_scan", tmp);
-    GBS_HIP(hipcub::DeviceScan::ExclusiveSum(tb, tmp, nseg, rp, (int)(n + 1), st));
-    GBS_HIP(hipcub::DeviceScan::ExclusiveSum(tb, tmp, nface, fbase, (int)(n + 1), st));
     int64_t tot[2] = {0, 0};
-    int h_bad = 0;
-    GBS_HIP(hipMemcpyAsync(&tot[0], rp + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    GBS_HIP(hipMemcpyAsync(&tot[1], fbase + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    GBS_HIP(hipMemcpyAsync(&h_bad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
-    GBS_HIP(hipStreamSynchronize(st));
-    GBS_CHECK(!(h_bad & 1), "fan.dirs must be unit vectors");
-    GBS_CHECK(!(h_bad & 2), "fan.ray_src must be non-decreasing and in [0, n_src)");
-    if (!out) return {tot[0], tot[1]};
+    if (reuse) {
+        // the offsets of the counted call, into the caller's ray_ptr
+        GBS_HIP(hipMemcpyAsync(rp, ws.get<int64_t>("tr_rayptr", n + 1), sizeof(int64_t) * (n + 1),
+                               hipMemcpyDeviceToDevice, st));
+        tot[0] = ctx->trace_tot[0];
+        tot[1] = ctx->trace_tot[1];
+    } else {
+        int* bad = ws.get<int>("tr_bad", 1);
+        GBS_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+        GBS_HIP(hipMemsetAsync(nseg + n, 0, sizeof(int64_t), st));
+        if (n > 0)
+            hipLaunchKernelGGL(k_trace<true>, grid, block, 0, st, n, fan->n_src, fan->src_xyz, fan->ray_src, fan->dirs,
+                               fan->s_max_src, d_box, d_gbox, d_mem, S.n_groups, sc->panels, sc->max_refl, sc->s_max,
+                               sc->image_complete, nseg, bad,
+                               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+        GBS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_trace_face_counts, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st, n, nseg, nface);
+        size_t tmp = 0;
+        GBS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, nseg, rp, (int)(n + 1), st));
+        void* tb = ws.get<char>("tr_scan", tmp);
+        GBS_HIP(hipcub::DeviceScan::ExclusiveSum(tb, tmp, nseg, rp, (int)(n + 1), st));
+        GBS_HIP(hipcub::DeviceScan::ExclusiveSum(tb, tmp, nface, fbase, (int)(n + 1), st));
+        int h_bad = 0;
+        GBS_HIP(hipMemcpyAsync(&tot[0], rp + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        GBS_HIP(hipMemcpyAsync(&tot[1], fbase + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        GBS_HIP(hipMemcpyAsync(&h_bad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+        GBS_HIP(hipStreamSynchronize(st));
+        GBS_CHECK(!(h_bad & 1), "fan.dirs must be unit vectors");
+        GBS_CHECK(!(h_bad & 2), "fan.ray_src must be non-decreasing and in [0, n_src)");
+        if (!out) {
+            ctx->trace_token = ++ctx->trace_token_next;
+            ctx->trace_sig = trace_signature(sc, fan);
+            ctx->trace_tot[0] = tot[0];
+            ctx->trace_tot[1] = tot[1];
+            ctx->trace_groups = S.n_groups;
+            return {tot[0], tot[1]};
+        }
+    }
     GBS_CHECK(tot[0] <= cap_segs && tot[1] <= cap_faces,
               "table capacity too small: needs " + std::to_string(tot[0]) + " segments and " +
                   std::to_string(tot[1]) + " face ids");
@@ -1060,7 +1100,7 @@ std::pair<int64_t, int64_t> trace_impl(gbs_ctx* ctx, const gbs_scene* sc, const 
     GBS_CHECK(out->face_ptr, "face_ptr must be non-null");
     if (n > 0)
         hipLaunchKernelGGL(k_trace<false>, grid, block, 0, st, n, fan->n_src, fan->src_xyz, fan->ray_src,
-                           fan->dirs, fan->s_max_src, d_box, d_gbox, d_mem, S.n_groups, sc->panels, sc->max_refl,
+                           fan->dirs, fan->s_max_src, d_box, d_gbox, d_mem, n_groups, sc->panels, sc->max_refl,
                            sc->s_max, sc->image_complete,
                            nullptr, nullptr, rp, fbase, out->a, out->t, out->s0, out->lo, out->hi, out->face_ptr,
                            out->face_ids);
@@ -1430,7 +1470,7 @@ int gbs_impulse_response(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* seg
 }
 
 int gbs_trace_count(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, int64_t* n_segs,
-                    int64_t* n_face_ids) {
+                    int64_t* n_face_ids, int64_t* token) {
     if (!ctx) return GBS_E_INVALID;
     return guarded(ctx, [&]() {
         GBS_CHECK(n_segs && n_face_ids, "n_segs and n_face_ids must be non-null");
@@ -1438,19 +1478,20 @@ int gbs_trace_count(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, in
         const auto r = trace_impl(ctx, scene, fan, 0, 0, nullptr);
         *n_segs = r.first;
         *n_face_ids = r.second;
+        if (token) *token = ctx->trace_token;
         return GBS_OK;
     });
 }
 
-int gbs_trace(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, int64_t cap_segs, int64_t cap_face_ids,
-              int64_t* ray_ptr, double* seg_a, double* seg_t, double* seg_s0, double* seg_lo, double* seg_hi,
-              int64_t* face_ptr, int32_t* face_ids, int64_t* n_segs, int64_t* n_face_ids) {
+int gbs_trace(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, int64_t token, int64_t cap_segs,
+              int64_t cap_face_ids, int64_t* ray_ptr, double* seg_a, double* seg_t, double* seg_s0, double* seg_lo,
+              double* seg_hi, int64_t* face_ptr, int32_t* face_ids, int64_t* n_segs, int64_t* n_face_ids) {
     if (!ctx) return GBS_E_INVALID;
     return guarded(ctx, [&]() {
         GBS_CHECK(ray_ptr, "ray_ptr must be non-null");
         GBS_HIP(hipSetDevice(ctx->device));
         const TraceOut o{ray_ptr, seg_a, seg_t, seg_s0, seg_lo, seg_hi, face_ptr, face_ids};
-        const auto r = trace_impl(ctx, scene, fan, cap_segs, cap_face_ids, &o);
+        const auto r = trace_impl(ctx, scene, fan, cap_segs, cap_face_ids, &o, token);
         if (n_segs) *n_segs = r.first;
         if (n_face_ids) *n_face_ids = r.second;
         return GBS_OK;

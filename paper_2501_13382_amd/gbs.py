@@ -255,9 +255,9 @@ def trace(src_xyz, dirs, weights, *, ray_src=None, boxes=None, panels=1, s_max, 
     scene = _lib.GbsScene(int(bx.shape[0]), int(panels), _ptr(bx), float(sm.max()) if sm.size else 0.0,
                           int(max_refl), 1 if image_complete else 0)
     fan = _lib.GbsFan(int(src.shape[0]), _ptr(src), n, _ptr(d), _ptr(rs), _ptr(sm_src) if sm_src is not None else None)
-    ns, nf = ctypes.c_int64(0), ctypes.c_int64(0)
+    ns, nf, token = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
     _lib.check(ctx.lib.gbs_trace_count(ctx.handle, ctypes.byref(scene), ctypes.byref(fan), ctypes.byref(ns),
-                                       ctypes.byref(nf)), ctx.handle)
+                                       ctypes.byref(nf), ctypes.byref(token)), ctx.handle)
     S, F = int(ns.value), int(nf.value)
     out = _Traced(src_xyz=src, ray_w=w, ray_src=rs, n_faces=1 + int(bx.shape[0]) * 5 * int(panels) ** 2,
                   ray_ptr=torch.empty(n + 1, dtype=torch.int64, device=dev),
@@ -266,9 +266,11 @@ def trace(src_xyz, dirs, weights, *, ray_src=None, boxes=None, panels=1, s_max, 
                   seg_hi=torch.empty(S, dtype=f64, device=dev),
                   face_ptr=torch.empty(S + 1, dtype=torch.int64, device=dev),
                   face_ids=torch.empty(F, dtype=torch.int32, device=dev))
-    rc = ctx.lib.gbs_trace(ctx.handle, ctypes.byref(scene), ctypes.byref(fan), S, F, _ptr(out.ray_ptr),
-                           _ptr(out.seg_a), _ptr(out.seg_t), _ptr(out.seg_s0), _ptr(out.seg_lo), _ptr(out.seg_hi),
-                           _ptr(out.face_ptr), _ptr(out.face_ids), ctypes.byref(ns), ctypes.byref(nf))
+    # the count just taken is reused (same arguments, inputs untouched in between)
+    rc = ctx.lib.gbs_trace(ctx.handle, ctypes.byref(scene), ctypes.byref(fan), token.value, S, F,
+                           _ptr(out.ray_ptr), _ptr(out.seg_a), _ptr(out.seg_t), _ptr(out.seg_s0), _ptr(out.seg_lo),
+                           _ptr(out.seg_hi), _ptr(out.face_ptr), _ptr(out.face_ids), ctypes.byref(ns),
+                           ctypes.byref(nf))
     _lib.check(rc, ctx.handle)
     return Table(out, device=dev)
 

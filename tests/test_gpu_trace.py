@@ -126,6 +126,49 @@ def test_degenerate_fans():
     assert t.n_segs == 0 and list(got["ray_ptr"]) == [0] and list(got["face_ptr"]) == [0]
 
 
+def test_count_token_reuse_and_staleness():
+    """gbs_trace with the token of the last count reuses it (same table as a
+    full trace); a token from an earlier count, or for other arguments, is
+    refused."""
+    import ctypes
+    city = grid_city(3, 40.0, 20.0, 10.0, 40.0, seed=11)
+    src = torch.as_tensor(np.array([[50.0, 50.0, 6.0]]), device="cuda")
+    d, w = fibonacci_fan(2000)
+    dd = torch.as_tensor(d, device="cuda")
+    bx = torch.as_tensor(city.boxes, device="cuda")
+    rs = torch.zeros(len(d), dtype=torch.int32, device="cuda")
+    ctx = gbs.context("cuda")
+    ctx.bind_stream()
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())
+    scene = _lib.GbsScene(len(city.boxes), 1, ptr(bx), 400.0, 6, 0)
+    fan = _lib.GbsFan(1, ptr(src), len(d), ptr(dd), ptr(rs), None)
+    ns, nf, tok1, tok2 = (ctypes.c_int64(0) for _ in range(4))
+    cnt = lambda tok: ctx.lib.gbs_trace_count(ctx.handle, ctypes.byref(scene), ctypes.byref(fan), ctypes.byref(ns),
+                                              ctypes.byref(nf), ctypes.byref(tok))
+    assert cnt(tok1) == 0 and cnt(tok2) == 0 and tok1.value != tok2.value != 0
+    S, F = ns.value, nf.value
+    out = [torch.empty(len(d) + 1, dtype=torch.int64, device="cuda"), torch.empty((S, 3), dtype=torch.float64,
+           device="cuda"), torch.empty((S, 3), dtype=torch.float64, device="cuda")] + \
+        [torch.empty(S, dtype=torch.float64, device="cuda") for _ in range(3)] + \
+        [torch.empty(S + 1, dtype=torch.int64, device="cuda"), torch.empty(F, dtype=torch.int32, device="cuda")]
+    run = lambda tok: ctx.lib.gbs_trace(ctx.handle, ctypes.byref(scene), ctypes.byref(fan), tok, S, F,
+                                        *[ptr(t) for t in out], ctypes.byref(ns), ctypes.byref(nf))
+    assert run(tok1.value) == _lib.GBS_E_INVALID           # an earlier count
+    assert cnt(tok2) == 0
+    scene_other = _lib.GbsScene(len(city.boxes), 1, ptr(bx), 300.0, 6, 0)
+    assert ctx.lib.gbs_trace(ctx.handle, ctypes.byref(scene_other), ctypes.byref(fan), tok2.value, S, F,
+                             *[ptr(t) for t in out], ctypes.byref(ns), ctypes.byref(nf)) == _lib.GBS_E_INVALID
+    assert cnt(tok2) == 0 and run(tok2.value) == 0         # reuses the count
+    torch.cuda.synchronize()
+    reused = [t.cpu().numpy() for t in out]
+    assert run(0) == 0                                      # full trace, no token
+    torch.cuda.synchronize()
+    for a, b in zip(reused, out):
+        assert np.array_equal(a, b.cpu().numpy())
+    ref = ot.trace(np.array([[50.0, 50.0, 6.0]]), d, w, boxes=city.boxes, s_max=400.0, max_refl=6)
+    assert np.array_equal(reused[0], ref["ray_ptr"]) and np.array_equal(reused[7], ref["face_ids"])
+
+
 def test_invalid_requests_rejected():
     city = grid_city(2, 40.0, 20.0, 10.0, 30.0, seed=7)
     d, w = fibonacci_fan(10)
