@@ -132,3 +132,22 @@ def test_full_size_open_plane_with_paper_atmosphere():
     P = P.cpu().numpy().reshape(8, -1)[:, idx]
     TL = TL.cpu().numpy().reshape(8, -1)[:, idx]
     assert_within(compare(P, TL, P_ref, TL_ref, ab), "mix")
+
+
+def test_gradcheck_with_absorption():
+    """torch.autograd.gradcheck through GBSFunction with absorption on
+    (finite differences of TL on the GPU F64 path: coefficients, receivers, eps)."""
+    from scenes import city_scene
+    sc = city_scene(n_blocks=2, n_rays=500, grid=3, freqs=(400.0,), max_refl=4, city_seed=5, panels=2,
+                    complex_gamma=True)
+    t = gbs.Table(sc.table, device="cuda")
+    gamma = torch.tensor(sc.gamma, dtype=torch.complex128, device="cuda", requires_grad=True)
+    rcv = torch.tensor(sc.rcv, dtype=torch.float64, device="cuda", requires_grad=True)
+    eps = torch.tensor(sc.eps, dtype=torch.float64, device="cuda", requires_grad=True)
+    opts = {"mode": "f64", "c": sc.c, "gate": sc.gate, "alpha": np.array([[0.02]])}
+    freqs = torch.tensor(sc.freqs, dtype=torch.float64, device="cuda")
+
+    def f(g, r, e):
+        P, TL = gbs.GBSFunction.apply(g, r, e, t, freqs, opts)
+        return TL
+    assert torch.autograd.gradcheck(f, (gamma, rcv, eps), eps=1e-6, atol=1e-5, rtol=1e-4, nondet_tol=1e-9)
