@@ -93,6 +93,18 @@ WORKLOADS = {"open_plane_100k": ("open_plane_100k_8band", _open_plane_100k),
              "city_batched": ("city_batched_16src_4band_1024sq", _city_batched)}
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (first entry of /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def absorption_bench(sc, dev, table, rcv, freqs, eps, gamma, args, sec_step):
     """The same forward with atmospheric absorption in the paper's atmosphere
     (Tables 2 and 3: 20 deg C, 70 % relative humidity, 1 atm; ISO 9613-1 per
@@ -490,6 +502,7 @@ def main():
         el = time.perf_counter() - t
         pairs = table.n_segs * len(idx) * len(sc.freqs)
         result["cpu_baseline"] = {"value": pairs / el, "unit": "evals/s", "cores": threads, "kind": "oracle",
+                                  "cpu_model": cpu_model(),
                                   "sample": f"{len(idx)} of {len(sc.rcv)} receivers (seed 5), all "
                                             f"{table.n_segs} segments, {len(sc.freqs)} bands; {el:.1f}s",
                                   "extrapolated_full_config_s": dense / (pairs / el)}
