@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
 baseline leg may use this package; the library under test never does.  The C
 source (gbs_oracle.c) is the plain definition of the sum (paper Sec. 2,
 Eqs. (1)-(3)), with an optional per-job atmospheric absorption exp(-alpha s)
-(the atmosphere of Tables 2 and 3 through ISO 9613-1); this module only
+(the atmosphere of Tables 2 and 3 through ISO 9613-1) and optional
+anisotropic beams (a diagonal 2x2 Q in each segment's ray frame); this module only
 marshals numpy arrays to it and builds it.  oracle/tracer.py is the oracle
 of the ray-tracing stage.
 """
@@ -43,6 +44,8 @@ def _load():
         common = [i32, i64, P, P, P, i64, P, P, P, P, P, P, P, i32, P, i64, P, i32, P, P, P, f64, f64]
         lib.gbso_forward.argtypes = common + [i32, i32, P, P, P, P]
         lib.gbso_forward.restype = ctypes.c_int
+        lib.gbso_forward_aniso.argtypes = common + [P, P, i32, P, P, P]
+        lib.gbso_forward_aniso.restype = ctypes.c_int
         lib.gbso_backward.argtypes = common + [P, i32, P, P, P, P]
         lib.gbso_backward.restype = ctypes.c_int
         lib.gbso_air_absorption_db.argtypes = [f64, f64, f64, f64]
@@ -88,7 +91,7 @@ def _table_args(table, gamma, rcv, freqs, eps, c, gate, alpha=None):
 
 
 def forward(table, gamma, rcv, freqs, eps, c=343.0, gate=9.21, n_threads=1, mask_mode=0, mask=None,
-            return_absum=False, alpha=None):
+            return_absum=False, alpha=None, eps_e2=None, seg_e1=None):
     """P [n_jobs, n_rcv] complex128 and TL [n_jobs, n_rcv] float64.
 
     mask_mode 1 records the active (job, receiver, segment) set into `mask`
@@ -96,6 +99,9 @@ def forward(table, gamma, rcv, freqs, eps, c=343.0, gate=9.21, n_threads=1, mask
     frozen instead of the gate.  return_absum adds sum |u| per output (the
     scale against which cancellation in P is judged).  alpha: atmospheric
     absorption per job in Np/m (amplitude factor exp(-alpha s)), or None.
+    eps_e2 and seg_e1 (given together) select anisotropic beams: eps is then
+    the beam parameter along each segment's unit normal e1 (seg_e1, [n_segs, 3])
+    and eps_e2 (one per job) the one along e2 = t x e1.
     """
     args, arrs = _table_args(table, gamma, rcv, freqs, eps, c, gate, alpha)
     n_jobs = table.n_src * arrs["freqs"].shape[0]
@@ -106,7 +112,18 @@ def forward(table, gamma, rcv, freqs, eps, c=343.0, gate=9.21, n_threads=1, mask
         if mask is None or mask.dtype != np.uint8 or mask.size != n_jobs * n_rcv * table.n_segs:
             raise ValueError("mask must be uint8 [n_jobs, n_rcv, n_segs]")
     absum = np.zeros((n_jobs, n_rcv), np.float64) if return_absum else None
-    rc = _load().gbso_forward(*args, int(n_threads), int(mask_mode), _ptr(mask), _ptr(P), _ptr(TL), _ptr(absum))
+    if (eps_e2 is None) != (seg_e1 is None):
+        raise ValueError("eps_e2 and seg_e1 go together")
+    if eps_e2 is not None:
+        if mask_mode:
+            raise ValueError("anisotropic beams take no mask")
+        e2 = np.ascontiguousarray(eps_e2, np.float64).reshape(-1)
+        f1 = np.ascontiguousarray(seg_e1, np.float64).reshape(-1, 3)
+        if e2.shape[0] != n_jobs or f1.shape[0] != table.n_segs:
+            raise ValueError("eps_e2 needs one value per job and seg_e1 one frame vector per segment")
+        rc = _load().gbso_forward_aniso(*args, _ptr(e2), _ptr(f1), int(n_threads), _ptr(P), _ptr(TL), _ptr(absum))
+    else:
+        rc = _load().gbso_forward(*args, int(n_threads), int(mask_mode), _ptr(mask), _ptr(P), _ptr(TL), _ptr(absum))
     if rc != 0:
         raise RuntimeError(f"gbso_forward failed ({rc})")
     if return_absum:

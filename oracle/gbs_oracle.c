@@ -193,6 +193,89 @@ int gbso_forward(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const do
 }
 
 /*
+ * Anisotropic beams: Eq. (1) with a 2x2 Q.  Ray-centred coordinates (s, q1, q2)
+ * measure the normal offset along unit vectors e1 and e2 = t x e1 (both normal
+ * to the axis t).  Eq. (2) in a homogeneous medium with P = I / c and the
+ * initial Q0 = diag(-i eps1, -i eps2) gives Q(s) = diag(q1, q2) with
+ * q_m = s - i eps_m, hence
+ *
+ *   amplitude  sqrt(det Q0 / det Q) = sqrt(q01 / q1) * sqrt(q02 / q2)
+ *   exponent   E = i omega (tau + 1/2 p (n1^2 / q1 + n2^2 / q2)),
+ *              n_m = (R - a).e_m        keep iff Re E >= -G
+ *
+ * Each ratio q0m / qm = eps_m (eps_m - i s) / |q_m|^2 has a positive real part
+ * for every real s, so the principal square root is the branch that is
+ * continuous along the beam (and equals 1 at s = 0): no branch tracking is
+ * needed.  A planar reflection maps the frame by the mirror, which leaves n1^2
+ * and n2^2 unchanged, so the frame of a reflected segment is the mirror image
+ * of the incident one (the sign of e1 does not matter).  eps1 = eps[job] is the
+ * beam parameter along e1, eps2 = eps_e2[job] along e2; with eps1 = eps2 the
+ * beam is the isotropic one of gbso_forward.  seg_e1[3 j..] is e1 of segment j.
+ */
+int gbso_forward_aniso(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const double* ray_w,
+                       const int32_t* ray_src, int64_t n_segs, const double* seg_a, const double* seg_t,
+                       const double* seg_s0, const double* seg_lo, const double* seg_hi, const int64_t* face_ptr,
+                       const int32_t* face_ids, int32_t n_faces, const double* gamma, int64_t n_rcv,
+                       const double* rcv, int32_t n_freq, const double* freqs, const double* eps,
+                       const double* alpha, double c, double gate_G, const double* eps_e2, const double* seg_e1,
+                       int32_t n_threads, double* P_out, double* TL_out, double* absum_out) {
+    (void)n_faces;
+    if (n_src < 0 || n_rays < 0 || n_segs < 0 || n_rcv < 0 || n_freq < 0 || c <= 0) return -1;
+    if (eps_e2 == NULL || (n_segs > 0 && seg_e1 == NULL)) return -1;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    for (int32_t src = 0; src < n_src; ++src) {
+        for (int32_t b = 0; b < n_freq; ++b) {
+            const int64_t job = (int64_t)src * n_freq + b;
+            const double omega = 2.0 * PI * freqs[b];
+            const double k = omega / c;
+            const double p = 1.0 / c;
+            const double e1 = eps[job], e2 = eps_e2[job];
+            const double al = alpha ? alpha[job] : 0.0;
+#pragma omp parallel for schedule(dynamic, 16) if (n_threads != 1)
+            for (int64_t r = 0; r < n_rcv; ++r) {
+                const double* R = rcv + 3 * r;
+                nsum re = {0, 0}, im = {0, 0}, ab = {0, 0};
+                for (int64_t i = 0; i < n_rays; ++i) {
+                    if (ray_src[i] != src) continue;
+                    const cplx weight = I * k * ray_w[i] / (8.0 * PI * PI);
+                    for (int64_t j = ray_ptr[i]; j < ray_ptr[i + 1]; ++j) {
+                        pair_geom g;
+                        const double* t = seg_t + 3 * j;
+                        const double* f1 = seg_e1 + 3 * j;
+                        if (!pair_geometry(R, seg_a + 3 * j, t, seg_s0[j], seg_lo[j], seg_hi[j], &g)) continue;
+                        const double f2[3] = {t[1] * f1[2] - t[2] * f1[1], t[2] * f1[0] - t[0] * f1[2],
+                                              t[0] * f1[1] - t[1] * f1[0]};
+                        const double n1 = g.v[0] * f1[0] + g.v[1] * f1[1] + g.v[2] * f1[2];
+                        const double n2 = g.v[0] * f2[0] + g.v[1] * f2[1] + g.v[2] * f2[2];
+                        const cplx q01 = -I * e1, q02 = -I * e2;
+                        const cplx q1 = q01 + g.s, q2 = q02 + g.s;
+                        const cplx E = I * omega * (g.s / c + 0.5 * p * (n1 * n1 / q1 + n2 * n2 / q2));
+                        if (!(creal(E) >= -gate_G)) continue;
+                        const cplx amp = csqrt(q01 / q1) * csqrt(q02 / q2);
+                        const cplx u = weight * face_product(face_ptr, face_ids, gamma, j) * amp * cexp(E) *
+                                       exp(-al * g.s);
+                        nsum_add(&re, creal(u));
+                        nsum_add(&im, cimag(u));
+                        nsum_add(&ab, cabs(u));
+                    }
+                }
+                double pr = nsum_get(&re), pi = nsum_get(&im);
+                if (absum_out) absum_out[job * n_rcv + r] = nsum_get(&ab);
+                P_out[2 * (job * n_rcv + r)] = pr;
+                P_out[2 * (job * n_rcv + r) + 1] = pi;
+                double mag = hypot(pr, pi);
+                TL_out[job * n_rcv + r] = mag > 0 ? -20.0 * log10(mag) : INFINITY;
+            }
+        }
+    }
+    return 0;
+}
+
+/*
  * Hand-derived adjoint.  With dL = Re sum_{job,r} lambda[job,r] dP[job,r]:
  *
  *   d ln u / dR   = t (ik - 1/q - (ik/2) n^2 / q^2 - alpha) + (ik/q) nvec,

@@ -437,6 +437,25 @@ def trace_city(src, dirs, weights, city: City, s_max: float, max_refl: int) -> R
         meta={"kind": "city", "s_max": s_max, "max_refl": max_refl})
 
 
+def normal_frame(t, up=(0.0, 0.0, 1.0)) -> np.ndarray:
+    """Unit vector e1 normal to each axis t ([n, 3]): up x t normalised, or,
+    where t is parallel to `up`, the coordinate axis least aligned with t made
+    normal to it.  With the default up = z this is the horizontal normal
+    (-t_y, t_x, 0) / |(t_x, t_y)|, which a reflection on a vertical wall, a roof
+    or the ground maps to plus or minus the horizontal normal of the reflected
+    axis: the frame of anisotropic beams in the box scenes."""
+    t = np.asarray(t, np.float64).reshape(-1, 3)
+    u = np.broadcast_to(np.asarray(up, np.float64), t.shape)
+    e = np.cross(u, t)
+    n = np.linalg.norm(e, axis=1)
+    bad = ~(n > 0.0)
+    if bad.any():
+        ax = np.eye(3)[np.argmin(np.abs(t[bad]), axis=1)]
+        e[bad] = ax - (ax * t[bad]).sum(1, keepdims=True) * t[bad]
+        n[bad] = np.linalg.norm(e[bad], axis=1)
+    return e / n[:, None]
+
+
 def receiver_grid(nx: int, ny: int, x0: float, x1: float, y0: float, y1: float, z: float) -> np.ndarray:
     """Row-major grid (x fastest) of receivers at height z."""
     xs = x0 + (x1 - x0) * np.arange(nx) / max(nx - 1, 1)

@@ -1,0 +1,143 @@
+"""Pins for the oracle's anisotropic beams (Eq. (1) with Q = diag(q1, q2)).
+
+Each test compares the oracle with something its formula does not contain:
+the free-field monopole and Lloyd's mirror (closed forms the beam sum must
+reach whatever the beam widths and frame), the on-axis beam with its Gouy
+phase split over the two axes, the Gaussian decay along each frame vector,
+the isotropic oracle (a separate code path) at equal widths, and the exact
+symmetry that swaps the two axes.  A swapped width, a wrong square-root
+branch, a dropped factor or a wrong frame vector fails at least one of them.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from scenes import eps_rule, fibonacci_fan, normal_frame, open_plane_2k, trace_open_plane
+
+from .test_oracle_pins import monopole, single_ray_table
+
+C = 343.0
+
+
+def _frame(table, up=(0.0, 0.0, 1.0)):
+    return normal_frame(table.seg_t, up)
+
+
+@pytest.mark.parametrize("up", [(0.0, 0.0, 1.0), (1.0, 2.0, 3.0)])
+def test_free_field_monopole_anisotropic(oracle_lib, up):
+    """Beams twice as wide along e2 as along e1 still sum to exp(ikr)/(4 pi r)
+    (the stationary-phase value of the beam integral does not depend on the
+    initial Q), for the horizontal frame and for a tilted one."""
+    f = 500.0
+    k = 2 * np.pi * f / C
+    rng = np.random.default_rng(11)
+    d = rng.standard_normal((48, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    r = rng.uniform(10.0, 140.0, 48)
+    S = np.array([0.0, 0.0, 10.0])
+    R = S + d * r[:, None]
+    dirs, w = fibonacci_fan(20000)
+    table = trace_open_plane(S, dirs, w, s_max=180.0, policy="EC")
+    e = eps_rule([f], 150.0)[0]
+    P, TL = oracle.forward(table, np.array([0.0 + 0j]), R, [f], [0.8 * e], eps_e2=[1.6 * e],
+                           seg_e1=_frame(table, up))
+    ref = monopole(R, S, k)
+    dTL = np.abs(TL[0] + 20 * np.log10(np.abs(ref)))
+    rel = np.abs(P[0] - ref) / np.abs(ref)
+    assert dTL.max() <= 0.1, dTL.max()
+    assert rel.max() <= 0.05, rel.max()
+    assert np.percentile(rel, 50) <= 0.03
+
+
+@pytest.mark.parametrize("gamma", [1.0 + 0j, 0.8 * np.exp(1j * np.pi / 8)])
+def test_lloyds_mirror_anisotropic(oracle_lib, gamma):
+    """Lloyd's mirror with anisotropic beams in the horizontal frame (which
+    the ground reflection maps to itself): the direct plus Gamma times the
+    image monopole, on the 64 x 64 grid at 500 Hz."""
+    sc = open_plane_2k(eps="rule")
+    k = 2 * np.pi * 500.0 / C
+    e = sc.eps[0]
+    P, TL = oracle.forward(sc.table, np.array([gamma]), sc.rcv, sc.freqs, [e], eps_e2=[1.8 * e],
+                           seg_e1=_frame(sc.table), n_threads=4)
+    S = sc.table.src_xyz[0]
+    Pd = monopole(sc.rcv, S, k)
+    Pi = gamma * monopole(sc.rcv, S * np.array([1, 1, -1]), k)
+    ref = Pd + Pi
+    err_norm = np.abs(P[0] - ref) / (np.abs(Pd) + np.abs(Pi))
+    dTL = np.abs(TL[0] + 20 * np.log10(np.abs(ref)))
+    assert np.percentile(dTL, 99) <= 0.1, np.percentile(dTL, 99)
+    assert np.percentile(err_norm, 99) <= 0.03, np.percentile(err_norm, 99)
+    assert np.median(dTL) <= 0.01
+
+
+def test_on_axis_beam_anisotropic():
+    """On the axis the term is w k / (8 pi^2) sqrt(eps1 eps2 / (|q1| |q2|))
+    exp(i (k s + (atan(eps1/s) + atan(eps2/s)) / 2)): each axis contributes
+    half its Gouy phase (the isotropic beam's is atan(eps/s)).  The far-field footprint
+    2 pi / (k sqrt(eps1 eps2)) times the on-axis magnitude is the monopole."""
+    w = 1e-3
+    table = single_ray_table(a=[0, 0, 0], t=[0, 1, 0], s0=12.0, lo=-100, hi=100.0, faces=[], w=w)
+    f, e1, e2 = 700.0, 3.0, 7.5
+    k = 2 * np.pi * f / C
+    s = 37.0
+    P, _ = oracle.forward(table, np.ones(4, complex), np.array([[0, 25.0, 0]]), [f], [e1], eps_e2=[e2],
+                          seg_e1=np.array([[0.0, 0.0, 1.0]]))
+    mag = w * k / (8 * np.pi ** 2) * np.sqrt(e1 * e2 / (np.hypot(s, e1) * np.hypot(s, e2)))
+    phase = k * s + 0.5 * (np.arctan(e1 / s) + np.arctan(e2 / s))
+    expect = mag * np.exp(1j * phase)
+    assert abs(P[0, 0] - expect) <= 1e-13 * abs(expect)
+    s_far = 1e5
+    table = single_ray_table(a=[0, 0, 0], t=[0, 1, 0], s0=12.0, lo=-100, hi=2 * s_far, faces=[], w=w)
+    P, _ = oracle.forward(table, np.ones(4, complex), np.array([[0, s_far - 12.0, 0]]), [f], [e1], eps_e2=[e2],
+                          seg_e1=np.array([[0.0, 0.0, 1.0]]), gate=1e9)
+    footprint = 2 * np.pi / (k * np.sqrt(e1 * e2))
+    assert abs(abs(P[0, 0]) * footprint / w - 1 / (4 * np.pi * s_far)) <= 1e-3 / (4 * np.pi * s_far)
+
+
+def test_gaussian_decay_along_each_axis():
+    """Off the axis by n along e1 the magnitude falls by exp(-(k/2) n^2
+    eps1/(s^2 + eps1^2)), along e2 by the same with eps2: the width that goes
+    with each frame vector."""
+    table = single_ray_table(a=[0, 0, 0], t=[1, 0, 0], s0=5.0, lo=-100, hi=100.0, faces=[], w=1.0)
+    f, e1, e2 = 300.0, 4.0, 12.0
+    k = 2 * np.pi * f / C
+    x, n = 20.0, 3.0
+    s = 5.0 + x
+    f1 = np.array([[0.0, 1.0, 0.0]])                  # e1 = y, e2 = t x e1 = z
+    R = np.array([[x, 0, 0], [x, n, 0], [x, 0, n]])
+    P, _ = oracle.forward(table, np.ones(4, complex), R, [f], [e1], eps_e2=[e2], seg_e1=f1, gate=1e9)
+    r1 = abs(P[0, 1]) / abs(P[0, 0])
+    r2 = abs(P[0, 2]) / abs(P[0, 0])
+    assert abs(r1 - np.exp(-0.5 * k * n * n * e1 / (s * s + e1 * e1))) <= 1e-13
+    assert abs(r2 - np.exp(-0.5 * k * n * n * e2 / (s * s + e2 * e2))) <= 1e-13
+
+
+def test_equal_widths_is_the_isotropic_beam(oracle_lib):
+    """eps1 = eps2 gives the isotropic oracle's field (another code path: the
+    q0/q amplitude and the n^2/q exponent) for any frame."""
+    sc = open_plane_2k(eps="rule")
+    rng = np.random.default_rng(2)
+    idx = rng.choice(len(sc.rcv), 200, replace=False)
+    g = np.array([0.8 * np.exp(1j * np.pi / 8)])
+    P0, _ = oracle.forward(sc.table, g, sc.rcv[idx], sc.freqs, sc.eps, n_threads=4)
+    P1, _ = oracle.forward(sc.table, g, sc.rcv[idx], sc.freqs, sc.eps, eps_e2=sc.eps,
+                           seg_e1=_frame(sc.table, (0.3, -1.0, 0.2)), n_threads=4)
+    scale = np.abs(P0).max()
+    assert np.abs(P1 - P0).max() <= 1e-12 * scale
+
+
+def test_axis_swap_symmetry(oracle_lib):
+    """Exchanging the widths and the frame vectors (e1 -> e2 = t x e1) leaves
+    the field unchanged."""
+    sc = open_plane_2k(eps="rule")
+    rng = np.random.default_rng(9)
+    idx = rng.choice(len(sc.rcv), 150, replace=False)
+    g = np.array([0.9 + 0.1j])
+    e = sc.eps[0]
+    f1 = _frame(sc.table)
+    f2 = np.cross(sc.table.seg_t, f1)
+    Pa, _ = oracle.forward(sc.table, g, sc.rcv[idx], sc.freqs, [0.6 * e], eps_e2=[2.0 * e], seg_e1=f1, n_threads=4)
+    Pb, _ = oracle.forward(sc.table, g, sc.rcv[idx], sc.freqs, [2.0 * e], eps_e2=[0.6 * e], seg_e1=f2, n_threads=4)
+    assert np.abs(Pa - Pb).max() <= 1e-12 * np.abs(Pa).max()
+    Pc, _ = oracle.forward(sc.table, g, sc.rcv[idx], sc.freqs, [2.0 * e], eps_e2=[0.6 * e], seg_e1=f1, n_threads=4)
+    assert np.abs(Pc - Pa).max() > 1e-3 * np.abs(Pa).max()     # the widths do matter
