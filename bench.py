@@ -17,8 +17,9 @@ FP64 oracle on 16,384 seeded receivers, the oracle timed on this host's
 cores on that sample (and single-threaded on a smaller one), and the device
 ray tracer re-tracing the workload's fan (with the per-ray oracle tracer
 timed on a sample of rays), the forward with atmospheric absorption in
-the paper's atmosphere, and broadband synthesis (an impulse response per
-receiver from 1,751 frequency bins) on a receiver subsample.
+the paper's atmosphere, the forward with anisotropic beams (beam parameter
+along e2 twice the one along e1), and broadband synthesis (an impulse
+response per receiver from 1,751 frequency bins) on a receiver subsample.
 """
 from __future__ import annotations
 
@@ -137,6 +138,53 @@ def absorption_bench(sc, dev, table, rcv, freqs, eps, gamma, args, sec_step):
         threads = int(os.environ.get("OMP_NUM_THREADS", str(min(16, os.cpu_count() or 1))))
         P_ref, TL_ref, ab = oracle.scene_forward(sc, rcv=sc.rcv[idx], n_threads=threads, return_absum=True,
                                                  alpha=alpha)
+        Pg = P.cpu().numpy().reshape(-1, len(sc.rcv))[:, idx]
+        TLg = TL.cpu().numpy().reshape(-1, len(sc.rcv))[:, idx]
+        ok = ab / np.maximum(np.abs(P_ref), 1e-300) <= 1e4
+        leg["accuracy_vs_oracle"] = {
+            "tl_err_db_max": float(np.abs(TLg - TL_ref)[ok].max()),
+            "rel_err_max": float((np.abs(Pg - P_ref) / np.maximum(np.abs(P_ref), 1e-300))[ok].max()),
+            "receivers": int(len(idx))}
+    return leg
+
+
+def aniso_bench(sc, dev, table, rcv, freqs, eps, gamma, args, sec_step):
+    """The same forward with anisotropic beams (Q = diag(q1, q2); the beam
+    parameter along e2 twice the one along the horizontal e1): time per
+    step, the pair kernel's time, and the error against the oracle's
+    anisotropic sum on a small seeded receiver sample."""
+    import torch
+
+    import paper_2501_13382_amd as gbs
+    from scenes import normal_frame, receiver_subsample
+    e2 = 2.0 * np.asarray(sc.eps, np.float64).reshape(-1)
+    e2_dev = torch.as_tensor(e2, device=dev)
+    call = lambda tk=False: gbs.forward(table, rcv, freqs, eps, gamma, c=sc.c, gate=sc.gate, mode="mix",
+                                        eps_e2=e2_dev, time_kernels=tk)
+    call()
+    torch.cuda.synchronize()
+    n = max(2, args.steps // 2)
+    t = time.perf_counter()
+    for _ in range(n):
+        P, TL = call()
+    torch.cuda.synchronize()
+    s_an = (time.perf_counter() - t) / n
+    call(True)
+    torch.cuda.synchronize()
+    st = gbs.stats()
+    leg = {"value": sc.dense_pairs / s_an, "ms_per_step": s_an * 1e3, "overhead_vs_value": s_an / sec_step - 1.0,
+           "eps_e2_over_eps": 2.0, "ms_pair_kernel": st["ms_pairs"], "listed_pairs": st["listed_pairs"],
+           "kernel": "k_pairs<MIX|aniso>"}
+    print(f"# anisotropic: {s_an * 1e3:.2f} ms/step, pair kernel {st['ms_pairs']:.2f} ms", file=sys.stderr,
+          flush=True)
+    if not args.no_cpu:
+        import oracle
+        n_cpu = int(min(1024, max(16, 4e9 / (sc.table.n_segs * len(sc.freqs)))))
+        idx = receiver_subsample(len(sc.rcv), n=n_cpu, seed=9)
+        threads = int(os.environ.get("OMP_NUM_THREADS", str(min(16, os.cpu_count() or 1))))
+        P_ref, TL_ref, ab = oracle.forward(sc.table, sc.gamma, sc.rcv[idx], sc.freqs, sc.eps, c=sc.c, gate=sc.gate,
+                                           n_threads=threads, return_absum=True, eps_e2=e2,
+                                           seg_e1=normal_frame(sc.table.seg_t))
         Pg = P.cpu().numpy().reshape(-1, len(sc.rcv))[:, idx]
         TLg = TL.cpu().numpy().reshape(-1, len(sc.rcv))[:, idx]
         ok = ab / np.maximum(np.abs(P_ref), 1e-300) <= 1e4
@@ -277,6 +325,7 @@ def parse():
     ap.add_argument("--no-trace", action="store_true", help="skip the device ray-tracing leg")
     ap.add_argument("--no-absorption", action="store_true", help="skip the atmospheric-absorption leg")
     ap.add_argument("--no-impulse", action="store_true", help="skip the broadband (impulse response) leg")
+    ap.add_argument("--no-aniso", action="store_true", help="skip the anisotropic-beam leg")
     ap.add_argument("--workload", default="open_plane_100k", choices=sorted(WORKLOADS),
                     help="open_plane_100k (default, the headline); city_1m: 10 x 10 city, 1,000,000 rays, "
                          "1024 x 1024 receivers, 1 kHz; city_batched: 16 sources x 4 bands, ragged ray counts, "
@@ -426,6 +475,10 @@ def main():
     if not args.no_absorption:
         absorption_leg = absorption_bench(sc, dev, table, rcv, freqs, eps, gamma, args, sec_step)
 
+    aniso_leg = None
+    if not args.no_aniso:
+        aniso_leg = aniso_bench(sc, dev, table, rcv, freqs, eps, gamma, args, sec_step)
+
     impulse_leg = None
     if not args.no_impulse and sc.table.meta.get("kind") == "open_plane":
         impulse_leg = impulse_bench(sc, dev, table, gamma, args)
@@ -476,6 +529,7 @@ def main():
         "adjoint": adj_leg,
         "trace": trace_leg,
         "absorption": absorption_leg,
+        "anisotropic": aniso_leg,
         "impulse_response": impulse_leg,
     }
 

@@ -16,6 +16,8 @@
  * kept iff lo <= sigma < hi and the Gaussian factor exp(-(k eps/2) n^2/|q|^2)
  * is >= exp(-gate_G).  P(R) = sum over the kept pairs, TL = -20 log10 |P|.
  * With atmospheric absorption (params.alpha) u also carries exp(-alpha s).
+ * With anisotropic beams (params.eps_e2) Q = diag(q1, q2) (Eq. (1) with a
+ * 2x2 Q; Eq. (2) with P = I/c): see gbs_params.eps_e2.
  * w is the launch solid angle of the segment's ray; prod(Gamma) the product of
  * the complex reflection coefficients of the faces the ray hit before the
  * segment.  A dense fan reproduces the unit monopole exp(ikr)/(4 pi r).
@@ -48,7 +50,7 @@
 extern "C" {
 #endif
 
-#define GBS_VERSION 2
+#define GBS_VERSION 3
 
 typedef enum gbs_status {
     GBS_OK = 0,
@@ -117,6 +119,25 @@ typedef struct gbs_params {
                                  for none: each beam's amplitude carries
                                  exp(-alpha s) along its arc length s.  The gate
                                  stays on the Gaussian factor alone.           */
+    const double* eps_e2;     /* [n_src * n_freq] beam parameter along e2 per job
+                                 (m, finite, > 0; device memory), or NULL for
+                                 isotropic beams.  Anisotropic beams (Eq. (1)
+                                 with Q = diag(q1, q2), q_m = s - i eps_m; eps
+                                 of the call is eps_1): in the ray frame
+                                 e1 = z x t / |z x t| (x when t is vertical),
+                                 e2 = t x e1, with n1 = (R - a).e1 and
+                                 n2^2 = n^2 - n1^2,
+                                   u = (i k w / (8 pi^2)) prod(Gamma)
+                                       sqrt(q01/q1) sqrt(q02/q2) exp(i k s
+                                       + (i k / 2)(n1^2/q1 + n2^2/q2))
+                                 (principal roots: continuous along the beam),
+                                 kept iff the Gaussian factor is >= exp(-gate_G).
+                                 e1 stays horizontal under reflection on the
+                                 ground, roofs and walls of the box scenes, so
+                                 it is the transported frame there.  Modes F64
+                                 and MIX only; not with gbs_backward,
+                                 gbs_impulse_response or GBS_FLAG_COUNT_ACTIVE
+                                 (GBS_E_UNSUPPORTED).                          */
 } gbs_params;
 
 /* Plan statistics of the last forward/backward call on a context. */

@@ -43,7 +43,8 @@ class GbsFaces(ctypes.Structure):
 
 class GbsParams(ctypes.Structure):
     _fields_ = [("c", c_double), ("gate_G", c_double), ("mode", c_int32), ("flags", c_int32),
-                ("chunk_segs", c_int64), ("rcv_per_lane", c_int32), ("work_chunk", c_int32), ("alpha", c_void_p)]
+                ("chunk_segs", c_int64), ("rcv_per_lane", c_int32), ("work_chunk", c_int32), ("alpha", c_void_p),
+                ("eps_e2", c_void_p)]
 
 
 class GbsScene(ctypes.Structure):

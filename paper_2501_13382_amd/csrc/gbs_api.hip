@@ -268,6 +268,10 @@ void validate_host(const Args& a) {
     GBS_CHECK(a.faces->n_faces >= 0, "negative face count");
     if (a.n_freq > kMaxBands)
         throw GbsError(GBS_E_UNSUPPORTED, "at most 64 bands per call");
+    if (p.eps_e2 && p.mode == GBS_MODE_F32)
+        throw GbsError(GBS_E_UNSUPPORTED, "anisotropic beams need mode F64 or MIX");
+    if (p.eps_e2 && (p.flags & GBS_FLAG_COUNT_ACTIVE))
+        throw GbsError(GBS_E_UNSUPPORTED, "anisotropic beams do not count active pairs");
     GBS_CHECK(a.n_rcv <= (int64_t)INT32_MAX - 4096, "too many receivers");
     GBS_CHECK(a.segs->n_segs <= (int64_t)INT32_MAX, "too many segments");
     GBS_CHECK(a.rays->n_rays == 0 || a.rays->n_src > 0, "rays without sources");
@@ -291,7 +295,7 @@ struct Planner {
     const Args& a;
     int mode, nr;
     int n_jobs;
-    std::vector<double> h_freqs, h_eps, h_alpha;
+    std::vector<double> h_freqs, h_eps, h_alpha, h_epsb;
     std::vector<int64_t> src_off;     // [n_src + 1] first segment of each source
     std::vector<PassRange> passes;
     std::vector<int64_t> h_ray_ptr, h_face_ptr;  // host copies (only when chunking)
@@ -324,13 +328,21 @@ struct Planner {
                 if (a.params->alpha)
                     GBS_HIP(hipMemcpyAsync(h_alpha.data(), a.params->alpha, sizeof(double) * n_jobs,
                                            hipMemcpyDeviceToHost, st));
+                if (a.params->eps_e2) {
+                    h_epsb.resize(n_jobs);
+                    GBS_HIP(hipMemcpyAsync(h_epsb.data(), a.params->eps_e2, sizeof(double) * n_jobs,
+                                           hipMemcpyDeviceToHost, st));
+                }
             }
             GBS_HIP(hipStreamSynchronize(st));
         }
         for (double f : h_freqs) GBS_CHECK(std::isfinite(f) && f > 0, "frequencies must be finite and > 0");
         for (double e : h_eps) GBS_CHECK(std::isfinite(e) && e > 0, "eps must be finite and > 0");
         for (double al : h_alpha) GBS_CHECK(std::isfinite(al) && al >= 0, "alpha must be finite and >= 0");
+        for (double e : h_epsb) GBS_CHECK(std::isfinite(e) && e > 0, "eps_e2 must be finite and > 0");
     }
+
+    bool aniso() const { return a.params->eps_e2 != nullptr; }
 
     bool absorb() const {
         for (double al : h_alpha)
@@ -474,6 +486,28 @@ struct Planner {
                 j.scale = ke / (8.0 * pi * pi);
                 j.aexp = -h_alpha[s * a.n_freq + b];
                 j.aexp2 = j.aexp * 1.4426950408889634;
+                j.epsb = e;
+                j.epsa2 = e * e;
+                j.epsb2 = e * e;
+                j.gate_a = 2.0 * G / k;
+                j.gexpa = -0.5 * k;
+                j.gexpa2 = -0.5 * k * 1.4426950408889634;
+                j.ampc = 0.5 * e;
+                if (aniso()) {
+                    // envelope of the two widths for the cull and the pre-gate (it keeps
+                    // every pair the exact gate keeps), widened by a relative 1e-12
+                    // against rounding; the pair kernel applies the exact gate
+                    const double eb = h_epsb[s * a.n_freq + b];
+                    const double margin = 1.0 + 1e-12;
+                    j.epsb = eb;
+                    j.epsb2 = eb * eb;
+                    j.ampc = 0.5 * std::sqrt(e * eb);
+                    j.kappa = 2.0 * G / (k * std::min(e, eb)) * margin;
+                    j.eps2 = e * eb * margin;
+                    j.gate_c1 = 1.0 + j.kappa;
+                    j.gate_c2 = j.kappa * j.eps2;
+                    j.scale = k / (8.0 * pi * pi);
+                }
                 j.src = s;
                 j.band = b;
             }
@@ -802,12 +836,23 @@ void dispatch_count(bool count, int nr, gbs_ctx* ctx, hipStream_t st, const Plan
 }
 
 // mode: GBS_MODE_*; absorb: some job has atmospheric absorption (the kernel
-// variant with the absorption exponent; the others skip it).
-void dispatch_pairs(int mode, bool absorb, bool count, int nr, gbs_ctx* ctx, hipStream_t st,
+// variant with the absorption exponent; the others skip it); aniso:
+// anisotropic beams (F64 and MIX, no counting).
+void dispatch_pairs(int mode, bool absorb, bool aniso, bool count, int nr, gbs_ctx* ctx, hipStream_t st,
                     const Planner::Lists& L, const RcvPlan& R, int64_t n_rcv, double* P, unsigned* ctr,
                     unsigned long long* na) {
     GBS_CHECK(L.partial != nullptr, "work-unit partials not allocated");
     const int m = (mode == GBS_MODE_F64 ? 0 : mode == GBS_MODE_MIX ? 1 : 2) | (absorb ? 4 : 0);
+    if (aniso) {
+        GBS_CHECK(!count && (m & 3) != 2, "anisotropic beams: F64 or MIX, no counting");
+        switch (m) {
+            case 0: dispatch_nr<8, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
+            case 1: dispatch_nr<9, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
+            case 4: dispatch_nr<12, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
+            default: dispatch_nr<13, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
+        }
+        return;
+    }
     switch (m) {
         case 0: dispatch_count<0>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
         case 1: dispatch_count<1>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
@@ -888,7 +933,7 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
             if (L.n_items > 0 && L.total > 0) {
                 L.partial = ws.get<double>("partial", L.work_cap * nr * 64 * 2);
                 ev_pairs.begin(st);
-                dispatch_pairs(a.params->mode, pl.absorb(), count, nr, ctx, st, L, pl.R, a.n_rcv, P, ctr, na);
+                dispatch_pairs(a.params->mode, pl.absorb(), pl.aniso(), count, nr, ctx, st, L, pl.R, a.n_rcv, P, ctr, na);
                 stats.ms_pairs += ev_pairs.end(st);
             }
             if (overlap) GBS_HIP(hipEventRecord(ctx->released[pi % 2], st));
@@ -1215,6 +1260,7 @@ int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
         Args a{rays, segs, faces, rcv, n_rcv, freqs, n_freq, eps, params};
         validate_host(a);
         GBS_CHECK(params->mode != GBS_MODE_F32, "the adjoint supports F64 and MIX");
+        if (params->eps_e2) throw GbsError(GBS_E_UNSUPPORTED, "the adjoint supports isotropic beams only");
         Workspace& ws = *ctx->ws;
         Planner pl(ctx, ws, a, 1);
         hipStream_t st = ctx->stream;
@@ -1354,7 +1400,7 @@ int gbs_graph_create(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, c
                     L.rec = rs;
                 }
                 L.partial = partial;
-                dispatch_pairs(params->mode, pl.absorb(), false, nr, ctx, st, L, pl.R, n_rcv, P, ctr, nullptr);
+                dispatch_pairs(params->mode, pl.absorb(), pl.aniso(), false, nr, ctx, st, L, pl.R, n_rcv, P, ctr, nullptr);
             }
             if (TL && n_out > 0)
                 hipLaunchKernelGGL(k_tl, dim3(blocks_for(n_out, 256)), dim3(256), 0, st, P, n_out, TL);
@@ -1398,6 +1444,8 @@ int gbs_impulse_response(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* seg
     return guarded(ctx, [&]() {
         GBS_HIP(hipSetDevice(ctx->device));
         GBS_CHECK(rays && segs && faces && params, "null struct argument");
+        if (params->eps_e2)
+            throw GbsError(GBS_E_UNSUPPORTED, "impulse responses support isotropic beams only");
         GBS_CHECK(std::isfinite(df) && df > 0, "df must be finite and > 0");
         GBS_CHECK(n_fft >= 64 && n_fft <= kIrMaxFft && (n_fft & (n_fft - 1)) == 0,
                   "n_fft must be a power of two in [64, 4096]");

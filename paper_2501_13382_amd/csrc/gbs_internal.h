@@ -27,9 +27,20 @@ struct JobConst {
     double hfk;          // f / (2c)
     double gexp2;        // -(k eps / 2) log2(e): Gaussian exponent in base 2 per n^2/den
     double gexp;         // -(k eps / 2)
-    double scale;        // k eps / (8 pi^2): weight factored out of the per-job sum
+    double scale;        // k eps / (8 pi^2) (anisotropic: k / (8 pi^2)): weight factored out of the sum
     double aexp;         // -alpha: atmospheric absorption exponent per metre of arc length
     double aexp2;        // -alpha log2(e)
+    // Anisotropic beams (beam parameter eps along the frame vector e1, epsb
+    // along e2).  The cull and the pre-gate then use the envelope of the two
+    // widths: kappa = 2G/(k min(eps, epsb)), eps2 = eps epsb (so that
+    // kappa eps2 = 2G max(eps, epsb)/k), gate_c1 = 1 + kappa, gate_c2 = kappa eps2.
+    double epsb;         // beam parameter along e2
+    double epsa2;        // eps^2
+    double epsb2;        // epsb^2
+    double gate_a;       // exact gate: eps a1 + epsb a2 <= 2G/k
+    double gexpa;        // -(k/2): Gaussian exponent per (eps a1 + epsb a2)
+    double gexpa2;       // -(k/2) log2(e)
+    double ampc;         // sqrt(eps epsb) / 2
     int32_t src;
     int32_t band;
 };

@@ -17,6 +17,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace gbs {
 
 // ------------------------------------------------------------------ helpers
@@ -666,8 +668,10 @@ struct Beam;
 
 constexpr int kF64 = 0, kMIX = 1, kF32 = 2;
 // Pair-kernel variants: the precision mode, plus kAbsorb when any job has
-// atmospheric absorption (without it the term skips the absorption exponent).
+// atmospheric absorption (without it the term skips the absorption exponent),
+// plus kAniso for anisotropic beams (F64 and MIX only).
 constexpr int kAbsorb = 4;
+constexpr int kAniso = 8;
 
 __device__ __forceinline__ float4 tile_weights(const TileRec& S) {
     return *reinterpret_cast<const float4*>(&S.wgr);
@@ -770,11 +774,144 @@ struct Beam<kF32> {
     }
 };
 
+// Anisotropic beams: Eq. (1) with Q = diag(q1, q2), q_m = s - i eps_m, and
+// P = I/c (Eq. (2) in a homogeneous medium), in the ray frame
+//   e1 = z x t / |z x t| (the x axis when t is vertical),  e2 = t x e1.
+// A reflection on the ground, a roof or a wall maps e1 to plus or minus the e1
+// of the reflected axis, so this frame is the transported one in scenes of
+// axis-aligned faces; only n1^2 and n2^2 enter.  With
+//   n1 = (R - o).e1,  n2^2 = n^2 - n1^2,  den_m = s^2 + eps_m^2,  a_m = n_m^2/den_m:
+//   Gaussian exp(-(k/2)(eps a1 + epsb a2)), kept iff eps a1 + epsb a2 <= 2G/k,
+//   phase (f/c) s (1 + (a1 + a2)/2) cycles,
+//   i sqrt(q01/q1) sqrt(q02/q2) = sqrt(eps epsb / (den1 den2)) / (2 sqrt(b1 b2))
+//                                 * (s (b1 + b2) + i (b1 b2 - s^2)),  b_m = sqrt(den_m) + eps_m
+// (the product of the principal roots sqrt(eps_m - i s) = (r_m, -s/(2 r_m)),
+// r_m^2 = b_m/2: every eps_m - i s has a positive real part, so the principal
+// branch is the continuous one along the beam).  The job weight is k/(8 pi^2).
+// gate() is the isotropic pre-gate on the envelope of the two widths (it keeps
+// every pair the exact gate keeps); term() applies the exact gate.
+struct TileRecA {
+    TileRec b;           // isotropic record; b.pad holds -o.e1
+    double e1x, e1y;     // frame vector e1 (its z component is zero)
+};
+static_assert(sizeof(TileRecA) == 128, "TileRecA layout");
+
+// 1/d from the FP32 reciprocal and one Newton step in FP64.
+__device__ __forceinline__ double rcp_newton(double d) {
+    const double r0 = (double)__builtin_amdgcn_rcpf((float)d);
+    return fma(r0, fma(-d, r0, 1.0), r0);
+}
+
+struct GeoA {
+    double s, l;         // as Beam<kF64>::Geo
+    double x, y;         // receiver x, y (for n1)
+};
+
+template <int MODE>
+struct BeamA;
+
+template <>
+struct BeamA<kMIX> {
+    using T = float;
+    using Geo = GeoA;
+    __device__ __forceinline__ static bool gate(const TileRecA& S, const JobConst& J, double X, double Y, double Z,
+                                                double R2, Geo& g) {
+        Beam<kF64>::Geo h;
+        const bool k = Beam<kF64>::gate(S.b, J, X, Y, Z, R2, h);
+        g.s = h.s;
+        g.l = h.l;
+        g.x = X;
+        g.y = Y;
+        return k;
+    }
+    template <bool ABS>
+    __device__ __forceinline__ static void term(const TileRecA& S, const JobConst& J, const Geo& g, bool live,
+                                                float& ur, float& ui) {
+        const double s = g.s;
+        const double nn = fma(-s, s, g.l + S.b.oo);                      // n1^2 + n2^2
+        const double n1 = fma(g.x, S.e1x, fma(g.y, S.e1y, S.b.pad));     // offset along e1
+        const double q1 = n1 * n1;
+        const double q2 = nn - q1;                                       // offset^2 along e2
+        const double den1 = fma(s, s, J.epsa2), den2 = fma(s, s, J.epsb2);
+        const double a1 = q1 * rcp_newton(den1), a2 = q2 * rcp_newton(den2);
+        const double e = fma(J.eps, a1, J.epsb * a2);
+        const bool in = live && e <= J.gate_a;
+        const double cyc = s * fma(J.hfk, a1 + a2, J.fk);                // phase in cycles, FP64
+        const float ph = (float)__builtin_amdgcn_fract(cyc);
+        const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
+        const float sf = (float)s;
+        const float gg = (float)(e * J.gexpa2);
+        const float w = __builtin_amdgcn_exp2f(in ? (ABS ? fmaf(sf, (float)J.aexp2, gg) : gg) : -INFINITY);
+        const float d1f = (float)den1, d2f = (float)den2;
+        const float d1 = __builtin_amdgcn_sqrtf(d1f), d2 = __builtin_amdgcn_sqrtf(d2f);
+        const float e1 = (float)J.eps, e2 = (float)J.epsb;
+        const float b1 = d1 + e1, b2 = d2 + e2;
+        const float ss = sf * sf;
+        // b1 b2 - s^2 = (s^2 (eps^2 + epsb^2) + eps^2 epsb^2) / (d1 d2 + s^2) + eps d2 + epsb d1 + eps epsb
+        // (no cancellation when s >> eps)
+        const float x = fmaf(ss, (float)(J.epsa2 + J.epsb2), (float)(J.epsa2 * J.epsb2)) *
+                        __builtin_amdgcn_rcpf(fmaf(d1, d2, ss));
+        const float im = x + fmaf(e1, d2, fmaf(e2, d1, e1 * e2));
+        const float re = sf * (b1 + b2);
+        const float pre = (float)J.ampc * __builtin_amdgcn_rsqf(d1f * d2f * (b1 * b2)) * w;
+        const float4 W = tile_weights(S.b);
+        const float cr = (re * W.x - im * W.y) * pre;
+        const float ci = (re * W.y + im * W.x) * pre;
+        ur = cr * cs - ci * sn;
+        ui = cr * sn + ci * cs;
+    }
+};
+
+template <>
+struct BeamA<kF64> {
+    using T = double;
+    using Geo = GeoA;
+    __device__ __forceinline__ static bool gate(const TileRecA& S, const JobConst& J, double X, double Y, double Z,
+                                                double R2, Geo& g) {
+        return BeamA<kMIX>::gate(S, J, X, Y, Z, R2, g);
+    }
+    template <bool ABS>
+    __device__ __forceinline__ static void term(const TileRecA& S, const JobConst& J, const Geo& g, bool live,
+                                                double& ur, double& ui) {
+        const double s = g.s;
+        const double nn = fma(-s, s, g.l + S.b.oo);
+        const double n1 = fma(g.x, S.e1x, fma(g.y, S.e1y, S.b.pad));
+        const double q1 = n1 * n1;
+        const double q2 = nn - q1;
+        const double den1 = fma(s, s, J.epsa2), den2 = fma(s, s, J.epsb2);
+        const double a1 = q1 / den1, a2 = q2 / den2;
+        const double e = fma(J.eps, a1, J.epsb * a2);
+        const bool in = live && e <= J.gate_a;
+        const double cyc = s * fma(J.hfk, a1 + a2, J.fk);
+        const double ph = cyc - floor(cyc);
+        double sn, cs;
+        sincospi(2.0 * ph, &sn, &cs);
+        const double ge = ABS ? fma(s, J.aexp, e * J.gexpa) : e * J.gexpa;
+        const double w = in ? exp(ge) : 0.0;
+        const double d1 = sqrt(den1), d2 = sqrt(den2);
+        const double b1 = d1 + J.eps, b2 = d2 + J.epsb;
+        const double bb = b1 * b2;
+        const double re = s * (b1 + b2);
+        const double im = fma(-s, s, bb);
+        const double pre = J.ampc / sqrt(den1 * den2 * bb) * w;
+        const double cr = (re * S.b.wgr - im * S.b.wgi) * pre;
+        const double ci = (re * S.b.wgi + im * S.b.wgr) * pre;
+        ur = cr * cs - ci * sn;
+        ui = cr * sn + ci * cs;
+    }
+};
+
+// The beam model and LDS tile record of a pair-kernel variant.
+template <int MODE>
+using BeamOf = typename std::conditional<(MODE & kAniso) != 0, BeamA<MODE & 3>, Beam<MODE & 3>>::type;
+template <int MODE>
+using TileOf = typename std::conditional<(MODE & kAniso) != 0, TileRecA, TileRec>::type;
+
 // One segment for one receiver: wave-uniform skip when no lane passes.
 template <int MODE>
-__device__ __forceinline__ int pair_one(const TileRec& S, const JobConst& J, double X, double Y, double Z, double R2,
-                                        double& ar, double& ai) {
-    using B = Beam<MODE & 3>;
+__device__ __forceinline__ int pair_one(const TileOf<MODE>& S, const JobConst& J, double X, double Y, double Z,
+                                        double R2, double& ar, double& ai) {
+    using B = BeamOf<MODE>;
     constexpr bool ABS = (MODE & kAbsorb) != 0;
     typename B::Geo g;
     const bool k0 = B::gate(S, J, X, Y, Z, R2, g);
@@ -791,9 +928,9 @@ __device__ __forceinline__ int pair_one(const TileRec& S, const JobConst& J, dou
 // dependency chains that the compiler interleaves; one wave-uniform branch
 // skips both when no lane passes either gate.
 template <int MODE>
-__device__ __forceinline__ int pair_two(const TileRec& S0, const TileRec& S1, const JobConst& J, double X, double Y,
-                                        double Z, double R2, double& ar, double& ai) {
-    using B = Beam<MODE & 3>;
+__device__ __forceinline__ int pair_two(const TileOf<MODE>& S0, const TileOf<MODE>& S1, const JobConst& J, double X,
+                                        double Y, double Z, double R2, double& ar, double& ai) {
+    using B = BeamOf<MODE>;
     constexpr bool ABS = (MODE & kAbsorb) != 0;
     using T = typename B::T;
     typename B::Geo g0, g1;
@@ -844,6 +981,24 @@ __device__ __forceinline__ void stage_rec(TileRec* dst, double2 r0, double2 r1, 
             make_float4((float)r5.x, (float)r5.y, (float)(J.eps * r5.x), (float)(J.eps * r5.y));
     }
 }
+// The anisotropic tile record: the isotropic one plus the frame vector e1 of
+// the segment's axis and -o.e1 (in the isotropic record's spare slot).
+template <int MODE>
+__device__ __forceinline__ void stage_rec(TileRecA* dst, double2 r0, double2 r1, double2 r2, double2 r3, double2 r4,
+                                          double2 r5, const JobConst& J) {
+    stage_rec<MODE>(&dst->b, r0, r1, r2, r3, r4, r5, J);
+    const double tx = r2.x, ty = r2.y;
+    const double h2 = fma(tx, tx, ty * ty);
+    double ex = 1.0, ey = 0.0;
+    if (h2 > 0.0) {
+        const double rh = 1.0 / sqrt(h2);
+        ex = -ty * rh;
+        ey = tx * rh;
+    }
+    dst->e1x = ex;
+    dst->e1y = ey;
+    dst->b.pad = 0.5 * fma(r0.x, ex, r0.y * ey);   // -o.e1 from -2 o
+}
 #define GBS_STAGE(MODE, dst, n, J) stage_rec<MODE>((dst), n##0, n##1, n##2, n##3, n##4, n##5, (J))
 
 // Pops the next work item (wave-uniform) from the global counter.  Lane 0
@@ -879,9 +1034,10 @@ __global__ __launch_bounds__(kPairThreads, GBS_PAIR_MIN_WAVES) void k_pairs(cons
                                               const double* __restrict__ rx, const double* __restrict__ ry,
                                               const double* __restrict__ rz, const double* __restrict__ r2,
                                               double* __restrict__ partial, unsigned long long* __restrict__ n_active) {
-    __shared__ __align__(16) TileRec tile[kPairThreads / kWave][kWave];
+    using Tile = TileOf<MODE>;
+    __shared__ __align__(16) Tile tile[kPairThreads / kWave][kWave];
     const int lane = threadIdx.x & (kWave - 1);
-    TileRec* const my = tile[threadIdx.x / kWave];
+    Tile* const my = tile[threadIdx.x / kWave];
     const int n_work = __builtin_amdgcn_readfirstlane(*n_work_p);
     unsigned long long active = 0;
     for (;;) {
@@ -919,7 +1075,7 @@ __global__ __launch_bounds__(kPairThreads, GBS_PAIR_MIN_WAVES) void k_pairs(cons
             int k = 0;
 #ifndef GBS_PAIR_SINGLE
             for (; k + 2 <= cnt; k += 2) {
-                const TileRec S0 = my[k], S1 = my[k + 1];
+                const Tile S0 = my[k], S1 = my[k + 1];
 #pragma unroll
                 for (int m = 0; m < NR; ++m) {
                     const int hit = pair_two<MODE>(S0, S1, J, X[m], Y[m], Z[m], R2[m], ar[m], ai[m]);
@@ -928,7 +1084,7 @@ __global__ __launch_bounds__(kPairThreads, GBS_PAIR_MIN_WAVES) void k_pairs(cons
             }
 #endif
             for (; k < cnt; ++k) {
-                const TileRec S = my[k];
+                const Tile S = my[k];
 #pragma unroll
                 for (int m = 0; m < NR; ++m) {
                     const int hit = pair_one<MODE>(S, J, X[m], Y[m], Z[m], R2[m], ar[m], ai[m]);
@@ -1375,6 +1531,11 @@ GBS_INST_PAIRS_MODE(2)
 GBS_INST_PAIRS_MODE(4)
 GBS_INST_PAIRS_MODE(5)
 GBS_INST_PAIRS_MODE(6)
+#define GBS_INST_PAIRS_ANISO(M) GBS_INST_PAIRS(M, 1, false) GBS_INST_PAIRS(M, 2, false) GBS_INST_PAIRS(M, 4, false)
+GBS_INST_PAIRS_ANISO(8)
+GBS_INST_PAIRS_ANISO(9)
+GBS_INST_PAIRS_ANISO(12)
+GBS_INST_PAIRS_ANISO(13)
 #define GBS_INST_ADJ(M)                                                                                          \
     template __global__ void k_adjoint<M>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,       \
                                           const int32_t*, const SegRec*, const double*, const double*,            \

@@ -134,21 +134,21 @@ def _gamma_ri(gamma, device):
 _TUNED = {}
 
 
-def _params(c, gate, mode, flags, chunk_segs, rcv_per_lane, work_chunk, device, alpha=None):
+def _params(c, gate, mode, flags, chunk_segs, rcv_per_lane, work_chunk, device, alpha=None, eps_e2=None):
     if mode not in _lib.MODES:
         raise ValueError(f"mode must be one of {sorted(_lib.MODES)}")
     tuned = _TUNED.get((_device_index(device), mode), {})
     nr = int(rcv_per_lane) or int(tuned.get("rcv_per_lane", 0))
     wc = int(work_chunk) or int(tuned.get("work_chunk", 0))
     return _lib.GbsParams(float(c), float(gate), _lib.MODES[mode], int(flags), int(chunk_segs), nr, wc,
-                          _ptr(alpha) if alpha is not None else None)
+                          _ptr(alpha) if alpha is not None else None, _ptr(eps_e2) if eps_e2 is not None else None)
 
 
 class _Call:
     """Marshalled arguments of one forward/backward call."""
 
     def __init__(self, table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, validate,
-                 count_active, time_kernels=False, work_chunk=0, alpha=None):
+                 count_active, time_kernels=False, work_chunk=0, alpha=None, eps_e2=None):
         if not isinstance(table, Table):
             raise TypeError("table must be a gbs.Table")
         dev = table.device
@@ -168,7 +168,13 @@ class _Call:
             self.alpha = _as_tensor(alpha, torch.float64, dev).reshape(-1)
             if self.alpha.numel() != self.eps.numel():
                 raise ValueError("alpha must hold one value per (source, band)")
-        self.params = _params(c, gate, mode, flags, chunk_segs, rcv_per_lane, work_chunk, dev, self.alpha)
+        self.eps_e2 = None
+        if eps_e2 is not None:
+            self.eps_e2 = _as_tensor(eps_e2, torch.float64, dev).reshape(-1)
+            if self.eps_e2.numel() != self.eps.numel():
+                raise ValueError("eps_e2 must hold one value per (source, band)")
+        self.params = _params(c, gate, mode, flags, chunk_segs, rcv_per_lane, work_chunk, dev, self.alpha,
+                              self.eps_e2)
         self.rays, self.segs = table.structs()
         self.faces = _lib.GbsFaces(table.n_faces, _ptr(self.gamma))
         self.n_rcv = int(self.rcv.shape[0])
@@ -182,15 +188,18 @@ class _Call:
 
 def forward(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix", chunk_segs=0,
             rcv_per_lane=0, work_chunk=0, validate=False, count_active=False, time_kernels=False, want_tl=True,
-            alpha=None):
+            alpha=None, eps_e2=None):
     """Beam summation.  Returns (P complex128 [n_src, n_freq, n_rcv],
     TL float64 of the same shape or None).  count_active / time_kernels fill
     the statistics returned by stats().  alpha: atmospheric absorption per
-    (source, band) in Np/m (see air_absorption), or None."""
+    (source, band) in Np/m (see air_absorption), or None.  eps_e2: beam
+    parameter along e2 per (source, band) for anisotropic beams (eps is then
+    the one along the horizontal frame vector e1; modes "f64" and "mix"), or
+    None."""
     ctx = context(table.device)
     ctx.bind_stream()
     call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, validate, count_active,
-                 time_kernels, work_chunk, alpha)
+                 time_kernels, work_chunk, alpha, eps_e2)
     P = torch.empty(call.shape + (2,), dtype=torch.float64, device=table.device)
     TL = torch.empty(call.shape, dtype=torch.float64, device=table.device) if want_tl else None
     rc = ctx.lib.gbs_forward(*call.common(ctx), _ptr(P), _ptr(TL))
@@ -283,7 +292,8 @@ def _tune_key(table: Table, call, mode: str) -> str:
     return f"{arch}|{mode}|2^{int(math.log2(dense))}|bands{call.n_freq}|src{table.n_src}"
 
 
-def autotune(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix", cache=None, alpha=None):
+def autotune(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix", cache=None, alpha=None,
+             eps_e2=None):
     """Times the pair-kernel shapes (receivers per lane x work-unit size) on
     this problem; later calls in `mode` that leave rcv_per_lane / work_chunk
     at 0 use the fastest.  With `cache` (a JSON file path) a stored choice for
@@ -291,7 +301,7 @@ def autotune(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="
     a new one is stored.  Returns {"rcv_per_lane": .., "work_chunk": ..}."""
     ctx = context(table.device)
     ctx.bind_stream()
-    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, 0, 0, False, False, alpha=alpha)
+    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, 0, 0, False, False, alpha=alpha, eps_e2=eps_e2)
     key = _tune_key(table, call, mode)
     store = {}
     if cache is not None and os.path.exists(cache):
@@ -361,11 +371,11 @@ class Graph:
     coefficient tensor may be updated in place between replays."""
 
     def __init__(self, table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix", rcv_per_lane=0,
-                 chunk_segs=0, alpha=None):
+                 chunk_segs=0, alpha=None, eps_e2=None):
         self.ctx = context(table.device)
         self.stream = torch.cuda.Stream(device=table.device)
         self.call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, False, False,
-                          alpha=alpha)
+                          alpha=alpha, eps_e2=eps_e2)
         self.gamma = self.call.gamma          # [n_faces, 2] device buffer read at every replay
         self.P = torch.empty(self.call.shape + (2,), dtype=torch.float64, device=table.device)
         self.TL = torch.empty(self.call.shape, dtype=torch.float64, device=table.device)

@@ -2,6 +2,7 @@
 function include/gbs.h declares; struct layouts match the header."""
 import ctypes
 import os
+import subprocess
 import re
 
 import pytest
@@ -28,17 +29,42 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(_lib.LIB_PATH)
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert _lib.load().gbs_version() == 2
+    assert _lib.load().gbs_version() == 3
 
 
 def test_struct_sizes_match_c_layout():
     assert ctypes.sizeof(_lib.GbsRays) == 40
     assert ctypes.sizeof(_lib.GbsSegs) == 64
     assert ctypes.sizeof(_lib.GbsFaces) == 16
-    assert ctypes.sizeof(_lib.GbsParams) == 48
+    assert ctypes.sizeof(_lib.GbsParams) == 56
     assert ctypes.sizeof(_lib.GbsStats) == 64
     assert ctypes.sizeof(_lib.GbsScene) == 32
     assert ctypes.sizeof(_lib.GbsFan) == 48
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every field offset of the ctypes mirrors equals the C compiler's
+    offsetof for include/gbs.h (host compiler, no device code)."""
+    structs = {"gbs_rays": _lib.GbsRays, "gbs_segs": _lib.GbsSegs, "gbs_faces": _lib.GbsFaces,
+               "gbs_params": _lib.GbsParams, "gbs_stats": _lib.GbsStats, "gbs_scene": _lib.GbsScene,
+               "gbs_fan": _lib.GbsFan}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "gbs.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'    printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'    printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_create_without_gpu_fails_cleanly():

@@ -141,3 +141,28 @@ def test_axis_swap_symmetry(oracle_lib):
     assert np.abs(Pa - Pb).max() <= 1e-12 * np.abs(Pa).max()
     Pc, _ = oracle.forward(sc.table, g, sc.rcv[idx], sc.freqs, [2.0 * e], eps_e2=[0.6 * e], seg_e1=f1, n_threads=4)
     assert np.abs(Pc - Pa).max() > 1e-3 * np.abs(Pa).max()     # the widths do matter
+
+
+def test_horizontal_frame_is_transported_by_reflections():
+    """In a traced city (ground, roofs, walls: every face axis-aligned) the
+    frame carried along each ray by the reflections (the mirror flips the
+    component of e1 along the face normal, as it flips the axis) equals,
+    up to sign, the horizontal normal of each reflected axis: the frame the
+    library forms from the axis alone is the transported one."""
+    from scenes import city_scene
+    sc = city_scene(n_blocks=3, n_rays=3000, grid=4, freqs=(500.0,), max_refl=8, city_seed=5)
+    tab = sc.table
+    checked = 0
+    for i in range(tab.n_rays):
+        b, e = tab.ray_ptr[i], tab.ray_ptr[i + 1]
+        f = normal_frame(tab.seg_t[b:b + 1])[0]
+        for j in range(b + 1, e):
+            t0, t1 = tab.seg_t[j - 1], tab.seg_t[j]
+            flipped = np.nonzero(np.sign(t0) != np.sign(t1))[0]
+            assert len(flipped) == 1 and np.allclose(np.abs(t0), np.abs(t1), rtol=0, atol=0)
+            f = f.copy()
+            f[flipped[0]] = -f[flipped[0]]
+            g = normal_frame(t1[None, :])[0]
+            assert abs(abs(float(f @ g)) - 1.0) <= 1e-12
+            checked += 1
+    assert checked > 2000
