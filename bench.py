@@ -59,9 +59,9 @@ PEAK_F32 = 157.3e12
 # FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy and fill (the summary in
 # profiles/k_pairs_mix_open_plane_100k.md).  Valid only for the kernel source
 # it was measured on; reported as null once that source changes.
-PAIR_TRAFFIC_BYTES = 3.262e9
-PAIR_TRAFFIC_SOURCE_MD5 = {"gbs_kernels.hip": "ef22558239091d865b4432717cd3842b",
-                           "gbs_internal.h": "de7ded7b56bf541eea501fc8b641a30b"}
+PAIR_TRAFFIC_BYTES = 3.266e9
+PAIR_TRAFFIC_SOURCE_MD5 = {"gbs_kernels.hip": "8a599498f3785ccbccb6f7c2b2677f36",
+                           "gbs_internal.h": "8f063ad29778f953d75dedfaaf919c38"}
 
 
 def pair_traffic():
