@@ -150,3 +150,28 @@ def test_unsupported_requests_fail(plane):
     P, _ = gbs.forward(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, eps_e2=e2)
     torch.cuda.synchronize()
     assert torch.isfinite(torch.view_as_real(P)).all()
+
+
+def test_adjoint_and_impulse_response_reject_anisotropic_beams(plane):
+    """Through the C ABI: gbs_backward and gbs_impulse_response return
+    GBS_E_UNSUPPORTED when params.eps_e2 is set, and write nothing."""
+    import ctypes
+    from paper_2501_13382_amd import _lib
+    from paper_2501_13382_amd.gbs import _Call, _ptr, context
+    sc, e2, _ = plane
+    t = gbs.Table(sc.table, device="cuda")
+    ctx = context(t.device)
+    ctx.bind_stream()
+    call = _Call(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, sc.c, sc.gate, "mix", 0, 0, False, False, eps_e2=e2)
+    lam = torch.ones(call.shape + (2,), dtype=torch.float64, device="cuda")
+    d_gamma = torch.full((t.n_faces, 2), 7.0, dtype=torch.float64, device="cuda")
+    rc = ctx.lib.gbs_backward(*call.common(ctx), _ptr(lam), _ptr(d_gamma), None, None)
+    assert rc == _lib.GBS_E_UNSUPPORTED
+    assert b"isotropic" in ctx.lib.gbs_last_error(ctx.handle)
+    h = torch.full((t.n_src, call.n_rcv, 64), 7.0, dtype=torch.float64, device="cuda")
+    rc = ctx.lib.gbs_impulse_response(ctx.handle, ctypes.byref(call.rays), ctypes.byref(call.segs),
+                                      ctypes.byref(call.faces), _ptr(call.rcv), call.n_rcv, 2.0, 1, 1,
+                                      _ptr(call.eps), None, ctypes.byref(call.params), 64, 64, _ptr(h))
+    assert rc == _lib.GBS_E_UNSUPPORTED
+    torch.cuda.synchronize()
+    assert bool((d_gamma == 7.0).all()) and bool((h == 7.0).all())
