@@ -50,6 +50,16 @@ FLOP_KEPT_F64 = 17
 FLOP_KEPT_F32 = 18
 ADJ_FLOP_KEPT_F64 = 29
 ADJ_FLOP_KEPT_F32 = 69
+# The anisotropic variant (same 12 FP64 per listed pair):
+#   every kept pair: n1^2 + n2^2 (add, FMA), n1 (2 FMA), n1^2, n2^2, two
+#     denominators (2 FMA), two Newton reciprocals (4 FMA), a1, a2, the gate
+#     sum (mul, FMA), cycles (add, FMA, mul), fract, Gaussian exponent,
+#     accumulation (2 adds)                                                -> 34 FP64
+#     2 rcp, sin, cos, exp2, 2 sqrt, b1, b2, s^2, b1 b2 - s^2 (2 FMA, rcp,
+#     mul; eps1 eps2, 2 FMA, add), s (b1 + b2) (add, mul), prefactor (5 mul,
+#     rsq), weights (2 x (mul, FMA, mul)), rotation (2 x (mul, FMA)), pair sum -> 45 FP32
+ANI_FLOP_KEPT_F64 = 34
+ANI_FLOP_KEPT_F32 = 45
 # Vector peaks from unit counts and clock: 256 CUs x 2.4 GHz x 64 FMA lanes x 2
 # = 78.6 TFLOP/s FP64; FP32 157.3 TFLOP/s (vendor figure).
 PEAK_F64 = 256 * 2.4e9 * 64 * 2
@@ -59,8 +69,8 @@ PEAK_F32 = 157.3e12
 # FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy and fill (the summary in
 # profiles/k_pairs_mix_open_plane_100k.md).  Valid only for the kernel source
 # it was measured on; reported as null once that source changes.
-PAIR_TRAFFIC_BYTES = 3.266e9
-PAIR_TRAFFIC_SOURCE_MD5 = {"gbs_kernels.hip": "8a599498f3785ccbccb6f7c2b2677f36",
+PAIR_TRAFFIC_BYTES = 3.267e9
+PAIR_TRAFFIC_SOURCE_MD5 = {"gbs_kernels.hip": "2b8736999054d69c7f321f894d45b3ec",
                            "gbs_internal.h": "8f063ad29778f953d75dedfaaf919c38"}
 
 
@@ -169,13 +179,28 @@ def aniso_bench(sc, dev, table, rcv, freqs, eps, gamma, args, sec_step):
         P, TL = call()
     torch.cuda.synchronize()
     s_an = (time.perf_counter() - t) / n
-    call(True)
+    ms_pairs = []
+    for _ in range(3):
+        call(True)
+        torch.cuda.synchronize()
+        ms_pairs.append(gbs.stats()["ms_pairs"])
+    ms_pairs = float(np.mean(ms_pairs))
+    gbs.forward(table, rcv, freqs, eps, gamma, c=sc.c, gate=sc.gate, mode="mix", eps_e2=e2_dev, count_active=True)
     torch.cuda.synchronize()
     st = gbs.stats()
+    listed, active = st["listed_pairs"], st["active_pairs"]
+    f64 = FLOP_LISTED_F64 * listed + ANI_FLOP_KEPT_F64 * active
+    f32 = ANI_FLOP_KEPT_F32 * active
+    achieved = (f64 + f32) / (ms_pairs * 1e-3)
+    peak = (f64 + f32) / (f64 / PEAK_F64 + f32 / PEAK_F32)
     leg = {"value": sc.dense_pairs / s_an, "ms_per_step": s_an * 1e3, "overhead_vs_value": s_an / sec_step - 1.0,
-           "eps_e2_over_eps": 2.0, "ms_pair_kernel": st["ms_pairs"], "listed_pairs": st["listed_pairs"],
-           "kernel": "k_pairs<MIX|aniso>"}
-    print(f"# anisotropic: {s_an * 1e3:.2f} ms/step, pair kernel {st['ms_pairs']:.2f} ms", file=sys.stderr,
+           "eps_e2_over_eps": 2.0,
+           "roofline": {"bound": "alu", "kernel": "k_pairs<MIX|aniso>", "achieved": achieved / 1e12,
+                        "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak, "ms_per_launch": ms_pairs,
+                        "listed_pairs": listed, "kept_pairs": active,
+                        "flop_per_listed_pair": {"f64": FLOP_LISTED_F64},
+                        "flop_per_kept_pair": {"f64": ANI_FLOP_KEPT_F64, "f32": ANI_FLOP_KEPT_F32}}}
+    print(f"# anisotropic: {s_an * 1e3:.2f} ms/step, pair kernel {ms_pairs:.2f} ms", file=sys.stderr,
           flush=True)
     if not args.no_cpu:
         import oracle

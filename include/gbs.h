@@ -135,9 +135,8 @@ typedef struct gbs_params {
                                  e1 stays horizontal under reflection on the
                                  ground, roofs and walls of the box scenes, so
                                  it is the transported frame there.  Modes F64
-                                 and MIX only; not with gbs_backward,
-                                 gbs_impulse_response or GBS_FLAG_COUNT_ACTIVE
-                                 (GBS_E_UNSUPPORTED).                          */
+                                 and MIX only; not with gbs_backward or
+                                 gbs_impulse_response (GBS_E_UNSUPPORTED).     */
 } gbs_params;
 
 /* Plan statistics of the last forward/backward call on a context. */

@@ -789,7 +789,8 @@ struct Beam<kF32> {
 // r_m^2 = b_m/2: every eps_m - i s has a positive real part, so the principal
 // branch is the continuous one along the beam).  The job weight is k/(8 pi^2).
 // gate() is the isotropic pre-gate on the envelope of the two widths (it keeps
-// every pair the exact gate keeps); term() applies the exact gate.
+// every pair the exact gate keeps); term() applies the exact gate and returns
+// its decision.
 struct TileRecA {
     TileRec b;           // isotropic record; b.pad holds -o.e1
     double e1x, e1y;     // frame vector e1 (its z component is zero)
@@ -825,7 +826,7 @@ struct BeamA<kMIX> {
         return k;
     }
     template <bool ABS>
-    __device__ __forceinline__ static void term(const TileRecA& S, const JobConst& J, const Geo& g, bool live,
+    __device__ __forceinline__ static bool term(const TileRecA& S, const JobConst& J, const Geo& g, bool live,
                                                 float& ur, float& ui) {
         const double s = g.s;
         const double nn = fma(-s, s, g.l + S.b.oo);                      // n1^2 + n2^2
@@ -859,6 +860,7 @@ struct BeamA<kMIX> {
         const float ci = (re * W.y + im * W.x) * pre;
         ur = cr * cs - ci * sn;
         ui = cr * sn + ci * cs;
+        return in;
     }
 };
 
@@ -871,7 +873,7 @@ struct BeamA<kF64> {
         return BeamA<kMIX>::gate(S, J, X, Y, Z, R2, g);
     }
     template <bool ABS>
-    __device__ __forceinline__ static void term(const TileRecA& S, const JobConst& J, const Geo& g, bool live,
+    __device__ __forceinline__ static bool term(const TileRecA& S, const JobConst& J, const Geo& g, bool live,
                                                 double& ur, double& ui) {
         const double s = g.s;
         const double nn = fma(-s, s, g.l + S.b.oo);
@@ -898,6 +900,7 @@ struct BeamA<kF64> {
         const double ci = (re * S.b.wgi + im * S.b.wgr) * pre;
         ur = cr * cs - ci * sn;
         ui = cr * sn + ci * cs;
+        return in;
     }
 };
 
@@ -918,10 +921,16 @@ __device__ __forceinline__ int pair_one(const TileOf<MODE>& S, const JobConst& J
     if (__ballot(k0) == 0ull) return 0;
     branch_barrier();
     typename B::T ur, ui;
-    B::template term<ABS>(S, J, g, k0, ur, ui);
+    int hit;
+    if constexpr ((MODE & kAniso) != 0) {
+        hit = (int)B::template term<ABS>(S, J, g, k0, ur, ui);
+    } else {
+        B::template term<ABS>(S, J, g, k0, ur, ui);
+        hit = (int)k0;
+    }
     ar += (double)ur;
     ai += (double)ui;
-    return k0;
+    return hit;
 }
 
 // Two consecutive segments for one receiver: their beam terms are independent
@@ -939,11 +948,19 @@ __device__ __forceinline__ int pair_two(const TileOf<MODE>& S0, const TileOf<MOD
     if (__ballot(k0 || k1) == 0ull) return 0;
     branch_barrier();
     T u0r, u0i, u1r, u1i;
-    B::template term<ABS>(S0, J, g0, k0, u0r, u0i);
-    B::template term<ABS>(S1, J, g1, k1, u1r, u1i);
+    int hit;
+    if constexpr ((MODE & kAniso) != 0) {
+        const bool h0 = B::template term<ABS>(S0, J, g0, k0, u0r, u0i);
+        const bool h1 = B::template term<ABS>(S1, J, g1, k1, u1r, u1i);
+        hit = (int)h0 + (int)h1;
+    } else {
+        B::template term<ABS>(S0, J, g0, k0, u0r, u0i);
+        B::template term<ABS>(S1, J, g1, k1, u1r, u1i);
+        hit = (int)k0 + (int)k1;
+    }
     ar += (double)(u0r + u1r);
     ai += (double)(u0i + u1i);
-    return (int)k0 + (int)k1;
+    return hit;
 }
 
 // A segment record in registers, as six named 16-byte vectors (kept out of
@@ -1531,11 +1548,10 @@ GBS_INST_PAIRS_MODE(2)
 GBS_INST_PAIRS_MODE(4)
 GBS_INST_PAIRS_MODE(5)
 GBS_INST_PAIRS_MODE(6)
-#define GBS_INST_PAIRS_ANISO(M) GBS_INST_PAIRS(M, 1, false) GBS_INST_PAIRS(M, 2, false) GBS_INST_PAIRS(M, 4, false)
-GBS_INST_PAIRS_ANISO(8)
-GBS_INST_PAIRS_ANISO(9)
-GBS_INST_PAIRS_ANISO(12)
-GBS_INST_PAIRS_ANISO(13)
+GBS_INST_PAIRS_MODE(8)
+GBS_INST_PAIRS_MODE(9)
+GBS_INST_PAIRS_MODE(12)
+GBS_INST_PAIRS_MODE(13)
 #define GBS_INST_ADJ(M)                                                                                          \
     template __global__ void k_adjoint<M>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,       \
                                           const int32_t*, const SegRec*, const double*, const double*,            \
