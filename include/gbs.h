@@ -203,8 +203,9 @@ int gbs_get_stats(const gbs_ctx* ctx, gbs_stats* out);
  * the table slice (copied from host memory with GBS_FLAG_TABLE_HOST, which
  * then must be page-locked), the segment records and the pair kernel.
  * Between replays the caller may change the CONTENTS of faces->gamma and of a
- * host table's arrays, but not the geometry, receivers, frequencies or eps
- * (the culled work lists are baked in).  The graph holds the pointers given
+ * host table's arrays, but not the geometry, receivers, frequencies, eps,
+ * params.eps_e2 or params.alpha (the culled work lists and the per-job
+ * constants are baked in).  The graph holds the pointers given
  * at creation.
  */
 typedef struct gbs_graph gbs_graph;
