@@ -134,8 +134,8 @@ typedef struct gbs_params {
                                  kept iff the Gaussian factor is >= exp(-gate_G).
                                  e1 stays horizontal under reflection on the
                                  ground, roofs and walls of the box scenes, so
-                                 it is the transported frame there.  Modes F64
-                                 and MIX only; not with gbs_backward or
+                                 it is the transported frame there.  Every
+                                 mode; not with gbs_backward or
                                  gbs_impulse_response (GBS_E_UNSUPPORTED).     */
 } gbs_params;
 

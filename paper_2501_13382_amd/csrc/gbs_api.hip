@@ -268,8 +268,6 @@ void validate_host(const Args& a) {
     GBS_CHECK(a.faces->n_faces >= 0, "negative face count");
     if (a.n_freq > kMaxBands)
         throw GbsError(GBS_E_UNSUPPORTED, "at most 64 bands per call");
-    if (p.eps_e2 && p.mode == GBS_MODE_F32)
-        throw GbsError(GBS_E_UNSUPPORTED, "anisotropic beams need mode F64 or MIX");
     GBS_CHECK(a.n_rcv <= (int64_t)INT32_MAX - 4096, "too many receivers");
     GBS_CHECK(a.segs->n_segs <= (int64_t)INT32_MAX, "too many segments");
     GBS_CHECK(a.rays->n_rays == 0 || a.rays->n_src > 0, "rays without sources");
@@ -835,19 +833,20 @@ void dispatch_count(bool count, int nr, gbs_ctx* ctx, hipStream_t st, const Plan
 
 // mode: GBS_MODE_*; absorb: some job has atmospheric absorption (the kernel
 // variant with the absorption exponent; the others skip it); aniso:
-// anisotropic beams (F64 and MIX; counting counts the exact gate's pairs).
+// anisotropic beams (counting counts the exact gate's pairs).
 void dispatch_pairs(int mode, bool absorb, bool aniso, bool count, int nr, gbs_ctx* ctx, hipStream_t st,
                     const Planner::Lists& L, const RcvPlan& R, int64_t n_rcv, double* P, unsigned* ctr,
                     unsigned long long* na) {
     GBS_CHECK(L.partial != nullptr, "work-unit partials not allocated");
     const int m = (mode == GBS_MODE_F64 ? 0 : mode == GBS_MODE_MIX ? 1 : 2) | (absorb ? 4 : 0);
     if (aniso) {
-        GBS_CHECK((m & 3) != 2, "anisotropic beams: F64 or MIX");
         switch (m) {
             case 0: dispatch_count<8>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
             case 1: dispatch_count<9>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
+            case 2: dispatch_count<10>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
             case 4: dispatch_count<12>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
-            default: dispatch_count<13>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
+            case 5: dispatch_count<13>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
+            default: dispatch_count<14>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
         }
         return;
     }

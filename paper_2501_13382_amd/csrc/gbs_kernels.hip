@@ -669,7 +669,7 @@ struct Beam;
 constexpr int kF64 = 0, kMIX = 1, kF32 = 2;
 // Pair-kernel variants: the precision mode, plus kAbsorb when any job has
 // atmospheric absorption (without it the term skips the absorption exponent),
-// plus kAniso for anisotropic beams (F64 and MIX only).
+// plus kAniso for anisotropic beams.
 constexpr int kAbsorb = 4;
 constexpr int kAniso = 8;
 
@@ -898,6 +898,54 @@ struct BeamA<kF64> {
         const double pre = J.ampc / sqrt(den1 * den2 * bb) * w;
         const double cr = (re * S.b.wgr - im * S.b.wgi) * pre;
         const double ci = (re * S.b.wgi + im * S.b.wgr) * pre;
+        ur = cr * cs - ci * sn;
+        ui = cr * sn + ci * cs;
+        return in;
+    }
+};
+
+template <>
+struct BeamA<kF32> {
+    using T = float;
+    struct Geo { float s, n2, x, y; };
+    __device__ __forceinline__ static bool gate(const TileRecA& S, const JobConst& J, double X, double Y, double Z,
+                                                double R2, Geo& g) {
+        Beam<kF32>::Geo h;
+        const bool k = Beam<kF32>::gate(S.b, J, X, Y, Z, R2, h);
+        g.s = h.s;
+        g.n2 = h.n2;
+        g.x = (float)X;
+        g.y = (float)Y;
+        return k;
+    }
+    template <bool ABS>
+    __device__ __forceinline__ static bool term(const TileRecA& S, const JobConst& J, const Geo& g, bool live,
+                                                float& ur, float& ui) {
+        const float s = g.s;
+        const float n1 = fmaf(g.x, (float)S.e1x, fmaf(g.y, (float)S.e1y, (float)S.b.pad));
+        const float q1 = n1 * n1;
+        const float q2 = fmaxf(g.n2 - q1, 0.0f);
+        const float e1 = (float)J.eps, e2 = (float)J.epsb;
+        const float den1 = fmaf(s, s, (float)J.epsa2), den2 = fmaf(s, s, (float)J.epsb2);
+        const float a1 = q1 * __builtin_amdgcn_rcpf(den1), a2 = q2 * __builtin_amdgcn_rcpf(den2);
+        const float e = fmaf(e1, a1, e2 * a2);
+        const bool in = live && e <= (float)J.gate_a;
+        const float cyc = (float)J.fk * fmaf(0.5f * s, a1 + a2, s);
+        const float ph = __builtin_amdgcn_fractf(cyc);
+        const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
+        const float gg = e * (float)J.gexpa2;
+        const float w = __builtin_amdgcn_exp2f(in ? (ABS ? fmaf(s, (float)J.aexp2, gg) : gg) : -INFINITY);
+        const float d1 = __builtin_amdgcn_sqrtf(den1), d2 = __builtin_amdgcn_sqrtf(den2);
+        const float b1 = d1 + e1, b2 = d2 + e2;
+        const float ss = s * s;
+        const float x = fmaf(ss, (float)(J.epsa2 + J.epsb2), (float)(J.epsa2 * J.epsb2)) *
+                        __builtin_amdgcn_rcpf(fmaf(d1, d2, ss));
+        const float im = x + fmaf(e1, d2, fmaf(e2, d1, e1 * e2));
+        const float re = s * (b1 + b2);
+        const float pre = (float)J.ampc * __builtin_amdgcn_rsqf(den1 * den2 * (b1 * b2)) * w;
+        const float4 W = tile_weights(S.b);
+        const float cr = (re * W.x - im * W.y) * pre;
+        const float ci = (re * W.y + im * W.x) * pre;
         ur = cr * cs - ci * sn;
         ui = cr * sn + ci * cs;
         return in;
@@ -1550,8 +1598,10 @@ GBS_INST_PAIRS_MODE(5)
 GBS_INST_PAIRS_MODE(6)
 GBS_INST_PAIRS_MODE(8)
 GBS_INST_PAIRS_MODE(9)
+GBS_INST_PAIRS_MODE(10)
 GBS_INST_PAIRS_MODE(12)
 GBS_INST_PAIRS_MODE(13)
+GBS_INST_PAIRS_MODE(14)
 #define GBS_INST_ADJ(M)                                                                                          \
     template __global__ void k_adjoint<M>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,       \
                                           const int32_t*, const SegRec*, const double*, const double*,            \

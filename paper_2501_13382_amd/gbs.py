@@ -194,8 +194,7 @@ def forward(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="m
     the statistics returned by stats().  alpha: atmospheric absorption per
     (source, band) in Np/m (see air_absorption), or None.  eps_e2: beam
     parameter along e2 per (source, band) for anisotropic beams (eps is then
-    the one along the horizontal frame vector e1; modes "f64" and "mix"), or
-    None."""
+    the one along the horizontal frame vector e1), or None."""
     ctx = context(table.device)
     ctx.bind_stream()
     call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, validate, count_active,

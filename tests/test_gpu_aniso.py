@@ -1,5 +1,5 @@
 """GPU anisotropic beams (Eq. (1) with Q = diag(q1, q2)) against the oracle's
-anisotropic sum, element by element: F64 and MIX on the open plane (ground
+anisotropic sum, element by element: F64, MIX and F32 on the open plane (ground
 reflections, image fan) and on a batched city (walls and roofs, several
 sources and bands), with atmospheric absorption, over several passes of the
 table, from a host-resident table and through a graph; equal widths give the
@@ -26,13 +26,14 @@ pytestmark = pytest.mark.gpu
 # amplifies.  On the batched city an FP64 numpy evaluation of the library's
 # formula order lands at 2e-9 from the oracle (1.5e-9 on the GPU); the
 # isotropic formula order at 4e-10.
-TOL_ANISO = {"f64": (1e-8, 1e-6), "mix": TOL["mix"]}
+TOL_ANISO = {"f64": (1e-8, 1e-6), "mix": TOL["mix"], "f32": TOL["f32"]}
 
 
 def assert_within(stats, mode):
     rel_tol, dtl_tol = TOL_ANISO[mode]
     assert stats["dead_ok"], "receivers with no beam must get exactly zero"
-    assert stats["rel_max"] <= rel_tol, (mode, stats)
+    if rel_tol is not None:
+        assert stats["rel_max"] <= rel_tol, (mode, stats)
     assert stats["dtl_max"] <= dtl_tol, (mode, stats)
     assert stats["masked_frac"] <= 0.01, stats
 
@@ -59,7 +60,7 @@ def city():
     return sc, e2, ref_aniso(sc, e2)
 
 
-@pytest.mark.parametrize("mode", ["f64", "mix"])
+@pytest.mark.parametrize("mode", ["f64", "mix", "f32"])
 def test_open_plane_anisotropic(plane, mode):
     sc, e2, (P_ref, TL_ref, ab) = plane
     print(f"case aniso open plane mode={mode}", flush=True)
@@ -69,6 +70,9 @@ def test_open_plane_anisotropic(plane, mode):
     assert_within(compare(P.cpu().numpy(), TL.cpu().numpy(), P_ref, TL_ref, ab), mode)
 
 
+# F32 is the ablation mode: on this city (8 kHz, paths up to ~900 m) neither FP32
+# form meets its 0.2 dB bar (a float32 numpy evaluation of the library's formula
+# orders: isotropic 0.51 dB, anisotropic 6.1 dB), so F32 is checked on the open plane.
 @pytest.mark.parametrize("mode", ["f64", "mix"])
 def test_city_anisotropic(city, mode):
     sc, e2, (P_ref, TL_ref, ab) = city
@@ -138,8 +142,6 @@ def test_equal_widths_match_the_isotropic_kernel(plane):
 def test_unsupported_requests_fail(plane):
     sc, e2, _ = plane
     t = gbs.Table(sc.table, device="cuda")
-    with pytest.raises(gbs._lib.GbsError):
-        gbs.forward(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, mode="f32", eps_e2=e2)
     with pytest.raises(gbs._lib.GbsError):
         gbs.forward(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, eps_e2=-e2)
     with pytest.raises(ValueError):
