@@ -1,7 +1,7 @@
 """GPU anisotropic beams (Eq. (1) with Q = diag(q1, q2)) against the oracle's
 anisotropic sum, element by element: F64, MIX and F32 on the open plane (ground
-reflections, image fan) and on a batched city (walls and roofs, several
-sources and bands), with atmospheric absorption, over several passes of the
+reflections, image fan), F64 and MIX on a batched city (walls and roofs,
+several sources and bands), with atmospheric absorption, over several passes of the
 table, from a host-resident table and through a graph; equal widths give the
 isotropic kernel's field; unsupported requests fail with an error.
 The oracle takes each segment's frame vector as input (scenes.normal_frame,
