@@ -20,6 +20,11 @@ timed on a sample of rays), the forward with atmospheric absorption in
 the paper's atmosphere, the forward with anisotropic beams (beam parameter
 along e2 twice the one along e1), and broadband synthesis (an impulse
 response per receiver from 1,751 frequency bins) on a receiver subsample.
+Two more workloads run on the same clock (`workloads`): the 10 x 10 city
+with 1,000,000 rays over 1024 x 1024 receivers at 1 kHz, and the batched
+city (16 sources with U(10k, 500k) rays, four bands, 1024 x 1024 receivers),
+each with its forward, pair-kernel roofline, graph replay and a sampled
+oracle check.
 """
 from __future__ import annotations
 
@@ -37,20 +42,25 @@ sys.path.insert(0, ROOT)
 # Algorithmic work per pair of the pair kernel, counted from the evaluated
 # formulas (an FMA counts 2; a transcendental, a reciprocal or a fract 1;
 # compares count 0):
-#   every listed pair: arc length s (3 FMA) and |R-o|^2 - |o|^2 (3 FMA)        -> 12 FP64
-#     (the gate's right-hand side, skipped where the cull proved that every
-#     receiver of the patch passes, is not counted)
+#   every listed pair: arc length s (3 FMA), |R-o|^2 - |o|^2 (3 FMA) and the
+#     gate's right-hand side c1 s^2 + c2 - |o|^2 (mul, FMA)                 -> 15 FP64
 #   every kept pair: n^2 (add, FMA), den (FMA), Newton reciprocal (2 FMA),
 #     a = n^2/den, cycles (FMA, mul), fract, Gaussian exponent, accumulation
 #     (2 adds)                                                             -> 17 FP64
 #     rcp, sin, cos, exp2, weight, amplitude (2 x (FMA, mul)), rotation
 #     (2 x (mul, FMA)), pair sum                                           -> 18 FP32
-FLOP_LISTED_F64 = 12
+FLOP_LISTED_F64 = 15
 FLOP_KEPT_F64 = 17
 FLOP_KEPT_F32 = 18
-ADJ_FLOP_KEPT_F64 = 29
-ADJ_FLOP_KEPT_F32 = 69
-# The anisotropic variant (same 12 FP64 per listed pair):
+# The survey's algorithmic count per pair (what the method must do, FMA = 2):
+# a pre-gate of ~20 flops on every listed (not culled) pair; per kept pair ~30
+# FP64 flops (arc length, normal distance, denominator, reciprocal, phase and
+# its reduction), ~40 FP32 flops (Gaussian, amplitude, complex rotation,
+# compensated accumulation) and 3 transcendentals (counted 1 each, as FP32).
+SURVEY_FLOP_LISTED = 20
+SURVEY_FLOP_KEPT_F64 = 30
+SURVEY_FLOP_KEPT_F32 = 43
+# The anisotropic variant (same 15 FP64 per listed pair):
 #   every kept pair: n1^2 + n2^2 (add, FMA), n1 (2 FMA), n1^2, n2^2, two
 #     denominators (2 FMA), two Newton reciprocals (4 FMA), a1, a2, the gate
 #     sum (mul, FMA), cycles (add, FMA, mul), fract, Gaussian exponent,
@@ -104,6 +114,45 @@ WORKLOADS = {"open_plane_100k": ("open_plane_100k_8band", _open_plane_100k),
              "city_batched": ("city_batched_16src_4band_1024sq", _city_batched)}
 
 
+def oracle_threads() -> int:
+    """Threads for the oracle: every CPU this process may run on
+    (sched_getaffinity), capped by OMP_NUM_THREADS where the host sets it
+    to its CPU share."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS")
+    return max(1, min(n, int(env))) if env else n
+
+
+def host_cpus() -> dict:
+    return {"nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def roofline(listed, kept, ms, kernel, f64_listed=FLOP_LISTED_F64, f64_kept=FLOP_KEPT_F64, f32_kept=FLOP_KEPT_F32):
+    """The pair kernel's roofline from its listed and kept pair counts and its
+    HIP-event time: `achieved` and `frac` from the kernel's own algorithmic
+    count against the peak for its FP64/FP32 mix (time at peak = f64/PEAK_F64
+    + f32/PEAK_F32), and the same with the survey's per-pair count, also as a
+    fraction of the FP32 vector peak alone."""
+    f64 = f64_listed * listed + f64_kept * kept
+    f32 = f32_kept * kept
+    achieved = (f64 + f32) / (ms * 1e-3)
+    peak = (f64 + f32) / (f64 / PEAK_F64 + f32 / PEAK_F32)
+    s64 = SURVEY_FLOP_LISTED * listed + SURVEY_FLOP_KEPT_F64 * kept
+    s32 = SURVEY_FLOP_KEPT_F32 * kept
+    s_ach = (s64 + s32) / (ms * 1e-3)
+    s_peak = (s64 + s32) / (s64 / PEAK_F64 + s32 / PEAK_F32)
+    return {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / peak, "frac_of_fp32_peak": achieved / PEAK_F32, "frac_of_fp64_peak": achieved / PEAK_F64,
+            "ms_per_launch": ms, "listed_pairs": int(listed), "kept_pairs": int(kept),
+            "flop_per_listed_pair": {"f64": f64_listed}, "flop_per_kept_pair": {"f64": f64_kept, "f32": f32_kept},
+            "survey_count": {"achieved": s_ach / 1e12, "peak": s_peak / 1e12, "frac": s_ach / s_peak,
+                             "frac_of_fp32_peak": s_ach / PEAK_F32,
+                             "flop_per_listed_pair": SURVEY_FLOP_LISTED,
+                             "flop_per_kept_pair": {"f64": SURVEY_FLOP_KEPT_F64, "f32": SURVEY_FLOP_KEPT_F32}}}
+
+
 def cpu_model() -> str:
     """The host CPU's model name (first entry of /proc/cpuinfo), or "unknown"."""
     try:
@@ -145,7 +194,7 @@ def absorption_bench(sc, dev, table, rcv, freqs, eps, gamma, args, sec_step):
         import oracle
         n_cpu = int(min(1024, max(16, 4e9 / (sc.table.n_segs * len(sc.freqs)))))
         idx = receiver_subsample(len(sc.rcv), n=n_cpu, seed=8)
-        threads = int(os.environ.get("OMP_NUM_THREADS", str(min(16, os.cpu_count() or 1))))
+        threads = oracle_threads()
         P_ref, TL_ref, ab = oracle.scene_forward(sc, rcv=sc.rcv[idx], n_threads=threads, return_absum=True,
                                                  alpha=alpha)
         Pg = P.cpu().numpy().reshape(-1, len(sc.rcv))[:, idx]
@@ -189,24 +238,17 @@ def aniso_bench(sc, dev, table, rcv, freqs, eps, gamma, args, sec_step):
     torch.cuda.synchronize()
     st = gbs.stats()
     listed, active = st["listed_pairs"], st["active_pairs"]
-    f64 = FLOP_LISTED_F64 * listed + ANI_FLOP_KEPT_F64 * active
-    f32 = ANI_FLOP_KEPT_F32 * active
-    achieved = (f64 + f32) / (ms_pairs * 1e-3)
-    peak = (f64 + f32) / (f64 / PEAK_F64 + f32 / PEAK_F32)
     leg = {"value": sc.dense_pairs / s_an, "ms_per_step": s_an * 1e3, "overhead_vs_value": s_an / sec_step - 1.0,
            "eps_e2_over_eps": 2.0,
-           "roofline": {"bound": "alu", "kernel": "k_pairs<MIX|aniso>", "achieved": achieved / 1e12,
-                        "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak, "ms_per_launch": ms_pairs,
-                        "listed_pairs": listed, "kept_pairs": active,
-                        "flop_per_listed_pair": {"f64": FLOP_LISTED_F64},
-                        "flop_per_kept_pair": {"f64": ANI_FLOP_KEPT_F64, "f32": ANI_FLOP_KEPT_F32}}}
+           "roofline": roofline(listed, active, ms_pairs, "k_pairs<MIX|aniso>", f64_kept=ANI_FLOP_KEPT_F64,
+                                f32_kept=ANI_FLOP_KEPT_F32)}
     print(f"# anisotropic: {s_an * 1e3:.2f} ms/step, pair kernel {ms_pairs:.2f} ms", file=sys.stderr,
           flush=True)
     if not args.no_cpu:
         import oracle
         n_cpu = int(min(1024, max(16, 4e9 / (sc.table.n_segs * len(sc.freqs)))))
         idx = receiver_subsample(len(sc.rcv), n=n_cpu, seed=9)
-        threads = int(os.environ.get("OMP_NUM_THREADS", str(min(16, os.cpu_count() or 1))))
+        threads = oracle_threads()
         P_ref, TL_ref, ab = oracle.forward(sc.table, sc.gamma, sc.rcv[idx], sc.freqs, sc.eps, c=sc.c, gate=sc.gate,
                                            n_threads=threads, return_absum=True, eps_e2=e2,
                                            seg_e1=normal_frame(sc.table.seg_t))
@@ -252,7 +294,7 @@ def impulse_bench(sc, dev, table, gamma, args):
     if not args.no_cpu:
         import oracle
         k = np.array([0, 1000, 2000, 3000])
-        threads = int(os.environ.get("OMP_NUM_THREADS", str(min(16, os.cpu_count() or 1))))
+        threads = oracle_threads()
         ref = oracle.impulse_response(sc.table, sc.gamma, sc.rcv[idx[k]], df, bin0, n_bins, eps, n_fft, n_fft,
                                       window=win, c=sc.c, gate=sc.gate, n_threads=threads)
         got = h.cpu().numpy()[:, k, :]
@@ -336,6 +378,85 @@ def trace_bench(sc, dev, args):
     return leg
 
 
+def workload_leg(key, dev, args):
+    """One more workload on the same clock as the headline: the forward (MIX,
+    table resident in HBM) timed over a few steps, the pair kernel's roofline,
+    the graph replay, and the error against the oracle on a small seeded
+    receiver sample, which also times the oracle."""
+    import torch
+
+    import paper_2501_13382_amd as gbs
+    from scenes import receiver_subsample
+    name, build = WORKLOADS[key]
+    t0 = time.time()
+    sc = build()
+    t_build = time.time() - t0
+    table = gbs.Table(sc.table, device=dev)
+    rcv = torch.as_tensor(sc.rcv, device=dev)
+    freqs = torch.as_tensor(sc.freqs, device=dev)
+    eps = torch.as_tensor(sc.eps, device=dev)
+    gamma = torch.as_tensor(sc.gamma, device=dev)
+    dense = sc.dense_pairs
+    print(f"# {key}: built in {t_build:.1f}s, {table.n_rays} rays, {table.n_segs} segments", file=sys.stderr,
+          flush=True)
+    call = lambda **kw: gbs.forward(table, rcv, freqs, eps, gamma, c=sc.c, gate=sc.gate, mode="mix", **kw)
+    call()
+    torch.cuda.synchronize()
+    n = max(2, args.city_steps)
+    t = time.perf_counter()
+    for _ in range(n):
+        P, TL = call()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t) / n
+    ms_pairs = []
+    for _ in range(2):
+        call(time_kernels=True)
+        torch.cuda.synchronize()
+        ms_pairs.append(gbs.stats(dev)["ms_pairs"])
+    call(count_active=True)
+    torch.cuda.synchronize()
+    st = gbs.stats(dev)
+    leg = {"workload": name, "value": dense / sec, "unit": "evals/s", "ms_per_step": sec * 1e3, "steps": n,
+           "dense_pairs": dense, "rays": table.n_rays, "segments": table.n_segs, "receivers": int(len(sc.rcv)),
+           "bands": int(len(sc.freqs)), "sources": int(table.n_src),
+           "roofline": roofline(st["listed_pairs"], st["active_pairs"], float(np.mean(ms_pairs)), "k_pairs<MIX>"),
+           "scene_build_s": t_build}
+    print(f"# {key}: {sec * 1e3:.1f} ms/step, pair kernel {np.mean(ms_pairs):.1f} ms", file=sys.stderr, flush=True)
+    graph = gbs.Graph(table, rcv, freqs, eps, gamma, c=sc.c, gate=sc.gate, mode="mix")
+    graph.launch()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(n):
+        graph.launch()
+    torch.cuda.synchronize()
+    s_gr = (time.perf_counter() - t) / n
+    leg["graph"] = {"value": dense / s_gr, "ms_per_step": s_gr * 1e3, "replays": n}
+    del graph
+    if not args.no_cpu:
+        import oracle
+        threads = oracle_threads()
+        # about 1e10 oracle pairs (a few seconds on the host) at most
+        n_cpu = int(min(256, max(16, 1e10 / (sc.table.n_segs * len(sc.freqs)))))
+        idx = receiver_subsample(len(sc.rcv), n=n_cpu, seed=5)
+        t = time.perf_counter()
+        P_ref, TL_ref, ab = oracle.scene_forward(sc, rcv=sc.rcv[idx], n_threads=threads, return_absum=True)
+        el = time.perf_counter() - t
+        pairs = sc.table.n_segs * len(idx) * len(sc.freqs)
+        Pg = P.cpu().numpy().reshape(-1, len(sc.rcv))[:, idx]
+        TLg = TL.cpu().numpy().reshape(-1, len(sc.rcv))[:, idx]
+        ok = ab / np.maximum(np.abs(P_ref), 1e-300) <= 1e4
+        leg["accuracy_vs_oracle"] = {
+            "tl_err_db_max": float(np.abs(TLg - TL_ref)[ok].max()),
+            "rel_err_max": float((np.abs(Pg - P_ref) / np.maximum(np.abs(P_ref), 1e-300))[ok].max()),
+            "receivers": int(len(idx)), "masked_fraction": float(1.0 - ok.mean())}
+        leg["cpu_baseline"] = {"value": pairs / el, "unit": "evals/s", "cores": threads, "kind": "oracle",
+                               "sample": f"{len(idx)} of {len(sc.rcv)} receivers (seed 5), all segments; {el:.1f}s",
+                               "extrapolated_full_config_s": dense / (pairs / el)}
+    del table, P, TL
+    torch.cuda.empty_cache()
+    return leg
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -355,6 +476,9 @@ def parse():
                     help="open_plane_100k (default, the headline); city_1m: 10 x 10 city, 1,000,000 rays, "
                          "1024 x 1024 receivers, 1 kHz; city_batched: 16 sources x 4 bands, ragged ray counts, "
                          "replayed as a captured graph")
+    ap.add_argument("--no-cities", action="store_true",
+                    help="skip the extra workload legs (the 1M-ray city and the 16-source batched city)")
+    ap.add_argument("--city-steps", type=int, default=5, help="timed steps of each extra workload leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the steps, run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -418,12 +542,7 @@ def main():
     step(mode, count=True)
     st = gbs.stats(dev)
     listed, active = st["listed_pairs"], st["active_pairs"]
-    f64 = FLOP_LISTED_F64 * listed + FLOP_KEPT_F64 * active
-    f32 = FLOP_KEPT_F32 * active
-    flops = f64 + f32
-    achieved = flops / (ms_pairs * 1e-3)
-    # peak for this kernel's FP64/FP32 mix: time at peak = f64/PEAK_F64 + f32/PEAK_F32
-    peak = flops / (f64 / PEAK_F64 + f32 / PEAK_F32)
+    roof = roofline(listed, active, ms_pairs, "k_pairs<MIX>")
 
     stream_leg = None
     if not args.no_stream:
@@ -519,6 +638,12 @@ def main():
                    "mix_speedup": s64 / sec_step}
         print(f"# f64: {s64 * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
 
+    workloads = {}
+    if not args.no_cities:
+        for key in ("city_1m", "city_batched"):
+            if key != args.workload:
+                workloads[key] = workload_leg(key, dev, args)
+
     result = {
         "metric": "GBS segment x receiver evals/s, % FP32 VALU peak; TL error dB vs FP64 oracle",
         "value": dense / sec_step,
@@ -535,12 +660,7 @@ def main():
         "config": {"workload": workload_name, "rays": table.n_rays, "segments": table.n_segs,
                    "receivers": int(len(sc.rcv)), "bands": int(len(sc.freqs)), "mode": mode,
                    "dense_pairs": dense, "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "kernel": "k_pairs<MIX>", "achieved": achieved / 1e12,
-                     "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "frac_of_fp32_peak": achieved / PEAK_F32, "frac_of_fp64_peak": achieved / PEAK_F64,
-                     "traffic": pair_traffic() if headline else None, "ms_per_launch": ms_pairs, "listed_pairs": listed, "kept_pairs": active,
-                     "flop_per_listed_pair": {"f64": FLOP_LISTED_F64},
-                     "flop_per_kept_pair": {"f64": FLOP_KEPT_F64, "f32": FLOP_KEPT_F32}},
+        "roofline": dict(roof, traffic=pair_traffic() if headline else None),
         "pair_kernel_share": ms_pairs / (sec_step * 1e3),
         "ms_step_median": launch["ms_step_median"],
         "ms_step_min": launch["ms_step_min"],
@@ -556,6 +676,7 @@ def main():
         "absorption": absorption_leg,
         "anisotropic": aniso_leg,
         "impulse_response": impulse_leg,
+        "workloads": workloads,
     }
 
     if args.copy_calibration > 0:
@@ -574,14 +695,14 @@ def main():
     if not args.no_cpu:
         import oracle
         oracle.build(force=False)
-        threads = int(os.environ.get("OMP_NUM_THREADS", str(min(16, os.cpu_count() or 1))))
+        threads = oracle_threads()
         print(f"# oracle, {threads} threads, {len(idx)} receivers", file=sys.stderr, flush=True)
         t = time.perf_counter()
         P_ref, TL_ref, ab = oracle.scene_forward(sc, rcv=sc.rcv[idx], n_threads=threads, return_absum=True)
         el = time.perf_counter() - t
         pairs = table.n_segs * len(idx) * len(sc.freqs)
         result["cpu_baseline"] = {"value": pairs / el, "unit": "evals/s", "cores": threads, "kind": "oracle",
-                                  "cpu_model": cpu_model(),
+                                  "cpu_model": cpu_model(), "host_cpus": host_cpus(),
                                   "sample": f"{len(idx)} of {len(sc.rcv)} receivers (seed 5), all "
                                             f"{table.n_segs} segments, {len(sc.freqs)} bands; {el:.1f}s",
                                   "extrapolated_full_config_s": dense / (pairs / el)}

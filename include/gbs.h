@@ -35,11 +35,22 @@
  * creation until gbs_graph_destroy.
  *
  * Errors.  Every entry point returns GBS_OK (0) or a negative gbs_status;
- * gbs_last_error() describes the last failure on the context.  Argument
- * checks run on the host before any device work.  No C++ exception crosses
- * this interface.  Calls on one context are not thread-safe; use one context
- * per host thread.  Work is enqueued on the context's stream; outputs are
- * complete when that stream is synchronised.
+ * gbs_last_error() describes the last failure on the context.  Sizes,
+ * pointers and scalar parameters are checked on the host before any device
+ * work.  Array contents are always checked (GBS_E_INVALID) before any beam is
+ * evaluated: the ray CSR (ray_ptr[0] = 0, non-decreasing, ray_ptr[n_rays] =
+ * n_segs; ray_src in [0, n_src) and non-decreasing), the face CSR
+ * (face_ptr[0] = 0, non-decreasing; ids in [0, n_faces); n_faces > 0 when any
+ * history is non-empty), finite a, s0, lo, hi with lo <= hi and |t| = 1
+ * (+-1e-9), finite non-negative ray weights, finite receivers, frequencies,
+ * beam parameters and absorption; in gbs_backward also finite lambda.  The
+ * kernels that read these arrays flag problems in a device status word that
+ * the host reads at its next synchronisation, so a failed call may already
+ * have written zeros to its outputs; no kernel reads outside an array
+ * because of bad contents.  No C++ exception crosses this interface.  Calls
+ * on one context are not thread-safe; use one context per host thread.  Work
+ * is enqueued on the context's stream; outputs are complete when that stream
+ * is synchronised.
  */
 #ifndef GBS_H
 #define GBS_H
@@ -71,7 +82,7 @@ typedef enum gbs_mode { GBS_MODE_F64 = 0, GBS_MODE_MIX = 1, GBS_MODE_F32 = 2 } g
 
 /* params.flags */
 #define GBS_FLAG_TABLE_HOST   1   /* ray/segment arrays are host memory: stream them */
-#define GBS_FLAG_VALIDATE     2   /* check table contents on the device first (syncs) */
+#define GBS_FLAG_VALIDATE     2   /* accepted and ignored: contents are always checked */
 #define GBS_FLAG_COUNT_ACTIVE 4   /* count kept pairs into gbs_stats (slower)          */
 #define GBS_FLAG_TIME_KERNELS 8   /* time the pair kernel with HIP events (syncs)      */
 
@@ -184,8 +195,11 @@ int gbs_forward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const 
  *   d_gamma [n_faces * 2]  out: (dL/dRe Gamma_f, dL/dIm Gamma_f)
  *   d_rcv   [n_rcv * 3]    out: dL/dR
  *   d_eps   [n_src*n_freq] out: dL/deps per job
- * Any output pointer may be NULL to skip it.  Sums of per-segment terms use
- * FP64 atomics: results agree to rounding but are not bitwise repeatable.
+ * Any output pointer may be NULL to skip it.  Deterministic: repeated calls
+ * with equal inputs give bitwise-equal outputs (receiver and beam-parameter
+ * sums are reduced in a fixed order; the per-segment and per-face sums
+ * behind d_gamma are exact fixed-point sums with a resolution of 2^-92 of a
+ * bound on them, whose value does not depend on the order of accumulation).
  */
 int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces,
                  const double* rcv, int64_t n_rcv, const double* freqs, int32_t n_freq, const double* eps,

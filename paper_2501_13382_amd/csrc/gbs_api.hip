@@ -25,14 +25,14 @@ __global__ void k_bbox_partial(const double*, int64_t, double*);
 __global__ void k_bbox_final(const double*, int, double*);
 __global__ void k_morton(const double*, int64_t, const double*, uint32_t*, int32_t*);
 __global__ void k_gather_rcv(const double*, int64_t, int64_t, const int32_t*, double*, double*, double*, double*,
-                             int32_t*);
+                             int32_t*, int*);
 __global__ void k_patches(const double*, const double*, const double*, int64_t, int64_t, int, Patch*);
 __global__ void k_sphere_of_spheres(const Patch*, int, int, int, Patch*);
-__global__ void k_src_ranges(const int64_t*, const int32_t*, int64_t, int32_t, int64_t*);
+__global__ void k_src_ranges(const int64_t*, const int32_t*, int64_t, int32_t, int64_t, const int64_t*, int64_t*, int*);
 __global__ void k_seg2ray(const int64_t*, int64_t, int64_t, int64_t, int32_t*);
 __global__ void k_records(int64_t, const double*, const double*, const double*, const double*, const double*,
                           const int64_t*, int64_t, const int32_t*, int32_t, const double*, const double*,
-                          const int32_t*, SegRec*);
+                          const int32_t*, int64_t, int64_t, SegRec*, int*, unsigned long long*);
 template <bool FILL, int NB>
 __global__ void k_cull(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int, const CullSplit*,
                        const unsigned long long*, int, int, int32_t*, const int64_t*, int32_t*);
@@ -57,15 +57,17 @@ __global__ void k_tl(const double*, int64_t, double*);
 template <int MODE>
 __global__ void k_adjoint(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*, const int32_t*,
                           const SegRec*, const double*, const double*, const double*, const double*, const int32_t*,
-                          int64_t, const double*, double*, const int32_t*, double*, double*);
+                          int64_t, const double*, double*, const int32_t*, Fixed*, const double*, double*);
 __global__ void k_reduce_adjoint(const JobConst*, const int32_t*, const int32_t*, int32_t, int32_t, const int32_t*,
                                  int64_t, const double*, double*);
 __global__ void k_sum_jobs(const double*, int32_t, int64_t, double*);
 __global__ void k_face_scatter(int64_t, const int64_t*, int64_t, const int32_t*, int32_t, const double*,
-                               const double*, const int32_t*, const double*, double*);
+                               const double*, const int32_t*, const Fixed*, const double*, Fixed*);
 __global__ void k_dgamma(const double*, int32_t, double*);
-__global__ void k_validate(int64_t, const double*, const double*, const double*, const int64_t*, int64_t,
-                           const int32_t*, int32_t, int*);
+__global__ void k_lambda_l1(const double*, int64_t, double*, int*);
+__global__ void k_fixed_scales(const JobConst*, const double*, int32_t, int64_t, const unsigned long long*, double*);
+__global__ void k_reduce_eps(const int32_t*, const int32_t*, int32_t, const double*, double*);
+__global__ void k_fixed_flush(const Fixed*, int64_t, const double*, double*);
 // ray tracing (gbs_trace.hip)
 template <bool COUNT>
 __global__ void k_trace(int64_t, int, const double*, const int32_t*, const double*, const double*, const double*,
@@ -283,6 +285,21 @@ void validate_host(const Args& a) {
     if (a.n_freq > 0) GBS_CHECK(a.freqs && a.eps, "null freqs/eps");
 }
 
+// The device status word (StatusBit) as an error.
+void check_status(int bits) {
+    if (bits == 0) return;
+    std::string m = "invalid input:";
+    if (bits & kBadSegment) m += " segment values (non-finite a, s0, lo or hi, lo > hi, or |t| != 1);";
+    if (bits & kBadFacePtr) m += " face_ptr (not a non-decreasing CSR from 0);";
+    if (bits & kBadFaceId) m += " face id outside [0, n_faces);";
+    if (bits & kBadRayPtr) m += " ray_ptr (not a non-decreasing CSR from 0 to n_segs);";
+    if (bits & kBadRayWeight) m += " ray weight (non-finite or negative);";
+    if (bits & kBadReceiver) m += " receiver coordinate (non-finite);";
+    if (bits & kBadRaySource) m += " ray_src (outside [0, n_src) or not non-decreasing);";
+    if (bits & kBadLambda) m += " lambda (non-finite);";
+    throw GbsError(GBS_E_INVALID, m);
+}
+
 // ------------------------------------------------------------- planning
 struct Planner {
     gbs_ctx* ctx;
@@ -296,6 +313,8 @@ struct Planner {
     std::vector<PassRange> passes;
     std::vector<int64_t> h_ray_ptr, h_face_ptr;  // host copies (only when chunking)
     RcvPlan R;
+    int* status = nullptr;            // device StatusBit word of this call
+    int64_t face_total = 0;           // face_ptr[n_segs]: length of face_ids
 
     Planner(gbs_ctx* c, Workspace& w, const Args& args, int nr_)
         : ctx(c), ws(w), st(c->stream), a(args), mode(args.params->mode), nr(nr_) {
@@ -304,6 +323,12 @@ struct Planner {
     }
 
     bool table_host() const { return (a.params->flags & GBS_FLAG_TABLE_HOST) != 0; }
+
+    // Clears the status word; the kernels that read the inputs set its bits.
+    void reset_status() {
+        status = ws.get<int>("status", 2);
+        fill(st, reinterpret_cast<double*>(status), 1, 0.0);
+    }
     int chunk_override = 0;   // autotuner candidate
     std::string tag;          // graph creation: per-pass names for the buffers the replays read
     int work_chunk() const {
@@ -346,15 +371,18 @@ struct Planner {
         return false;
     }
 
+    // First segment of every source, and the checks of the ray and face CSR
+    // arrays (on the host for host tables, by k_src_ranges otherwise; one
+    // synchronisation).
     void source_offsets() {
         const int32_t n_src = a.rays->n_src;
-        const int64_t n_rays = a.rays->n_rays;
+        const int64_t n_rays = a.rays->n_rays, n_segs = a.segs->n_segs;
         src_off.assign(n_src + 1, 0);
-        if (n_src == 0) return;
         if (table_host()) {
             const int64_t* rp = a.rays->ray_ptr;
             const int32_t* rs = a.rays->ray_src;
-            GBS_CHECK(rp[0] == 0 && rp[n_rays] == a.segs->n_segs, "ray_ptr must span the segments");
+            const int64_t* fp = a.segs->face_ptr;
+            GBS_CHECK(rp[0] == 0 && rp[n_rays] == n_segs, "ray_ptr must span the segments");
             for (int64_t i = 0; i <= n_rays; ++i) {
                 int32_t prev = i == 0 ? -1 : rs[i - 1];
                 int32_t cur = i == n_rays ? n_src : rs[i];
@@ -363,16 +391,25 @@ struct Planner {
                 if (i < n_rays) GBS_CHECK(rp[i + 1] >= rp[i], "ray_ptr must be non-decreasing");
                 for (int32_t s = prev + 1; s <= cur; ++s) src_off[s] = rp[i];
             }
-            return;
-        }
-        int64_t* d_off = ws.get<int64_t>("src_off", n_src + 1);
-        if (n_rays > 0) {
-            hipLaunchKernelGGL(k_src_ranges, dim3(blocks_for(n_rays + 1, 256)), dim3(256), 0, st,
-                               a.rays->ray_ptr, a.rays->ray_src, n_rays, n_src, d_off);
+            GBS_CHECK(fp[0] == 0, "face_ptr[0] must be 0");
+            for (int64_t j = 0; j < n_segs; ++j) GBS_CHECK(fp[j + 1] >= fp[j], "face_ptr must be non-decreasing");
+            face_total = fp[n_segs];
+        } else {
+            int64_t* d_off = ws.get<int64_t>("src_off", n_src + 2);
+            int h_status = 0;
+            hipLaunchKernelGGL(k_src_ranges, dim3(blocks_for(n_rays + 1, 256)), dim3(256), 0, st, a.rays->ray_ptr,
+                               a.rays->ray_src, n_rays, n_src, n_segs, a.segs->face_ptr, d_off, status);
             GBS_HIP(hipGetLastError());
             GBS_HIP(hipMemcpyAsync(src_off.data(), d_off, sizeof(int64_t) * (n_src + 1), hipMemcpyDeviceToHost, st));
+            GBS_HIP(hipMemcpyAsync(&face_total, a.segs->face_ptr + n_segs, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                   st));
+            GBS_HIP(hipMemcpyAsync(&h_status, status, sizeof(int), hipMemcpyDeviceToHost, st));
             GBS_HIP(hipStreamSynchronize(st));
+            check_status(h_status);
         }
+        GBS_CHECK(face_total >= 0, "face_ptr[n_segs] must be >= 0");
+        GBS_CHECK(face_total == 0 || a.segs->face_ids, "null face_ids");
+        GBS_CHECK(face_total == 0 || a.faces->n_faces > 0, "face histories need n_faces > 0");
     }
 
     void make_passes() {
@@ -400,6 +437,7 @@ struct Planner {
             GBS_HIP(hipStreamSynchronize(st));
             rp = h_ray_ptr.data();
             fp = h_face_ptr.data();
+            for (int64_t j = 0; j < n_segs; ++j) GBS_CHECK(fp[j + 1] >= fp[j], "face_ptr must be non-decreasing");
         }
         const int64_t limit = cs > 0 ? cs : n_segs;
         int64_t r0 = 0;
@@ -443,7 +481,7 @@ struct Planner {
         R.r2 = ws.get<double>("r2", R.n_pad);
         R.perm = ws.get<int32_t>("perm", R.n_pad);
         hipLaunchKernelGGL(k_gather_rcv, dim3(blocks_for(R.n_pad, 256)), dim3(256), 0, st, a.rcv, R.n, R.n_pad,
-                           vals2, R.rx, R.ry, R.rz, R.r2, R.perm);
+                           vals2, R.rx, R.ry, R.rz, R.r2, R.perm, status);
         R.patches = ws.get<Patch>("patches", R.n_patch);
         R.supers = ws.get<Patch>("supers", R.n_super);
         hipLaunchKernelGGL(k_patches, dim3(R.n_patch), dim3(64), 0, st, R.rx, R.ry, R.rz, R.n_pad, (int64_t)per,
@@ -587,27 +625,22 @@ struct Planner {
 
     // Records, job constants, culled lists and the longest-first item order
     // for one pass.  Synchronises once to size the lists.
-    Lists build_lists(const PassRange& ps, const PassView& v, int pass_idx) {
+    // Absolute end of the face ids a pass may read: the staged slice of a
+    // host table, the whole array otherwise.
+    int64_t face_end(const PassRange& ps) const { return table_host() ? ps.face_end : face_total; }
+
+    Lists build_lists(const PassRange& ps, const PassView& v, int pass_idx,
+                      unsigned long long* bmax = nullptr) {
         Lists L;
         const int64_t nseg = v.n_segs;
         int32_t* seg_ray = ws.get<int32_t>("seg_ray", nseg);
         SegRec* rec = ws.get<SegRec>("rec", nseg);
         if (nseg > 0) {
-            if (a.params->flags & GBS_FLAG_VALIDATE) {
-                int* bad = ws.get<int>("bad", 1);
-                GBS_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
-                hipLaunchKernelGGL(k_validate, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, nseg, v.t, v.lo, v.hi,
-                                   v.face_ptr, v.face_base, v.face_ids, a.faces->n_faces, bad);
-                int hb = 0;
-                GBS_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
-                GBS_HIP(hipStreamSynchronize(st));
-                GBS_CHECK(hb == 0, "segment table failed validation (non-unit t, lo > hi, or face id out of range)");
-            }
             hipLaunchKernelGGL(k_seg2ray, dim3(blocks_for(v.n_rays, 256)), dim3(256), 0, st, v.ray_ptr, v.n_rays,
                                ps.seg_begin, nseg, seg_ray);
             hipLaunchKernelGGL(k_records, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, nseg, v.a, v.t, v.s0, v.lo,
                                v.hi, v.face_ptr, v.face_base, v.face_ids, a.faces->n_faces, a.faces->gamma, v.ray_w,
-                               seg_ray, rec);
+                               seg_ray, v.n_rays, face_end(ps), rec, status, bmax);
             GBS_HIP(hipGetLastError());
         }
         L.rec = rec;
@@ -618,8 +651,7 @@ struct Planner {
         void* h = pinned_staging(ctx, sizeof(JobConst) * n_jobs);
         GBS_HIP(hipStreamSynchronize(st));  // the staging buffer may still feed an earlier copy
         std::memcpy(h, J.data(), sizeof(JobConst) * n_jobs);
-        GBS_HIP(hipMemcpyAsync(dJ, h, sizeof(JobConst) * n_jobs, hipMemcpyHostToDevice, st));
-        L.jobs = dJ;
+        GBS_HIP(hipMemcpyAsync(dJ, h, sizeof(JobConst) * n_jobs, hipMemcpyHostToDevice, st));        L.jobs = dJ;
         if (nseg > 0 && R.bbox) {
             // spatial order of the segments (each source's range stays in place)
             unsigned long long* k1 = ws.get<unsigned long long>("skeys", nseg);
@@ -697,8 +729,11 @@ struct Planner {
         GBS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, in64, off, (int)(n_cnt + 1), st));
         void* t = ws.get<char>("cub_tmp_scan", tmp);
         GBS_HIP(hipcub::DeviceScan::ExclusiveSum(t, tmp, in64, off, (int)(n_cnt + 1), st));
+        int h_status = 0;
         GBS_HIP(hipMemcpyAsync(&L.total, off + n_cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        GBS_HIP(hipMemcpyAsync(&h_status, status, sizeof(int), hipMemcpyDeviceToHost, st));
         GBS_HIP(hipStreamSynchronize(st));
+        check_status(h_status);     // before any list is filled or any pair kernel runs
         int32_t* lists = ws.get<int32_t>("lists" + tag, std::max<int64_t>(L.total, 1));
         if (!sv.empty())
             hipLaunchKernelGGL(cull_fill, cg, dim3(kWave), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
@@ -886,6 +921,7 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
     gbs_stats stats{};
     stats.patch_rcv = 64 * nr;
     if (n_out > 0 && a.segs->n_segs > 0) {
+        pl.reset_status();
         pl.source_offsets();
         for (int s = 0; s < a.rays->n_src; ++s)
             stats.dense_pairs += (pl.src_off[s + 1] - pl.src_off[s]) * a.n_rcv * a.n_freq;
@@ -1276,6 +1312,14 @@ int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
         stats.patch_rcv = 64;
         const bool timed = (params->flags & GBS_FLAG_TIME_KERNELS) != 0;
         if (n_out > 0 && segs->n_segs > 0) {
+            pl.reset_status();
+            // scales of the exact (order-independent) segment and face sums, from
+            // sum |lambda| per job and, per pass, the coefficient-derivative bound
+            double* l1 = ws.get<double>("lambda_l1", n_jobs);
+            double* fscale = ws.get<double>("fixed_scales", 4);
+            unsigned long long* bmax = ws.get<unsigned long long>("bmax", 1);
+            hipLaunchKernelGGL(k_lambda_l1, dim3(n_jobs), dim3(256), 0, st, lambda, n_rcv, l1, pl.status);
+            GBS_HIP(hipGetLastError());
             pl.source_offsets();
             pl.make_passes();
             pl.plan_receivers(64);
@@ -1283,34 +1327,43 @@ int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
             for (size_t pi = 0; pi < pl.passes.size(); ++pi) {
                 const PassRange& ps = pl.passes[pi];
                 Planner::PassView v = pl.view(ps);
-                Planner::Lists L = pl.build_lists(ps, v, (int)pi);
+                fill(st, reinterpret_cast<double*>(bmax), 1, 0.0);
+                Planner::Lists L = pl.build_lists(ps, v, (int)pi, bmax);
                 stats.listed_pairs += L.total * 64;
                 stats.n_items += L.n_items;
                 const int64_t nseg = v.n_segs;
-                double* Sseg = ws.get<double>("Sseg", 2 * std::max<int64_t>(nseg, 1));
-                fill(st, Sseg, 2 * nseg, 0.0);
+                hipLaunchKernelGGL(k_fixed_scales, dim3(1), dim3(64), 0, st, L.jobs, l1, n_jobs, nseg, bmax, fscale);
+                Fixed* Sseg = ws.get<Fixed>("Sseg", 2 * std::max<int64_t>(nseg, 1));
+                fill(st, reinterpret_cast<double*>(Sseg), 4 * nseg, 0.0);
                 if (L.n_items > 0 && L.total > 0) {
                     const bool f64 = params->mode == GBS_MODE_F64, ab = pl.absorb();
                     auto kern = f64 ? (ab ? k_adjoint<4> : k_adjoint<0>) : (ab ? k_adjoint<5> : k_adjoint<1>);
                     double* part = ws.get<double>("adj_partial", L.work_cap * 64 * 3);
+                    double* epart = ws.get<double>("eps_partial", L.work_cap);
                     const int64_t grid = persistent_grid(ctx, (const void*)kern, L.work_cap);
                     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, ctr);
                     EventPair ev(timed);
                     ev.begin(st);
                     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPairThreads), 0, st, L.jobs, L.work,
                                        L.n_work, pl.R.n_patch, ctr, L.lists, L.rec, pl.R.rx, pl.R.ry, pl.R.rz,
-                                       pl.R.r2, pl.R.perm, n_rcv, lambda, part, L.seg_perm, Sseg, dE);
+                                       pl.R.r2, pl.R.perm, n_rcv, lambda, part, L.seg_perm, Sseg, fscale, epart);
                     GBS_HIP(hipGetLastError());
                     stats.ms_pairs += ev.end(st);
                     hipLaunchKernelGGL(k_reduce_adjoint, dim3(blocks_for((int64_t)L.n_items * 64, 256)), dim3(256), 0,
                                        st, L.jobs, L.item_wbase, L.item_wcount, L.n_items, pl.R.n_patch, pl.R.perm,
                                        n_rcv, part, dRj);
+                    hipLaunchKernelGGL(k_reduce_eps, dim3(n_jobs), dim3(256), 0, st, L.item_wbase, L.item_wcount,
+                                       pl.R.n_patch, epart, dE);
                     GBS_HIP(hipGetLastError());
                 }
                 if (nf > 0 && nseg > 0) {
+                    Fixed* Zfix = ws.get<Fixed>("Zfix", 2 * (int64_t)nf);
+                    fill(st, reinterpret_cast<double*>(Zfix), 4 * (int64_t)nf, 0.0);
                     hipLaunchKernelGGL(k_face_scatter, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, nseg,
                                        v.face_ptr, v.face_base, v.face_ids, nf, faces->gamma, v.ray_w, L.seg_ray,
-                                       Sseg, Zf);
+                                       Sseg, fscale, Zfix);
+                    hipLaunchKernelGGL(k_fixed_flush, dim3(blocks_for(2 * (int64_t)nf, 256)), dim3(256), 0, st, Zfix,
+                                       2 * (int64_t)nf, fscale, Zf);
                     GBS_HIP(hipGetLastError());
                 }
             }
@@ -1324,7 +1377,10 @@ int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
         if (d_eps && n_jobs > 0)
             GBS_HIP(hipMemcpyAsync(d_eps, dE, sizeof(double) * n_jobs, hipMemcpyDeviceToDevice, st));
         GBS_HIP(hipGetLastError());
+        int h_status = 0;
+        if (pl.status) GBS_HIP(hipMemcpyAsync(&h_status, pl.status, sizeof(int), hipMemcpyDeviceToHost, st));
         GBS_HIP(hipStreamSynchronize(st));  // scratch reused by the next call
+        check_status(h_status);
         stats.grid = ctx->stats.grid;
         stats.blocks_per_cu = ctx->stats.blocks_per_cu;
         ctx->stats = stats;
@@ -1359,6 +1415,7 @@ int gbs_graph_create(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, c
         const bool work = n_out > 0 && segs->n_segs > 0;
         int64_t cap = 0;
         if (work) {
+            pl.reset_status();
             pl.source_offsets();
             pl.make_passes();
             pl.plan_receivers(64 * nr);
@@ -1388,7 +1445,8 @@ int gbs_graph_create(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, c
                 // coefficients may change between replays: rebuild the records
                 hipLaunchKernelGGL(k_records, dim3(blocks_for(v.n_segs, 256)), dim3(256), 0, st, v.n_segs, v.a, v.t,
                                    v.s0, v.lo, v.hi, v.face_ptr, v.face_base, v.face_ids, faces->n_faces,
-                                   faces->gamma, v.ray_w, seg_ray, rec);
+                                   faces->gamma, v.ray_w, seg_ray, v.n_rays, pl.face_end(pl.passes[pi]), rec,
+                                   pl.status, nullptr);
                 L.rec = rec;
                 if (L.seg_perm) {   // into the spatial order planned at creation
                     SegRec* rs = ws.get<SegRec>("rec_sorted", v.n_segs);

@@ -77,6 +77,31 @@ struct CullSplit {
     int32_t idx;              // index of the piece within its source
 };
 
+// Table and receiver checks done by the kernels that read the data anyway:
+// each problem sets one bit of a device status word, which the host reads at
+// its next synchronisation (before any pair kernel runs) and reports as
+// GBS_E_INVALID.  Kernels never read outside an array because of bad data.
+enum StatusBit : int {
+    kBadSegment = 1,      // non-finite a, s0, lo or hi; lo > hi; |t| != 1
+    kBadFacePtr = 2,      // face_ptr not non-decreasing inside [0, face_ptr[n_segs]]
+    kBadFaceId = 4,       // face id outside [0, n_faces)
+    kBadRayPtr = 8,       // ray_ptr not a CSR over the segments, or a segment without a ray
+    kBadRayWeight = 16,   // non-finite or negative ray weight
+    kBadReceiver = 32,    // non-finite receiver coordinate
+    kBadRaySource = 64,   // ray_src outside [0, n_src) or not non-decreasing
+    kBadLambda = 128      // non-finite adjoint weight lambda
+};
+
+// Exact, order-independent accumulation of doubles (deterministic sums with
+// atomics): a value x is scaled by 2^K, chosen per sum so that every partial
+// sum stays below 2^92 in magnitude, and split into hi = floor(y / 2^32) and
+// the integer part of y - hi 2^32 in [0, 2^32); both parts add as 64-bit
+// integers, whose sum does not depend on the order.  Resolution 2^-K.
+struct Fixed {
+    unsigned long long hi, lo;
+};
+constexpr int kFixedBits = 92;
+
 // Ray tracing: threads per workgroup (one ray each), the largest R_max (the
 // face history of a ray is staged in LDS) and boxes per bounding group.
 constexpr int kTraceThreads = 128;

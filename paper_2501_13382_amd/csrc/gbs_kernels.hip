@@ -85,6 +85,29 @@ __device__ __forceinline__ int lanes_before(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
+// Exact accumulation (see Fixed): adds x scaled by `scale` = 2^K.  The split
+// y = hi 2^32 + lo is exact: fma forms y - hi 2^32 with one rounding, and that
+// difference is representable.
+__device__ __forceinline__ void fixed_add(Fixed* acc, double x, double scale) {
+    const double y = x * scale;
+    const double h = floor(y * 0x1p-32);
+    const double l = fma(-h, 0x1p32, y);
+    atomicAdd(&acc->hi, (unsigned long long)(long long)h);
+    atomicAdd(&acc->lo, (unsigned long long)(long long)l);
+}
+// The accumulated value times inv_scale = 2^-K (deterministic rounding).
+__device__ __forceinline__ double fixed_value(const Fixed& acc, double inv_scale) {
+    const long long l = (long long)acc.lo;
+    const long long h = (long long)acc.hi + (l >> 32);
+    return fma((double)h, 0x1p32, (double)(l & 0xffffffffll)) * inv_scale;
+}
+// 2^K with K the largest integer such that bound * 2^K <= 2^kFixedBits
+// (bound <= 0 or not finite: 1).
+__device__ __forceinline__ double fixed_scale_for(double bound) {
+    if (!(bound > 0.0) || !isfinite(bound)) return 1.0;
+    return ldexp(1.0, kFixedBits - 1 - ilogb(bound));
+}
+
 __global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -172,11 +195,13 @@ __global__ void k_morton(const double* __restrict__ rcv, int64_t n, const double
 // receiver (perm = -1 marks padding, whose results are discarded).
 __global__ void k_gather_rcv(const double* __restrict__ rcv, int64_t n, int64_t n_pad,
                              const int32_t* __restrict__ order, double* __restrict__ rx, double* __restrict__ ry,
-                             double* __restrict__ rz, double* __restrict__ r2, int32_t* __restrict__ perm) {
+                             double* __restrict__ rz, double* __restrict__ r2, int32_t* __restrict__ perm,
+                             int* __restrict__ status) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n_pad) return;
     int32_t o = order[i < n ? i : n - 1];
     double x = rcv[3 * (int64_t)o], y = rcv[3 * (int64_t)o + 1], z = rcv[3 * (int64_t)o + 2];
+    if (i < n && !(isfinite(x) && isfinite(y) && isfinite(z))) atomicOr(status, kBadReceiver);
     rx[i] = x;
     ry[i] = y;
     rz[i] = z;
@@ -245,14 +270,25 @@ __global__ __launch_bounds__(64) void k_sphere_of_spheres(const Patch* __restric
 // ----------------------------------------------------------------- segments
 // First segment of every source (rays are sorted by source); src_off[n_src]
 // is the end of the table.
+// Also checks the ray CSR (ray_ptr[0] = 0, non-decreasing, ray_ptr[n_rays] =
+// n_segs), the source order and face_ptr[0] = 0.
 __global__ void k_src_ranges(const int64_t* __restrict__ ray_ptr, const int32_t* __restrict__ ray_src,
-                             int64_t n_rays, int32_t n_src, int64_t* __restrict__ src_off) {
+                             int64_t n_rays, int32_t n_src, int64_t n_segs, const int64_t* __restrict__ face_ptr,
+                             int64_t* __restrict__ src_off, int* __restrict__ status) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i > n_rays) return;
+    const int32_t rp = i == 0 ? -1 : ray_src[i - 1], rc = i == n_rays ? n_src : ray_src[i];
+    int bad = 0;
+    if ((i > 0 && (rp < 0 || rp >= n_src)) || rc < rp) bad |= kBadRaySource;
+    const int64_t p = ray_ptr[i];
+    if (i == 0 ? p != 0 : p < ray_ptr[i - 1]) bad |= kBadRayPtr;
+    if (i == n_rays && p != n_segs) bad |= kBadRayPtr;
+    if (i == 0 && face_ptr && face_ptr[0] != 0) bad |= kBadFacePtr;
+    if (bad) atomicOr(status, bad);
     // clamped so that an unsorted or out-of-range table cannot write outside src_off
-    int32_t prev = i == 0 ? -1 : min(max(ray_src[i - 1], -1), n_src);
-    int32_t cur = i == n_rays ? n_src : min(max(ray_src[i], -1), n_src);
-    for (int32_t s = prev + 1; s <= cur; ++s) src_off[s] = ray_ptr[i];
+    int32_t prev = min(max(rp, -1), n_src);
+    int32_t cur = min(max(rc, -1), n_src);
+    for (int32_t s = prev + 1; s <= cur; ++s) src_off[s] = p;
 }
 
 // seg_ray[j] = index (within the pass) of the ray that owns segment j.
@@ -266,24 +302,59 @@ __global__ void k_seg2ray(const int64_t* __restrict__ ray_ptr, int64_t n_rays, i
 
 // Segment records: virtual-source anchoring, arc-length interval and the
 // complex weight w * prod(Gamma) over the faces hit before the segment.
+// Checks the segment's values, its face-history range (inside
+// [face_base, face_end], absolute offsets) and ids, and its ray (status bits); bad
+// entries are skipped, never read out of range.  With bmax, also the largest
+// w * (history length) * prod max(1, |Gamma|) over the pass (a bound on the
+// coefficient derivatives, for the adjoint's exact face sums).
 __global__ void k_records(int64_t n_segs, const double* __restrict__ a, const double* __restrict__ t,
                           const double* __restrict__ s0, const double* __restrict__ lo,
                           const double* __restrict__ hi, const int64_t* __restrict__ face_ptr,
                           int64_t face_base, const int32_t* __restrict__ face_ids, int32_t n_faces,
                           const double* __restrict__ gamma, const double* __restrict__ ray_w,
-                          const int32_t* __restrict__ seg_ray, SegRec* __restrict__ rec) {
+                          const int32_t* __restrict__ seg_ray, int64_t n_rays, int64_t face_end,
+                          SegRec* __restrict__ rec, int* __restrict__ status, unsigned long long* __restrict__ bmax) {
     int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= n_segs) return;
+    int bad = 0;
     double tx = t[3 * j], ty = t[3 * j + 1], tz = t[3 * j + 2];
     double s = s0[j];
-    double ox = a[3 * j] - s * tx, oy = a[3 * j + 1] - s * ty, oz = a[3 * j + 2] - s * tz;
-    double gr = ray_w[seg_ray[j]], gi = 0.0;
-    for (int64_t m = face_ptr[j] - face_base; m < face_ptr[j + 1] - face_base; ++m) {
-        int32_t f = min(max(face_ids[m], 0), n_faces - 1);   // ids are validated on request only
-        double xr = gamma[2 * f], xi = gamma[2 * f + 1];
-        double nr = gr * xr - gi * xi;
-        gi = gr * xi + gi * xr;
-        gr = nr;
+    const double ax = a[3 * j], ay = a[3 * j + 1], az = a[3 * j + 2], l0 = lo[j], l1 = hi[j];
+    const double tn = tx * tx + ty * ty + tz * tz;
+    if (!(isfinite(ax) && isfinite(ay) && isfinite(az) && isfinite(s) && isfinite(l0) && isfinite(l1) &&
+          l0 <= l1 && fabs(tn - 1.0) <= 2e-9))
+        bad |= kBadSegment;
+    double ox = ax - s * tx, oy = ay - s * ty, oz = az - s * tz;
+    const int32_t ray = seg_ray[j];
+    double gr = 0.0, gi = 0.0;
+    if (ray < 0 || ray >= n_rays) {
+        bad |= kBadRayPtr;
+    } else {
+        gr = ray_w[ray];
+        if (!(isfinite(gr) && gr >= 0.0)) bad |= kBadRayWeight;
+    }
+    const int64_t f0 = face_ptr[j], f1 = face_ptr[j + 1];
+    double gmax = 1.0;
+    if (!(face_base <= f0 && f0 <= f1 && f1 <= face_end)) {
+        bad |= kBadFacePtr;
+    } else {
+        for (int64_t m = f0 - face_base; m < f1 - face_base; ++m) {
+            const int32_t f = face_ids[m];
+            if (f < 0 || f >= n_faces) {
+                bad |= kBadFaceId;
+                continue;
+            }
+            double xr = gamma[2 * f], xi = gamma[2 * f + 1];
+            double nr = gr * xr - gi * xi;
+            gi = gr * xi + gi * xr;
+            gr = nr;
+            gmax *= fmax(1.0, hypot(xr, xi));
+        }
+    }
+    if (bad) atomicOr(status, bad);
+    if (bmax) {
+        const double b = (ray >= 0 && ray < n_rays ? fabs(ray_w[ray]) : 0.0) * (double)(f1 - f0) * gmax;
+        if (b > 0.0 && isfinite(b)) atomicMax(bmax, (unsigned long long)__double_as_longlong(b));
     }
     SegRec r;
     r.m2ox = -2.0 * ox;
@@ -294,8 +365,8 @@ __global__ void k_records(int64_t n_segs, const double* __restrict__ a, const do
     r.ty = ty;
     r.tz = tz;
     r.mot = -(ox * tx + oy * ty + oz * tz);
-    r.slo = s + lo[j];
-    r.shi = s + hi[j];
+    r.slo = s + l0;
+    r.shi = s + l1;
     r.wgr = gr;
     r.wgi = gi;
     rec[j] = r;
@@ -1366,8 +1437,9 @@ __device__ __forceinline__ bool adj_eval(const TileRec& S, const JobConst& J, do
 // the same LDS-staged segment tiles.  Per receiver (lane): dL/dR accumulates
 // in FP64 and is written as the unit's partial (k_reduce_adjoint adds a
 // patch's units in order); per segment: the sum over lanes of lambda * B
-// (wave reduction) goes to Sseg with FP64 atomics; per job: dL/deps from a
-// wave reduction and one atomic per unit.
+// (wave reduction) goes to Sseg as an exact fixed-point sum (scale
+// fixed_scales[0]); per unit: dL/deps from a wave reduction, reduced per job
+// in unit order by k_reduce_eps.  Every output is bitwise repeatable.
 template <int MODE>
 __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __restrict__ jobs,
                                                 const Work* __restrict__ work, const int32_t* __restrict__ n_work_p,
@@ -1377,8 +1449,9 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
                                                 const double* __restrict__ rz, const double* __restrict__ r2,
                                                 const int32_t* __restrict__ perm, int64_t n_rcv,
                                                 const double* __restrict__ lambda, double* __restrict__ partial,
-                                                const int32_t* __restrict__ seg_perm,
-                                                double* __restrict__ Sseg, double* __restrict__ d_eps) {
+                                                const int32_t* __restrict__ seg_perm, Fixed* __restrict__ Sseg,
+                                                const double* __restrict__ fixed_scales,
+                                                double* __restrict__ eps_partial) {
     __shared__ __align__(16) TileRec tile[kPairThreads / kWave][kWave];
     __shared__ int32_t tile_idx[kPairThreads / kWave][kWave];
     const int lane = threadIdx.x & (kWave - 1);
@@ -1386,6 +1459,7 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
     int32_t* const my_idx = tile_idx[threadIdx.x / kWave];
     using ST = typename Beam<MODE & 3>::T;                // beam-term precision
     const int n_work = __builtin_amdgcn_readfirstlane(*n_work_p);
+    const double sscale = fixed_scales[0];
     for (;;) {
         branch_barrier();
         const int w = pop_item(ctr);
@@ -1423,8 +1497,8 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
                     Si = wave_sum_last(Si);
                     if (lane == kLastLane) {
                         const int64_t j = my_idx[k];
-                        atomicAdd(&Sseg[2 * j], J.scale * (double)Sr);
-                        atomicAdd(&Sseg[2 * j + 1], J.scale * (double)Si);
+                        fixed_add(&Sseg[2 * j], J.scale * (double)Sr, sscale);
+                        fixed_add(&Sseg[2 * j + 1], J.scale * (double)Si, sscale);
                     }
                 }
             }
@@ -1434,7 +1508,7 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
         p[1] = fma(acc.g, Y, fma(0.5, acc.wy, acc.vy));
         p[2] = fma(acc.g, Z, fma(0.5, acc.wz, acc.vz));
         const double dE = wave_sum_last(acc.e);
-        if (lane == kLastLane) atomicAdd(&d_eps[job], J.scale * dE);
+        if (lane == kLastLane) eps_partial[w] = J.scale * dE;
     }
 }
 
@@ -1478,24 +1552,29 @@ __global__ void k_sum_jobs(const double* __restrict__ dR_job, int32_t n_jobs, in
 
 // Z_f += d(prod Gamma_j)/dGamma_f * w_j * S_j for every distinct face f in
 // segment j's history (product of the other factors, summed over the
-// occurrences of f).  One thread per segment; the wave walks history
-// positions in step and adds the contributions of lanes that hit the same
-// face with one wave reduction and one atomic per distinct face (most
-// segments of a scene share a few faces, the ground above all).
+// occurrences of f), as an exact fixed-point sum (scale fixed_scales[1]).
+// One thread per segment; the wave walks history positions in step and adds
+// the contributions of lanes that hit the same face with one wave reduction
+// and one pair of integer atomics per distinct face (most segments of a scene
+// share a few faces, the ground above all).  Histories were checked by
+// k_records; ids outside [0, n_faces) are skipped.
 __global__ void k_face_scatter(int64_t n_segs, const int64_t* __restrict__ face_ptr, int64_t face_base,
                                const int32_t* __restrict__ face_ids, int32_t n_faces, const double* __restrict__ gamma,
                                const double* __restrict__ ray_w, const int32_t* __restrict__ seg_ray,
-                               const double* __restrict__ Sseg, double* __restrict__ Zf) {
+                               const Fixed* __restrict__ Sseg, const double* __restrict__ fixed_scales,
+                               Fixed* __restrict__ Zf) {
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
+    const double zscale = fixed_scales[1], sinv = fixed_scales[2];
     double sr = 0.0, si = 0.0, w = 0.0;
     int64_t b = 0, e = 0;
     if (j < n_segs) {
-        sr = Sseg[2 * j];
-        si = Sseg[2 * j + 1];
-        if (sr != 0.0 || si != 0.0) {
-            b = face_ptr[j] - face_base;
-            e = face_ptr[j + 1] - face_base;
+        sr = fixed_value(Sseg[2 * j], sinv);
+        si = fixed_value(Sseg[2 * j + 1], sinv);
+        const int64_t f0 = face_ptr[j] - face_base, f1 = face_ptr[j + 1] - face_base;
+        if ((sr != 0.0 || si != 0.0) && f0 >= 0 && f1 >= f0) {
+            b = f0;
+            e = f1;
             w = ray_w[seg_ray[j]];
         }
     }
@@ -1507,7 +1586,7 @@ __global__ void k_face_scatter(int64_t n_segs, const int64_t* __restrict__ face_
         double zr = 0.0, zi = 0.0;
         if (l < len) {
             f = face_ids[b + l];
-            bool skip = f < 0 || f >= n_faces;   // ids are validated on request only
+            bool skip = f < 0 || f >= n_faces;
             for (int64_t m = b; m < b + l; ++m) skip |= face_ids[m] == f;   // counted at its first occurrence
             if (skip) {
                 f = -1;
@@ -1517,8 +1596,8 @@ __global__ void k_face_scatter(int64_t n_segs, const int64_t* __restrict__ face_
                     if (face_ids[l2] != f) continue;
                     double pr = 1.0, pi = 0.0;
                     for (int64_t m = b; m < e; ++m) {
-                        if (m == l2) continue;
-                        const int32_t g = min(max(face_ids[m], 0), n_faces - 1);
+                        const int32_t g = face_ids[m];
+                        if (m == l2 || g < 0 || g >= n_faces) continue;
                         const double xr = gamma[2 * g], xi = gamma[2 * g + 1];
                         const double nr = pr * xr - pi * xi;
                         pi = pr * xi + pi * xr;
@@ -1538,12 +1617,87 @@ __global__ void k_face_scatter(int64_t n_segs, const int64_t* __restrict__ face_
             const bool mine = f == f0;
             const double tr = wave_sum_last(mine ? zr : 0.0), ti = wave_sum_last(mine ? zi : 0.0);
             if (lane == kLastLane) {
-                atomicAdd(&Zf[2 * (int64_t)f0], tr);
-                atomicAdd(&Zf[2 * (int64_t)f0 + 1], ti);
+                fixed_add(&Zf[2 * (int64_t)f0], tr, zscale);
+                fixed_add(&Zf[2 * (int64_t)f0 + 1], ti, zscale);
             }
             pending &= ~__ballot(mine);
         }
     }
+}
+
+// Sum over the receivers of |Re lambda| + |Im lambda| per job (a bound on
+// sum |lambda|), one workgroup per job in a fixed order; also flags
+// non-finite lambda.
+__global__ __launch_bounds__(256) void k_lambda_l1(const double* __restrict__ lambda, int64_t n_rcv,
+                                                   double* __restrict__ l1, int* __restrict__ status) {
+    __shared__ double sm[256];
+    const int job = blockIdx.x;
+    const double* lj = lambda + 2 * (int64_t)job * n_rcv;
+    double acc = 0.0;
+    bool ok = true;
+    for (int64_t r = threadIdx.x; r < n_rcv; r += 256) {
+        const double x = lj[2 * r], y = lj[2 * r + 1];
+        ok &= isfinite(x) && isfinite(y);
+        acc += fabs(x) + fabs(y);
+    }
+    if (!ok) atomicOr(status, kBadLambda);
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) l1[job] = sm[0];
+}
+
+// Scales of the adjoint's exact sums.  Segment sums: every contribution is
+// scale_job * lambda * B with |B| <= 1/eps (isotropic; scale = k eps/(8 pi^2))
+// or <= 1 (anisotropic; scale = k/(8 pi^2)), so sum_job k/(8 pi^2) sum|lambda|,
+// doubled against FP32 rounding, bounds every partial sum.  Face sums: at most
+// n_segs terms, each |w d(prod Gamma)/dGamma_f S_j| <= bmax * bound_S.
+// out = {2^K_S, 2^K_Z, 2^-K_S, 2^-K_Z}.
+__global__ void k_fixed_scales(const JobConst* __restrict__ jobs, const double* __restrict__ l1, int32_t n_jobs,
+                               int64_t n_segs, const unsigned long long* __restrict__ bmax,
+                               double* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double bs = 0.0;
+    for (int32_t j = 0; j < n_jobs; ++j) bs += jobs[j].k * (1.0 / (8.0 * 3.14159265358979323846 * 3.14159265358979323846)) * l1[j];
+    bs *= 2.0;
+    const double bz = bs * (double)n_segs * __longlong_as_double((long long)*bmax) * 2.0;
+    out[0] = fixed_scale_for(bs);
+    out[1] = fixed_scale_for(bz);
+    out[2] = 1.0 / out[0];
+    out[3] = 1.0 / out[1];
+}
+
+// d_eps[job] += sum over the job's work units of eps_partial, in (patch, unit)
+// order: one workgroup per job, a strided pass then a fixed tree.
+__global__ __launch_bounds__(256) void k_reduce_eps(const int32_t* __restrict__ item_wbase,
+                                                    const int32_t* __restrict__ item_wcount, int32_t n_patch,
+                                                    const double* __restrict__ eps_partial, double* __restrict__ d_eps) {
+    __shared__ double sm[256];
+    const int job = blockIdx.x;
+    double acc = 0.0;
+    for (int p = threadIdx.x; p < n_patch; p += 256) {
+        const int item = job * n_patch + p;
+        const int b = item_wbase[item], c = item_wcount[item];
+        for (int u = 0; u < c; ++u) acc += eps_partial[b + u];
+    }
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d_eps[job] += sm[0];
+}
+
+// Zf (FP64) += the pass's exact face sums.
+__global__ void k_fixed_flush(const Fixed* __restrict__ acc, int64_t n, const double* __restrict__ fixed_scales,
+                              double* __restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] += fixed_value(acc[i], fixed_scales[3]);
 }
 
 // d_gamma = (Re Z, -Im Z).
@@ -1552,21 +1706,6 @@ __global__ void k_dgamma(const double* __restrict__ Zf, int32_t n_faces, double*
     if (i >= n_faces) return;
     d_gamma[2 * i] = Zf[2 * i];
     d_gamma[2 * i + 1] = -Zf[2 * i + 1];
-}
-
-// Device-side table validation: writes 1 into *bad on the first problem.
-__global__ void k_validate(int64_t n_segs, const double* __restrict__ t, const double* __restrict__ lo,
-                           const double* __restrict__ hi, const int64_t* __restrict__ face_ptr,
-                           int64_t face_base, const int32_t* __restrict__ face_ids, int32_t n_faces,
-                           int* __restrict__ bad) {
-    int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (j >= n_segs) return;
-    double tn = t[3 * j] * t[3 * j] + t[3 * j + 1] * t[3 * j + 1] + t[3 * j + 2] * t[3 * j + 2];
-    bool ok = fabs(tn - 1.0) <= 2e-9 && lo[j] <= hi[j] && isfinite(lo[j]) && isfinite(hi[j]) &&
-              face_ptr[j + 1] >= face_ptr[j];
-    for (int64_t m = face_ptr[j] - face_base; ok && m < face_ptr[j + 1] - face_base; ++m)
-        ok = face_ids[m] >= 0 && face_ids[m] < n_faces;
-    if (!ok) atomicOr(bad, 1);
 }
 
 // Explicit instantiations used by the host planner.
@@ -1606,7 +1745,7 @@ GBS_INST_PAIRS_MODE(14)
     template __global__ void k_adjoint<M>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,       \
                                           const int32_t*, const SegRec*, const double*, const double*,            \
                                           const double*, const double*, const int32_t*, int64_t, const double*,   \
-                                          double*, const int32_t*, double*, double*);
+                                          double*, const int32_t*, Fixed*, const double*, double*);
 GBS_INST_ADJ(0)
 GBS_INST_ADJ(1)
 GBS_INST_ADJ(4)

@@ -147,8 +147,8 @@ def _params(c, gate, mode, flags, chunk_segs, rcv_per_lane, work_chunk, device, 
 class _Call:
     """Marshalled arguments of one forward/backward call."""
 
-    def __init__(self, table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, validate,
-                 count_active, time_kernels=False, work_chunk=0, alpha=None, eps_e2=None):
+    def __init__(self, table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, count_active,
+                 time_kernels=False, work_chunk=0, alpha=None, eps_e2=None):
         if not isinstance(table, Table):
             raise TypeError("table must be a gbs.Table")
         dev = table.device
@@ -161,7 +161,7 @@ class _Call:
         self.gamma = _gamma_ri(gamma, dev)
         if self.gamma.shape[0] != table.n_faces:
             raise ValueError("gamma must hold one coefficient per face")
-        flags = (_lib.FLAG_TABLE_HOST if table.on_host else 0) | (_lib.FLAG_VALIDATE if validate else 0) | \
+        flags = (_lib.FLAG_TABLE_HOST if table.on_host else 0) | \
             (_lib.FLAG_COUNT_ACTIVE if count_active else 0) | (_lib.FLAG_TIME_KERNELS if time_kernels else 0)
         self.alpha = None
         if alpha is not None:
@@ -187,7 +187,7 @@ class _Call:
 
 
 def forward(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix", chunk_segs=0,
-            rcv_per_lane=0, work_chunk=0, validate=False, count_active=False, time_kernels=False, want_tl=True,
+            rcv_per_lane=0, work_chunk=0, count_active=False, time_kernels=False, want_tl=True,
             alpha=None, eps_e2=None):
     """Beam summation.  Returns (P complex128 [n_src, n_freq, n_rcv],
     TL float64 of the same shape or None).  count_active / time_kernels fill
@@ -197,7 +197,7 @@ def forward(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="m
     the one along the horizontal frame vector e1), or None."""
     ctx = context(table.device)
     ctx.bind_stream()
-    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, validate, count_active,
+    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, count_active,
                  time_kernels, work_chunk, alpha, eps_e2)
     P = torch.empty(call.shape + (2,), dtype=torch.float64, device=table.device)
     TL = torch.empty(call.shape, dtype=torch.float64, device=table.device) if want_tl else None
@@ -207,12 +207,12 @@ def forward(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="m
 
 
 def backward(table: Table, rcv, freqs, eps, gamma, lam, *, c=343.0, gate=9.21, mode="mix", chunk_segs=0,
-             validate=False, alpha=None, time_kernels=False):
+             alpha=None, time_kernels=False):
     """Adjoint for dL = Re sum lam * dP.  Returns (d_gamma [n_faces, 2] as
     (dL/dRe, dL/dIm), d_rcv [n_rcv, 3], d_eps [n_src, n_freq])."""
     ctx = context(table.device)
     ctx.bind_stream()
-    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, 0, validate, False, time_kernels,
+    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, 0, False, time_kernels,
                  alpha=alpha)
     lam_t = lam if isinstance(lam, torch.Tensor) else torch.as_tensor(np.asarray(lam))
     lam_t = lam_t.to(device=table.device, dtype=torch.complex128).reshape(call.shape).contiguous()
@@ -300,7 +300,7 @@ def autotune(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="
     a new one is stored.  Returns {"rcv_per_lane": .., "work_chunk": ..}."""
     ctx = context(table.device)
     ctx.bind_stream()
-    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, 0, 0, False, False, alpha=alpha, eps_e2=eps_e2)
+    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, 0, 0, False, alpha=alpha, eps_e2=eps_e2)
     key = _tune_key(table, call, mode)
     store = {}
     if cache is not None and os.path.exists(cache):
@@ -334,7 +334,7 @@ def impulse_response(table: Table, rcv, df, bin0, n_bins, eps, gamma, *, n_fft, 
     ctx.bind_stream()
     n_t = n_fft if n_t is None else int(n_t)
     freqs = (int(bin0) + np.arange(int(n_bins))) * float(df)
-    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, 0, False, False, alpha=alpha)
+    call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, 0, False, alpha=alpha)
     win = None if window is None else _as_tensor(window, torch.float64, table.device).reshape(-1)
     if win is not None and win.numel() != int(n_bins):
         raise ValueError("one window value per bin")
@@ -373,7 +373,7 @@ class Graph:
                  chunk_segs=0, alpha=None, eps_e2=None):
         self.ctx = context(table.device)
         self.stream = torch.cuda.Stream(device=table.device)
-        self.call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, False, False,
+        self.call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, False,
                           alpha=alpha, eps_e2=eps_e2)
         self.gamma = self.call.gamma          # [n_faces, 2] device buffer read at every replay
         self.P = torch.empty(self.call.shape + (2,), dtype=torch.float64, device=table.device)
@@ -429,6 +429,8 @@ class GBSFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, gamma, rcv, eps, table, freqs, opts):
         opts = dict(opts or {})
+        if opts.get("eps_e2") is not None:
+            raise NotImplementedError("GBSFunction differentiates isotropic beams only (no eps_e2)")
         P, TL = forward(table, rcv.detach(), freqs, eps.detach(), gamma.detach(), **opts)
         ctx.save_for_backward(gamma, rcv, eps, P)
         ctx.table, ctx.freqs, ctx.opts = table, freqs, opts

@@ -60,6 +60,22 @@ def test_chunked_adjoint_matches(panel_case):
     assert rel_err(dG, rG) <= 1e-9 and rel_err(dR, rR) <= 1e-9 and rel_err(dE, rE) <= 1e-9
 
 
+@pytest.mark.parametrize("mode", ["f64", "mix"])
+def test_adjoint_bitwise_repeatable(panel_case, mode):
+    """Every adjoint output is bitwise equal over repeated calls (fixed-order
+    receiver and beam-parameter sums, exact fixed-point segment and face
+    sums), with one pass and with several."""
+    sc, lam, (rG, rR, rE) = panel_case
+    for chunk in (0, 4000):
+        print(f"case adjoint repeat mode={mode} chunk={chunk}", flush=True)
+        first = gpu_backward(sc, lam, mode, chunk_segs=chunk)
+        for _ in range(2):
+            again = gpu_backward(sc, lam, mode, chunk_segs=chunk)
+            for x, y in zip(first, again):
+                assert np.array_equal(x, y)
+        assert rel_err(first[0], rG) <= (1e-9 if mode == "f64" else 1e-3)
+
+
 def test_gradcheck_through_autograd():
     """torch.autograd.gradcheck of TL with respect to the complex coefficients,
     the receivers and eps (finite differences on the GPU F64 path)."""

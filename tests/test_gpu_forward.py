@@ -201,12 +201,6 @@ def test_invalid_arguments_rejected():
     with pytest.raises(_lib.GbsError) as e:
         gbs.forward(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, rcv_per_lane=3)
     assert e.value.code == _lib.GBS_E_INVALID
-    bad = sc.table
-    bad.seg_t = bad.seg_t * 1.01
-    tb = gbs.Table(bad, device="cuda")
-    with pytest.raises(_lib.GbsError) as e:
-        gbs.forward(tb, sc.rcv, sc.freqs, sc.eps, sc.gamma, validate=True)
-    assert e.value.code == _lib.GBS_E_INVALID
 
 
 @pytest.fixture(scope="module")

@@ -1,14 +1,17 @@
-"""Full-size city parity: the 10 x 10 city with 1,000,000 rays (up to ten
-reflections, 1 kHz) over 1024 x 1024 receivers, in the launch shape the
-benchmark uses.  The oracle cannot finish the dense sum at this size, so 256
-seeded receivers are checked against it, and the full output against
-properties that hold at any size."""
+"""Full-size city parity, in the launch shapes the benchmark uses: the 10 x 10
+city with 1,000,000 rays (up to ten reflections, 1 kHz) over 1024 x 1024
+receivers; the batched city (16 sources, 4 bands, 15.7 M segments) streamed
+from host memory; the differentiable 5 x 5 paneled city (200,000 rays, 501
+faces) forward and adjoint.  The oracle cannot finish the dense sums at these
+sizes, so 256 seeded receivers are checked against it, and the full outputs
+against properties that hold at any size."""
 import numpy as np
 import pytest
 import torch
 
+import oracle
 import paper_2501_13382_amd as gbs
-from scenes import city_10x10, receiver_subsample
+from scenes import city_10x10, city_5x5_panels, city_batched, receiver_subsample
 
 from tests.gpu_util import assert_within, compare, reference
 
@@ -42,3 +45,87 @@ def test_full_size_city_sampled(city1m, mode):
     assert np.allclose(TL[live], -20 * np.log10(np.abs(P[live])), rtol=0, atol=1e-9)
     assert st_all["dense_pairs"] == sc.dense_pairs
     assert 0 < st_all["listed_pairs"] < sc.dense_pairs
+
+
+def rel_err(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def batched_full():
+    """The batched city at full size: 16 sources at U(2, 30) m, U(10k, 500k)
+    rays each (4.89 M rays, 15.7 M segments), four bands, 1024 x 1024
+    receivers; 256 seeded receivers for the oracle."""
+    print("case full-size batched city: tracing 16 sources", flush=True)
+    sc = city_batched(grid=1024)
+    idx = receiver_subsample(len(sc.rcv), n=256, seed=11)
+    print("case full-size batched city: oracle on 256 receivers", flush=True)
+    return sc, idx, reference(sc, rcv=sc.rcv[idx])
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("mode", ["mix", "f64"])
+def test_full_size_batched_city_streamed(batched_full, mode):
+    """All 64 (source, band) jobs in one persistent launch per pass, the table
+    streamed from pinned host memory in passes of at most 4 M segments."""
+    sc, idx, (P_ref, TL_ref, ab) = batched_full
+    print(f"case full-size batched city streamed mode={mode}", flush=True)
+    t = gbs.Table(sc.table, device="cuda", on_host=True)
+    P, TL = gbs.forward(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, c=sc.c, gate=sc.gate, mode=mode,
+                        chunk_segs=4_000_000)
+    torch.cuda.synchronize()
+    st_all = gbs.stats()
+    assert st_all["n_chunks"] >= 4
+    P, TL = P.cpu().numpy(), TL.cpu().numpy()
+    st = compare(P[:, :, idx], TL[:, :, idx], P_ref, TL_ref, ab)
+    print(st, st_all, flush=True)
+    assert_within(st, mode)
+    assert np.all(np.isfinite(P))
+    assert st_all["dense_pairs"] == sc.dense_pairs
+
+
+@pytest.fixture(scope="module")
+def diff_city_full():
+    """The differentiable 5 x 5 paneled city at full size: 501 faces with
+    complex coefficients, 200,000 rays (<= 8 reflections), 1 kHz, 256 x 256
+    receivers; 256 seeded receivers carry the adjoint weights."""
+    print("case full-size differentiable city: tracing", flush=True)
+    sc = city_5x5_panels(n_rays=200_000, grid=256)
+    idx = receiver_subsample(len(sc.rcv), n=256, seed=12)
+    rng = np.random.default_rng(13)
+    lam_s = rng.standard_normal((1, len(idx))) + 1j * rng.standard_normal((1, len(idx)))
+    print("case full-size differentiable city: oracle forward and adjoint on 256 receivers", flush=True)
+    fwd = reference(sc, rcv=sc.rcv[idx])
+    adj = oracle.backward(sc.table, sc.gamma, sc.rcv[idx], sc.freqs, sc.eps, lam_s, c=sc.c, gate=sc.gate)
+    return sc, idx, lam_s, fwd, adj
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("mode", ["f64", "mix"])
+def test_full_size_differentiable_city(diff_city_full, mode):
+    """Forward at the sampled receivers, and the adjoint with lambda non-zero
+    on the sampled receivers only: d_gamma and d_eps against the oracle's
+    hand adjoint for the same lambda, d_rcv on the sampled receivers, and
+    exactly zero on every other receiver."""
+    sc, idx, lam_s, (P_ref, TL_ref, ab), (rG, rR, rE) = diff_city_full
+    print(f"case full-size differentiable city mode={mode}", flush=True)
+    t = gbs.Table(sc.table, device="cuda")
+    P, TL = gbs.forward(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, c=sc.c, gate=sc.gate, mode=mode)
+    torch.cuda.synchronize()
+    st = compare(P.cpu().numpy()[:, :, idx], TL.cpu().numpy()[:, :, idx], P_ref, TL_ref, ab)
+    print(st, flush=True)
+    assert_within(st, mode)
+    lam = np.zeros((1, len(sc.rcv)), np.complex128)
+    lam[0, idx] = lam_s[0]
+    dG, dR, dE = gbs.backward(t, sc.rcv, sc.freqs, sc.eps, sc.gamma, lam, c=sc.c, gate=sc.gate, mode=mode)
+    torch.cuda.synchronize()
+    dG, dR, dE = dG.cpu().numpy(), dR.cpu().numpy(), dE.cpu().numpy().reshape(-1)
+    tol = 1e-9 if mode == "f64" else 1e-3
+    errs = (rel_err(dG, rG), rel_err(dR[idx], rR), rel_err(dE, rE))
+    print("adjoint rel errors (d_gamma, d_rcv, d_eps)", errs, flush=True)
+    assert max(errs) <= tol
+    rest = np.ones(len(sc.rcv), bool)
+    rest[idx] = False
+    assert np.all(dR[rest] == 0.0)
+    assert len(np.unique(sc.table.face_ids)) > 250

@@ -42,3 +42,19 @@ def test_missing_library_raises():
         "    print('computed')\n" % ROOT)
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert "raised" in r.stdout and "not built" in r.stdout, r.stdout + r.stderr
+
+
+def test_autograd_refuses_anisotropic_beams():
+    """GBSFunction differentiates isotropic beams only: with eps_e2 in its
+    options it raises before any work instead of returning the isotropic
+    adjoint's gradient for an anisotropic forward."""
+    import pytest
+    import torch
+
+    sys.path.insert(0, ROOT)
+    import paper_2501_13382_amd as gbs
+    g = torch.zeros(1, dtype=torch.complex128, requires_grad=True)
+    r = torch.zeros((1, 3), dtype=torch.float64, requires_grad=True)
+    e = torch.ones((1, 1), dtype=torch.float64, requires_grad=True)
+    with pytest.raises(NotImplementedError):
+        gbs.GBSFunction.apply(g, r, e, None, torch.ones(1, dtype=torch.float64), {"eps_e2": torch.ones(1)})
