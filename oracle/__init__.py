@@ -44,10 +44,12 @@ def _load():
         common = [i32, i64, P, P, P, i64, P, P, P, P, P, P, P, i32, P, i64, P, i32, P, P, P, f64, f64]
         lib.gbso_forward.argtypes = common + [i32, i32, P, P, P, P]
         lib.gbso_forward.restype = ctypes.c_int
-        lib.gbso_forward_aniso.argtypes = common + [P, P, i32, P, P, P]
+        lib.gbso_forward_aniso.argtypes = common + [P, P, i32, i32, P, P, P, P]
         lib.gbso_forward_aniso.restype = ctypes.c_int
         lib.gbso_backward.argtypes = common + [P, i32, P, P, P, P]
         lib.gbso_backward.restype = ctypes.c_int
+        lib.gbso_backward_aniso.argtypes = common + [P, P, P, i32, P, P, P, P, P]
+        lib.gbso_backward_aniso.restype = ctypes.c_int
         lib.gbso_air_absorption_db.argtypes = [f64, f64, f64, f64]
         lib.gbso_air_absorption_db.restype = f64
         _lib = lib
@@ -115,13 +117,12 @@ def forward(table, gamma, rcv, freqs, eps, c=343.0, gate=9.21, n_threads=1, mask
     if (eps_e2 is None) != (seg_e1 is None):
         raise ValueError("eps_e2 and seg_e1 go together")
     if eps_e2 is not None:
-        if mask_mode:
-            raise ValueError("anisotropic beams take no mask")
         e2 = np.ascontiguousarray(eps_e2, np.float64).reshape(-1)
         f1 = np.ascontiguousarray(seg_e1, np.float64).reshape(-1, 3)
         if e2.shape[0] != n_jobs or f1.shape[0] != table.n_segs:
             raise ValueError("eps_e2 needs one value per job and seg_e1 one frame vector per segment")
-        rc = _load().gbso_forward_aniso(*args, _ptr(e2), _ptr(f1), int(n_threads), _ptr(P), _ptr(TL), _ptr(absum))
+        rc = _load().gbso_forward_aniso(*args, _ptr(e2), _ptr(f1), int(n_threads), int(mask_mode), _ptr(mask),
+                                        _ptr(P), _ptr(TL), _ptr(absum))
     else:
         rc = _load().gbso_forward(*args, int(n_threads), int(mask_mode), _ptr(mask), _ptr(P), _ptr(TL), _ptr(absum))
     if rc != 0:
@@ -131,11 +132,13 @@ def forward(table, gamma, rcv, freqs, eps, c=343.0, gate=9.21, n_threads=1, mask
     return P[..., 0] + 1j * P[..., 1], TL
 
 
-def backward(table, gamma, rcv, freqs, eps, lam, c=343.0, gate=9.21, mask_mode=0, mask=None, alpha=None):
+def backward(table, gamma, rcv, freqs, eps, lam, c=343.0, gate=9.21, mask_mode=0, mask=None, alpha=None,
+             eps_e2=None, seg_e1=None):
     """Hand adjoint for dL = Re sum lam * dP.
 
     Returns (d_gamma [n_faces, 2] = (dL/dRe, dL/dIm), d_rcv [n_rcv, 3],
-    d_eps [n_jobs])."""
+    d_eps [n_jobs]); with anisotropic beams (eps_e2 and seg_e1 as for
+    forward) also d_eps_e2 [n_jobs]."""
     args, arrs = _table_args(table, gamma, rcv, freqs, eps, c, gate, alpha)
     n_jobs = table.n_src * arrs["freqs"].shape[0]
     n_rcv = arrs["rcv"].shape[0]
@@ -144,6 +147,19 @@ def backward(table, gamma, rcv, freqs, eps, lam, c=343.0, gate=9.21, mask_mode=0
     d_gamma = np.zeros((table.n_faces, 2), np.float64)
     d_rcv = np.zeros((n_rcv, 3), np.float64)
     d_eps = np.zeros(n_jobs, np.float64)
+    if (eps_e2 is None) != (seg_e1 is None):
+        raise ValueError("eps_e2 and seg_e1 go together")
+    if eps_e2 is not None:
+        e2 = np.ascontiguousarray(eps_e2, np.float64).reshape(-1)
+        f1 = np.ascontiguousarray(seg_e1, np.float64).reshape(-1, 3)
+        if e2.shape[0] != n_jobs or f1.shape[0] != table.n_segs:
+            raise ValueError("eps_e2 needs one value per job and seg_e1 one frame vector per segment")
+        d_eps2 = np.zeros(n_jobs, np.float64)
+        rc = _load().gbso_backward_aniso(*args, _ptr(e2), _ptr(f1), _ptr(lam_ri), int(mask_mode), _ptr(mask),
+                                         _ptr(d_gamma), _ptr(d_rcv), _ptr(d_eps), _ptr(d_eps2))
+        if rc != 0:
+            raise RuntimeError(f"gbso_backward_aniso failed ({rc})")
+        return d_gamma, d_rcv, d_eps, d_eps2
     rc = _load().gbso_backward(*args, _ptr(lam_ri), int(mask_mode), _ptr(mask), _ptr(d_gamma), _ptr(d_rcv),
                                _ptr(d_eps))
     if rc != 0:

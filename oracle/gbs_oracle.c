@@ -212,16 +212,30 @@ int gbso_forward(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const do
  * beam parameter along e1, eps2 = eps_e2[job] along e2; with eps1 = eps2 the
  * beam is the isotropic one of gbso_forward.  seg_e1[3 j..] is e1 of segment j.
  */
+/* Ray-centred coordinates of a pair for anisotropic beams: the offsets n1, n2
+ * of R along e1 and e2 = t x e1 (v = R - a from pair_geometry). */
+static void frame_offsets(const pair_geom* g, const double* t, const double* f1, double* n1, double* n2,
+                          double f2[3]) {
+    f2[0] = t[1] * f1[2] - t[2] * f1[1];
+    f2[1] = t[2] * f1[0] - t[0] * f1[2];
+    f2[2] = t[0] * f1[1] - t[1] * f1[0];
+    *n1 = g->v[0] * f1[0] + g->v[1] * f1[1] + g->v[2] * f1[2];
+    *n2 = g->v[0] * f2[0] + g->v[1] * f2[1] + g->v[2] * f2[2];
+}
+
+/* mask_mode as for gbso_forward (0: gate; 1: gate and record; 2: recorded set). */
 int gbso_forward_aniso(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const double* ray_w,
                        const int32_t* ray_src, int64_t n_segs, const double* seg_a, const double* seg_t,
                        const double* seg_s0, const double* seg_lo, const double* seg_hi, const int64_t* face_ptr,
                        const int32_t* face_ids, int32_t n_faces, const double* gamma, int64_t n_rcv,
                        const double* rcv, int32_t n_freq, const double* freqs, const double* eps,
                        const double* alpha, double c, double gate_G, const double* eps_e2, const double* seg_e1,
-                       int32_t n_threads, double* P_out, double* TL_out, double* absum_out) {
+                       int32_t n_threads, int32_t mask_mode, uint8_t* mask, double* P_out, double* TL_out,
+                       double* absum_out) {
     (void)n_faces;
     if (n_src < 0 || n_rays < 0 || n_segs < 0 || n_rcv < 0 || n_freq < 0 || c <= 0) return -1;
     if (eps_e2 == NULL || (n_segs > 0 && seg_e1 == NULL)) return -1;
+    if (mask_mode != 0 && mask == NULL) return -1;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #else
@@ -245,16 +259,16 @@ int gbso_forward_aniso(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, co
                     for (int64_t j = ray_ptr[i]; j < ray_ptr[i + 1]; ++j) {
                         pair_geom g;
                         const double* t = seg_t + 3 * j;
-                        const double* f1 = seg_e1 + 3 * j;
-                        if (!pair_geometry(R, seg_a + 3 * j, t, seg_s0[j], seg_lo[j], seg_hi[j], &g)) continue;
-                        const double f2[3] = {t[1] * f1[2] - t[2] * f1[1], t[2] * f1[0] - t[0] * f1[2],
-                                              t[0] * f1[1] - t[1] * f1[0]};
-                        const double n1 = g.v[0] * f1[0] + g.v[1] * f1[1] + g.v[2] * f1[2];
-                        const double n2 = g.v[0] * f2[0] + g.v[1] * f2[1] + g.v[2] * f2[2];
+                        const int inside = pair_geometry(R, seg_a + 3 * j, t, seg_s0[j], seg_lo[j], seg_hi[j], &g);
+                        double n1, n2, f2[3];
+                        frame_offsets(&g, t, seg_e1 + 3 * j, &n1, &n2, f2);
                         const cplx q01 = -I * e1, q02 = -I * e2;
                         const cplx q1 = q01 + g.s, q2 = q02 + g.s;
                         const cplx E = I * omega * (g.s / c + 0.5 * p * (n1 * n1 / q1 + n2 * n2 / q2));
-                        if (!(creal(E) >= -gate_G)) continue;
+                        int active = inside && creal(E) >= -gate_G;
+                        if (mask_mode == 1) mask[(job * n_rcv + r) * n_segs + j] = (uint8_t)active;
+                        if (mask_mode == 2) active = mask[(job * n_rcv + r) * n_segs + j];
+                        if (!active) continue;
                         const cplx amp = csqrt(q01 / q1) * csqrt(q02 / q2);
                         const cplx u = weight * face_product(face_ptr, face_ids, gamma, j) * amp * cexp(E) *
                                        exp(-al * g.s);
@@ -365,6 +379,95 @@ int gbso_backward(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const d
 }
 
 /*
+ * Hand-derived adjoint for anisotropic beams (the field of gbso_forward_aniso),
+ * dL = Re sum lambda dP.  With q_m = s - i eps_m, n_m = (R - a).e_m and the
+ * amplitude sqrt(q01/q1) sqrt(q02/q2):
+ *
+ *   d ln u / dR    = t (ik - 1/(2 q1) - 1/(2 q2) - (ik/2)(n1^2/q1^2 + n2^2/q2^2)
+ *                       - alpha) + (ik n1/q1) e1 + (ik n2/q2) e2
+ *                    (ds/dR = t, dn_m/dR = e_m, d(1/q_m)/ds = -1/q_m^2,
+ *                    d ln sqrt(q0m/qm)/ds = -1/(2 q_m))
+ *   d ln u / deps_m = (1/eps_m + i/q_m)/2 - (k/2) n_m^2/q_m^2
+ *                    (dq0m/deps_m = dq_m/deps_m = -i)
+ *   dP / dGamma_f  as for isotropic beams (u without the coefficient product).
+ *
+ * With eps_1 = eps_2 = eps the two beam-parameter derivatives add up to the
+ * isotropic d ln u/deps.  Outputs as gbso_backward, plus d_eps_e2[job].
+ */
+int gbso_backward_aniso(int32_t n_src, int64_t n_rays, const int64_t* ray_ptr, const double* ray_w,
+                        const int32_t* ray_src, int64_t n_segs, const double* seg_a, const double* seg_t,
+                        const double* seg_s0, const double* seg_lo, const double* seg_hi, const int64_t* face_ptr,
+                        const int32_t* face_ids, int32_t n_faces, const double* gamma, int64_t n_rcv,
+                        const double* rcv, int32_t n_freq, const double* freqs, const double* eps,
+                        const double* alpha, double c, double gate_G, const double* eps_e2, const double* seg_e1,
+                        const double* lambda, int32_t mask_mode, const uint8_t* mask, double* d_gamma,
+                        double* d_rcv, double* d_eps, double* d_eps_e2) {
+    if (n_src < 0 || n_rays < 0 || n_segs < 0 || n_rcv < 0 || n_freq < 0 || c <= 0) return -1;
+    if (eps_e2 == NULL || (n_segs > 0 && seg_e1 == NULL)) return -1;
+    if (mask_mode == 2 && mask == NULL) return -1;
+    cplx* Z = (cplx*)calloc((size_t)(n_faces > 0 ? n_faces : 1), sizeof(cplx));
+    if (!Z) return -2;
+    for (int64_t r = 0; r < n_rcv; ++r) d_rcv[3 * r] = d_rcv[3 * r + 1] = d_rcv[3 * r + 2] = 0.0;
+    for (int32_t src = 0; src < n_src; ++src) {
+        for (int32_t b = 0; b < n_freq; ++b) {
+            const int64_t job = (int64_t)src * n_freq + b;
+            const double omega = 2.0 * PI * freqs[b];
+            const double k = omega / c;
+            const double p = 1.0 / c;
+            const double e1 = eps[job], e2 = eps_e2[job];
+            const double al = alpha ? alpha[job] : 0.0;
+            double de1 = 0.0, de2 = 0.0;
+            for (int64_t r = 0; r < n_rcv; ++r) {
+                const double* R = rcv + 3 * r;
+                const cplx lam = lambda[2 * (job * n_rcv + r)] + I * lambda[2 * (job * n_rcv + r) + 1];
+                for (int64_t i = 0; i < n_rays; ++i) {
+                    if (ray_src[i] != src) continue;
+                    const cplx weight = I * k * ray_w[i] / (8.0 * PI * PI);
+                    for (int64_t j = ray_ptr[i]; j < ray_ptr[i + 1]; ++j) {
+                        const double* t = seg_t + 3 * j;
+                        const double* f1 = seg_e1 + 3 * j;
+                        pair_geom g;
+                        const int inside = pair_geometry(R, seg_a + 3 * j, t, seg_s0[j], seg_lo[j], seg_hi[j], &g);
+                        double n1, n2, f2[3];
+                        frame_offsets(&g, t, f1, &n1, &n2, f2);
+                        const cplx q01 = -I * e1, q02 = -I * e2;
+                        const cplx q1 = q01 + g.s, q2 = q02 + g.s;
+                        const cplx E = I * omega * (g.s / c + 0.5 * p * (n1 * n1 / q1 + n2 * n2 / q2));
+                        int active = inside && creal(E) >= -gate_G;
+                        if (mask_mode == 2) active = mask[(job * n_rcv + r) * n_segs + j];
+                        if (!active) continue;
+                        const cplx bare = weight * csqrt(q01 / q1) * csqrt(q02 / q2) * cexp(E) * exp(-al * g.s);
+                        const cplx u = face_product(face_ptr, face_ids, gamma, j) * bare;
+                        const cplx lu = lam * u;
+                        const cplx ct = I * k - 0.5 / q1 - 0.5 / q2 - 0.5 * I * k * (n1 * n1 / (q1 * q1) +
+                                        n2 * n2 / (q2 * q2)) - al;
+                        const cplx c1 = I * k * n1 / q1, c2 = I * k * n2 / q2;
+                        for (int d = 0; d < 3; ++d) d_rcv[3 * r + d] += creal(lu * (ct * t[d] + c1 * f1[d] + c2 * f2[d]));
+                        de1 += creal(lu * (0.5 * (1.0 / e1 + I / q1) - 0.5 * k * n1 * n1 / (q1 * q1)));
+                        de2 += creal(lu * (0.5 * (1.0 / e2 + I / q2) - 0.5 * k * n2 * n2 / (q2 * q2)));
+                        for (int64_t m = face_ptr[j]; m < face_ptr[j + 1]; ++m) {
+                            int32_t f = face_ids[m];
+                            int seen = 0;
+                            for (int64_t mm = face_ptr[j]; mm < m; ++mm) seen |= (face_ids[mm] == f);
+                            if (seen) continue;
+                            Z[f] += lam * bare * face_product_deriv(face_ptr, face_ids, gamma, j, f);
+                        }
+                    }
+                }
+            }
+            d_eps[job] = de1;
+            d_eps_e2[job] = de2;
+        }
+    }
+    for (int32_t f = 0; f < n_faces; ++f) {
+        d_gamma[2 * f] = creal(Z[f]);
+        d_gamma[2 * f + 1] = -cimag(Z[f]);
+    }
+    free(Z);
+    return 0;
+}
+
+/*
  * Pure-tone atmospheric attenuation coefficient in dB per metre (ISO 9613-1,
  * its Eqs. for the molar concentration of water vapour, the oxygen and
  * nitrogen relaxation frequencies and the attenuation), for frequency f (Hz),
@@ -388,4 +491,4 @@ double gbso_air_absorption_db(double f, double temp_c, double rh, double p_atm) 
                                  0.1068 * exp(-3352.0 / T) / (frN + f2 / frN)));
 }
 
-int gbso_version(void) { return 2; }
+int gbso_version(void) { return 3; }

@@ -39,6 +39,13 @@ the face history follow the table conventions of the beam summation:
     from the ground gets a second, virtual segment from the image source
     (source mirrored in z = 0) along the mirrored direction, with lo = 0,
     hi = s_max and face history [0].
+
+With a launch frame per ray (the unit vector e1 normal to the launch
+direction along which an anisotropic beam has its first width), each
+segment also carries that frame transported along the path: a specular
+reflection mirrors e1 in the face's plane like the direction, flipping the
+same component (an exact sign change); the image segment carries the launch
+frame mirrored in z = 0.
 """
 from __future__ import annotations
 
@@ -92,11 +99,13 @@ def _face_id(box_idx, box, axis, side, hit, panels):
     return 1 + box_idx * 5 * panels * panels + wall * panels * panels + cell
 
 
-def trace_ray(src, d0, boxes, panels, s_max, max_refl):
-    """Path of one ray: a list of segments (a, t, s0, L, end_face, ends_on_ground);
-    end_face is -1 for the last segment."""
+def trace_ray(src, d0, boxes, panels, s_max, max_refl, e0=(0.0, 0.0, 0.0)):
+    """Path of one ray: a list of segments (a, t, s0, L, end_face, ends_on_ground,
+    e); end_face is -1 for the last segment; e is the launch frame e0
+    transported to the segment."""
     p = [float(src[0]), float(src[1]), float(src[2])]
     d = [float(d0[0]), float(d0[1]), float(d0[2])]
+    e = [float(e0[0]), float(e0[1]), float(e0[2])]
     s = 0.0
     out = []
     for k in range(max_refl + 1):
@@ -133,11 +142,12 @@ def trace_ray(src, d0, boxes, panels, s_max, max_refl):
             face = 0
         else:
             face = _face_id(best_box, tuple(float(v) for v in boxes[best_box]), best_axis, best_side, hp, panels)
-        out.append((tuple(p), tuple(d), s, L, face, ground))
+        out.append((tuple(p), tuple(d), s, L, face, ground, tuple(e)))
         if ends:
             break
         axis = 2 if ground else best_axis
         d[axis] = -d[axis]
+        e[axis] = -e[axis]
         if ground:
             hp[2] = 0.0
         p = hp
@@ -145,29 +155,32 @@ def trace_ray(src, d0, boxes, panels, s_max, max_refl):
     return out
 
 
-def ray_segments(src, d0, boxes, panels, s_max, max_refl, image_complete):
-    """Table rows of one ray: a list of (a, t, s0, lo, hi, face_history)."""
-    path = trace_ray(src, d0, boxes, panels, s_max, max_refl)
+def ray_segments(src, d0, boxes, panels, s_max, max_refl, image_complete, e0=(0.0, 0.0, 0.0)):
+    """Table rows of one ray: a list of (a, t, s0, lo, hi, face_history, e1)."""
+    path = trace_ray(src, d0, boxes, panels, s_max, max_refl, e0)
     rows = []
-    for j, (a, t, s0, L, _face, ground) in enumerate(path):
+    for j, (a, t, s0, L, _face, ground, e) in enumerate(path):
         lo, hi = 0.0, L
         if ground and j + 1 < len(path):
             hi = L + path[j + 1][3]
         if j > 0 and path[j - 1][5]:
             lo = -path[j - 1][3]
-        rows.append((a, t, s0, lo, hi, [path[m][4] for m in range(j)]))
+        rows.append((a, t, s0, lo, hi, [path[m][4] for m in range(j)], e))
     if image_complete and not any(seg[5] for seg in path):
         img = (float(src[0]), float(src[1]), -float(src[2]))
         tm = (float(d0[0]), float(d0[1]), -float(d0[2]))
-        rows.append((img, tm, 0.0, 0.0, float(s_max), [0]))
+        em = (float(e0[0]), float(e0[1]), -float(e0[2]))
+        rows.append((img, tm, 0.0, 0.0, float(s_max), [0], em))
     return rows
 
 
 def trace(src_xyz, dirs, weights, ray_src=None, boxes=None, panels=1, s_max=1.0, max_refl=10,
-          image_complete=False, rays=None):
+          image_complete=False, rays=None, e1=None):
     """Ray table (dict of numpy arrays in the beam-summation table layout)
     of the given rays, or of the subset `rays` (indices, kept in order).
-    s_max: one arc-length budget, or one per source."""
+    s_max: one arc-length budget, or one per source.  e1: launch frame per
+    ray ([n_rays, 3]); the table then also holds seg_e1, the frame carried to
+    every segment."""
     src_xyz = np.asarray(src_xyz, np.float64).reshape(-1, 3)
     dirs = np.asarray(dirs, np.float64).reshape(-1, 3)
     weights = np.asarray(weights, np.float64).reshape(-1)
@@ -177,11 +190,14 @@ def trace(src_xyz, dirs, weights, ray_src=None, boxes=None, panels=1, s_max=1.0,
         raise ValueError("image completion is defined for the open plane only")
     idx = np.arange(len(dirs)) if rays is None else np.asarray(rays, np.int64)
     s_max_src = np.broadcast_to(np.asarray(s_max, np.float64), (len(src_xyz),))
+    frames = None if e1 is None else np.asarray(e1, np.float64).reshape(-1, 3)
     ray_ptr, face_ptr = [0], [0]
-    A, T, S0, LO, HI, F = [], [], [], [], [], []
+    A, T, S0, LO, HI, F, E = [], [], [], [], [], [], []
     for i in idx:
-        for a, t, s0, lo, hi, hist in ray_segments(src_xyz[ray_src[i]], dirs[i], boxes, panels,
-                                                   float(s_max_src[ray_src[i]]), max_refl, image_complete):
+        e0 = (0.0, 0.0, 0.0) if frames is None else frames[i]
+        for a, t, s0, lo, hi, hist, e in ray_segments(src_xyz[ray_src[i]], dirs[i], boxes, panels,
+                                                      float(s_max_src[ray_src[i]]), max_refl, image_complete, e0):
+            E.append(e)
             A.append(a)
             T.append(t)
             S0.append(s0)
@@ -191,8 +207,11 @@ def trace(src_xyz, dirs, weights, ray_src=None, boxes=None, panels=1, s_max=1.0,
             face_ptr.append(face_ptr[-1] + len(hist))
         ray_ptr.append(len(S0))
     n_faces = 1 + len(boxes) * 5 * panels * panels
-    return dict(src_xyz=src_xyz.copy(), ray_ptr=np.asarray(ray_ptr, np.int64), ray_w=weights[idx].copy(),
-                ray_src=ray_src[idx].copy(), seg_a=np.asarray(A, np.float64).reshape(-1, 3),
-                seg_t=np.asarray(T, np.float64).reshape(-1, 3), seg_s0=np.asarray(S0, np.float64),
-                seg_lo=np.asarray(LO, np.float64), seg_hi=np.asarray(HI, np.float64),
-                face_ptr=np.asarray(face_ptr, np.int64), face_ids=np.asarray(F, np.int32), n_faces=n_faces)
+    out = dict(src_xyz=src_xyz.copy(), ray_ptr=np.asarray(ray_ptr, np.int64), ray_w=weights[idx].copy(),
+               ray_src=ray_src[idx].copy(), seg_a=np.asarray(A, np.float64).reshape(-1, 3),
+               seg_t=np.asarray(T, np.float64).reshape(-1, 3), seg_s0=np.asarray(S0, np.float64),
+               seg_lo=np.asarray(LO, np.float64), seg_hi=np.asarray(HI, np.float64),
+               face_ptr=np.asarray(face_ptr, np.int64), face_ids=np.asarray(F, np.int32), n_faces=n_faces)
+    if frames is not None:
+        out["seg_e1"] = np.asarray(E, np.float64).reshape(-1, 3)
+    return out

@@ -456,6 +456,58 @@ def normal_frame(t, up=(0.0, 0.0, 1.0)) -> np.ndarray:
     return e / n[:, None]
 
 
+def face_normal_axis(face_ids, panels: int = 1) -> np.ndarray:
+    """Coordinate axis of each face's normal in the box scenes: z (2) for the
+    ground (face 0) and the roofs, x (0) for the -x and +x walls, y (1) for
+    the -y and +y walls (face layout of _box_face_id)."""
+    f = np.asarray(face_ids, np.int64)
+    wall = ((f - 1) // (panels * panels)) % 5
+    ax = np.where(wall < 2, 0, np.where(wall < 4, 1, 2))
+    return np.where(f == 0, 2, ax)
+
+
+def transported_frame(table: RayTable, psi=0.0, panels: int = 1) -> np.ndarray:
+    """The ray frame of anisotropic beams carried along every ray ([n_segs, 3]).
+
+    At launch e1 = cos(psi) h + sin(psi) (t x h), with t the ray's first axis
+    and h = normal_frame(t) (psi, one value or one per ray, turns the frame
+    onto the principal axes of the beam's initial width matrix); at every
+    reflection e1 is mirrored in the face's plane like the axis itself, so it
+    stays a unit vector normal to the axis.  The box scenes' faces are normal
+    to a coordinate axis: a mirror flips that component of e1, and segment j
+    carries the flips of the faces in its history (the open plane's image
+    segments carry the ground's)."""
+    n_rays = table.n_rays
+    lens = np.diff(table.ray_ptr)
+    ray_of_seg = np.repeat(np.arange(n_rays), lens)
+    first = table.ray_ptr[:-1][lens > 0]
+    t0 = np.zeros((n_rays, 3))
+    t0[lens > 0] = table.seg_t[first]
+    h = normal_frame(t0)
+    ps = np.broadcast_to(np.asarray(psi, np.float64), (n_rays,))
+    e0 = np.cos(ps)[:, None] * h + np.sin(ps)[:, None] * np.cross(t0, h)
+    e = e0[ray_of_seg].copy()
+    flen = np.diff(table.face_ptr)
+    seg_of_face = np.repeat(np.arange(table.n_segs), flen)
+    ax = face_normal_axis(table.face_ids, panels)
+    flips = np.zeros((table.n_segs, 3), np.int64)
+    np.add.at(flips, (seg_of_face, ax), 1)
+    e *= np.where(flips % 2 == 1, -1.0, 1.0)
+    return e
+
+
+def rotate_table(table: RayTable, rot) -> RayTable:
+    """The same table in coordinates turned by the rotation matrix `rot`
+    (points and axes map by rot; arc lengths, intervals and histories are
+    unchanged): e.g. an open plane over a tilted ground."""
+    R = np.asarray(rot, np.float64)
+    return RayTable(src_xyz=table.src_xyz @ R.T, ray_ptr=table.ray_ptr.copy(), ray_w=table.ray_w.copy(),
+                    ray_src=table.ray_src.copy(), seg_a=table.seg_a @ R.T, seg_t=table.seg_t @ R.T,
+                    seg_s0=table.seg_s0.copy(), seg_lo=table.seg_lo.copy(), seg_hi=table.seg_hi.copy(),
+                    face_ptr=table.face_ptr.copy(), face_ids=table.face_ids.copy(), n_faces=table.n_faces,
+                    meta=dict(table.meta))
+
+
 def receiver_grid(nx: int, ny: int, x0: float, x1: float, y0: float, y1: float, z: float) -> np.ndarray:
     """Row-major grid (x fastest) of receivers at height z."""
     xs = x0 + (x1 - x0) * np.arange(nx) / max(nx - 1, 1)

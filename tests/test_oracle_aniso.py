@@ -166,3 +166,123 @@ def test_horizontal_frame_is_transported_by_reflections():
             assert abs(abs(float(f @ g)) - 1.0) <= 1e-12
             checked += 1
     assert checked > 2000
+
+
+# ------------------------------------------------------ anisotropic adjoint
+def _aniso_adjoint_case(up=(1.0, 2.0, 3.0)):
+    """A small paneled city (complex coefficients, several reflections) with
+    a tilted frame, so that every frame term of the receiver gradient is
+    exercised, and random adjoint weights."""
+    from scenes import city_scene
+    sc = city_scene(n_blocks=2, n_rays=400, grid=3, freqs=(400.0, 900.0), max_refl=4, city_seed=5, panels=2,
+                    complex_gamma=True)
+    e1 = _frame(sc.table, up)
+    eps2 = sc.eps * np.array([[1.7, 0.6]])
+    rng = np.random.default_rng(8)
+    lam = rng.standard_normal((sc.n_jobs, len(sc.rcv))) + 1j * rng.standard_normal((sc.n_jobs, len(sc.rcv)))
+    return sc, e1, eps2, lam
+
+
+def _aniso_loss(sc, e1, lam, gamma, rcv, eps, eps2, mask):
+    P, _ = oracle.forward(sc.table, gamma, rcv, sc.freqs, eps, eps_e2=eps2, seg_e1=e1, mask_mode=2, mask=mask)
+    return float(np.real(np.sum(lam * P)))
+
+
+def test_aniso_adjoint_matches_finite_differences(oracle_lib):
+    """Central differences of the anisotropic sum with the active set frozen
+    agree with the hand adjoint for Gamma, the receivers (frame terms along
+    e1 and e2 = t x e1) and both beam parameters."""
+    sc, e1, eps2, lam = _aniso_adjoint_case()
+    n_jobs, n_rcv, n_segs = sc.n_jobs, len(sc.rcv), sc.table.n_segs
+    mask = np.zeros((n_jobs, n_rcv, n_segs), np.uint8)
+    oracle.forward(sc.table, sc.gamma, sc.rcv, sc.freqs, sc.eps, eps_e2=eps2, seg_e1=e1, mask_mode=1, mask=mask)
+    assert mask.sum() > 50
+    dG, dR, dE, dE2 = oracle.backward(sc.table, sc.gamma, sc.rcv, sc.freqs, sc.eps, lam, eps_e2=eps2, seg_e1=e1)
+    L = lambda g=sc.gamma, r=sc.rcv, e=sc.eps, e2=eps2: _aniso_loss(sc, e1, lam, g, r, e, e2, mask)
+    used = np.unique(sc.table.face_ids)
+    rng = np.random.default_rng(1)
+    for f in rng.choice(used, size=min(6, len(used)), replace=False):
+        for comp, unit in ((0, 1.0), (1, 1j)):
+            h = 1e-6
+            gp = sc.gamma.copy(); gp[f] += h * unit
+            gm = sc.gamma.copy(); gm[f] -= h * unit
+            fd = (L(g=gp) - L(g=gm)) / (2 * h)
+            assert abs(fd - dG[f, comp]) <= 1e-6 * max(1.0, abs(fd)), (f, comp, fd, dG[f, comp])
+    for r in range(n_rcv):
+        for d in range(3):
+            h = 1e-6 * max(1.0, abs(sc.rcv[r, d]))
+            Rp = sc.rcv.copy(); Rp[r, d] += h
+            Rm = sc.rcv.copy(); Rm[r, d] -= h
+            fd = (L(r=Rp) - L(r=Rm)) / (2 * h)
+            assert abs(fd - dR[r, d]) <= 1e-5 * max(1e-3, np.abs(dR).max()), (r, d, fd, dR[r, d])
+    for j in range(n_jobs):
+        for which, base, got in (("eps", sc.eps, dE), ("eps_e2", eps2, dE2)):
+            h = 1e-6 * base.reshape(-1)[j]
+            ep = base.reshape(-1).copy(); ep[j] += h
+            em = base.reshape(-1).copy(); em[j] -= h
+            if which == "eps":
+                fd = (L(e=ep) - L(e=em)) / (2 * h)
+            else:
+                fd = (L(e2=ep) - L(e2=em)) / (2 * h)
+            assert abs(fd - got[j]) <= 1e-6 * max(1e-3, abs(fd)), (which, j, fd, got[j])
+
+
+def test_aniso_adjoint_equal_widths_is_isotropic(oracle_lib):
+    """With eps_e2 = eps the anisotropic adjoint (any frame) equals the
+    isotropic one, and its two beam-parameter derivatives add up to the
+    isotropic d/deps (another code path)."""
+    sc, e1, _, lam = _aniso_adjoint_case()
+    dG, dR, dE, dE2 = oracle.backward(sc.table, sc.gamma, sc.rcv, sc.freqs, sc.eps, lam, eps_e2=sc.eps, seg_e1=e1)
+    iG, iR, iE = oracle.backward(sc.table, sc.gamma, sc.rcv, sc.freqs, sc.eps, lam)
+    scale = lambda x: max(np.abs(x).max(), 1e-300)
+    assert np.abs(dG - iG).max() <= 1e-10 * scale(iG)
+    assert np.abs(dR - iR).max() <= 1e-10 * scale(iR)
+    assert np.abs(dE + dE2 - iE).max() <= 1e-10 * scale(iE)
+
+
+def test_aniso_adjoint_axis_swap(oracle_lib):
+    """Swapping the widths together with the frame vectors (e1 -> e2 = t x e1)
+    leaves the field unchanged, so d_gamma and d_rcv are unchanged and the two
+    beam-parameter derivatives trade places."""
+    sc, e1, eps2, lam = _aniso_adjoint_case()
+    e2 = np.cross(sc.table.seg_t, e1)
+    a = oracle.backward(sc.table, sc.gamma, sc.rcv, sc.freqs, sc.eps, lam, eps_e2=eps2, seg_e1=e1)
+    b = oracle.backward(sc.table, sc.gamma, sc.rcv, sc.freqs, eps2, lam, eps_e2=sc.eps, seg_e1=e2)
+    scale = lambda x: max(np.abs(x).max(), 1e-300)
+    assert np.abs(a[0] - b[0]).max() <= 1e-10 * scale(a[0])
+    assert np.abs(a[1] - b[1]).max() <= 1e-10 * scale(a[1])
+    assert np.abs(a[2] - b[3]).max() <= 1e-10 * scale(a[2])
+    assert np.abs(a[3] - b[2]).max() <= 1e-10 * scale(a[3])
+
+
+# ---------------------------------------------- frames carried in the table
+def _rot(ax, ang):
+    c, s = np.cos(ang), np.sin(ang)
+    if ax == 0:
+        return np.array([[1, 0, 0], [0, c, -s], [0, s, c]])
+    return np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]])
+
+
+def test_tilted_ground_rotation_invariance(oracle_lib):
+    """An open plane over a ground tilted by 20 degrees (the whole scene turned
+    by a rotation R, a face that is not axis-aligned) with the frame carried by
+    the table (R times the frame transported in the level scene, launch
+    widths turned by a per-ray angle) gives, at the turned receivers, the
+    level scene's anisotropic field to rounding.  The default horizontal
+    frame of the turned axes (z x t) is not the transported one there and
+    gives another field."""
+    from scenes import rotate_table, transported_frame
+    sc = open_plane_2k(eps="rule", n_rays=1500, grid=12)
+    psi = np.random.default_rng(3).uniform(0, np.pi, sc.table.n_rays)
+    e1 = transported_frame(sc.table, psi)
+    e2 = 1.9 * np.asarray(sc.eps)
+    gam = np.array([0.8 * np.exp(1j * np.pi / 8)])
+    R = _rot(2, 0.3) @ _rot(0, np.deg2rad(20.0))
+    tab_r = rotate_table(sc.table, R)
+    P0, _ = oracle.forward(sc.table, gam, sc.rcv, sc.freqs, sc.eps, eps_e2=e2, seg_e1=e1, n_threads=4)
+    P1, _ = oracle.forward(tab_r, gam, sc.rcv @ R.T, sc.freqs, sc.eps, eps_e2=e2, seg_e1=e1 @ R.T, n_threads=4)
+    scale = np.abs(P0).max()
+    assert np.abs(P1 - P0).max() <= 1e-9 * scale
+    P2, _ = oracle.forward(tab_r, gam, sc.rcv @ R.T, sc.freqs, sc.eps, eps_e2=e2, seg_e1=normal_frame(tab_r.seg_t),
+                           n_threads=4)
+    assert np.abs(P2 - P0).max() >= 1e-4 * scale

@@ -229,3 +229,33 @@ def test_per_source_budgets():
     k0 = tab["ray_ptr"][60]
     for key in ("seg_a", "seg_t", "seg_s0", "seg_lo", "seg_hi"):
         assert np.array_equal(tab[key][k0:], one[key]), key
+
+
+def test_frame_transport_matches_the_history_rule():
+    """The oracle tracer's frame, mirrored at every reflection along the path,
+    equals the launch frame with the components flipped by the parity of the
+    face normals in each segment's history (an independent construction from
+    the finished table), and stays a unit vector normal to every axis."""
+    from scenes import fibonacci_fan, grid_city, normal_frame
+    from scenes.tracer import face_normal_axis
+    city = grid_city(2, 40.0, 20.0, 10.0, 40.0, seed=3, panels=2)
+    d, w = fibonacci_fan(300)
+    psi = np.random.default_rng(2).uniform(0, np.pi, len(d))
+    h = normal_frame(d)
+    e0 = np.cos(psi)[:, None] * h + np.sin(psi)[:, None] * np.cross(d, h)
+    tab = ot.trace(np.array([[50.0, 50.0, 6.0]]), d, w, boxes=city.boxes, panels=2, s_max=300.0, max_refl=5, e1=e0)
+    e = tab["seg_e1"]
+    lens = np.diff(tab["ray_ptr"])
+    expect = e0[np.repeat(np.arange(len(d)), lens)].copy()
+    flips = np.zeros((len(e), 3), np.int64)
+    seg_of_face = np.repeat(np.arange(len(e)), np.diff(tab["face_ptr"]))
+    np.add.at(flips, (seg_of_face, face_normal_axis(tab["face_ids"], 2)), 1)
+    expect *= np.where(flips % 2 == 1, -1.0, 1.0)
+    assert np.array_equal(e, expect)
+    assert np.abs((e * tab["seg_t"]).sum(1)).max() <= 1e-14
+    assert (np.diff(tab["face_ptr"]) >= 2).any()
+    # the open plane's image segments carry the launch frame mirrored in z = 0
+    tab2 = ot.trace(np.array([[0.0, 0.0, 10.0]]), d, w, s_max=200.0, max_refl=1, image_complete=True, e1=e0)
+    two = np.where(np.diff(tab2["ray_ptr"]) == 2)[0]
+    img = tab2["ray_ptr"][two] + 1
+    assert np.array_equal(tab2["seg_e1"][img], e0[two] * np.array([1.0, 1.0, -1.0]))

@@ -102,3 +102,30 @@ def test_batched_city_sorted_by_source():
     t.validate()
     assert t.n_src == 3 and sc.eps.shape == (3, 4)
     assert np.all(np.diff(t.ray_src) >= 0)
+
+
+def test_transported_frame_mirrors_the_launch_frame():
+    """The frame carried along each ray stays a unit vector normal to every
+    axis; with launch angle psi it makes angle psi with the horizontal frame
+    after an even number of reflections and -psi after an odd number (a
+    mirror reverses orientation), and psi = 0 gives the horizontal frame."""
+    from scenes import city_scene, normal_frame, transported_frame
+    sc = city_scene(n_blocks=2, n_rays=600, grid=3, freqs=(400.0,), max_refl=5, city_seed=5, panels=2)
+    T = sc.table
+    psi = 0.4
+    e = transported_frame(T, psi, panels=2)
+    assert np.allclose(np.linalg.norm(e, axis=1), 1.0, atol=1e-14)
+    assert np.abs((e * T.seg_t).sum(1)).max() <= 1e-14
+    h = normal_frame(T.seg_t)
+    cosang = (e * h).sum(1)
+    sinang = (e * np.cross(T.seg_t, h)).sum(1)
+    nref = np.diff(T.face_ptr)
+    ang = np.arctan2(sinang, cosang)
+    # the horizontal frame of a reflected axis may be the mirror image up to sign: compare modulo pi
+    d_even = np.angle(np.exp(2j * (ang - psi))) / 2
+    d_odd = np.angle(np.exp(2j * (ang + psi))) / 2
+    assert np.abs(d_even[nref % 2 == 0]).max() <= 1e-12
+    assert np.abs(d_odd[nref % 2 == 1]).max() <= 1e-12
+    assert (nref % 2 == 1).any() and (nref >= 2).any()
+    e0 = transported_frame(T, 0.0, panels=2)
+    assert np.abs(np.abs((e0 * h).sum(1)) - 1.0).max() <= 1e-14
