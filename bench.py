@@ -44,19 +44,27 @@ sys.path.insert(0, ROOT)
 # compares count 0):
 #   every listed pair: arc length s (3 FMA), |R-o|^2 - |o|^2 (3 FMA) and the
 #     gate's right-hand side c1 s^2 + c2 - |o|^2 (mul, FMA)                 -> 15 FP64
-#   every kept pair: n^2 (add, FMA), den (FMA), Newton reciprocal (2 FMA),
-#     a = n^2/den, cycles (FMA, mul), fract, Gaussian exponent, accumulation
-#     (2 adds)                                                             -> 17 FP64
-#     rcp, sin, cos, exp2, weight, amplitude (2 x (FMA, mul)), rotation
-#     (2 x (mul, FMA)), pair sum                                           -> 18 FP32
+#   every kept pair: n^2 (add, FMA), the leading phase (f/c) s + arg(w Gamma)/2pi
+#     (FMA) and its fract, accumulation (2 adds)                           -> 8 FP64
+#     den (FMA), rcp, a = n^2/den, the phase correction (mul, FMA), fract,
+#     sin, cos, Gaussian exponent with log2|w Gamma| (FMA), exp2, weight,
+#     (s + i eps) w (2 mul), rotation (2 x (mul, FMA)), pair sum            -> 23 FP32
 FLOP_LISTED_F64 = 15
-FLOP_KEPT_F64 = 17
-FLOP_KEPT_F32 = 18
+FLOP_KEPT_F64 = 8
+FLOP_KEPT_F32 = 23
 # The survey's algorithmic count per pair (what the method must do, FMA = 2):
 # a pre-gate of ~20 flops on every listed (not culled) pair; per kept pair ~30
 # FP64 flops (arc length, normal distance, denominator, reciprocal, phase and
 # its reduction), ~40 FP32 flops (Gaussian, amplitude, complex rotation,
 # compensated accumulation) and 3 transcendentals (counted 1 each, as FP32).
+# The adjoint kernel per kept pair (the forward gate per listed pair as above):
+# 29 FP64 flops (n^2, den, Newton reciprocal, a, phase, fract, Gaussian
+# exponent: 15; the receiver-gradient sums V, W, G and the eps sum: 14) and
+# 69 FP32 (rcp, sin, cos, exp2 and the weight; d ln u/dR and d ln u/deps: 25;
+# the beam term, lambda u, the gradient coefficients and the segment and eps
+# sums).
+ADJ_FLOP_KEPT_F64 = 29
+ADJ_FLOP_KEPT_F32 = 69
 SURVEY_FLOP_LISTED = 20
 SURVEY_FLOP_KEPT_F64 = 30
 SURVEY_FLOP_KEPT_F32 = 43
@@ -513,24 +521,31 @@ def main():
                            count_active=count)
 
     def run(mode, steps, warmup):
+        """Time `steps` forward calls back to back (no synchronisation inside
+        the timed region but the library's own list-length read), each also
+        bracketed by events on the stream; then the pair kernel's and the
+        cull's durations from a few more calls with the library's kernel
+        timers (which synchronise, so they stay outside the timed region)."""
         for _ in range(warmup):
             step(mode)
         torch.cuda.synchronize()
-        ms_pairs, ms_cull, ms_step = [], [], []
         stream = torch.cuda.current_stream(dev)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         t = time.perf_counter()
-        for _ in range(steps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for e0, e1 in evs:
             e0.record(stream)
-            out = step(mode, timed=True)
+            out = step(mode)
             e1.record(stream)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        ms_step = [e0.elapsed_time(e1) for e0, e1 in evs]
+        ms_pairs, ms_cull = [], []
+        for _ in range(3):
+            step(mode, timed=True)
             st = gbs.stats(dev)
             ms_pairs.append(st["ms_pairs"])
             ms_cull.append(st["ms_cull"])
-            e1.synchronize()
-            ms_step.append(e0.elapsed_time(e1))
         torch.cuda.synchronize()
-        el = time.perf_counter() - t
         run.last = {"ms_cull": float(np.mean(ms_cull)), "grid": st["grid"], "blocks_per_cu": st["blocks_per_cu"],
                     "ms_step_median": float(np.median(ms_step)), "ms_step_min": float(np.min(ms_step))}
         return el / steps, float(np.mean(ms_pairs)), out
@@ -581,22 +596,10 @@ def main():
         s_adj = (time.perf_counter() - t) / n_adj
         gbs.backward(table, rcv, freqs, eps, gamma, lam, c=sc.c, gate=sc.gate, mode=mode, time_kernels=True)
         ms_adj_kernel = gbs.stats(dev)["ms_pairs"]
-        # algorithmic work of the adjoint kernel: the forward gate per listed
-        # pair; per kept pair 29 FP64 flops (n^2, den, Newton reciprocal, a,
-        # phase, fract, Gaussian exponent: 15; the receiver-gradient sums
-        # V, W, G and the eps sum: 14) and 69 FP32 (rcp, sin, cos, exp2 and the
-        # weight; d ln u/dR and d ln u/deps: 25; the beam term, lambda u, the
-        # gradient coefficients and the segment and eps sums)
-        a64 = FLOP_LISTED_F64 * listed + ADJ_FLOP_KEPT_F64 * active
-        a32 = ADJ_FLOP_KEPT_F32 * active
-        a_ach = (a64 + a32) / (ms_adj_kernel * 1e-3)
-        a_peak = (a64 + a32) / (a64 / PEAK_F64 + a32 / PEAK_F32)
         adj_leg = {"value": dense / s_adj, "ms_per_call": s_adj * 1e3, "mode": mode,
                    "forward_plus_adjoint_ms": sec_step * 1e3 + s_adj * 1e3,
-                   "roofline": {"bound": "alu", "kernel": "k_adjoint<MIX>", "achieved": a_ach / 1e12,
-                                "peak": a_peak / 1e12, "unit": "TFLOP/s", "frac": a_ach / a_peak,
-                                "ms_per_launch": ms_adj_kernel,
-                                "flop_per_kept_pair": {"f64": ADJ_FLOP_KEPT_F64, "f32": ADJ_FLOP_KEPT_F32}}}
+                   "roofline": roofline(listed, active, ms_adj_kernel, "k_adjoint<MIX>",
+                                        f64_kept=ADJ_FLOP_KEPT_F64, f32_kept=ADJ_FLOP_KEPT_F32)}
         print(f"# adjoint: {s_adj * 1e3:.2f} ms/call", file=sys.stderr, flush=True)
 
     # the same forward captured once as a hipGraph and replayed (the lists are

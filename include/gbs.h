@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define GBS_VERSION 3
+#define GBS_VERSION 4
 
 typedef enum gbs_status {
     GBS_OK = 0,
@@ -108,6 +108,14 @@ typedef struct gbs_segs {
     const double* hi;         /* [n_segs] beam interval end, exclusive (m)     */
     const int64_t* face_ptr;  /* [n_segs + 1] CSR into face_ids                */
     const int32_t* face_ids;  /* faces hit before the segment, in hit order    */
+    const double* e1;         /* [n_segs * 3] ray frame of anisotropic beams:
+                                 a unit vector normal to t (+-1e-9), the axis of
+                                 eps (params.eps_e2: e2 = t x e1 is the axis of
+                                 eps_e2), carried along each ray and mirrored at
+                                 every reflection; or NULL for e1 = z x t/|z x t|
+                                 (x when t is vertical), the frame that the
+                                 ground, roofs and walls of axis-aligned box
+                                 scenes transport.  Only read with eps_e2.     */
 } gbs_segs;
 
 /* Faces: complex reflection coefficients (always device memory). */
@@ -134,20 +142,20 @@ typedef struct gbs_params {
                                  (m, finite, > 0; device memory), or NULL for
                                  isotropic beams.  Anisotropic beams (Eq. (1)
                                  with Q = diag(q1, q2), q_m = s - i eps_m; eps
-                                 of the call is eps_1): in the ray frame
-                                 e1 = z x t / |z x t| (x when t is vertical),
-                                 e2 = t x e1, with n1 = (R - a).e1 and
-                                 n2^2 = n^2 - n1^2,
+                                 of the call is eps_1): in the segment's ray
+                                 frame (segs.e1, e2 = t x e1; a real symmetric
+                                 initial width matrix is diagonal in the frame
+                                 of its principal axes), with n1 = (R - a).e1
+                                 and n2^2 = n^2 - n1^2,
                                    u = (i k w / (8 pi^2)) prod(Gamma)
                                        sqrt(q01/q1) sqrt(q02/q2) exp(i k s
                                        + (i k / 2)(n1^2/q1 + n2^2/q2))
                                  (principal roots: continuous along the beam),
                                  kept iff the Gaussian factor is >= exp(-gate_G).
-                                 e1 stays horizontal under reflection on the
-                                 ground, roofs and walls of the box scenes, so
-                                 it is the transported frame there.  Every
-                                 mode; not with gbs_backward or
-                                 gbs_impulse_response (GBS_E_UNSUPPORTED).     */
+                                 Every mode of gbs_forward and graphs; F64 and
+                                 MIX in gbs_backward (which then also returns
+                                 d_eps_e2); not with gbs_impulse_response
+                                 (GBS_E_UNSUPPORTED).                          */
 } gbs_params;
 
 /* Plan statistics of the last forward/backward call on a context. */
@@ -190,11 +198,17 @@ int gbs_forward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const 
 
 /*
  * Adjoint of gbs_forward for dL = Re sum_{job,r} lambda[job,r] * dP[job,r],
- * with the ray geometry and the gate's active set held fixed.
+ * with the ray geometry and the gate's active set held fixed (F64 and MIX).
  *   lambda  [n_src*n_freq*n_rcv*2]  (re, im)
  *   d_gamma [n_faces * 2]  out: (dL/dRe Gamma_f, dL/dIm Gamma_f)
  *   d_rcv   [n_rcv * 3]    out: dL/dR
- *   d_eps   [n_src*n_freq] out: dL/deps per job
+ *   d_eps   [n_src*n_freq] out: dL/deps per job (anisotropic beams: dL/deps_1)
+ *   d_eps_e2 [n_src*n_freq] out: dL/deps_e2 per job with anisotropic beams
+ *                          (params.eps_e2; ignored without), with the frame
+ *                          held fixed:
+ *     d ln u/dR = t (ik - (1/q1 + 1/q2)/2 - (ik/2)(n1^2/q1^2 + n2^2/q2^2) - alpha)
+ *                 + (ik n1/q1) e1 + (ik n2/q2) e2,
+ *     d ln u/deps_m = (1/eps_m + i/q_m)/2 - (k/2) n_m^2/q_m^2
  * Any output pointer may be NULL to skip it.  Deterministic: repeated calls
  * with equal inputs give bitwise-equal outputs (receiver and beam-parameter
  * sums are reduced in a fixed order; the per-segment and per-face sums
@@ -204,7 +218,7 @@ int gbs_forward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const 
 int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces,
                  const double* rcv, int64_t n_rcv, const double* freqs, int32_t n_freq, const double* eps,
                  const gbs_params* params, const double* lambda, double* d_gamma, double* d_rcv,
-                 double* d_eps);
+                 double* d_eps, double* d_eps_e2);
 
 /* Statistics of the last gbs_forward / gbs_backward on ctx. */
 int gbs_get_stats(const gbs_ctx* ctx, gbs_stats* out);
@@ -311,6 +325,9 @@ typedef struct gbs_fan {
                                  non-decreasing, or NULL for source 0            */
     const double* s_max_src;  /* [n_src] arc-length budget per source (m, > 0;
                                  device), or NULL for scene.s_max everywhere     */
+    const double* e1;         /* [n_rays * 3] launch frame of anisotropic beams
+                                 (unit, normal to the direction +-1e-9; device),
+                                 or NULL: gbs_trace then writes no frames       */
 } gbs_fan;
 
 /*
@@ -332,6 +349,11 @@ int gbs_trace_count(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, in
  *   seg_a, seg_t [cap_segs * 3], seg_s0, seg_lo, seg_hi [cap_segs]
  *   face_ptr [cap_segs + 1]  CSR into face_ids
  *   face_ids [cap_face_ids]
+ *   seg_e1   [cap_segs * 3]  optional (NULL to skip; needs fan.e1): the launch
+ *                            frame carried to every segment, mirrored at each
+ *                            reflection like the direction (the image segment
+ *                            of the open plane: mirrored in z = 0), for
+ *                            gbs_segs.e1
  * The ray weights and sources of the table are the caller's (unchanged).
  * *n_segs and *n_face_ids receive the sizes; a capacity below them is
  * GBS_E_INVALID (nothing written past the capacities).  A direction that is
@@ -340,8 +362,8 @@ int gbs_trace_count(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, in
  */
 int gbs_trace(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, int64_t token, int64_t cap_segs,
               int64_t cap_face_ids, int64_t* ray_ptr, double* seg_a, double* seg_t, double* seg_s0,
-              double* seg_lo, double* seg_hi, int64_t* face_ptr, int32_t* face_ids, int64_t* n_segs,
-              int64_t* n_face_ids);
+              double* seg_lo, double* seg_hi, int64_t* face_ptr, int32_t* face_ids, double* seg_e1,
+              int64_t* n_segs, int64_t* n_face_ids);
 
 /*
  * Atmospheric attenuation of a pure tone in dB per metre: the model of

@@ -34,7 +34,7 @@ class GbsRays(ctypes.Structure):
 
 class GbsSegs(ctypes.Structure):
     _fields_ = [("n_segs", c_int64), ("a", c_void_p), ("t", c_void_p), ("s0", c_void_p), ("lo", c_void_p),
-                ("hi", c_void_p), ("face_ptr", c_void_p), ("face_ids", c_void_p)]
+                ("hi", c_void_p), ("face_ptr", c_void_p), ("face_ids", c_void_p), ("e1", c_void_p)]
 
 
 class GbsFaces(ctypes.Structure):
@@ -54,7 +54,7 @@ class GbsScene(ctypes.Structure):
 
 class GbsFan(ctypes.Structure):
     _fields_ = [("n_src", c_int32), ("src_xyz", c_void_p), ("n_rays", c_int64), ("dirs", c_void_p),
-                ("ray_src", c_void_p), ("s_max_src", c_void_p)]
+                ("ray_src", c_void_p), ("s_max_src", c_void_p), ("e1", c_void_p)]
 
 
 class GbsStats(ctypes.Structure):
@@ -97,7 +97,7 @@ def load() -> ctypes.CDLL:
               P(GbsParams)]
     lib.gbs_forward.argtypes = common + [c_void_p, c_void_p]
     lib.gbs_forward.restype = ctypes.c_int
-    lib.gbs_backward.argtypes = common + [c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.gbs_backward.argtypes = common + [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.gbs_backward.restype = ctypes.c_int
     lib.gbs_get_stats.argtypes = [c_void_p, P(GbsStats)]
     lib.gbs_get_stats.restype = ctypes.c_int
@@ -111,7 +111,7 @@ def load() -> ctypes.CDLL:
     lib.gbs_autotune.restype = ctypes.c_int
     lib.gbs_trace_count.argtypes = [c_void_p, P(GbsScene), P(GbsFan), P(c_int64), P(c_int64), P(c_int64)]
     lib.gbs_trace_count.restype = ctypes.c_int
-    lib.gbs_trace.argtypes = [c_void_p, P(GbsScene), P(GbsFan), c_int64, c_int64, c_int64] + [c_void_p] * 8 + \
+    lib.gbs_trace.argtypes = [c_void_p, P(GbsScene), P(GbsFan), c_int64, c_int64, c_int64] + [c_void_p] * 9 + \
         [P(c_int64), P(c_int64)]
     lib.gbs_trace.restype = ctypes.c_int
     lib.gbs_impulse_response.argtypes = [c_void_p, P(GbsRays), P(GbsSegs), P(GbsFaces), c_void_p, c_int64, c_double,

@@ -28,26 +28,32 @@ __global__ void k_gather_rcv(const double*, int64_t, int64_t, const int32_t*, do
                              int32_t*, int*);
 __global__ void k_patches(const double*, const double*, const double*, int64_t, int64_t, int, Patch*);
 __global__ void k_sphere_of_spheres(const Patch*, int, int, int, Patch*);
-__global__ void k_src_ranges(const int64_t*, const int32_t*, int64_t, int32_t, int64_t, const int64_t*, int64_t*, int*);
+__global__ void k_src_ranges(const int64_t*, const int32_t*, int64_t, int32_t, int64_t, const int64_t*, int, int32_t,
+                             int64_t*, int*);
+__global__ void k_job_consts(const double*, const double*, const double*, const double*, int32_t, int32_t, double,
+                             double, const int64_t*, int64_t, int64_t, JobConst*, int*);
+__global__ void k_make_splits(const int64_t*, int32_t, int64_t, int64_t, int64_t, int32_t, CullSplit*, int32_t*);
 __global__ void k_seg2ray(const int64_t*, int64_t, int64_t, int64_t, int32_t*);
 __global__ void k_records(int64_t, const double*, const double*, const double*, const double*, const double*,
                           const int64_t*, int64_t, const int32_t*, int32_t, const double*, const double*,
-                          const int32_t*, int64_t, int64_t, SegRec*, int*, unsigned long long*);
+                          const int32_t*, int64_t, const int64_t*, int64_t, SegRec*, int*, unsigned long long*);
 template <bool FILL, int NB>
 __global__ void k_cull(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int, const CullSplit*,
-                       const unsigned long long*, int, int, int32_t*, const int64_t*, int32_t*);
+                       const int32_t*, const unsigned long long*, int, int, int32_t*, const int64_t*, int32_t*);
 template <int NB>
 __global__ void k_cull_hyper(const JobConst*, const SegRec*, const Patch*, int, int, int, const CullSplit*,
-                             unsigned long long*);
+                             const int32_t*, unsigned long long*);
 __global__ void k_item_lengths(const int64_t*, int32_t, int, int32_t*);
 __global__ void k_iota(int32_t*, int32_t);
 __global__ void k_seg_keys(int64_t, const SegRec*, const JobConst*, int32_t, int32_t, const double*,
                            unsigned long long*, int32_t*);
 __global__ void k_permute_rec(int64_t, const SegRec*, const int32_t*, SegRec*);
+__global__ void k_frames(int64_t, const double*, const double*, const double*, const double*, FrameRec*, int*);
+__global__ void k_permute_frames(int64_t, const FrameRec*, const int32_t*, FrameRec*);
 template <int MODE, int NR, bool COUNT>
 __global__ void k_pairs(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*, const int32_t*,
-                        const SegRec*, const double*, const double*, const double*, const double*, double*,
-                        unsigned long long*);
+                        const SegRec*, const FrameRec*, const double*, const double*, const double*, const double*,
+                        double*, unsigned long long*);
 __global__ void k_work_counts(const int32_t*, const int32_t*, int32_t, int32_t, int32_t*);
 __global__ void k_make_work(const int32_t*, const int64_t*, int32_t, const int32_t*, int32_t, int32_t, Work*, int32_t*,
                             int32_t*, int32_t*);
@@ -56,8 +62,9 @@ __global__ void k_reduce_partials(const JobConst*, const int32_t*, const int32_t
 __global__ void k_tl(const double*, int64_t, double*);
 template <int MODE>
 __global__ void k_adjoint(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*, const int32_t*,
-                          const SegRec*, const double*, const double*, const double*, const double*, const int32_t*,
-                          int64_t, const double*, double*, const int32_t*, Fixed*, const double*, double*);
+                          const SegRec*, const FrameRec*, const double*, const double*, const double*, const double*,
+                          const int32_t*, int64_t, const double*, double*, const int32_t*, Fixed*, const double*,
+                          double*, double*);
 __global__ void k_reduce_adjoint(const JobConst*, const int32_t*, const int32_t*, int32_t, int32_t, const int32_t*,
                                  int64_t, const double*, double*);
 __global__ void k_sum_jobs(const double*, int32_t, int64_t, double*);
@@ -73,7 +80,7 @@ template <bool COUNT>
 __global__ void k_trace(int64_t, int, const double*, const int32_t*, const double*, const double*, const double*,
                         const double*,
                         const int32_t*, int, int, int, double, int, int64_t*, int*, const int64_t*, const int64_t*,
-                        double*, double*, double*, double*, double*, int64_t*, int32_t*);
+                        double*, double*, double*, double*, double*, int64_t*, int32_t*, const double*, double*);
 __global__ void k_trace_face_counts(int64_t, const int64_t*, int64_t*);
 // broadband synthesis (gbs_ir.hip)
 __global__ void k_ir_twiddles(int, double2*);
@@ -173,8 +180,6 @@ struct gbs_ctx {
     std::unique_ptr<Workspace> ws{new Workspace};
     int tuned_nr[3] = {0, 0, 0};      // per mode, 0 = not tuned
     int tuned_chunk[3] = {0, 0, 0};
-    void* pinned = nullptr;
-    size_t pinned_cap = 0;
     // streaming of host-resident tables: pass i+1 is copied on copy_stream
     // while pass i computes; two staging slots, ordered by these events
     hipStream_t copy_stream = nullptr;
@@ -220,21 +225,6 @@ int guarded(gbs_ctx* ctx, F&& f) {
         set_err(ctx, "unknown failure");
         return GBS_E_HIP;
     }
-}
-
-void* pinned_staging(gbs_ctx* ctx, size_t bytes) {
-    if (ctx->pinned_cap < bytes) {
-        if (ctx->pinned) {
-            GBS_HIP(hipStreamSynchronize(ctx->stream));
-            GBS_HIP(hipHostFree(ctx->pinned));
-            ctx->pinned = nullptr;
-            ctx->pinned_cap = 0;
-        }
-        size_t cap = std::max<size_t>(bytes, 1 << 16);
-        GBS_HIP(hipHostMalloc(&ctx->pinned, cap, hipHostMallocDefault));
-        ctx->pinned_cap = cap;
-    }
-    return ctx->pinned;
 }
 
 // ------------------------------------------------------------- validation
@@ -289,7 +279,9 @@ void validate_host(const Args& a) {
 void check_status(int bits) {
     if (bits == 0) return;
     std::string m = "invalid input:";
-    if (bits & kBadSegment) m += " segment values (non-finite a, s0, lo or hi, lo > hi, or |t| != 1);";
+    if (bits & kBadSegment)
+        m += " segment values (non-finite a, s0, lo or hi, lo > hi, |t| != 1, or a frame vector e1 not unit or not "
+             "normal to t);";
     if (bits & kBadFacePtr) m += " face_ptr (not a non-decreasing CSR from 0);";
     if (bits & kBadFaceId) m += " face id outside [0, n_faces);";
     if (bits & kBadRayPtr) m += " ray_ptr (not a non-decreasing CSR from 0 to n_segs);";
@@ -297,6 +289,7 @@ void check_status(int bits) {
     if (bits & kBadReceiver) m += " receiver coordinate (non-finite);";
     if (bits & kBadRaySource) m += " ray_src (outside [0, n_src) or not non-decreasing);";
     if (bits & kBadLambda) m += " lambda (non-finite);";
+    if (bits & kBadJob) m += " frequency, eps, alpha or eps_e2 (non-finite, or not > 0; alpha >= 0);";
     throw GbsError(GBS_E_INVALID, m);
 }
 
@@ -308,13 +301,12 @@ struct Planner {
     const Args& a;
     int mode, nr;
     int n_jobs;
-    std::vector<double> h_freqs, h_eps, h_alpha, h_epsb;
-    std::vector<int64_t> src_off;     // [n_src + 1] first segment of each source
+    const int64_t* d_src_off = nullptr;   // device: first segment of each source, [n_src + 1]
+    std::vector<int64_t> h_src_off;       // host tables: the same, computed on the host and copied
     std::vector<PassRange> passes;
     std::vector<int64_t> h_ray_ptr, h_face_ptr;  // host copies (only when chunking)
     RcvPlan R;
     int* status = nullptr;            // device StatusBit word of this call
-    int64_t face_total = 0;           // face_ptr[n_segs]: length of face_ids
 
     Planner(gbs_ctx* c, Workspace& w, const Args& args, int nr_)
         : ctx(c), ws(w), st(c->stream), a(args), mode(args.params->mode), nr(nr_) {
@@ -338,47 +330,45 @@ struct Planner {
         return kWorkChunk;
     }
 
-    void read_job_inputs() {
-        h_freqs.resize(a.n_freq);
-        h_eps.resize(n_jobs);
-        h_alpha.assign(n_jobs, 0.0);
-        if (a.n_freq > 0) {
-            GBS_HIP(hipMemcpyAsync(h_freqs.data(), a.freqs, sizeof(double) * a.n_freq, hipMemcpyDeviceToHost, st));
-            if (n_jobs > 0) {
-                GBS_HIP(hipMemcpyAsync(h_eps.data(), a.eps, sizeof(double) * n_jobs, hipMemcpyDeviceToHost, st));
-                if (a.params->alpha)
-                    GBS_HIP(hipMemcpyAsync(h_alpha.data(), a.params->alpha, sizeof(double) * n_jobs,
-                                           hipMemcpyDeviceToHost, st));
-                if (a.params->eps_e2) {
-                    h_epsb.resize(n_jobs);
-                    GBS_HIP(hipMemcpyAsync(h_epsb.data(), a.params->eps_e2, sizeof(double) * n_jobs,
-                                           hipMemcpyDeviceToHost, st));
-                }
-            }
-            GBS_HIP(hipStreamSynchronize(st));
-        }
-        for (double f : h_freqs) GBS_CHECK(std::isfinite(f) && f > 0, "frequencies must be finite and > 0");
-        for (double e : h_eps) GBS_CHECK(std::isfinite(e) && e > 0, "eps must be finite and > 0");
-        for (double al : h_alpha) GBS_CHECK(std::isfinite(al) && al >= 0, "alpha must be finite and >= 0");
-        for (double e : h_epsb) GBS_CHECK(std::isfinite(e) && e > 0, "eps_e2 must be finite and > 0");
-    }
-
     bool aniso() const { return a.params->eps_e2 != nullptr; }
 
-    bool absorb() const {
-        for (double al : h_alpha)
-            if (al != 0.0) return true;
-        return false;
+    // The job inputs checked on the host, for calls with no device work (with
+    // work, k_job_consts checks them on the device).  Synchronises.
+    void check_jobs_on_host() {
+        if (n_jobs == 0) return;
+        std::vector<double> f(a.n_freq), e(n_jobs), al(a.params->alpha ? n_jobs : 0), e2(a.params->eps_e2 ? n_jobs : 0);
+        GBS_HIP(hipMemcpyAsync(f.data(), a.freqs, sizeof(double) * f.size(), hipMemcpyDeviceToHost, st));
+        GBS_HIP(hipMemcpyAsync(e.data(), a.eps, sizeof(double) * e.size(), hipMemcpyDeviceToHost, st));
+        if (!al.empty())
+            GBS_HIP(hipMemcpyAsync(al.data(), a.params->alpha, sizeof(double) * al.size(), hipMemcpyDeviceToHost, st));
+        if (!e2.empty())
+            GBS_HIP(hipMemcpyAsync(e2.data(), a.params->eps_e2, sizeof(double) * e2.size(), hipMemcpyDeviceToHost,
+                                   st));
+        GBS_HIP(hipStreamSynchronize(st));
+        int bad = 0;
+        for (double x : f) bad |= !(std::isfinite(x) && x > 0);
+        for (double x : e) bad |= !(std::isfinite(x) && x > 0);
+        for (double x : al) bad |= !(std::isfinite(x) && x >= 0);
+        for (double x : e2) bad |= !(std::isfinite(x) && x > 0);
+        check_status(bad ? kBadJob : 0);
     }
 
-    // First segment of every source, and the checks of the ray and face CSR
-    // arrays (on the host for host tables, by k_src_ranges otherwise; one
-    // synchronisation).
+    // The pair kernel's absorption variant runs whenever absorption is given
+    // (a zero alpha then gives bitwise the same sum as none).
+    bool absorb() const { return a.params->alpha != nullptr; }
+
+    // First segment of every source (device array d_src_off), and the checks
+    // of the ray and face CSR arrays: on the host for host tables, by
+    // k_src_ranges otherwise (flags read at the list-length synchronisation,
+    // before any beam is evaluated).  No synchronisation for device tables.
     void source_offsets() {
         const int32_t n_src = a.rays->n_src;
         const int64_t n_rays = a.rays->n_rays, n_segs = a.segs->n_segs;
-        src_off.assign(n_src + 1, 0);
+        int64_t* d_off = ws.get<int64_t>("src_off", n_src + 2);
+        d_src_off = d_off;
         if (table_host()) {
+            std::vector<int64_t>& src_off = h_src_off;
+            src_off.assign(n_src + 1, 0);
             const int64_t* rp = a.rays->ray_ptr;
             const int32_t* rs = a.rays->ray_src;
             const int64_t* fp = a.segs->face_ptr;
@@ -393,23 +383,15 @@ struct Planner {
             }
             GBS_CHECK(fp[0] == 0, "face_ptr[0] must be 0");
             for (int64_t j = 0; j < n_segs; ++j) GBS_CHECK(fp[j + 1] >= fp[j], "face_ptr must be non-decreasing");
-            face_total = fp[n_segs];
+            GBS_CHECK(fp[n_segs] == 0 || a.segs->face_ids, "null face_ids");
+            GBS_CHECK(fp[n_segs] == 0 || a.faces->n_faces > 0, "face histories need n_faces > 0");
+            GBS_HIP(hipMemcpyAsync(d_off, src_off.data(), sizeof(int64_t) * (n_src + 1), hipMemcpyHostToDevice, st));
         } else {
-            int64_t* d_off = ws.get<int64_t>("src_off", n_src + 2);
-            int h_status = 0;
             hipLaunchKernelGGL(k_src_ranges, dim3(blocks_for(n_rays + 1, 256)), dim3(256), 0, st, a.rays->ray_ptr,
-                               a.rays->ray_src, n_rays, n_src, n_segs, a.segs->face_ptr, d_off, status);
+                               a.rays->ray_src, n_rays, n_src, n_segs, a.segs->face_ptr,
+                               a.segs->face_ids != nullptr ? 1 : 0, a.faces->n_faces, d_off, status);
             GBS_HIP(hipGetLastError());
-            GBS_HIP(hipMemcpyAsync(src_off.data(), d_off, sizeof(int64_t) * (n_src + 1), hipMemcpyDeviceToHost, st));
-            GBS_HIP(hipMemcpyAsync(&face_total, a.segs->face_ptr + n_segs, sizeof(int64_t), hipMemcpyDeviceToHost,
-                                   st));
-            GBS_HIP(hipMemcpyAsync(&h_status, status, sizeof(int), hipMemcpyDeviceToHost, st));
-            GBS_HIP(hipStreamSynchronize(st));
-            check_status(h_status);
         }
-        GBS_CHECK(face_total >= 0, "face_ptr[n_segs] must be >= 0");
-        GBS_CHECK(face_total == 0 || a.segs->face_ids, "null face_ids");
-        GBS_CHECK(face_total == 0 || a.faces->n_faces > 0, "face histories need n_faces > 0");
     }
 
     void make_passes() {
@@ -437,6 +419,10 @@ struct Planner {
             GBS_HIP(hipStreamSynchronize(st));
             rp = h_ray_ptr.data();
             fp = h_face_ptr.data();
+            // the pass ranges come from these arrays: check them before using them
+            GBS_CHECK(rp[0] == 0 && rp[n_rays] == n_segs, "ray_ptr must span the segments");
+            for (int64_t i = 0; i < n_rays; ++i) GBS_CHECK(rp[i + 1] >= rp[i], "ray_ptr must be non-decreasing");
+            GBS_CHECK(fp[0] == 0, "face_ptr[0] must be 0");
             for (int64_t j = 0; j < n_segs; ++j) GBS_CHECK(fp[j + 1] >= fp[j], "face_ptr must be non-decreasing");
         }
         const int64_t limit = cs > 0 ? cs : n_segs;
@@ -494,60 +480,6 @@ struct Planner {
         GBS_HIP(hipGetLastError());
     }
 
-    std::vector<JobConst> job_consts(const PassRange& ps) const {
-        std::vector<JobConst> J(n_jobs);
-        const double G = a.params->gate_G, c = a.params->c;
-        const double pi = 3.14159265358979323846;
-        for (int s = 0; s < a.rays->n_src; ++s)
-            for (int b = 0; b < a.n_freq; ++b) {
-                JobConst& j = J[s * a.n_freq + b];
-                const double f = h_freqs[b], e = h_eps[s * a.n_freq + b];
-                const double k = 2.0 * pi * f / c;
-                const double ke = k * e;
-                j.seg_begin = std::max(src_off[s], ps.seg_begin) - ps.seg_begin;
-                j.seg_end = std::min(src_off[s + 1], ps.seg_end) - ps.seg_begin;
-                if (j.seg_end < j.seg_begin) j.seg_end = j.seg_begin;
-                j.k = k;
-                j.eps = e;
-                j.eps2 = e * e;
-                j.gate_c1 = 1.0 + 2.0 * G / ke;
-                j.gate_c2 = 2.0 * G * e * e / ke;
-                j.kappa = 2.0 * G / ke;
-                j.fk = f / c;
-                j.hfk = 0.5 * f / c;
-                j.gexp2 = -0.5 * ke * 1.4426950408889634;
-                j.gexp = -0.5 * ke;
-                j.scale = ke / (8.0 * pi * pi);
-                j.aexp = -h_alpha[s * a.n_freq + b];
-                j.aexp2 = j.aexp * 1.4426950408889634;
-                j.epsb = e;
-                j.epsa2 = e * e;
-                j.epsb2 = e * e;
-                j.gate_a = 2.0 * G / k;
-                j.gexpa = -0.5 * k;
-                j.gexpa2 = -0.5 * k * 1.4426950408889634;
-                j.ampc = 0.5 * e;
-                if (aniso()) {
-                    // envelope of the two widths for the cull and the pre-gate (it keeps
-                    // every pair the exact gate keeps), widened by a relative 1e-12
-                    // against rounding; the pair kernel applies the exact gate
-                    const double eb = h_epsb[s * a.n_freq + b];
-                    const double margin = 1.0 + 1e-12;
-                    j.epsb = eb;
-                    j.epsb2 = eb * eb;
-                    j.ampc = 0.5 * std::sqrt(e * eb);
-                    j.kappa = 2.0 * G / (k * std::min(e, eb)) * margin;
-                    j.eps2 = e * eb * margin;
-                    j.gate_c1 = 1.0 + j.kappa;
-                    j.gate_c2 = j.kappa * j.eps2;
-                    j.scale = k / (8.0 * pi * pi);
-                }
-                j.src = s;
-                j.band = b;
-            }
-        return J;
-    }
-
     // Device views of one pass of the table (copied in if the table is on the host).
     struct PassView {
         int64_t n_rays, n_segs;
@@ -557,6 +489,7 @@ struct Planner {
         const int64_t* face_ptr;  // absolute offsets into the full face_ids
         int64_t face_base;
         const int32_t* face_ids;  // starts at face_base
+        const double* e1;         // frame vectors (anisotropic beams), or null
     };
 
     template <typename T>
@@ -586,6 +519,7 @@ struct Planner {
             v.face_ptr = S.face_ptr + ps.seg_begin;
             v.face_base = 0;
             v.face_ids = S.face_ids;
+            v.e1 = S.e1 ? S.e1 + 3 * ps.seg_begin : nullptr;
             return v;
         }
         v.ray_ptr = stage("p_ray_ptr" + sfx, a.rays->ray_ptr + ps.ray_begin, v.n_rays + 1, cs);
@@ -599,6 +533,7 @@ struct Planner {
         v.face_base = ps.face_begin;
         v.face_ids = stage("p_face_ids" + sfx, S.face_ids ? S.face_ids + ps.face_begin : nullptr,
                            ps.face_end - ps.face_begin, cs);
+        v.e1 = S.e1 && aniso() ? stage("p_e1" + sfx, S.e1 + 3 * ps.seg_begin, 3 * v.n_segs, cs) : nullptr;
         return v;
     }
 
@@ -608,6 +543,7 @@ struct Planner {
         int64_t total = 0;
         const JobConst* jobs = nullptr;
         const SegRec* rec = nullptr;       // records in spatial order (what the kernels read)
+        const FrameRec* frames = nullptr;  // anisotropic beams: ray frames in the same order
         SegRec* rec_raw = nullptr;         // records in table order (k_records writes them)
         const int32_t* seg_perm = nullptr; // spatial position -> table position
         const int32_t* seg_ray = nullptr;
@@ -625,9 +561,12 @@ struct Planner {
 
     // Records, job constants, culled lists and the longest-first item order
     // for one pass.  Synchronises once to size the lists.
-    // Absolute end of the face ids a pass may read: the staged slice of a
-    // host table, the whole array otherwise.
-    int64_t face_end(const PassRange& ps) const { return table_host() ? ps.face_end : face_total; }
+    // Absolute end of the face ids a pass may read: the staged slice of a host
+    // table; face_ptr[n_segs] on the device otherwise (none without face_ids).
+    const int64_t* face_end_dev() const {
+        return table_host() || !a.segs->face_ids ? nullptr : a.segs->face_ptr + a.segs->n_segs;
+    }
+    int64_t face_end_host(const PassRange& ps) const { return table_host() ? ps.face_end : 0; }
 
     Lists build_lists(const PassRange& ps, const PassView& v, int pass_idx,
                       unsigned long long* bmax = nullptr) {
@@ -640,18 +579,20 @@ struct Planner {
                                ps.seg_begin, nseg, seg_ray);
             hipLaunchKernelGGL(k_records, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, nseg, v.a, v.t, v.s0, v.lo,
                                v.hi, v.face_ptr, v.face_base, v.face_ids, a.faces->n_faces, a.faces->gamma, v.ray_w,
-                               seg_ray, v.n_rays, face_end(ps), rec, status, bmax);
+                               seg_ray, v.n_rays, face_end_dev(), face_end_host(ps), rec, status, bmax);
             GBS_HIP(hipGetLastError());
         }
         L.rec = rec;
         L.rec_raw = rec;
         L.seg_ray = seg_ray;
-        std::vector<JobConst> J = job_consts(ps);
         JobConst* dJ = ws.get<JobConst>(tag.empty() ? "jobs" + std::to_string(pass_idx % 2) : "jobs" + tag, n_jobs);
-        void* h = pinned_staging(ctx, sizeof(JobConst) * n_jobs);
-        GBS_HIP(hipStreamSynchronize(st));  // the staging buffer may still feed an earlier copy
-        std::memcpy(h, J.data(), sizeof(JobConst) * n_jobs);
-        GBS_HIP(hipMemcpyAsync(dJ, h, sizeof(JobConst) * n_jobs, hipMemcpyHostToDevice, st));        L.jobs = dJ;
+        if (n_jobs > 0) {
+            hipLaunchKernelGGL(k_job_consts, dim3(blocks_for(n_jobs, 64)), dim3(64), 0, st, a.freqs, a.eps,
+                               a.params->alpha, a.params->eps_e2, a.rays->n_src, a.n_freq, a.params->c,
+                               a.params->gate_G, d_src_off, ps.seg_begin, ps.seg_end, dJ, status);
+            GBS_HIP(hipGetLastError());
+        }
+        L.jobs = dJ;
         if (nseg > 0 && R.bbox) {
             // spatial order of the segments (each source's range stays in place)
             unsigned long long* k1 = ws.get<unsigned long long>("skeys", nseg);
@@ -673,38 +614,48 @@ struct Planner {
             L.seg_perm = perm;
             rec = rs;
         }
+        if (nseg > 0 && aniso()) {
+            // ray frames (job independent; graphs keep them per pass): table order, then the records' order
+            FrameRec* fr = ws.get<FrameRec>("frames_raw" + tag, nseg);
+            hipLaunchKernelGGL(k_frames, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, nseg, v.a, v.t, v.s0, v.e1,
+                               fr, status);
+            L.frames = fr;
+            if (L.seg_perm) {
+                FrameRec* fs = ws.get<FrameRec>("frames" + tag, nseg);
+                hipLaunchKernelGGL(k_permute_frames, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, nseg, fr,
+                                   L.seg_perm, fs);
+                L.frames = fs;
+            }
+            GBS_HIP(hipGetLastError());
+        }
         const int64_t n_items = (int64_t)n_jobs * R.n_patch;
         GBS_CHECK(n_items < INT32_MAX, "too many work items");
         L.n_items = (int32_t)n_items;
         if (n_items == 0) return L;
         // split every source's segment range so that culling runs wide; one
-        // workgroup culls one piece for all bands of its source
+        // workgroup culls one piece for all bands of its source.  The pieces
+        // are laid out on the device (k_make_splits); the host sizes the grids
+        // for the most pieces a pass can have: one cull wave per (super-patch,
+        // piece), up to 256 pieces per source, fewer when the per-piece
+        // lengths would outgrow 64M counters
         const int n_src = a.rays->n_src, n_freq = a.n_freq;
-        int64_t max_src = 0;
-        for (int sidx = 0; sidx < n_src; ++sidx)
-            max_src = std::max(max_src, J[sidx * n_freq].seg_end - J[sidx * n_freq].seg_begin);
-        // one cull wave per (super-patch, split): up to 256 splits per source,
-        // fewer when the per-split lengths would outgrow 64M counters
         const int64_t max_split = std::max<int64_t>(1, std::min<int64_t>(256, (int64_t(1) << 26) / n_items));
-        int64_t span = std::max<int64_t>(1024, (max_src + max_split - 1) / max_split);
+        int64_t span = std::max<int64_t>(1024, (nseg + max_split - 1) / max_split);
         span = (span + kCullThreads - 1) / kCullThreads * kCullThreads;
-        const int n_split = (int)std::max<int64_t>(1, (max_src + span - 1) / span);
-        std::vector<CullSplit> sv;
-        for (int sidx = 0; sidx < n_src; ++sidx) {
-            const int64_t b = J[sidx * n_freq].seg_begin, e = J[sidx * n_freq].seg_end;
-            int k = 0;
-            for (int64_t x = b; x < e; x += span, ++k) sv.push_back(CullSplit{x, std::min(x + span, e), sidx, k});
-        }
+        const int n_split = (int)std::max<int64_t>(1, (nseg + span - 1) / span);   // pieces per source, at most
+        const int64_t max_pieces = std::min<int64_t>((int64_t)n_src * n_split, n_src + (nseg + span - 1) / span);
+        GBS_CHECK(max_pieces < 65536, "too many cull pieces");
         L.n_split = n_split;
         const int64_t n_cnt = n_items * n_split;
         GBS_CHECK(n_cnt < INT32_MAX, "too many cull partitions");
         int32_t* counts = ws.get<int32_t>("counts", n_cnt + 2);
         int64_t* off = ws.get<int64_t>("item_off", n_cnt + 1);
         fill(st, (double*)counts, (n_cnt + 2) / 2, 0.0);
-        CullSplit* d_split = ws.get<CullSplit>("splits", std::max<size_t>(sv.size(), 1));
-        if (!sv.empty())
-            GBS_HIP(hipMemcpyAsync(d_split, sv.data(), sizeof(CullSplit) * sv.size(), hipMemcpyHostToDevice, st));
-        dim3 cg(R.n_super, (unsigned)std::max<size_t>(sv.size(), 1));
+        CullSplit* d_split = ws.get<CullSplit>("splits", std::max<int64_t>(max_pieces, 1));
+        int32_t* d_nsplit = ws.get<int32_t>("n_splits", 1);
+        hipLaunchKernelGGL(k_make_splits, dim3(1), dim3(64), 0, st, d_src_off, n_src, ps.seg_begin, ps.seg_end, span,
+                           (int32_t)max_pieces, d_split, d_nsplit);
+        dim3 cg(R.n_super, (unsigned)std::max<int64_t>(max_pieces, 1));
         // up to 8 bands: band constants in wave-uniform registers, as many as needed
         auto cull_count = n_freq == 1 ? k_cull<false, 1> : n_freq <= 4 ? k_cull<false, 4>
                         : n_freq <= 8 ? k_cull<false, 8> : k_cull<false, 0>;
@@ -714,14 +665,14 @@ struct Planner {
                         : n_freq <= 8 ? k_cull_hyper<8> : k_cull_hyper<0>;
         // level 0: which segments of each chunk may reach each hyper-patch
         const int cps = (int)(span / kCullThreads);
-        unsigned long long* hmask =
-            ws.get<unsigned long long>("hmask", std::max<size_t>(sv.size(), 1) * cps * R.n_hyper * (kCullThreads / kWave));
-        if (!sv.empty())
-            hipLaunchKernelGGL(cull_hyper, dim3(cps, (unsigned)sv.size()), dim3(kCullThreads), 0, st, dJ, rec,
-                               R.hypers, R.n_hyper, n_freq, cps, d_split, hmask);
-        if (!sv.empty())
+        unsigned long long* hmask = ws.get<unsigned long long>(
+            "hmask", (size_t)std::max<int64_t>(max_pieces, 1) * cps * R.n_hyper * (kCullThreads / kWave));
+        if (nseg > 0) {
+            hipLaunchKernelGGL(cull_hyper, dim3(cps, (unsigned)max_pieces), dim3(kCullThreads), 0, st, dJ, rec,
+                               R.hypers, R.n_hyper, n_freq, cps, d_split, d_nsplit, hmask);
             hipLaunchKernelGGL(cull_count, cg, dim3(kWave), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
-                               n_freq, n_split, d_split, hmask, R.n_hyper, cps, counts, nullptr, nullptr);
+                               n_freq, n_split, d_split, d_nsplit, hmask, R.n_hyper, cps, counts, nullptr, nullptr);
+        }
         GBS_HIP(hipGetLastError());
         // counts are int32; accumulate in int64 through a converting iterator
         auto in64 = hipcub::TransformInputIterator<int64_t, Widen, const int32_t*>(counts, Widen());
@@ -735,9 +686,9 @@ struct Planner {
         GBS_HIP(hipStreamSynchronize(st));
         check_status(h_status);     // before any list is filled or any pair kernel runs
         int32_t* lists = ws.get<int32_t>("lists" + tag, std::max<int64_t>(L.total, 1));
-        if (!sv.empty())
+        if (nseg > 0)
             hipLaunchKernelGGL(cull_fill, cg, dim3(kWave), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
-                               n_freq, n_split, d_split, hmask, R.n_hyper, cps, nullptr, off, lists);
+                               n_freq, n_split, d_split, d_nsplit, hmask, R.n_hyper, cps, nullptr, off, lists);
         GBS_HIP(hipGetLastError());
         // longest lists first
         int32_t* lens = ws.get<int32_t>("lens", n_items);
@@ -843,7 +794,7 @@ void launch_pairs(gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const R
     const int64_t grid = persistent_grid(ctx, (const void*)kern, L.work_cap);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, ctr);
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPairThreads), 0, st, L.jobs, L.work, L.n_work, R.n_patch, ctr,
-                       L.lists, L.rec, R.rx, R.ry, R.rz, R.r2, L.partial, n_active);
+                       L.lists, L.rec, L.frames, R.rx, R.ry, R.rz, R.r2, L.partial, n_active);
     GBS_HIP(hipGetLastError());
     const int64_t threads = (int64_t)L.n_items * 64 * NR;
     hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(threads, 256)), dim3(256), 0, st, L.jobs, L.item_wbase,
@@ -916,15 +867,13 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
     pl.chunk_override = chunk_override;
     hipStream_t st = ctx->stream;
     const int64_t n_out = (int64_t)pl.n_jobs * a.n_rcv;
-    pl.read_job_inputs();
     fill(st, P, 2 * n_out, 0.0);
     gbs_stats stats{};
     stats.patch_rcv = 64 * nr;
     if (n_out > 0 && a.segs->n_segs > 0) {
         pl.reset_status();
         pl.source_offsets();
-        for (int s = 0; s < a.rays->n_src; ++s)
-            stats.dense_pairs += (pl.src_off[s + 1] - pl.src_off[s]) * a.n_rcv * a.n_freq;
+        stats.dense_pairs = a.segs->n_segs * a.n_rcv * a.n_freq;   // every segment belongs to one source
         pl.make_passes();
         pl.plan_receivers(64 * nr);
         unsigned* ctr = ws.get<unsigned>("ctr", 1);
@@ -978,6 +927,8 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
             GBS_HIP(hipStreamSynchronize(st));
             stats.active_pairs = (int64_t)h;
         }
+    } else {
+        pl.check_jobs_on_host();
     }
     if (TL && n_out > 0) {
         hipLaunchKernelGGL(k_tl, dim3(blocks_for(n_out, 256)), dim3(256), 0, st, P, n_out, TL);
@@ -1053,6 +1004,7 @@ struct TraceOut {
     double *a, *t, *s0, *lo, *hi;
     int64_t* face_ptr;
     int32_t* face_ids;
+    double* e1;          // optional: the carried ray frame (needs fan.e1)
 };
 
 // What a count token stands for: the arguments of the counted call.
@@ -1062,7 +1014,7 @@ std::vector<uint64_t> trace_signature(const gbs_scene* sc, const gbs_fan* fan) {
     std::memcpy(&smax_bits, &sc->s_max, sizeof smax_bits);
     return {(uint64_t)sc->n_boxes, (uint64_t)sc->panels, ptr(sc->boxes), smax_bits, (uint64_t)sc->max_refl,
             (uint64_t)sc->image_complete, (uint64_t)fan->n_src, ptr(fan->src_xyz), (uint64_t)fan->n_rays,
-            ptr(fan->dirs), ptr(fan->ray_src), ptr(fan->s_max_src)};
+            ptr(fan->dirs), ptr(fan->ray_src), ptr(fan->s_max_src), ptr(fan->e1)};
 }
 
 // Count pass and prefix sums; with `out` also the write pass (after the
@@ -1145,7 +1097,8 @@ std::pair<int64_t, int64_t> trace_impl(gbs_ctx* ctx, const gbs_scene* sc, const 
             hipLaunchKernelGGL(k_trace<true>, grid, block, 0, st, n, fan->n_src, fan->src_xyz, fan->ray_src, fan->dirs,
                                fan->s_max_src, d_box, d_gbox, d_mem, S.n_groups, sc->panels, sc->max_refl, sc->s_max,
                                sc->image_complete, nseg, bad,
-                               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+                               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                               fan->e1, nullptr);
         GBS_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_trace_face_counts, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st, n, nseg, nface);
         size_t tmp = 0;
@@ -1160,6 +1113,7 @@ std::pair<int64_t, int64_t> trace_impl(gbs_ctx* ctx, const gbs_scene* sc, const 
         GBS_HIP(hipStreamSynchronize(st));
         GBS_CHECK(!(h_bad & 1), "fan.dirs must be unit vectors");
         GBS_CHECK(!(h_bad & 2), "fan.ray_src must be non-decreasing and in [0, n_src)");
+        GBS_CHECK(!(h_bad & 4), "fan.e1 must be unit vectors normal to the directions");
         if (!out) {
             ctx->trace_token = ++ctx->trace_token_next;
             ctx->trace_sig = trace_signature(sc, fan);
@@ -1176,12 +1130,13 @@ std::pair<int64_t, int64_t> trace_impl(gbs_ctx* ctx, const gbs_scene* sc, const 
               "table outputs must be non-null");
     GBS_CHECK(tot[1] == 0 || out->face_ids, "face_ids must be non-null");
     GBS_CHECK(out->face_ptr, "face_ptr must be non-null");
+    GBS_CHECK(!out->e1 || fan->e1, "the frame output needs launch frames (fan.e1)");
     if (n > 0)
         hipLaunchKernelGGL(k_trace<false>, grid, block, 0, st, n, fan->n_src, fan->src_xyz, fan->ray_src,
                            fan->dirs, fan->s_max_src, d_box, d_gbox, d_mem, n_groups, sc->panels, sc->max_refl,
                            sc->s_max, sc->image_complete,
                            nullptr, nullptr, rp, fbase, out->a, out->t, out->s0, out->lo, out->hi, out->face_ptr,
-                           out->face_ids);
+                           out->face_ids, fan->e1, out->e1);
     hipLaunchKernelGGL(k_trace_close, dim3(1), dim3(64), 0, st, fbase, n, tot[0], out->face_ptr);
     GBS_HIP(hipGetLastError());
     return {tot[0], tot[1]};
@@ -1249,7 +1204,6 @@ void gbs_destroy(gbs_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->copy_stream) (void)hipStreamSynchronize(ctx->copy_stream);
     ctx->ws.reset();
-    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     for (int i = 0; i < 2; ++i) {
         if (ctx->copied[i]) (void)hipEventDestroy(ctx->copied[i]);
         if (ctx->released[i]) (void)hipEventDestroy(ctx->released[i]);
@@ -1286,27 +1240,25 @@ int gbs_forward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const 
 
 int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces, const double* rcv,
                  int64_t n_rcv, const double* freqs, int32_t n_freq, const double* eps, const gbs_params* params,
-                 const double* lambda, double* d_gamma, double* d_rcv, double* d_eps) {
+                 const double* lambda, double* d_gamma, double* d_rcv, double* d_eps, double* d_eps_e2) {
     if (!ctx) return GBS_E_INVALID;
     return guarded(ctx, [&]() {
         GBS_HIP(hipSetDevice(ctx->device));
         Args a{rays, segs, faces, rcv, n_rcv, freqs, n_freq, eps, params};
         validate_host(a);
         GBS_CHECK(params->mode != GBS_MODE_F32, "the adjoint supports F64 and MIX");
-        if (params->eps_e2) throw GbsError(GBS_E_UNSUPPORTED, "the adjoint supports isotropic beams only");
         Workspace& ws = *ctx->ws;
         Planner pl(ctx, ws, a, 1);
         hipStream_t st = ctx->stream;
         const int n_jobs = pl.n_jobs;
         const int64_t n_out = (int64_t)n_jobs * n_rcv;
         GBS_CHECK(lambda || n_out == 0, "null lambda");
-        pl.read_job_inputs();
         const int32_t nf = faces->n_faces;
         double* Zf = ws.get<double>("Zf", 2 * std::max(nf, 1));
-        double* dE = ws.get<double>("dE", std::max(n_jobs, 1));
+        double* dE = ws.get<double>("dE", std::max(2 * n_jobs, 1));   // d_eps, then d_eps_e2
         double* dRj = ws.get<double>("dR_job", std::max<int64_t>(3 * n_out, 1));
         fill(st, Zf, 2 * nf, 0.0);
-        fill(st, dE, n_jobs, 0.0);
+        fill(st, dE, 2 * n_jobs, 0.0);
         fill(st, dRj, 3 * n_out, 0.0);
         gbs_stats stats{};
         stats.patch_rcv = 64;
@@ -1337,16 +1289,19 @@ int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
                 fill(st, reinterpret_cast<double*>(Sseg), 4 * nseg, 0.0);
                 if (L.n_items > 0 && L.total > 0) {
                     const bool f64 = params->mode == GBS_MODE_F64, ab = pl.absorb();
-                    auto kern = f64 ? (ab ? k_adjoint<4> : k_adjoint<0>) : (ab ? k_adjoint<5> : k_adjoint<1>);
+                    auto kern = pl.aniso()
+                                    ? (f64 ? (ab ? k_adjoint<12> : k_adjoint<8>) : (ab ? k_adjoint<13> : k_adjoint<9>))
+                                    : (f64 ? (ab ? k_adjoint<4> : k_adjoint<0>) : (ab ? k_adjoint<5> : k_adjoint<1>));
                     double* part = ws.get<double>("adj_partial", L.work_cap * 64 * 3);
-                    double* epart = ws.get<double>("eps_partial", L.work_cap);
+                    double* epart = ws.get<double>("eps_partial", 2 * L.work_cap);   // eps, then eps_e2
                     const int64_t grid = persistent_grid(ctx, (const void*)kern, L.work_cap);
                     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, ctr);
                     EventPair ev(timed);
                     ev.begin(st);
                     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPairThreads), 0, st, L.jobs, L.work,
-                                       L.n_work, pl.R.n_patch, ctr, L.lists, L.rec, pl.R.rx, pl.R.ry, pl.R.rz,
-                                       pl.R.r2, pl.R.perm, n_rcv, lambda, part, L.seg_perm, Sseg, fscale, epart);
+                                       L.n_work, pl.R.n_patch, ctr, L.lists, L.rec, L.frames, pl.R.rx, pl.R.ry,
+                                       pl.R.rz, pl.R.r2, pl.R.perm, n_rcv, lambda, part, L.seg_perm, Sseg, fscale,
+                                       epart, epart + L.work_cap);
                     GBS_HIP(hipGetLastError());
                     stats.ms_pairs += ev.end(st);
                     hipLaunchKernelGGL(k_reduce_adjoint, dim3(blocks_for((int64_t)L.n_items * 64, 256)), dim3(256), 0,
@@ -1354,6 +1309,9 @@ int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
                                        n_rcv, part, dRj);
                     hipLaunchKernelGGL(k_reduce_eps, dim3(n_jobs), dim3(256), 0, st, L.item_wbase, L.item_wcount,
                                        pl.R.n_patch, epart, dE);
+                    if (pl.aniso())
+                        hipLaunchKernelGGL(k_reduce_eps, dim3(n_jobs), dim3(256), 0, st, L.item_wbase,
+                                           L.item_wcount, pl.R.n_patch, epart + L.work_cap, dE + n_jobs);
                     GBS_HIP(hipGetLastError());
                 }
                 if (nf > 0 && nseg > 0) {
@@ -1376,6 +1334,8 @@ int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
                                d_rcv);
         if (d_eps && n_jobs > 0)
             GBS_HIP(hipMemcpyAsync(d_eps, dE, sizeof(double) * n_jobs, hipMemcpyDeviceToDevice, st));
+        if (d_eps_e2 && n_jobs > 0 && params->eps_e2)
+            GBS_HIP(hipMemcpyAsync(d_eps_e2, dE + n_jobs, sizeof(double) * n_jobs, hipMemcpyDeviceToDevice, st));
         GBS_HIP(hipGetLastError());
         int h_status = 0;
         if (pl.status) GBS_HIP(hipMemcpyAsync(&h_status, pl.status, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1407,7 +1367,6 @@ int gbs_graph_create(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, c
         Planner pl(ctx, ws, a, nr);
         hipStream_t st = ctx->stream;
         const int64_t n_out = (int64_t)pl.n_jobs * n_rcv;
-        pl.read_job_inputs();
         // plan every pass once (each pass keeps its own lists and work units);
         // a replay re-stages each pass's table (host tables: copies captured
         // from pinned memory), rebuilds its records and runs its pair kernel
@@ -1445,8 +1404,8 @@ int gbs_graph_create(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, c
                 // coefficients may change between replays: rebuild the records
                 hipLaunchKernelGGL(k_records, dim3(blocks_for(v.n_segs, 256)), dim3(256), 0, st, v.n_segs, v.a, v.t,
                                    v.s0, v.lo, v.hi, v.face_ptr, v.face_base, v.face_ids, faces->n_faces,
-                                   faces->gamma, v.ray_w, seg_ray, v.n_rays, pl.face_end(pl.passes[pi]), rec,
-                                   pl.status, nullptr);
+                                   faces->gamma, v.ray_w, seg_ray, v.n_rays, pl.face_end_dev(),
+                                   pl.face_end_host(pl.passes[pi]), rec, pl.status, nullptr);
                 L.rec = rec;
                 if (L.seg_perm) {   // into the spatial order planned at creation
                     SegRec* rs = ws.get<SegRec>("rec_sorted", v.n_segs);
@@ -1588,12 +1547,13 @@ int gbs_trace_count(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, in
 
 int gbs_trace(gbs_ctx* ctx, const gbs_scene* scene, const gbs_fan* fan, int64_t token, int64_t cap_segs,
               int64_t cap_face_ids, int64_t* ray_ptr, double* seg_a, double* seg_t, double* seg_s0, double* seg_lo,
-              double* seg_hi, int64_t* face_ptr, int32_t* face_ids, int64_t* n_segs, int64_t* n_face_ids) {
+              double* seg_hi, int64_t* face_ptr, int32_t* face_ids, double* seg_e1, int64_t* n_segs,
+              int64_t* n_face_ids) {
     if (!ctx) return GBS_E_INVALID;
     return guarded(ctx, [&]() {
         GBS_CHECK(ray_ptr, "ray_ptr must be non-null");
         GBS_HIP(hipSetDevice(ctx->device));
-        const TraceOut o{ray_ptr, seg_a, seg_t, seg_s0, seg_lo, seg_hi, face_ptr, face_ids};
+        const TraceOut o{ray_ptr, seg_a, seg_t, seg_s0, seg_lo, seg_hi, face_ptr, face_ids, seg_e1};
         const auto r = trace_impl(ctx, scene, fan, cap_segs, cap_face_ids, &o, token);
         if (n_segs) *n_segs = r.first;
         if (n_face_ids) *n_face_ids = r.second;

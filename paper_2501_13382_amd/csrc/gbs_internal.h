@@ -55,8 +55,18 @@ struct SegRec {
     double mot;               // -o.t
     double slo, shi;          // beam interval in arc length [s0 + lo, s0 + hi)
     double wgr, wgi;          // ray solid angle times the reflection-coefficient product
+    double wph, pad;          // the weight's argument / (2 pi) (cycles)
 };
-static_assert(sizeof(SegRec) == 96, "SegRec layout");
+static_assert(sizeof(SegRec) == 112, "SegRec layout");
+
+// The ray frame of a segment for anisotropic beams (job independent): unit
+// vectors e1 and e2 = t x e1 normal to the axis, with -o.e1 and -o.e2, so that
+// the offsets of R along them are R.e1 - o.e1 and R.e2 - o.e2.
+struct FrameRec {
+    double e1x, e1y, e1z, moe1;
+    double e2x, e2y, e2z, moe2;
+};
+static_assert(sizeof(FrameRec) == 64, "FrameRec layout");
 
 struct Patch {
     double cx, cy, cz, rad;   // bounding sphere of a receiver patch
@@ -89,7 +99,8 @@ enum StatusBit : int {
     kBadRayWeight = 16,   // non-finite or negative ray weight
     kBadReceiver = 32,    // non-finite receiver coordinate
     kBadRaySource = 64,   // ray_src outside [0, n_src) or not non-decreasing
-    kBadLambda = 128      // non-finite adjoint weight lambda
+    kBadLambda = 128,     // non-finite adjoint weight lambda
+    kBadJob = 256         // frequency, beam parameter or absorption non-finite or out of range
 };
 
 // Exact, order-independent accumulation of doubles (deterministic sums with

@@ -274,7 +274,8 @@ __global__ __launch_bounds__(64) void k_sphere_of_spheres(const Patch* __restric
 // n_segs), the source order and face_ptr[0] = 0.
 __global__ void k_src_ranges(const int64_t* __restrict__ ray_ptr, const int32_t* __restrict__ ray_src,
                              int64_t n_rays, int32_t n_src, int64_t n_segs, const int64_t* __restrict__ face_ptr,
-                             int64_t* __restrict__ src_off, int* __restrict__ status) {
+                             int face_ids_given, int32_t n_faces, int64_t* __restrict__ src_off,
+                             int* __restrict__ status) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i > n_rays) return;
     const int32_t rp = i == 0 ? -1 : ray_src[i - 1], rc = i == n_rays ? n_src : ray_src[i];
@@ -283,12 +284,94 @@ __global__ void k_src_ranges(const int64_t* __restrict__ ray_ptr, const int32_t*
     const int64_t p = ray_ptr[i];
     if (i == 0 ? p != 0 : p < ray_ptr[i - 1]) bad |= kBadRayPtr;
     if (i == n_rays && p != n_segs) bad |= kBadRayPtr;
-    if (i == 0 && face_ptr && face_ptr[0] != 0) bad |= kBadFacePtr;
+    if (i == 0 && face_ptr) {
+        const int64_t total = face_ptr[n_segs];
+        if (face_ptr[0] != 0 || total < 0 || (total > 0 && !face_ids_given)) bad |= kBadFacePtr;
+        if (total > 0 && n_faces <= 0) bad |= kBadFaceId;
+    }
     if (bad) atomicOr(status, bad);
     // clamped so that an unsorted or out-of-range table cannot write outside src_off
     int32_t prev = min(max(rp, -1), n_src);
     int32_t cur = min(max(rc, -1), n_src);
     for (int32_t s = prev + 1; s <= cur; ++s) src_off[s] = p;
+}
+
+// Per-job constants of one pass (one thread per job), from the band
+// frequencies, the beam parameters, the optional absorption and second beam
+// parameter, and the sources' segment ranges; flags invalid job inputs.
+// Anisotropic beams: the cull and the pre-gate use the envelope of the two
+// widths (it keeps every pair the exact gate keeps), widened by a relative
+// 1e-12 against rounding; the pair kernel applies the exact gate.
+__global__ void k_job_consts(const double* __restrict__ freqs, const double* __restrict__ eps,
+                             const double* __restrict__ alpha, const double* __restrict__ eps_e2, int32_t n_src,
+                             int32_t n_freq, double c, double G, const int64_t* __restrict__ src_off,
+                             int64_t pass_begin, int64_t pass_end, JobConst* __restrict__ jobs,
+                             int* __restrict__ status) {
+    const int job = blockIdx.x * blockDim.x + threadIdx.x;
+    if (job >= n_src * n_freq) return;
+    const int s = job / n_freq, b = job - s * n_freq;
+    constexpr double pi = 3.14159265358979323846, log2e = 1.4426950408889634;
+    const double f = freqs[b], e = eps[job], al = alpha ? alpha[job] : 0.0, eb = eps_e2 ? eps_e2[job] : e;
+    if (!(isfinite(f) && f > 0.0 && isfinite(e) && e > 0.0 && isfinite(al) && al >= 0.0 && isfinite(eb) &&
+          eb > 0.0))
+        atomicOr(status, kBadJob);
+    const double k = 2.0 * pi * f / c;
+    const double ke = k * e;
+    JobConst j;
+    j.seg_begin = max(src_off[s], pass_begin) - pass_begin;
+    j.seg_end = min(src_off[s + 1], pass_end) - pass_begin;
+    if (j.seg_end < j.seg_begin) j.seg_end = j.seg_begin;
+    j.k = k;
+    j.eps = e;
+    j.eps2 = e * e;
+    j.gate_c1 = 1.0 + 2.0 * G / ke;
+    j.gate_c2 = 2.0 * G * e * e / ke;
+    j.kappa = 2.0 * G / ke;
+    j.fk = f / c;
+    j.hfk = 0.5 * f / c;
+    j.gexp2 = -0.5 * ke * log2e;
+    j.gexp = -0.5 * ke;
+    j.scale = ke / (8.0 * pi * pi);
+    j.aexp = -al;
+    j.aexp2 = j.aexp * log2e;
+    j.epsb = e;
+    j.epsa2 = e * e;
+    j.epsb2 = e * e;
+    j.gate_a = 2.0 * G / k;
+    j.gexpa = -0.5 * k;
+    j.gexpa2 = -0.5 * k * log2e;
+    j.ampc = 0.5 * e;
+    if (eps_e2) {
+        const double margin = 1.0 + 1e-12;
+        j.epsb = eb;
+        j.epsb2 = eb * eb;
+        j.ampc = 0.5 * sqrt(e * eb);
+        j.kappa = 2.0 * G / (k * fmin(e, eb)) * margin;
+        j.eps2 = e * eb * margin;
+        j.gate_c1 = 1.0 + j.kappa;
+        j.gate_c2 = j.kappa * j.eps2;
+        j.scale = k / (8.0 * pi * pi);
+    }
+    j.src = s;
+    j.band = b;
+    jobs[job] = j;
+}
+
+// The cull's pieces of a pass: every source's segment range [src_off[s],
+// src_off[s+1]) inside the pass cut into pieces of `span` segments, in source
+// order (one thread; at most n_src + n_segs / span pieces).
+__global__ void k_make_splits(const int64_t* __restrict__ src_off, int32_t n_src, int64_t pass_begin,
+                              int64_t pass_end, int64_t span, int32_t max_splits, CullSplit* __restrict__ splits,
+                              int32_t* __restrict__ n_splits) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int32_t n = 0;
+    for (int32_t s = 0; s < n_src; ++s) {
+        const int64_t b = max(src_off[s], pass_begin) - pass_begin, e = min(src_off[s + 1], pass_end) - pass_begin;
+        int32_t k = 0;
+        for (int64_t x = b; x < e && n < max_splits; x += span, ++k)
+            splits[n++] = CullSplit{x, min(x + span, e), s, k};
+    }
+    *n_splits = n;
 }
 
 // seg_ray[j] = index (within the pass) of the ray that owns segment j.
@@ -303,7 +386,8 @@ __global__ void k_seg2ray(const int64_t* __restrict__ ray_ptr, int64_t n_rays, i
 // Segment records: virtual-source anchoring, arc-length interval and the
 // complex weight w * prod(Gamma) over the faces hit before the segment.
 // Checks the segment's values, its face-history range (inside
-// [face_base, face_end], absolute offsets) and ids, and its ray (status bits); bad
+// [face_base, face_end], absolute offsets; face_end read from face_end_p when
+// given) and ids, and its ray (status bits); bad
 // entries are skipped, never read out of range.  With bmax, also the largest
 // w * (history length) * prod max(1, |Gamma|) over the pass (a bound on the
 // coefficient derivatives, for the adjoint's exact face sums).
@@ -312,8 +396,9 @@ __global__ void k_records(int64_t n_segs, const double* __restrict__ a, const do
                           const double* __restrict__ hi, const int64_t* __restrict__ face_ptr,
                           int64_t face_base, const int32_t* __restrict__ face_ids, int32_t n_faces,
                           const double* __restrict__ gamma, const double* __restrict__ ray_w,
-                          const int32_t* __restrict__ seg_ray, int64_t n_rays, int64_t face_end,
-                          SegRec* __restrict__ rec, int* __restrict__ status, unsigned long long* __restrict__ bmax) {
+                          const int32_t* __restrict__ seg_ray, int64_t n_rays,
+                          const int64_t* __restrict__ face_end_p, int64_t face_end_h, SegRec* __restrict__ rec,
+                          int* __restrict__ status, unsigned long long* __restrict__ bmax) {
     int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= n_segs) return;
     int bad = 0;
@@ -334,6 +419,7 @@ __global__ void k_records(int64_t n_segs, const double* __restrict__ a, const do
         if (!(isfinite(gr) && gr >= 0.0)) bad |= kBadRayWeight;
     }
     const int64_t f0 = face_ptr[j], f1 = face_ptr[j + 1];
+    const int64_t face_end = face_end_p ? *face_end_p : face_end_h;
     double gmax = 1.0;
     if (!(face_base <= f0 && f0 <= f1 && f1 <= face_end)) {
         bad |= kBadFacePtr;
@@ -369,6 +455,8 @@ __global__ void k_records(int64_t n_segs, const double* __restrict__ a, const do
     r.shi = s + l1;
     r.wgr = gr;
     r.wgi = gi;
+    r.wph = atan2(gi, gr) * (0.5 / 3.14159265358979323846);
+    r.pad = 0.0;
     rec[j] = r;
 }
 
@@ -401,6 +489,56 @@ __global__ void k_seg_keys(int64_t n_segs, const SegRec* __restrict__ rec, const
 // out[i] = in[perm[i]] for 96-byte segment records.
 __global__ void k_permute_rec(int64_t n, const SegRec* __restrict__ in, const int32_t* __restrict__ perm,
                               SegRec* __restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = in[perm[i]];
+}
+
+// Ray frames of a pass (table order): e1 given per segment (checked: unit and
+// normal to t within 1e-9), or, without one, e1 = z x t / |z x t| (the x axis
+// when t is vertical); e2 = t x e1; -o.e_m with o = a - s0 t.
+__global__ void k_frames(int64_t n_segs, const double* __restrict__ a, const double* __restrict__ t,
+                         const double* __restrict__ s0, const double* __restrict__ e1, FrameRec* __restrict__ out,
+                         int* __restrict__ status) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n_segs) return;
+    const double tx = t[3 * j], ty = t[3 * j + 1], tz = t[3 * j + 2];
+    double ex, ey, ez;
+    if (e1) {
+        ex = e1[3 * j];
+        ey = e1[3 * j + 1];
+        ez = e1[3 * j + 2];
+        const double nn = ex * ex + ey * ey + ez * ez, d = ex * tx + ey * ty + ez * tz;
+        if (!(fabs(nn - 1.0) <= 2e-9 && fabs(d) <= 1e-9)) atomicOr(status, kBadSegment);
+    } else {
+        const double h2 = fma(tx, tx, ty * ty);
+        ex = 1.0;
+        ey = 0.0;
+        ez = 0.0;
+        if (h2 > 0.0) {
+            const double rh = 1.0 / sqrt(h2);
+            ex = -ty * rh;
+            ey = tx * rh;
+        }
+    }
+    const double fx = ty * ez - tz * ey, fy = tz * ex - tx * ez, fz = tx * ey - ty * ex;
+    const double s = s0[j];
+    const double ox = a[3 * j] - s * tx, oy = a[3 * j + 1] - s * ty, oz = a[3 * j + 2] - s * tz;
+    FrameRec f;
+    f.e1x = ex;
+    f.e1y = ey;
+    f.e1z = ez;
+    f.moe1 = -(ox * ex + oy * ey + oz * ez);
+    f.e2x = fx;
+    f.e2y = fy;
+    f.e2z = fz;
+    f.moe2 = -(ox * fx + oy * fy + oz * fz);
+    out[j] = f;
+}
+
+// out[i] = in[perm[i]] for frame records.
+__global__ void k_permute_frames(int64_t n, const FrameRec* __restrict__ in, const int32_t* __restrict__ perm,
+                                 FrameRec* __restrict__ out) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     out[i] = in[perm[i]];
@@ -506,8 +644,10 @@ __global__ __launch_bounds__(kCullThreads) void k_cull_hyper(const JobConst* __r
                                                              const Patch* __restrict__ hypers, int n_hyper,
                                                              int n_freq, int chunks_per_split,
                                                              const CullSplit* __restrict__ splits,
+                                                             const int32_t* __restrict__ n_splits,
                                                              unsigned long long* __restrict__ hmask) {
     constexpr int kWaves = kCullThreads / kWave;
+    if ((int)blockIdx.y >= *n_splits) return;     // the grid covers the most pieces a pass can have
     const CullSplit sl = splits[blockIdx.y];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t j = sl.begin + (int64_t)blockIdx.x * kCullThreads + tid;
@@ -553,6 +693,7 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
                                                 const Patch* __restrict__ patches, const Patch* __restrict__ supers,
                                                 int n_patch, int n_freq, int n_split,
                                                 const CullSplit* __restrict__ splits,
+                                                const int32_t* __restrict__ n_splits,
                                                 const unsigned long long* __restrict__ hmask, int n_hyper,
                                                 int chunks_per_split, int32_t* __restrict__ counts,
                                                 const int64_t* __restrict__ off, int32_t* __restrict__ lists) {
@@ -564,6 +705,7 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
     __shared__ unsigned long long q_mask[kQ];
     __shared__ int64_t cur_s[kSuperPatches * kNB];        // cursor of (patch pm, band b) at pm * kNB + b
     const int sp = blockIdx.x;
+    if ((int)blockIdx.y >= *n_splits) return;             // the grid covers the most pieces a pass can have
     const CullSplit sl = splits[blockIdx.y];
     const int lane = threadIdx.x;
     const int64_t job0 = (int64_t)sl.src * n_freq;
@@ -780,6 +922,13 @@ struct Beam<kF64> {
     }
 };
 
+// MIX: the gate, the arc length s, the squared normal distance n^2, 1/den
+// (FP32 reciprocal and one Newton step), a = n^2/den and the phase in cycles,
+// (f/c) s (1 + a/2) + arg(w Gamma)/(2 pi), reduced modulo one, in FP64 (the
+// correction (f/2c) s a alone reaches G s / (2 pi eps) cycles at the gate's
+// edge, hundreds for narrow beams); the Gaussian, sine and cosine, and the
+// amplitude in FP32, with the weight as its modulus times (s + i eps) and its
+// argument carried by the phase.
 template <>
 struct Beam<kMIX> {
     using T = float;
@@ -798,18 +947,14 @@ struct Beam<kMIX> {
         const double r0 = (double)r0f;
         const double rden = fma(r0, fma(-den, r0, 1.0), r0);                 // one Newton step
         const double a = n2 * rden;
-        const double cyc = s * fma(J.hfk, a, J.fk);                          // phase in cycles, FP64
-        const float ph = (float)__builtin_amdgcn_fract(cyc);                 // reduced modulo one in FP64
+        const float ph = (float)__builtin_amdgcn_fract(fma(s, fma(J.hfk, a, J.fk), S.pad));
         const float sn = __builtin_amdgcn_sinf(ph);                          // sin(2 pi ph)
         const float cs = __builtin_amdgcn_cosf(ph);
         const float sf = (float)s;
-        // Gaussian (and absorption) exponent, base 2
-        const float gg = (float)(a * J.gexp2);
+        const float gg = (float)a * (float)J.gexp2;                          // Gaussian exponent, base 2
         const float g2 = live ? (ABS ? fmaf(sf, (float)J.aexp2, gg) : gg) : -INFINITY;
-        const float w = r0f * __builtin_amdgcn_exp2f(g2);
-        const float4 W = tile_weights(S);
-        const float cr = fmaf(sf, W.x, -W.w) * w;
-        const float ci = fmaf(sf, W.y, W.z) * w;
+        const float w = r0f * __builtin_amdgcn_exp2f(g2) * *reinterpret_cast<const float*>(&S.wgr);
+        const float cr = sf * w, ci = (float)J.eps * w;                      // |w Gamma| (s + i eps) / den e^g
         ur = cr * cs - ci * sn;
         ui = cr * sn + ci * cs;
     }
@@ -846,11 +991,10 @@ struct Beam<kF32> {
 };
 
 // Anisotropic beams: Eq. (1) with Q = diag(q1, q2), q_m = s - i eps_m, and
-// P = I/c (Eq. (2) in a homogeneous medium), in the ray frame
-//   e1 = z x t / |z x t| (the x axis when t is vertical),  e2 = t x e1.
-// A reflection on the ground, a roof or a wall maps e1 to plus or minus the e1
-// of the reflected axis, so this frame is the transported one in scenes of
-// axis-aligned faces; only n1^2 and n2^2 enter.  With
+// P = I/c (Eq. (2) in a homogeneous medium), in the segment's ray frame
+// (e1, e2 = t x e1) from the table (FrameRec; by default e1 = z x t / |z x t|,
+// the frame the ground, roofs and walls of the box scenes transport); only
+// n1^2 and n2^2 enter.  With
 //   n1 = (R - o).e1,  n2^2 = n^2 - n1^2,  den_m = s^2 + eps_m^2,  a_m = n_m^2/den_m:
 //   Gaussian exp(-(k/2)(eps a1 + epsb a2)), kept iff eps a1 + epsb a2 <= 2G/k,
 //   phase (f/c) s (1 + (a1 + a2)/2) cycles,
@@ -864,9 +1008,10 @@ struct Beam<kF32> {
 // its decision.
 struct TileRecA {
     TileRec b;           // isotropic record; b.pad holds -o.e1
-    double e1x, e1y;     // frame vector e1 (its z component is zero)
+    double e1x, e1y;     // frame vector e1
+    double e1z, pad;
 };
-static_assert(sizeof(TileRecA) == 128, "TileRecA layout");
+static_assert(sizeof(TileRecA) == 144, "TileRecA layout");
 
 // 1/d from the FP32 reciprocal and one Newton step in FP64.
 __device__ __forceinline__ double rcp_newton(double d) {
@@ -876,7 +1021,7 @@ __device__ __forceinline__ double rcp_newton(double d) {
 
 struct GeoA {
     double s, l;         // as Beam<kF64>::Geo
-    double x, y;         // receiver x, y (for n1)
+    double x, y, z;      // receiver (for n1)
 };
 
 template <int MODE>
@@ -894,6 +1039,7 @@ struct BeamA<kMIX> {
         g.l = h.l;
         g.x = X;
         g.y = Y;
+        g.z = Z;
         return k;
     }
     template <bool ABS>
@@ -901,7 +1047,7 @@ struct BeamA<kMIX> {
                                                 float& ur, float& ui) {
         const double s = g.s;
         const double nn = fma(-s, s, g.l + S.b.oo);                      // n1^2 + n2^2
-        const double n1 = fma(g.x, S.e1x, fma(g.y, S.e1y, S.b.pad));     // offset along e1
+        const double n1 = fma(g.x, S.e1x, fma(g.y, S.e1y, fma(g.z, S.e1z, S.b.pad)));     // offset along e1
         const double q1 = n1 * n1;
         const double q2 = nn - q1;                                       // offset^2 along e2
         const double den1 = fma(s, s, J.epsa2), den2 = fma(s, s, J.epsb2);
@@ -948,7 +1094,7 @@ struct BeamA<kF64> {
                                                 double& ur, double& ui) {
         const double s = g.s;
         const double nn = fma(-s, s, g.l + S.b.oo);
-        const double n1 = fma(g.x, S.e1x, fma(g.y, S.e1y, S.b.pad));
+        const double n1 = fma(g.x, S.e1x, fma(g.y, S.e1y, fma(g.z, S.e1z, S.b.pad)));
         const double q1 = n1 * n1;
         const double q2 = nn - q1;
         const double den1 = fma(s, s, J.epsa2), den2 = fma(s, s, J.epsb2);
@@ -978,7 +1124,7 @@ struct BeamA<kF64> {
 template <>
 struct BeamA<kF32> {
     using T = float;
-    struct Geo { float s, n2, x, y; };
+    struct Geo { float s, n2, x, y, z; };
     __device__ __forceinline__ static bool gate(const TileRecA& S, const JobConst& J, double X, double Y, double Z,
                                                 double R2, Geo& g) {
         Beam<kF32>::Geo h;
@@ -987,13 +1133,14 @@ struct BeamA<kF32> {
         g.n2 = h.n2;
         g.x = (float)X;
         g.y = (float)Y;
+        g.z = (float)Z;
         return k;
     }
     template <bool ABS>
     __device__ __forceinline__ static bool term(const TileRecA& S, const JobConst& J, const Geo& g, bool live,
                                                 float& ur, float& ui) {
         const float s = g.s;
-        const float n1 = fmaf(g.x, (float)S.e1x, fmaf(g.y, (float)S.e1y, (float)S.b.pad));
+        const float n1 = fmaf(g.x, (float)S.e1x, fmaf(g.y, (float)S.e1y, fmaf(g.z, (float)S.e1z, (float)S.b.pad)));
         const float q1 = n1 * n1;
         const float q2 = fmaxf(g.n2 - q1, 0.0f);
         const float e1 = (float)J.eps, e2 = (float)J.epsb;
@@ -1022,6 +1169,10 @@ struct BeamA<kF32> {
         return in;
     }
 };
+
+// The pair-kernel variants whose tile records carry the weight in polar form.
+template <int MODE>
+constexpr bool kPolar = (MODE & 3) == kMIX && (MODE & kAniso) == 0;
 
 // The beam model and LDS tile record of a pair-kernel variant.
 template <int MODE>
@@ -1082,35 +1233,34 @@ __device__ __forceinline__ int pair_two(const TileOf<MODE>& S0, const TileOf<MOD
     return hit;
 }
 
-// A segment record in registers, as six named 16-byte vectors (kept out of
+// A segment record in registers, as seven named 16-byte vectors (kept out of
 // arrays so the compiler keeps them in VGPRs): vector loads, 128-bit LDS stores.
-#define GBS_REC_REGS(n) double2 n##0, n##1, n##2, n##3, n##4, n##5
+#define GBS_REC_REGS(n) double2 n##0, n##1, n##2, n##3, n##4, n##5, n##6
 #define GBS_REC_LOAD(n, recp, j)                                                  \
     do {                                                                          \
         const double2* p_ = reinterpret_cast<const double2*>((recp) + (j));       \
         n##0 = p_[0]; n##1 = p_[1]; n##2 = p_[2];                                 \
-        n##3 = p_[3]; n##4 = p_[4]; n##5 = p_[5];                                 \
-    } while (0)
-#define GBS_REC_STORE(dst, n)                                                     \
-    do {                                                                          \
-        double2* q_ = reinterpret_cast<double2*>(dst);                            \
-        q_[0] = n##0; q_[1] = n##1; q_[2] = n##2;                                 \
-        q_[3] = n##3; q_[4] = n##4; q_[5] = n##5;                                 \
+        n##3 = p_[3]; n##4 = p_[4]; n##5 = p_[5]; n##6 = p_[6];                   \
     } while (0)
 
-// Builds a lane's tile record from its segment record (six 16-byte vectors in
-// SegRec field order) for job J and stores it to the wave's LDS tile.
-template <int MODE>
+// Builds a lane's tile record from its segment record (seven 16-byte vectors
+// in SegRec field order) for job J and stores it to the wave's LDS tile.
+// POLAR (the isotropic MIX pair kernel): the weight in polar form, its phase
+// in cycles in the spare slot and its modulus as FP32 in place of the complex
+// weight.
+template <int MODE, bool POLAR = false>
 __device__ __forceinline__ void stage_rec(TileRec* dst, double2 r0, double2 r1, double2 r2, double2 r3, double2 r4,
-                                          double2 r5, const JobConst& J) {
+                                          double2 r5, double2 r6, const JobConst& J) {
     double2* q = reinterpret_cast<double2*>(dst);
     q[0] = r0;
     q[1] = make_double2(r1.x, J.gate_c2 - r1.y);
     q[2] = r2;
     q[3] = r3;
     q[4] = r4;
-    q[5] = make_double2(r1.y, 0.0);
-    if (MODE == kF64) {
+    q[5] = make_double2(r1.y, POLAR ? r6.x : 0.0);
+    if (POLAR) {
+        *reinterpret_cast<float4*>(q + 6) = make_float4((float)hypot(r5.x, r5.y), 0.f, 0.f, 0.f);
+    } else if (MODE == kF64) {
         q[6] = r5;
     } else {
         *reinterpret_cast<float4*>(q + 6) =
@@ -1118,24 +1268,23 @@ __device__ __forceinline__ void stage_rec(TileRec* dst, double2 r0, double2 r1, 
     }
 }
 // The anisotropic tile record: the isotropic one plus the frame vector e1 of
-// the segment's axis and -o.e1 (in the isotropic record's spare slot).
+// the segment (f0 = (e1x, e1y), f1 = (e1z, -o.e1) of its FrameRec), with -o.e1
+// in the isotropic record's spare slot.
 template <int MODE>
-__device__ __forceinline__ void stage_rec(TileRecA* dst, double2 r0, double2 r1, double2 r2, double2 r3, double2 r4,
-                                          double2 r5, const JobConst& J) {
-    stage_rec<MODE>(&dst->b, r0, r1, r2, r3, r4, r5, J);
-    const double tx = r2.x, ty = r2.y;
-    const double h2 = fma(tx, tx, ty * ty);
-    double ex = 1.0, ey = 0.0;
-    if (h2 > 0.0) {
-        const double rh = 1.0 / sqrt(h2);
-        ex = -ty * rh;
-        ey = tx * rh;
-    }
-    dst->e1x = ex;
-    dst->e1y = ey;
-    dst->b.pad = 0.5 * fma(r0.x, ex, r0.y * ey);   // -o.e1 from -2 o
+__device__ __forceinline__ void stage_rec_a(TileRecA* dst, double2 r0, double2 r1, double2 r2, double2 r3,
+                                            double2 r4, double2 r5, double2 r6, double2 f0, double2 f1,
+                                            const JobConst& J) {
+    stage_rec<MODE>(&dst->b, r0, r1, r2, r3, r4, r5, r6, J);
+    dst->b.pad = f1.y;
+    double2* q = reinterpret_cast<double2*>(&dst->e1x);
+    q[0] = f0;
+    q[1] = make_double2(f1.x, 0.0);
 }
-#define GBS_STAGE(MODE, dst, n, J) stage_rec<MODE>((dst), n##0, n##1, n##2, n##3, n##4, n##5, (J))
+#define GBS_STAGE(MODE, dst, n, J) stage_rec<MODE>((dst), n##0, n##1, n##2, n##3, n##4, n##5, n##6, (J))
+#define GBS_STAGE_P(MODE, POLAR, dst, n, J) \
+    stage_rec<MODE, POLAR>((dst), n##0, n##1, n##2, n##3, n##4, n##5, n##6, (J))
+#define GBS_STAGE_A(MODE, dst, n, J) \
+    stage_rec_a<MODE>((dst), n##0, n##1, n##2, n##3, n##4, n##5, n##6, n##f0, n##f1, (J))
 
 // Pops the next work item (wave-uniform) from the global counter.  Lane 0
 // issues the atomic.  Callers put branch_barrier() in front of it and issue
@@ -1167,9 +1316,11 @@ __global__ __launch_bounds__(kPairThreads, GBS_PAIR_MIN_WAVES) void k_pairs(cons
                                               const Work* __restrict__ work, const int32_t* __restrict__ n_work_p,
                                               int32_t n_patch, unsigned* __restrict__ ctr,
                                               const int32_t* __restrict__ lists, const SegRec* __restrict__ rec,
+                                              const FrameRec* __restrict__ frames,
                                               const double* __restrict__ rx, const double* __restrict__ ry,
                                               const double* __restrict__ rz, const double* __restrict__ r2,
                                               double* __restrict__ partial, unsigned long long* __restrict__ n_active) {
+    constexpr bool kA = (MODE & kAniso) != 0;
     using Tile = TileOf<MODE>;
     __shared__ __align__(16) Tile tile[kPairThreads / kWave][kWave];
     const int lane = threadIdx.x & (kWave - 1);
@@ -1199,14 +1350,30 @@ __global__ __launch_bounds__(kPairThreads, GBS_PAIR_MIN_WAVES) void k_pairs(cons
         // tile ahead of the tile being evaluated (clamped: the tail re-reads a
         // valid entry, never out of range)
         GBS_REC_REGS(nx);
-        GBS_REC_LOAD(nx, rec, lists[min(beg + lane, end - 1)]);
+        double2 nxf0 = make_double2(0.0, 0.0), nxf1 = nxf0;   // frame (anisotropic beams)
+        const int32_t idx_first = lists[min(beg + lane, end - 1)];
+        GBS_REC_LOAD(nx, rec, idx_first);
+        if constexpr (kA) {
+            const double2* f_ = reinterpret_cast<const double2*>(frames + idx_first);
+            nxf0 = f_[0];
+            nxf1 = f_[1];
+        }
         int32_t idx_ahead = lists[min(beg + kWave + lane, end - 1)];
         for (int64_t e0 = beg; e0 < end; e0 += kWave) {
             const int cnt = (int)min<int64_t>(kWave, end - e0);
             wave_lds_fence();
-            GBS_STAGE((MODE & 3), my + lane, nx, J);
+            if constexpr (kA) {
+                GBS_STAGE_A((MODE & 3), my + lane, nx, J);
+            } else {
+                GBS_STAGE_P((MODE & 3), kPolar<MODE>, my + lane, nx, J);
+            }
             wave_lds_fence();
             GBS_REC_LOAD(nx, rec, idx_ahead);
+            if constexpr (kA) {
+                const double2* f_ = reinterpret_cast<const double2*>(frames + idx_ahead);
+                nxf0 = f_[0];
+                nxf1 = f_[1];
+            }
             idx_ahead = lists[min(e0 + 2 * kWave + lane, end - 1)];
             int k = 0;
 #ifndef GBS_PAIR_SINGLE
@@ -1433,29 +1600,143 @@ __device__ __forceinline__ bool adj_eval(const TileRec& S, const JobConst& J, do
     return true;
 }
 
+// Anisotropic adjoint (Eq. (1) with Q = diag(q1, q2)).  With n_m the
+// offsets along the frame vectors, 1/q_m = (s + i eps_m)/den_m and
+// n_m^2/q_m^2 = n_m^2 (s^2 - eps_m^2 + 2 i eps_m s)/den_m^2:
+//   d ln u/dR     = t (ik - (1/q1 + 1/q2)/2 - (ik/2)(n1^2/q1^2 + n2^2/q2^2) - alpha)
+//                   + (ik n1/q1) e1 + (ik n2/q2) e2
+//   d ln u/deps_m = (1/eps_m + i/q_m)/2 - (k/2) n_m^2/q_m^2
+// and the coefficient sums take B = u/(scale w prod Gamma) as for isotropic
+// beams.  The tile record adds the whole frame.
+struct TileRecAdj {
+    TileRec b;               // isotropic record; b.pad holds -o.e1
+    double e1x, e1y, e1z, moe2;
+    double e2x, e2y, e2z, pad;
+};
+static_assert(sizeof(TileRecAdj) == 176, "TileRecAdj layout");
+
+template <int MODE>
+__device__ __forceinline__ void stage_rec_adj(TileRecAdj* dst, double2 r0, double2 r1, double2 r2, double2 r3,
+                                              double2 r4, double2 r5, double2 r6, double2 f0, double2 f1,
+                                              double2 f2, double2 f3, const JobConst& J) {
+    stage_rec<MODE>(&dst->b, r0, r1, r2, r3, r4, r5, r6, J);
+    dst->b.pad = f1.y;
+    double2* q = reinterpret_cast<double2*>(&dst->e1x);
+    q[0] = f0;
+    q[1] = make_double2(f1.x, f3.y);
+    q[2] = f2;
+    q[3] = make_double2(f3.x, 0.0);
+}
+
+struct AdjAccA {
+    double x, y, z, e1, e2;   // dL/dR and the two beam-parameter sums
+};
+
+template <int MODE, typename ST>
+__device__ __forceinline__ bool adj_eval_aniso(const TileRecAdj& S, const JobConst& J, double X, double Y, double Z,
+                                               double R2, ST lr, ST li, AdjAccA& acc, ST& Sr, ST& Si) {
+    constexpr bool ABS = (MODE & kAbsorb) != 0;
+    constexpr bool F64 = (MODE & 3) == kF64;
+    using T = ST;
+    Beam<kF64>::Geo g;
+    const bool keep = Beam<kF64>::gate(S.b, J, X, Y, Z, R2, g);    // envelope pre-gate
+    if (__ballot(keep) == 0ull) return false;                        // wave-uniform skip
+    branch_barrier();
+    if (!keep) return false;
+    const double s = g.s;
+    const double nn = fma(-s, s, g.l + S.b.oo);
+    const double n1 = fma(X, S.e1x, fma(Y, S.e1y, fma(Z, S.e1z, S.b.pad)));
+    const double n2 = fma(X, S.e2x, fma(Y, S.e2y, fma(Z, S.e2z, S.moe2)));
+    const double q1 = n1 * n1, q2 = nn - q1;                         // as the forward's exact gate
+    const double den1 = fma(s, s, J.epsa2), den2 = fma(s, s, J.epsb2);
+    const double rd1 = F64 ? 1.0 / den1 : rcp_newton(den1), rd2 = F64 ? 1.0 / den2 : rcp_newton(den2);
+    const double a1 = q1 * rd1, a2 = q2 * rd2;
+    const double e = fma(J.eps, a1, J.epsb * a2);
+    if (!(e <= J.gate_a)) return false;
+    const double cyc = s * fma(J.hfk, a1 + a2, J.fk);
+    T sn, cs, w;
+    if constexpr (F64) {
+        const double ph = cyc - floor(cyc);
+        sincospi(2.0 * ph, &sn, &cs);
+        w = exp(ABS ? fma(s, J.aexp, e * J.gexpa) : e * J.gexpa);
+    } else {
+        const float ph = (float)__builtin_amdgcn_fract(cyc);
+        sn = __builtin_amdgcn_sinf(ph);
+        cs = __builtin_amdgcn_cosf(ph);
+        const float gg = (float)(e * J.gexpa2);
+        w = __builtin_amdgcn_exp2f(ABS ? fmaf((float)s, (float)J.aexp2, gg) : gg);
+    }
+    // B = i sqrt(q01/q1) sqrt(q02/q2) e^{i phase} e^{g}
+    const T st = (T)s, e1 = (T)J.eps, e2 = (T)J.epsb, k = (T)J.k;
+    const T d1 = sqrt((T)den1), d2 = sqrt((T)den2);
+    const T b1 = d1 + e1, b2 = d2 + e2;
+    const T re = st * (b1 + b2), im = b1 * b2 - st * st;
+    const T pre = (T)J.ampc / sqrt((T)den1 * (T)den2 * (b1 * b2)) * w;
+    const T ar = re * pre, ai = im * pre;
+    const T Br = ar * cs - ai * sn, Bi = ar * sn + ai * cs;
+    T wr, wi;
+    if constexpr (F64) {
+        wr = S.b.wgr;
+        wi = S.b.wgi;
+    } else {
+        const float4 W = tile_weights(S.b);
+        wr = W.x;
+        wi = W.y;
+    }
+    const T ur = wr * Br - wi * Bi, ui = wr * Bi + wi * Br;
+    const T vr = lr * ur - li * ui, vi = lr * ui + li * ur;           // lambda u
+    const T r1 = (T)rd1, r2 = (T)rd2, m1 = (T)n1, m2 = (T)n2;
+    const T n1s = m1 * m1, n2s = m2 * m2;
+    const T A1 = n1s * (st * st - e1 * e1) * r1 * r1, B1 = n1s * (2 * e1 * st) * r1 * r1;   // n1^2/q1^2
+    const T A2 = n2s * (st * st - e2 * e2) * r2 * r2, B2 = n2s * (2 * e2 * st) * r2 * r2;
+    const T hk = (T)0.5 * k;
+    T ctr = (T)-0.5 * st * (r1 + r2) + hk * (B1 + B2);
+    if (ABS) ctr += (T)J.aexp;
+    const T cti = k - (T)0.5 * (e1 * r1 + e2 * r2) - hk * (A1 + A2);
+    const T c1r = -k * m1 * e1 * r1, c1i = k * m1 * st * r1;
+    const T c2r = -k * m2 * e2 * r2, c2i = k * m2 * st * r2;
+    const T gt = vr * ctr - vi * cti, g1 = vr * c1r - vi * c1i, g2 = vr * c2r - vi * c2i;
+    const T de1r = (T)0.5 * ((T)1 / e1 - e1 * r1) - hk * A1, de1i = (T)0.5 * st * r1 - hk * B1;
+    const T de2r = (T)0.5 * ((T)1 / e2 - e2 * r2) - hk * A2, de2i = (T)0.5 * st * r2 - hk * B2;
+    acc.e1 += (double)(vr * de1r - vi * de1i);
+    acc.e2 += (double)(vr * de2r - vi * de2i);
+    const double Gt = (double)gt, G1 = (double)g1, G2 = (double)g2;
+    acc.x = fma(Gt, S.b.tx, fma(G1, S.e1x, fma(G2, S.e2x, acc.x)));
+    acc.y = fma(Gt, S.b.ty, fma(G1, S.e1y, fma(G2, S.e2y, acc.y)));
+    acc.z = fma(Gt, S.b.tz, fma(G1, S.e1z, fma(G2, S.e2z, acc.z)));
+    Sr += lr * Br - li * Bi;
+    Si += lr * Bi + li * Br;
+    return true;
+}
+
 // Persistent adjoint kernel over the same work units as the forward, with
 // the same LDS-staged segment tiles.  Per receiver (lane): dL/dR accumulates
 // in FP64 and is written as the unit's partial (k_reduce_adjoint adds a
 // patch's units in order); per segment: the sum over lanes of lambda * B
 // (wave reduction) goes to Sseg as an exact fixed-point sum (scale
-// fixed_scales[0]); per unit: dL/deps from a wave reduction, reduced per job
-// in unit order by k_reduce_eps.  Every output is bitwise repeatable.
+// fixed_scales[0]); per unit: dL/deps (and dL/deps_e2 for anisotropic beams)
+// from wave reductions, reduced per job in unit order by k_reduce_eps.  Every
+// output is bitwise repeatable.
 template <int MODE>
 __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __restrict__ jobs,
                                                 const Work* __restrict__ work, const int32_t* __restrict__ n_work_p,
                                                 int32_t n_patch, unsigned* __restrict__ ctr,
                                                 const int32_t* __restrict__ lists, const SegRec* __restrict__ rec,
+                                                const FrameRec* __restrict__ frames,
                                                 const double* __restrict__ rx, const double* __restrict__ ry,
                                                 const double* __restrict__ rz, const double* __restrict__ r2,
                                                 const int32_t* __restrict__ perm, int64_t n_rcv,
                                                 const double* __restrict__ lambda, double* __restrict__ partial,
                                                 const int32_t* __restrict__ seg_perm, Fixed* __restrict__ Sseg,
                                                 const double* __restrict__ fixed_scales,
-                                                double* __restrict__ eps_partial) {
-    __shared__ __align__(16) TileRec tile[kPairThreads / kWave][kWave];
+                                                double* __restrict__ eps_partial, double* __restrict__ eps2_partial) {
+    constexpr bool kA = (MODE & kAniso) != 0;
+    using Tile = typename std::conditional<kA, TileRecAdj, TileRec>::type;
+    using Acc = typename std::conditional<kA, AdjAccA, AdjAcc>::type;
+    __shared__ __align__(16) Tile tile[kPairThreads / kWave][kWave];
     __shared__ int32_t tile_idx[kPairThreads / kWave][kWave];
     const int lane = threadIdx.x & (kWave - 1);
-    TileRec* const my = tile[threadIdx.x / kWave];
+    Tile* const my = tile[threadIdx.x / kWave];
     int32_t* const my_idx = tile_idx[threadIdx.x / kWave];
     using ST = typename Beam<MODE & 3>::T;                // beam-term precision
     const int n_work = __builtin_amdgcn_readfirstlane(*n_work_p);
@@ -1476,22 +1757,46 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
             lr = (ST)lambda[2 * ((int64_t)job * n_rcv + o)];
             li = (ST)lambda[2 * ((int64_t)job * n_rcv + o) + 1];
         }
-        AdjAcc acc{0, 0, 0, 0, 0, 0, 0, 0};
+        Acc acc{};
         GBS_REC_REGS(nx);
+        double2 nxf0 = make_double2(0.0, 0.0), nxf1 = nxf0, nxf2 = nxf0, nxf3 = nxf0;
         int32_t idx_cur = lists[min(beg + lane, end - 1)];
         GBS_REC_LOAD(nx, rec, idx_cur);
+        if constexpr (kA) {
+            const double2* f_ = reinterpret_cast<const double2*>(frames + idx_cur);
+            nxf0 = f_[0];
+            nxf1 = f_[1];
+            nxf2 = f_[2];
+            nxf3 = f_[3];
+        }
         for (int64_t e0 = beg; e0 < end; e0 += kWave) {
             const int cnt = (int)min<int64_t>(kWave, end - e0);
             wave_lds_fence();
-            GBS_STAGE((MODE & 3), my + lane, nx, J);
+            if constexpr (kA) {
+                stage_rec_adj<MODE & 3>(my + lane, nx0, nx1, nx2, nx3, nx4, nx5, nx6, nxf0, nxf1, nxf2, nxf3, J);
+            } else {
+                GBS_STAGE((MODE & 3), my + lane, nx, J);
+            }
             my_idx[lane] = seg_perm ? seg_perm[idx_cur] : idx_cur;   // table order for the segment sums
             wave_lds_fence();
             idx_cur = lists[min(e0 + kWave + lane, end - 1)];
             GBS_REC_LOAD(nx, rec, idx_cur);
+            if constexpr (kA) {
+                const double2* f_ = reinterpret_cast<const double2*>(frames + idx_cur);
+                nxf0 = f_[0];
+                nxf1 = f_[1];
+                nxf2 = f_[2];
+                nxf3 = f_[3];
+            }
             for (int k = 0; k < cnt; ++k) {
-                const TileRec S = my[k];
+                const Tile S = my[k];
                 ST Sr = 0, Si = 0;
-                const bool hit = adj_eval<MODE>(S, J, X, Y, Z, R2, lr, li, acc, Sr, Si);
+                bool hit;
+                if constexpr (kA) {
+                    hit = adj_eval_aniso<MODE>(S, J, X, Y, Z, R2, lr, li, acc, Sr, Si);
+                } else {
+                    hit = adj_eval<MODE>(S, J, X, Y, Z, R2, lr, li, acc, Sr, Si);
+                }
                 if (__ballot(hit) != 0ull) {
                     Sr = wave_sum_last(Sr);
                     Si = wave_sum_last(Si);
@@ -1504,11 +1809,22 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
             }
         }
         double* p = partial + 3 * ((int64_t)w * kWave + lane);
-        p[0] = fma(acc.g, X, fma(0.5, acc.wx, acc.vx));
-        p[1] = fma(acc.g, Y, fma(0.5, acc.wy, acc.vy));
-        p[2] = fma(acc.g, Z, fma(0.5, acc.wz, acc.vz));
-        const double dE = wave_sum_last(acc.e);
-        if (lane == kLastLane) eps_partial[w] = J.scale * dE;
+        if constexpr (kA) {
+            p[0] = acc.x;
+            p[1] = acc.y;
+            p[2] = acc.z;
+            const double dE1 = wave_sum_last(acc.e1), dE2 = wave_sum_last(acc.e2);
+            if (lane == kLastLane) {
+                eps_partial[w] = J.scale * dE1;
+                eps2_partial[w] = J.scale * dE2;
+            }
+        } else {
+            p[0] = fma(acc.g, X, fma(0.5, acc.wx, acc.vx));
+            p[1] = fma(acc.g, Y, fma(0.5, acc.wy, acc.vy));
+            p[2] = fma(acc.g, Z, fma(0.5, acc.wz, acc.vz));
+            const double dE = wave_sum_last(acc.e);
+            if (lane == kLastLane) eps_partial[w] = J.scale * dE;
+        }
     }
 }
 
@@ -1711,21 +2027,22 @@ __global__ void k_dgamma(const double* __restrict__ Zf, int32_t n_faces, double*
 // Explicit instantiations used by the host planner.
 #define GBS_INST_CULL(F, NB)                                                                                   \
     template __global__ void k_cull<F, NB>(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int, \
-                                           const CullSplit*, const unsigned long long*, int, int, int32_t*,          \
-                                           const int64_t*, int32_t*);
+                                           const CullSplit*, const int32_t*, const unsigned long long*, int, int,    \
+                                           int32_t*, const int64_t*, int32_t*);
 #define GBS_INST_CULL_NB(NB)                                                                                   \
     GBS_INST_CULL(false, NB)                                                                                   \
     GBS_INST_CULL(true, NB)                                                                                    \
     template __global__ void k_cull_hyper<NB>(const JobConst*, const SegRec*, const Patch*, int, int, int,       \
-                                              const CullSplit*, unsigned long long*);
+                                              const CullSplit*, const int32_t*, unsigned long long*);
 GBS_INST_CULL_NB(1)
 GBS_INST_CULL_NB(4)
 GBS_INST_CULL_NB(8)
 GBS_INST_CULL_NB(0)
 #define GBS_INST_PAIRS(M, N, C)                                                                                  \
     template __global__ void k_pairs<M, N, C>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,    \
-                                              const int32_t*, const SegRec*, const double*, const double*,       \
-                                              const double*, const double*, double*, unsigned long long*);
+                                              const int32_t*, const SegRec*, const FrameRec*, const double*,     \
+                                              const double*, const double*, const double*, double*,              \
+                                              unsigned long long*);
 #define GBS_INST_PAIRS_MODE(M) \
     GBS_INST_PAIRS(M, 1, false) GBS_INST_PAIRS(M, 2, false) GBS_INST_PAIRS(M, 4, false) \
     GBS_INST_PAIRS(M, 1, true) GBS_INST_PAIRS(M, 2, true) GBS_INST_PAIRS(M, 4, true)
@@ -1743,12 +2060,17 @@ GBS_INST_PAIRS_MODE(13)
 GBS_INST_PAIRS_MODE(14)
 #define GBS_INST_ADJ(M)                                                                                          \
     template __global__ void k_adjoint<M>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,       \
-                                          const int32_t*, const SegRec*, const double*, const double*,            \
-                                          const double*, const double*, const int32_t*, int64_t, const double*,   \
-                                          double*, const int32_t*, Fixed*, const double*, double*);
+                                          const int32_t*, const SegRec*, const FrameRec*, const double*,          \
+                                          const double*, const double*, const double*, const int32_t*, int64_t,   \
+                                          const double*, double*, const int32_t*, Fixed*, const double*, double*, \
+                                          double*);
 GBS_INST_ADJ(0)
 GBS_INST_ADJ(1)
 GBS_INST_ADJ(4)
 GBS_INST_ADJ(5)
+GBS_INST_ADJ(8)
+GBS_INST_ADJ(9)
+GBS_INST_ADJ(12)
+GBS_INST_ADJ(13)
 
 }  // namespace gbs

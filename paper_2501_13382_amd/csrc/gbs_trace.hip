@@ -86,7 +86,9 @@ __device__ __forceinline__ int32_t face_of(int32_t box, const double* bx, int ax
 
 // One thread per ray.  COUNT: nseg[i] = segments of ray i; bad[0] gets bit 0
 // for a direction that is not a unit vector, bit 1 for a source index out of
-// range or out of order (the index is clamped for the reads meanwhile).  Otherwise the segments are
+// range or out of order (the index is clamped for the reads meanwhile), bit 2
+// for a launch frame (e1_in) that is not a unit vector normal to the
+// direction.  Otherwise the segments are
 // written from ray_ptr[i]; their face histories from face_base[i] (segment j
 // of a ray holds j faces, at face_base + j (j - 1) / 2).
 //   boxes   [n_boxes * 5] x0, x1, y0, y1, h in the caller's order
@@ -101,7 +103,8 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace(
     int64_t* __restrict__ nseg, int* __restrict__ bad, const int64_t* __restrict__ ray_ptr,
     const int64_t* __restrict__ face_base, double* __restrict__ seg_a, double* __restrict__ seg_t,
     double* __restrict__ seg_s0, double* __restrict__ seg_lo, double* __restrict__ seg_hi,
-    int64_t* __restrict__ face_ptr, int32_t* __restrict__ face_ids) {
+    int64_t* __restrict__ face_ptr, int32_t* __restrict__ face_ids, const double* __restrict__ e1_in,
+    double* __restrict__ seg_e1) {
     __shared__ int32_t hist_s[kTraceMaxRefl * kTraceThreads];   // face history: slot j * threads + tid
     const int64_t i = (int64_t)blockIdx.x * kTraceThreads + threadIdx.x;
     const bool live = i < n_rays;
@@ -115,21 +118,37 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace(
         const double n2 = d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2];
         int flag = fabs(n2 - 1.0) <= 1e-9 ? 0 : 1;
         if (sraw != sidx || (ray_src && ii > 0 && ray_src[ii - 1] > sraw)) flag |= 2;
+        if (e1_in) {
+            const double en = e1_in[3 * ii] * e1_in[3 * ii] + e1_in[3 * ii + 1] * e1_in[3 * ii + 1] +
+                              e1_in[3 * ii + 2] * e1_in[3 * ii + 2];
+            const double ed = e1_in[3 * ii] * d0[0] + e1_in[3 * ii + 1] * d0[1] + e1_in[3 * ii + 2] * d0[2];
+            if (!(fabs(en - 1.0) <= 1e-9 && fabs(ed) <= 1e-9)) flag |= 4;
+        }
         if (flag) atomicOr(bad, flag);
     }
     double p[3] = {src[0], src[1], src[2]};
     double d[3] = {d0[0], d0[1], d0[2]};
+    // launch frame (anisotropic beams), mirrored at every reflection like d
+    const double e0[3] = {e1_in ? e1_in[3 * ii] : 0.0, e1_in ? e1_in[3 * ii + 1] : 0.0,
+                          e1_in ? e1_in[3 * ii + 2] : 0.0};
+    double e[3] = {e0[0], e0[1], e0[2]};
     double s = 0.0;
     int n = 0;
     bool any_ground = false;
     // the previous segment, written once the next one is known (its hi
     // extends through a ground reflection)
-    double pa[3] = {0, 0, 0}, pt[3] = {0, 0, 0}, ps0 = 0.0, plo = 0.0, pL = 0.0;
+    double pa[3] = {0, 0, 0}, pt[3] = {0, 0, 0}, pe[3] = {0, 0, 0}, ps0 = 0.0, plo = 0.0, pL = 0.0;
     bool pground = false;
     const int64_t out0 = (!COUNT && live) ? ray_ptr[ii] : 0;
     const int64_t f0 = (!COUNT && live) ? face_base[ii] : 0;
-    auto emit = [&](int j, const double a[3], const double t[3], double s0, double lo, double hi) {
+    auto emit = [&](int j, const double a[3], const double t[3], const double fe[3], double s0, double lo,
+                    double hi) {
         const int64_t o = out0 + j;
+        if (seg_e1) {
+            seg_e1[3 * o] = fe[0];
+            seg_e1[3 * o + 1] = fe[1];
+            seg_e1[3 * o + 2] = fe[2];
+        }
         seg_a[3 * o] = a[0];
         seg_a[3 * o + 1] = a[1];
         seg_a[3 * o + 2] = a[2];
@@ -190,9 +209,10 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace(
         if (!ends) face = ground ? 0 : face_of(best_box, boxes + 5 * (int64_t)best_box, best_axis, best_side, hp,
                                                panels);
         if (!COUNT) {
-            if (n > 0) emit(n - 1, pa, pt, ps0, plo, pground ? pL + L : pL);
+            if (n > 0) emit(n - 1, pa, pt, pe, ps0, plo, pground ? pL + L : pL);
             pa[0] = p[0]; pa[1] = p[1]; pa[2] = p[2];
             pt[0] = d[0]; pt[1] = d[1]; pt[2] = d[2];
+            pe[0] = e[0]; pe[1] = e[1]; pe[2] = e[2];
             ps0 = s;
             plo = (n > 0 && pground) ? -pL : 0.0;
             pL = L;
@@ -207,6 +227,7 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace(
         }
         const int ax = ground ? 2 : best_axis;
         d[ax] = -d[ax];
+        e[ax] = -e[ax];
         if (ground) hp[2] = 0.0;
         p[0] = hp[0]; p[1] = hp[1]; p[2] = hp[2];
         s = s + L;
@@ -217,8 +238,14 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace(
         nseg[i] = n + (image ? 1 : 0);
         return;
     }
-    emit(n - 1, pa, pt, ps0, plo, pL);
+    emit(n - 1, pa, pt, pe, ps0, plo, pL);
     if (image) {
+        if (seg_e1) {
+            const int64_t oi = out0 + n;
+            seg_e1[3 * oi] = e0[0];
+            seg_e1[3 * oi + 1] = e0[1];
+            seg_e1[3 * oi + 2] = -e0[2];
+        }
         const double a[3] = {src[0], src[1], -src[2]};
         const double t[3] = {d0[0], d0[1], -d0[2]};
         const int64_t o = out0 + n;
@@ -255,11 +282,11 @@ template __global__ void k_trace<true>(int64_t, int, const double*, const int32_
                                        const double*,
                                        const double*, const int32_t*, int, int, int, double, int, int64_t*, int*,
                                        const int64_t*, const int64_t*, double*, double*, double*, double*, double*,
-                                       int64_t*, int32_t*);
+                                       int64_t*, int32_t*, const double*, double*);
 template __global__ void k_trace<false>(int64_t, int, const double*, const int32_t*, const double*, const double*,
                                         const double*,
                                         const double*, const int32_t*, int, int, int, double, int, int64_t*, int*,
                                         const int64_t*, const int64_t*, double*, double*, double*, double*, double*,
-                                        int64_t*, int32_t*);
+                                        int64_t*, int32_t*, const double*, double*);
 
 }  // namespace gbs

@@ -87,9 +87,10 @@ class Table:
 
     `src` is any object with the ray-table fields: src_xyz, ray_ptr, ray_w,
     ray_src, seg_a, seg_t, seg_s0, seg_lo, seg_hi, face_ptr, face_ids,
-    n_faces (numpy arrays or tensors)."""
+    n_faces (numpy arrays or tensors), and optionally seg_e1 (the ray frame
+    of anisotropic beams, [n_segs, 3]; or the `seg_e1` argument)."""
 
-    def __init__(self, src, device="cuda", on_host=False):
+    def __init__(self, src, device="cuda", on_host=False, seg_e1=None):
         dev = None if on_host else torch.device("cuda", _device_index(device))
         self.on_host = on_host
         self.device = torch.device("cuda", _device_index(device))
@@ -108,11 +109,16 @@ class Table:
         self.face_ids = _as_tensor(src.face_ids, i32, dev, on_host)
         self.n_rays = int(self.ray_w.numel())
         self.n_segs = int(self.seg_s0.numel())
+        e1 = seg_e1 if seg_e1 is not None else getattr(src, "seg_e1", None)
+        self.seg_e1 = None if e1 is None else _as_tensor(e1, f64, dev, on_host).reshape(-1, 3)
+        if self.seg_e1 is not None and self.seg_e1.shape[0] != self.n_segs:
+            raise ValueError("seg_e1 needs one frame vector per segment")
 
     def structs(self):
         rays = _lib.GbsRays(self.n_src, self.n_rays, _ptr(self.ray_ptr), _ptr(self.ray_w), _ptr(self.ray_src))
         segs = _lib.GbsSegs(self.n_segs, _ptr(self.seg_a), _ptr(self.seg_t), _ptr(self.seg_s0), _ptr(self.seg_lo),
-                            _ptr(self.seg_hi), _ptr(self.face_ptr), _ptr(self.face_ids))
+                            _ptr(self.seg_hi), _ptr(self.face_ptr), _ptr(self.face_ids),
+                            _ptr(self.seg_e1) if self.seg_e1 is not None else None)
         return rays, segs
 
 
@@ -207,21 +213,26 @@ def forward(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="m
 
 
 def backward(table: Table, rcv, freqs, eps, gamma, lam, *, c=343.0, gate=9.21, mode="mix", chunk_segs=0,
-             alpha=None, time_kernels=False):
+             alpha=None, time_kernels=False, eps_e2=None):
     """Adjoint for dL = Re sum lam * dP.  Returns (d_gamma [n_faces, 2] as
-    (dL/dRe, dL/dIm), d_rcv [n_rcv, 3], d_eps [n_src, n_freq])."""
+    (dL/dRe, dL/dIm), d_rcv [n_rcv, 3], d_eps [n_src, n_freq]); with
+    anisotropic beams (eps_e2) also d_eps_e2 [n_src, n_freq]."""
     ctx = context(table.device)
     ctx.bind_stream()
     call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, 0, False, time_kernels,
-                 alpha=alpha)
+                 alpha=alpha, eps_e2=eps_e2)
     lam_t = lam if isinstance(lam, torch.Tensor) else torch.as_tensor(np.asarray(lam))
     lam_t = lam_t.to(device=table.device, dtype=torch.complex128).reshape(call.shape).contiguous()
     lam_ri = torch.view_as_real(lam_t).contiguous()
     d_gamma = torch.empty((table.n_faces, 2), dtype=torch.float64, device=table.device)
     d_rcv = torch.empty((call.n_rcv, 3), dtype=torch.float64, device=table.device)
     d_eps = torch.empty((table.n_src, call.n_freq), dtype=torch.float64, device=table.device)
-    rc = ctx.lib.gbs_backward(*call.common(ctx), _ptr(lam_ri), _ptr(d_gamma), _ptr(d_rcv), _ptr(d_eps))
+    d_eps2 = torch.empty_like(d_eps) if eps_e2 is not None else None
+    rc = ctx.lib.gbs_backward(*call.common(ctx), _ptr(lam_ri), _ptr(d_gamma), _ptr(d_rcv), _ptr(d_eps),
+                              _ptr(d_eps2) if d_eps2 is not None else None)
     _lib.check(rc, ctx.handle)
+    if eps_e2 is not None:
+        return d_gamma, d_rcv, d_eps, d_eps2
     return d_gamma, d_rcv, d_eps
 
 
@@ -233,12 +244,15 @@ class _Traced:
 
 
 def trace(src_xyz, dirs, weights, *, ray_src=None, boxes=None, panels=1, s_max, max_refl=10,
-          image_complete=False, device="cuda") -> Table:
+          image_complete=False, e1=None, device="cuda") -> Table:
     """Ray tracing on the device (gbs_trace): the fan `dirs` [n, 3] (unit) from
     the sources `src_xyz` [n_src, 3] (ray i from source ray_src[i], default 0)
     through the ground plane and `boxes` [n_boxes, 5] (x0, x1, y0, y1, h),
     each ray until its arc length reaches s_max (a number, or one per source);
-    returns the ray table as a device Table with the given ray weights."""
+    returns the ray table as a device Table with the given ray weights.
+    e1: launch frame per ray ([n, 3], unit, normal to the direction) for
+    anisotropic beams; the table then carries the frame of every segment
+    (mirrored at each reflection) as seg_e1."""
     ctx = context(device)
     ctx.bind_stream()
     dev = ctx.device
@@ -262,7 +276,11 @@ def trace(src_xyz, dirs, weights, *, ray_src=None, boxes=None, panels=1, s_max, 
             raise ValueError("s_max: one value, or one per source")
     scene = _lib.GbsScene(int(bx.shape[0]), int(panels), _ptr(bx), float(sm.max()) if sm.size else 0.0,
                           int(max_refl), 1 if image_complete else 0)
-    fan = _lib.GbsFan(int(src.shape[0]), _ptr(src), n, _ptr(d), _ptr(rs), _ptr(sm_src) if sm_src is not None else None)
+    e1t = None if e1 is None else _as_tensor(e1, f64, dev).reshape(-1, 3)
+    if e1t is not None and e1t.shape[0] != n:
+        raise ValueError("e1: one launch frame per ray")
+    fan = _lib.GbsFan(int(src.shape[0]), _ptr(src), n, _ptr(d), _ptr(rs), _ptr(sm_src) if sm_src is not None else None,
+                      _ptr(e1t) if e1t is not None else None)
     ns, nf, token = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
     _lib.check(ctx.lib.gbs_trace_count(ctx.handle, ctypes.byref(scene), ctypes.byref(fan), ctypes.byref(ns),
                                        ctypes.byref(nf), ctypes.byref(token)), ctx.handle)
@@ -273,12 +291,13 @@ def trace(src_xyz, dirs, weights, *, ray_src=None, boxes=None, panels=1, s_max, 
                   seg_s0=torch.empty(S, dtype=f64, device=dev), seg_lo=torch.empty(S, dtype=f64, device=dev),
                   seg_hi=torch.empty(S, dtype=f64, device=dev),
                   face_ptr=torch.empty(S + 1, dtype=torch.int64, device=dev),
-                  face_ids=torch.empty(F, dtype=torch.int32, device=dev))
+                  face_ids=torch.empty(F, dtype=torch.int32, device=dev),
+                  seg_e1=torch.empty((S, 3), dtype=f64, device=dev) if e1t is not None else None)
     # the count just taken is reused (same arguments, inputs untouched in between)
     rc = ctx.lib.gbs_trace(ctx.handle, ctypes.byref(scene), ctypes.byref(fan), token.value, S, F,
                            _ptr(out.ray_ptr), _ptr(out.seg_a), _ptr(out.seg_t), _ptr(out.seg_s0), _ptr(out.seg_lo),
-                           _ptr(out.seg_hi), _ptr(out.face_ptr), _ptr(out.face_ids), ctypes.byref(ns),
-                           ctypes.byref(nf))
+                           _ptr(out.seg_hi), _ptr(out.face_ptr), _ptr(out.face_ids),
+                           _ptr(out.seg_e1) if out.seg_e1 is not None else None, ctypes.byref(ns), ctypes.byref(nf))
     _lib.check(rc, ctx.handle)
     return Table(out, device=dev)
 
@@ -420,26 +439,29 @@ class GBSFunction(torch.autograd.Function):
     """Differentiable beam summation with the ray geometry held fixed.
 
     apply(gamma [n_faces] complex128, rcv [n_rcv, 3] float64,
-          eps [n_src, n_freq] float64, table, freqs, opts dict) -> (P, TL)
+          eps [n_src, n_freq] float64, table, freqs, opts dict,
+          eps_e2 [n_src, n_freq] float64 or None) -> (P, TL)
 
     Gradients flow to the reflection coefficients (torch's complex
-    convention: dL/dRe + i dL/dIm), the receiver positions and eps.
+    convention: dL/dRe + i dL/dIm), the receiver positions, eps and, with
+    anisotropic beams, eps_e2 (the table's frame held fixed).
     """
 
     @staticmethod
-    def forward(ctx, gamma, rcv, eps, table, freqs, opts):
+    def forward(ctx, gamma, rcv, eps, table, freqs, opts, eps_e2=None):
         opts = dict(opts or {})
-        if opts.get("eps_e2") is not None:
-            raise NotImplementedError("GBSFunction differentiates isotropic beams only (no eps_e2)")
-        P, TL = forward(table, rcv.detach(), freqs, eps.detach(), gamma.detach(), **opts)
-        ctx.save_for_backward(gamma, rcv, eps, P)
-        ctx.table, ctx.freqs, ctx.opts = table, freqs, opts
+        if "eps_e2" in opts:
+            raise ValueError("pass eps_e2 as GBSFunction's last input, not in opts")
+        e2 = eps_e2.detach() if eps_e2 is not None else None
+        P, TL = forward(table, rcv.detach(), freqs, eps.detach(), gamma.detach(), eps_e2=e2, **opts)
+        ctx.save_for_backward(gamma, rcv, eps, P, e2 if e2 is not None else torch.empty(0))
+        ctx.table, ctx.freqs, ctx.opts, ctx.aniso = table, freqs, opts, eps_e2 is not None
         ctx.mark_non_differentiable()
         return P, TL
 
     @staticmethod
     def backward(ctx, gP, gTL):
-        gamma, rcv, eps, P = ctx.saved_tensors
+        gamma, rcv, eps, P, e2 = ctx.saved_tensors
         lam = torch.zeros_like(P)
         if gP is not None:
             lam = lam + torch.conj(gP)
@@ -450,8 +472,13 @@ class GBSFunction(torch.autograd.Function):
             lam = lam - (20.0 / LN10) * torch.where(g != 0, g / torch.where(P != 0, P, torch.ones_like(P)),
                                                      torch.zeros_like(P))
         opts = {k: v for k, v in ctx.opts.items() if k in ("c", "gate", "mode", "chunk_segs", "alpha")}
-        dG, dR, dE = backward(ctx.table, rcv.detach(), ctx.freqs, eps.detach(), gamma.detach(), lam, **opts)
+        out = backward(ctx.table, rcv.detach(), ctx.freqs, eps.detach(), gamma.detach(), lam,
+                       eps_e2=e2 if ctx.aniso else None, **opts)
+        dG, dR, dE = out[:3]
         g_gamma = torch.complex(dG[:, 0], dG[:, 1]).to(gamma.dtype) if ctx.needs_input_grad[0] else None
         g_rcv = dR.to(rcv.dtype).reshape(rcv.shape) if ctx.needs_input_grad[1] else None
         g_eps = dE.to(eps.dtype).reshape(eps.shape) if ctx.needs_input_grad[2] else None
-        return g_gamma, g_rcv, g_eps, None, None, None
+        g_e2 = None
+        if ctx.aniso and len(ctx.needs_input_grad) > 6 and ctx.needs_input_grad[6]:
+            g_e2 = out[3].to(e2.dtype).reshape(e2.shape)
+        return g_gamma, g_rcv, g_eps, None, None, None, g_e2

@@ -29,17 +29,17 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(_lib.LIB_PATH)
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert _lib.load().gbs_version() == 3
+    assert _lib.load().gbs_version() == 4
 
 
 def test_struct_sizes_match_c_layout():
     assert ctypes.sizeof(_lib.GbsRays) == 40
-    assert ctypes.sizeof(_lib.GbsSegs) == 64
+    assert ctypes.sizeof(_lib.GbsSegs) == 72
     assert ctypes.sizeof(_lib.GbsFaces) == 16
     assert ctypes.sizeof(_lib.GbsParams) == 56
     assert ctypes.sizeof(_lib.GbsStats) == 64
     assert ctypes.sizeof(_lib.GbsScene) == 32
-    assert ctypes.sizeof(_lib.GbsFan) == 48
+    assert ctypes.sizeof(_lib.GbsFan) == 56
 
 
 def test_struct_layouts_match_the_header(tmp_path):

@@ -235,3 +235,58 @@ def test_traced_table_through_the_summation():
         P, TL = gbs.forward(t, rcv, freqs, eps, gamma, mode=mode)
         torch.cuda.synchronize()
         assert_within(compare(P.cpu().numpy(), TL.cpu().numpy(), P_ref, TL_ref, ab), mode)
+
+
+def _launch_frames(d, seed):
+    from scenes import normal_frame
+    psi = np.random.default_rng(seed).uniform(0, np.pi, len(d))
+    h = normal_frame(d)
+    return np.cos(psi)[:, None] * h + np.sin(psi)[:, None] * np.cross(d, h)
+
+
+@pytest.mark.parametrize("case", ["city", "open_plane"])
+def test_frames_carried_bit_exact(case):
+    """With launch frames (anisotropic beams' widths turned per ray) the device
+    tracer carries the frame to every segment, mirrored at each reflection,
+    bit for bit as the oracle tracer does; the table with its frames then
+    sums, on the device, to the oracle's anisotropic field."""
+    from scenes import normal_frame
+    d, w = fibonacci_fan(1200)
+    e0 = _launch_frames(d, 5)
+    if case == "city":
+        city = grid_city(3, 40.0, 20.0, 10.0, 40.0, seed=11, panels=2)
+        src = np.array([[50.0, 50.0, 6.0]])
+        kw = dict(boxes=city.boxes, panels=2, s_max=400.0, max_refl=6)
+    else:
+        src = np.array([[0.0, 0.0, 10.0]])
+        kw = dict(s_max=200.0, max_refl=1, image_complete=True)
+    print(f"case trace frames {case}", flush=True)
+    ref = ot.trace(src, d, w, e1=e0, **kw)
+    got, t = gpu_trace(src, d, w, e1=e0, **kw)
+    assert_same(ref, got)
+    assert np.array_equal(t.seg_e1.cpu().numpy(), ref["seg_e1"])
+    # the device table with its frames, summed on the device, against the oracle's sum of the oracle's table
+    rcv = receiver_grid(6, 6, -40.0, 140.0, -40.0, 140.0, 1.5)
+    f = np.array([500.0])
+    eps = np.array([[12.0]])
+    e2 = np.array([[20.0]])
+    gam = np.full(t.n_faces, 0.9 * np.exp(0.2j))
+    tab = types.SimpleNamespace(n_faces=t.n_faces, **{k: ref[k] for k in KEYS}, ray_w=ref["ray_w"],
+                                ray_src=ref["ray_src"], src_xyz=ref["src_xyz"])
+    tab.n_src, tab.n_rays, tab.n_segs = 1, len(ref["ray_w"]), len(ref["seg_s0"])
+    import oracle
+    P_ref, TL_ref, ab = oracle.forward(tab, gam, rcv, f, eps, eps_e2=e2, seg_e1=ref["seg_e1"],
+                                       n_threads=oracle_threads(), return_absum=True)
+    P, TL = gbs.forward(t, rcv, f, eps, gam, mode="f64", eps_e2=e2)
+    torch.cuda.synchronize()
+    st = compare(P.cpu().numpy(), TL.cpu().numpy(), P_ref, TL_ref, ab)
+    assert st["rel_max"] <= 1e-8 and st["dtl_max"] <= 1e-6, st
+    # without frames in the table the library's default (horizontal) frame gives another field
+    assert not np.allclose(ref["seg_e1"], normal_frame(ref["seg_t"]))
+
+
+def test_bad_launch_frames_rejected():
+    d, w = fibonacci_fan(50)
+    with pytest.raises(_lib.GbsError) as e:
+        gbs.trace(np.array([[0.0, 0.0, 10.0]]), d, w, s_max=100.0, max_refl=1, e1=d)
+    assert e.value.code == _lib.GBS_E_INVALID and "e1" in str(e.value)

@@ -44,10 +44,10 @@ def test_missing_library_raises():
     assert "raised" in r.stdout and "not built" in r.stdout, r.stdout + r.stderr
 
 
-def test_autograd_refuses_anisotropic_beams():
-    """GBSFunction differentiates isotropic beams only: with eps_e2 in its
-    options it raises before any work instead of returning the isotropic
-    adjoint's gradient for an anisotropic forward."""
+def test_autograd_takes_eps_e2_as_an_input_only():
+    """GBSFunction differentiates anisotropic beams through its last input;
+    eps_e2 smuggled in through the options is refused before any work (it
+    would get no gradient)."""
     import pytest
     import torch
 
@@ -56,5 +56,5 @@ def test_autograd_refuses_anisotropic_beams():
     g = torch.zeros(1, dtype=torch.complex128, requires_grad=True)
     r = torch.zeros((1, 3), dtype=torch.float64, requires_grad=True)
     e = torch.ones((1, 1), dtype=torch.float64, requires_grad=True)
-    with pytest.raises(NotImplementedError):
+    with pytest.raises(ValueError):
         gbs.GBSFunction.apply(g, r, e, None, torch.ones(1, dtype=torch.float64), {"eps_e2": torch.ones(1)})
