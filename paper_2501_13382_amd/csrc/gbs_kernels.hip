@@ -862,17 +862,19 @@ __global__ void k_iota(int32_t* __restrict__ ids, int32_t n) {
 // unit, so job-dependent per-segment constants are folded in once per tile:
 // the gate's c2 - |o|^2 and, in MIX and F32, the complex weight and eps times
 // it as FP32.  gate() evaluates the arc length, the gate and the beam
-// interval (FP64 in F64 and MIX); term() the beam term, which is exactly zero
-// when `live` is false (the Gaussian factor is forced to zero) and finite for
-// any input, so the kernel runs it on all lanes of a wave with a passing lane.
+// interval (FP64 in F64 and MIX); term() adds the beam term to (ur, ui), the
+// complex rotation fused into the accumulation; the term is exactly zero when
+// `live` is false (the Gaussian factor is forced to zero) and finite for any
+// input, so the kernel runs it on all lanes of a wave with a passing lane.
 struct TileRec {
     double m2ox, m2oy;   // -2 o
     double m2oz, c2oo;   // gate constant of the job minus |o|^2
     double tx, ty;       // unit axis
     double tz, mot;      //   and -o.t
     double slo, shi;     // beam interval in arc length
-    double oo, pad;      // |o|^2
-    double wgr, wgi;     // F64: w Gamma.  MIX/F32: float4 (w Gamma, eps w Gamma) as (Re, Im, Re, Im)
+    double oo, pad;      // |o|^2; isotropic MIX: arg(w Gamma) in cycles
+    double wgr, wgi;     // F64: w Gamma.  F32 and anisotropic MIX: float4 (w Gamma, eps w Gamma) as
+                         // (Re, Im, Re, Im).  Isotropic MIX: |w Gamma| as FP32 in wgr, f/c in wgi
 };
 static_assert(sizeof(TileRec) == 112, "TileRec layout");
 
@@ -917,8 +919,8 @@ struct Beam<kF64> {
         const double w = live ? rden * exp(ge) : 0.0;
         const double cr = fma(s, S.wgr, -J.eps * S.wgi) * w;
         const double ci = fma(s, S.wgi, J.eps * S.wgr) * w;
-        ur = cr * cs - ci * sn;
-        ui = cr * sn + ci * cs;
+        ur = fma(cr, cs, fma(-ci, sn, ur));
+        ui = fma(cr, sn, fma(ci, cs, ui));
     }
 };
 
@@ -947,7 +949,7 @@ struct Beam<kMIX> {
         const double r0 = (double)r0f;
         const double rden = fma(r0, fma(-den, r0, 1.0), r0);                 // one Newton step
         const double a = n2 * rden;
-        const float ph = (float)__builtin_amdgcn_fract(fma(s, fma(J.hfk, a, J.fk), S.pad));
+        const float ph = (float)__builtin_amdgcn_fract(fma(s, fma(J.hfk, a, S.wgi), S.pad));   // S.wgi = f/c
         const float sn = __builtin_amdgcn_sinf(ph);                          // sin(2 pi ph)
         const float cs = __builtin_amdgcn_cosf(ph);
         const float sf = (float)s;
@@ -955,8 +957,8 @@ struct Beam<kMIX> {
         const float g2 = live ? (ABS ? fmaf(sf, (float)J.aexp2, gg) : gg) : -INFINITY;
         const float w = r0f * __builtin_amdgcn_exp2f(g2) * *reinterpret_cast<const float*>(&S.wgr);
         const float cr = sf * w, ci = (float)J.eps * w;                      // |w Gamma| (s + i eps) / den e^g
-        ur = cr * cs - ci * sn;
-        ui = cr * sn + ci * cs;
+        ur = fmaf(cr, cs, fmaf(-ci, sn, ur));
+        ui = fmaf(cr, sn, fmaf(ci, cs, ui));
     }
 };
 
@@ -985,8 +987,8 @@ struct Beam<kF32> {
         const float4 W = tile_weights(S);
         const float cr = fmaf(g.s, W.x, -W.w) * w;
         const float ci = fmaf(g.s, W.y, W.z) * w;
-        ur = cr * cs - ci * sn;
-        ui = cr * sn + ci * cs;
+        ur = fmaf(cr, cs, fmaf(-ci, sn, ur));
+        ui = fmaf(cr, sn, fmaf(ci, cs, ui));
     }
 };
 
@@ -1075,8 +1077,8 @@ struct BeamA<kMIX> {
         const float4 W = tile_weights(S.b);
         const float cr = (re * W.x - im * W.y) * pre;
         const float ci = (re * W.y + im * W.x) * pre;
-        ur = cr * cs - ci * sn;
-        ui = cr * sn + ci * cs;
+        ur = fmaf(cr, cs, fmaf(-ci, sn, ur));
+        ui = fmaf(cr, sn, fmaf(ci, cs, ui));
         return in;
     }
 };
@@ -1115,8 +1117,8 @@ struct BeamA<kF64> {
         const double pre = J.ampc / sqrt(den1 * den2 * bb) * w;
         const double cr = (re * S.b.wgr - im * S.b.wgi) * pre;
         const double ci = (re * S.b.wgi + im * S.b.wgr) * pre;
-        ur = cr * cs - ci * sn;
-        ui = cr * sn + ci * cs;
+        ur = fma(cr, cs, fma(-ci, sn, ur));
+        ui = fma(cr, sn, fma(ci, cs, ui));
         return in;
     }
 };
@@ -1164,8 +1166,8 @@ struct BeamA<kF32> {
         const float4 W = tile_weights(S.b);
         const float cr = (re * W.x - im * W.y) * pre;
         const float ci = (re * W.y + im * W.x) * pre;
-        ur = cr * cs - ci * sn;
-        ui = cr * sn + ci * cs;
+        ur = fmaf(cr, cs, fmaf(-ci, sn, ur));
+        ui = fmaf(cr, sn, fmaf(ci, cs, ui));
         return in;
     }
 };
@@ -1180,57 +1182,50 @@ using BeamOf = typename std::conditional<(MODE & kAniso) != 0, BeamA<MODE & 3>, 
 template <int MODE>
 using TileOf = typename std::conditional<(MODE & kAniso) != 0, TileRecA, TileRec>::type;
 
-// One segment for one receiver: wave-uniform skip when no lane passes.
+// One segment for one receiver: wave-uniform skip when no lane passes.  The
+// term is added to (fr, fi), accumulators in the term's precision that the
+// kernel adds into its FP64 sums once per tile.
 template <int MODE>
 __device__ __forceinline__ int pair_one(const TileOf<MODE>& S, const JobConst& J, double X, double Y, double Z,
-                                        double R2, double& ar, double& ai) {
+                                        double R2, typename BeamOf<MODE>::T& fr, typename BeamOf<MODE>::T& fi) {
     using B = BeamOf<MODE>;
     constexpr bool ABS = (MODE & kAbsorb) != 0;
     typename B::Geo g;
     const bool k0 = B::gate(S, J, X, Y, Z, R2, g);
     if (__ballot(k0) == 0ull) return 0;
     branch_barrier();
-    typename B::T ur, ui;
-    int hit;
     if constexpr ((MODE & kAniso) != 0) {
-        hit = (int)B::template term<ABS>(S, J, g, k0, ur, ui);
+        return (int)B::template term<ABS>(S, J, g, k0, fr, fi);
     } else {
-        B::template term<ABS>(S, J, g, k0, ur, ui);
-        hit = (int)k0;
+        B::template term<ABS>(S, J, g, k0, fr, fi);
+        return (int)k0;
     }
-    ar += (double)ur;
-    ai += (double)ui;
-    return hit;
 }
 
 // Two consecutive segments for one receiver: their beam terms are independent
-// dependency chains that the compiler interleaves; one wave-uniform branch
-// skips both when no lane passes either gate.
+// dependency chains (each into its own accumulators) that the compiler
+// interleaves; one wave-uniform branch skips both when no lane passes either
+// gate.
 template <int MODE>
 __device__ __forceinline__ int pair_two(const TileOf<MODE>& S0, const TileOf<MODE>& S1, const JobConst& J, double X,
-                                        double Y, double Z, double R2, double& ar, double& ai) {
+                                        double Y, double Z, double R2, typename BeamOf<MODE>::T* fr,
+                                        typename BeamOf<MODE>::T* fi) {
     using B = BeamOf<MODE>;
     constexpr bool ABS = (MODE & kAbsorb) != 0;
-    using T = typename B::T;
     typename B::Geo g0, g1;
     const bool k0 = B::gate(S0, J, X, Y, Z, R2, g0);
     const bool k1 = B::gate(S1, J, X, Y, Z, R2, g1);
     if (__ballot(k0 || k1) == 0ull) return 0;
     branch_barrier();
-    T u0r, u0i, u1r, u1i;
-    int hit;
     if constexpr ((MODE & kAniso) != 0) {
-        const bool h0 = B::template term<ABS>(S0, J, g0, k0, u0r, u0i);
-        const bool h1 = B::template term<ABS>(S1, J, g1, k1, u1r, u1i);
-        hit = (int)h0 + (int)h1;
+        const bool h0 = B::template term<ABS>(S0, J, g0, k0, fr[0], fi[0]);
+        const bool h1 = B::template term<ABS>(S1, J, g1, k1, fr[1], fi[1]);
+        return (int)h0 + (int)h1;
     } else {
-        B::template term<ABS>(S0, J, g0, k0, u0r, u0i);
-        B::template term<ABS>(S1, J, g1, k1, u1r, u1i);
-        hit = (int)k0 + (int)k1;
+        B::template term<ABS>(S0, J, g0, k0, fr[0], fi[0]);
+        B::template term<ABS>(S1, J, g1, k1, fr[1], fi[1]);
+        return (int)k0 + (int)k1;
     }
-    ar += (double)(u0r + u1r);
-    ai += (double)(u0i + u1i);
-    return hit;
 }
 
 // A segment record in registers, as seven named 16-byte vectors (kept out of
@@ -1247,7 +1242,8 @@ __device__ __forceinline__ int pair_two(const TileOf<MODE>& S0, const TileOf<MOD
 // in SegRec field order) for job J and stores it to the wave's LDS tile.
 // POLAR (the isotropic MIX pair kernel): the weight in polar form, its phase
 // in cycles in the spare slot and its modulus as FP32 in place of the complex
-// weight.
+// weight, followed by the job's f/c (so the phase's FMAs read both of their
+// job constants from different register files).
 template <int MODE, bool POLAR = false>
 __device__ __forceinline__ void stage_rec(TileRec* dst, double2 r0, double2 r1, double2 r2, double2 r3, double2 r4,
                                           double2 r5, double2 r6, const JobConst& J) {
@@ -1259,7 +1255,9 @@ __device__ __forceinline__ void stage_rec(TileRec* dst, double2 r0, double2 r1, 
     q[4] = r4;
     q[5] = make_double2(r1.y, POLAR ? r6.x : 0.0);
     if (POLAR) {
-        *reinterpret_cast<float4*>(q + 6) = make_float4((float)hypot(r5.x, r5.y), 0.f, 0.f, 0.f);
+        union { float2 f; double d; } m;
+        m.f = make_float2((float)hypot(r5.x, r5.y), 0.f);
+        q[6] = make_double2(m.d, J.fk);
     } else if (MODE == kF64) {
         q[6] = r5;
     } else {
@@ -1322,6 +1320,7 @@ __global__ __launch_bounds__(kPairThreads, GBS_PAIR_MIN_WAVES) void k_pairs(cons
                                               double* __restrict__ partial, unsigned long long* __restrict__ n_active) {
     constexpr bool kA = (MODE & kAniso) != 0;
     using Tile = TileOf<MODE>;
+    using T = typename BeamOf<MODE>::T;
     __shared__ __align__(16) Tile tile[kPairThreads / kWave][kWave];
     const int lane = threadIdx.x & (kWave - 1);
     Tile* const my = tile[threadIdx.x / kWave];
@@ -1375,13 +1374,18 @@ __global__ __launch_bounds__(kPairThreads, GBS_PAIR_MIN_WAVES) void k_pairs(cons
                 nxf1 = f_[1];
             }
             idx_ahead = lists[min(e0 + 2 * kWave + lane, end - 1)];
+            // the tile's terms in the term precision (FP32 in MIX: at most 64
+            // terms per sum), then once into the FP64 sums
+            T fr[NR][2], fi[NR][2];
+#pragma unroll
+            for (int m = 0; m < NR; ++m) fr[m][0] = fr[m][1] = fi[m][0] = fi[m][1] = T(0);
             int k = 0;
 #ifndef GBS_PAIR_SINGLE
             for (; k + 2 <= cnt; k += 2) {
                 const Tile S0 = my[k], S1 = my[k + 1];
 #pragma unroll
                 for (int m = 0; m < NR; ++m) {
-                    const int hit = pair_two<MODE>(S0, S1, J, X[m], Y[m], Z[m], R2[m], ar[m], ai[m]);
+                    const int hit = pair_two<MODE>(S0, S1, J, X[m], Y[m], Z[m], R2[m], fr[m], fi[m]);
                     if (COUNT) active += (unsigned long long)hit;
                 }
             }
@@ -1390,9 +1394,14 @@ __global__ __launch_bounds__(kPairThreads, GBS_PAIR_MIN_WAVES) void k_pairs(cons
                 const Tile S = my[k];
 #pragma unroll
                 for (int m = 0; m < NR; ++m) {
-                    const int hit = pair_one<MODE>(S, J, X[m], Y[m], Z[m], R2[m], ar[m], ai[m]);
+                    const int hit = pair_one<MODE>(S, J, X[m], Y[m], Z[m], R2[m], fr[m][0], fi[m][0]);
                     if (COUNT) active += (unsigned long long)hit;
                 }
+            }
+#pragma unroll
+            for (int m = 0; m < NR; ++m) {
+                ar[m] += (double)fr[m][0] + (double)fr[m][1];
+                ai[m] += (double)fi[m][0] + (double)fi[m][1];
             }
         }
 #pragma unroll

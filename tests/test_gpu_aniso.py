@@ -296,7 +296,9 @@ def test_aniso_gradcheck_through_autograd():
     e1 = transported_frame(sc.table, 0.7, panels=2)
     t = gbs.Table(sc.table, device="cuda", seg_e1=e1)
     gamma = torch.tensor(sc.gamma, dtype=torch.complex128, device="cuda", requires_grad=True)
-    rcv = torch.tensor(sc.rcv, dtype=torch.float64, device="cuda", requires_grad=True)
+    # the far corner of the 3 x 3 grid, (140, 140), gets no beam (P = 0, TL =
+    # inf): no finite difference exists there
+    rcv = torch.tensor(sc.rcv[:8], dtype=torch.float64, device="cuda", requires_grad=True)
     eps = torch.tensor(sc.eps, dtype=torch.float64, device="cuda", requires_grad=True)
     eps2 = torch.tensor(1.6 * sc.eps, dtype=torch.float64, device="cuda", requires_grad=True)
     opts = {"mode": "f64", "c": sc.c, "gate": sc.gate}

@@ -115,6 +115,35 @@ def test_batched_sources_and_bands(mode):
     assert_within(compare(P, TL, P_ref, TL_ref, ab), mode)
 
 
+def test_batched_city_f32_ablation():
+    """The all-FP32 ablation on the batched city: within its 0.2 dB bar in
+    the 125 Hz and 500 Hz bands.  At 2 and 8 kHz, over paths of several
+    hundred metres, FP32 geometry and phase lose that bar (the reason the
+    FP32 + FP64 phase mode exists: FP32 arc lengths of ~900 m are off by
+    ~5e-5 m, a phase error of k 5e-5 ~ 7e-3 rad per term at 8 kHz, amplified
+    where terms cancel); the test then reports the measured error as an
+    expected failure instead of hiding those bands."""
+    sc = city_batched(n_src=4, ray_lo=2000, ray_hi=9000, grid=24)
+    P_ref, TL_ref, ab = reference(sc)
+    print("case batched f32", flush=True)
+    P, TL = gpu_forward(sc, mode="f32")
+    shape = (sc.table.n_src, len(sc.freqs), len(sc.rcv))     # (source, band, receiver)
+    P, TL, P_ref, TL_ref, ab = (np.reshape(x, shape) for x in (P, TL, P_ref, TL_ref, ab))
+    missed = []
+    for b, f in enumerate(sc.freqs):
+        st = compare(P[:, b], TL[:, b], P_ref[:, b], TL_ref[:, b], ab[:, b])
+        print(f"{f:.0f} Hz: {st}", flush=True)
+        if f <= 500.0:
+            assert_within(st, "f32")
+        else:
+            assert st["dead_ok"] and st["masked_frac"] <= 0.01, st
+            if st["dtl_max"] > 0.2:
+                missed.append(f"{f:.0f} Hz: max |dTL| {st['dtl_max']:.3f} dB, max relative error "
+                              f"{st['rel_max']:.2e}")
+    if missed:
+        pytest.xfail("F32 ablation over the 0.2 dB bar at " + "; ".join(missed))
+
+
 def test_deterministic_repeat(city_small):
     sc, _ = city_small
     P1, _ = gpu_forward(sc, mode="mix")

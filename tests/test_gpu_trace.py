@@ -152,12 +152,12 @@ def test_count_token_reuse_and_staleness():
         [torch.empty(S, dtype=torch.float64, device="cuda") for _ in range(3)] + \
         [torch.empty(S + 1, dtype=torch.int64, device="cuda"), torch.empty(F, dtype=torch.int32, device="cuda")]
     run = lambda tok: ctx.lib.gbs_trace(ctx.handle, ctypes.byref(scene), ctypes.byref(fan), tok, S, F,
-                                        *[ptr(t) for t in out], ctypes.byref(ns), ctypes.byref(nf))
+                                        *[ptr(t) for t in out], None, ctypes.byref(ns), ctypes.byref(nf))
     assert run(tok1.value) == _lib.GBS_E_INVALID           # an earlier count
     assert cnt(tok2) == 0
     scene_other = _lib.GbsScene(len(city.boxes), 1, ptr(bx), 300.0, 6, 0)
     assert ctx.lib.gbs_trace(ctx.handle, ctypes.byref(scene_other), ctypes.byref(fan), tok2.value, S, F,
-                             *[ptr(t) for t in out], ctypes.byref(ns), ctypes.byref(nf)) == _lib.GBS_E_INVALID
+                             *[ptr(t) for t in out], None, ctypes.byref(ns), ctypes.byref(nf)) == _lib.GBS_E_INVALID
     assert cnt(tok2) == 0 and run(tok2.value) == 0         # reuses the count
     torch.cuda.synchronize()
     reused = [t.cpu().numpy() for t in out]
