@@ -171,6 +171,9 @@ typedef struct gbs_stats {
     double ms_cull;           /* culling/list-building time (GBS_FLAG_TIME_KERNELS)   */
     int32_t grid;             /* workgroups of the last persistent launch          */
     int32_t blocks_per_cu;    /* resident workgroups per CU for that kernel        */
+    int64_t scratch_bytes;    /* device scratch held by the forward's workspace;
+                                 for gbs_forward_noalloc, the bytes of the static
+                                 scratch that the call used                        */
 } gbs_stats;
 
 /* Create a context on `device` (HIP ordinal) that enqueues on `hip_stream`
@@ -195,6 +198,33 @@ int gbs_set_stream(gbs_ctx* ctx, void* hip_stream);
 int gbs_forward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces,
                 const double* rcv, int64_t n_rcv, const double* freqs, int32_t n_freq, const double* eps,
                 const gbs_params* params, double* P, double* TL);
+
+/*
+ * gbs_forward without any device allocation, for callers that cannot
+ * allocate (code between HIP calls that must not allocate, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, outputs and
+ * determinism as gbs_forward (bitwise the same P and TL); no hipMalloc,
+ * hipFree or allocating library routine is called.  Every intermediate
+ * buffer (receiver order, segment records, culled lists, work units,
+ * partial sums) is carved from one static device array of 128 MiB per GPU,
+ * loaded with the library's code object and held until the process ends;
+ * its device address is looked up once per device by gbs_create.
+ * Limits and errors:
+ *   - a call whose buffers need more than 128 MiB returns GBS_E_UNSUPPORTED
+ *     (message names the buffer); the check runs as the plan is laid out,
+ *     so P may already be zeroed and TL is untouched.  The 2,000-ray open
+ *     plane over 64 x 64 receivers needs a few MiB; gbs_stats.scratch_bytes
+ *     reports what a call used;
+ *   - device tables only: GBS_FLAG_TABLE_HOST returns GBS_E_UNSUPPORTED;
+ *   - the array is shared by every call on a GPU, from every context and
+ *     stream, and keeps the last call's contents (each call clears what must
+ *     start at zero).  Calls that overlap on one GPU race: issue them on one
+ *     stream, or wait for one call's work before starting the next.
+ * Like gbs_forward it synchronises the stream once to size the culled lists.
+ */
+int gbs_forward_noalloc(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces,
+                        const double* rcv, int64_t n_rcv, const double* freqs, int32_t n_freq, const double* eps,
+                        const gbs_params* params, double* P, double* TL);
 
 /*
  * Adjoint of gbs_forward for dL = Re sum_{job,r} lambda[job,r] * dP[job,r],

@@ -5,10 +5,10 @@ this package is its Python binding.  Importing it does not load the
 library; the first call does, and fails loudly if it is not built.
 """
 from .gbs import (Context, GBSFunction, Graph, Table, air_absorption, autotune, backward, context, forward,
-                  impulse_response, stats, trace)
+                  forward_noalloc, impulse_response, stats, trace)
 
 __all__ = ["Context", "GBSFunction", "Graph", "Table", "air_absorption", "autotune", "backward", "context",
-           "forward", "impulse_response", "stats", "trace"]
+           "forward", "forward_noalloc", "impulse_response", "stats", "trace"]
 
 
 def build(verbose: bool = False) -> str:

@@ -60,14 +60,15 @@ class GbsFan(ctypes.Structure):
 class GbsStats(ctypes.Structure):
     _fields_ = [("dense_pairs", c_int64), ("listed_pairs", c_int64), ("active_pairs", c_int64),
                 ("n_items", c_int64), ("n_chunks", c_int32), ("patch_rcv", c_int32), ("ms_pairs", c_double),
-                ("ms_cull", c_double), ("grid", c_int32), ("blocks_per_cu", c_int32)]
+                ("ms_cull", c_double), ("grid", c_int32), ("blocks_per_cu", c_int32),
+                ("scratch_bytes", c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-EXPORTS = ("gbs_create", "gbs_destroy", "gbs_set_stream", "gbs_forward", "gbs_backward", "gbs_get_stats",
-           "gbs_graph_create", "gbs_graph_launch", "gbs_graph_destroy", "gbs_autotune", "gbs_trace_count",
+EXPORTS = ("gbs_create", "gbs_destroy", "gbs_set_stream", "gbs_forward", "gbs_forward_noalloc", "gbs_backward",
+           "gbs_get_stats", "gbs_graph_create", "gbs_graph_launch", "gbs_graph_destroy", "gbs_autotune", "gbs_trace_count",
            "gbs_trace", "gbs_air_absorption_db", "gbs_impulse_response", "gbs_last_error", "gbs_version")
 
 _lib = None
@@ -97,6 +98,8 @@ def load() -> ctypes.CDLL:
               P(GbsParams)]
     lib.gbs_forward.argtypes = common + [c_void_p, c_void_p]
     lib.gbs_forward.restype = ctypes.c_int
+    lib.gbs_forward_noalloc.argtypes = common + [c_void_p, c_void_p]
+    lib.gbs_forward_noalloc.restype = ctypes.c_int
     lib.gbs_backward.argtypes = common + [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.gbs_backward.restype = ctypes.c_int
     lib.gbs_get_stats.argtypes = [c_void_p, P(GbsStats)]

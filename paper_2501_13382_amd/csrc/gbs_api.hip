@@ -12,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -91,6 +92,14 @@ __global__ void k_trace_close(const int64_t*, int64_t, int64_t, int64_t*);
 
 using namespace gbs;
 
+// Scratch of the allocation-free forward (gbs_forward_noalloc): one array per
+// device, loaded with the code object and held until the process ends.  In
+// host code `scratch` names a host-side stand-in, not device memory: the
+// device address comes from hipGetSymbolAddress, once per device, at
+// gbs_create (scratch_base()), and only that address is ever passed on.
+constexpr size_t kStaticScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
 
 struct GbsError : std::runtime_error {
@@ -111,6 +120,28 @@ struct GbsError : std::runtime_error {
         if (!(cond)) throw GbsError(GBS_E_INVALID, (msg));     \
     } while (0)
 
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (gbs_create); null until then.
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_base;
+
+void scratch_init(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_base.size() <= device) g_scratch_base.resize(device + 1, nullptr);
+    if (g_scratch_base[device]) return;
+    void* p = nullptr;
+    GBS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    GBS_CHECK(p != nullptr, "static scratch has no device address");
+    g_scratch_base[device] = p;
+}
+
+void* scratch_base(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= (int)g_scratch_base.size() || !g_scratch_base[device])
+        throw GbsError(GBS_E_STATE, "static scratch not set up on this device");
+    return g_scratch_base[device];
+}
+
 inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)std::max<int64_t>(1, (n + threads - 1) / threads); }
 
 // Device fill with a kernel (no memset nodes, so it is safe in captured graphs).
@@ -120,22 +151,52 @@ void fill(hipStream_t st, double* p, int64_t n, double v) {
                        n, v);
 }
 
-// Grow-only device buffers, keyed by name.
+// Grow-only device buffers, keyed by name.  In arena mode (the
+// allocation-free forward) every buffer is carved from one fixed device
+// region instead: nothing is allocated or freed, and a call that needs more
+// than the region fails with GBS_E_UNSUPPORTED.
 struct Workspace {
     std::map<std::string, std::pair<void*, size_t>> bufs;
     hipStream_t stream = nullptr;
     hipStream_t copy_stream = nullptr;    // also drained before a buffer is freed
     bool frozen = false;                  // set during graph capture: no allocation allowed
+    char* arena = nullptr;                // arena mode: base of the region, its size, bytes handed out
+    size_t arena_cap = 0, arena_used = 0;
+    Workspace() = default;
+    Workspace(void* base, size_t cap) : arena(static_cast<char*>(base)), arena_cap(cap) {}
     ~Workspace() { release(); }
+    // Device bytes this workspace holds (arena mode: handed out this call).
+    size_t held() const {
+        if (arena) return arena_used;
+        size_t n = 0;
+        for (const auto& kv : bufs) n += kv.second.second;
+        return n;
+    }
     void release() {
-        for (auto& kv : bufs)
-            if (kv.second.first) (void)hipFree(kv.second.first);
+        if (!arena)
+            for (auto& kv : bufs)
+                if (kv.second.first) (void)hipFree(kv.second.first);
         bufs.clear();
     }
     template <typename T>
     T* get(const std::string& name, size_t count) {
         size_t bytes = std::max<size_t>(count * sizeof(T), 256);
         auto& b = bufs[name];
+        if (arena) {
+            if (b.second < bytes) {   // a new slice; a smaller earlier one of the same name is left unused
+                const size_t off = (arena_used + 255) & ~size_t(255);
+                if (off > arena_cap || bytes > arena_cap - off)
+                    throw GbsError(GBS_E_UNSUPPORTED,
+                                   "gbs_forward_noalloc: the call needs more than the " +
+                                       std::to_string(arena_cap >> 20) + " MiB of static scratch (buffer '" + name +
+                                       "' of " + std::to_string(bytes) + " bytes at offset " + std::to_string(off) +
+                                       "); use gbs_forward");
+                b.first = arena + off;
+                b.second = bytes;
+                arena_used = off + bytes;
+            }
+            return static_cast<T*>(b.first);
+        }
         if (b.second < bytes) {
             GBS_CHECK(!frozen, "internal: workspace growth during graph capture");
             if (b.first) {
@@ -936,6 +997,7 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
     }
     stats.grid = ctx->stats.grid;
     stats.blocks_per_cu = ctx->stats.blocks_per_cu;
+    stats.scratch_bytes = (int64_t)ws.held();
     ctx->stats = stats;
     return GBS_OK;
 }
@@ -1186,6 +1248,7 @@ int gbs_create(gbs_ctx** out, int device, void* hip_stream) {
         GBS_HIP(hipGetDeviceProperties(&prop, device));
         ctx->device = device;
         ctx->n_cu = prop.multiProcessorCount;
+        scratch_init(device);
         ctx->stream = (hipStream_t)hip_stream;
         ctx->ws->stream = ctx->stream;
         return GBS_OK;
@@ -1235,6 +1298,22 @@ int gbs_forward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const 
         GBS_HIP(hipSetDevice(ctx->device));
         Args a{rays, segs, faces, rcv, n_rcv, freqs, n_freq, eps, params};
         return forward_impl(ctx, *ctx->ws, a, P, TL, 0);
+    });
+}
+
+int gbs_forward_noalloc(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const gbs_faces* faces,
+                        const double* rcv, int64_t n_rcv, const double* freqs, int32_t n_freq, const double* eps,
+                        const gbs_params* params, double* P, double* TL) {
+    if (!ctx) return GBS_E_INVALID;
+    return guarded(ctx, [&]() {
+        GBS_HIP(hipSetDevice(ctx->device));
+        if (params && (params->flags & GBS_FLAG_TABLE_HOST))
+            throw GbsError(GBS_E_UNSUPPORTED, "gbs_forward_noalloc takes device tables only (a host table needs "
+                                              "staging buffers); use gbs_forward");
+        Workspace ws(scratch_base(ctx->device), kStaticScratchBytes);
+        ws.stream = ctx->stream;
+        Args a{rays, segs, faces, rcv, n_rcv, freqs, n_freq, eps, params};
+        return forward_impl(ctx, ws, a, P, TL, 0);
     });
 }
 

@@ -201,13 +201,39 @@ def forward(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="m
     (source, band) in Np/m (see air_absorption), or None.  eps_e2: beam
     parameter along e2 per (source, band) for anisotropic beams (eps is then
     the one along the horizontal frame vector e1), or None."""
+    return _forward("gbs_forward", table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane,
+                    work_chunk, count_active, time_kernels, want_tl, alpha, eps_e2)
+
+
+def forward_noalloc(table: Table, rcv, freqs, eps, gamma, *, c=343.0, gate=9.21, mode="mix", rcv_per_lane=0,
+                    work_chunk=0, count_active=False, time_kernels=False, want_tl=True, alpha=None, eps_e2=None,
+                    out=None):
+    """forward() through gbs_forward_noalloc: the library allocates no device
+    memory (its scratch is a static 128 MiB array per GPU, shared by every
+    call on that GPU; stats()["scratch_bytes"] is what the call used).
+    Device tables only.  `out` = (P float64 [n_src, n_freq, n_rcv, 2],
+    TL float64 [n_src, n_freq, n_rcv] or None) reuses caller-owned outputs."""
+    return _forward("gbs_forward_noalloc", table, rcv, freqs, eps, gamma, c, gate, mode, 0, rcv_per_lane,
+                    work_chunk, count_active, time_kernels, want_tl, alpha, eps_e2, out)
+
+
+def _forward(entry, table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, work_chunk,
+             count_active, time_kernels, want_tl, alpha, eps_e2, out=None):
     ctx = context(table.device)
     ctx.bind_stream()
     call = _Call(table, rcv, freqs, eps, gamma, c, gate, mode, chunk_segs, rcv_per_lane, count_active,
                  time_kernels, work_chunk, alpha, eps_e2)
-    P = torch.empty(call.shape + (2,), dtype=torch.float64, device=table.device)
-    TL = torch.empty(call.shape, dtype=torch.float64, device=table.device) if want_tl else None
-    rc = ctx.lib.gbs_forward(*call.common(ctx), _ptr(P), _ptr(TL))
+    if out is not None:
+        P, TL = out
+        if P.dtype != torch.float64 or tuple(P.shape) != call.shape + (2,) or not P.is_contiguous():
+            raise ValueError("out P must be contiguous float64 of shape (n_src, n_freq, n_rcv, 2)")
+        if TL is not None and (TL.dtype != torch.float64 or tuple(TL.shape) != call.shape or
+                               not TL.is_contiguous()):
+            raise ValueError("out TL must be contiguous float64 of shape (n_src, n_freq, n_rcv)")
+    else:
+        P = torch.empty(call.shape + (2,), dtype=torch.float64, device=table.device)
+        TL = torch.empty(call.shape, dtype=torch.float64, device=table.device) if want_tl else None
+    rc = getattr(ctx.lib, entry)(*call.common(ctx), _ptr(P), _ptr(TL))
     _lib.check(rc, ctx.handle)
     return torch.view_as_complex(P), TL
 

@@ -37,7 +37,7 @@ def test_struct_sizes_match_c_layout():
     assert ctypes.sizeof(_lib.GbsSegs) == 72
     assert ctypes.sizeof(_lib.GbsFaces) == 16
     assert ctypes.sizeof(_lib.GbsParams) == 56
-    assert ctypes.sizeof(_lib.GbsStats) == 64
+    assert ctypes.sizeof(_lib.GbsStats) == 72
     assert ctypes.sizeof(_lib.GbsScene) == 32
     assert ctypes.sizeof(_lib.GbsFan) == 56
 
