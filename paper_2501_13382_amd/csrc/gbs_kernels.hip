@@ -69,6 +69,23 @@ __device__ __forceinline__ T wave_sum_last(T v) {
     return v;
 }
 
+// The sum over each row of 16 lanes, left in the row's last lane.
+template <typename T>
+__device__ __forceinline__ T row_sum_last(T v) {
+    if constexpr (sizeof(T) == 8) {
+        v += dpp_f64<0x111, 0xf>(v);
+        v += dpp_f64<0x112, 0xf>(v);
+        v += dpp_f64<0x114, 0xf>(v);
+        v += dpp_f64<0x118, 0xf>(v);
+    } else {
+        v += dpp_f32<0x111, 0xf>(v);
+        v += dpp_f32<0x112, 0xf>(v);
+        v += dpp_f32<0x114, 0xf>(v);
+        v += dpp_f32<0x118, 0xf>(v);
+    }
+    return v;
+}
+
 // An empty volatile asm has side effects, so the compiler cannot hoist the
 // gated block above its wave-uniform branch and execute it for every pair.
 __device__ __forceinline__ void branch_barrier() { asm volatile(""); }
@@ -1722,10 +1739,11 @@ __device__ __forceinline__ bool adj_eval_aniso(const TileRecAdj& S, const JobCon
 // the same LDS-staged segment tiles.  Per receiver (lane): dL/dR accumulates
 // in FP64 and is written as the unit's partial (k_reduce_adjoint adds a
 // patch's units in order); per segment: the sum over lanes of lambda * B
-// (wave reduction) goes to Sseg as an exact fixed-point sum (scale
-// fixed_scales[0]); per unit: dL/deps (and dL/deps_e2 for anisotropic beams)
-// from wave reductions, reduced per job in unit order by k_reduce_eps.  Every
-// output is bitwise repeatable.
+// (a reduction within each row of 16 lanes, the four row sums left in the
+// tile's LDS slot of the segment) goes to Sseg as an exact fixed-point sum
+// (scale fixed_scales[0]) at the end of the tile, one segment per lane; per unit: dL/deps (and dL/deps_e2 for
+// anisotropic beams) from wave reductions, reduced per job in unit order by
+// k_reduce_eps.  Every output is bitwise repeatable.
 template <int MODE>
 __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __restrict__ jobs,
                                                 const Work* __restrict__ work, const int32_t* __restrict__ n_work_p,
@@ -1742,12 +1760,14 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
     constexpr bool kA = (MODE & kAniso) != 0;
     using Tile = typename std::conditional<kA, TileRecAdj, TileRec>::type;
     using Acc = typename std::conditional<kA, AdjAccA, AdjAcc>::type;
+    using ST = typename Beam<MODE & 3>::T;                // beam-term precision
     __shared__ __align__(16) Tile tile[kPairThreads / kWave][kWave];
     __shared__ int32_t tile_idx[kPairThreads / kWave][kWave];
+    __shared__ ST tile_sum[kPairThreads / kWave][kWave][8];    // per tile segment: row sums of lambda B
     const int lane = threadIdx.x & (kWave - 1);
     Tile* const my = tile[threadIdx.x / kWave];
     int32_t* const my_idx = tile_idx[threadIdx.x / kWave];
-    using ST = typename Beam<MODE & 3>::T;                // beam-term precision
+    ST (*const my_sum)[8] = tile_sum[threadIdx.x / kWave];
     const int n_work = __builtin_amdgcn_readfirstlane(*n_work_p);
     const double sscale = fixed_scales[0];
     for (;;) {
@@ -1787,6 +1807,8 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
                 GBS_STAGE((MODE & 3), my + lane, nx, J);
             }
             my_idx[lane] = seg_perm ? seg_perm[idx_cur] : idx_cur;   // table order for the segment sums
+#pragma unroll
+            for (int q = 0; q < 8; ++q) my_sum[lane][q] = 0;
             wave_lds_fence();
             idx_cur = lists[min(e0 + kWave + lane, end - 1)];
             GBS_REC_LOAD(nx, rec, idx_cur);
@@ -1807,14 +1829,22 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint(const JobConst* __rest
                     hit = adj_eval<MODE>(S, J, X, Y, Z, R2, lr, li, acc, Sr, Si);
                 }
                 if (__ballot(hit) != 0ull) {
-                    Sr = wave_sum_last(Sr);
-                    Si = wave_sum_last(Si);
-                    if (lane == kLastLane) {
-                        const int64_t j = my_idx[k];
-                        fixed_add(&Sseg[2 * j], J.scale * (double)Sr, sscale);
-                        fixed_add(&Sseg[2 * j + 1], J.scale * (double)Si, sscale);
+                    Sr = row_sum_last(Sr);
+                    Si = row_sum_last(Si);
+                    if ((lane & 15) == 15) {
+                        my_sum[k][2 * (lane >> 4)] = Sr;
+                        my_sum[k][2 * (lane >> 4) + 1] = Si;
                     }
                 }
+            }
+            // the tile's segment sums, one segment per lane (rows added in order)
+            wave_lds_fence();
+            const ST tr = (my_sum[lane][0] + my_sum[lane][2]) + (my_sum[lane][4] + my_sum[lane][6]);
+            const ST ti = (my_sum[lane][1] + my_sum[lane][3]) + (my_sum[lane][5] + my_sum[lane][7]);
+            if (lane < cnt && (tr != 0 || ti != 0)) {
+                const int64_t j = my_idx[lane];
+                fixed_add(&Sseg[2 * j], J.scale * (double)tr, sscale);
+                fixed_add(&Sseg[2 * j + 1], J.scale * (double)ti, sscale);
             }
         }
         double* p = partial + 3 * ((int64_t)w * kWave + lane);
