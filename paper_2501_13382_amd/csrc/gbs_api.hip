@@ -246,6 +246,11 @@ struct gbs_ctx {
     hipStream_t copy_stream = nullptr;
     hipEvent_t copied[2] = {nullptr, nullptr};
     hipEvent_t released[2] = {nullptr, nullptr};
+    // list-length reads of up to two planned passes: pinned host words (list
+    // total, status word) per slot and the events behind their copies; made
+    // at creation so that no call allocates them
+    int64_t* plan_words = nullptr;    // [2][2]: total, status
+    hipEvent_t planned[2] = {nullptr, nullptr};
     // the last gbs_trace_count: its token, what it counted, and its sizes
     // (the per-ray offsets stay in the workspace for gbs_trace to reuse)
     int64_t trace_token = 0, trace_token_next = 0;
@@ -620,8 +625,6 @@ struct Planner {
         int64_t work_cap = 0;
     };
 
-    // Records, job constants, culled lists and the longest-first item order
-    // for one pass.  Synchronises once to size the lists.
     // Absolute end of the face ids a pass may read: the staged slice of a host
     // table; face_ptr[n_segs] on the device otherwise (none without face_ids).
     const int64_t* face_end_dev() const {
@@ -629,12 +632,36 @@ struct Planner {
     }
     int64_t face_end_host(const PassRange& ps) const { return table_host() ? ps.face_end : 0; }
 
-    Lists build_lists(const PassRange& ps, const PassView& v, int pass_idx,
-                      unsigned long long* bmax = nullptr) {
+    // A pass planned up to its list total (plan_pass) and waiting to be
+    // finished (finish_pass: lists, longest-first order, work units).
+    struct Planned {
         Lists L;
+        int slot = 0, cps = 0;
+        int64_t n_cnt = 0, max_pieces = 0;
+        const CullSplit* d_split = nullptr;
+        const int32_t* d_nsplit = nullptr;
+        const unsigned long long* hmask = nullptr;
+        int64_t* off = nullptr;
+    };
+
+    // Names of a pass's planning buffers: graph creation keeps every pass's
+    // under its tag; a call's passes alternate between two slots, so that
+    // the plan of pass i + 1 can be enqueued before pass i is finished.
+    std::string slot_name(const char* base, int slot) const {
+        return std::string(base) + (tag.empty() ? "%" + std::to_string(slot) : tag);
+    }
+
+    // Records, job constants, spatial order, the cull's count pass and the
+    // scan of the counts for one pass; the list total and the status word
+    // are copied to the slot's pinned words behind the slot's event.  No
+    // synchronisation.
+    Planned plan_pass(const PassRange& ps, const PassView& v, int pass_idx, unsigned long long* bmax = nullptr) {
+        Planned P;
+        P.slot = pass_idx % 2;
+        Lists& L = P.L;
         const int64_t nseg = v.n_segs;
-        int32_t* seg_ray = ws.get<int32_t>("seg_ray", nseg);
-        SegRec* rec = ws.get<SegRec>("rec", nseg);
+        int32_t* seg_ray = ws.get<int32_t>(slot_name("seg_ray", P.slot), nseg);
+        SegRec* rec = ws.get<SegRec>(slot_name("rec", P.slot), nseg);
         if (nseg > 0) {
             hipLaunchKernelGGL(k_seg2ray, dim3(blocks_for(v.n_rays, 256)), dim3(256), 0, st, v.ray_ptr, v.n_rays,
                                ps.seg_begin, nseg, seg_ray);
@@ -646,7 +673,7 @@ struct Planner {
         L.rec = rec;
         L.rec_raw = rec;
         L.seg_ray = seg_ray;
-        JobConst* dJ = ws.get<JobConst>(tag.empty() ? "jobs" + std::to_string(pass_idx % 2) : "jobs" + tag, n_jobs);
+        JobConst* dJ = ws.get<JobConst>(slot_name("jobs", P.slot), n_jobs);
         if (n_jobs > 0) {
             hipLaunchKernelGGL(k_job_consts, dim3(blocks_for(n_jobs, 64)), dim3(64), 0, st, a.freqs, a.eps,
                                a.params->alpha, a.params->eps_e2, a.rays->n_src, a.n_freq, a.params->c,
@@ -659,7 +686,7 @@ struct Planner {
             unsigned long long* k1 = ws.get<unsigned long long>("skeys", nseg);
             unsigned long long* k2 = ws.get<unsigned long long>("skeys2", nseg);
             int32_t* ids = ws.get<int32_t>("sids", nseg);
-            int32_t* perm = ws.get<int32_t>("seg_perm" + tag, nseg);
+            int32_t* perm = ws.get<int32_t>(slot_name("seg_perm", P.slot), nseg);
             hipLaunchKernelGGL(k_seg_keys, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, nseg, rec, dJ,
                                a.rays->n_src, a.n_freq, R.bbox, k1, ids);
             int end_bit = 32;
@@ -668,7 +695,7 @@ struct Planner {
             GBS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, k1, k2, ids, perm, (int)nseg, 0, end_bit, st));
             void* t = ws.get<char>("cub_tmp_segsort", tmp);
             GBS_HIP(hipcub::DeviceRadixSort::SortPairs(t, tmp, k1, k2, ids, perm, (int)nseg, 0, end_bit, st));
-            SegRec* rs = ws.get<SegRec>("rec_sorted", nseg);
+            SegRec* rs = ws.get<SegRec>(slot_name("rec_sorted", P.slot), nseg);
             hipLaunchKernelGGL(k_permute_rec, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, nseg, rec, perm, rs);
             GBS_HIP(hipGetLastError());
             L.rec = rs;
@@ -676,13 +703,13 @@ struct Planner {
             rec = rs;
         }
         if (nseg > 0 && aniso()) {
-            // ray frames (job independent; graphs keep them per pass): table order, then the records' order
-            FrameRec* fr = ws.get<FrameRec>("frames_raw" + tag, nseg);
+            // ray frames (job independent): table order, then the records' order
+            FrameRec* fr = ws.get<FrameRec>(slot_name("frames_raw", P.slot), nseg);
             hipLaunchKernelGGL(k_frames, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, nseg, v.a, v.t, v.s0, v.e1,
                                fr, status);
             L.frames = fr;
             if (L.seg_perm) {
-                FrameRec* fs = ws.get<FrameRec>("frames" + tag, nseg);
+                FrameRec* fs = ws.get<FrameRec>(slot_name("frames", P.slot), nseg);
                 hipLaunchKernelGGL(k_permute_frames, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, nseg, fr,
                                    L.seg_perm, fs);
                 L.frames = fs;
@@ -692,7 +719,7 @@ struct Planner {
         const int64_t n_items = (int64_t)n_jobs * R.n_patch;
         GBS_CHECK(n_items < INT32_MAX, "too many work items");
         L.n_items = (int32_t)n_items;
-        if (n_items == 0) return L;
+        if (n_items == 0) return P;
         // split every source's segment range so that culling runs wide; one
         // workgroup culls one piece for all bands of its source.  The pieces
         // are laid out on the device (k_make_splits); the host sizes the grids
@@ -709,25 +736,23 @@ struct Planner {
         L.n_split = n_split;
         const int64_t n_cnt = n_items * n_split;
         GBS_CHECK(n_cnt < INT32_MAX, "too many cull partitions");
-        int32_t* counts = ws.get<int32_t>("counts", n_cnt + 2);
-        int64_t* off = ws.get<int64_t>("item_off", n_cnt + 1);
+        int32_t* counts = ws.get<int32_t>(slot_name("counts", P.slot), n_cnt + 2);
+        int64_t* off = ws.get<int64_t>(slot_name("item_off", P.slot), n_cnt + 1);
         fill(st, (double*)counts, (n_cnt + 2) / 2, 0.0);
-        CullSplit* d_split = ws.get<CullSplit>("splits", std::max<int64_t>(max_pieces, 1));
-        int32_t* d_nsplit = ws.get<int32_t>("n_splits", 1);
+        CullSplit* d_split = ws.get<CullSplit>(slot_name("splits", P.slot), std::max<int64_t>(max_pieces, 1));
+        int32_t* d_nsplit = ws.get<int32_t>(slot_name("n_splits", P.slot), 1);
         hipLaunchKernelGGL(k_make_splits, dim3(1), dim3(64), 0, st, d_src_off, n_src, ps.seg_begin, ps.seg_end, span,
                            (int32_t)max_pieces, d_split, d_nsplit);
         dim3 cg(R.n_super, (unsigned)std::max<int64_t>(max_pieces, 1));
         // up to 8 bands: band constants in wave-uniform registers, as many as needed
         auto cull_count = n_freq == 1 ? k_cull<false, 1> : n_freq <= 4 ? k_cull<false, 4>
                         : n_freq <= 8 ? k_cull<false, 8> : k_cull<false, 0>;
-        auto cull_fill = n_freq == 1 ? k_cull<true, 1> : n_freq <= 4 ? k_cull<true, 4>
-                       : n_freq <= 8 ? k_cull<true, 8> : k_cull<true, 0>;
         auto cull_hyper = n_freq == 1 ? k_cull_hyper<1> : n_freq <= 4 ? k_cull_hyper<4>
                         : n_freq <= 8 ? k_cull_hyper<8> : k_cull_hyper<0>;
         // level 0: which segments of each chunk may reach each hyper-patch
         const int cps = (int)(span / kCullThreads);
         unsigned long long* hmask = ws.get<unsigned long long>(
-            "hmask", (size_t)std::max<int64_t>(max_pieces, 1) * cps * R.n_hyper * (kCullThreads / kWave));
+            slot_name("hmask", P.slot), (size_t)std::max<int64_t>(max_pieces, 1) * cps * R.n_hyper * (kCullThreads / kWave));
         if (nseg > 0) {
             hipLaunchKernelGGL(cull_hyper, dim3(cps, (unsigned)max_pieces), dim3(kCullThreads), 0, st, dJ, rec,
                                R.hypers, R.n_hyper, n_freq, cps, d_split, d_nsplit, hmask);
@@ -741,16 +766,44 @@ struct Planner {
         GBS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, in64, off, (int)(n_cnt + 1), st));
         void* t = ws.get<char>("cub_tmp_scan", tmp);
         GBS_HIP(hipcub::DeviceScan::ExclusiveSum(t, tmp, in64, off, (int)(n_cnt + 1), st));
-        int h_status = 0;
-        GBS_HIP(hipMemcpyAsync(&L.total, off + n_cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        GBS_HIP(hipMemcpyAsync(&h_status, status, sizeof(int), hipMemcpyDeviceToHost, st));
-        GBS_HIP(hipStreamSynchronize(st));
-        check_status(h_status);     // before any list is filled or any pair kernel runs
+        int64_t* words = ctx->plan_words + 2 * P.slot;
+        words[1] = 0;
+        GBS_HIP(hipMemcpyAsync(words, off + n_cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        GBS_HIP(hipMemcpyAsync(words + 1, status, sizeof(int), hipMemcpyDeviceToHost, st));
+        GBS_HIP(hipEventRecord(ctx->planned[P.slot], st));
+        P.n_cnt = n_cnt;
+        P.max_pieces = max_pieces;
+        P.cps = cps;
+        P.d_split = d_split;
+        P.d_nsplit = d_nsplit;
+        P.hmask = hmask;
+        P.off = off;
+        return P;
+    }
+
+    // Waits for a planned pass's list total (the host's one synchronisation
+    // per pass, on work enqueued before it), checks the status word, then
+    // fills the lists and lays out the work units.
+    Lists finish_pass(const Planned& P) {
+        Lists L = P.L;
+        if (L.n_items == 0) return L;
+        GBS_HIP(hipEventSynchronize(ctx->planned[P.slot]));
+        const int64_t* words = ctx->plan_words + 2 * P.slot;
+        L.total = words[0];
+        check_status((int)words[1]);     // before any list is filled or any pair kernel runs
+        const int n_freq = a.n_freq, n_split = L.n_split;
+        const int64_t n_items = L.n_items;
+        const SegRec* rec = L.rec;
         int32_t* lists = ws.get<int32_t>("lists" + tag, std::max<int64_t>(L.total, 1));
-        if (nseg > 0)
-            hipLaunchKernelGGL(cull_fill, cg, dim3(kWave), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
-                               n_freq, n_split, d_split, d_nsplit, hmask, R.n_hyper, cps, nullptr, off, lists);
+        auto cull_fill = n_freq == 1 ? k_cull<true, 1> : n_freq <= 4 ? k_cull<true, 4>
+                       : n_freq <= 8 ? k_cull<true, 8> : k_cull<true, 0>;
+        dim3 cg(R.n_super, (unsigned)std::max<int64_t>(P.max_pieces, 1));
+        if (L.total > 0)
+            hipLaunchKernelGGL(cull_fill, cg, dim3(kWave), 0, st, L.jobs, rec, R.patches, R.supers, R.n_patch,
+                               n_freq, n_split, P.d_split, P.d_nsplit, P.hmask, R.n_hyper, P.cps, nullptr, P.off,
+                               lists);
         GBS_HIP(hipGetLastError());
+        int64_t* off = P.off;
         // longest lists first
         int32_t* lens = ws.get<int32_t>("lens", n_items);
         hipLaunchKernelGGL(k_item_lengths, dim3(blocks_for(n_items, 256)), dim3(256), 0, st, off, (int32_t)n_items,
@@ -793,6 +846,11 @@ struct Planner {
         L.item_order = order;
         L.lists = lists;
         return L;
+    }
+
+    // Plans and finishes one pass (one synchronisation).
+    Lists build_lists(const PassRange& ps, const PassView& v, int pass_idx, unsigned long long* bmax = nullptr) {
+        return finish_pass(plan_pass(ps, v, pass_idx, bmax));
     }
 
     struct Widen {
@@ -943,10 +1001,16 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
         if (count) GBS_HIP(hipMemsetAsync(na, 0, sizeof(unsigned long long), st));
         const bool timed = (a.params->flags & GBS_FLAG_TIME_KERNELS) != 0;
         EventPair ev_pairs(timed), ev_cull(timed);
-        // host tables over several passes: copy pass i+1 on the copy stream
-        // while pass i computes (two staging slots)
+        // Several passes: pass i + 1 is planned (up to its list total) before
+        // pass i's lists are filled, so the host's wait for pass i's total
+        // covers only work that was enqueued before it, and the host enqueues
+        // pass i's lists and pair kernel while the device still plans; a
+        // timed call plans pass by pass.  Host tables: pass i + 2 is copied on
+        // the copy stream into the staging slot of pass i as soon as pass i's
+        // records are built (the pair kernel never reads the staged table).
         const size_t n_pass = pl.passes.size();
         const bool overlap = pl.table_host() && n_pass > 1;
+        const bool pipe = n_pass > 1 && !timed;
         Planner::PassView views[2];
         auto issue = [&](size_t pi) {
             const int slot = (int)(pi % 2);
@@ -954,22 +1018,34 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
             views[slot] = pl.view(pl.passes[pi], slot, ctx->copy_stream);
             GBS_HIP(hipEventRecord(ctx->copied[slot], ctx->copy_stream));
         };
-        if (overlap) {
-            ensure_copy_stream(ctx);
-            issue(0);
-        }
-        for (size_t pi = 0; pi < n_pass; ++pi) {
-            const PassRange& ps = pl.passes[pi];
+        Planner::Planned pend[2];
+        auto start = [&](size_t pi) {
             Planner::PassView v;
             if (overlap) {
-                if (pi + 1 < n_pass) issue(pi + 1);
                 GBS_HIP(hipStreamWaitEvent(st, ctx->copied[pi % 2], 0));
                 v = views[pi % 2];
             } else {
-                v = pl.view(ps);
+                v = pl.view(pl.passes[pi]);
             }
+            pend[pi % 2] = pl.plan_pass(pl.passes[pi], v, (int)pi);
+            if (overlap) {
+                GBS_HIP(hipEventRecord(ctx->released[pi % 2], st));
+                if (pi + 2 < n_pass) issue(pi + 2);
+            }
+        };
+        if (overlap) {
+            ensure_copy_stream(ctx);
+            issue(0);
+            issue(1);
+        }
+        if (pipe) {
+            start(0);
+            start(1);
+        }
+        for (size_t pi = 0; pi < n_pass; ++pi) {
             ev_cull.begin(st);
-            Planner::Lists L = pl.build_lists(ps, v, (int)pi);
+            if (!pipe) start(pi);
+            Planner::Lists L = pl.finish_pass(pend[pi % 2]);
             stats.ms_cull += ev_cull.end(st);
             stats.listed_pairs += L.total * (int64_t)pl.R.per;
             stats.n_items += L.n_items;
@@ -979,7 +1055,7 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
                 dispatch_pairs(a.params->mode, pl.absorb(), pl.aniso(), count, nr, ctx, st, L, pl.R, a.n_rcv, P, ctr, na);
                 stats.ms_pairs += ev_pairs.end(st);
             }
-            if (overlap) GBS_HIP(hipEventRecord(ctx->released[pi % 2], st));
+            if (pipe && pi + 2 < n_pass) start(pi + 2);
         }
         stats.n_chunks = (int32_t)pl.passes.size();
         if (count) {
@@ -1249,11 +1325,16 @@ int gbs_create(gbs_ctx** out, int device, void* hip_stream) {
         ctx->device = device;
         ctx->n_cu = prop.multiProcessorCount;
         scratch_init(device);
+        GBS_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->plan_words), 4 * sizeof(int64_t)));
+        for (int i = 0; i < 2; ++i) GBS_HIP(hipEventCreateWithFlags(&ctx->planned[i], hipEventDisableTiming));
         ctx->stream = (hipStream_t)hip_stream;
         ctx->ws->stream = ctx->stream;
         return GBS_OK;
     });
     if (rc != GBS_OK) {
+        for (int i = 0; i < 2; ++i)
+            if (ctx->planned[i]) (void)hipEventDestroy(ctx->planned[i]);
+        if (ctx->plan_words) (void)hipHostFree(ctx->plan_words);
         delete ctx;
         return rc;
     }
@@ -1270,7 +1351,9 @@ void gbs_destroy(gbs_ctx* ctx) {
     for (int i = 0; i < 2; ++i) {
         if (ctx->copied[i]) (void)hipEventDestroy(ctx->copied[i]);
         if (ctx->released[i]) (void)hipEventDestroy(ctx->released[i]);
+        if (ctx->planned[i]) (void)hipEventDestroy(ctx->planned[i]);
     }
+    if (ctx->plan_words) (void)hipHostFree(ctx->plan_words);
     if (ctx->copy_stream) (void)hipStreamDestroy(ctx->copy_stream);
     delete ctx;
 }
@@ -1475,9 +1558,10 @@ int gbs_graph_create(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, c
                 Planner::Lists L = Ls[pi];
                 if (L.n_items == 0 || L.total == 0) continue;
                 const Planner::PassView v = pl.view(pl.passes[pi]);
-                // shared buffers: fetched again, they may have grown after this pass was planned
-                int32_t* seg_ray = ws.get<int32_t>("seg_ray", v.n_segs);
-                SegRec* rec = ws.get<SegRec>("rec", v.n_segs);
+                // the pass's own planning buffers (named after its tag)
+                const std::string t = "#" + std::to_string(pi);
+                int32_t* seg_ray = ws.get<int32_t>("seg_ray" + t, v.n_segs);
+                SegRec* rec = ws.get<SegRec>("rec" + t, v.n_segs);
                 hipLaunchKernelGGL(k_seg2ray, dim3(blocks_for(v.n_rays, 256)), dim3(256), 0, st, v.ray_ptr, v.n_rays,
                                    pl.passes[pi].seg_begin, v.n_segs, seg_ray);
                 // coefficients may change between replays: rebuild the records
@@ -1487,7 +1571,7 @@ int gbs_graph_create(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, c
                                    pl.face_end_host(pl.passes[pi]), rec, pl.status, nullptr);
                 L.rec = rec;
                 if (L.seg_perm) {   // into the spatial order planned at creation
-                    SegRec* rs = ws.get<SegRec>("rec_sorted", v.n_segs);
+                    SegRec* rs = ws.get<SegRec>("rec_sorted" + t, v.n_segs);
                     hipLaunchKernelGGL(k_permute_rec, dim3(blocks_for(v.n_segs, 256)), dim3(256), 0, st, v.n_segs,
                                        rec, L.seg_perm, rs);
                     L.rec = rs;
