@@ -8,8 +8,12 @@ work lists, persistent pair kernel, TL) in the FP32 + FP64-phase mode with
 the table resident in HBM.  `value` = dense segment x receiver x band
 evaluations per second (the dense sum the culled kernel reproduces).
 
-Also reported: the pair kernel's roofline (algorithmic FLOPs per launch over
-its HIP-event-timed duration), the all-FP64 mode on the same GPU, the forward
+Also reported: the pair kernel's roofline (the survey's algorithmic FLOPs
+per pair times the listed and kept pairs of one launch, over its
+HIP-event-timed duration, against the FP32 VALU peak; the kernel's own count
+against its FP64/FP32 mixed peak beside it; the launch's HBM traffic from
+rocprofv3 counters while the pair kernel's source is the one they were
+measured on), the all-FP64 mode on the same GPU, the forward
 captured as a hipGraph and replayed, the table
 streamed from pinned host memory in four overlapped passes (PCIe-inclusive,
 never `value`), the adjoint call on the same workload, the error against the
@@ -85,20 +89,31 @@ PEAK_F32 = 157.3e12
 
 # HBM bytes per launch of the pair kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy and fill (the summary in
-# profiles/k_pairs_mix_open_plane_100k.md).  Valid only for the kernel source
-# it was measured on; reported as null once that source changes.
-PAIR_TRAFFIC_BYTES = 3.272e9
-PAIR_TRAFFIC_SOURCE_MD5 = {"gbs_kernels.hip": "d55337bc6c813e0add3d67507ba11b6c",
-                           "gbs_internal.h": "8f063ad29778f953d75dedfaaf919c38"}
+# profiles/k_pairs_mix_open_plane_100k.md).  Valid only for the pair-kernel
+# source it was measured on: the MD5 of the "pair kernels" section of
+# gbs_kernels.hip (from its section rule up to the adjoint's) and of
+# gbs_internal.h; reported as null once either changes.
+PAIR_TRAFFIC_BYTES = 4.324e9
+PAIR_TRAFFIC_SOURCE_MD5 = {"pair_section": "d9736f53ba28fa5440afc95e03449328", "gbs_internal.h": "69bc0b9e3ee1e33c6f3bc1b81db3b8c2"}
+
+
+def pair_source_md5():
+    """MD5s of the pair kernel's source: its section of gbs_kernels.hip and gbs_internal.h."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2501_13382_amd", "csrc")
+    text = open(os.path.join(csrc, "gbs_kernels.hip")).read()
+    i = text.find("// " + "-" * 61 + " pair kernels")
+    j = text.find("// " + "-" * 65 + " adjoint")
+    section = text[i:j] if 0 <= i < j else text
+    with open(os.path.join(csrc, "gbs_internal.h"), "rb") as f:
+        internal = f.read()
+    return {"pair_section": hashlib.md5(section.encode()).hexdigest(),
+            "gbs_internal.h": hashlib.md5(internal).hexdigest()}
 
 
 def pair_traffic():
-    import hashlib
-    csrc = os.path.join(ROOT, "paper_2501_13382_amd", "csrc")
-    for name, md5 in PAIR_TRAFFIC_SOURCE_MD5.items():
-        with open(os.path.join(csrc, name), "rb") as f:
-            if hashlib.md5(f.read()).hexdigest() != md5:
-                return None
+    if PAIR_TRAFFIC_BYTES is None or pair_source_md5() != PAIR_TRAFFIC_SOURCE_MD5:
+        return None
     return PAIR_TRAFFIC_BYTES
 
 
@@ -137,28 +152,40 @@ def host_cpus() -> dict:
             "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
-def roofline(listed, kept, ms, kernel, f64_listed=FLOP_LISTED_F64, f64_kept=FLOP_KEPT_F64, f32_kept=FLOP_KEPT_F32):
+def roofline(listed, kept, ms, kernel, f64_listed=FLOP_LISTED_F64, f64_kept=FLOP_KEPT_F64, f32_kept=FLOP_KEPT_F32,
+             survey=True):
     """The pair kernel's roofline from its listed and kept pair counts and its
-    HIP-event time: `achieved` and `frac` from the kernel's own algorithmic
-    count against the peak for its FP64/FP32 mix (time at peak = f64/PEAK_F64
-    + f32/PEAK_F32), and the same with the survey's per-pair count, also as a
-    fraction of the FP32 vector peak alone."""
+    HIP-event time.  `achieved` counts the survey's algorithmic work per pair
+    of the forward sum (20 flops per listed pair, 30 FP64 + 43 FP32 per kept
+    pair) and `frac` sets it against the FP32 VALU peak, the metric's
+    denominator; beside it, the same time with the kernel's own per-pair
+    count (the formulas it evaluates) against the peak for its FP64/FP32 mix
+    (time at peak = f64/PEAK_F64 + f32/PEAK_F32).  For kernels the survey
+    gives no count for (survey=False: the adjoint, anisotropic beams) the
+    kernel's own count is the algorithmic one."""
+    if survey:
+        s64 = SURVEY_FLOP_LISTED * listed + SURVEY_FLOP_KEPT_F64 * kept
+        s32 = SURVEY_FLOP_KEPT_F32 * kept
+    else:
+        s64 = f64_listed * listed + f64_kept * kept
+        s32 = f32_kept * kept
+    s_ach = (s64 + s32) / (ms * 1e-3)
+    s_mixed = (s64 + s32) / (s64 / PEAK_F64 + s32 / PEAK_F32)
     f64 = f64_listed * listed + f64_kept * kept
     f32 = f32_kept * kept
-    achieved = (f64 + f32) / (ms * 1e-3)
-    peak = (f64 + f32) / (f64 / PEAK_F64 + f32 / PEAK_F32)
-    s64 = SURVEY_FLOP_LISTED * listed + SURVEY_FLOP_KEPT_F64 * kept
-    s32 = SURVEY_FLOP_KEPT_F32 * kept
-    s_ach = (s64 + s32) / (ms * 1e-3)
-    s_peak = (s64 + s32) / (s64 / PEAK_F64 + s32 / PEAK_F32)
-    return {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "frac_of_fp32_peak": achieved / PEAK_F32, "frac_of_fp64_peak": achieved / PEAK_F64,
+    k_ach = (f64 + f32) / (ms * 1e-3)
+    k_mixed = (f64 + f32) / (f64 / PEAK_F64 + f32 / PEAK_F32)
+    return {"bound": "alu", "kernel": kernel, "achieved": s_ach / 1e12, "peak": PEAK_F32 / 1e12, "unit": "TFLOP/s",
+            "frac": s_ach / PEAK_F32, "frac_of_mixed_peak": s_ach / s_mixed, "mixed_peak": s_mixed / 1e12,
+            "flop_per_listed_pair": SURVEY_FLOP_LISTED if survey else {"f64": f64_listed},
+            "flop_per_kept_pair": ({"f64": SURVEY_FLOP_KEPT_F64, "f32": SURVEY_FLOP_KEPT_F32} if survey else
+                                   {"f64": f64_kept, "f32": f32_kept}),
+            "count": "survey" if survey else "kernel",
             "ms_per_launch": ms, "listed_pairs": int(listed), "kept_pairs": int(kept),
-            "flop_per_listed_pair": {"f64": f64_listed}, "flop_per_kept_pair": {"f64": f64_kept, "f32": f32_kept},
-            "survey_count": {"achieved": s_ach / 1e12, "peak": s_peak / 1e12, "frac": s_ach / s_peak,
-                             "frac_of_fp32_peak": s_ach / PEAK_F32,
-                             "flop_per_listed_pair": SURVEY_FLOP_LISTED,
-                             "flop_per_kept_pair": {"f64": SURVEY_FLOP_KEPT_F64, "f32": SURVEY_FLOP_KEPT_F32}}}
+            "kernel_count": {"achieved": k_ach / 1e12, "mixed_peak": k_mixed / 1e12, "frac_of_mixed_peak": k_ach / k_mixed,
+                             "frac_of_fp32_peak": k_ach / PEAK_F32,
+                             "flop_per_listed_pair": {"f64": f64_listed},
+                             "flop_per_kept_pair": {"f64": f64_kept, "f32": f32_kept}}}
 
 
 def cpu_model() -> str:
@@ -249,7 +276,7 @@ def aniso_bench(sc, dev, table, rcv, freqs, eps, gamma, args, sec_step):
     leg = {"value": sc.dense_pairs / s_an, "ms_per_step": s_an * 1e3, "overhead_vs_value": s_an / sec_step - 1.0,
            "eps_e2_over_eps": 2.0,
            "roofline": roofline(listed, active, ms_pairs, "k_pairs<MIX|aniso>", f64_kept=ANI_FLOP_KEPT_F64,
-                                f32_kept=ANI_FLOP_KEPT_F32)}
+                                f32_kept=ANI_FLOP_KEPT_F32, survey=False)}
     print(f"# anisotropic: {s_an * 1e3:.2f} ms/step, pair kernel {ms_pairs:.2f} ms", file=sys.stderr,
           flush=True)
     if not args.no_cpu:
@@ -599,7 +626,7 @@ def main():
         adj_leg = {"value": dense / s_adj, "ms_per_call": s_adj * 1e3, "mode": mode,
                    "forward_plus_adjoint_ms": sec_step * 1e3 + s_adj * 1e3,
                    "roofline": roofline(listed, active, ms_adj_kernel, "k_adjoint<MIX>",
-                                        f64_kept=ADJ_FLOP_KEPT_F64, f32_kept=ADJ_FLOP_KEPT_F32)}
+                                        f64_kept=ADJ_FLOP_KEPT_F64, f32_kept=ADJ_FLOP_KEPT_F32, survey=False)}
         print(f"# adjoint: {s_adj * 1e3:.2f} ms/call", file=sys.stderr, flush=True)
 
     # the same forward captured once as a hipGraph and replayed (the lists are

@@ -73,6 +73,7 @@ __global__ void k_face_scatter(int64_t, const int64_t*, int64_t, const int32_t*,
                                const double*, const int32_t*, const Fixed*, const double*, Fixed*);
 __global__ void k_dgamma(const double*, int32_t, double*);
 __global__ void k_lambda_l1(const double*, int64_t, double*, int*);
+__global__ void k_lambda_l1_sum(const double*, int32_t, int, double*);
 __global__ void k_fixed_scales(const JobConst*, const double*, int32_t, int64_t, const unsigned long long*, double*);
 __global__ void k_reduce_eps(const int32_t*, const int32_t*, int32_t, const double*, double*);
 __global__ void k_fixed_flush(const Fixed*, int64_t, const double*, double*);
@@ -873,12 +874,20 @@ struct EventPair {
         if (a) (void)hipEventDestroy(a);
         if (b) (void)hipEventDestroy(b);
     }
+    bool stopped = false;
     void begin(hipStream_t st) {
         if (on) GBS_HIP(hipEventRecord(a, st));
+        stopped = false;
+    }
+    // Records the stop event now; end() then only waits for it.
+    void stop(hipStream_t st) {
+        if (on) GBS_HIP(hipEventRecord(b, st));
+        stopped = true;
     }
     double end(hipStream_t st) {
         if (!on) return 0.0;
-        GBS_HIP(hipEventRecord(b, st));
+        if (!stopped) GBS_HIP(hipEventRecord(b, st));
+        stopped = false;
         GBS_HIP(hipEventSynchronize(b));
         float ms = 0.f;
         GBS_HIP(hipEventElapsedTime(&ms, a, b));
@@ -908,13 +917,15 @@ int64_t persistent_grid(gbs_ctx* ctx, const void* kern, int64_t n_items) {
 
 template <int MODE, int NR, bool COUNT>
 void launch_pairs(gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const RcvPlan& R, int64_t n_rcv, double* P,
-                  unsigned* ctr, unsigned long long* n_active) {
+                  unsigned* ctr, unsigned long long* n_active, EventPair* ev) {
     auto kern = k_pairs<MODE, NR, COUNT>;
     const int64_t grid = persistent_grid(ctx, (const void*)kern, L.work_cap);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, ctr);
+    if (ev) ev->begin(st);
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPairThreads), 0, st, L.jobs, L.work, L.n_work, R.n_patch, ctr,
                        L.lists, L.rec, L.frames, R.rx, R.ry, R.rz, R.r2, L.partial, n_active);
     GBS_HIP(hipGetLastError());
+    if (ev) ev->stop(st);
     const int64_t threads = (int64_t)L.n_items * 64 * NR;
     hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(threads, 256)), dim3(256), 0, st, L.jobs, L.item_wbase,
                        L.item_wcount, L.n_items, R.n_patch, NR, R.perm, n_rcv, L.partial, P);
@@ -923,45 +934,46 @@ void launch_pairs(gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const R
 
 template <int MODE, bool COUNT>
 void dispatch_nr(int nr, gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const RcvPlan& R, int64_t n_rcv,
-                 double* P, unsigned* ctr, unsigned long long* na) {
-    if (nr == 1) launch_pairs<MODE, 1, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na);
-    else if (nr == 2) launch_pairs<MODE, 2, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na);
-    else launch_pairs<MODE, 4, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na);
+                 double* P, unsigned* ctr, unsigned long long* na, EventPair* ev) {
+    if (nr == 1) launch_pairs<MODE, 1, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na, ev);
+    else if (nr == 2) launch_pairs<MODE, 2, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na, ev);
+    else launch_pairs<MODE, 4, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na, ev);
 }
 
 template <int MODE>
 void dispatch_count(bool count, int nr, gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const RcvPlan& R,
-                    int64_t n_rcv, double* P, unsigned* ctr, unsigned long long* na) {
-    count ? dispatch_nr<MODE, true>(nr, ctx, st, L, R, n_rcv, P, ctr, na)
-          : dispatch_nr<MODE, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na);
+                    int64_t n_rcv, double* P, unsigned* ctr, unsigned long long* na, EventPair* ev) {
+    count ? dispatch_nr<MODE, true>(nr, ctx, st, L, R, n_rcv, P, ctr, na, ev)
+          : dispatch_nr<MODE, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na, ev);
 }
 
 // mode: GBS_MODE_*; absorb: some job has atmospheric absorption (the kernel
 // variant with the absorption exponent; the others skip it); aniso:
 // anisotropic beams (counting counts the exact gate's pairs).
+// ev (optional): HIP events around the pair kernel's launch alone.
 void dispatch_pairs(int mode, bool absorb, bool aniso, bool count, int nr, gbs_ctx* ctx, hipStream_t st,
                     const Planner::Lists& L, const RcvPlan& R, int64_t n_rcv, double* P, unsigned* ctr,
-                    unsigned long long* na) {
+                    unsigned long long* na, EventPair* ev = nullptr) {
     GBS_CHECK(L.partial != nullptr, "work-unit partials not allocated");
     const int m = (mode == GBS_MODE_F64 ? 0 : mode == GBS_MODE_MIX ? 1 : 2) | (absorb ? 4 : 0);
     if (aniso) {
         switch (m) {
-            case 0: dispatch_count<8>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
-            case 1: dispatch_count<9>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
-            case 2: dispatch_count<10>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
-            case 4: dispatch_count<12>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
-            case 5: dispatch_count<13>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
-            default: dispatch_count<14>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
+            case 0: dispatch_count<8>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
+            case 1: dispatch_count<9>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
+            case 2: dispatch_count<10>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
+            case 4: dispatch_count<12>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
+            case 5: dispatch_count<13>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
+            default: dispatch_count<14>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
         }
         return;
     }
     switch (m) {
-        case 0: dispatch_count<0>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
-        case 1: dispatch_count<1>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
-        case 2: dispatch_count<2>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
-        case 4: dispatch_count<4>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
-        case 5: dispatch_count<5>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
-        default: dispatch_count<6>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na); break;
+        case 0: dispatch_count<0>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
+        case 1: dispatch_count<1>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
+        case 2: dispatch_count<2>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
+        case 4: dispatch_count<4>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
+        case 5: dispatch_count<5>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
+        default: dispatch_count<6>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
     }
 }
 
@@ -1051,8 +1063,8 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
             stats.n_items += L.n_items;
             if (L.n_items > 0 && L.total > 0) {
                 L.partial = ws.get<double>("partial", L.work_cap * nr * 64 * 2);
-                ev_pairs.begin(st);
-                dispatch_pairs(a.params->mode, pl.absorb(), pl.aniso(), count, nr, ctx, st, L, pl.R, a.n_rcv, P, ctr, na);
+                dispatch_pairs(a.params->mode, pl.absorb(), pl.aniso(), count, nr, ctx, st, L, pl.R, a.n_rcv, P, ctr, na,
+                               timed ? &ev_pairs : nullptr);
                 stats.ms_pairs += ev_pairs.end(st);
             }
             if (pipe && pi + 2 < n_pass) start(pi + 2);
@@ -1432,7 +1444,13 @@ int gbs_backward(gbs_ctx* ctx, const gbs_rays* rays, const gbs_segs* segs, const
             double* l1 = ws.get<double>("lambda_l1", n_jobs);
             double* fscale = ws.get<double>("fixed_scales", 4);
             unsigned long long* bmax = ws.get<unsigned long long>("bmax", 1);
-            hipLaunchKernelGGL(k_lambda_l1, dim3(n_jobs), dim3(256), 0, st, lambda, n_rcv, l1, pl.status);
+            // sum |lambda| per job over 64 pieces of the receivers, then the pieces in order
+            const int pieces = 64;
+            double* l1_part = ws.get<double>("lambda_l1_part", (int64_t)n_jobs * pieces);
+            hipLaunchKernelGGL(k_lambda_l1, dim3(n_jobs, pieces), dim3(256), 0, st, lambda, n_rcv, l1_part,
+                               pl.status);
+            hipLaunchKernelGGL(k_lambda_l1_sum, dim3(blocks_for(n_jobs, 64)), dim3(64), 0, st, l1_part, n_jobs,
+                               pieces, l1);
             GBS_HIP(hipGetLastError());
             pl.source_offsets();
             pl.make_passes();

@@ -1981,16 +1981,19 @@ __global__ void k_face_scatter(int64_t n_segs, const int64_t* __restrict__ face_
 }
 
 // Sum over the receivers of |Re lambda| + |Im lambda| per job (a bound on
-// sum |lambda|), one workgroup per job in a fixed order; also flags
-// non-finite lambda.
+// sum |lambda|) in a fixed order: one workgroup per (job, piece of the
+// receivers) writes a partial sum, k_lambda_l1_sum adds a job's pieces in order;
+// also flags non-finite lambda.
 __global__ __launch_bounds__(256) void k_lambda_l1(const double* __restrict__ lambda, int64_t n_rcv,
-                                                   double* __restrict__ l1, int* __restrict__ status) {
+                                                   double* __restrict__ part, int* __restrict__ status) {
     __shared__ double sm[256];
-    const int job = blockIdx.x;
+    const int job = blockIdx.x, piece = blockIdx.y, pieces = gridDim.y;
+    const int64_t span = (n_rcv + pieces - 1) / pieces;
+    const int64_t r0 = piece * span, r1 = min(n_rcv, r0 + span);
     const double* lj = lambda + 2 * (int64_t)job * n_rcv;
     double acc = 0.0;
     bool ok = true;
-    for (int64_t r = threadIdx.x; r < n_rcv; r += 256) {
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
         const double x = lj[2 * r], y = lj[2 * r + 1];
         ok &= isfinite(x) && isfinite(y);
         acc += fabs(x) + fabs(y);
@@ -2002,7 +2005,17 @@ __global__ __launch_bounds__(256) void k_lambda_l1(const double* __restrict__ la
         if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) l1[job] = sm[0];
+    if (threadIdx.x == 0) part[(int64_t)job * pieces + piece] = sm[0];
+}
+
+// l1[job] = sum of the job's partial sums (pieces per job), in order.
+__global__ void k_lambda_l1_sum(const double* __restrict__ part, int32_t n_jobs, int pieces,
+                                double* __restrict__ l1) {
+    const int job = blockIdx.x * blockDim.x + threadIdx.x;
+    if (job >= n_jobs) return;
+    double acc = 0.0;
+    for (int c = 0; c < pieces; ++c) acc += part[(int64_t)job * pieces + c];
+    l1[job] = acc;
 }
 
 // Scales of the adjoint's exact sums.  Segment sums: every contribution is

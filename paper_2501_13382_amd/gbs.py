@@ -495,7 +495,8 @@ class GBSFunction(torch.autograd.Function):
             # TL = -20 log10|P|: dTL = -(20/ln10) Re(dP/P); receivers with P = 0
             # (TL = inf) take no gradient
             g = gTL.to(P.dtype)
-            lam = lam - (20.0 / LN10) * torch.where(g != 0, g / torch.where(P != 0, P, torch.ones_like(P)),
+            live = (g != 0) & (P != 0)
+            lam = lam - (20.0 / LN10) * torch.where(live, g / torch.where(live, P, torch.ones_like(P)),
                                                      torch.zeros_like(P))
         opts = {k: v for k, v in ctx.opts.items() if k in ("c", "gate", "mode", "chunk_segs", "alpha")}
         out = backward(ctx.table, rcv.detach(), ctx.freqs, eps.detach(), gamma.detach(), lam,
