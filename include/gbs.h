@@ -33,6 +33,12 @@
  * library never frees caller memory and keeps no caller pointer after a call
  * returns, except for graphs (gbs_graph_*), which hold the pointers given at
  * creation until gbs_graph_destroy.
+ * Device scratch is held by the context and grows to what its calls need; it
+ * includes the cull's batch records (up to 8 bands), sized from the largest
+ * need seen and capped by the environment variable GBS_CULL_RECORD_BYTES
+ * (bytes, read at each call; default 2 GiB, 0 turns the records off).  The
+ * cap changes speed only: waves whose records do not fit are recomputed and
+ * the results are the same bit for bit.
  *
  * Errors.  Every entry point returns GBS_OK (0) or a negative gbs_status;
  * gbs_last_error() describes the last failure on the context.  Sizes,

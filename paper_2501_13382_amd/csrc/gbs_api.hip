@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -40,7 +41,13 @@ __global__ void k_records(int64_t, const double*, const double*, const double*, 
                           const int32_t*, int64_t, const int64_t*, int64_t, SegRec*, int*, unsigned long long*);
 template <bool FILL, int NB>
 __global__ void k_cull(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int, const CullSplit*,
-                       const int32_t*, const unsigned long long*, int, int, int32_t*, const int64_t*, int32_t*);
+                       const int32_t*, const unsigned long long*, int, int, int32_t*, const int64_t*, int32_t*,
+                       unsigned char*, unsigned*, int64_t, int32_t*);
+__global__ void k_cull_need(const unsigned*, unsigned*);
+size_t cull_batch_bytes(int nb);
+int cull_batch_regions();
+int cull_batch_ctr_stride();
+int cull_batch_block();
 template <int NB>
 __global__ void k_cull_hyper(const JobConst*, const SegRec*, const Patch*, int, int, int, const CullSplit*,
                              const int32_t*, unsigned long long*);
@@ -250,8 +257,11 @@ struct gbs_ctx {
     // list-length reads of up to two planned passes: pinned host words (list
     // total, status word) per slot and the events behind their copies; made
     // at creation so that no call allocates them
-    int64_t* plan_words = nullptr;    // [2][2]: total, status
+    int64_t* plan_words = nullptr;    // [2][3]: total, status, cull batches
     hipEvent_t planned[2] = {nullptr, nullptr};
+    // the most batch records one region of the cull has needed in a pass:
+    // sizes the regions of later passes
+    int64_t cull_region_need = 0;
     // the last gbs_trace_count: its token, what it counted, and its sizes
     // (the per-ray offsets stay in the workspace for gbs_trace to reuse)
     int64_t trace_token = 0, trace_token_next = 0;
@@ -643,7 +653,28 @@ struct Planner {
         const int32_t* d_nsplit = nullptr;
         const unsigned long long* hmask = nullptr;
         int64_t* off = nullptr;
+        unsigned char* bat = nullptr;      // the count pass's batch records, replayed by the fill pass
+        int64_t cap_r = 0;                 // records per region
+        int32_t* heads = nullptr;
     };
+
+    // Records per region of the cull's batch records (up to 8 bands): 1/8
+    // above the most a region of this context has needed, 64 MiB in all
+    // before any pass has run, at most GBS_CULL_RECORD_BYTES in all (default
+    // 2 GiB; 0 turns the records off); none for the allocation-free forward.
+    // The waves that do not fit are recomputed by the fill pass.
+    int64_t cull_region_cap(int nb) const {
+        if (ws.arena || nb == 0) return 0;
+        const size_t stride = cull_batch_bytes(nb), regions = (size_t)cull_batch_regions();
+        size_t limit = size_t(2) << 30;
+        if (const char* e = std::getenv("GBS_CULL_RECORD_BYTES")) limit = (size_t)std::strtoull(e, nullptr, 10);
+        const int64_t need = ctx->cull_region_need;
+        const size_t want = need > 0 ? (size_t)(need + need / 8 + 2 * cull_batch_block()) * stride * regions
+                                     : size_t(64) << 20;
+        // record indices are int32
+        return std::min<int64_t>((int64_t)(std::min(want, limit) / (stride * regions)),
+                                 INT32_MAX / (int64_t)regions - cull_batch_block());
+    }
 
     // Names of a pass's planning buffers: graph creation keeps every pass's
     // under its tag; a call's passes alternate between two slots, so that
@@ -745,6 +776,15 @@ struct Planner {
         hipLaunchKernelGGL(k_make_splits, dim3(1), dim3(64), 0, st, d_src_off, n_src, ps.seg_begin, ps.seg_end, span,
                            (int32_t)max_pieces, d_split, d_nsplit);
         dim3 cg(R.n_super, (unsigned)std::max<int64_t>(max_pieces, 1));
+        // batch records, shared by the passes of a slot (filled before the slot's next plan)
+        const int nb = n_freq == 1 ? 1 : n_freq <= 4 ? 4 : n_freq <= 8 ? 8 : 0;
+        P.cap_r = cull_region_cap(nb);
+        const size_t n_ctr = (size_t)cull_batch_regions() * cull_batch_ctr_stride();
+        P.bat = ws.get<unsigned char>("cull_batches%" + std::to_string(P.slot),
+                                      P.cap_r > 0 ? (size_t)P.cap_r * cull_batch_regions() * cull_batch_bytes(nb) : 1);
+        unsigned* bat_ctr = ws.get<unsigned>("cull_batch_ctr%" + std::to_string(P.slot), n_ctr + 2);
+        P.heads = ws.get<int32_t>("cull_heads%" + std::to_string(P.slot), (size_t)2 * cg.x * cg.y);
+        fill(st, (double*)bat_ctr, (n_ctr + 2) / 2, 0.0);
         // up to 8 bands: band constants in wave-uniform registers, as many as needed
         auto cull_count = n_freq == 1 ? k_cull<false, 1> : n_freq <= 4 ? k_cull<false, 4>
                         : n_freq <= 8 ? k_cull<false, 8> : k_cull<false, 0>;
@@ -758,7 +798,8 @@ struct Planner {
             hipLaunchKernelGGL(cull_hyper, dim3(cps, (unsigned)max_pieces), dim3(kCullThreads), 0, st, dJ, rec,
                                R.hypers, R.n_hyper, n_freq, cps, d_split, d_nsplit, hmask);
             hipLaunchKernelGGL(cull_count, cg, dim3(kWave), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
-                               n_freq, n_split, d_split, d_nsplit, hmask, R.n_hyper, cps, counts, nullptr, nullptr);
+                               n_freq, n_split, d_split, d_nsplit, hmask, R.n_hyper, cps, counts, nullptr, nullptr,
+                               P.bat, bat_ctr, P.cap_r, P.heads);
         }
         GBS_HIP(hipGetLastError());
         // counts are int32; accumulate in int64 through a converting iterator
@@ -767,10 +808,13 @@ struct Planner {
         GBS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, in64, off, (int)(n_cnt + 1), st));
         void* t = ws.get<char>("cub_tmp_scan", tmp);
         GBS_HIP(hipcub::DeviceScan::ExclusiveSum(t, tmp, in64, off, (int)(n_cnt + 1), st));
-        int64_t* words = ctx->plan_words + 2 * P.slot;
+        int64_t* words = ctx->plan_words + 3 * P.slot;
         words[1] = 0;
+        words[2] = 0;
         GBS_HIP(hipMemcpyAsync(words, off + n_cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st));
         GBS_HIP(hipMemcpyAsync(words + 1, status, sizeof(int), hipMemcpyDeviceToHost, st));
+        hipLaunchKernelGGL(k_cull_need, dim3(1), dim3(cull_batch_regions()), 0, st, bat_ctr, bat_ctr + n_ctr);
+        GBS_HIP(hipMemcpyAsync(words + 2, bat_ctr + n_ctr, sizeof(unsigned), hipMemcpyDeviceToHost, st));
         GBS_HIP(hipEventRecord(ctx->planned[P.slot], st));
         P.n_cnt = n_cnt;
         P.max_pieces = max_pieces;
@@ -789,8 +833,9 @@ struct Planner {
         Lists L = P.L;
         if (L.n_items == 0) return L;
         GBS_HIP(hipEventSynchronize(ctx->planned[P.slot]));
-        const int64_t* words = ctx->plan_words + 2 * P.slot;
+        const int64_t* words = ctx->plan_words + 3 * P.slot;
         L.total = words[0];
+        ctx->cull_region_need = std::max(ctx->cull_region_need, words[2]);
         check_status((int)words[1]);     // before any list is filled or any pair kernel runs
         const int n_freq = a.n_freq, n_split = L.n_split;
         const int64_t n_items = L.n_items;
@@ -802,7 +847,7 @@ struct Planner {
         if (L.total > 0)
             hipLaunchKernelGGL(cull_fill, cg, dim3(kWave), 0, st, L.jobs, rec, R.patches, R.supers, R.n_patch,
                                n_freq, n_split, P.d_split, P.d_nsplit, P.hmask, R.n_hyper, P.cps, nullptr, P.off,
-                               lists);
+                               lists, P.bat, nullptr, P.cap_r, P.heads);
         GBS_HIP(hipGetLastError());
         int64_t* off = P.off;
         // longest lists first
@@ -1337,7 +1382,7 @@ int gbs_create(gbs_ctx** out, int device, void* hip_stream) {
         ctx->device = device;
         ctx->n_cu = prop.multiProcessorCount;
         scratch_init(device);
-        GBS_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->plan_words), 4 * sizeof(int64_t)));
+        GBS_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->plan_words), 6 * sizeof(int64_t)));
         for (int i = 0; i < 2; ++i) GBS_HIP(hipEventCreateWithFlags(&ctx->planned[i], hipEventDisableTiming));
         ctx->stream = (hipStream_t)hip_stream;
         ctx->ws->stream = ctx->stream;

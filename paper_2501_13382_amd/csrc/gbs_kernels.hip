@@ -705,6 +705,53 @@ __global__ __launch_bounds__(kCullThreads) void k_cull_hyper(const JobConst* __r
 // cursor at the exclusive prefix sum of those lengths, so each job-patch list
 // is the concatenation of its splits in segment order: deterministic, and
 // identical between the two passes.
+//
+// Batch records (up to 8 bands).  The count pass also writes each level-2
+// batch it tests as a record: the batch's 64 segment indices and, per (patch
+// pm, band b), the ballot of the lanes that passed, at cell pm * NB + b.  A
+// wave takes records in blocks of kBatchBlock consecutive ones from one of
+// kBatchRegions counters (chosen by a hash of the wave), each over its own
+// range of cap_r records; the first record of a block holds the index of the
+// wave's next block, and heads[2 wave] / heads[2 wave + 1] hold the first
+// record and the number of batches.  A wave whose block does not fit stops
+// recording and adds what it still tests to its region's counter, so that
+// the counters tell the host what each region needed.  The fill pass replays
+// a complete chain (no geometry, no record gathers: one load per lane per
+// record, the list cursors of the 16 x NB cells in lane c of one or two
+// registers) and recomputes only the waves whose chain did not fit: either
+// way the same decisions land at the same list positions.
+constexpr int kBatchIds = 16;                              // byte offset of the segment indices
+constexpr int kBatchMasks = kBatchIds + 4 * kWave;         // byte offset of the ballots
+constexpr int kBatchBlock = 4;                             // records a wave takes at a time
+constexpr int kBatchRegions = 256;                         // record counters (power of two)
+constexpr int kBatchCtrStride = 32;                        // counters 128 bytes apart
+constexpr int32_t kChainNone = -1;                         // the wave tested no level-2 batch
+constexpr int32_t kChainOverflow = -2;                     // recompute the wave in the fill pass
+
+// Bytes of one batch record for nb bands (nb = 1, 4 or 8): the index of the
+// next block (int32, padded to 16 bytes), the 64 segment indices (int32),
+// then the ballot (uint64) of cell pm * nb + b.
+size_t cull_batch_bytes(int nb) { return (size_t)kBatchMasks + 8 * (size_t)kSuperPatches * (size_t)nb; }
+int cull_batch_regions() { return kBatchRegions; }
+int cull_batch_ctr_stride() { return kBatchCtrStride; }
+int cull_batch_block() { return kBatchBlock; }
+
+// The largest region counter: what the most loaded region needed.
+__global__ __launch_bounds__(kBatchRegions) void k_cull_need(const unsigned* __restrict__ ctr,
+                                                            unsigned* __restrict__ need) {
+    __shared__ unsigned m[kBatchRegions / kWave];
+    unsigned v = ctr[threadIdx.x * kBatchCtrStride];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, o));
+    if ((threadIdx.x & 63) == 0) m[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned r = 0u;
+        for (int w = 0; w < kBatchRegions / kWave; ++w) r = max(r, m[w]);
+        *need = r;
+    }
+}
+
 template <bool FILL, int NB>
 __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ jobs, const SegRec* __restrict__ rec,
                                                 const Patch* __restrict__ patches, const Patch* __restrict__ supers,
@@ -713,7 +760,9 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
                                                 const int32_t* __restrict__ n_splits,
                                                 const unsigned long long* __restrict__ hmask, int n_hyper,
                                                 int chunks_per_split, int32_t* __restrict__ counts,
-                                                const int64_t* __restrict__ off, int32_t* __restrict__ lists) {
+                                                const int64_t* __restrict__ off, int32_t* __restrict__ lists,
+                                                unsigned char* __restrict__ bat, unsigned* __restrict__ bat_ctr,
+                                                int64_t cap_r, int32_t* __restrict__ heads) {
     constexpr int kQ = 2 * kWave;                         // a partial batch plus one more
     constexpr int kNB = NB > 0 ? NB : kMaxBands;
     __shared__ int32_t q1[kQ];                            // level-1 queue: segment indices
@@ -736,6 +785,76 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
             cur_s[pm * kNB + lane] = (FILL && p < n_patch) ? off[((job0 + lane) * n_patch + p) * n_split + sl.idx] : 0;
     }
     wave_lds_fence();
+    const int64_t wave_id = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    constexpr int kCells = kSuperPatches * (NB > 0 ? NB : 1);         // cells per record
+    constexpr int64_t kStride = kBatchMasks + 8 * kCells;
+    if (FILL) {
+        const int32_t h = heads[2 * wave_id];
+        if (h == kChainNone) return;                      // no list entries from this wave
+        if constexpr (NB > 0) {
+            if (h >= 0) {
+                const int n = heads[2 * wave_id + 1];
+                // cursors: cell c = pm * NB + b in lane c & 63 of cr[c >> 6]
+                int64_t cr[2] = {0, 0};
+#pragma unroll
+                for (int k = 0; k < (kCells + kWave - 1) / kWave; ++k) {
+                    const int c = k * kWave + lane, pm = c / NB, b = c % NB;
+                    if (c < kCells && p0 + pm < n_patch && b < n_freq)
+                        cr[k] = off[((job0 + b) * n_patch + p0 + pm) * n_split + sl.idx];
+                }
+                auto load = [&](int64_t r, int32_t& seg, unsigned long long* m) {
+                    const unsigned char* rp = bat + r * kStride;
+                    seg = reinterpret_cast<const int32_t*>(rp + kBatchIds)[lane];
+                    const unsigned long long* mk = reinterpret_cast<const unsigned long long*>(rp + kBatchMasks);
+#pragma unroll
+                    for (int k = 0; k < (kCells + kWave - 1) / kWave; ++k)
+                        m[k] = k * kWave + lane < kCells ? mk[k * kWave + lane] : 0ull;
+                };
+                int64_t r = h;
+                int32_t nxt = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(bat + r * kStride));
+                int32_t seg;
+                unsigned long long m[2] = {0ull, 0ull};
+                load(r, seg, m);
+                for (int i = 0; i < n; ++i) {
+                    // the next record: the following one in the block, or the next block's first
+                    int32_t seg_n = 0;
+                    unsigned long long m_n[2] = {0ull, 0ull};
+                    int64_t rn = r + 1;
+                    if (i + 1 < n) {
+                        if ((i + 1) % kBatchBlock == 0) {
+                            rn = nxt;
+                            nxt = __builtin_amdgcn_readfirstlane(
+                                *reinterpret_cast<const int32_t*>(bat + rn * kStride));
+                        }
+                        load(rn, seg_n, m_n);
+                    }
+#pragma unroll
+                    for (int k = 0; k < (kCells + kWave - 1) / kWave; ++k) {
+                        unsigned long long live = __ballot(m[k] != 0ull);
+                        while (live) {
+                            const int c = __builtin_ctzll(live);
+                            live &= live - 1ull;
+                            const unsigned long long bl = (unsigned long long)lane_i64((int64_t)m[k], c);
+                            if ((bl >> lane) & 1ull) lists[lane_i64(cr[k], c) + lanes_before(bl)] = seg;
+                            cr[k] += lane == c ? (int64_t)__popcll(bl) : 0;
+                        }
+                    }
+                    r = rn;
+                    seg = seg_n;
+                    m[0] = m_n[0];
+                    m[1] = m_n[1];
+                }
+                return;
+            }
+        }
+    }
+    // count pass: this wave's chain (the current block and the records used in it)
+    const unsigned region = ((unsigned)wave_id * 0x9E3779B1u) >> 24;
+    unsigned* my_ctr = bat_ctr + region * kBatchCtrStride;
+    int32_t head = kChainNone;
+    int64_t blk = -1;
+    int used = kBatchBlock, n_batch = 0, n_lost = 0;
+    bool chain_ok = true;
     // level 2 over queue entries [0, n), n <= 64
     auto level2 = [&](int n) {
         const bool valid = lane < n;
@@ -743,6 +862,33 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
         const CullRec S = q_rec[i];
         const int32_t seg = q_seg[i];
         const unsigned long long bm = valid ? q_mask[i] : 0ull;
+        int64_t slot = -1;                                // count pass: this batch's record, if it has one
+        if constexpr (!FILL) ++n_batch;
+        if constexpr (!FILL && NB > 0) {
+            if (chain_ok && used == kBatchBlock) {
+                unsigned got = 0u;
+                if (lane == 0) got = atomicAdd(my_ctr, (unsigned)kBatchBlock);
+                got = __builtin_amdgcn_readfirstlane(got);
+                if ((int64_t)got + kBatchBlock <= cap_r) {
+                    const int64_t nb = (int64_t)region * cap_r + got;
+                    if (blk >= 0) {
+                        if (lane == 0) *reinterpret_cast<int32_t*>(bat + blk * kStride) = (int32_t)nb;
+                    } else {
+                        head = (int32_t)nb;
+                    }
+                    blk = nb;
+                    used = 0;
+                } else {
+                    chain_ok = false;
+                }
+            }
+            if (chain_ok) {
+                slot = blk + used++;
+            } else {
+                ++n_lost;
+            }
+        }
+        unsigned long long mrec[2] = {0ull, 0ull};        // count pass: cell c's ballot in lane c & 63
         for (int pm = 0; pm < kSuperPatches; ++pm) {
             const int p = p0 + pm;
             if (p >= n_patch) break;
@@ -755,8 +901,26 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
                 if (bl == 0ull) continue;
                 if (FILL && k2) lists[lane_i64(cur, b) + lanes_before(bl)] = seg;
                 cur += lane == b ? (int64_t)__popcll(bl) : 0;
+                if constexpr (!FILL && NB > 0) {
+                    const int c = pm * NB + b;
+                    if (c < kWave) {
+                        mrec[0] = lane == c ? bl : mrec[0];
+                    } else {
+                        mrec[1] = lane == c - kWave ? bl : mrec[1];
+                    }
+                }
             }
             if (lane < n_freq) cur_s[pm * kNB + lane] = cur;
+        }
+        if constexpr (!FILL && NB > 0) {
+            if (slot >= 0) {
+                unsigned char* rp = bat + slot * kStride;
+                reinterpret_cast<int32_t*>(rp + kBatchIds)[lane] = valid ? seg : -1;
+                unsigned long long* mk = reinterpret_cast<unsigned long long*>(rp + kBatchMasks);
+#pragma unroll
+                for (int k = 0; k < (kCells + kWave - 1) / kWave; ++k)
+                    if (k * kWave + lane < kCells) mk[k * kWave + lane] = mrec[k];
+            }
         }
     };
     int qn = 0;                                           // level-2 queue length
@@ -852,6 +1016,16 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
             const int p = p0 + pm;
             if (p < n_patch && lane < n_freq)
                 counts[((job0 + lane) * n_patch + p) * n_split + sl.idx] = (int32_t)cur_s[pm * kNB + lane];
+        }
+        if constexpr (NB > 0) {
+            if (lane == 0) {
+                heads[2 * wave_id] = chain_ok ? head : kChainOverflow;
+                heads[2 * wave_id + 1] = n_batch;
+                if (n_lost > kBatchBlock)      // the failed block's counter step covered the first of them
+                    atomicAdd(my_ctr, (unsigned)((n_lost - 1) / kBatchBlock * kBatchBlock));
+            }
+        } else {
+            if (lane == 0) heads[2 * wave_id] = n_batch > 0 ? kChainOverflow : kChainNone;
         }
     }
 }
@@ -2080,7 +2254,8 @@ __global__ void k_dgamma(const double* __restrict__ Zf, int32_t n_faces, double*
 #define GBS_INST_CULL(F, NB)                                                                                   \
     template __global__ void k_cull<F, NB>(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int, \
                                            const CullSplit*, const int32_t*, const unsigned long long*, int, int,    \
-                                           int32_t*, const int64_t*, int32_t*);
+                                           int32_t*, const int64_t*, int32_t*, unsigned char*, unsigned*, int64_t,   \
+                                           int32_t*);
 #define GBS_INST_CULL_NB(NB)                                                                                   \
     GBS_INST_CULL(false, NB)                                                                                   \
     GBS_INST_CULL(true, NB)                                                                                    \

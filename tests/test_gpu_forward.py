@@ -17,7 +17,7 @@ import torch
 
 import paper_2501_13382_amd as gbs
 from paper_2501_13382_amd import _lib
-from scenes import (RayTable, city_10x10, city_5x5_panels, city_batched, open_plane, open_plane_100k,
+from scenes import (OCTAVES_8, RayTable, city_10x10, city_5x5_panels, city_batched, open_plane, open_plane_100k,
                     open_plane_2k, receiver_subsample)
 from tests.gpu_util import assert_within, compare, reference
 
@@ -149,6 +149,33 @@ def test_deterministic_repeat(city_small):
     P1, _ = gpu_forward(sc, mode="mix")
     P2, _ = gpu_forward(sc, mode="mix")
     assert np.array_equal(P1, P2)
+
+
+@pytest.mark.parametrize("case", ["city_1band", "batched_4band", "plane_8band"])
+def test_cull_records_replayed_or_recomputed_agree(case, city_small, monkeypatch):
+    """The cull's fill pass replays the batch records of its count pass, and
+    recomputes the waves whose records did not fit in GBS_CULL_RECORD_BYTES:
+    the same lists, so the same sums bit for bit, whether every wave, one
+    block of records per region (the rest recomputed) or no wave is recorded."""
+    if case == "city_1band":
+        sc, nb = city_small[0], 1
+    elif case == "batched_4band":
+        sc, nb = city_batched(n_src=4, ray_lo=2000, ray_hi=9000, grid=24), 4
+    else:
+        sc, nb = open_plane(n_rays=20000, grid=64, freqs=OCTAVES_8, name="plane_8band"), 8
+    one_block_per_region = 4 * 256 * (272 + 128 * nb)
+    out = {}
+    for label, limit in (("all", None), ("some", one_block_per_region), ("none", 0)):
+        if limit is None:
+            monkeypatch.delenv("GBS_CULL_RECORD_BYTES", raising=False)
+        else:
+            monkeypatch.setenv("GBS_CULL_RECORD_BYTES", str(limit))
+        print(f"case {case} records={label}", flush=True)
+        out[label] = [gpu_forward(sc, mode="mix")[0] for _ in range(2)]
+    ref = out["all"][1]
+    for label, runs in out.items():
+        for P in runs:
+            assert np.array_equal(P, ref), label
 
 
 @pytest.mark.parametrize("nr", [1, 2, 4])
