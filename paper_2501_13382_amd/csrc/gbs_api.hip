@@ -44,10 +44,14 @@ __global__ void k_cull(const JobConst*, const SegRec*, const Patch*, const Patch
                        const int32_t*, const unsigned long long*, int, int, int32_t*, const int64_t*, int32_t*,
                        unsigned char*, unsigned*, int64_t, int32_t*);
 __global__ void k_cull_need(const unsigned*, unsigned*);
+template <int NB>
+__global__ void k_cull_replay(const CullSplit*, const int32_t*, int, int, int, int, const int64_t*,
+                              const unsigned char*, const int32_t*, int32_t*);
 size_t cull_batch_bytes(int nb);
 int cull_batch_regions();
 int cull_batch_ctr_stride();
 int cull_batch_block();
+int cull_replay_waves();
 template <int NB>
 __global__ void k_cull_hyper(const JobConst*, const SegRec*, const Patch*, int, int, int, const CullSplit*,
                              const int32_t*, unsigned long long*);
@@ -163,6 +167,10 @@ void fill(hipStream_t st, double* p, int64_t n, double v) {
 // allocation-free forward) every buffer is carved from one fixed device
 // region instead: nothing is allocated or freed, and a call that needs more
 // than the region fails with GBS_E_UNSUPPORTED.
+// Work-unit size of calls that run in several passes (smaller than
+// kWorkChunk: a short pass cannot hide a long last unit).
+constexpr int kWorkChunkPasses = 512;
+
 struct Workspace {
     std::map<std::string, std::pair<void*, size_t>> bufs;
     hipStream_t stream = nullptr;
@@ -400,11 +408,14 @@ struct Planner {
     }
     int chunk_override = 0;   // autotuner candidate
     std::string tag;          // graph creation: per-pass names for the buffers the replays read
+    // Segments per work unit: the caller's, the tuned one, else kWorkChunk
+    // for one pass and kWorkChunkPasses when the call runs in several passes
+    // (each pass's pair launch ends on its own longest unit).
     int work_chunk() const {
         if (chunk_override) return chunk_override;
         if (a.params->work_chunk) return a.params->work_chunk;
         if (ctx->tuned_chunk[a.params->mode]) return ctx->tuned_chunk[a.params->mode];
-        return kWorkChunk;
+        return passes.size() > 1 ? kWorkChunkPasses : kWorkChunk;
     }
 
     bool aniso() const { return a.params->eps_e2 != nullptr; }
@@ -757,10 +768,15 @@ struct Planner {
         // are laid out on the device (k_make_splits); the host sizes the grids
         // for the most pieces a pass can have: one cull wave per (super-patch,
         // piece), up to 256 pieces per source, fewer when the per-piece
-        // lengths would outgrow 64M counters
+        // lengths would outgrow 64M counters.  Pieces hold 1,024 segments or
+        // more, down to 256 when a pass is too short for 32,768 cull waves
+        // (the waves near the source set a short pass's time)
         const int n_src = a.rays->n_src, n_freq = a.n_freq;
         const int64_t max_split = std::max<int64_t>(1, std::min<int64_t>(256, (int64_t(1) << 26) / n_items));
-        int64_t span = std::max<int64_t>(1024, (nseg + max_split - 1) / max_split);
+        int64_t span_min = 1024;
+        while (span_min > kCullThreads && (int64_t)R.n_super * ((nseg + span_min - 1) / span_min) < 32768)
+            span_min -= kCullThreads;
+        int64_t span = std::max<int64_t>(span_min, (nseg + max_split - 1) / max_split);
         span = (span + kCullThreads - 1) / kCullThreads * kCullThreads;
         const int n_split = (int)std::max<int64_t>(1, (nseg + span - 1) / span);   // pieces per source, at most
         const int64_t max_pieces = std::min<int64_t>((int64_t)n_src * n_split, n_src + (nseg + span - 1) / span);
@@ -844,28 +860,44 @@ struct Planner {
         auto cull_fill = n_freq == 1 ? k_cull<true, 1> : n_freq <= 4 ? k_cull<true, 4>
                        : n_freq <= 8 ? k_cull<true, 8> : k_cull<true, 0>;
         dim3 cg(R.n_super, (unsigned)std::max<int64_t>(P.max_pieces, 1));
-        if (L.total > 0)
-            hipLaunchKernelGGL(cull_fill, cg, dim3(kWave), 0, st, L.jobs, rec, R.patches, R.supers, R.n_patch,
-                               n_freq, n_split, P.d_split, P.d_nsplit, P.hmask, R.n_hyper, P.cps, nullptr, P.off,
-                               lists, P.bat, nullptr, P.cap_r, P.heads);
+        if (L.total > 0) {
+            // recorded waves are replayed; k_cull recomputes the others, and
+            // runs only when a region ran out of records (or none were kept)
+            auto replay = n_freq == 1 ? k_cull_replay<1> : n_freq <= 4 ? k_cull_replay<4>
+                        : n_freq <= 8 ? k_cull_replay<8> : nullptr;
+            const int64_t n_waves = (int64_t)cg.x * cg.y;
+            if (replay && P.cap_r > 0)
+                hipLaunchKernelGGL(replay, dim3((unsigned)((n_waves + cull_replay_waves() - 1) / cull_replay_waves())),
+                                   dim3(cull_replay_waves() * kWave), 0, st, P.d_split,
+                                   P.d_nsplit, (int)R.n_super, R.n_patch, n_freq, n_split, P.off, P.bat, P.heads,
+                                   lists);
+            if (!replay || words[2] > P.cap_r)
+                hipLaunchKernelGGL(cull_fill, cg, dim3(kWave), 0, st, L.jobs, rec, R.patches, R.supers, R.n_patch,
+                                   n_freq, n_split, P.d_split, P.d_nsplit, P.hmask, R.n_hyper, P.cps, nullptr, P.off,
+                                   lists, P.bat, nullptr, P.cap_r, P.heads);
+        }
         GBS_HIP(hipGetLastError());
         int64_t* off = P.off;
-        // longest lists first
+        // longest lists first, unless the units are short enough that their
+        // order cannot leave a long one for the end (items keep their order)
+        const int chunk = work_chunk();
         int32_t* lens = ws.get<int32_t>("lens", n_items);
         hipLaunchKernelGGL(k_item_lengths, dim3(blocks_for(n_items, 256)), dim3(256), 0, st, off, (int32_t)n_items,
                            n_split, lens);
-        int32_t* keys2 = ws.get<int32_t>("okeys", n_items);
         int32_t* ids = ws.get<int32_t>("oids", n_items);
-        int32_t* order = ws.get<int32_t>("order", n_items);
+        int32_t* order = ids;
         hipLaunchKernelGGL(k_iota, dim3(blocks_for(n_items, 256)), dim3(256), 0, st, ids, (int32_t)n_items);
-        size_t tmp2 = 0;
-        GBS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tmp2, lens, keys2, ids, order, (int)n_items,
-                                                             0, 32, st));
-        void* t2 = ws.get<char>("cub_tmp_order", tmp2);
-        GBS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(t2, tmp2, lens, keys2, ids, order, (int)n_items, 0, 32,
-                                                             st));
+        if (chunk > kWorkChunkPasses) {
+            int32_t* keys2 = ws.get<int32_t>("okeys", n_items);
+            order = ws.get<int32_t>("order", n_items);
+            size_t tmp2 = 0;
+            GBS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tmp2, lens, keys2, ids, order,
+                                                                 (int)n_items, 0, 32, st));
+            void* t2 = ws.get<char>("cub_tmp_order", tmp2);
+            GBS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(t2, tmp2, lens, keys2, ids, order, (int)n_items, 0,
+                                                                 32, st));
+        }
         // work units: every list cut into chunks of at most `chunk` segments
-        const int chunk = work_chunk();
         const int64_t cap = n_items + L.total / chunk + 1;
         GBS_CHECK(cap < INT32_MAX, "too many work units");
         int32_t* nw = ws.get<int32_t>("nwork", n_items + 1);

@@ -696,7 +696,9 @@ __global__ __launch_bounds__(kCullThreads) void k_cull_hyper(const JobConst* __r
 //   keeps for the super-patch's hyper-patch are queued by index;
 //   level 1: a batch of queued segments is loaded (one record per lane) and
 //            tested against the super-patch sphere for every band of its
-//            source; survivors, with their records and band masks, are queued;
+//            source; survivors, with their records and band masks, are queued
+//            (the level-2 queue holds one batch in LDS: survivors past it
+//            wait in their lanes' registers until that batch is tested);
 //   level 2: a batch of survivors is tested against the 16 patches, band by
 //            band, and appended to the (job, patch) lists.
 // The list cursors of the wave's 16 patches live in LDS between batches and
@@ -766,9 +768,9 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
     constexpr int kQ = 2 * kWave;                         // a partial batch plus one more
     constexpr int kNB = NB > 0 ? NB : kMaxBands;
     __shared__ int32_t q1[kQ];                            // level-1 queue: segment indices
-    __shared__ __align__(16) CullRec q_rec[kQ];           // level-2 queue: records, indices, band masks
-    __shared__ int32_t q_seg[kQ];
-    __shared__ unsigned long long q_mask[kQ];
+    __shared__ __align__(16) CullRec q_rec[kWave];        // level-2 queue (one batch): records, indices,
+    __shared__ int32_t q_seg[kWave];                      // band masks
+    __shared__ unsigned long long q_mask[kWave];
     __shared__ int64_t cur_s[kSuperPatches * kNB];        // cursor of (patch pm, band b) at pm * kNB + b
     const int sp = blockIdx.x;
     if ((int)blockIdx.y >= *n_splits) return;             // the grid covers the most pieces a pass can have
@@ -788,66 +790,7 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
     const int64_t wave_id = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     constexpr int kCells = kSuperPatches * (NB > 0 ? NB : 1);         // cells per record
     constexpr int64_t kStride = kBatchMasks + 8 * kCells;
-    if (FILL) {
-        const int32_t h = heads[2 * wave_id];
-        if (h == kChainNone) return;                      // no list entries from this wave
-        if constexpr (NB > 0) {
-            if (h >= 0) {
-                const int n = heads[2 * wave_id + 1];
-                // cursors: cell c = pm * NB + b in lane c & 63 of cr[c >> 6]
-                int64_t cr[2] = {0, 0};
-#pragma unroll
-                for (int k = 0; k < (kCells + kWave - 1) / kWave; ++k) {
-                    const int c = k * kWave + lane, pm = c / NB, b = c % NB;
-                    if (c < kCells && p0 + pm < n_patch && b < n_freq)
-                        cr[k] = off[((job0 + b) * n_patch + p0 + pm) * n_split + sl.idx];
-                }
-                auto load = [&](int64_t r, int32_t& seg, unsigned long long* m) {
-                    const unsigned char* rp = bat + r * kStride;
-                    seg = reinterpret_cast<const int32_t*>(rp + kBatchIds)[lane];
-                    const unsigned long long* mk = reinterpret_cast<const unsigned long long*>(rp + kBatchMasks);
-#pragma unroll
-                    for (int k = 0; k < (kCells + kWave - 1) / kWave; ++k)
-                        m[k] = k * kWave + lane < kCells ? mk[k * kWave + lane] : 0ull;
-                };
-                int64_t r = h;
-                int32_t nxt = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(bat + r * kStride));
-                int32_t seg;
-                unsigned long long m[2] = {0ull, 0ull};
-                load(r, seg, m);
-                for (int i = 0; i < n; ++i) {
-                    // the next record: the following one in the block, or the next block's first
-                    int32_t seg_n = 0;
-                    unsigned long long m_n[2] = {0ull, 0ull};
-                    int64_t rn = r + 1;
-                    if (i + 1 < n) {
-                        if ((i + 1) % kBatchBlock == 0) {
-                            rn = nxt;
-                            nxt = __builtin_amdgcn_readfirstlane(
-                                *reinterpret_cast<const int32_t*>(bat + rn * kStride));
-                        }
-                        load(rn, seg_n, m_n);
-                    }
-#pragma unroll
-                    for (int k = 0; k < (kCells + kWave - 1) / kWave; ++k) {
-                        unsigned long long live = __ballot(m[k] != 0ull);
-                        while (live) {
-                            const int c = __builtin_ctzll(live);
-                            live &= live - 1ull;
-                            const unsigned long long bl = (unsigned long long)lane_i64((int64_t)m[k], c);
-                            if ((bl >> lane) & 1ull) lists[lane_i64(cr[k], c) + lanes_before(bl)] = seg;
-                            cr[k] += lane == c ? (int64_t)__popcll(bl) : 0;
-                        }
-                    }
-                    r = rn;
-                    seg = seg_n;
-                    m[0] = m_n[0];
-                    m[1] = m_n[1];
-                }
-                return;
-            }
-        }
-    }
+    if (FILL && heads[2 * wave_id] != kChainOverflow) return;   // replayed by k_cull_replay, or empty
     // count pass: this wave's chain (the current block and the records used in it)
     const unsigned region = ((unsigned)wave_id * 0x9E3779B1u) >> 24;
     unsigned* my_ctr = bat_ctr + region * kBatchCtrStride;
@@ -940,8 +883,10 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
         }
         const unsigned long long bal = __ballot(mask != 0ull);
         if (bal == 0ull) return;
-        if (mask != 0ull) {
-            const int pos = qn + lanes_before(bal);
+        // survivors at queue positions past the batch keep their records in
+        // registers until the full batch has been tested
+        const int pos = qn + lanes_before(bal);
+        if (mask != 0ull && pos < kWave) {
             q_rec[pos] = me;
             q_seg[pos] = j;
             q_mask[pos] = mask;
@@ -950,31 +895,14 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
         wave_lds_fence();
         if (qn >= kWave) {
             level2(kWave);
-            const int rest = qn - kWave;                  // move the tail [64, qn) to the front
-            double2 t0 = make_double2(0, 0), t1 = t0, t2 = t0, t3 = t0;
-            int32_t ts = 0;
-            unsigned long long tm = 0ull;
-            if (lane < rest) {
-                const double2* q = reinterpret_cast<const double2*>(q_rec + kWave + lane);
-                t0 = q[0];
-                t1 = q[1];
-                t2 = q[2];
-                t3 = q[3];
-                ts = q_seg[kWave + lane];
-                tm = q_mask[kWave + lane];
+            wave_lds_fence();
+            if (mask != 0ull && pos >= kWave) {
+                q_rec[pos - kWave] = me;
+                q_seg[pos - kWave] = j;
+                q_mask[pos - kWave] = mask;
             }
             wave_lds_fence();
-            if (lane < rest) {
-                double2* q = reinterpret_cast<double2*>(q_rec + lane);
-                q[0] = t0;
-                q[1] = t1;
-                q[2] = t2;
-                q[3] = t3;
-                q_seg[lane] = ts;
-                q_mask[lane] = tm;
-            }
-            wave_lds_fence();
-            qn = rest;
+            qn -= kWave;
         }
     };
     // level-0 bits of 64-segment chunk ci for the super-patch's hyper-patch
@@ -1027,6 +955,84 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
         } else {
             if (lane == 0) heads[2 * wave_id] = n_batch > 0 ? kChainOverflow : kChainNone;
         }
+    }
+}
+
+// The fill pass of the waves whose batch records are complete: one wave per
+// cull wave (super-patch, piece), kReplayWaves per workgroup, no LDS.  The records
+// are replayed in chain order (the next one loaded while the current one is
+// written); the list cursors of the 16 x NB cells start at the prefix sums
+// of the count pass, as in k_cull, and live in lane c & 63 of cr[c >> 6].
+constexpr int kReplayWaves = 1;
+int cull_replay_waves() { return kReplayWaves; }
+template <int NB>
+__global__ __launch_bounds__(kReplayWaves * kWave) void k_cull_replay(const CullSplit* __restrict__ splits,
+                                                     const int32_t* __restrict__ n_splits, int n_super,
+                                                     int n_patch, int n_freq, int n_split,
+                                                     const int64_t* __restrict__ off,
+                                                     const unsigned char* __restrict__ bat,
+                                                     const int32_t* __restrict__ heads, int32_t* __restrict__ lists) {
+    constexpr int kCells = kSuperPatches * NB;
+    constexpr int kRegs = (kCells + kWave - 1) / kWave;
+    constexpr int64_t kStride = kBatchMasks + 8 * kCells;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave_id = (int64_t)blockIdx.x * kReplayWaves + (threadIdx.x >> 6);
+    const int64_t piece = wave_id / n_super;
+    if (piece >= *n_splits) return;
+    const int32_t h = heads[2 * wave_id];
+    if (h < 0) return;                                    // empty, or recomputed by k_cull
+    const int n = heads[2 * wave_id + 1];
+    const CullSplit sl = splits[piece];
+    const int64_t job0 = (int64_t)sl.src * n_freq;
+    const int p0 = (int)(wave_id - piece * n_super) * kSuperPatches;
+    int64_t cr[kRegs];
+#pragma unroll
+    for (int k = 0; k < kRegs; ++k) {
+        const int c = k * kWave + lane, pm = c / NB, b = c % NB;
+        cr[k] = c < kCells && p0 + pm < n_patch && b < n_freq
+                    ? off[((job0 + b) * n_patch + p0 + pm) * n_split + sl.idx] : 0;
+    }
+    auto load = [&](int64_t r, int32_t& seg, unsigned long long* m) {
+        const unsigned char* rp = bat + r * kStride;
+        seg = reinterpret_cast<const int32_t*>(rp + kBatchIds)[lane];
+        const unsigned long long* mk = reinterpret_cast<const unsigned long long*>(rp + kBatchMasks);
+#pragma unroll
+        for (int k = 0; k < kRegs; ++k) m[k] = k * kWave + lane < kCells ? mk[k * kWave + lane] : 0ull;
+    };
+    int64_t r = h;
+    int32_t nxt = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(bat + r * kStride));
+    int32_t seg;
+    unsigned long long m[kRegs];
+    load(r, seg, m);
+    for (int i = 0; i < n; ++i) {
+        // the next record: the following one in the block, or the next block's first
+        int32_t seg_n = 0;
+        unsigned long long m_n[kRegs];
+#pragma unroll
+        for (int k = 0; k < kRegs; ++k) m_n[k] = 0ull;
+        int64_t rn = r + 1;
+        if (i + 1 < n) {
+            if ((i + 1) % kBatchBlock == 0) {
+                rn = nxt;
+                nxt = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(bat + rn * kStride));
+            }
+            load(rn, seg_n, m_n);
+        }
+#pragma unroll
+        for (int k = 0; k < kRegs; ++k) {
+            unsigned long long live = __ballot(m[k] != 0ull);
+            while (live) {
+                const int c = __builtin_ctzll(live);
+                live &= live - 1ull;
+                const unsigned long long bl = (unsigned long long)lane_i64((int64_t)m[k], c);
+                if ((bl >> lane) & 1ull) lists[lane_i64(cr[k], c) + lanes_before(bl)] = seg;
+                cr[k] += lane == c ? (int64_t)__popcll(bl) : 0;
+            }
+        }
+        r = rn;
+        seg = seg_n;
+#pragma unroll
+        for (int k = 0; k < kRegs; ++k) m[k] = m_n[k];
     }
 }
 
@@ -2265,6 +2271,12 @@ GBS_INST_CULL_NB(1)
 GBS_INST_CULL_NB(4)
 GBS_INST_CULL_NB(8)
 GBS_INST_CULL_NB(0)
+#define GBS_INST_REPLAY(NB)                                                                                    \
+    template __global__ void k_cull_replay<NB>(const CullSplit*, const int32_t*, int, int, int, int,           \
+                                               const int64_t*, const unsigned char*, const int32_t*, int32_t*);
+GBS_INST_REPLAY(1)
+GBS_INST_REPLAY(4)
+GBS_INST_REPLAY(8)
 #define GBS_INST_PAIRS(M, N, C)                                                                                  \
     template __global__ void k_pairs<M, N, C>(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*,    \
                                               const int32_t*, const SegRec*, const FrameRec*, const double*,     \
