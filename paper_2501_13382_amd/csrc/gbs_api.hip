@@ -34,18 +34,20 @@ __global__ void k_src_ranges(const int64_t*, const int32_t*, int64_t, int32_t, i
                              int64_t*, int*);
 __global__ void k_job_consts(const double*, const double*, const double*, const double*, int32_t, int32_t, double,
                              double, const int64_t*, int64_t, int64_t, JobConst*, int*);
-__global__ void k_make_splits(const int64_t*, int32_t, int64_t, int64_t, int64_t, int32_t, CullSplit*, int32_t*);
+__global__ void k_make_splits(const int64_t*, int32_t, int64_t, int64_t, int64_t, int32_t, int64_t, CullSplit*,
+                              int32_t*, int64_t*);
 __global__ void k_seg2ray(const int64_t*, int64_t, int64_t, int64_t, int32_t*);
 __global__ void k_records(int64_t, const double*, const double*, const double*, const double*, const double*,
                           const int64_t*, int64_t, const int32_t*, int32_t, const double*, const double*,
                           const int32_t*, int64_t, const int64_t*, int64_t, SegRec*, int*, unsigned long long*);
 template <bool FILL, int NB>
-__global__ void k_cull(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int, const CullSplit*,
+__global__ void k_cull(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, const int64_t*,
+                       const CullSplit*,
                        const int32_t*, const unsigned long long*, int, int, int32_t*, const int64_t*, int32_t*,
                        unsigned char*, unsigned*, int64_t, int32_t*);
 __global__ void k_cull_need(const unsigned*, unsigned*);
 template <int NB>
-__global__ void k_cull_replay(const CullSplit*, const int32_t*, int, int, int, int, const int64_t*,
+__global__ void k_cull_replay(const CullSplit*, const int32_t*, int, int, int, const int64_t*, const int64_t*,
                               const unsigned char*, const int32_t*, int32_t*);
 size_t cull_batch_bytes(int nb);
 int cull_batch_regions();
@@ -55,7 +57,7 @@ int cull_replay_waves();
 template <int NB>
 __global__ void k_cull_hyper(const JobConst*, const SegRec*, const Patch*, int, int, int, const CullSplit*,
                              const int32_t*, unsigned long long*);
-__global__ void k_item_lengths(const int64_t*, int32_t, int, int32_t*);
+__global__ void k_item_lengths(const int64_t*, int32_t, int, int, const int64_t*, int32_t*);
 __global__ void k_iota(int32_t*, int32_t);
 __global__ void k_seg_keys(int64_t, const SegRec*, const JobConst*, int32_t, int32_t, const double*,
                            unsigned long long*, int32_t*);
@@ -67,8 +69,8 @@ __global__ void k_pairs(const JobConst*, const Work*, const int32_t*, int32_t, u
                         const SegRec*, const FrameRec*, const double*, const double*, const double*, const double*,
                         double*, unsigned long long*);
 __global__ void k_work_counts(const int32_t*, const int32_t*, int32_t, int32_t, int32_t*);
-__global__ void k_make_work(const int32_t*, const int64_t*, int32_t, const int32_t*, int32_t, int32_t, Work*, int32_t*,
-                            int32_t*, int32_t*);
+__global__ void k_make_work(const int32_t*, const int64_t*, int, int, const int64_t*, const int32_t*, int32_t, int32_t,
+                            Work*, int32_t*, int32_t*, int32_t*);
 __global__ void k_reduce_partials(const JobConst*, const int32_t*, const int32_t*, int32_t, int32_t, int,
                                   const int32_t*, int64_t, const double*, double*);
 __global__ void k_tl(const double*, int64_t, double*);
@@ -627,7 +629,7 @@ struct Planner {
 
     struct Lists {
         int32_t n_items = 0;
-        int32_t n_split = 1;      // list offsets are strided: item i spans off[i*n_split .. (i+1)*n_split]
+        const int64_t* src_cnt = nullptr;   // per source: first counter, pieces (item_cnt in the kernels)
         int64_t total = 0;
         const JobConst* jobs = nullptr;
         const SegRec* rec = nullptr;       // records in spatial order (what the kernels read)
@@ -767,30 +769,37 @@ struct Planner {
         // workgroup culls one piece for all bands of its source.  The pieces
         // are laid out on the device (k_make_splits); the host sizes the grids
         // for the most pieces a pass can have: one cull wave per (super-patch,
-        // piece), up to 256 pieces per source, fewer when the per-piece
-        // lengths would outgrow 64M counters.  Pieces hold 1,024 segments or
-        // more, down to 256 when a pass is too short for 32,768 cull waves
-        // (the waves near the source set a short pass's time)
+        // piece), up to 256 pieces per source and about 64M list-length
+        // counters in all.  A piece holds 1,024 segments or more, down to 256
+        // when a pass is too short for 32,768 cull waves (the waves near the
+        // source set a short pass's time).  Each piece has one counter per
+        // (band, patch) of its source; a source's counters are (band, patch,
+        // piece) in that order from src_cnt[2 s], so the prefix sum of all
+        // counters lays every (source, band, patch) list out as its pieces in
+        // segment order
         const int n_src = a.rays->n_src, n_freq = a.n_freq;
-        const int64_t max_split = std::max<int64_t>(1, std::min<int64_t>(256, (int64_t(1) << 26) / n_items));
+        const int64_t cells = (int64_t)n_freq * R.n_patch;
+        const int64_t budget = std::max<int64_t>(
+            1, std::min<int64_t>(256 * (int64_t)n_src, ((int64_t(1) << 26) / cells) - n_src));
         int64_t span_min = 1024;
         while (span_min > kCullThreads && (int64_t)R.n_super * ((nseg + span_min - 1) / span_min) < 32768)
             span_min -= kCullThreads;
-        int64_t span = std::max<int64_t>(span_min, (nseg + max_split - 1) / max_split);
+        int64_t span = std::max<int64_t>(span_min, (nseg + budget - 1) / budget);
         span = (span + kCullThreads - 1) / kCullThreads * kCullThreads;
-        const int n_split = (int)std::max<int64_t>(1, (nseg + span - 1) / span);   // pieces per source, at most
-        const int64_t max_pieces = std::min<int64_t>((int64_t)n_src * n_split, n_src + (nseg + span - 1) / span);
+        const int64_t n_span = std::max<int64_t>(1, (nseg + span - 1) / span);   // pieces per source, at most
+        const int64_t max_pieces = std::min<int64_t>((int64_t)n_src * n_span, n_src + n_span);
         GBS_CHECK(max_pieces < 65536, "too many cull pieces");
-        L.n_split = n_split;
-        const int64_t n_cnt = n_items * n_split;
+        const int64_t n_cnt = cells * max_pieces;
         GBS_CHECK(n_cnt < INT32_MAX, "too many cull partitions");
         int32_t* counts = ws.get<int32_t>(slot_name("counts", P.slot), n_cnt + 2);
         int64_t* off = ws.get<int64_t>(slot_name("item_off", P.slot), n_cnt + 1);
         fill(st, (double*)counts, (n_cnt + 2) / 2, 0.0);
         CullSplit* d_split = ws.get<CullSplit>(slot_name("splits", P.slot), std::max<int64_t>(max_pieces, 1));
         int32_t* d_nsplit = ws.get<int32_t>(slot_name("n_splits", P.slot), 1);
+        int64_t* src_cnt = ws.get<int64_t>(slot_name("src_cnt", P.slot), 2 * (size_t)n_src);
         hipLaunchKernelGGL(k_make_splits, dim3(1), dim3(64), 0, st, d_src_off, n_src, ps.seg_begin, ps.seg_end, span,
-                           (int32_t)max_pieces, d_split, d_nsplit);
+                           (int32_t)max_pieces, cells, d_split, d_nsplit, src_cnt);
+        L.src_cnt = src_cnt;
         dim3 cg(R.n_super, (unsigned)std::max<int64_t>(max_pieces, 1));
         // batch records, shared by the passes of a slot (filled before the slot's next plan)
         const int nb = n_freq == 1 ? 1 : n_freq <= 4 ? 4 : n_freq <= 8 ? 8 : 0;
@@ -814,7 +823,7 @@ struct Planner {
             hipLaunchKernelGGL(cull_hyper, dim3(cps, (unsigned)max_pieces), dim3(kCullThreads), 0, st, dJ, rec,
                                R.hypers, R.n_hyper, n_freq, cps, d_split, d_nsplit, hmask);
             hipLaunchKernelGGL(cull_count, cg, dim3(kWave), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
-                               n_freq, n_split, d_split, d_nsplit, hmask, R.n_hyper, cps, counts, nullptr, nullptr,
+                               n_freq, src_cnt, d_split, d_nsplit, hmask, R.n_hyper, cps, counts, nullptr, nullptr,
                                P.bat, bat_ctr, P.cap_r, P.heads);
         }
         GBS_HIP(hipGetLastError());
@@ -853,7 +862,7 @@ struct Planner {
         L.total = words[0];
         ctx->cull_region_need = std::max(ctx->cull_region_need, words[2]);
         check_status((int)words[1]);     // before any list is filled or any pair kernel runs
-        const int n_freq = a.n_freq, n_split = L.n_split;
+        const int n_freq = a.n_freq;
         const int64_t n_items = L.n_items;
         const SegRec* rec = L.rec;
         int32_t* lists = ws.get<int32_t>("lists" + tag, std::max<int64_t>(L.total, 1));
@@ -869,11 +878,11 @@ struct Planner {
             if (replay && P.cap_r > 0)
                 hipLaunchKernelGGL(replay, dim3((unsigned)((n_waves + cull_replay_waves() - 1) / cull_replay_waves())),
                                    dim3(cull_replay_waves() * kWave), 0, st, P.d_split,
-                                   P.d_nsplit, (int)R.n_super, R.n_patch, n_freq, n_split, P.off, P.bat, P.heads,
+                                   P.d_nsplit, (int)R.n_super, R.n_patch, n_freq, L.src_cnt, P.off, P.bat, P.heads,
                                    lists);
             if (!replay || words[2] > P.cap_r)
                 hipLaunchKernelGGL(cull_fill, cg, dim3(kWave), 0, st, L.jobs, rec, R.patches, R.supers, R.n_patch,
-                                   n_freq, n_split, P.d_split, P.d_nsplit, P.hmask, R.n_hyper, P.cps, nullptr, P.off,
+                                   n_freq, L.src_cnt, P.d_split, P.d_nsplit, P.hmask, R.n_hyper, P.cps, nullptr, P.off,
                                    lists, P.bat, nullptr, P.cap_r, P.heads);
         }
         GBS_HIP(hipGetLastError());
@@ -883,7 +892,7 @@ struct Planner {
         const int chunk = work_chunk();
         int32_t* lens = ws.get<int32_t>("lens", n_items);
         hipLaunchKernelGGL(k_item_lengths, dim3(blocks_for(n_items, 256)), dim3(256), 0, st, off, (int32_t)n_items,
-                           n_split, lens);
+                           R.n_patch, n_freq, L.src_cnt, lens);
         int32_t* ids = ws.get<int32_t>("oids", n_items);
         int32_t* order = ids;
         hipLaunchKernelGGL(k_iota, dim3(blocks_for(n_items, 256)), dim3(256), 0, st, ids, (int32_t)n_items);
@@ -912,7 +921,8 @@ struct Planner {
         int32_t* iwb = ws.get<int32_t>("item_wbase" + tag, n_items);
         int32_t* iwc = ws.get<int32_t>("item_wcount" + tag, n_items);
         int32_t* n_work = ws.get<int32_t>("n_work" + tag, 1);
-        hipLaunchKernelGGL(k_make_work, dim3(blocks_for(n_items, 256)), dim3(256), 0, st, order, off, n_split, wb,
+        hipLaunchKernelGGL(k_make_work, dim3(blocks_for(n_items, 256)), dim3(256), 0, st, order, off, R.n_patch,
+                           n_freq, L.src_cnt, wb,
                            (int32_t)n_items, chunk, work, iwb, iwc, n_work);
         GBS_HIP(hipGetLastError());
         L.work = work;

@@ -378,15 +378,18 @@ __global__ void k_job_consts(const double* __restrict__ freqs, const double* __r
 // src_off[s+1]) inside the pass cut into pieces of `span` segments, in source
 // order (one thread; at most n_src + n_segs / span pieces).
 __global__ void k_make_splits(const int64_t* __restrict__ src_off, int32_t n_src, int64_t pass_begin,
-                              int64_t pass_end, int64_t span, int32_t max_splits, CullSplit* __restrict__ splits,
-                              int32_t* __restrict__ n_splits) {
+                              int64_t pass_end, int64_t span, int32_t max_splits, int64_t cells,
+                              CullSplit* __restrict__ splits, int32_t* __restrict__ n_splits,
+                              int64_t* __restrict__ src_cnt) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     int32_t n = 0;
     for (int32_t s = 0; s < n_src; ++s) {
         const int64_t b = max(src_off[s], pass_begin) - pass_begin, e = min(src_off[s + 1], pass_end) - pass_begin;
         int32_t k = 0;
+        src_cnt[2 * s] = (int64_t)n * cells;
         for (int64_t x = b; x < e && n < max_splits; x += span, ++k)
             splits[n++] = CullSplit{x, min(x + span, e), s, k};
+        src_cnt[2 * s + 1] = k;
     }
     *n_splits = n;
 }
@@ -757,7 +760,7 @@ __global__ __launch_bounds__(kBatchRegions) void k_cull_need(const unsigned* __r
 template <bool FILL, int NB>
 __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ jobs, const SegRec* __restrict__ rec,
                                                 const Patch* __restrict__ patches, const Patch* __restrict__ supers,
-                                                int n_patch, int n_freq, int n_split,
+                                                int n_patch, int n_freq, const int64_t* __restrict__ src_cnt,
                                                 const CullSplit* __restrict__ splits,
                                                 const int32_t* __restrict__ n_splits,
                                                 const unsigned long long* __restrict__ hmask, int n_hyper,
@@ -777,6 +780,7 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
     const CullSplit sl = splits[blockIdx.y];
     const int lane = threadIdx.x;
     const int64_t job0 = (int64_t)sl.src * n_freq;
+    const int64_t cnt0 = src_cnt[2 * sl.src], n_piece = src_cnt[2 * sl.src + 1];
     Bands<NB> B;
     B.load(jobs, job0, n_freq, lane);
     const Patch SPt = supers[sp];
@@ -784,7 +788,8 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
     for (int pm = 0; pm < kSuperPatches; ++pm) {
         const int p = p0 + pm;
         if (lane < n_freq)
-            cur_s[pm * kNB + lane] = (FILL && p < n_patch) ? off[((job0 + lane) * n_patch + p) * n_split + sl.idx] : 0;
+            cur_s[pm * kNB + lane] =
+                (FILL && p < n_patch) ? off[cnt0 + ((int64_t)lane * n_patch + p) * n_piece + sl.idx] : 0;
     }
     wave_lds_fence();
     const int64_t wave_id = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
@@ -943,7 +948,7 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
         for (int pm = 0; pm < kSuperPatches; ++pm) {
             const int p = p0 + pm;
             if (p < n_patch && lane < n_freq)
-                counts[((job0 + lane) * n_patch + p) * n_split + sl.idx] = (int32_t)cur_s[pm * kNB + lane];
+                counts[cnt0 + ((int64_t)lane * n_patch + p) * n_piece + sl.idx] = (int32_t)cur_s[pm * kNB + lane];
         }
         if constexpr (NB > 0) {
             if (lane == 0) {
@@ -968,7 +973,7 @@ int cull_replay_waves() { return kReplayWaves; }
 template <int NB>
 __global__ __launch_bounds__(kReplayWaves * kWave) void k_cull_replay(const CullSplit* __restrict__ splits,
                                                      const int32_t* __restrict__ n_splits, int n_super,
-                                                     int n_patch, int n_freq, int n_split,
+                                                     int n_patch, int n_freq, const int64_t* __restrict__ src_cnt,
                                                      const int64_t* __restrict__ off,
                                                      const unsigned char* __restrict__ bat,
                                                      const int32_t* __restrict__ heads, int32_t* __restrict__ lists) {
@@ -983,14 +988,14 @@ __global__ __launch_bounds__(kReplayWaves * kWave) void k_cull_replay(const Cull
     if (h < 0) return;                                    // empty, or recomputed by k_cull
     const int n = heads[2 * wave_id + 1];
     const CullSplit sl = splits[piece];
-    const int64_t job0 = (int64_t)sl.src * n_freq;
+    const int64_t cnt0 = src_cnt[2 * sl.src], n_piece = src_cnt[2 * sl.src + 1];
     const int p0 = (int)(wave_id - piece * n_super) * kSuperPatches;
     int64_t cr[kRegs];
 #pragma unroll
     for (int k = 0; k < kRegs; ++k) {
         const int c = k * kWave + lane, pm = c / NB, b = c % NB;
         cr[k] = c < kCells && p0 + pm < n_patch && b < n_freq
-                    ? off[((job0 + b) * n_patch + p0 + pm) * n_split + sl.idx] : 0;
+                    ? off[cnt0 + ((int64_t)b * n_patch + p0 + pm) * n_piece + sl.idx] : 0;
     }
     auto load = [&](int64_t r, int32_t& seg, unsigned long long* m) {
         const unsigned char* rp = bat + r * kStride;
@@ -1036,12 +1041,23 @@ __global__ __launch_bounds__(kReplayWaves * kWave) void k_cull_replay(const Cull
     }
 }
 
-// Length of every item's list: the span of its splits in the prefix sum.
-__global__ void k_item_lengths(const int64_t* __restrict__ off, int32_t n_items, int n_split,
-                               int32_t* __restrict__ len) {
+// The counters of item i = (source s, band b) * n_patch + patch p: the
+// pieces of source s, at src_cnt[2 s] + (b n_patch + p) src_cnt[2 s + 1].
+__device__ __forceinline__ int64_t item_cnt(int64_t i, int n_patch, int n_freq, const int64_t* __restrict__ src_cnt,
+                                            int64_t& n_piece) {
+    const int64_t job = i / n_patch, p = i - job * n_patch, s = job / n_freq, b = job - s * n_freq;
+    n_piece = src_cnt[2 * s + 1];
+    return src_cnt[2 * s] + (b * n_patch + p) * n_piece;
+}
+
+// Length of every item's list: the span of its pieces in the prefix sum.
+__global__ void k_item_lengths(const int64_t* __restrict__ off, int32_t n_items, int n_patch, int n_freq,
+                               const int64_t* __restrict__ src_cnt, int32_t* __restrict__ len) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_items) return;
-    len[i] = (int32_t)(off[(int64_t)(i + 1) * n_split] - off[(int64_t)i * n_split]);
+    int64_t n_piece;
+    const int64_t c = item_cnt(i, n_patch, n_freq, src_cnt, n_piece);
+    len[i] = (int32_t)(off[c + n_piece] - off[c]);
 }
 
 // ids[i] = i: the payload of the longest-first item sort.
@@ -1623,14 +1639,17 @@ __global__ void k_work_counts(const int32_t* __restrict__ order, const int32_t* 
 }
 
 // Lays out the work units of every item from the exclusive scan of the counts.
-__global__ void k_make_work(const int32_t* __restrict__ order, const int64_t* __restrict__ off, int32_t off_stride,
+__global__ void k_make_work(const int32_t* __restrict__ order, const int64_t* __restrict__ off, int n_patch,
+                            int n_freq, const int64_t* __restrict__ src_cnt,
                             const int32_t* __restrict__ wbase, int32_t n_items, int32_t chunk,
                             Work* __restrict__ work, int32_t* __restrict__ item_wbase,
                             int32_t* __restrict__ item_wcount, int32_t* __restrict__ n_work) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_items) return;
     const int item = order[k];
-    const int64_t beg = off[(int64_t)item * off_stride], end = off[(int64_t)(item + 1) * off_stride];
+    int64_t n_piece;
+    const int64_t c = item_cnt(item, n_patch, n_freq, src_cnt, n_piece);
+    const int64_t beg = off[c], end = off[c + n_piece];
     const int32_t b = wbase[k], cnt = wbase[k + 1] - b;
     for (int c = 0; c < cnt; ++c) {
         Work u;
@@ -2258,7 +2277,8 @@ __global__ void k_dgamma(const double* __restrict__ Zf, int32_t n_faces, double*
 
 // Explicit instantiations used by the host planner.
 #define GBS_INST_CULL(F, NB)                                                                                   \
-    template __global__ void k_cull<F, NB>(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, int, \
+    template __global__ void k_cull<F, NB>(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int,      \
+                                           const int64_t*,                                                         \
                                            const CullSplit*, const int32_t*, const unsigned long long*, int, int,    \
                                            int32_t*, const int64_t*, int32_t*, unsigned char*, unsigned*, int64_t,   \
                                            int32_t*);
@@ -2272,7 +2292,7 @@ GBS_INST_CULL_NB(4)
 GBS_INST_CULL_NB(8)
 GBS_INST_CULL_NB(0)
 #define GBS_INST_REPLAY(NB)                                                                                    \
-    template __global__ void k_cull_replay<NB>(const CullSplit*, const int32_t*, int, int, int, int,           \
+    template __global__ void k_cull_replay<NB>(const CullSplit*, const int32_t*, int, int, int, const int64_t*, \
                                                const int64_t*, const unsigned char*, const int32_t*, int32_t*);
 GBS_INST_REPLAY(1)
 GBS_INST_REPLAY(4)
