@@ -36,7 +36,7 @@
  * Device scratch is held by the context and grows to what its calls need; it
  * includes the cull's batch records (up to 8 bands), sized from the largest
  * need seen and capped by the environment variable GBS_CULL_RECORD_BYTES
- * (bytes, read at each call; default 2 GiB, 0 turns the records off).  The
+ * (bytes, read at each call; default 8 GiB, 0 turns the records off).  The
  * cap changes speed only: waves whose records do not fit are recomputed and
  * the results are the same bit for bit.
  *

@@ -674,12 +674,12 @@ struct Planner {
     // Records per region of the cull's batch records (up to 8 bands): 1/8
     // above the most a region of this context has needed, 64 MiB in all
     // before any pass has run, at most GBS_CULL_RECORD_BYTES in all (default
-    // 2 GiB; 0 turns the records off); none for the allocation-free forward.
+    // 8 GiB; 0 turns the records off); none for the allocation-free forward.
     // The waves that do not fit are recomputed by the fill pass.
     int64_t cull_region_cap(int nb) const {
         if (ws.arena || nb == 0) return 0;
         const size_t stride = cull_batch_bytes(nb), regions = (size_t)cull_batch_regions();
-        size_t limit = size_t(2) << 30;
+        size_t limit = size_t(8) << 30;
         if (const char* e = std::getenv("GBS_CULL_RECORD_BYTES")) limit = (size_t)std::strtoull(e, nullptr, 10);
         const int64_t need = ctx->cull_region_need;
         const size_t want = need > 0 ? (size_t)(need + need / 8 + 2 * cull_batch_block()) * stride * regions
