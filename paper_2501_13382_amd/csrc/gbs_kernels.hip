@@ -1790,23 +1790,34 @@ __device__ __forceinline__ bool adj_eval(const TileRec& S, const JobConst& J, do
     } else {
         const float ph = (float)__builtin_amdgcn_fract(cyc);
         const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
-        const float sf = (float)s, epsf = (float)J.eps;
+        const float sf = (float)s, epsf = (float)J.eps, kf = (float)J.k;
         const float gg = (float)(a * J.gexp2);
         const float w = r0f * __builtin_amdgcn_exp2f(ABS ? fmaf(sf, (float)J.aexp2, gg) : gg);
-        AdjTerms<float> A;
-        adj_factors<float, ABS>(sf, (float)n2, r0f, epsf, (float)J.k, (float)J.aexp, A);
+        // adj_factors with its shared products: with t1 = Im(1/q) + (k/2) n^2 Re(1/q^2),
+        // Im(d ln u/dR . t) = k - t1 and Re(d ln u/deps) = 1/eps - t1; Re(d ln u/dR . t)
+        // = -Im(d ln u/deps) (+ the absorption term); the n coefficient is i k (1/q)
+        const float r2d = r0f * r0f;
+        const float iq_r = sf * r0f, iq_i = epsf * r0f;                          // 1/q
+        const float iq2_r = fmaf(sf, sf, -(float)J.eps2) * r2d;                   // Re 1/q^2
+        const float iq2_i = (2.0f * epsf) * sf * r2d;                             // Im 1/q^2
+        const float hk = (0.5f * kf) * (float)n2;
+        const float t1 = fmaf(hk, iq2_r, iq_i);
+        const float dei = fmaf(-hk, iq2_i, iq_r);
+        const float cti = kf - t1, der = 1.0f / epsf - t1;
+        const float ctr = ABS ? (float)J.aexp - dei : -dei;
         const float br = sf * w, bi = epsf * w;
-        A.Br = br * cs - bi * sn;
-        A.Bi = br * sn + bi * cs;
+        const float Br = br * cs - bi * sn, Bi = br * sn + bi * cs;
+        // lambda B (the coefficient sums), then lambda w Gamma B
+        const float lbr = lr * Br - li * Bi, lbi = lr * Bi + li * Br;
+        Sr += lbr;
+        Si += lbi;
         const float4 Wg = tile_weights(S);                       // (w Gamma, eps w Gamma) as FP32
-        const float ur = Wg.x * A.Br - Wg.y * A.Bi, ui = Wg.x * A.Bi + Wg.y * A.Br;
-        const float vr = lr * ur - li * ui, vi = lr * ui + li * ur;
-        const float gtf = vr * A.ctr - vi * A.cti, gnf = vr * A.cnr - vi * A.cni;
+        const float vr = Wg.x * lbr - Wg.y * lbi, vi = Wg.x * lbi + Wg.y * lbr;
+        const float gtf = vr * ctr - vi * cti;
+        const float gnf = -kf * fmaf(vr, iq_i, vi * iq_r);       // vr Re(ik/q) - vi Im(ik/q)
         const double c = (double)fmaf(-gnf, sf, gtf);            // gt - gn s
         gn = (double)gnf;
-        acc.e += (double)(vr * A.der - vi * A.dei);
-        Sr += lr * A.Br - li * A.Bi;
-        Si += lr * A.Bi + li * A.Br;
+        acc.e += (double)(vr * der - vi * dei);
         acc.vx = fma(c, S.tx, acc.vx);
         acc.vy = fma(c, S.ty, acc.vy);
         acc.vz = fma(c, S.tz, acc.vz);
