@@ -1087,7 +1087,7 @@ struct TileRec {
     double slo, shi;     // beam interval in arc length
     double oo, pad;      // |o|^2; isotropic MIX: arg(w Gamma) in cycles
     double wgr, wgi;     // F64: w Gamma.  F32 and anisotropic MIX: float4 (w Gamma, eps w Gamma) as
-                         // (Re, Im, Re, Im).  Isotropic MIX: log2 |w Gamma| as FP32 in wgr, f/c in wgi
+                         // (Re, Im, Re, Im).  Isotropic MIX: |w Gamma| as FP32 in wgr, f/c in wgi
 };
 static_assert(sizeof(TileRec) == 112, "TileRec layout");
 
@@ -1143,8 +1143,7 @@ struct Beam<kF64> {
 // correction (f/2c) s a alone reaches G s / (2 pi eps) cycles at the gate's
 // edge, hundreds for narrow beams); the Gaussian, sine and cosine, and the
 // amplitude in FP32, with the weight as its modulus times (s + i eps) and its
-// argument carried by the phase; log2 of the modulus joins the Gaussian's
-// base-2 exponent (one FMA), so the modulus costs no multiply.
+// argument carried by the phase.
 template <>
 struct Beam<kMIX> {
     using T = float;
@@ -1167,10 +1166,9 @@ struct Beam<kMIX> {
         const float sn = __builtin_amdgcn_sinf(ph);                          // sin(2 pi ph)
         const float cs = __builtin_amdgcn_cosf(ph);
         const float sf = (float)s;
-        const float lwg = *reinterpret_cast<const float*>(&S.wgr);          // log2 |w Gamma|
-        const float gg = fmaf((float)a, (float)J.gexp2, lwg);                // Gaussian exponent, base 2
+        const float gg = (float)a * (float)J.gexp2;                          // Gaussian exponent, base 2
         const float g2 = live ? (ABS ? fmaf(sf, (float)J.aexp2, gg) : gg) : -INFINITY;
-        const float w = r0f * __builtin_amdgcn_exp2f(g2);
+        const float w = r0f * __builtin_amdgcn_exp2f(g2) * *reinterpret_cast<const float*>(&S.wgr);
         const float cr = sf * w, ci = (float)J.eps * w;                      // |w Gamma| (s + i eps) / den e^g
         ur = fmaf(cr, cs, fmaf(-ci, sn, ur));
         ui = fmaf(cr, sn, fmaf(ci, cs, ui));
@@ -1456,7 +1454,7 @@ __device__ __forceinline__ int pair_two(const TileOf<MODE>& S0, const TileOf<MOD
 // Builds a lane's tile record from its segment record (seven 16-byte vectors
 // in SegRec field order) for job J and stores it to the wave's LDS tile.
 // POLAR (the isotropic MIX pair kernel): the weight in polar form, its phase
-// in cycles in the spare slot and log2 of its modulus as FP32 in place of the complex
+// in cycles in the spare slot and its modulus as FP32 in place of the complex
 // weight, followed by the job's f/c (so the phase's FMAs read both of their
 // job constants from different register files).
 template <int MODE, bool POLAR = false>
@@ -1471,7 +1469,7 @@ __device__ __forceinline__ void stage_rec(TileRec* dst, double2 r0, double2 r1, 
     q[5] = make_double2(r1.y, POLAR ? r6.x : 0.0);
     if (POLAR) {
         union { float2 f; double d; } m;
-        m.f = make_float2(log2f((float)hypot(r5.x, r5.y)), 0.f);
+        m.f = make_float2((float)hypot(r5.x, r5.y), 0.f);
         q[6] = make_double2(m.d, J.fk);
     } else if (MODE == kF64) {
         q[6] = r5;
