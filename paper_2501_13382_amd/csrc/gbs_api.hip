@@ -463,16 +463,22 @@ struct Planner {
             const int32_t* rs = a.rays->ray_src;
             const int64_t* fp = a.segs->face_ptr;
             GBS_CHECK(rp[0] == 0 && rp[n_rays] == n_segs, "ray_ptr must span the segments");
+            // the checks as branch-free reductions over the arrays (they vectorise), then the offsets
+            bool src_ok = true, sorted = true, rp_ok = true, fp_ok = true;
+            for (int64_t i = 0; i < n_rays; ++i) src_ok &= rs[i] >= 0 && rs[i] < n_src;
+            for (int64_t i = 1; i < n_rays; ++i) sorted &= rs[i] >= rs[i - 1];
+            for (int64_t i = 0; i < n_rays; ++i) rp_ok &= rp[i + 1] >= rp[i];
+            GBS_CHECK(src_ok, "ray_src out of range");
+            GBS_CHECK(sorted, "rays must be sorted by source");
+            GBS_CHECK(rp_ok, "ray_ptr must be non-decreasing");
             for (int64_t i = 0; i <= n_rays; ++i) {
-                int32_t prev = i == 0 ? -1 : rs[i - 1];
-                int32_t cur = i == n_rays ? n_src : rs[i];
-                GBS_CHECK(i == n_rays || (cur >= 0 && cur < n_src), "ray_src out of range");
-                GBS_CHECK(cur >= prev, "rays must be sorted by source");
-                if (i < n_rays) GBS_CHECK(rp[i + 1] >= rp[i], "ray_ptr must be non-decreasing");
+                const int32_t prev = i == 0 ? -1 : rs[i - 1];
+                const int32_t cur = i == n_rays ? n_src : rs[i];
                 for (int32_t s = prev + 1; s <= cur; ++s) src_off[s] = rp[i];
             }
             GBS_CHECK(fp[0] == 0, "face_ptr[0] must be 0");
-            for (int64_t j = 0; j < n_segs; ++j) GBS_CHECK(fp[j + 1] >= fp[j], "face_ptr must be non-decreasing");
+            for (int64_t j = 0; j < n_segs; ++j) fp_ok &= fp[j + 1] >= fp[j];
+            GBS_CHECK(fp_ok, "face_ptr must be non-decreasing");
             GBS_CHECK(fp[n_segs] == 0 || a.segs->face_ids, "null face_ids");
             GBS_CHECK(fp[n_segs] == 0 || a.faces->n_faces > 0, "face histories need n_faces > 0");
             GBS_HIP(hipMemcpyAsync(d_off, src_off.data(), sizeof(int64_t) * (n_src + 1), hipMemcpyHostToDevice, st));
@@ -1090,10 +1096,12 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
     stats.patch_rcv = 64 * nr;
     if (n_out > 0 && a.segs->n_segs > 0) {
         pl.reset_status();
+        // the receivers' planning first: the device works on it while the
+        // host checks a host table and lays out its passes
+        pl.plan_receivers(64 * nr);
         pl.source_offsets();
         stats.dense_pairs = a.segs->n_segs * a.n_rcv * a.n_freq;   // every segment belongs to one source
         pl.make_passes();
-        pl.plan_receivers(64 * nr);
         unsigned* ctr = ws.get<unsigned>("ctr", 1);
         const bool count = (a.params->flags & GBS_FLAG_COUNT_ACTIVE) != 0;
         unsigned long long* na = ws.get<unsigned long long>("n_active", 1);
