@@ -72,7 +72,7 @@ __global__ void k_work_counts(const int32_t*, const int32_t*, int32_t, int32_t, 
 __global__ void k_make_work(const int32_t*, const int64_t*, int, int, const int64_t*, const int32_t*, int32_t, int32_t,
                             Work*, int32_t*, int32_t*, int32_t*);
 __global__ void k_reduce_partials(const JobConst*, const int32_t*, const int32_t*, int32_t, int32_t, int,
-                                  const int32_t*, int64_t, const double*, double*);
+                                  const int32_t*, int64_t, const double*, double*, double*, int);
 __global__ void k_tl(const double*, int64_t, double*);
 template <int MODE>
 __global__ void k_adjoint(const JobConst*, const Work*, const int32_t*, int32_t, unsigned*, const int32_t*,
@@ -1010,7 +1010,7 @@ int64_t persistent_grid(gbs_ctx* ctx, const void* kern, int64_t n_items) {
 
 template <int MODE, int NR, bool COUNT>
 void launch_pairs(gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const RcvPlan& R, int64_t n_rcv, double* P,
-                  unsigned* ctr, unsigned long long* n_active, EventPair* ev) {
+                  unsigned* ctr, unsigned long long* n_active, EventPair* ev, double* TL, bool write) {
     auto kern = k_pairs<MODE, NR, COUNT>;
     const int64_t grid = persistent_grid(ctx, (const void*)kern, L.work_cap);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, ctr);
@@ -1021,52 +1021,55 @@ void launch_pairs(gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const R
     if (ev) ev->stop(st);
     const int64_t threads = (int64_t)L.n_items * 64 * NR;
     hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(threads, 256)), dim3(256), 0, st, L.jobs, L.item_wbase,
-                       L.item_wcount, L.n_items, R.n_patch, NR, R.perm, n_rcv, L.partial, P);
+                       L.item_wcount, L.n_items, R.n_patch, NR, R.perm, n_rcv, L.partial, P, TL, (int)write);
     GBS_HIP(hipGetLastError());
 }
 
 template <int MODE, bool COUNT>
 void dispatch_nr(int nr, gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const RcvPlan& R, int64_t n_rcv,
-                 double* P, unsigned* ctr, unsigned long long* na, EventPair* ev) {
-    if (nr == 1) launch_pairs<MODE, 1, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na, ev);
-    else if (nr == 2) launch_pairs<MODE, 2, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na, ev);
-    else launch_pairs<MODE, 4, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na, ev);
+                 double* P, unsigned* ctr, unsigned long long* na, EventPair* ev, double* TL, bool write) {
+    if (nr == 1) launch_pairs<MODE, 1, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write);
+    else if (nr == 2) launch_pairs<MODE, 2, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write);
+    else launch_pairs<MODE, 4, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write);
 }
 
 template <int MODE>
 void dispatch_count(bool count, int nr, gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const RcvPlan& R,
-                    int64_t n_rcv, double* P, unsigned* ctr, unsigned long long* na, EventPair* ev) {
-    count ? dispatch_nr<MODE, true>(nr, ctx, st, L, R, n_rcv, P, ctr, na, ev)
-          : dispatch_nr<MODE, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na, ev);
+                    int64_t n_rcv, double* P, unsigned* ctr, unsigned long long* na, EventPair* ev, double* TL,
+                    bool write) {
+    count ? dispatch_nr<MODE, true>(nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write)
+          : dispatch_nr<MODE, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write);
 }
 
 // mode: GBS_MODE_*; absorb: some job has atmospheric absorption (the kernel
 // variant with the absorption exponent; the others skip it); aniso:
 // anisotropic beams (counting counts the exact gate's pairs).
 // ev (optional): HIP events around the pair kernel's launch alone.
+// write: the call's only pass; the reduction writes every output of P (no
+// zero fill before it) and, with TL, the transmission loss.
 void dispatch_pairs(int mode, bool absorb, bool aniso, bool count, int nr, gbs_ctx* ctx, hipStream_t st,
                     const Planner::Lists& L, const RcvPlan& R, int64_t n_rcv, double* P, unsigned* ctr,
-                    unsigned long long* na, EventPair* ev = nullptr) {
+                    unsigned long long* na, EventPair* ev = nullptr, double* TL = nullptr, bool write = false) {
     GBS_CHECK(L.partial != nullptr, "work-unit partials not allocated");
     const int m = (mode == GBS_MODE_F64 ? 0 : mode == GBS_MODE_MIX ? 1 : 2) | (absorb ? 4 : 0);
     if (aniso) {
         switch (m) {
-            case 0: dispatch_count<8>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
-            case 1: dispatch_count<9>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
-            case 2: dispatch_count<10>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
-            case 4: dispatch_count<12>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
-            case 5: dispatch_count<13>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
-            default: dispatch_count<14>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
+            case 0: dispatch_count<8>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
+            case 1: dispatch_count<9>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
+            case 2: dispatch_count<10>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
+            case 4: dispatch_count<12>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
+            case 5: dispatch_count<13>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
+            default: dispatch_count<14>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
         }
         return;
     }
     switch (m) {
-        case 0: dispatch_count<0>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
-        case 1: dispatch_count<1>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
-        case 2: dispatch_count<2>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
-        case 4: dispatch_count<4>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
-        case 5: dispatch_count<5>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
-        default: dispatch_count<6>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev); break;
+        case 0: dispatch_count<0>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
+        case 1: dispatch_count<1>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
+        case 2: dispatch_count<2>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
+        case 4: dispatch_count<4>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
+        case 5: dispatch_count<5>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
+        default: dispatch_count<6>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
     }
 }
 
@@ -1091,7 +1094,13 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
     pl.chunk_override = chunk_override;
     hipStream_t st = ctx->stream;
     const int64_t n_out = (int64_t)pl.n_jobs * a.n_rcv;
-    fill(st, P, 2 * n_out, 0.0);
+    // P is zeroed before a call in several passes accumulates into it; a
+    // call's only pass writes all of it (and TL) in its reduction
+    bool zeroed = false, tl_done = false;
+    auto zero_P = [&]() {
+        if (!zeroed) fill(st, P, 2 * n_out, 0.0);
+        zeroed = true;
+    };
     gbs_stats stats{};
     stats.patch_rcv = 64 * nr;
     if (n_out > 0 && a.segs->n_segs > 0) {
@@ -1116,6 +1125,8 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
         // the copy stream into the staging slot of pass i as soon as pass i's
         // records are built (the pair kernel never reads the staged table).
         const size_t n_pass = pl.passes.size();
+        const bool one_pass = n_pass == 1;
+        if (!one_pass) zero_P();
         const bool overlap = pl.table_host() && n_pass > 1;
         const bool pipe = n_pass > 1 && !timed;
         Planner::PassView views[2];
@@ -1159,12 +1170,17 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
             if (L.n_items > 0 && L.total > 0) {
                 L.partial = ws.get<double>("partial", L.work_cap * nr * 64 * 2);
                 dispatch_pairs(a.params->mode, pl.absorb(), pl.aniso(), count, nr, ctx, st, L, pl.R, a.n_rcv, P, ctr, na,
-                               timed ? &ev_pairs : nullptr);
+                               timed ? &ev_pairs : nullptr, one_pass ? TL : nullptr, one_pass);
+                if (one_pass) {
+                    zeroed = true;
+                    tl_done = TL != nullptr;
+                }
                 stats.ms_pairs += ev_pairs.end(st);
             }
             if (pipe && pi + 2 < n_pass) start(pi + 2);
         }
         stats.n_chunks = (int32_t)pl.passes.size();
+        zero_P();                         // a call with nothing to reduce
         if (count) {
             unsigned long long h = 0;
             GBS_HIP(hipMemcpyAsync(&h, na, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -1172,9 +1188,10 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
             stats.active_pairs = (int64_t)h;
         }
     } else {
+        zero_P();
         pl.check_jobs_on_host();
     }
-    if (TL && n_out > 0) {
+    if (TL && n_out > 0 && !tl_done) {
         hipLaunchKernelGGL(k_tl, dim3(blocks_for(n_out, 256)), dim3(256), 0, st, P, n_out, TL);
         GBS_HIP(hipGetLastError());
     }

@@ -1669,13 +1669,13 @@ __global__ void k_make_work(const int32_t* __restrict__ order, const int64_t* __
 __global__ void k_reduce_partials(const JobConst* __restrict__ jobs, const int32_t* __restrict__ item_wbase,
                                   const int32_t* __restrict__ item_wcount, int32_t n_items, int32_t n_patch, int nr,
                                   const int32_t* __restrict__ perm, int64_t n_rcv, const double* __restrict__ partial,
-                                  double* __restrict__ P) {
+                                  double* __restrict__ P, double* __restrict__ TL, int write) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int per = kWave * nr;
     if (t >= (int64_t)n_items * per) return;
     const int item = (int)(t / per), slot = (int)(t - (int64_t)item * per);
     const int cnt = item_wcount[item];
-    if (cnt == 0) return;
+    if (cnt == 0 && !write) return;
     const int job = item / n_patch, patch = item - job * n_patch;
     const int m = slot / kWave, lane = slot - m * kWave;
     const int32_t o = perm[(int64_t)patch * per + slot];
@@ -1687,10 +1687,23 @@ __global__ void k_reduce_partials(const JobConst* __restrict__ jobs, const int32
         sr += p[0];
         si += p[1];
     }
-    double* q = P + 2 * ((int64_t)job * n_rcv + o);
+    const int64_t out = (int64_t)job * n_rcv + o;
+    double* q = P + 2 * out;
     const double sc = jobs[job].scale;
-    q[0] += sc * sr;
-    q[1] += sc * si;
+    if (write) {
+        // a call's only pass: every (job, receiver) output is written here,
+        // with its TL
+        const double pr = sc * sr, pi = sc * si;
+        q[0] = pr;
+        q[1] = pi;
+        if (TL) {
+            const double mag = hypot(pr, pi);
+            TL[out] = mag > 0.0 ? -20.0 * log10(mag) : INFINITY;
+        }
+    } else {
+        q[0] += sc * sr;
+        q[1] += sc * si;
+    }
 }
 
 // TL = -20 log10 |P|  (+inf where P = 0).
