@@ -22,6 +22,7 @@
 // kernels (gbs_kernels.hip)
 namespace gbs {
 __global__ void k_fill_f64(double*, int64_t, double);
+__global__ void k_fill_i32(int32_t*, int64_t, int32_t);
 __global__ void k_reset_counter(unsigned*);
 __global__ void k_bbox_partial(const double*, int64_t, double*);
 __global__ void k_bbox_final(const double*, int, double*);
@@ -816,6 +817,10 @@ struct Planner {
         unsigned* bat_ctr = ws.get<unsigned>("cull_batch_ctr%" + std::to_string(P.slot), n_ctr + 2);
         P.heads = ws.get<int32_t>("cull_heads%" + std::to_string(P.slot), (size_t)2 * cg.x * cg.y);
         fill(st, (double*)bat_ctr, (n_ctr + 2) / 2, 0.0);
+        // every chain starts empty (-1): the cull waves that level 0 leaves
+        // without a segment end before they write theirs
+        hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>(4096, blocks_for(2 * (int64_t)cg.x * cg.y, 256))),
+                           dim3(256), 0, st, P.heads, 2 * (int64_t)cg.x * cg.y, (int32_t)-1);
         // up to 8 bands: band constants in wave-uniform registers, as many as needed
         auto cull_count = n_freq == 1 ? k_cull<false, 1> : n_freq <= 4 ? k_cull<false, 4>
                         : n_freq <= 8 ? k_cull<false, 8> : k_cull<false, 0>;

@@ -98,6 +98,15 @@ __device__ __forceinline__ void wave_lds_fence() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// An empty asm that takes v and hands it back in the same registers: the
+// compiler waits for v's load before it, and afterwards v is no longer a load
+// in flight, so a loop that reads it has no wait of its own (a value loaded
+// before a loop is otherwise waited for at each store in it, and on gfx9 the
+// wait covers the earlier stores as well).  The memory clobber keeps the
+// stores issued before it in front of it.
+template <typename T>
+__device__ __forceinline__ void settle(T& v) { asm volatile("" : "+v"(v) : : "memory"); }
+
 __device__ __forceinline__ int lanes_before(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
@@ -126,6 +135,11 @@ __device__ __forceinline__ double fixed_scale_for(double bound) {
 }
 
 __global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
@@ -776,6 +790,21 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
     __shared__ unsigned long long q_mask[kWave];
     __shared__ int64_t cur_s[kSuperPatches * kNB];        // cursor of (patch pm, band b) at pm * kNB + b
     const int sp = blockIdx.x;
+    // level-0 bits of 64-segment chunk ci for the super-patch's hyper-patch
+    const unsigned long long* hm = hmask + (int64_t)blockIdx.y * chunks_per_split * n_hyper * 4 +
+                                   (int64_t)(sp / kHyperSupers) * 4;
+    {
+        // most waves have no segment that may reach their hyper-patch: they
+        // end here, their counts zero and their chain empty from the pass's
+        // set-up (every word of a piece's level 0 is written, zero past its
+        // end; those of pieces past the last hold old bits, and those waves
+        // end at the piece check)
+        const int n_words = chunks_per_split * 4;
+        bool any = false;
+        for (int cl = threadIdx.x; cl < n_words; cl += kWave)
+            any |= hm[(int64_t)(cl >> 2) * n_hyper * 4 + (cl & 3)] != 0ull;
+        if (__ballot(any) == 0ull) return;
+    }
     if ((int)blockIdx.y >= *n_splits) return;             // the grid covers the most pieces a pass can have
     const CullSplit sl = splits[blockIdx.y];
     const int lane = threadIdx.x;
@@ -910,9 +939,6 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
             qn -= kWave;
         }
     };
-    // level-0 bits of 64-segment chunk ci for the super-patch's hyper-patch
-    const unsigned long long* hm = hmask + (int64_t)blockIdx.y * chunks_per_split * n_hyper * 4 +
-                                   (int64_t)(sp / kHyperSupers) * 4;
     const int n_chunks = (int)((sl.end - sl.begin + kWave - 1) / kWave);
     int q1n = 0;                                          // level-1 queue length
     // 64 chunks' level-0 words at a time, one per lane; only chunks with a
@@ -1004,11 +1030,16 @@ __global__ __launch_bounds__(kReplayWaves * kWave) void k_cull_replay(const Cull
 #pragma unroll
         for (int k = 0; k < kRegs; ++k) m[k] = k * kWave + lane < kCells ? mk[k * kWave + lane] : 0ull;
     };
+    // one wait per record: the next record's loads are issued before the
+    // current one is written, and settled after its stores
     int64_t r = h;
     int32_t nxt = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(bat + r * kStride));
     int32_t seg;
     unsigned long long m[kRegs];
     load(r, seg, m);
+    settle(seg);
+#pragma unroll
+    for (int k = 0; k < kRegs; ++k) settle(m[k]);
     for (int i = 0; i < n; ++i) {
         // the next record: the following one in the block, or the next block's first
         int32_t seg_n = 0;
@@ -1031,9 +1062,12 @@ __global__ __launch_bounds__(kReplayWaves * kWave) void k_cull_replay(const Cull
                 live &= live - 1ull;
                 const unsigned long long bl = (unsigned long long)lane_i64((int64_t)m[k], c);
                 if ((bl >> lane) & 1ull) lists[lane_i64(cr[k], c) + lanes_before(bl)] = seg;
-                cr[k] += lane == c ? (int64_t)__popcll(bl) : 0;
             }
+            cr[k] += __popcll(m[k]);                      // lane c: cell c's ballot
         }
+        settle(seg_n);
+#pragma unroll
+        for (int k = 0; k < kRegs; ++k) settle(m_n[k]);
         r = rn;
         seg = seg_n;
 #pragma unroll

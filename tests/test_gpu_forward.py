@@ -242,6 +242,34 @@ def test_source_without_rays_and_far_receivers():
     assert_within(compare(P, TL, P_ref, TL_ref, ab), "mix")
 
 
+@pytest.mark.parametrize("entry,chunk", [("gbs_forward", 0), ("gbs_forward", 300), ("gbs_forward_noalloc", 0)])
+def test_outputs_overwritten_whatever_they_held(entry, chunk):
+    """P and TL are outputs only: buffers that hold NaN before the call come
+    back with the sums of a call into fresh buffers, bit for bit, in one pass
+    (the reduction writes every output itself), in several passes (P is
+    cleared, then accumulated) and without allocation; receivers no beam
+    reaches get P = 0 and TL = +inf."""
+    from paper_2501_13382_amd import gbs as G
+    sc = open_plane(n_rays=600, grid=4, half=60.0, freqs=(250.0, 1000.0))
+    far = np.vstack([sc.rcv, [[1e5, 1e5, 3.0]]])
+    t = gbs.Table(sc.table, device="cuda")
+    P0, TL0 = gbs.forward(t, far, sc.freqs, sc.eps, sc.gamma, c=sc.c, gate=sc.gate, mode="mix",
+                          chunk_segs=chunk)
+    shape = (1, len(sc.freqs), len(far))
+    P = torch.full(shape + (2,), float("nan"), dtype=torch.float64, device="cuda")
+    TL = torch.full(shape, float("nan"), dtype=torch.float64, device="cuda")
+    print(f"case {entry} chunk_segs={chunk}", flush=True)
+    Pc, TLc = G._forward(entry, t, far, sc.freqs, sc.eps, sc.gamma, sc.c, sc.gate, "mix", chunk, 0, 0, False,
+                         False, True, None, None, (P, TL))
+    torch.cuda.synchronize()
+    if chunk:
+        assert gbs.stats()["n_chunks"] > 1
+    assert torch.equal(torch.view_as_real(Pc), torch.view_as_real(P0))
+    assert torch.equal(TLc, TL0)
+    assert torch.all(Pc[..., -1] == 0) and torch.all(torch.isinf(TLc[..., -1]))
+    assert not torch.isnan(TLc).any()
+
+
 def test_invalid_arguments_rejected():
     sc = open_plane(n_rays=200, grid=4, half=50.0, freqs=(500.0,))
     t = gbs.Table(sc.table, device="cuda")
