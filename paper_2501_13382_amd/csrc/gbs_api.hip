@@ -48,13 +48,12 @@ __global__ void k_cull(const JobConst*, const SegRec*, const Patch*, const Patch
                        unsigned char*, unsigned*, int64_t, int32_t*);
 __global__ void k_cull_need(const unsigned*, unsigned*);
 template <int NB>
-__global__ void k_cull_replay(const CullSplit*, const int32_t*, int, int, int, const int64_t*, const int64_t*,
-                              const unsigned char*, const int32_t*, int32_t*);
+__global__ void k_cull_replay(const CullSplit*, int, int, int, const int64_t*, const int64_t*, const unsigned char*,
+                              const unsigned*, int64_t, const int32_t*, int32_t*);
 size_t cull_batch_bytes(int nb);
 int cull_batch_regions();
 int cull_batch_ctr_stride();
 int cull_batch_block();
-int cull_replay_waves();
 template <int NB>
 __global__ void k_cull_hyper(const JobConst*, const SegRec*, const Patch*, int, int, int, const CullSplit*,
                              const int32_t*, unsigned long long*);
@@ -674,7 +673,8 @@ struct Planner {
         const unsigned long long* hmask = nullptr;
         int64_t* off = nullptr;
         unsigned char* bat = nullptr;      // the count pass's batch records, replayed by the fill pass
-        int64_t cap_r = 0;                 // records per region
+        int64_t cap_r = 0;                 // records per region (whole blocks)
+        const unsigned* bat_ctr = nullptr; // records handed out per region
         int32_t* heads = nullptr;
     };
 
@@ -691,9 +691,10 @@ struct Planner {
         const int64_t need = ctx->cull_region_need;
         const size_t want = need > 0 ? (size_t)(need + need / 8 + 2 * cull_batch_block()) * stride * regions
                                      : size_t(64) << 20;
-        // record indices are int32
-        return std::min<int64_t>((int64_t)(std::min(want, limit) / (stride * regions)),
-                                 INT32_MAX / (int64_t)regions - cull_batch_block());
+        // whole blocks; block indices are int32
+        const int64_t cap = std::min<int64_t>((int64_t)(std::min(want, limit) / (stride * regions)),
+                                              INT32_MAX / (int64_t)regions);
+        return cap / cull_batch_block() * cull_batch_block();
     }
 
     // Names of a pass's planning buffers: graph creation keeps every pass's
@@ -815,6 +816,7 @@ struct Planner {
         P.bat = ws.get<unsigned char>("cull_batches%" + std::to_string(P.slot),
                                       P.cap_r > 0 ? (size_t)P.cap_r * cull_batch_regions() * cull_batch_bytes(nb) : 1);
         unsigned* bat_ctr = ws.get<unsigned>("cull_batch_ctr%" + std::to_string(P.slot), n_ctr + 2);
+        P.bat_ctr = bat_ctr;
         P.heads = ws.get<int32_t>("cull_heads%" + std::to_string(P.slot), (size_t)2 * cg.x * cg.y);
         fill(st, (double*)bat_ctr, (n_ctr + 2) / 2, 0.0);
         // every chain starts empty (-1): the cull waves that level 0 leaves
@@ -885,12 +887,12 @@ struct Planner {
             // runs only when a region ran out of records (or none were kept)
             auto replay = n_freq == 1 ? k_cull_replay<1> : n_freq <= 4 ? k_cull_replay<4>
                         : n_freq <= 8 ? k_cull_replay<8> : nullptr;
-            const int64_t n_waves = (int64_t)cg.x * cg.y;
-            if (replay && P.cap_r > 0)
-                hipLaunchKernelGGL(replay, dim3((unsigned)((n_waves + cull_replay_waves() - 1) / cull_replay_waves())),
-                                   dim3(cull_replay_waves() * kWave), 0, st, P.d_split,
-                                   P.d_nsplit, (int)R.n_super, R.n_patch, n_freq, L.src_cnt, P.off, P.bat, P.heads,
-                                   lists);
+            // one wave per block: as many blocks as the fullest region handed out
+            const int64_t n_blk = (std::min<int64_t>(words[2], P.cap_r) + cull_batch_block() - 1) / cull_batch_block();
+            if (replay && P.cap_r > 0 && n_blk > 0)
+                hipLaunchKernelGGL(replay, dim3((unsigned)n_blk, (unsigned)cull_batch_regions()), dim3(kWave), 0, st,
+                                   P.d_split, (int)R.n_super, R.n_patch, n_freq, L.src_cnt, P.off, P.bat, P.bat_ctr,
+                                   P.cap_r, P.heads, lists);
             if (!replay || words[2] > P.cap_r)
                 hipLaunchKernelGGL(cull_fill, cg, dim3(kWave), 0, st, L.jobs, rec, R.patches, R.supers, R.n_patch,
                                    n_freq, L.src_cnt, P.d_split, P.d_nsplit, P.hmask, R.n_hyper, P.cps, nullptr, P.off,

@@ -728,29 +728,37 @@ __global__ __launch_bounds__(kCullThreads) void k_cull_hyper(const JobConst* __r
 // Batch records (up to 8 bands).  The count pass also writes each level-2
 // batch it tests as a record: the batch's 64 segment indices and, per (patch
 // pm, band b), the ballot of the lanes that passed, at cell pm * NB + b.  A
-// wave takes records in blocks of kBatchBlock consecutive ones from one of
-// kBatchRegions counters (chosen by a hash of the wave), each over its own
-// range of cap_r records; the first record of a block holds the index of the
-// wave's next block, and heads[2 wave] / heads[2 wave + 1] hold the first
-// record and the number of batches.  A wave whose block does not fit stops
-// recording and adds what it still tests to its region's counter, so that
-// the counters tell the host what each region needed.  The fill pass replays
-// a complete chain (no geometry, no record gathers: one load per lane per
-// record, the list cursors of the 16 x NB cells in lane c of one or two
-// registers) and recomputes only the waves whose chain did not fit: either
-// way the same decisions land at the same list positions.
-constexpr int kBatchIds = 16;                              // byte offset of the segment indices
-constexpr int kBatchMasks = kBatchIds + 4 * kWave;         // byte offset of the ballots
+// wave takes records in blocks of kBatchBlock from one of kBatchRegions
+// counters (chosen by a hash of the wave), each over its own range of cap_r
+// records (a multiple of kBatchBlock).  A block starts with a header: the
+// wave, the number of its records in use, and the wave's list cursor of
+// every cell, relative to the wave's first entry, as it stood before the
+// block's first batch.  heads[2 wave] is a block of the wave (kChainNone: the
+// wave tested no batch; kChainOverflow: it ran out of blocks) and
+// heads[2 wave + 1] its number of batches.  A wave whose block does not fit
+// stops recording and adds what it still tests to its region's counter, so
+// that the counters tell the host what each region needed.  The fill pass
+// replays every block of a complete wave on its own (no geometry, no record
+// gathers: one load per lane per record, the cursors of the 16 x NB cells in
+// lane c of one or two registers) and recomputes only the waves that ran out
+// of blocks: either way the same decisions land at the same list positions.
 constexpr int kBatchBlock = 4;                             // records a wave takes at a time
 constexpr int kBatchRegions = 256;                         // record counters (power of two)
 constexpr int kBatchCtrStride = 32;                        // counters 128 bytes apart
 constexpr int32_t kChainNone = -1;                         // the wave tested no level-2 batch
 constexpr int32_t kChainOverflow = -2;                     // recompute the wave in the fill pass
 
-// Bytes of one batch record for nb bands (nb = 1, 4 or 8): the index of the
-// next block (int32, padded to 16 bytes), the 64 segment indices (int32),
-// then the ballot (uint64) of cell pm * nb + b.
-size_t cull_batch_bytes(int nb) { return (size_t)kBatchMasks + 8 * (size_t)kSuperPatches * (size_t)nb; }
+// A block for C = 16 nb cells (nb = 1, 4 or 8): the header (the wave and the
+// records in use as int32, 8 bytes of padding, then the C cursors as int32),
+// then kBatchBlock records of 64 segment indices (int32) followed by the
+// ballot (uint64) of cell pm * nb + b.  All offsets are multiples of 16.
+__host__ __device__ constexpr int64_t batch_hdr_bytes(int cells) { return 16 + 4 * (int64_t)cells; }
+__host__ __device__ constexpr int64_t batch_rec_bytes(int cells) { return 4 * kWave + 8 * (int64_t)cells; }
+__host__ __device__ constexpr int64_t batch_block_bytes(int cells) {
+    return batch_hdr_bytes(cells) + kBatchBlock * batch_rec_bytes(cells);
+}
+// Bytes per record, the header shared out over a block's records.
+size_t cull_batch_bytes(int nb) { return (size_t)batch_block_bytes(kSuperPatches * nb) / kBatchBlock; }
 int cull_batch_regions() { return kBatchRegions; }
 int cull_batch_ctr_stride() { return kBatchCtrStride; }
 int cull_batch_block() { return kBatchBlock; }
@@ -823,9 +831,10 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
     wave_lds_fence();
     const int64_t wave_id = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     constexpr int kCells = kSuperPatches * (NB > 0 ? NB : 1);         // cells per record
-    constexpr int64_t kStride = kBatchMasks + 8 * kCells;
+    constexpr int64_t kBlock = batch_block_bytes(kCells), kHdr = batch_hdr_bytes(kCells);
+    constexpr int64_t kRec = batch_rec_bytes(kCells);
     if (FILL && heads[2 * wave_id] != kChainOverflow) return;   // replayed by k_cull_replay, or empty
-    // count pass: this wave's chain (the current block and the records used in it)
+    // count pass: this wave's current block and the records used in it
     const unsigned region = ((unsigned)wave_id * 0x9E3779B1u) >> 24;
     unsigned* my_ctr = bat_ctr + region * kBatchCtrStride;
     int32_t head = kChainNone;
@@ -847,20 +856,23 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
                 if (lane == 0) got = atomicAdd(my_ctr, (unsigned)kBatchBlock);
                 got = __builtin_amdgcn_readfirstlane(got);
                 if ((int64_t)got + kBatchBlock <= cap_r) {
-                    const int64_t nb = (int64_t)region * cap_r + got;
-                    if (blk >= 0) {
-                        if (lane == 0) *reinterpret_cast<int32_t*>(bat + blk * kStride) = (int32_t)nb;
-                    } else {
-                        head = (int32_t)nb;
-                    }
-                    blk = nb;
+                    blk = ((int64_t)region * cap_r + got) / kBatchBlock;
+                    if (head == kChainNone) head = (int32_t)blk;
+                    // the header: this wave and its cursors before the block
+                    wave_lds_fence();
+                    int32_t* hd = reinterpret_cast<int32_t*>(bat + blk * kBlock);
+                    if (lane == 0) hd[0] = (int32_t)wave_id;
+#pragma unroll
+                    for (int k = 0; k < (kCells + kWave - 1) / kWave; ++k)
+                        if (k * kWave + lane < kCells) hd[4 + k * kWave + lane] = (int32_t)cur_s[k * kWave + lane];
                     used = 0;
                 } else {
                     chain_ok = false;
                 }
             }
             if (chain_ok) {
-                slot = blk + used++;
+                slot = used++;
+                if (lane == 0) reinterpret_cast<int32_t*>(bat + blk * kBlock)[1] = used;
             } else {
                 ++n_lost;
             }
@@ -891,9 +903,9 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
         }
         if constexpr (!FILL && NB > 0) {
             if (slot >= 0) {
-                unsigned char* rp = bat + slot * kStride;
-                reinterpret_cast<int32_t*>(rp + kBatchIds)[lane] = valid ? seg : -1;
-                unsigned long long* mk = reinterpret_cast<unsigned long long*>(rp + kBatchMasks);
+                unsigned char* rp = bat + blk * kBlock + kHdr + slot * kRec;
+                reinterpret_cast<int32_t*>(rp)[lane] = valid ? seg : -1;
+                unsigned long long* mk = reinterpret_cast<unsigned long long*>(rp + 4 * kWave);
 #pragma unroll
                 for (int k = 0; k < (kCells + kWave - 1) / kWave; ++k)
                     if (k * kWave + lane < kCells) mk[k * kWave + lane] = mrec[k];
@@ -990,29 +1002,34 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
 }
 
 // The fill pass of the waves whose batch records are complete: one wave per
-// cull wave (super-patch, piece), kReplayWaves per workgroup, no LDS.  The records
-// are replayed in chain order (the next one loaded while the current one is
-// written); the list cursors of the 16 x NB cells start at the prefix sums
-// of the count pass, as in k_cull, and live in lane c & 63 of cr[c >> 6].
-constexpr int kReplayWaves = 1;
-int cull_replay_waves() { return kReplayWaves; }
+// block of records (grid: blocks x regions; a block's position past what its
+// region handed out ends the wave), no LDS.  A block holds its wave, so the
+// wave's pieces of the lists start at the prefix sums of the count pass as
+// in k_cull, plus the block's own cursors; they live in lane c & 63 of
+// cr[c >> 6].  The records are written in order, the next one loaded while
+// the current one is written.
 template <int NB>
-__global__ __launch_bounds__(kReplayWaves * kWave) void k_cull_replay(const CullSplit* __restrict__ splits,
-                                                     const int32_t* __restrict__ n_splits, int n_super,
+__global__ __launch_bounds__(kWave) void k_cull_replay(const CullSplit* __restrict__ splits, int n_super,
                                                      int n_patch, int n_freq, const int64_t* __restrict__ src_cnt,
                                                      const int64_t* __restrict__ off,
                                                      const unsigned char* __restrict__ bat,
+                                                     const unsigned* __restrict__ bat_ctr, int64_t cap_r,
                                                      const int32_t* __restrict__ heads, int32_t* __restrict__ lists) {
     constexpr int kCells = kSuperPatches * NB;
     constexpr int kRegs = (kCells + kWave - 1) / kWave;
-    constexpr int64_t kStride = kBatchMasks + 8 * kCells;
-    const int lane = threadIdx.x & 63;
-    const int64_t wave_id = (int64_t)blockIdx.x * kReplayWaves + (threadIdx.x >> 6);
+    constexpr int64_t kBlock = batch_block_bytes(kCells), kHdr = batch_hdr_bytes(kCells);
+    constexpr int64_t kRec = batch_rec_bytes(kCells);
+    const int lane = threadIdx.x;
+    const int region = blockIdx.y;
+    const int64_t handed = min<int64_t>(bat_ctr[region * kBatchCtrStride], cap_r);
+    if ((int64_t)blockIdx.x * kBatchBlock >= handed) return;
+    const int64_t blk = ((int64_t)region * cap_r) / kBatchBlock + blockIdx.x;
+    const unsigned char* bp = bat + blk * kBlock;
+    const int32_t* hd = reinterpret_cast<const int32_t*>(bp);
+    const int64_t wave_id = __builtin_amdgcn_readfirstlane(hd[0]);
+    const int n = __builtin_amdgcn_readfirstlane(hd[1]);
+    if (heads[2 * wave_id] == kChainOverflow) return;     // recomputed by k_cull
     const int64_t piece = wave_id / n_super;
-    if (piece >= *n_splits) return;
-    const int32_t h = heads[2 * wave_id];
-    if (h < 0) return;                                    // empty, or recomputed by k_cull
-    const int n = heads[2 * wave_id + 1];
     const CullSplit sl = splits[piece];
     const int64_t cnt0 = src_cnt[2 * sl.src], n_piece = src_cnt[2 * sl.src + 1];
     const int p0 = (int)(wave_id - piece * n_super) * kSuperPatches;
@@ -1021,39 +1038,29 @@ __global__ __launch_bounds__(kReplayWaves * kWave) void k_cull_replay(const Cull
     for (int k = 0; k < kRegs; ++k) {
         const int c = k * kWave + lane, pm = c / NB, b = c % NB;
         cr[k] = c < kCells && p0 + pm < n_patch && b < n_freq
-                    ? off[cnt0 + ((int64_t)b * n_patch + p0 + pm) * n_piece + sl.idx] : 0;
+                    ? off[cnt0 + ((int64_t)b * n_patch + p0 + pm) * n_piece + sl.idx] + hd[4 + c] : 0;
     }
-    auto load = [&](int64_t r, int32_t& seg, unsigned long long* m) {
-        const unsigned char* rp = bat + r * kStride;
-        seg = reinterpret_cast<const int32_t*>(rp + kBatchIds)[lane];
-        const unsigned long long* mk = reinterpret_cast<const unsigned long long*>(rp + kBatchMasks);
+    auto load = [&](int j, int32_t& seg, unsigned long long* m) {
+        const unsigned char* rp = bp + kHdr + j * kRec;
+        seg = reinterpret_cast<const int32_t*>(rp)[lane];
+        const unsigned long long* mk = reinterpret_cast<const unsigned long long*>(rp + 4 * kWave);
 #pragma unroll
         for (int k = 0; k < kRegs; ++k) m[k] = k * kWave + lane < kCells ? mk[k * kWave + lane] : 0ull;
     };
     // one wait per record: the next record's loads are issued before the
     // current one is written, and settled after its stores
-    int64_t r = h;
-    int32_t nxt = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(bat + r * kStride));
     int32_t seg;
     unsigned long long m[kRegs];
-    load(r, seg, m);
+    load(0, seg, m);
     settle(seg);
 #pragma unroll
     for (int k = 0; k < kRegs; ++k) settle(m[k]);
     for (int i = 0; i < n; ++i) {
-        // the next record: the following one in the block, or the next block's first
         int32_t seg_n = 0;
         unsigned long long m_n[kRegs];
 #pragma unroll
         for (int k = 0; k < kRegs; ++k) m_n[k] = 0ull;
-        int64_t rn = r + 1;
-        if (i + 1 < n) {
-            if ((i + 1) % kBatchBlock == 0) {
-                rn = nxt;
-                nxt = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(bat + rn * kStride));
-            }
-            load(rn, seg_n, m_n);
-        }
+        if (i + 1 < n) load(i + 1, seg_n, m_n);
 #pragma unroll
         for (int k = 0; k < kRegs; ++k) {
             unsigned long long live = __ballot(m[k] != 0ull);
@@ -1068,7 +1075,6 @@ __global__ __launch_bounds__(kReplayWaves * kWave) void k_cull_replay(const Cull
         settle(seg_n);
 #pragma unroll
         for (int k = 0; k < kRegs; ++k) settle(m_n[k]);
-        r = rn;
         seg = seg_n;
 #pragma unroll
         for (int k = 0; k < kRegs; ++k) m[k] = m_n[k];
@@ -2350,8 +2356,9 @@ GBS_INST_CULL_NB(4)
 GBS_INST_CULL_NB(8)
 GBS_INST_CULL_NB(0)
 #define GBS_INST_REPLAY(NB)                                                                                    \
-    template __global__ void k_cull_replay<NB>(const CullSplit*, const int32_t*, int, int, int, const int64_t*, \
-                                               const int64_t*, const unsigned char*, const int32_t*, int32_t*);
+    template __global__ void k_cull_replay<NB>(const CullSplit*, int, int, int, const int64_t*, const int64_t*, \
+                                               const unsigned char*, const unsigned*, int64_t, const int32_t*,  \
+                                               int32_t*);
 GBS_INST_REPLAY(1)
 GBS_INST_REPLAY(4)
 GBS_INST_REPLAY(8)

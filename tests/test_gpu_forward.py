@@ -163,7 +163,7 @@ def test_cull_records_replayed_or_recomputed_agree(case, city_small, monkeypatch
         sc, nb = city_batched(n_src=4, ray_lo=2000, ray_hi=9000, grid=24), 4
     else:
         sc, nb = open_plane(n_rays=20000, grid=64, freqs=OCTAVES_8, name="plane_8band"), 8
-    one_block_per_region = 4 * 256 * (272 + 128 * nb)
+    one_block_per_region = 4 * 256 * (260 + 144 * nb)
     out = {}
     for label, limit in (("all", None), ("some", one_block_per_region), ("none", 0)):
         if limit is None:
