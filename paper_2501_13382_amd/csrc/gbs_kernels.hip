@@ -797,6 +797,7 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
     __shared__ int32_t q_seg[kWave];                      // band masks
     __shared__ unsigned long long q_mask[kWave];
     __shared__ int64_t cur_s[kSuperPatches * kNB];        // cursor of (patch pm, band b) at pm * kNB + b
+    __shared__ __align__(16) Patch q_patch[kSuperPatches];  // the super-patch's patches
     const int sp = blockIdx.x;
     // level-0 bits of 64-segment chunk ci for the super-patch's hyper-patch
     const unsigned long long* hm = hmask + (int64_t)blockIdx.y * chunks_per_split * n_hyper * 4 +
@@ -822,6 +823,12 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
     B.load(jobs, job0, n_freq, lane);
     const Patch SPt = supers[sp];
     const int p0 = sp * kSuperPatches;
+    // the 16 patches, read by every level-2 batch: from LDS rather than one
+    // scalar load (and wait) per patch and batch
+    if (lane < 2 * kSuperPatches) {
+        const int p = min(p0 + (lane >> 1), n_patch - 1);
+        reinterpret_cast<double2*>(q_patch)[lane] = reinterpret_cast<const double2*>(patches + p)[lane & 1];
+    }
     for (int pm = 0; pm < kSuperPatches; ++pm) {
         const int p = p0 + pm;
         if (lane < n_freq)
@@ -842,7 +849,7 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
     int used = kBatchBlock, n_batch = 0, n_lost = 0;
     bool chain_ok = true;
     // level 2 over queue entries [0, n), n <= 64
-    auto level2 = [&](int n) {
+    auto level2 = [&](int n) __attribute__((always_inline)) {
         const bool valid = lane < n;
         const int i = valid ? lane : 0;
         const CullRec S = q_rec[i];
@@ -881,7 +888,7 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
         for (int pm = 0; pm < kSuperPatches; ++pm) {
             const int p = p0 + pm;
             if (p >= n_patch) break;
-            const Reach r = reach(S, patches[p]);
+            const Reach r = reach(S, q_patch[pm]);
             int64_t cur = lane < n_freq ? cur_s[pm * kNB + lane] : 0;
 #pragma unroll
             for (int b = 0; b < B.count(); ++b) {
@@ -914,7 +921,7 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
     };
     int qn = 0;                                           // level-2 queue length
     // level 1 over level-1 queue entries [0, n), n <= 64
-    auto level1 = [&](int n) {
+    auto level1 = [&](int n) __attribute__((always_inline)) {
         const bool valid = lane < n;
         const int32_t j = q1[valid ? lane : 0];
         unsigned long long mask = 0ull;
