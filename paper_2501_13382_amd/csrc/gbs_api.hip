@@ -45,8 +45,10 @@ template <bool FILL, int NB>
 __global__ void k_cull(const JobConst*, const SegRec*, const Patch*, const Patch*, int, int, const int64_t*,
                        const CullSplit*,
                        const int32_t*, const unsigned long long*, int, int, int32_t*, const int64_t*, int32_t*,
-                       unsigned char*, unsigned*, int64_t, int32_t*);
+                       unsigned char*, unsigned*, int64_t, int32_t*, const int32_t*);
 __global__ void k_cull_need(const unsigned*, unsigned*);
+template <bool SCATTER>
+__global__ void k_cull_order(const unsigned*, int, int, int64_t, unsigned*, int32_t*);
 template <int NB>
 __global__ void k_cull_replay(const CullSplit*, int, int, int, const int64_t*, const int64_t*, const unsigned char*,
                               const unsigned*, int64_t, const int32_t*, int32_t*);
@@ -56,7 +58,7 @@ int cull_batch_ctr_stride();
 int cull_batch_block();
 template <int NB>
 __global__ void k_cull_hyper(const JobConst*, const SegRec*, const Patch*, int, int, int, const CullSplit*,
-                             const int32_t*, unsigned long long*);
+                             const int32_t*, unsigned long long*, unsigned*);
 __global__ void k_item_lengths(const int64_t*, int32_t, int, int, const int64_t*, int32_t*);
 __global__ void k_iota(int32_t*, int32_t);
 __global__ void k_seg_keys(int64_t, const SegRec*, const JobConst*, int32_t, int32_t, const double*,
@@ -833,11 +835,22 @@ struct Planner {
         unsigned long long* hmask = ws.get<unsigned long long>(
             slot_name("hmask", P.slot), (size_t)std::max<int64_t>(max_pieces, 1) * cps * R.n_hyper * (kCullThreads / kWave));
         if (nseg > 0) {
+            // level 0 also weighs each (piece, hyper-patch); the count pass
+            // starts its waves heaviest first
+            const int64_t n_wt = std::max<int64_t>(max_pieces, 1) * R.n_hyper, n_waves = (int64_t)cg.x * cg.y;
+            unsigned* weight = ws.get<unsigned>(slot_name("cull_weight", P.slot), n_wt + 32);
+            int32_t* order = ws.get<int32_t>(slot_name("cull_order", P.slot), n_waves);
+            hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>(4096, blocks_for(n_wt + 32, 256))), dim3(256),
+                               0, st, (int32_t*)weight, n_wt + 32, 0);
             hipLaunchKernelGGL(cull_hyper, dim3(cps, (unsigned)max_pieces), dim3(kCullThreads), 0, st, dJ, rec,
-                               R.hypers, R.n_hyper, n_freq, cps, d_split, d_nsplit, hmask);
+                               R.hypers, R.n_hyper, n_freq, cps, d_split, d_nsplit, hmask, weight);
+            hipLaunchKernelGGL(k_cull_order<false>, dim3(blocks_for(n_waves, 256)), dim3(256), 0, st, weight,
+                               (int)R.n_super, (int)R.n_hyper, n_waves, weight + n_wt, order);
+            hipLaunchKernelGGL(k_cull_order<true>, dim3(blocks_for(n_waves, 256)), dim3(256), 0, st, weight,
+                               (int)R.n_super, (int)R.n_hyper, n_waves, weight + n_wt, order);
             hipLaunchKernelGGL(cull_count, cg, dim3(kWave), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
                                n_freq, src_cnt, d_split, d_nsplit, hmask, R.n_hyper, cps, counts, nullptr, nullptr,
-                               P.bat, bat_ctr, P.cap_r, P.heads);
+                               P.bat, bat_ctr, P.cap_r, P.heads, order);
         }
         GBS_HIP(hipGetLastError());
         // counts are int32; accumulate in int64 through a converting iterator
@@ -896,7 +909,7 @@ struct Planner {
             if (!replay || words[2] > P.cap_r)
                 hipLaunchKernelGGL(cull_fill, cg, dim3(kWave), 0, st, L.jobs, rec, R.patches, R.supers, R.n_patch,
                                    n_freq, L.src_cnt, P.d_split, P.d_nsplit, P.hmask, R.n_hyper, P.cps, nullptr, P.off,
-                                   lists, P.bat, nullptr, P.cap_r, P.heads);
+                                   lists, P.bat, nullptr, P.cap_r, P.heads, nullptr);
         }
         GBS_HIP(hipGetLastError());
         int64_t* off = P.off;

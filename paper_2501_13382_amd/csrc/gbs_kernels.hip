@@ -679,7 +679,8 @@ __global__ __launch_bounds__(kCullThreads) void k_cull_hyper(const JobConst* __r
                                                              int n_freq, int chunks_per_split,
                                                              const CullSplit* __restrict__ splits,
                                                              const int32_t* __restrict__ n_splits,
-                                                             unsigned long long* __restrict__ hmask) {
+                                                             unsigned long long* __restrict__ hmask,
+                                                             unsigned* __restrict__ weight) {
     constexpr int kWaves = kCullThreads / kWave;
     if ((int)blockIdx.y >= *n_splits) return;     // the grid covers the most pieces a pass can have
     const CullSplit sl = splits[blockIdx.y];
@@ -701,8 +702,52 @@ __global__ __launch_bounds__(kCullThreads) void k_cull_hyper(const JobConst* __r
 #pragma unroll
         for (int b = 0; b < B.count(); ++b) any |= B.pass(r, b);
         const unsigned long long bal = __ballot(valid && any);
-        if (lane == 0) out[h * kWaves + wv] = bal;
+        if (lane == 0) {
+            out[h * kWaves + wv] = bal;
+            if (bal != 0ull) atomicAdd(weight + (int64_t)blockIdx.y * n_hyper + h, (unsigned)__popcll(bal));
+        }
     }
+}
+
+// The count pass's launch order: heaviest cull waves first, by the number of
+// their piece's segments that level 0 keeps for their hyper-patch (16 classes
+// of its log2; zero last), so that the long waves of the super-patches next
+// to a source do not start at the end of the grid.  A counting sort in two
+// launches over one thread per wave: the class sizes (ctr[0, 16)), then each
+// block reserves its range of every class (ctr[16, 32)).  The order within a
+// class is that of the atomics; the lists do not depend on it.
+__device__ __forceinline__ int cull_order_class(unsigned w) {
+    return w == 0u ? 15 : max(0, 14 - (31 - __builtin_clz(w)));
+}
+template <bool SCATTER>
+__global__ __launch_bounds__(256) void k_cull_order(const unsigned* __restrict__ weight, int n_super, int n_hyper,
+                                                    int64_t n_waves, unsigned* __restrict__ ctr,
+                                                    int32_t* __restrict__ order) {
+    __shared__ unsigned cnt[16], base[16];
+    if (threadIdx.x < 16) cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int cls = -1;
+    unsigned loc = 0u;
+    if (i < n_waves) {
+        const int64_t piece = i / n_super;
+        cls = cull_order_class(weight[piece * n_hyper + (i - piece * n_super) / kHyperSupers]);
+        loc = atomicAdd(&cnt[cls], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        const unsigned c = cnt[threadIdx.x];
+        if (!SCATTER) {
+            if (c != 0u) atomicAdd(&ctr[threadIdx.x], c);
+        } else {
+            unsigned b = 0u;
+            for (int k = 0; k < (int)threadIdx.x; ++k) b += ctr[k];
+            base[threadIdx.x] = c != 0u ? b + atomicAdd(&ctr[16 + threadIdx.x], c) : 0u;
+        }
+    }
+    if (!SCATTER) return;
+    __syncthreads();
+    if (cls >= 0) order[base[cls] + loc] = (int32_t)i;
 }
 
 // Cull, levels 1 and 2.  One wave per (super-patch of kSuperPatches
@@ -789,7 +834,8 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
                                                 int chunks_per_split, int32_t* __restrict__ counts,
                                                 const int64_t* __restrict__ off, int32_t* __restrict__ lists,
                                                 unsigned char* __restrict__ bat, unsigned* __restrict__ bat_ctr,
-                                                int64_t cap_r, int32_t* __restrict__ heads) {
+                                                int64_t cap_r, int32_t* __restrict__ heads,
+                                                const int32_t* __restrict__ order) {
     constexpr int kQ = 2 * kWave;                         // a partial batch plus one more
     constexpr int kNB = NB > 0 ? NB : kMaxBands;
     __shared__ int32_t q1[kQ];                            // level-1 queue: segment indices
@@ -798,9 +844,14 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
     __shared__ unsigned long long q_mask[kWave];
     __shared__ int64_t cur_s[kSuperPatches * kNB];        // cursor of (patch pm, band b) at pm * kNB + b
     __shared__ __align__(16) Patch q_patch[kSuperPatches];  // the super-patch's patches
-    const int sp = blockIdx.x;
+    // this wave: (piece, super-patch) = wave_id / n_super, wave_id % n_super,
+    // taken from the launch order when there is one
+    const int64_t slot_id = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const int64_t wave_id = order ? (int64_t)order[slot_id] : slot_id;
+    const int piece = (int)(wave_id / gridDim.x);
+    const int sp = (int)(wave_id - (int64_t)piece * gridDim.x);
     // level-0 bits of 64-segment chunk ci for the super-patch's hyper-patch
-    const unsigned long long* hm = hmask + (int64_t)blockIdx.y * chunks_per_split * n_hyper * 4 +
+    const unsigned long long* hm = hmask + (int64_t)piece * chunks_per_split * n_hyper * 4 +
                                    (int64_t)(sp / kHyperSupers) * 4;
     {
         // most waves have no segment that may reach their hyper-patch: they
@@ -814,8 +865,8 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
             any |= hm[(int64_t)(cl >> 2) * n_hyper * 4 + (cl & 3)] != 0ull;
         if (__ballot(any) == 0ull) return;
     }
-    if ((int)blockIdx.y >= *n_splits) return;             // the grid covers the most pieces a pass can have
-    const CullSplit sl = splits[blockIdx.y];
+    if (piece >= *n_splits) return;                      // the grid covers the most pieces a pass can have
+    const CullSplit sl = splits[piece];
     const int lane = threadIdx.x;
     const int64_t job0 = (int64_t)sl.src * n_freq;
     const int64_t cnt0 = src_cnt[2 * sl.src], n_piece = src_cnt[2 * sl.src + 1];
@@ -836,7 +887,6 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
                 (FILL && p < n_patch) ? off[cnt0 + ((int64_t)lane * n_patch + p) * n_piece + sl.idx] : 0;
     }
     wave_lds_fence();
-    const int64_t wave_id = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     constexpr int kCells = kSuperPatches * (NB > 0 ? NB : 1);         // cells per record
     constexpr int64_t kBlock = batch_block_bytes(kCells), kHdr = batch_hdr_bytes(kCells);
     constexpr int64_t kRec = batch_rec_bytes(kCells);
@@ -2352,16 +2402,18 @@ __global__ void k_dgamma(const double* __restrict__ Zf, int32_t n_faces, double*
                                            const int64_t*,                                                         \
                                            const CullSplit*, const int32_t*, const unsigned long long*, int, int,    \
                                            int32_t*, const int64_t*, int32_t*, unsigned char*, unsigned*, int64_t,   \
-                                           int32_t*);
+                                           int32_t*, const int32_t*);
 #define GBS_INST_CULL_NB(NB)                                                                                   \
     GBS_INST_CULL(false, NB)                                                                                   \
     GBS_INST_CULL(true, NB)                                                                                    \
     template __global__ void k_cull_hyper<NB>(const JobConst*, const SegRec*, const Patch*, int, int, int,       \
-                                              const CullSplit*, const int32_t*, unsigned long long*);
+                                              const CullSplit*, const int32_t*, unsigned long long*, unsigned*);
 GBS_INST_CULL_NB(1)
 GBS_INST_CULL_NB(4)
 GBS_INST_CULL_NB(8)
 GBS_INST_CULL_NB(0)
+template __global__ void k_cull_order<false>(const unsigned*, int, int, int64_t, unsigned*, int32_t*);
+template __global__ void k_cull_order<true>(const unsigned*, int, int, int64_t, unsigned*, int32_t*);
 #define GBS_INST_REPLAY(NB)                                                                                    \
     template __global__ void k_cull_replay<NB>(const CullSplit*, int, int, int, const int64_t*, const int64_t*, \
                                                const unsigned char*, const unsigned*, int64_t, const int32_t*,  \
