@@ -179,6 +179,7 @@ struct Workspace {
     std::map<std::string, std::pair<void*, size_t>> bufs;
     hipStream_t stream = nullptr;
     hipStream_t copy_stream = nullptr;    // also drained before a buffer is freed
+    hipStream_t pair_streams[2] = {nullptr, nullptr};   // likewise
     bool frozen = false;                  // set during graph capture: no allocation allowed
     char* arena = nullptr;                // arena mode: base of the region, its size, bytes handed out
     size_t arena_cap = 0, arena_used = 0;
@@ -222,6 +223,8 @@ struct Workspace {
             if (b.first) {
                 GBS_HIP(hipStreamSynchronize(stream));
                 if (copy_stream) GBS_HIP(hipStreamSynchronize(copy_stream));
+                for (hipStream_t ps : pair_streams)
+                    if (ps) GBS_HIP(hipStreamSynchronize(ps));
                 GBS_HIP(hipFree(b.first));
                 b.first = nullptr;
                 b.second = 0;
@@ -266,6 +269,12 @@ struct gbs_ctx {
     hipStream_t copy_stream = nullptr;
     hipEvent_t copied[2] = {nullptr, nullptr};
     hipEvent_t released[2] = {nullptr, nullptr};
+    // calls in several passes: the pair kernel of pass i runs on
+    // pair_stream[i % 2] (ready: its lists are laid out; done: its partial
+    // sums are written), so that it overlaps the end of pass i - 1's
+    hipStream_t pair_stream[2] = {nullptr, nullptr};
+    hipEvent_t pair_ready[2] = {nullptr, nullptr};
+    hipEvent_t pair_done[2] = {nullptr, nullptr};
     // list-length reads of up to two planned passes: pinned host words (list
     // total, status word) per slot and the events behind their copies; made
     // at creation so that no call allocates them
@@ -891,7 +900,7 @@ struct Planner {
         const int n_freq = a.n_freq;
         const int64_t n_items = L.n_items;
         const SegRec* rec = L.rec;
-        int32_t* lists = ws.get<int32_t>("lists" + tag, std::max<int64_t>(L.total, 1));
+        int32_t* lists = ws.get<int32_t>(slot_name("lists", P.slot), std::max<int64_t>(L.total, 1));
         auto cull_fill = n_freq == 1 ? k_cull<true, 1> : n_freq <= 4 ? k_cull<true, 4>
                        : n_freq <= 8 ? k_cull<true, 8> : k_cull<true, 0>;
         dim3 cg(R.n_super, (unsigned)std::max<int64_t>(P.max_pieces, 1));
@@ -943,10 +952,10 @@ struct Planner {
         GBS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp3, nw, wb, (int)(n_items + 1), st));
         void* t3 = ws.get<char>("cub_tmp_work", tmp3);
         GBS_HIP(hipcub::DeviceScan::ExclusiveSum(t3, tmp3, nw, wb, (int)(n_items + 1), st));
-        Work* work = ws.get<Work>("work" + tag, cap);
-        int32_t* iwb = ws.get<int32_t>("item_wbase" + tag, n_items);
-        int32_t* iwc = ws.get<int32_t>("item_wcount" + tag, n_items);
-        int32_t* n_work = ws.get<int32_t>("n_work" + tag, 1);
+        Work* work = ws.get<Work>(slot_name("work", P.slot), cap);
+        int32_t* iwb = ws.get<int32_t>(slot_name("item_wbase", P.slot), n_items);
+        int32_t* iwc = ws.get<int32_t>(slot_name("item_wcount", P.slot), n_items);
+        int32_t* n_work = ws.get<int32_t>(slot_name("n_work", P.slot), 1);
         hipLaunchKernelGGL(k_make_work, dim3(blocks_for(n_items, 256)), dim3(256), 0, st, order, off, R.n_patch,
                            n_freq, L.src_cnt, wb,
                            (int32_t)n_items, chunk, work, iwb, iwc, n_work);
@@ -1028,9 +1037,19 @@ int64_t persistent_grid(gbs_ctx* ctx, const void* kern, int64_t n_items) {
     return std::max<int64_t>(grid, 1);
 }
 
+// Adds a pass's partial sums into P in work-unit order (write: the call's
+// only pass, which writes P and TL instead).
+void reduce_pass(hipStream_t st, const Planner::Lists& L, const RcvPlan& R, int nr, int64_t n_rcv, double* P,
+                 double* TL, bool write) {
+    const int64_t threads = (int64_t)L.n_items * 64 * nr;
+    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(threads, 256)), dim3(256), 0, st, L.jobs, L.item_wbase,
+                       L.item_wcount, L.n_items, R.n_patch, nr, R.perm, n_rcv, L.partial, P, TL, (int)write);
+    GBS_HIP(hipGetLastError());
+}
+
 template <int MODE, int NR, bool COUNT>
 void launch_pairs(gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const RcvPlan& R, int64_t n_rcv, double* P,
-                  unsigned* ctr, unsigned long long* n_active, EventPair* ev, double* TL, bool write) {
+                  unsigned* ctr, unsigned long long* n_active, EventPair* ev, double* TL, bool write, bool reduce) {
     auto kern = k_pairs<MODE, NR, COUNT>;
     const int64_t grid = persistent_grid(ctx, (const void*)kern, L.work_cap);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, ctr);
@@ -1039,26 +1058,24 @@ void launch_pairs(gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const R
                        L.lists, L.rec, L.frames, R.rx, R.ry, R.rz, R.r2, L.partial, n_active);
     GBS_HIP(hipGetLastError());
     if (ev) ev->stop(st);
-    const int64_t threads = (int64_t)L.n_items * 64 * NR;
-    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(threads, 256)), dim3(256), 0, st, L.jobs, L.item_wbase,
-                       L.item_wcount, L.n_items, R.n_patch, NR, R.perm, n_rcv, L.partial, P, TL, (int)write);
-    GBS_HIP(hipGetLastError());
+    if (reduce) reduce_pass(st, L, R, NR, n_rcv, P, TL, write);
 }
 
 template <int MODE, bool COUNT>
 void dispatch_nr(int nr, gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const RcvPlan& R, int64_t n_rcv,
-                 double* P, unsigned* ctr, unsigned long long* na, EventPair* ev, double* TL, bool write) {
-    if (nr == 1) launch_pairs<MODE, 1, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write);
-    else if (nr == 2) launch_pairs<MODE, 2, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write);
-    else launch_pairs<MODE, 4, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write);
+                 double* P, unsigned* ctr, unsigned long long* na, EventPair* ev, double* TL, bool write,
+                 bool reduce) {
+    if (nr == 1) launch_pairs<MODE, 1, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write, reduce);
+    else if (nr == 2) launch_pairs<MODE, 2, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write, reduce);
+    else launch_pairs<MODE, 4, COUNT>(ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write, reduce);
 }
 
 template <int MODE>
 void dispatch_count(bool count, int nr, gbs_ctx* ctx, hipStream_t st, const Planner::Lists& L, const RcvPlan& R,
                     int64_t n_rcv, double* P, unsigned* ctr, unsigned long long* na, EventPair* ev, double* TL,
-                    bool write) {
-    count ? dispatch_nr<MODE, true>(nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write)
-          : dispatch_nr<MODE, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write);
+                    bool write, bool reduce) {
+    count ? dispatch_nr<MODE, true>(nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write, reduce)
+          : dispatch_nr<MODE, false>(nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write, reduce);
 }
 
 // mode: GBS_MODE_*; absorb: some job has atmospheric absorption (the kernel
@@ -1066,30 +1083,32 @@ void dispatch_count(bool count, int nr, gbs_ctx* ctx, hipStream_t st, const Plan
 // anisotropic beams (counting counts the exact gate's pairs).
 // ev (optional): HIP events around the pair kernel's launch alone.
 // write: the call's only pass; the reduction writes every output of P (no
-// zero fill before it) and, with TL, the transmission loss.
+// zero fill before it) and, with TL, the transmission loss.  reduce: false
+// leaves the partial sums for reduce_pass on another stream.
 void dispatch_pairs(int mode, bool absorb, bool aniso, bool count, int nr, gbs_ctx* ctx, hipStream_t st,
                     const Planner::Lists& L, const RcvPlan& R, int64_t n_rcv, double* P, unsigned* ctr,
-                    unsigned long long* na, EventPair* ev = nullptr, double* TL = nullptr, bool write = false) {
+                    unsigned long long* na, EventPair* ev = nullptr, double* TL = nullptr, bool write = false,
+                    bool reduce = true) {
     GBS_CHECK(L.partial != nullptr, "work-unit partials not allocated");
     const int m = (mode == GBS_MODE_F64 ? 0 : mode == GBS_MODE_MIX ? 1 : 2) | (absorb ? 4 : 0);
     if (aniso) {
         switch (m) {
-            case 0: dispatch_count<8>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
-            case 1: dispatch_count<9>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
-            case 2: dispatch_count<10>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
-            case 4: dispatch_count<12>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
-            case 5: dispatch_count<13>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
-            default: dispatch_count<14>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
+            case 0: dispatch_count<8>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write, reduce); break;
+            case 1: dispatch_count<9>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write, reduce); break;
+            case 2: dispatch_count<10>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write, reduce); break;
+            case 4: dispatch_count<12>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write, reduce); break;
+            case 5: dispatch_count<13>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write, reduce); break;
+            default: dispatch_count<14>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write, reduce); break;
         }
         return;
     }
     switch (m) {
-        case 0: dispatch_count<0>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
-        case 1: dispatch_count<1>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
-        case 2: dispatch_count<2>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
-        case 4: dispatch_count<4>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
-        case 5: dispatch_count<5>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
-        default: dispatch_count<6>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write); break;
+        case 0: dispatch_count<0>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write, reduce); break;
+        case 1: dispatch_count<1>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write, reduce); break;
+        case 2: dispatch_count<2>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write, reduce); break;
+        case 4: dispatch_count<4>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write, reduce); break;
+        case 5: dispatch_count<5>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write, reduce); break;
+        default: dispatch_count<6>(count, nr, ctx, st, L, R, n_rcv, P, ctr, na, ev, TL, write, reduce); break;
     }
 }
 
@@ -1103,6 +1122,18 @@ void ensure_copy_stream(gbs_ctx* ctx) {
         GBS_HIP(hipEventCreateWithFlags(&ctx->released[i], hipEventDisableTiming));
     }
     ctx->ws->copy_stream = ctx->copy_stream;
+}
+
+// The pair streams and their events, created on first use (default priority).
+void ensure_pair_streams(gbs_ctx* ctx, Workspace& ws) {
+    for (int i = 0; i < 2; ++i) {
+        if (!ctx->pair_stream[i]) {
+            GBS_HIP(hipStreamCreateWithFlags(&ctx->pair_stream[i], hipStreamNonBlocking));
+            GBS_HIP(hipEventCreateWithFlags(&ctx->pair_ready[i], hipEventDisableTiming));
+            GBS_HIP(hipEventCreateWithFlags(&ctx->pair_done[i], hipEventDisableTiming));
+        }
+        ws.pair_streams[i] = ctx->pair_stream[i];
+    }
 }
 
 int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* TL, int nr_override,
@@ -1180,7 +1211,47 @@ int forward_impl(gbs_ctx* ctx, Workspace& ws, const Args& a, double* P, double* 
             start(0);
             start(1);
         }
-        for (size_t pi = 0; pi < n_pass; ++pi) {
+        // Several passes, untimed and uncounted: pass i's pair kernel runs on
+        // pair_stream[i % 2] once its lists are laid out, and pass i + 1's
+        // lists are laid out meanwhile, so that its pair kernel fills the
+        // GPU as pass i's drains; the partial sums are added into P on the
+        // compute stream, pass by pass, and a slot is planned again only
+        // after its pair kernel and reduction
+        const bool spread = pipe && !count;
+        if (spread) {
+            ensure_pair_streams(ctx, ws);
+            Planner::Lists Ls[2];
+            bool has[2] = {false, false};
+            auto finish_and_launch = [&](size_t pi) {
+                const int slot = (int)(pi % 2);
+                Planner::Lists L = pl.finish_pass(pend[slot]);
+                stats.listed_pairs += L.total * (int64_t)pl.R.per;
+                stats.n_items += L.n_items;
+                has[slot] = L.n_items > 0 && L.total > 0;
+                if (has[slot]) {
+                    L.partial = ws.get<double>(pl.slot_name("partial", slot), L.work_cap * nr * 64 * 2);
+                    unsigned* c = ws.get<unsigned>(pl.slot_name("ctr", slot), 1);
+                    hipStream_t ps = ctx->pair_stream[slot];
+                    GBS_HIP(hipEventRecord(ctx->pair_ready[slot], st));
+                    GBS_HIP(hipStreamWaitEvent(ps, ctx->pair_ready[slot], 0));
+                    dispatch_pairs(a.params->mode, pl.absorb(), pl.aniso(), false, nr, ctx, ps, L, pl.R, a.n_rcv, P,
+                                   c, na, nullptr, nullptr, false, false);
+                    GBS_HIP(hipEventRecord(ctx->pair_done[slot], ps));
+                }
+                Ls[slot] = L;
+            };
+            finish_and_launch(0);
+            for (size_t pi = 0; pi < n_pass; ++pi) {
+                const int slot = (int)(pi % 2);
+                if (pi + 1 < n_pass) finish_and_launch(pi + 1);
+                if (has[slot]) {
+                    GBS_HIP(hipStreamWaitEvent(st, ctx->pair_done[slot], 0));
+                    reduce_pass(st, Ls[slot], pl.R, nr, a.n_rcv, P, nullptr, false);
+                }
+                if (pi + 2 < n_pass) start(pi + 2);
+            }
+        }
+        for (size_t pi = 0; pi < (spread ? 0 : n_pass); ++pi) {
             ev_cull.begin(st);
             if (!pipe) start(pi);
             Planner::Lists L = pl.finish_pass(pend[pi % 2]);
@@ -1491,8 +1562,13 @@ void gbs_destroy(gbs_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->copy_stream) (void)hipStreamSynchronize(ctx->copy_stream);
+    for (hipStream_t ps : ctx->pair_stream)
+        if (ps) (void)hipStreamSynchronize(ps);
     ctx->ws.reset();
     for (int i = 0; i < 2; ++i) {
+        if (ctx->pair_ready[i]) (void)hipEventDestroy(ctx->pair_ready[i]);
+        if (ctx->pair_done[i]) (void)hipEventDestroy(ctx->pair_done[i]);
+        if (ctx->pair_stream[i]) (void)hipStreamDestroy(ctx->pair_stream[i]);
         if (ctx->copied[i]) (void)hipEventDestroy(ctx->copied[i]);
         if (ctx->released[i]) (void)hipEventDestroy(ctx->released[i]);
         if (ctx->planned[i]) (void)hipEventDestroy(ctx->planned[i]);
