@@ -56,7 +56,9 @@
  * because of bad contents.  No C++ exception crosses this interface.  Calls
  * on one context are not thread-safe; use one context per host thread.  Work
  * is enqueued on the context's stream; outputs are complete when that stream
- * is synchronised.
+ * is synchronised.  (A forward in several passes also runs its pair kernels
+ * on two streams of its own, default priority; the context's stream waits
+ * for each before it adds that pass into P, so the rule holds.)
  */
 #ifndef GBS_H
 #define GBS_H
