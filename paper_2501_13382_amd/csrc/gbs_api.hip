@@ -788,8 +788,8 @@ struct Planner {
         // workgroup culls one piece for all bands of its source.  The pieces
         // are laid out on the device (k_make_splits); the host sizes the grids
         // for the most pieces a pass can have: one cull wave per (super-patch,
-        // piece), up to 256 pieces per source and about 64M list-length
-        // counters in all.  A piece holds 1,024 segments or more, down to 256
+        // piece), up to 256 pieces per source (more when there are fewer than
+        // 128 super-patches) and about 64M list-length counters in all.  A piece holds 1,024 segments or more, down to 256
         // when a pass is too short for 32,768 cull waves (the waves near the
         // source set a short pass's time).  Each piece has one counter per
         // (band, patch) of its source; a source's counters are (band, patch,
@@ -798,8 +798,12 @@ struct Planner {
         // segment order
         const int n_src = a.rays->n_src, n_freq = a.n_freq;
         const int64_t cells = (int64_t)n_freq * R.n_patch;
+        // few super-patches (impulse responses: a few thousand receivers,
+        // many bands) take up to 32,768 / n_super pieces per source, so that
+        // the cull still runs that many waves
+        const int64_t per_src = std::max<int64_t>(256, 32768 / std::max<int64_t>(1, R.n_super));
         const int64_t budget = std::max<int64_t>(
-            1, std::min<int64_t>(256 * (int64_t)n_src, ((int64_t(1) << 26) / cells) - n_src));
+            1, std::min<int64_t>(per_src * n_src, ((int64_t(1) << 26) / cells) - n_src));
         int64_t span_min = 1024;
         while (span_min > kCullThreads && (int64_t)R.n_super * ((nseg + span_min - 1) / span_min) < 32768)
             span_min -= kCullThreads;
