@@ -802,8 +802,9 @@ struct Planner {
         // many bands) take up to 32,768 / n_super pieces per source, so that
         // the cull still runs that many waves
         const int64_t per_src = std::max<int64_t>(256, 32768 / std::max<int64_t>(1, R.n_super));
+        // a pass has at most n_src + budget pieces, fewer than 65,536
         const int64_t budget = std::max<int64_t>(
-            1, std::min<int64_t>(per_src * n_src, ((int64_t(1) << 26) / cells) - n_src));
+            1, std::min<int64_t>({per_src * n_src, ((int64_t(1) << 26) / cells) - n_src, 65535 - (int64_t)n_src}));
         int64_t span_min = 1024;
         while (span_min > kCullThreads && (int64_t)R.n_super * ((nseg + span_min - 1) / span_min) < 32768)
             span_min -= kCullThreads;
