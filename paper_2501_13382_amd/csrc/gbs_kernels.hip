@@ -850,6 +850,12 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
     const int64_t wave_id = order ? (int64_t)order[slot_id] : slot_id;
     const int piece = (int)(wave_id / gridDim.x);
     const int sp = (int)(wave_id - (int64_t)piece * gridDim.x);
+    // the piece and the super-patch, loaded before the level-0 test so that a
+    // wave that goes on does not wait for them after it (piece < the grid's
+    // height, the pieces' allocation; those past the last are not used)
+    const int n_spl = *n_splits;
+    const CullSplit sl = splits[piece];
+    const Patch SPt = supers[sp];
     // level-0 bits of 64-segment chunk ci for the super-patch's hyper-patch
     const unsigned long long* hm = hmask + (int64_t)piece * chunks_per_split * n_hyper * 4 +
                                    (int64_t)(sp / kHyperSupers) * 4;
@@ -865,14 +871,12 @@ __global__ __launch_bounds__(kWave) void k_cull(const JobConst* __restrict__ job
             any |= hm[(int64_t)(cl >> 2) * n_hyper * 4 + (cl & 3)] != 0ull;
         if (__ballot(any) == 0ull) return;
     }
-    if (piece >= *n_splits) return;                      // the grid covers the most pieces a pass can have
-    const CullSplit sl = splits[piece];
+    if (piece >= n_spl) return;                          // the grid covers the most pieces a pass can have
     const int lane = threadIdx.x;
     const int64_t job0 = (int64_t)sl.src * n_freq;
     const int64_t cnt0 = src_cnt[2 * sl.src], n_piece = src_cnt[2 * sl.src + 1];
     Bands<NB> B;
     B.load(jobs, job0, n_freq, lane);
-    const Patch SPt = supers[sp];
     const int p0 = sp * kSuperPatches;
     // the 16 patches, read by every level-2 batch: from LDS rather than one
     // scalar load (and wait) per patch and batch
