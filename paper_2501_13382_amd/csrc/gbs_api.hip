@@ -48,7 +48,7 @@ __global__ void k_cull(const JobConst*, const SegRec*, const Patch*, const Patch
                        unsigned char*, unsigned*, int64_t, int32_t*, const int32_t*);
 __global__ void k_cull_need(const unsigned*, unsigned*);
 template <bool SCATTER>
-__global__ void k_cull_order(const unsigned*, int, int, int64_t, unsigned*, int32_t*);
+__global__ void k_cull_order(const unsigned*, int, int, int, int64_t, unsigned*, int32_t*);
 template <int NB>
 __global__ void k_cull_replay(const CullSplit*, int, int, int, const int64_t*, const int64_t*, const unsigned char*,
                               const unsigned*, int64_t, const int32_t*, int32_t*);
@@ -58,7 +58,7 @@ int cull_batch_ctr_stride();
 int cull_batch_block();
 template <int NB>
 __global__ void k_cull_hyper(const JobConst*, const SegRec*, const Patch*, int, int, int, const CullSplit*,
-                             const int32_t*, unsigned long long*, unsigned*);
+                             const int32_t*, unsigned long long*, const Patch*, int, int, unsigned*);
 __global__ void k_item_lengths(const int64_t*, int32_t, int, int, const int64_t*, int32_t*);
 __global__ void k_iota(int32_t*, int32_t);
 __global__ void k_seg_keys(int64_t, const SegRec*, const JobConst*, int32_t, int32_t, const double*,
@@ -849,19 +849,23 @@ struct Planner {
         unsigned long long* hmask = ws.get<unsigned long long>(
             slot_name("hmask", P.slot), (size_t)std::max<int64_t>(max_pieces, 1) * cps * R.n_hyper * (kCullThreads / kWave));
         if (nseg > 0) {
-            // level 0 also weighs each (piece, hyper-patch); the count pass
-            // starts its waves heaviest first
-            const int64_t n_wt = std::max<int64_t>(max_pieces, 1) * R.n_hyper, n_waves = (int64_t)cg.x * cg.y;
+            // level 0 also weighs each cull wave (piece, super-patch), or
+            // each (piece, hyper-patch) where the super-patch tests would cost
+            // too much (many segments and hyper-patches); the count pass starts
+            // its waves heaviest first
+            const int64_t n_waves = (int64_t)cg.x * cg.y, n_wt = n_waves;
+            const int per_super = nseg * (int64_t)R.n_hyper <= (int64_t(1) << 24) ? 1 : 0;
             unsigned* weight = ws.get<unsigned>(slot_name("cull_weight", P.slot), n_wt + 32);
             int32_t* order = ws.get<int32_t>(slot_name("cull_order", P.slot), n_waves);
             hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>(4096, blocks_for(n_wt + 32, 256))), dim3(256),
                                0, st, (int32_t*)weight, n_wt + 32, 0);
             hipLaunchKernelGGL(cull_hyper, dim3(cps, (unsigned)max_pieces), dim3(kCullThreads), 0, st, dJ, rec,
-                               R.hypers, R.n_hyper, n_freq, cps, d_split, d_nsplit, hmask, weight);
+                               R.hypers, R.n_hyper, n_freq, cps, d_split, d_nsplit, hmask, R.supers, (int)R.n_super,
+                               per_super, weight);
             hipLaunchKernelGGL(k_cull_order<false>, dim3(blocks_for(n_waves, 256)), dim3(256), 0, st, weight,
-                               (int)R.n_super, (int)R.n_hyper, n_waves, weight + n_wt, order);
+                               per_super, (int)R.n_super, (int)R.n_hyper, n_waves, weight + n_wt, order);
             hipLaunchKernelGGL(k_cull_order<true>, dim3(blocks_for(n_waves, 256)), dim3(256), 0, st, weight,
-                               (int)R.n_super, (int)R.n_hyper, n_waves, weight + n_wt, order);
+                               per_super, (int)R.n_super, (int)R.n_hyper, n_waves, weight + n_wt, order);
             hipLaunchKernelGGL(cull_count, cg, dim3(kWave), 0, st, dJ, rec, R.patches, R.supers, R.n_patch,
                                n_freq, src_cnt, d_split, d_nsplit, hmask, R.n_hyper, cps, counts, nullptr, nullptr,
                                P.bat, bat_ctr, P.cap_r, P.heads, order);

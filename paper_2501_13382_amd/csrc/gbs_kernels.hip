@@ -680,7 +680,8 @@ __global__ __launch_bounds__(kCullThreads) void k_cull_hyper(const JobConst* __r
                                                              const CullSplit* __restrict__ splits,
                                                              const int32_t* __restrict__ n_splits,
                                                              unsigned long long* __restrict__ hmask,
-                                                             unsigned* __restrict__ weight) {
+                                                             const Patch* __restrict__ supers, int n_super,
+                                                             int per_super, unsigned* __restrict__ weight) {
     constexpr int kWaves = kCullThreads / kWave;
     if ((int)blockIdx.y >= *n_splits) return;     // the grid covers the most pieces a pass can have
     const CullSplit sl = splits[blockIdx.y];
@@ -702,27 +703,44 @@ __global__ __launch_bounds__(kCullThreads) void k_cull_hyper(const JobConst* __r
 #pragma unroll
         for (int b = 0; b < B.count(); ++b) any |= B.pass(r, b);
         const unsigned long long bal = __ballot(valid && any);
-        if (lane == 0) {
-            out[h * kWaves + wv] = bal;
-            if (bal != 0ull) atomicAdd(weight + (int64_t)blockIdx.y * n_hyper + h, (unsigned)__popcll(bal));
+        if (lane == 0) out[h * kWaves + wv] = bal;
+        if (bal == 0ull) continue;
+        // the count pass's weights: these segments (per_super = 0: weight of
+        // the (piece, hyper-patch)), or those of them that also reach each
+        // super-patch of the hyper-patch (level 1's test)
+        if (!per_super) {
+            if (lane == 0) atomicAdd(weight + (int64_t)blockIdx.y * n_hyper + h, (unsigned)__popcll(bal));
+            continue;
+        }
+        const int q1 = min((h + 1) * kHyperSupers, n_super);
+        for (int q = h * kHyperSupers; q < q1; ++q) {
+            const Reach rq = reach(me, supers[q]);
+            bool in = false;
+#pragma unroll
+            for (int b = 0; b < B.count(); ++b) in |= B.pass(rq, b);
+            const unsigned long long bq = __ballot(valid && any && in);
+            if (lane == 0 && bq != 0ull)
+                atomicAdd(weight + (int64_t)blockIdx.y * n_super + q, (unsigned)__popcll(bq));
         }
     }
 }
 
 // The count pass's launch order: heaviest cull waves first, by the number of
-// their piece's segments that level 0 keeps for their hyper-patch (16 classes
-// of its log2; zero last), so that the long waves of the super-patches next
-// to a source do not start at the end of the grid.  A counting sort in two
-// launches over one thread per wave: the class sizes (ctr[0, 16)), then each
-// block reserves its range of every class (ctr[16, 32)).  The order within a
-// class is that of the atomics; the lists do not depend on it.
+// their piece's segments that reach their super-patch (per_super: weight
+// [piece n_super + super-patch]) or else their hyper-patch (weight[piece
+// n_hyper + hyper-patch]), 16 classes of its log2, zero last, so that the
+// long waves of the super-patches next to a source do not start at the end
+// of the grid.  A counting sort in two launches over one thread per wave
+// (wave = piece n_super + super-patch): the class sizes (ctr[0, 16)), then
+// each block reserves its range of every class (ctr[16, 32)).  The order
+// within a class is that of the atomics; the lists do not depend on it.
 __device__ __forceinline__ int cull_order_class(unsigned w) {
     return w == 0u ? 15 : max(0, 14 - (31 - __builtin_clz(w)));
 }
 template <bool SCATTER>
-__global__ __launch_bounds__(256) void k_cull_order(const unsigned* __restrict__ weight, int n_super, int n_hyper,
-                                                    int64_t n_waves, unsigned* __restrict__ ctr,
-                                                    int32_t* __restrict__ order) {
+__global__ __launch_bounds__(256) void k_cull_order(const unsigned* __restrict__ weight, int per_super,
+                                                    int n_super, int n_hyper, int64_t n_waves,
+                                                    unsigned* __restrict__ ctr, int32_t* __restrict__ order) {
     __shared__ unsigned cnt[16], base[16];
     if (threadIdx.x < 16) cnt[threadIdx.x] = 0u;
     __syncthreads();
@@ -731,7 +749,8 @@ __global__ __launch_bounds__(256) void k_cull_order(const unsigned* __restrict__
     unsigned loc = 0u;
     if (i < n_waves) {
         const int64_t piece = i / n_super;
-        cls = cull_order_class(weight[piece * n_hyper + (i - piece * n_super) / kHyperSupers]);
+        cls = cull_order_class(per_super ? weight[i]
+                                         : weight[piece * n_hyper + (i - piece * n_super) / kHyperSupers]);
         loc = atomicAdd(&cnt[cls], 1u);
     }
     __syncthreads();
@@ -2411,13 +2430,14 @@ __global__ void k_dgamma(const double* __restrict__ Zf, int32_t n_faces, double*
     GBS_INST_CULL(false, NB)                                                                                   \
     GBS_INST_CULL(true, NB)                                                                                    \
     template __global__ void k_cull_hyper<NB>(const JobConst*, const SegRec*, const Patch*, int, int, int,       \
-                                              const CullSplit*, const int32_t*, unsigned long long*, unsigned*);
+                                              const CullSplit*, const int32_t*, unsigned long long*, const Patch*, \
+                                              int, int, unsigned*);
 GBS_INST_CULL_NB(1)
 GBS_INST_CULL_NB(4)
 GBS_INST_CULL_NB(8)
 GBS_INST_CULL_NB(0)
-template __global__ void k_cull_order<false>(const unsigned*, int, int, int64_t, unsigned*, int32_t*);
-template __global__ void k_cull_order<true>(const unsigned*, int, int, int64_t, unsigned*, int32_t*);
+template __global__ void k_cull_order<false>(const unsigned*, int, int, int, int64_t, unsigned*, int32_t*);
+template __global__ void k_cull_order<true>(const unsigned*, int, int, int, int64_t, unsigned*, int32_t*);
 #define GBS_INST_REPLAY(NB)                                                                                    \
     template __global__ void k_cull_replay<NB>(const CullSplit*, int, int, int, const int64_t*, const int64_t*, \
                                                const unsigned char*, const unsigned*, int64_t, const int32_t*,  \
